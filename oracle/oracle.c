@@ -1,0 +1,558 @@
+/*
+ * CPU ORACLE — test infrastructure only.
+ *
+ * A plain, slow, obviously correct reference for everything the GPU library
+ * computes. Only the tests, the smoke check and the benchmark's CPU-baseline
+ * leg may load it; the library never does, and the two share no code.
+ *
+ * Contents, each following the paper (arxiv 2410.19119, "Tera-Scale
+ * Multilevel Graph Partitioning") and the synchronous reading of it:
+ *   - VarInt / zigzag codec and the gap-encoded neighbourhood format
+ *     (Section III-A, "Compression Scheme");
+ *   - size-constrained label-propagation clustering in synchronous rounds
+ *     (Section IV-A, Algorithm 1 for what one vertex computes; the
+ *     batch-synchronous form follows Section II-B on the distributed LP);
+ *   - cluster contraction into a quotient graph (Section IV-B, the weight
+ *     definition of a coarse edge);
+ *   - the edge cut (Section I, the partitioning objective);
+ *   - the coarsening loop (Sections I and II-A: cluster, contract, repeat).
+ *
+ * Floating point is never used: IDs are int32, offsets uint64, input weights
+ * int32 >= 1, ratings / gains / cluster weights int64.
+ *
+ * Parallelism: the per-vertex rating loop is an OpenMP parallel-for. Each
+ * vertex reads only the round's snapshot, so the result does not depend on the
+ * thread count. Everything else is sequential.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL -1
+#define ORC_ENOMEM -2
+#define ORC_EOVERFLOW -3
+#define ORC_EFORMAT -4
+
+/* Format constants: neighbourhoods with more than 10 000 neighbours are split
+ * into independently coded chunks of 1 000 (Section III-A). */
+#define ORC_CHUNK_THRESHOLD 10000
+#define ORC_CHUNK_LEN 1000
+
+/* ------------------------------------------------------------ VarInt ---- */
+/* VarInt (Section III-A): 7 payload bits per byte, least significant group
+ * first; the high bit of a byte says another byte of the same number
+ * follows. */
+size_t orc_varint_put(uint8_t *out, uint64_t x) {
+  size_t k = 0;
+  while (x >= 0x80) {
+    out[k++] = (uint8_t)(x & 0x7F) | 0x80;
+    x >>= 7;
+  }
+  out[k++] = (uint8_t)x;
+  return k;
+}
+
+/* Reads one VarInt at *pos (advancing it). Returns 0 on a malformed or
+ * truncated number (more than 10 bytes or running past `end`). */
+int orc_varint_get(const uint8_t *buf, uint64_t end, uint64_t *pos, uint64_t *value) {
+  uint64_t x = 0;
+  for (int shift = 0; shift < 70; shift += 7) {
+    if (*pos >= end) return 0;
+    uint8_t b = buf[(*pos)++];
+    x |= (uint64_t)(b & 0x7F) << shift;
+    if (!(b & 0x80)) {
+      *value = x;
+      return 1;
+    }
+  }
+  return 0;
+}
+
+/* Signed values (the first neighbour relative to u, weight differences) are
+ * mapped to unsigned ones so small magnitudes stay short: 0,-1,1,-2 -> 0,1,2,3. */
+uint64_t orc_zigzag(int64_t x) { return ((uint64_t)x << 1) ^ (uint64_t)(x >> 63); }
+int64_t orc_unzigzag(uint64_t z) { return (int64_t)(z >> 1) ^ -(int64_t)(z & 1); }
+
+/* ------------------------------------------------------- compression ---- */
+typedef struct {
+  int32_t v, w;
+} orc_nb;
+
+static int cmp_nb(const void *a, const void *b) {
+  const orc_nb *x = (const orc_nb *)a, *y = (const orc_nb *)b;
+  if (x->v != y->v) return x->v < y->v ? -1 : 1;
+  return (x->w > y->w) - (x->w < y->w);
+}
+
+/* Upper bound of the compressed size, for buffer allocation. */
+uint64_t orc_compress_bound(int32_t n, uint64_t two_m, int weighted) {
+  return (uint64_t)n * 10 + two_m * (weighted ? 10 : 5) + (two_m / ORC_CHUNK_LEN + 1) * 4 + 16;
+}
+
+/* Encodes one neighbourhood, already sorted by (id, weight), at `out`.
+ * Layout, in this order:
+ *   VarInt(first edge ID of u)     -- gives degrees and edge IDs (Section III-A)
+ *   if deg > 10 000: (ceil(deg/1000) - 1) little-endian uint32 byte offsets,
+ *                    relative to the start of this record, of chunks 2, 3, ...
+ *   per chunk of up to 1 000 neighbours:
+ *     VarInt(zigzag(v_0 - u)), then VarInt(v_i - v_{i-1}) for the rest (gap
+ *     encoding); if weighted, each neighbour code is followed by
+ *     VarInt(zigzag(w_i - w_{i-1})) with w_{-1} = 0 at the chunk start.
+ * Returns the number of bytes written. */
+static uint64_t encode_nbh(int32_t u, uint64_t first_edge, const orc_nb *nb, uint64_t deg,
+                           int weighted, uint8_t *out) {
+  uint64_t k = orc_varint_put(out, first_edge);
+  uint64_t nchunks = deg > ORC_CHUNK_THRESHOLD ? (deg + ORC_CHUNK_LEN - 1) / ORC_CHUNK_LEN : 1;
+  uint64_t table = k;
+  if (nchunks > 1) k += 4 * (nchunks - 1);
+  for (uint64_t ch = 0; ch < nchunks; ++ch) {
+    uint64_t b = ch * (nchunks > 1 ? ORC_CHUNK_LEN : 0);
+    uint64_t e = nchunks > 1 ? b + ORC_CHUNK_LEN : deg;
+    if (e > deg) e = deg;
+    if (ch > 0) {
+      uint32_t rel = (uint32_t)k;
+      memcpy(out + table + 4 * (ch - 1), &rel, 4);
+    }
+    int32_t wprev = 0;
+    for (uint64_t i = b; i < e; ++i) {
+      uint64_t code = (i == b) ? orc_zigzag((int64_t)nb[i].v - (int64_t)u)
+                               : (uint64_t)((int64_t)nb[i].v - (int64_t)nb[i - 1].v);
+      k += orc_varint_put(out + k, code);
+      if (weighted) {
+        k += orc_varint_put(out + k, orc_zigzag((int64_t)nb[i].w - (int64_t)wprev));
+        wprev = nb[i].w;
+      }
+    }
+  }
+  return k;
+}
+
+/* Compresses a CSR (neighbourhoods in any order; they are sorted here).
+ * offs gets n+1 byte offsets; bytes must hold orc_compress_bound() bytes. */
+int orc_compress(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
+                 uint64_t *offs, uint8_t *bytes, uint64_t *nbytes) {
+  uint64_t maxdeg = 0;
+  for (int32_t u = 0; u < n; ++u)
+    if (xadj[u + 1] - xadj[u] > maxdeg) maxdeg = xadj[u + 1] - xadj[u];
+  orc_nb *nb = (orc_nb *)malloc((maxdeg ? maxdeg : 1) * sizeof(orc_nb));
+  if (!nb) return ORC_ENOMEM;
+  uint64_t pos = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    uint64_t d = xadj[u + 1] - xadj[u];
+    for (uint64_t i = 0; i < d; ++i) {
+      nb[i].v = adjncy[xadj[u] + i];
+      nb[i].w = adjwgt ? adjwgt[xadj[u] + i] : 1;
+    }
+    qsort(nb, d, sizeof(orc_nb), cmp_nb);
+    offs[u] = pos;
+    pos += encode_nbh(u, xadj[u], nb, d, adjwgt != NULL, bytes + pos);
+  }
+  offs[n] = pos;
+  *nbytes = pos;
+  free(nb);
+  return ORC_OK;
+}
+
+/* Decodes the compressed graph back to CSR. Degrees come from the first-edge
+ * headers (deg(u) = fe(u+1) - fe(u), fe(n) = 2m). The chunk table of every
+ * split neighbourhood is checked against where the chunks actually start. */
+int orc_decompress(int32_t n, uint64_t two_m, int weighted, const uint64_t *offs,
+                   const uint8_t *bytes, uint64_t *xadj, int32_t *adjncy, int32_t *adjwgt) {
+  uint64_t end = offs[n];
+  uint64_t *fe = (uint64_t *)malloc(((size_t)n + 1) * sizeof(uint64_t));
+  if (!fe) return ORC_ENOMEM;
+  for (int32_t u = 0; u < n; ++u) {
+    uint64_t p = offs[u];
+    if (!orc_varint_get(bytes, end, &p, &fe[u])) { free(fe); return ORC_EFORMAT; }
+  }
+  fe[n] = two_m;
+  if (n > 0 && fe[0] != 0) { free(fe); return ORC_EFORMAT; }
+  for (int32_t u = 0; u <= n; ++u) {
+    if (u > 0 && fe[u] < fe[u - 1]) { free(fe); return ORC_EFORMAT; }
+    xadj[u] = fe[u];
+  }
+  for (int32_t u = 0; u < n; ++u) {
+    uint64_t deg = fe[u + 1] - fe[u];
+    uint64_t p = offs[u], hdr;
+    orc_varint_get(bytes, end, &p, &hdr);
+    uint64_t nchunks = deg > ORC_CHUNK_THRESHOLD ? (deg + ORC_CHUNK_LEN - 1) / ORC_CHUNK_LEN : 1;
+    uint64_t table = p;
+    if (nchunks > 1) p += 4 * (nchunks - 1);
+    int64_t prev = 0, wprev = 0;
+    for (uint64_t i = 0; i < deg; ++i) {
+      int chunk_start = (i == 0) || (nchunks > 1 && i % ORC_CHUNK_LEN == 0);
+      if (chunk_start && i > 0) {
+        uint32_t rel;
+        memcpy(&rel, bytes + table + 4 * (i / ORC_CHUNK_LEN - 1), 4);
+        if (offs[u] + rel != p) { free(fe); return ORC_EFORMAT; }
+      }
+      uint64_t code;
+      if (!orc_varint_get(bytes, offs[u + 1], &p, &code)) { free(fe); return ORC_EFORMAT; }
+      int64_t v = chunk_start ? (int64_t)u + orc_unzigzag(code) : prev + (int64_t)code;
+      if (v < 0 || v >= n) { free(fe); return ORC_EFORMAT; }
+      adjncy[fe[u] + i] = (int32_t)v;
+      prev = v;
+      if (chunk_start) wprev = 0;
+      if (weighted) {
+        uint64_t wc;
+        if (!orc_varint_get(bytes, offs[u + 1], &p, &wc)) { free(fe); return ORC_EFORMAT; }
+        int64_t w = wprev + orc_unzigzag(wc);
+        if (adjwgt) adjwgt[fe[u] + i] = (int32_t)w;
+        wprev = w;
+      } else if (adjwgt) {
+        adjwgt[fe[u] + i] = 1;
+      }
+    }
+    if (p != offs[u + 1]) { free(fe); return ORC_EFORMAT; }
+  }
+  free(fe);
+  return ORC_OK;
+}
+
+/* ---------------------------------------------- label propagation ---- */
+/* Tie-break priority of cluster c in round r: the SplitMix64 output function
+ * (Steele, Lea and Flood 2014) applied to seed XOR (r << 32) XOR c. It is a
+ * bijection of c, so two distinct clusters never share a priority. The
+ * smaller value wins a tie in rating. */
+uint64_t orc_tiebreak_key(uint64_t seed, uint32_t round, uint32_t c) {
+  uint64_t z = seed ^ ((uint64_t)round << 32) ^ (uint64_t)c;
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+typedef struct {
+  int32_t c;
+  int64_t r;
+} orc_rating;
+
+static int cmp_rating_label(const void *a, const void *b) {
+  const orc_rating *x = (const orc_rating *)a, *y = (const orc_rating *)b;
+  return (x->c > y->c) - (x->c < y->c);
+}
+
+typedef struct {
+  int32_t u, target;
+  int64_t gain, w;
+} orc_prop;
+
+static int cmp_prop(const void *a, const void *b) {
+  const orc_prop *x = (const orc_prop *)a, *y = (const orc_prop *)b;
+  if (x->target != y->target) return x->target < y->target ? -1 : 1;
+  if (x->gain != y->gain) return x->gain > y->gain ? -1 : 1; /* gain descending */
+  return (x->u > y->u) - (x->u < y->u);                      /* then vertex ascending */
+}
+
+typedef struct {
+  int32_t rounds_run;       /* rounds that made at least one proposal */
+  int64_t proposals[64];    /* per round (first 64 rounds) */
+  int64_t moves[64];
+} orc_lp_stats;
+
+/* The best move of u under the snapshot (C0, W0), or none.
+ * Rating of cluster c = sum of weights of the edges from u into c (Section
+ * IV-A1). Own = rating of u's current cluster. Candidates: clusters other
+ * than u's own with positive rating that can take u without exceeding the
+ * cap. The winner has the largest rating, ties broken by the smaller
+ * tie-break key. A move is proposed only if it strictly beats staying. */
+static int best_move(int32_t u, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
+                     const int32_t *vwgt, const int32_t *C0, const int64_t *W0, int64_t cap,
+                     uint64_t seed, uint32_t round, orc_rating *buf, int32_t *target, int64_t *gain) {
+  uint64_t d = xadj[u + 1] - xadj[u];
+  if (d == 0) return 0;
+  for (uint64_t i = 0; i < d; ++i) {
+    int32_t v = adjncy[xadj[u] + i];
+    buf[i].c = C0[v];
+    buf[i].r = adjwgt ? adjwgt[xadj[u] + i] : 1;
+  }
+  qsort(buf, d, sizeof(orc_rating), cmp_rating_label);
+  /* sum runs of equal labels into one rating per distinct cluster */
+  uint64_t k = 0;
+  for (uint64_t i = 0; i < d; ++i) {
+    if (k > 0 && buf[k - 1].c == buf[i].c) buf[k - 1].r += buf[i].r;
+    else buf[k++] = buf[i];
+  }
+  int32_t own_c = C0[u];
+  int64_t wu = vwgt ? vwgt[u] : 1;
+  int64_t own = 0;
+  int found = 0;
+  int32_t best_c = 0;
+  int64_t best_r = 0;
+  uint64_t best_key = 0;
+  for (uint64_t i = 0; i < k; ++i) {
+    int32_t c = buf[i].c;
+    if (c == own_c) {
+      own = buf[i].r;
+      continue;
+    }
+    if (buf[i].r <= 0) continue;
+    if (W0[c] + wu > cap) continue;
+    uint64_t key = orc_tiebreak_key(seed, round, (uint32_t)c);
+    if (!found || buf[i].r > best_r || (buf[i].r == best_r && key < best_key)) {
+      found = 1;
+      best_c = c;
+      best_r = buf[i].r;
+      best_key = key;
+    }
+  }
+  if (!found || best_r <= own) return 0;
+  *target = best_c;
+  *gain = best_r - own;
+  return 1;
+}
+
+/* Size-constrained LP clustering, synchronous rounds.
+ * Start: every vertex in its own cluster (C[u] = u, Section IV-A).
+ * Per round: every vertex computes its best move against the snapshot of
+ * the previous round; then, for each target cluster, the proposals are taken
+ * in (gain descending, vertex ascending) order and admitted while the
+ * running sum of their weights, added to the cluster's weight at the start of
+ * the round, stays within the cap; admitted vertices move. A round with no
+ * proposal is a fixed point, so the loop stops there.
+ * labels (out): n cluster IDs in [0, n); not renumbered. */
+int orc_lp_cluster(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
+                   const int32_t *vwgt, int64_t cap, int32_t rounds, uint64_t seed, int32_t *labels,
+                   orc_lp_stats *stats) {
+  if (n < 0 || cap < 1 || rounds < 0) return ORC_EINVAL;
+  if (stats) memset(stats, 0, sizeof(*stats));
+  int32_t *C0 = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+  int64_t *W = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+  int64_t *W0 = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+  int32_t *ptarget = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+  int64_t *pgain = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+  orc_prop *props = (orc_prop *)malloc(((size_t)n + 1) * sizeof(orc_prop));
+  if (!C0 || !W || !W0 || !ptarget || !pgain || !props) {
+    free(C0); free(W); free(W0); free(ptarget); free(pgain); free(props);
+    return ORC_ENOMEM;
+  }
+  uint64_t maxdeg = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    labels[u] = u;
+    W[u] = vwgt ? vwgt[u] : 1;
+    if (xadj[u + 1] - xadj[u] > maxdeg) maxdeg = xadj[u + 1] - xadj[u];
+  }
+  int status = ORC_OK;
+  for (int32_t r = 0; r < rounds; ++r) {
+    memcpy(C0, labels, (size_t)n * sizeof(int32_t));
+    memcpy(W0, W, (size_t)n * sizeof(int64_t));
+    int fail = 0;
+#pragma omp parallel
+    {
+      orc_rating *buf = (orc_rating *)malloc((maxdeg ? maxdeg : 1) * sizeof(orc_rating));
+      if (!buf) {
+#pragma omp atomic write
+        fail = 1;
+      }
+#pragma omp for schedule(dynamic, 256)
+      for (int32_t u = 0; u < n; ++u) {
+        ptarget[u] = -1;
+        if (buf && best_move(u, xadj, adjncy, adjwgt, vwgt, C0, W0, cap, seed, (uint32_t)r, buf,
+                             &ptarget[u], &pgain[u]) == 0)
+          ptarget[u] = -1;
+      }
+      free(buf);
+    }
+    if (fail) { status = ORC_ENOMEM; break; }
+    int64_t np = 0;
+    for (int32_t u = 0; u < n; ++u) {
+      if (ptarget[u] < 0) continue;
+      props[np].u = u;
+      props[np].target = ptarget[u];
+      props[np].gain = pgain[u];
+      props[np].w = vwgt ? vwgt[u] : 1;
+      ++np;
+    }
+    if (np == 0) break;
+    qsort(props, (size_t)np, sizeof(orc_prop), cmp_prop);
+    int64_t moves = 0;
+    for (int64_t i = 0; i < np;) {
+      int32_t c = props[i].target;
+      int64_t sum = 0;
+      int open = 1;
+      int64_t j = i;
+      for (; j < np && props[j].target == c; ++j) {
+        sum += props[j].w;
+        if (open && W0[c] + sum <= cap) {
+          labels[props[j].u] = c;
+          ++moves;
+        } else {
+          open = 0; /* longest admissible prefix: nothing after a rejection */
+        }
+      }
+      i = j;
+    }
+    /* cluster weights from scratch: W[c] = sum of w(u) over members of c */
+    for (int32_t c = 0; c < n; ++c) W[c] = 0;
+    for (int32_t u = 0; u < n; ++u) W[labels[u]] += vwgt ? vwgt[u] : 1;
+    if (stats) {
+      stats->rounds_run = r + 1;
+      if (r < 64) {
+        stats->proposals[r] = np;
+        stats->moves[r] = moves;
+      }
+    }
+  }
+  free(C0); free(W); free(W0); free(ptarget); free(pgain); free(props);
+  return status;
+}
+
+/* One LP round from an arbitrary snapshot, for sampled checks: fills the
+ * proposal (target or -1, gain) of each listed vertex. */
+int orc_lp_proposals(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
+                     const int32_t *vwgt, const int32_t *C0, const int64_t *W0, int64_t cap,
+                     uint64_t seed, int32_t round, int64_t count, const int32_t *vertices,
+                     int32_t *target, int64_t *gain) {
+  (void)n;
+  uint64_t maxdeg = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    int32_t u = vertices[i];
+    if (xadj[u + 1] - xadj[u] > maxdeg) maxdeg = xadj[u + 1] - xadj[u];
+  }
+  orc_rating *buf = (orc_rating *)malloc((maxdeg ? maxdeg : 1) * sizeof(orc_rating));
+  if (!buf) return ORC_ENOMEM;
+  for (int64_t i = 0; i < count; ++i) {
+    target[i] = -1;
+    gain[i] = 0;
+    best_move(vertices[i], xadj, adjncy, adjwgt, vwgt, C0, W0, cap, seed, (uint32_t)round, buf,
+              &target[i], &gain[i]);
+  }
+  free(buf);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------- contraction ---- */
+typedef struct {
+  int32_t b;
+  int64_t w;
+} orc_cedge;
+
+static int cmp_cedge(const void *a, const void *b) {
+  const orc_cedge *x = (const orc_cedge *)a, *y = (const orc_cedge *)b;
+  return (x->b > y->b) - (x->b < y->b);
+}
+
+/* Quotient graph of the clustering (Section IV-B): one coarse vertex per
+ * nonempty cluster, numbered by increasing cluster label; its weight is the
+ * sum of its members' weights; the coarse edge (a, b) carries the summed
+ * weight of all fine edges from members of a to members of b, for a != b
+ * (edges inside a cluster vanish). Neighbourhoods are sorted by coarse ID.
+ * Output arrays are allocated here (free with orc_free); map[u] = coarse ID
+ * of u's cluster. Returns ORC_EOVERFLOW if a coarse edge weight exceeds
+ * INT32_MAX. */
+int orc_contract(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
+                 const int32_t *vwgt, const int32_t *labels, int32_t *n_out, uint64_t **cxadj,
+                 int32_t **cadjncy, int32_t **cadjwgt, int32_t **cvwgt, int32_t *map) {
+  int32_t *id = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+  if (!id) return ORC_ENOMEM;
+  for (int32_t c = 0; c < n; ++c) id[c] = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    if (labels[u] < 0 || labels[u] >= n) { free(id); return ORC_EINVAL; }
+    id[labels[u]] = 1;
+  }
+  int32_t nc = 0;
+  for (int32_t c = 0; c < n; ++c) id[c] = id[c] ? nc++ : -1;
+  /* members of each coarse vertex, in increasing fine ID */
+  uint64_t *mstart = (uint64_t *)calloc((size_t)nc + 1, sizeof(uint64_t));
+  int32_t *members = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+  int32_t *vw = (int32_t *)calloc((size_t)nc + 1, sizeof(int32_t));
+  int64_t *vw64 = (int64_t *)calloc((size_t)nc + 1, sizeof(int64_t));
+  if (!mstart || !members || !vw || !vw64) { free(id); free(mstart); free(members); free(vw); free(vw64); return ORC_ENOMEM; }
+  for (int32_t u = 0; u < n; ++u) mstart[id[labels[u]] + 1]++;
+  for (int32_t a = 0; a < nc; ++a) mstart[a + 1] += mstart[a];
+  {
+    uint64_t *fill = (uint64_t *)malloc(((size_t)nc + 1) * sizeof(uint64_t));
+    if (!fill) { free(id); free(mstart); free(members); free(vw); free(vw64); return ORC_ENOMEM; }
+    memcpy(fill, mstart, ((size_t)nc + 1) * sizeof(uint64_t));
+    for (int32_t u = 0; u < n; ++u) members[fill[id[labels[u]]]++] = u;
+    free(fill);
+  }
+  int status = ORC_OK;
+  for (int32_t u = 0; u < n; ++u) {
+    int32_t a = id[labels[u]];
+    map[u] = a;
+    vw64[a] += vwgt ? vwgt[u] : 1;
+  }
+  for (int32_t a = 0; a < nc; ++a) {
+    if (vw64[a] > INT32_MAX) status = ORC_EOVERFLOW;
+    vw[a] = (int32_t)vw64[a];
+  }
+  free(vw64);
+  /* per coarse vertex: gather (coarse neighbour, weight), sort, sum runs */
+  uint64_t *cx = (uint64_t *)calloc((size_t)nc + 1, sizeof(uint64_t));
+  uint64_t cap_edges = 1024, used = 0;
+  int32_t *ca = (int32_t *)malloc(cap_edges * sizeof(int32_t));
+  int32_t *cw = (int32_t *)malloc(cap_edges * sizeof(int32_t));
+  uint64_t bufcap = 1024;
+  orc_cedge *buf = (orc_cedge *)malloc(bufcap * sizeof(orc_cedge));
+  if (!cx || !ca || !cw || !buf) { status = ORC_ENOMEM; goto done; }
+  for (int32_t a = 0; a < nc; ++a) {
+    uint64_t k = 0;
+    for (uint64_t m = mstart[a]; m < mstart[a + 1]; ++m) {
+      int32_t u = members[m];
+      for (uint64_t e = xadj[u]; e < xadj[u + 1]; ++e) {
+        int32_t b = id[labels[adjncy[e]]];
+        if (b == a) continue;
+        if (k == bufcap) {
+          bufcap *= 2;
+          orc_cedge *nb = (orc_cedge *)realloc(buf, bufcap * sizeof(orc_cedge));
+          if (!nb) { status = ORC_ENOMEM; goto done; }
+          buf = nb;
+        }
+        buf[k].b = b;
+        buf[k].w = adjwgt ? adjwgt[e] : 1;
+        ++k;
+      }
+    }
+    qsort(buf, k, sizeof(orc_cedge), cmp_cedge);
+    uint64_t j = 0;
+    for (uint64_t i = 0; i < k; ++i) {
+      if (j > 0 && buf[j - 1].b == buf[i].b) buf[j - 1].w += buf[i].w;
+      else buf[j++] = buf[i];
+    }
+    while (used + j > cap_edges) {
+      cap_edges *= 2;
+      int32_t *na = (int32_t *)realloc(ca, cap_edges * sizeof(int32_t));
+      if (!na) { status = ORC_ENOMEM; goto done; }
+      ca = na;
+      int32_t *nw = (int32_t *)realloc(cw, cap_edges * sizeof(int32_t));
+      if (!nw) { status = ORC_ENOMEM; goto done; }
+      cw = nw;
+    }
+    for (uint64_t i = 0; i < j; ++i) {
+      if (buf[i].w > INT32_MAX) status = ORC_EOVERFLOW;
+      ca[used + i] = buf[i].b;
+      cw[used + i] = (int32_t)buf[i].w;
+    }
+    used += j;
+    cx[a + 1] = used;
+  }
+done:
+  free(buf);
+  free(id);
+  free(mstart);
+  free(members);
+  if (status == ORC_ENOMEM) { free(cx); free(ca); free(cw); free(vw); return status; }
+  *n_out = nc;
+  *cxadj = cx;
+  *cadjncy = ca;
+  *cadjwgt = cw;
+  *cvwgt = vw;
+  return status;
+}
+
+void orc_free(void *p) { free(p); }
+
+/* Edge cut (Section I): total weight of edges whose endpoints lie in
+ * different clusters. Each undirected edge appears twice in the CSR, hence
+ * the halving. */
+int64_t orc_edge_cut(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
+                     const int32_t *labels) {
+  int64_t s = 0;
+  for (int32_t u = 0; u < n; ++u)
+    for (uint64_t e = xadj[u]; e < xadj[u + 1]; ++e)
+      if (labels[u] != labels[adjncy[e]]) s += adjwgt ? adjwgt[e] : 1;
+  return s / 2;
+}

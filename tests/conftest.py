@@ -1,0 +1,44 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs a HIP device (MI355X) and the built library")
+
+
+def gpu_available() -> bool:
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+@pytest.fixture(scope="session")
+def oracle_mod():
+    import oracle
+    oracle._load()
+    return oracle
+
+
+@pytest.fixture(scope="session")
+def synth_mod():
+    import synth
+    synth._load()
+    return synth
+
+
+@pytest.fixture(scope="session")
+def lp():
+    """The GPU library binding; fails loudly if it is not built or no device."""
+    import paper_2410_19119_amd as m
+    m._load()
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return m
