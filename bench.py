@@ -1,0 +1,198 @@
+"""Benchmark: LP-round edges/s of size-constrained label propagation on a
+compressed R-MAT graph, one MI355X.
+
+One step = one pass of the whole hot path over the resident compressed graph:
+lp_cluster (degree buckets + 5 synchronous rounds of rating, acceptance and
+apply), lp_contract (coarse graph) and lp_edge_cut. The graph is generated,
+compressed and made resident before the timed region.
+
+Workload (default): R-MAT scale 24, edge factor 16 (2^28 samples),
+(a, b, c, d) = (0.57, 0.19, 0.19, 0.05), symmetrised, self-loops and
+duplicates removed, no ID permutation, unit weights, max cluster weight 256,
+5 rounds, seed 1.
+
+value = 2m * rounds run / step time (directed adjacency entries processed per
+second per LP round, contraction and cut included in the step time).
+The JSON line also carries the LP-only round rate, a per-phase breakdown,
+the roofline of the dominant kernel (algorithmic bytes / event-timed launch
+duration against 8 TB/s HBM) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PHASE_KERNEL = {
+    "lane": "k_rate_lane",
+    "wave": "k_rate_group<64>",
+    "block": "k_rate_group<512>",
+    "hub": "k_hub_scatter+k_hub_reduce+k_hub_combine",
+    "accept": "acceptance (compaction, radix sort, segmented scan, admit, apply)",
+}
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def workload(name: str):
+    import synth
+    if name == "rmat24":
+        return synth.rmat_scale(24, 16, seed=1), 256, "rmat-s24-ef16 (0.57,0.19,0.19,0.05), unit weights"
+    if name == "rmat20":
+        return synth.rmat_scale(20, 16, seed=1), 256, "rmat-s20-ef16 (0.57,0.19,0.19,0.05), unit weights"
+    if name == "rgg2d16k":
+        return synth.rgg2d_16k(seed=1), 32, "rgg2d n=16384 avg-deg~8, unit weights"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def phase_bytes(st, phase: str, n_per_bucket, proposals) -> float:
+    """Algorithmic bytes of one launch of a phase (one round)."""
+    idx = {"lane": 0, "wave": 1, "block": 2, "hub": 3}
+    if phase in idx:
+        b = idx[phase]
+        nv = n_per_bucket[b]
+        # compressed records + per-edge label gather + per-vertex offset,
+        # degree, list entry, own label, one cluster weight, proposal writes
+        return st.bucket_bytes[b] + 4.0 * st.bucket_edges[b] + 40.0 * nv
+    if phase == "accept":
+        return 4.0 * sum(n_per_bucket) + 20.0 * proposals
+    return 0.0
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat24")
+    ap.add_argument("--rounds", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-rounds", type=int, default=1, help="oracle rounds timed for the baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a design "
+              f"note, not part of this build", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2410_19119_amd as lp
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    g, cap, desc = workload(args.workload)
+    log(f"[bench] generated {desc}: n={g.n} 2m={g.two_m} in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    G = lp.lp_compress(g.n, g.xadj.view(np.int64), g.adjncy)
+    torch.cuda.synchronize()
+    log(f"[bench] compressed on GPU: {G.nbytes} bytes ({G.nbytes / max(g.two_m, 1):.3f} B/edge) "
+        f"in {time.time() - t0:.1f}s")
+    labels = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    cfg = dict(timing=1)
+
+    def step():
+        lab, st = lp.lp_cluster(G, cap, args.rounds, 1, labels=labels, config=cfg, stats=True)
+        C, _ = lp.lp_contract(G, lab, want_map=False)
+        cut = lp.lp_edge_cut(G, lab)
+        n_coarse = C.n
+        C.free()
+        return st, cut, n_coarse
+
+    for i in range(args.warmup):
+        step()
+        log(f"[bench] warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    times, stats = [], []
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, cut, n_coarse = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        stats.append(st)
+        log(f"[bench] step {i + 1}/{args.steps}: {times[-1] * 1e3:.2f} ms, rounds {st.rounds_run}, "
+            f"coarse n {n_coarse}, cut {cut}")
+    total = sum(times)
+    ms_per_step = 1e3 * total / args.steps
+    st = stats[-1]
+    rounds_run = st.rounds_run
+    value = g.two_m * rounds_run * args.steps / total
+
+    # LP-only round rate and per-phase breakdown (event-timed, last step)
+    round_phases = ("lane", "wave", "block", "hub", "accept")
+    lp_ms = sum(st.phase_ms[p] for p in round_phases)
+    lp_round_rate = g.two_m * rounds_run / (lp_ms / 1e3) if lp_ms > 0 else None
+    nb = st.buckets
+    props = sum(st.proposals) / max(1, len(st.proposals))
+    phases = {}
+    for p in round_phases:
+        launches = st.phase_launches[p]
+        if not launches:
+            continue
+        avg_ms = st.phase_ms[p] / launches
+        b = phase_bytes(st, p, nb, props)
+        phases[p] = {"kernel": PHASE_KERNEL[p], "launches": launches, "avg_ms": round(avg_ms, 4),
+                     "alg_bytes": int(b), "alg_GBs": round(b / (avg_ms / 1e3) / 1e9, 1) if avg_ms > 0 else None}
+    dom = max((p for p in phases if p != "accept"), key=lambda p: phases[p]["avg_ms"], default=None)
+    roofline = None
+    if dom:
+        ach = phases[dom]["alg_GBs"]
+        roofline = {"bound": "hbm", "kernel": phases[dom]["kernel"], "achieved": ach, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "alg_bytes_per_launch": phases[dom]["alg_bytes"], "avg_launch_ms": phases[dom]["avg_ms"]}
+    round_bytes = sum(phases[p]["alg_bytes"] for p in phases)
+    round_ms = sum(phases[p]["avg_ms"] for p in phases)
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        oracle.set_threads(threads)
+        t = time.perf_counter()
+        _, ost = oracle.lp_cluster(g, cap, args.cpu_rounds, 1)
+        dt = time.perf_counter() - t
+        cpu = {"value": g.two_m * args.cpu_rounds / dt, "unit": "edges/s", "cores": threads, "kind": "oracle",
+               "sample": f"oracle lp_cluster, first {args.cpu_rounds} round(s) over the full graph "
+                         f"({dt:.1f} s wall)"}
+        log(f"[bench] cpu oracle: {args.cpu_rounds} round(s) in {dt:.1f}s with {threads} threads")
+
+    out = {
+        "metric": "LP-round edges/s",
+        "value": value,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": desc, "n": g.n, "two_m": g.two_m, "compressed_bytes": G.nbytes,
+                   "max_cluster_weight": cap, "rounds": args.rounds, "rounds_run": rounds_run, "seed": 1,
+                   "step": "lp_cluster + lp_contract + lp_edge_cut"},
+        "lp_round_edges_per_s": lp_round_rate,
+        "round_model": {"alg_bytes": int(round_bytes), "ms": round(round_ms, 4),
+                        "frac_hbm": round(round_bytes / (round_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if round_ms else None},
+        "phases": phases,
+        "setup_ms": round(st.phase_ms["setup"], 3),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,225 @@
+/*
+ * lp.h — C ABI of the MI355X label-propagation coarsening library.
+ *
+ * The library implements the coarsening hot path of the multilevel graph
+ * partitioner in "Tera-Scale Multilevel Graph Partitioning" (arxiv 2410.19119):
+ * size-constrained label-propagation (LP) clustering run directly on a
+ * gap + VarInt compressed adjacency (Section III-A), with the two-phase split
+ * of low- and high-degree vertices (Section IV-A2), followed by cluster
+ * contraction (Section IV-B). Every step runs in hand-written HIP kernels for
+ * gfx950.
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers named *_dev are device pointers on the current HIP device; all
+ *    other pointers are host pointers. No pointer is retained after a call
+ *    returns, except inside the lp_graph handles the library creates.
+ *  - `stream` is a hipStream_t (NULL = the default stream). Calls enqueue
+ *    their work on it; results written to device buffers are valid once the
+ *    stream has reached that point. Calls that return host values
+ *    (lp_graph_info, lp_edge_cut, lp_cluster_ex with stats, lp_compress,
+ *    lp_contract) synchronise the stream before returning.
+ *  - Scratch memory is taken from the device's stream-ordered pool
+ *    (hipMallocAsync on `stream`) and released before the call returns.
+ *  - Errors are returned as lp_status codes; no exception crosses the ABI.
+ *    Argument errors are detected before any work is enqueued. A device
+ *    fault surfaces as LP_EDEVICE from the next synchronising call.
+ *  - Handles are immutable after creation; one handle may be used from
+ *    several streams at once. Each handle must be freed with lp_graph_free.
+ *  - Integer widths: vertex IDs and labels int32 (n < 2^31), edge counts
+ *    and offsets uint64, input edge / vertex weights int32 >= 1, ratings,
+ *    gains, cluster weights and caps int64.
+ */
+#ifndef LP_H_
+#define LP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lp_graph lp_graph;
+typedef int32_t lp_status;
+
+#define LP_OK 0
+#define LP_EINVAL (-1)       /* bad argument or malformed input graph */
+#define LP_ENOMEM (-2)       /* device allocation failed */
+#define LP_EOVERFLOW (-3)    /* a coarse weight would exceed INT32_MAX */
+#define LP_EDEVICE (-4)      /* a HIP call or kernel failed */
+#define LP_EUNSUPPORTED (-5) /* input outside the supported range (see the call) */
+
+/* Neighbourhoods longer than this are split into independently decodable
+ * chunks of LP_CHUNK_LEN neighbours (Section III-A). Fixed by the format. */
+#define LP_CHUNK_THRESHOLD 10000
+#define LP_CHUNK_LEN 1000
+
+/* Human-readable name of a status code (static string). */
+const char *lp_strerror(lp_status s);
+
+/* Library version string. */
+const char *lp_version(void);
+
+/*
+ * lp_compress — build a compressed graph handle from a CSR (Section III-A).
+ *
+ * Input (device pointers, read only, owned by the caller):
+ *   n            number of vertices, 0 <= n < 2^31
+ *   xadj_dev     uint64[n+1], xadj[0] = 0, non-decreasing; neighbours of u
+ *                are adjncy[xadj[u] .. xadj[u+1])
+ *   adjncy_dev   int32[2m] neighbour IDs
+ *   adjwgt_dev   int32[2m] edge weights >= 1, or NULL for unit weights
+ *   vwgt_dev     int32[n] vertex weights >= 1, or NULL for unit weights
+ * The graph must be symmetric (u in N(v) iff v in N(u), with equal weights;
+ * this is not checked), without self-loops, with every neighbourhood sorted
+ * by (neighbour ID, weight); duplicate neighbours are allowed.
+ *
+ * Encoding of vertex u's record (byte offset offs[u], offs uint64[n+1]):
+ *   VarInt(first edge ID of u)   (degrees come from consecutive headers)
+ *   if deg(u) > LP_CHUNK_THRESHOLD: ceil(deg/LP_CHUNK_LEN) - 1 little-endian
+ *     uint32 byte offsets, relative to offs[u], of chunks 2, 3, ...
+ *   per chunk (the whole neighbourhood if not split): VarInt(zigzag(v0 - u)),
+ *     then VarInt(v_i - v_{i-1}) per further neighbour (gap encoding); if
+ *     adjwgt is given, every neighbour code is followed by
+ *     VarInt(zigzag(w_i - w_{i-1})), w_{-1} = 0 at each chunk start.
+ * VarInt = LEB128: 7 data bits per byte, low group first, bit 7 set when
+ * another byte follows (Section III-A). Interval encoding is not used.
+ *
+ * Output: *out receives a new handle owning device copies of the compressed
+ * bytes, offsets and vertex weights. Synchronises `stream`.
+ * Errors: LP_EINVAL for a neighbour ID out of range, a self-loop, a weight
+ * < 1, or an unsorted neighbourhood; LP_ENOMEM; LP_EDEVICE.
+ */
+lp_status lp_compress(int32_t n, const uint64_t *xadj_dev, const int32_t *adjncy_dev,
+                      const int32_t *adjwgt_dev, const int32_t *vwgt_dev, void *stream,
+                      lp_graph **out);
+
+/*
+ * lp_graph_from_csr — plain (uncompressed) CSR handle, same input contract
+ * as lp_compress. The library copies the arrays. Coarse graphs produced by
+ * lp_contract are handles of this kind (the paper compresses only the input
+ * graph, Section II-C).
+ */
+lp_status lp_graph_from_csr(int32_t n, const uint64_t *xadj_dev, const int32_t *adjncy_dev,
+                            const int32_t *adjwgt_dev, const int32_t *vwgt_dev, void *stream,
+                            lp_graph **out);
+
+/* Sizes of a handle (host outputs; any may be NULL). nbytes = compressed
+ * adjacency bytes (0 for plain handles); total_vwgt = sum of vertex weights. */
+lp_status lp_graph_info(const lp_graph *g, int32_t *n, uint64_t *two_m, uint64_t *nbytes,
+                        int32_t *is_compressed, int32_t *has_edge_weights, int64_t *total_vwgt);
+
+/* Copies the compressed representation of a compressed handle into caller
+ * buffers: offs_dev uint64[n+1], bytes_dev uint8[nbytes]. LP_EINVAL for a
+ * plain handle. */
+lp_status lp_graph_export(const lp_graph *g, uint64_t *offs_dev, uint8_t *bytes_dev, void *stream);
+
+/*
+ * lp_decompress — decode a handle back to CSR (device outputs, caller
+ * sized): xadj_dev uint64[n+1], adjncy_dev int32[2m], adjwgt_dev int32[2m]
+ * (may be NULL; unit weights are written as 1), vwgt_dev int32[n] (may be
+ * NULL). Neighbourhoods come out sorted by (ID, weight).
+ */
+lp_status lp_decompress(const lp_graph *g, uint64_t *xadj_dev, int32_t *adjncy_dev,
+                        int32_t *adjwgt_dev, int32_t *vwgt_dev, void *stream);
+
+/*
+ * Result-invariant tuning knobs of lp_cluster: degree-bucket thresholds.
+ * Vertices of degree 1..t_lane are rated one per lane, up to t_wave one per
+ * wavefront, up to t_block one per workgroup (LDS rating tables, Section
+ * IV-A2 first phase); higher-degree vertices go to the chunk-parallel hub
+ * path (second phase). Any valid setting gives identical labels.
+ * Zero fields mean "default".
+ */
+typedef struct {
+  int32_t t_lane;   /* 0..16, default 16 */
+  int32_t t_wave;   /* t_lane..512, default 256 */
+  int32_t t_block;  /* t_wave..8192, default 8192 (4096 if ratings need 64 bits) */
+  int32_t hub_part; /* target edges per hub partition, 256..8192, default 4096 */
+  int32_t timing;   /* nonzero: time each phase with HIP events (stats must be given) */
+} lp_config;
+
+/* Phases timed when lp_config.timing is set (milliseconds summed over rounds). */
+#define LP_PHASE_SETUP 0  /* degrees, buckets, hub metadata, initial labels */
+#define LP_PHASE_LANE 1   /* rating, lane-per-vertex bucket */
+#define LP_PHASE_WAVE 2   /* rating, wavefront-per-vertex bucket */
+#define LP_PHASE_BLOCK 3  /* rating, workgroup-per-vertex bucket */
+#define LP_PHASE_HUB 4    /* rating, hub path (scatter, reduce, combine) */
+#define LP_PHASE_ACCEPT 5 /* proposal compaction, sort, admission, apply */
+#define LP_NUM_PHASES 6
+
+/* Per-call statistics (host struct, filled when requested). */
+typedef struct {
+  int32_t rounds_run;         /* rounds that had at least one proposal */
+  int32_t n_lane, n_wave, n_block, n_hub; /* bucket sizes (vertices) */
+  int64_t proposals[64];      /* per round */
+  int64_t moves[64];          /* per round */
+  uint64_t bucket_edges[4];   /* adjacency entries per bucket (lane, wave, block, hub) */
+  uint64_t bucket_bytes[4];   /* compressed record bytes per bucket (0 for plain graphs) */
+  float phase_ms[LP_NUM_PHASES]; /* filled when lp_config.timing is set */
+  int32_t phase_launches[LP_NUM_PHASES]; /* rounds in which the phase ran */
+} lp_cluster_stats;
+
+/*
+ * lp_cluster — size-constrained label-propagation clustering.
+ *
+ * Semantics (Section IV-A, Algorithm 1 for what a vertex computes; rounds
+ * are synchronous as in the batch-synchronous distributed LP of Section II-B):
+ *   Start: C[u] = u, W[c] = weight of vertex c.
+ *   Each round r = 0..rounds-1 reads the snapshot (C0, W0) of the previous
+ *   round. For every u with neighbours: rating R(c) = sum of weights of the
+ *   edges from u to vertices v with C0[v] = c (Section IV-A1); own =
+ *   R(C0[u]). The best c != C0[u] with W0[c] + w(u) <= max_cluster_weight
+ *   maximises R(c), ties broken by the smaller SplitMix64 key of
+ *   (seed ^ (r << 32) ^ c). u proposes it iff R(c) > own, with gain
+ *   R(c) - own. Proposals to each target are ordered by (gain desc, u asc)
+ *   and admitted while W0[c] + the running sum of their weights stays
+ *   <= max_cluster_weight; admitted vertices move. A round without any
+ *   proposal ends the call early (the state is a fixed point).
+ * Arguments: g (compressed or plain handle), max_cluster_weight >= 1,
+ * rounds >= 0, seed, labels_dev int32[n] (output; labels are vertex IDs in
+ * [0, n), not renumbered).
+ * Errors: LP_EINVAL (cap < 1, rounds < 0, NULL labels); LP_ENOMEM;
+ * LP_EUNSUPPORTED if a vertex's weighted degree needs more than 64 - log2(n)
+ * bits.
+ */
+lp_status lp_cluster(const lp_graph *g, int64_t max_cluster_weight, int32_t rounds, uint64_t seed,
+                     int32_t *labels_dev, void *stream);
+
+/* lp_cluster with knobs (cfg may be NULL) and optional statistics (stats may
+ * be NULL; when given the call synchronises `stream`). */
+lp_status lp_cluster_ex(const lp_graph *g, int64_t max_cluster_weight, int32_t rounds, uint64_t seed,
+                        int32_t *labels_dev, const lp_config *cfg, lp_cluster_stats *stats,
+                        void *stream);
+
+/*
+ * lp_contract — quotient graph of a clustering (Section IV-B).
+ * Coarse vertex IDs are the ranks of the nonempty labels in increasing order;
+ * the weight of a coarse vertex is the sum of its members' weights; the
+ * coarse edge (a, b), a != b, carries the summed weight of all fine edges
+ * between members of a and members of b; edges inside a cluster vanish.
+ * Neighbourhoods are sorted by coarse ID.
+ * Arguments: g, labels_dev int32[n] with values in [0, n), map_dev int32[n]
+ * (output, fine vertex -> coarse vertex; may be NULL), *coarse_out receives a
+ * new plain handle. Synchronises `stream`.
+ * Errors: LP_EINVAL (label out of range), LP_EOVERFLOW (a coarse edge or
+ * vertex weight exceeds INT32_MAX), LP_ENOMEM.
+ */
+lp_status lp_contract(const lp_graph *g, const int32_t *labels_dev, int32_t *map_dev, void *stream,
+                      lp_graph **coarse_out);
+
+/*
+ * lp_edge_cut — total weight of the edges whose endpoints carry different
+ * labels (the cut of Section I, each undirected edge counted once).
+ * *cut_out is a host int64. Synchronises `stream`.
+ */
+lp_status lp_edge_cut(const lp_graph *g, const int32_t *labels_dev, int64_t *cut_out, void *stream);
+
+/* Frees a handle (NULL is ignored). Waits for the device to be idle first. */
+void lp_graph_free(lp_graph *g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LP_H_ */

@@ -1,0 +1,305 @@
+"""Python binding of the MI355X label-propagation coarsening library.
+
+Argument marshalling only: every step runs in the HIP kernels of
+``liblpgpu.so`` (built by :func:`build`), reached through the C ABI declared
+in ``include/lp.h``. PyTorch provides device memory and streams. There is no
+CPU fallback: importing works without a GPU, but every call needs the built
+library and a HIP device and raises otherwise.
+
+Entry points mirror the C names: :func:`lp_compress`, :func:`lp_graph_from_csr`,
+:func:`lp_decompress`, :func:`lp_cluster`, :func:`lp_contract`,
+:func:`lp_edge_cut`, plus the multilevel loop :func:`coarsen`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from ._build import LIB as _LIB_PATH
+from ._build import build as _build_lib
+
+LP_OK, LP_EINVAL, LP_ENOMEM, LP_EOVERFLOW, LP_EDEVICE, LP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+LP_CHUNK_THRESHOLD = 10000
+LP_CHUNK_LEN = 1000
+
+_P = ctypes.c_void_p
+_lib = None
+
+
+class LPError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _load().lp_strerror(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{where}: {msg} ({status})")
+
+
+PHASES = ("setup", "lane", "wave", "block", "hub", "accept")
+
+
+class lp_config(ctypes.Structure):
+    _fields_ = [("t_lane", ctypes.c_int32), ("t_wave", ctypes.c_int32),
+                ("t_block", ctypes.c_int32), ("hub_part", ctypes.c_int32), ("timing", ctypes.c_int32)]
+
+
+class lp_cluster_stats(ctypes.Structure):
+    _fields_ = [("rounds_run", ctypes.c_int32), ("n_lane", ctypes.c_int32), ("n_wave", ctypes.c_int32),
+                ("n_block", ctypes.c_int32), ("n_hub", ctypes.c_int32),
+                ("proposals", ctypes.c_int64 * 64), ("moves", ctypes.c_int64 * 64),
+                ("bucket_edges", ctypes.c_uint64 * 4), ("bucket_bytes", ctypes.c_uint64 * 4),
+                ("phase_ms", ctypes.c_float * 6), ("phase_launches", ctypes.c_int32 * 6)]
+
+
+def build() -> str:
+    """Compile the HIP library for gfx950 (always recompiles)."""
+    return _build_lib()
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is not built; run paper_2410_19119_amd.build()")
+    # torch first: its HIP runtime then satisfies the library's libamdhip64.so.7
+    # dependency, so one runtime serves both (two runtimes in one process do
+    # not share devices, memory or streams).
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(_LIB_PATH)
+    S = ctypes.c_int32
+    lib.lp_strerror.argtypes = [S]
+    lib.lp_strerror.restype = ctypes.c_char_p
+    lib.lp_version.restype = ctypes.c_char_p
+    lib.lp_compress.argtypes = [ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]
+    lib.lp_compress.restype = S
+    lib.lp_graph_from_csr.argtypes = [ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]
+    lib.lp_graph_from_csr.restype = S
+    lib.lp_graph_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint64),
+                                  ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
+    lib.lp_graph_info.restype = S
+    lib.lp_graph_export.argtypes = [_P, _P, _P, _P]
+    lib.lp_graph_export.restype = S
+    lib.lp_decompress.argtypes = [_P, _P, _P, _P, _P, _P]
+    lib.lp_decompress.restype = S
+    lib.lp_cluster.argtypes = [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, _P, _P]
+    lib.lp_cluster.restype = S
+    lib.lp_cluster_ex.argtypes = [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, _P,
+                                  ctypes.POINTER(lp_config), ctypes.POINTER(lp_cluster_stats), _P]
+    lib.lp_cluster_ex.restype = S
+    lib.lp_contract.argtypes = [_P, _P, _P, _P, ctypes.POINTER(_P)]
+    lib.lp_contract.restype = S
+    lib.lp_edge_cut.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_int64), _P]
+    lib.lp_edge_cut.restype = S
+    lib.lp_graph_free.argtypes = [_P]
+    lib.lp_graph_free.restype = None
+    _lib = lib
+    return lib
+
+
+def exported_symbols() -> list[str]:
+    return ["lp_strerror", "lp_version", "lp_compress", "lp_graph_from_csr", "lp_graph_info",
+            "lp_graph_export", "lp_decompress", "lp_cluster", "lp_cluster_ex", "lp_contract",
+            "lp_edge_cut", "lp_graph_free"]
+
+
+def _check(st: int, where: str) -> None:
+    if st != LP_OK:
+        raise LPError(st, where)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("a HIP device is required (no CPU fallback)")
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(a, dtype):
+    """Device tensor of `dtype` (copies numpy / host tensors; None stays None)."""
+    if a is None:
+        return None
+    torch = _torch()
+    if isinstance(a, np.ndarray):
+        a = torch.from_numpy(np.ascontiguousarray(a))
+    t = a.to(device="cuda", dtype=dtype)
+    return t.contiguous()
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Graph:
+    """Owns an ``lp_graph`` handle (device-resident, immutable)."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+        n = ctypes.c_int32()
+        two_m = ctypes.c_uint64()
+        nb = ctypes.c_uint64()
+        comp = ctypes.c_int32()
+        wt = ctypes.c_int32()
+        tot = ctypes.c_int64()
+        _check(_load().lp_graph_info(handle, n, two_m, nb, comp, wt, tot), "lp_graph_info")
+        self.n = n.value
+        self.two_m = two_m.value
+        self.nbytes = nb.value
+        self.compressed = bool(comp.value)
+        self.weighted = bool(wt.value)
+        self.total_vwgt = tot.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self) -> None:
+        if self._h is not None and _lib is not None:
+            _lib.lp_graph_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __repr__(self):
+        kind = "compressed" if self.compressed else "plain"
+        return f"Graph(n={self.n}, 2m={self.two_m}, {kind}, bytes={self.nbytes})"
+
+
+def _make(fn_name: str, n, xadj, adjncy, adjwgt=None, vwgt=None, stream=None) -> Graph:
+    torch = _torch()
+    lib = _load()
+    x = _dev(xadj, torch.int64)  # uint64 bit pattern
+    a = _dev(adjncy, torch.int32)
+    if a.numel() == 0:
+        a = torch.zeros(1, dtype=torch.int32, device="cuda")
+    w = _dev(adjwgt, torch.int32)
+    v = _dev(vwgt, torch.int32)
+    h = _P()
+    st = getattr(lib, fn_name)(int(n), _ptr(x), _ptr(a), _ptr(w), _ptr(v), _stream(stream), ctypes.byref(h))
+    _check(st, fn_name)
+    return Graph(h)
+
+
+def lp_compress(n, xadj, adjncy, adjwgt=None, vwgt=None, stream=None) -> Graph:
+    """Compressed handle from a CSR (numpy or tensors; copied to the device)."""
+    return _make("lp_compress", n, xadj, adjncy, adjwgt, vwgt, stream)
+
+
+def lp_graph_from_csr(n, xadj, adjncy, adjwgt=None, vwgt=None, stream=None) -> Graph:
+    """Plain CSR handle."""
+    return _make("lp_graph_from_csr", n, xadj, adjncy, adjwgt, vwgt, stream)
+
+
+def lp_graph_export(g: Graph, stream=None):
+    """(offs, bytes) device tensors of a compressed handle."""
+    torch = _torch()
+    offs = torch.empty(g.n + 1, dtype=torch.int64, device="cuda")
+    data = torch.empty(max(g.nbytes, 1), dtype=torch.uint8, device="cuda")
+    _check(_load().lp_graph_export(g.handle, _ptr(offs), _ptr(data), _stream(stream)), "lp_graph_export")
+    return offs, data[: g.nbytes]
+
+
+def lp_decompress(g: Graph, stream=None):
+    """(xadj, adjncy, adjwgt, vwgt) device tensors (int64 / int32)."""
+    torch = _torch()
+    xadj = torch.empty(g.n + 1, dtype=torch.int64, device="cuda")
+    adj = torch.empty(max(g.two_m, 1), dtype=torch.int32, device="cuda")
+    wgt = torch.empty(max(g.two_m, 1), dtype=torch.int32, device="cuda")
+    vw = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda")
+    _check(_load().lp_decompress(g.handle, _ptr(xadj), _ptr(adj), _ptr(wgt), _ptr(vw), _stream(stream)),
+           "lp_decompress")
+    return xadj, adj[: g.two_m], wgt[: g.two_m], vw[: g.n]
+
+
+@dataclass
+class ClusterStats:
+    rounds_run: int
+    buckets: tuple
+    proposals: list = field(default_factory=list)
+    moves: list = field(default_factory=list)
+    bucket_edges: tuple = ()
+    bucket_bytes: tuple = ()
+    phase_ms: dict = field(default_factory=dict)
+    phase_launches: dict = field(default_factory=dict)
+
+
+def lp_cluster(g: Graph, max_cluster_weight: int, rounds: int = 5, seed: int = 1, labels=None,
+               config: dict | None = None, stats: bool = False, stream=None):
+    """Size-constrained LP labels (int32 device tensor); with stats=True also ClusterStats."""
+    torch = _torch()
+    if labels is None:
+        labels = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda")
+    cfg = None
+    if config:
+        cfg = lp_config(**{k: int(v) for k, v in config.items()})
+    st_obj = lp_cluster_stats() if stats else None
+    st = _load().lp_cluster_ex(g.handle, int(max_cluster_weight), int(rounds), int(seed) & (2**64 - 1),
+                               _ptr(labels), ctypes.byref(cfg) if cfg else None,
+                               ctypes.byref(st_obj) if st_obj is not None else None, _stream(stream))
+    _check(st, "lp_cluster")
+    out = labels[: g.n]
+    if stats:
+        k = min(st_obj.rounds_run, 64)
+        return out, ClusterStats(st_obj.rounds_run, (st_obj.n_lane, st_obj.n_wave, st_obj.n_block, st_obj.n_hub),
+                                 list(st_obj.proposals[:k]), list(st_obj.moves[:k]),
+                                 tuple(st_obj.bucket_edges), tuple(st_obj.bucket_bytes),
+                                 dict(zip(PHASES, st_obj.phase_ms)), dict(zip(PHASES, st_obj.phase_launches)))
+    return out
+
+
+def lp_contract(g: Graph, labels, want_map: bool = True, stream=None):
+    """(coarse Graph, map int32 device tensor or None)."""
+    torch = _torch()
+    lab = _dev(labels, torch.int32)
+    mp = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda") if want_map else None
+    h = _P()
+    _check(_load().lp_contract(g.handle, _ptr(lab), _ptr(mp), _stream(stream), ctypes.byref(h)), "lp_contract")
+    return Graph(h), (mp[: g.n] if mp is not None else None)
+
+
+def lp_edge_cut(g: Graph, labels, stream=None) -> int:
+    torch = _torch()
+    lab = _dev(labels, torch.int32)
+    out = ctypes.c_int64()
+    _check(_load().lp_edge_cut(g.handle, _ptr(lab), ctypes.byref(out), _stream(stream)), "lp_edge_cut")
+    return out.value
+
+
+def coarsen_params(n0: int, total_weight: int):
+    """Target size and the level-constant cluster-weight cap of the multilevel loop."""
+    n_target = min(1 << 14, max(256, -(-n0 // 64)))
+    cap = -(-3 * total_weight // n_target)
+    return n_target, cap
+
+
+def coarsen(g: Graph, seed: int = 1, rounds: int = 5, max_levels: int = 32, stream=None):
+    """Repeated lp_cluster + lp_contract (all on the device; the host reads n' only).
+    Stops at n' <= n_target, when a level shrinks by less than 5 %, or after
+    max_levels levels. Level l clusters with seed + l. Returns
+    (levels: list of (Graph, labels, map), final Graph, n_target, cap)."""
+    n_target, cap = coarsen_params(g.n, g.total_vwgt)
+    levels = []
+    cur = g
+    lvl = 0
+    while lvl < max_levels and cur.n > n_target:
+        labels = lp_cluster(cur, cap, rounds, seed + lvl, stream=stream)
+        nxt, mp = lp_contract(cur, labels, stream=stream)
+        levels.append((cur, labels, mp))
+        prev_n = cur.n
+        cur = nxt
+        lvl += 1
+        if 100 * cur.n > 95 * prev_n:
+            break
+    return levels, cur, n_target, cap

@@ -1,0 +1,999 @@
+// Size-constrained label-propagation clustering (Section IV-A), one
+// synchronous round at a time:
+//   rating   - every vertex rates the clusters of its neighbours against the
+//              round's snapshot (labels C, cluster weights W) and proposes its
+//              best feasible move. Degree buckets pick the kernel, following
+//              the paper's two-phase split (Section IV-A2): one lane per
+//              vertex, one wavefront per vertex, one workgroup per vertex
+//              (all with LDS rating tables: phase one), and a chunk-parallel
+//              hub path for the highest degrees (phase two);
+//   accept   - proposals are gathered in vertex order, radix-sorted by
+//              (target, gain descending) and admitted per target while the
+//              running weight fits under the cap;
+//   apply    - admitted vertices move; W is updated with integer atomics.
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "decode.h"
+#include "graph.h"
+
+namespace lp {
+
+namespace {
+
+struct RoundCtx {
+  GraphView g;
+  const int32_t* C;  // labels of the snapshot
+  const int64_t* W;  // cluster weights of the snapshot
+  int64_t cap;
+  uint64_t seed;
+  uint32_t round;
+  int32_t* ptgt;     // proposal target per vertex, -1 = none
+  int64_t* pgain;    // proposal gain per vertex
+  const uint32_t* done;
+};
+
+__device__ __forceinline__ void emit(const RoundCtx& x, int32_t u, const Cand& best, int64_t own) {
+  if (best.c >= 0 && best.r > own) {
+    x.ptgt[u] = best.c;
+    x.pgain[u] = best.r - own;
+  } else {
+    x.ptgt[u] = -1;
+  }
+}
+
+// Candidate update with lazy feasibility: the cluster weight is only read
+// when the candidate would beat the current best.
+__device__ __forceinline__ void consider(const RoundCtx& x, int32_t c, int64_t r, int64_t wu, Cand& best) {
+  if (r < best.r) return;
+  Cand cd{r, tiebreak_key(x.seed, x.round, (uint32_t)c), c};
+  if (cand_better(cd, best) && x.W[c] + wu <= x.cap) best = cd;
+}
+
+// ------------------------------------------------------- lane per vertex --
+template <bool COMP>
+__global__ __launch_bounds__(256) void k_rate_lane(RoundCtx x, const int32_t* __restrict__ list, int32_t cnt,
+                                                   const int32_t* __restrict__ deg) {
+  if (*x.done) return;
+  const int32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= cnt) return;
+  const int32_t u = list[i];
+  const int32_t d = deg[u];
+  int32_t lab[kMaxLane];
+  int32_t wt[kMaxLane];
+  if constexpr (COMP) {
+    uint64_t pos;
+    (void)read_header(x.g, u, pos);
+    int32_t v = 0, w = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxLane; ++k) {
+      lab[k] = -1;
+      wt[k] = 0;
+      if (k < d) {
+        const uint64_t code = varint_read(x.g.bytes, pos);
+        v = (k == 0) ? u + (int32_t)unzigzag(code) : v + (int32_t)code;
+        if (x.g.weighted) w = (k == 0 ? 0 : w) + (int32_t)unzigzag(varint_read(x.g.bytes, pos));
+        else w = 1;
+        lab[k] = x.C[v];
+        wt[k] = w;
+      }
+    }
+  } else {
+    const uint64_t b = x.g.xadj[u];
+#pragma unroll
+    for (int k = 0; k < kMaxLane; ++k) {
+      lab[k] = -1;
+      wt[k] = 0;
+      if (k < d) {
+        lab[k] = x.C[x.g.adjncy[b + k]];
+        wt[k] = x.g.adjwgt ? x.g.adjwgt[b + k] : 1;
+      }
+    }
+  }
+  const int32_t own_c = x.C[u];
+  const int64_t wu = vweight(x.g, u);
+  int64_t own = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxLane; ++k) own += (lab[k] == own_c) ? wt[k] : 0;
+  Cand best = cand_none();
+#pragma unroll
+  for (int k = 0; k < kMaxLane; ++k) {
+    const int32_t c = lab[k];
+    bool first = (c >= 0) && (c != own_c);
+#pragma unroll
+    for (int j = 0; j < k; ++j) first &= (lab[j] != c);
+    if (first) {
+      int64_t r = 0;
+#pragma unroll
+      for (int j = k; j < kMaxLane; ++j) r += (lab[j] == c) ? wt[j] : 0;
+      consider(x, c, r, wu, best);
+    }
+  }
+  emit(x, u, best, own);
+}
+
+// ------------------------------------------- LDS rating table (phase one) --
+template <typename V>
+__device__ __forceinline__ void lds_add(V* p, V w) {
+  if constexpr (sizeof(V) == 8) atomicAdd((unsigned long long*)p, (unsigned long long)w);
+  else atomicAdd((int*)p, (int)w);
+}
+
+template <typename V>
+__device__ __forceinline__ void tbl_insert(int32_t* keys, V* vals, uint32_t mask, uint32_t shift, int32_t c, V w) {
+  uint32_t h = slot_hash((uint32_t)c) >> shift;
+  while (true) {
+    const int32_t k = keys[h];
+    if (k == c) {
+      lds_add(&vals[h], w);
+      return;
+    }
+    if (k == kEmpty) {
+      const int32_t old = atomicCAS(&keys[h], kEmpty, c);
+      if (old == kEmpty || old == c) {
+        lds_add(&vals[h], w);
+        return;
+      }
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+__host__ __device__ __forceinline__ uint32_t ceil_log2(uint32_t x) {
+  uint32_t k = 0;
+  while ((1u << k) < x) ++k;
+  return k;
+}
+
+template <int NT>
+struct GroupSmem {
+  DecodeSmem<NT> dec;
+  Cand best[NT / kWave > 0 ? NT / kWave : 1];
+  int64_t red[NT / kWave > 0 ? NT / kWave : 1];
+};
+
+// One group (wavefront or workgroup) per vertex; the LDS table holds the
+// vertex's ratings. Table capacity = next power of two >= 2 * deg.
+template <int NT, typename V, bool COMP>
+__global__ __launch_bounds__(NT == kWave ? 256 : NT) void k_rate_group(RoundCtx x, const int32_t* __restrict__ list,
+                                                                       int32_t cnt, const int32_t* __restrict__ deg,
+                                                                       uint32_t tmax) {
+  extern __shared__ __align__(16) uint8_t smem_raw[];
+  constexpr int G = (NT == kWave) ? 4 : 1;
+  const int gi = (NT == kWave) ? (int)(threadIdx.x / kWave) : 0;
+  const int tid = group_tid<NT>();
+  const size_t per = (size_t)tmax * (4 + sizeof(V)) + sizeof(GroupSmem<NT>);
+  uint8_t* base = smem_raw + gi * ((per + 15) & ~size_t(15));
+  int32_t* keys = (int32_t*)base;
+  V* vals = (V*)(base + (size_t)tmax * 4);
+  GroupSmem<NT>& sm = *(GroupSmem<NT>*)(base + (size_t)tmax * (4 + sizeof(V)));
+  if (*x.done) return;
+  for (int64_t it = (int64_t)blockIdx.x * G + gi; it < cnt; it += (int64_t)gridDim.x * G) {
+    const int32_t u = list[it];
+    const uint32_t d = (uint32_t)deg[u];
+    const uint32_t logc = max(6u, ceil_log2(2 * d));
+    const uint32_t cap = 1u << logc, mask = cap - 1, shift = 32 - logc;
+    for (uint32_t s = tid; s < cap; s += NT) {
+      keys[s] = kEmpty;
+      vals[s] = 0;
+    }
+    group_sync<NT>();
+    auto ins = [&](uint32_t, int32_t v, int32_t w) { tbl_insert<V>(keys, vals, mask, shift, x.C[v], (V)w); };
+    if constexpr (COMP) {
+      const Nbh h = nbh_locate(x.g, u, d);
+      uint64_t pos = h.codes;
+      int32_t pv, pw;
+      (void)group_decode<NT>(x.g.bytes, pos, u, d, x.g.weighted, true, pv, pw, sm.dec, ins);
+    } else {
+      const uint64_t b = x.g.xadj[u];
+      for (uint32_t k = tid; k < d; k += NT) ins(k, x.g.adjncy[b + k], x.g.adjwgt ? x.g.adjwgt[b + k] : 1);
+    }
+    group_sync<NT>();
+    const int32_t own_c = x.C[u];
+    const int64_t wu = vweight(x.g, u);
+    Cand best = cand_none();
+    int64_t own = 0;
+    for (uint32_t s = tid; s < cap; s += NT) {
+      const int32_t c = keys[s];
+      if (c == kEmpty) continue;
+      const int64_t r = (int64_t)vals[s];
+      if (c == own_c) {
+        own = r;
+        continue;
+      }
+      consider(x, c, r, wu, best);
+    }
+    if constexpr (NT == kWave) {
+      best = wave_best(best);
+      own = wave_reduce_add(own);
+    } else {
+      best = block_best<NT>(best, sm.best);
+      own = block_reduce_add<NT, int64_t>(own, sm.red);
+    }
+    if (tid == 0) emit(x, u, best, own);
+    group_sync<NT>();
+  }
+}
+
+// --------------------------------------------------- hub path (phase two) --
+// A hub's neighbours are cut into segments of LP_CHUNK_LEN (the format's
+// chunks, or consecutive runs of an unsplit neighbourhood). Step H1 decodes
+// every segment, looks up the neighbours' clusters and writes the
+// (cluster, weight) records of the segment grouped by a hash partition of the
+// cluster ID. Step H2 aggregates each (hub, partition) in an LDS table and
+// reports the partition's best feasible cluster and the hub's own rating if
+// its cluster hashes there. Step H3 combines the partitions of a hub.
+struct HubMeta {
+  const int32_t* u;         // hub vertex
+  const int32_t* deg;
+  const int32_t* nparts;    // P_h
+  const int32_t* nseg;      // segments
+  const uint64_t* rec_base; // first record of the hub
+  const uint64_t* poff_base;
+  const int32_t* task_base; // first (hub, partition) task
+  const int2* pieces;       // (hub, first segment)
+  const int2* tasks;        // (hub, partition)
+  int32_t* rec_c;           // records: cluster
+  int32_t* rec_w;           // records: weight (weighted graphs only)
+  uint32_t* poff;           // per segment: P_h + 1 partition offsets
+  int64_t* res_r;           // per task
+  uint64_t* res_key;
+  int32_t* res_c;
+  int64_t* res_own;
+};
+
+constexpr int kMaxParts = 1024;
+
+struct HubPieceSmem {
+  DecodeSmem<kWave> dec;
+  int32_t c[LP_CHUNK_LEN];
+  int32_t w[LP_CHUNK_LEN];
+  uint16_t p[LP_CHUNK_LEN];
+  uint32_t hist[kMaxParts];
+};
+
+__global__ __launch_bounds__(256) void k_hub_scatter(RoundCtx x, HubMeta hm, int32_t npieces) {
+  extern __shared__ __align__(16) uint8_t smem_raw[];
+  HubPieceSmem& sm = ((HubPieceSmem*)smem_raw)[threadIdx.x / kWave];
+  if (*x.done) return;
+  const int lane = lane_id();
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t pc = wid; pc < npieces; pc += nw) {
+    const int2 piece = hm.pieces[pc];
+    const int h = piece.x;
+    const int32_t u = hm.u[h];
+    const uint32_t d = (uint32_t)hm.deg[h];
+    const uint32_t P = (uint32_t)hm.nparts[h];
+    const uint64_t rb = hm.rec_base[h];
+    const uint64_t pb = hm.poff_base[h];
+    bool chunked = true;
+    uint32_t nseg_here = 1;
+    uint64_t pos = 0;
+    uint64_t ebase = 0;  // plain CSR: first edge of u
+    if (x.g.offs) {
+      const Nbh hb = nbh_locate(x.g, u, d);
+      chunked = hb.nchunks > 1;
+      nseg_here = chunked ? 1u : (uint32_t)hm.nseg[h];
+      pos = chunked ? nbh_chunk_pos(x.g, hb, (uint32_t)piece.y) : hb.codes;
+    } else {
+      ebase = x.g.xadj[u];
+    }
+    int32_t pv = 0, pw = 0;
+    for (uint32_t s = 0; s < nseg_here; ++s) {
+      const uint32_t k = (uint32_t)piece.y + s;
+      const uint32_t first = k * LP_CHUNK_LEN;
+      const uint32_t cnt = min((uint32_t)LP_CHUNK_LEN, d - first);
+      if (x.g.offs) {
+        (void)group_decode<kWave>(x.g.bytes, pos, u, cnt, x.g.weighted, chunked || s == 0, pv, pw, sm.dec,
+                                  [&](uint32_t i, int32_t v, int32_t w) {
+                                    sm.c[i] = x.C[v];
+                                    sm.w[i] = w;
+                                  });
+      } else {
+        for (uint32_t i = lane; i < cnt; i += kWave) {
+          const uint64_t e = ebase + first + i;
+          sm.c[i] = x.C[x.g.adjncy[e]];
+          sm.w[i] = x.g.adjwgt ? x.g.adjwgt[e] : 1;
+        }
+      }
+      for (uint32_t j = lane; j < P; j += kWave) sm.hist[j] = 0;
+      wave_sync_lds();
+      for (uint32_t i = lane; i < cnt; i += kWave) {
+        const uint32_t p = part_hash((uint32_t)sm.c[i]) % P;
+        sm.p[i] = (uint16_t)p;
+        atomicAdd(&sm.hist[p], 1u);
+      }
+      wave_sync_lds();
+      uint32_t* po = hm.poff + pb + (uint64_t)k * (P + 1);
+      uint32_t carry = 0;
+      for (uint32_t b0 = 0; b0 < P; b0 += kWave) {
+        const uint32_t j = b0 + lane;
+        const uint32_t v = j < P ? sm.hist[j] : 0;
+        const uint32_t inc = wave_incl_scan_add(v);
+        if (j < P) {
+          sm.hist[j] = carry + inc - v;
+          po[j] = carry + inc - v;
+        }
+        carry += __shfl(inc, kWave - 1, kWave);
+      }
+      if (lane == 0) po[P] = cnt;
+      wave_sync_lds();
+      const uint64_t out = rb + first;
+      for (uint32_t i = lane; i < cnt; i += kWave) {
+        const uint32_t slot = atomicAdd(&sm.hist[sm.p[i]], 1u);
+        hm.rec_c[out + slot] = sm.c[i];
+        if (hm.rec_w) hm.rec_w[out + slot] = sm.w[i];
+      }
+      wave_sync_lds();
+    }
+  }
+}
+
+template <typename V>
+__global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta hm, int32_t ntasks, uint32_t tcap) {
+  extern __shared__ __align__(16) uint8_t smem_raw[];
+  int32_t* keys = (int32_t*)smem_raw;
+  V* vals = (V*)(smem_raw + (size_t)tcap * 4);
+  __shared__ Cand sbest[kHubThreads / kWave];
+  __shared__ int64_t sred[kHubThreads / kWave];
+  __shared__ uint32_t distinct;
+  __shared__ uint32_t overflow;
+  if (*x.done) return;
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wv = tid / kWave;
+  const uint32_t mask = tcap - 1, shift = 32 - ceil_log2(tcap);
+  const uint32_t limit = tcap / 2;
+  for (int64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
+    const int2 task = hm.tasks[t];
+    const int h = task.x;
+    const uint32_t p = (uint32_t)task.y;
+    const int32_t u = hm.u[h];
+    const uint32_t P = (uint32_t)hm.nparts[h];
+    const uint32_t nseg = (uint32_t)hm.nseg[h];
+    const uint64_t rb = hm.rec_base[h];
+    const uint32_t* po = hm.poff + hm.poff_base[h];
+    const int32_t own_c = x.C[u];
+    const int64_t wu = vweight(x.g, u);
+    uint32_t S = 1;  // label-range sub-passes; doubled if a table overflows
+    Cand best;
+    int64_t own;
+    while (true) {
+      best = cand_none();
+      own = 0;
+      bool over = false;
+      for (uint32_t sp = 0; sp < S; ++sp) {
+        for (uint32_t s = tid; s < tcap; s += kHubThreads) {
+          keys[s] = kEmpty;
+          vals[s] = 0;
+        }
+        if (tid == 0) {
+          distinct = 0;
+          overflow = 0;
+        }
+        __syncthreads();
+        for (uint32_t k = wv; k < nseg; k += kHubThreads / kWave) {
+          const uint32_t a = po[(uint64_t)k * (P + 1) + p], b = po[(uint64_t)k * (P + 1) + p + 1];
+          const uint64_t base = rb + (uint64_t)k * LP_CHUNK_LEN;
+          for (uint32_t i = a + lane; i < b; i += kWave) {
+            const int32_t c = hm.rec_c[base + i];
+            if (S > 1 && (uint32_t)(((uint64_t)(uint32_t)c * S) / (uint64_t)x.g.n) != sp) continue;
+            const V w = hm.rec_w ? (V)hm.rec_w[base + i] : (V)1;
+            uint32_t hs = slot_hash((uint32_t)c) >> shift;
+            bool reserved = false;
+            while (true) {
+              const int32_t kk = keys[hs];
+              if (kk == c) {
+                lds_add(&vals[hs], w);
+                break;
+              }
+              if (kk == kEmpty) {
+                if (!reserved) {
+                  if (atomicAdd(&distinct, 1u) >= limit) {
+                    overflow = 1;
+                    break;
+                  }
+                  reserved = true;
+                }
+                const int32_t old = atomicCAS(&keys[hs], kEmpty, c);
+                if (old == kEmpty || old == c) {
+                  lds_add(&vals[hs], w);
+                  break;
+                }
+              }
+              hs = (hs + 1) & mask;
+            }
+          }
+        }
+        __syncthreads();
+        if (overflow) {
+          over = true;
+          break;
+        }
+        for (uint32_t s = tid; s < tcap; s += kHubThreads) {
+          const int32_t c = keys[s];
+          if (c == kEmpty) continue;
+          const int64_t r = (int64_t)vals[s];
+          if (c == own_c) {
+            own = r;
+            continue;
+          }
+          consider(x, c, r, wu, best);
+        }
+        __syncthreads();
+      }
+      if (!over) break;
+      __syncthreads();
+      S *= 2;
+    }
+    best = block_best<kHubThreads>(best, sbest);
+    own = block_reduce_add<kHubThreads, int64_t>(own, sred);
+    if (tid == 0) {
+      hm.res_r[t] = best.r;
+      hm.res_key[t] = best.key;
+      hm.res_c[t] = best.c;
+      hm.res_own[t] = own;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_hub_combine(RoundCtx x, HubMeta hm, int32_t nhubs) {
+  if (*x.done) return;
+  const int lane = lane_id();
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t h = wid; h < nhubs; h += nw) {
+    const int32_t P = hm.nparts[h];
+    const int32_t tb = hm.task_base[h];
+    Cand best = cand_none();
+    int64_t own = 0;
+    for (int32_t p = lane; p < P; p += kWave) {
+      Cand c{hm.res_r[tb + p], hm.res_key[tb + p], hm.res_c[tb + p]};
+      if (cand_better(c, best)) best = c;
+      own += hm.res_own[tb + p];
+    }
+    best = wave_best(best);
+    own = wave_reduce_add(own);
+    if (lane == 0) emit(x, hm.u[h], best, own);
+  }
+}
+
+// ------------------------------------------------------------ buckets ----
+constexpr int kBkThreads = 256;
+constexpr int kBkItems = 8;
+constexpr int kBkTile = kBkThreads * kBkItems;
+constexpr int kNumBuckets = 4;
+
+__device__ __forceinline__ int bucket_of(int32_t d, int32_t t_lane, int32_t t_wave, int32_t t_block) {
+  if (d <= 0) return -1;
+  if (d <= t_lane) return 0;
+  if (d <= t_wave) return 1;
+  if (d <= t_block) return 2;
+  return 3;
+}
+
+__global__ __launch_bounds__(kBkThreads) void k_bucket_count(const int32_t* deg, int32_t n, int32_t t_lane,
+                                                             int32_t t_wave, int32_t t_block, uint32_t* counts,
+                                                             uint32_t nb) {
+  __shared__ uint32_t c[kNumBuckets];
+  if (threadIdx.x < kNumBuckets) c[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kBkTile;
+  for (int i = 0; i < kBkItems; ++i) {
+    const int64_t u = base + (int64_t)i * kBkThreads + threadIdx.x;
+    if (u < n) {
+      const int b = bucket_of(deg[u], t_lane, t_wave, t_block);
+      if (b >= 0) atomicAdd(&c[b], 1u);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kNumBuckets) counts[(size_t)threadIdx.x * nb + blockIdx.x] = c[threadIdx.x];
+}
+
+// Stable: within a block, vertices keep increasing order per bucket.
+__global__ __launch_bounds__(kBkThreads) void k_bucket_scatter(const int32_t* deg, int32_t n, int32_t t_lane,
+                                                               int32_t t_wave, int32_t t_block,
+                                                               const uint32_t* offs, uint32_t nb, int32_t* order) {
+  __shared__ uint32_t run[kNumBuckets];
+  __shared__ uint32_t wc[kBkThreads / kWave][kNumBuckets];
+  const int w = threadIdx.x / kWave;
+  if (threadIdx.x < kNumBuckets) run[threadIdx.x] = offs[(size_t)threadIdx.x * nb + blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * kBkTile;
+  const uint64_t lt = lanemask_lt();
+  for (int i = 0; i < kBkItems; ++i) {
+    const int64_t u = base + (int64_t)i * kBkThreads + threadIdx.x;
+    const int b = (u < n) ? bucket_of(deg[u], t_lane, t_wave, t_block) : -1;
+    uint64_t m[kNumBuckets];
+#pragma unroll
+    for (int k = 0; k < kNumBuckets; ++k) m[k] = __ballot(b == k);
+    if (lane_id() < kNumBuckets) wc[w][lane_id()] = __popcll(m[lane_id()]);
+    __syncthreads();
+    if (b >= 0) {
+      uint32_t off = run[b] + __popcll(m[b] & lt);
+      for (int k = 0; k < w; ++k) off += wc[k][b];
+      order[off] = (int32_t)u;
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumBuckets) {
+      uint32_t add = 0;
+      for (int k = 0; k < kBkThreads / kWave; ++k) add += wc[k][threadIdx.x];
+      run[threadIdx.x] += add;
+    }
+    __syncthreads();
+  }
+}
+
+// Per-bucket adjacency entries and compressed record bytes (statistics).
+__global__ __launch_bounds__(256) void k_bucket_sums(const int32_t* deg, int32_t n, int32_t t_lane, int32_t t_wave,
+                                                     int32_t t_block, const uint64_t* offs,
+                                                     unsigned long long* sums) {
+  __shared__ unsigned long long sm[2 * kNumBuckets];
+  if (threadIdx.x < 2 * kNumBuckets) sm[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+    const int b = bucket_of(deg[u], t_lane, t_wave, t_block);
+    if (b < 0) continue;
+    atomicAdd(&sm[b], (unsigned long long)deg[u]);
+    if (offs) atomicAdd(&sm[kNumBuckets + b], (unsigned long long)(offs[u + 1] - offs[u]));
+  }
+  __syncthreads();
+  if (threadIdx.x < 2 * kNumBuckets && sm[threadIdx.x]) atomicAdd(&sums[threadIdx.x], sm[threadIdx.x]);
+}
+
+// ------------------------------------------------------------ accept -----
+constexpr int kCpThreads = 256;
+constexpr int kCpItems = 8;
+constexpr int kCpTile = kCpThreads * kCpItems;
+
+__global__ __launch_bounds__(kCpThreads) void k_prop_count(const int32_t* ptgt, int32_t n, uint32_t* bc,
+                                                           const uint32_t* done) {
+  __shared__ uint32_t sm[kCpThreads / kWave];
+  if (*done) return;
+  const int64_t base = (int64_t)blockIdx.x * kCpTile + (int64_t)threadIdx.x * kCpItems;
+  uint32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < kCpItems; ++i)
+    if (base + i < n && ptgt[base + i] >= 0) ++c;
+  c = block_reduce_add<kCpThreads, uint32_t>(c, sm);
+  if (threadIdx.x == 0) bc[blockIdx.x] = c;
+}
+
+// Writes the proposals in increasing vertex order: key = target << G |
+// (2^G - 1 - gain), value = vertex.
+__global__ __launch_bounds__(kCpThreads) void k_prop_write(const int32_t* ptgt, const int64_t* pgain, int32_t n,
+                                                           const uint32_t* boff, int G, uint64_t* keys,
+                                                           uint32_t* vals, const uint32_t* done) {
+  __shared__ uint32_t sm[kCpThreads / kWave];
+  if (*done) return;
+  const int64_t base = (int64_t)blockIdx.x * kCpTile + (int64_t)threadIdx.x * kCpItems;
+  uint32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < kCpItems; ++i)
+    if (base + i < n && ptgt[base + i] >= 0) ++c;
+  uint32_t tot;
+  uint32_t incl = block_incl_scan_add<kCpThreads, uint32_t>(c, sm, &tot);
+  uint32_t o = boff[blockIdx.x] + incl - c;
+  const uint64_t dmax = (G >= 64) ? ~0ull : ((1ull << G) - 1);
+#pragma unroll
+  for (int i = 0; i < kCpItems; ++i) {
+    const int64_t u = base + i;
+    if (u < n) {
+      const int32_t t = ptgt[u];
+      if (t >= 0) {
+        keys[o] = ((uint64_t)(uint32_t)t << G) | (dmax - (uint64_t)pgain[u]);
+        vals[o] = (uint32_t)u;
+        ++o;
+      }
+    }
+  }
+}
+
+__global__ void k_admit_prep(const uint64_t* keys, const uint32_t* vals, const uint32_t* count, int G,
+                             const int32_t* vwgt, uint32_t* seg, int64_t* wv) {
+  const int64_t n = *count;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    seg[i] = (uint32_t)(keys[i] >> G);
+    wv[i] = vwgt ? vwgt[vals[i]] : 1;
+  }
+}
+
+__global__ void k_admit(const uint32_t* seg, const int64_t* prefix, const uint32_t* count, const int64_t* W,
+                        int64_t cap, uint8_t* flag) {
+  const int64_t n = *count;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    flag[i] = (W[seg[i]] + prefix[i] <= cap) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_apply(const uint32_t* seg, const uint32_t* vals, const uint8_t* flag,
+                                               const int64_t* wv, const uint32_t* count, int32_t* C, int64_t* W,
+                                               int64_t* stats, int round) {
+  __shared__ int64_t sm[4];
+  const int64_t n = *count;
+  int64_t moves = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (!flag[i]) continue;
+    const int32_t u = (int32_t)vals[i];
+    const int32_t t = (int32_t)seg[i];
+    const int32_t old = C[u];
+    const int64_t w = wv[i];
+    C[u] = t;
+    atomicAdd((unsigned long long*)&W[t], (unsigned long long)w);
+    atomicAdd((unsigned long long*)&W[old], (unsigned long long)(-w));
+    ++moves;
+  }
+  moves = block_reduce_add<256, int64_t>(moves, sm);
+  if (threadIdx.x == 0 && moves && round < 64)
+    atomicAdd((unsigned long long*)&stats[64 + round], (unsigned long long)moves);
+}
+
+__global__ void k_round_end(const uint32_t* count, uint32_t* done, int64_t* stats, int round, int32_t* rounds_run) {
+  if (*done) return;
+  const uint32_t c = *count;
+  if (round < 64) stats[round] = c;
+  if (c == 0) *done = 1;
+  else *rounds_run = round + 1;
+}
+
+__global__ void k_init(int32_t n, const int32_t* vwgt, int32_t* C, int64_t* W, int32_t* ptgt) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+    C[u] = (int32_t)u;
+    W[u] = vwgt ? vwgt[u] : 1;
+    ptgt[u] = -1;
+  }
+}
+
+int bitlen(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
+
+template <typename F>
+lp_status set_lds(F* kern, size_t bytes) {
+  LP_CHECK_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  return LP_OK;
+}
+
+// Launch of one group-rating kernel, templated on group size, rating width
+// and representation.
+template <int NT, typename V, bool COMP>
+lp_status launch_group(const RoundCtx& x, const int32_t* list, int32_t cnt, const int32_t* deg, uint32_t tmax,
+                       hipStream_t s) {
+  if (cnt <= 0) return LP_OK;
+  constexpr int G = (NT == kWave) ? 4 : 1;
+  const size_t per = ((size_t)tmax * (4 + sizeof(V)) + sizeof(GroupSmem<NT>) + 15) & ~size_t(15);
+  const size_t bytes = per * G;
+  auto kern = k_rate_group<NT, V, COMP>;
+  LP_CHECK(set_lds(kern, bytes));
+  const int threads = (NT == kWave) ? 256 : NT;
+  const unsigned grid = grid_for(cnt, G, 1u << 20);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), bytes, s, x, list, cnt, deg, tmax);
+  return last_error();
+}
+
+}  // namespace
+
+}  // namespace lp
+
+using namespace lp;
+
+extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t rounds, uint64_t seed, int32_t* labels,
+                                   const lp_config* cfg_in, lp_cluster_stats* stats_out, void* stream) {
+  clear_error();
+  if (!g || cap < 1 || rounds < 0 || (!labels && g->n > 0)) return LP_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (stats_out) memset(stats_out, 0, sizeof(*stats_out));
+  const int32_t n = g->n;
+  if (n == 0) return LP_OK;
+  // knobs (results do not depend on them)
+  const bool wide = g->max_wdeg > 0x7FFFFFFFll;
+  int32_t t_lane = 16, t_wave = 256, t_block = wide ? 4096 : 8192, hub_part = 4096;
+  if (cfg_in) {
+    if (cfg_in->t_lane) t_lane = cfg_in->t_lane;
+    if (cfg_in->t_wave) t_wave = cfg_in->t_wave;
+    if (cfg_in->t_block) t_block = cfg_in->t_block;
+    if (cfg_in->hub_part) hub_part = cfg_in->hub_part;
+  }
+  const int32_t block_max = wide ? kMaxBlock / 2 : kMaxBlock;
+  if (t_lane < 0 || t_lane > kMaxLane || t_wave < t_lane || t_wave > kMaxWave || t_block < t_wave ||
+      t_block > block_max || hub_part < 256 || hub_part > 8192)
+    return LP_EINVAL;
+  // proposal sort key: target bits + gain bits
+  const int G = std::max(1, bitlen((uint64_t)g->max_wdeg));
+  const int nbits = std::max(1, bitlen((uint64_t)(n - 1)));
+  if (G + nbits > 64) return LP_EUNSUPPORTED;
+
+  Scratch sc(s);
+  int32_t* deg = sc.alloc<int32_t>(n);
+  int32_t* order = sc.alloc<int32_t>(n);
+  int64_t* W = sc.alloc<int64_t>(n);
+  int32_t* ptgt = sc.alloc<int32_t>(n);
+  int64_t* pgain = sc.alloc<int64_t>(n);
+  uint64_t* ka = sc.alloc<uint64_t>(n);
+  uint64_t* kb = sc.alloc<uint64_t>(n);
+  uint32_t* va = sc.alloc<uint32_t>(n);
+  uint32_t* vb = sc.alloc<uint32_t>(n);
+  uint32_t* seg = sc.alloc<uint32_t>(n);
+  int64_t* wv = sc.alloc<int64_t>(n);
+  int64_t* pref = sc.alloc<int64_t>(n);
+  uint8_t* flag = sc.alloc<uint8_t>(n);
+  const unsigned nbk = grid_for(n, kBkTile, 0x7FFFFFFF);
+  uint32_t* bcnt = sc.alloc<uint32_t>((size_t)kNumBuckets * nbk);
+  const unsigned ncp = grid_for(n, kCpTile, 0x7FFFFFFF);
+  uint32_t* pcnt = sc.alloc<uint32_t>(ncp);
+  struct Ctl {
+    uint32_t done;
+    uint32_t count;
+    int32_t rounds_run;
+    uint32_t pad;
+    uint32_t bucket_tot[4];
+    int64_t stats[128];
+    unsigned long long bsums[8];
+  };
+  Ctl* ctl = sc.alloc<Ctl>(1);
+  if (sc.failed) return LP_ENOMEM;
+  LP_CHECK_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), s));
+
+  // optional per-phase timing with events on the call's stream
+  const bool timing = cfg_in && cfg_in->timing && stats_out;
+  struct Mark {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  struct EventGuard {
+    std::vector<Mark>* m;
+    ~EventGuard() {
+      for (auto& k : *m) {
+        (void)hipEventDestroy(k.a);
+        (void)hipEventDestroy(k.b);
+      }
+    }
+  } guard{&marks};
+  auto begin = [&](int phase) -> lp_status {
+    if (!timing) return LP_OK;
+    Mark m{phase, nullptr, nullptr};
+    LP_CHECK_HIP(hipEventCreate(&m.a));
+    LP_CHECK_HIP(hipEventCreate(&m.b));
+    marks.push_back(m);
+    LP_CHECK_HIP(hipEventRecord(m.a, s));
+    return LP_OK;
+  };
+  auto end = [&]() -> lp_status {
+    if (!timing) return LP_OK;
+    LP_CHECK_HIP(hipEventRecord(marks.back().b, s));
+    return LP_OK;
+  };
+
+  LP_CHECK(begin(LP_PHASE_SETUP));
+  LP_CHECK(compute_degrees(g, deg, s));
+  // degree buckets: one stable list ordered by (bucket, vertex)
+  hipLaunchKernelGGL(k_bucket_count, dim3(nbk), dim3(kBkThreads), 0, s, deg, n, t_lane, t_wave, t_block, bcnt, nbk);
+  LP_CHECK_LAUNCH();
+  uint32_t* btot = sc.alloc<uint32_t>(1);
+  if (!btot) return LP_ENOMEM;
+  LP_CHECK(scan_exclusive_u32(bcnt, bcnt, (int64_t)kNumBuckets * nbk, btot, sc));
+  hipLaunchKernelGGL(k_bucket_scatter, dim3(nbk), dim3(kBkThreads), 0, s, deg, n, t_lane, t_wave, t_block, bcnt, nbk,
+                     order);
+  LP_CHECK_LAUNCH();
+  if (stats_out) {
+    hipLaunchKernelGGL(k_bucket_sums, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, deg, n, t_lane, t_wave, t_block,
+                       g->compressed ? g->offs : nullptr, ctl->bsums);
+    LP_CHECK_LAUNCH();
+  }
+  // bucket boundaries: offs of bucket b = bcnt[b * nbk]
+  uint32_t bstart[kNumBuckets + 1];
+  for (int b = 0; b < kNumBuckets; ++b)
+    LP_CHECK_HIP(hipMemcpyAsync(&bstart[b], bcnt + (size_t)b * nbk, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  LP_CHECK_HIP(hipMemcpyAsync(&bstart[kNumBuckets], btot, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  LP_CHECK_HIP(hipStreamSynchronize(s));
+  int32_t bn[kNumBuckets];
+  for (int b = 0; b < kNumBuckets; ++b) bn[b] = (int32_t)(bstart[b + 1] - bstart[b]);
+
+  // hub metadata (host-built, small)
+  const int32_t H = bn[3];
+  HubMeta hm{};
+  int32_t npieces = 0, ntasks = 0;
+  uint32_t tcap_hub = wide ? 8192 : 16384;
+  if (H > 0) {
+    std::vector<int32_t> hu(H), hd(H);
+    LP_CHECK_HIP(hipMemcpyAsync(hu.data(), order + bstart[3], H * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LP_CHECK_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> all_deg(H);
+    for (int h = 0; h < H; ++h)
+      LP_CHECK_HIP(hipMemcpyAsync(&hd[h], deg + hu[h], sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LP_CHECK_HIP(hipStreamSynchronize(s));
+    int64_t maxd = 0;
+    for (int h = 0; h < H; ++h) maxd = std::max<int64_t>(maxd, hd[h]);
+    const int64_t part = std::max<int64_t>(hub_part, (maxd + kMaxParts - 1) / kMaxParts);
+    std::vector<int32_t> np(H), ns(H), tb(H);
+    std::vector<uint64_t> rbase(H), pbase(H);
+    std::vector<int2> pieces, tasks;
+    uint64_t rsum = 0, psum = 0;
+    for (int h = 0; h < H; ++h) {
+      const int64_t d = hd[h];
+      np[h] = (int32_t)std::max<int64_t>(1, (d + part - 1) / part);
+      ns[h] = (int32_t)((d + LP_CHUNK_LEN - 1) / LP_CHUNK_LEN);
+      rbase[h] = rsum;
+      pbase[h] = psum;
+      tb[h] = ntasks;
+      rsum += (uint64_t)d;
+      psum += (uint64_t)ns[h] * (np[h] + 1);
+      ntasks += np[h];
+      const bool chunked = g->compressed ? (d > LP_CHUNK_THRESHOLD) : true;
+      if (chunked)
+        for (int k = 0; k < ns[h]; ++k) pieces.push_back(make_int2(h, k));
+      else
+        pieces.push_back(make_int2(h, 0));
+      for (int p = 0; p < np[h]; ++p) tasks.push_back(make_int2(h, p));
+    }
+    npieces = (int32_t)pieces.size();
+    int32_t* d_u = sc.alloc<int32_t>(H);
+    int32_t* d_deg = sc.alloc<int32_t>(H);
+    int32_t* d_np = sc.alloc<int32_t>(H);
+    int32_t* d_ns = sc.alloc<int32_t>(H);
+    int32_t* d_tb = sc.alloc<int32_t>(H);
+    uint64_t* d_rb = sc.alloc<uint64_t>(H);
+    uint64_t* d_pb = sc.alloc<uint64_t>(H);
+    int2* d_pieces = sc.alloc<int2>(npieces);
+    int2* d_tasks = sc.alloc<int2>(ntasks);
+    hm.rec_c = sc.alloc<int32_t>(rsum);
+    hm.rec_w = g->weighted ? sc.alloc<int32_t>(rsum) : nullptr;
+    hm.poff = sc.alloc<uint32_t>(psum);
+    hm.res_r = sc.alloc<int64_t>(ntasks);
+    hm.res_key = sc.alloc<uint64_t>(ntasks);
+    hm.res_c = sc.alloc<int32_t>(ntasks);
+    hm.res_own = sc.alloc<int64_t>(ntasks);
+    if (sc.failed) return LP_ENOMEM;
+    LP_CHECK_HIP(hipMemcpyAsync(d_u, hu.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_deg, hd.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_np, np.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_ns, ns.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_tb, tb.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_rb, rbase.data(), H * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_pb, pbase.data(), H * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_pieces, pieces.data(), npieces * sizeof(int2), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_tasks, tasks.data(), ntasks * sizeof(int2), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
+    hm.u = d_u;
+    hm.deg = d_deg;
+    hm.nparts = d_np;
+    hm.nseg = d_ns;
+    hm.rec_base = d_rb;
+    hm.poff_base = d_pb;
+    hm.task_base = d_tb;
+    hm.pieces = d_pieces;
+    hm.tasks = d_tasks;
+  }
+
+  hipLaunchKernelGGL(k_init, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, g->vwgt, labels, W, ptgt);
+  LP_CHECK_LAUNCH();
+  LP_CHECK(end());
+
+  RoundCtx x;
+  x.g = g->view();
+  x.C = labels;
+  x.W = W;
+  x.cap = cap;
+  x.seed = seed;
+  x.ptgt = ptgt;
+  x.pgain = pgain;
+  x.done = &ctl->done;
+  const int32_t* lists[kNumBuckets];
+  for (int b = 0; b < kNumBuckets; ++b) lists[b] = order + bstart[b];
+  const uint32_t wave_tmax = 1u << ceil_log2(2 * (uint32_t)std::max(t_wave, 32));
+  const uint32_t block_tmax = 1u << ceil_log2(2 * (uint32_t)std::max(t_block, 32));
+  const size_t piece_lds = sizeof(HubPieceSmem) * 4;
+  if (H > 0) {
+    LP_CHECK(set_lds(k_hub_scatter, piece_lds));
+    if (wide) LP_CHECK(set_lds(k_hub_reduce<int64_t>, (size_t)tcap_hub * 12));
+    else LP_CHECK(set_lds(k_hub_reduce<int32_t>, (size_t)tcap_hub * 8));
+  }
+
+  for (int32_t r = 0; r < rounds; ++r) {
+    x.round = (uint32_t)r;
+    // rating (all buckets) -> ptgt / pgain
+    if (bn[0] > 0) {
+      LP_CHECK(begin(LP_PHASE_LANE));
+      if (g->compressed)
+        hipLaunchKernelGGL(k_rate_lane<true>, dim3(grid_for(bn[0], 256)), dim3(256), 0, s, x, lists[0], bn[0], deg);
+      else
+        hipLaunchKernelGGL(k_rate_lane<false>, dim3(grid_for(bn[0], 256)), dim3(256), 0, s, x, lists[0], bn[0], deg);
+      LP_CHECK_LAUNCH();
+      LP_CHECK(end());
+    }
+    if (bn[1] > 0) {
+      LP_CHECK(begin(LP_PHASE_WAVE));
+      if (wide) {
+        if (g->compressed) LP_CHECK((launch_group<kWave, int64_t, true>(x, lists[1], bn[1], deg, wave_tmax, s)));
+        else LP_CHECK((launch_group<kWave, int64_t, false>(x, lists[1], bn[1], deg, wave_tmax, s)));
+      } else {
+        if (g->compressed) LP_CHECK((launch_group<kWave, int32_t, true>(x, lists[1], bn[1], deg, wave_tmax, s)));
+        else LP_CHECK((launch_group<kWave, int32_t, false>(x, lists[1], bn[1], deg, wave_tmax, s)));
+      }
+      LP_CHECK(end());
+    }
+    if (bn[2] > 0) {
+      LP_CHECK(begin(LP_PHASE_BLOCK));
+      if (wide) {
+        if (g->compressed)
+          LP_CHECK((launch_group<kBlockThreads, int64_t, true>(x, lists[2], bn[2], deg, block_tmax, s)));
+        else
+          LP_CHECK((launch_group<kBlockThreads, int64_t, false>(x, lists[2], bn[2], deg, block_tmax, s)));
+      } else {
+        if (g->compressed)
+          LP_CHECK((launch_group<kBlockThreads, int32_t, true>(x, lists[2], bn[2], deg, block_tmax, s)));
+        else
+          LP_CHECK((launch_group<kBlockThreads, int32_t, false>(x, lists[2], bn[2], deg, block_tmax, s)));
+      }
+      LP_CHECK(end());
+    }
+    if (H > 0) {
+      LP_CHECK(begin(LP_PHASE_HUB));
+      hipLaunchKernelGGL(k_hub_scatter, dim3(grid_for(npieces, 4)), dim3(256), piece_lds, s, x, hm, npieces);
+      LP_CHECK_LAUNCH();
+      if (wide)
+        hipLaunchKernelGGL(k_hub_reduce<int64_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads), (size_t)tcap_hub * 12,
+                           s, x, hm, ntasks, tcap_hub);
+      else
+        hipLaunchKernelGGL(k_hub_reduce<int32_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads), (size_t)tcap_hub * 8,
+                           s, x, hm, ntasks, tcap_hub);
+      LP_CHECK_LAUNCH();
+      hipLaunchKernelGGL(k_hub_combine, dim3(grid_for(H, 4)), dim3(256), 0, s, x, hm, H);
+      LP_CHECK_LAUNCH();
+      LP_CHECK(end());
+    }
+    // acceptance: compact in vertex order, sort by (target, gain desc)
+    LP_CHECK(begin(LP_PHASE_ACCEPT));
+    hipLaunchKernelGGL(k_prop_count, dim3(ncp), dim3(kCpThreads), 0, s, ptgt, n, pcnt, &ctl->done);
+    LP_CHECK_LAUNCH();
+    LP_CHECK(scan_exclusive_u32(pcnt, pcnt, ncp, &ctl->count, sc));
+    hipLaunchKernelGGL(k_prop_write, dim3(ncp), dim3(kCpThreads), 0, s, ptgt, pgain, n, pcnt, G, ka, va, &ctl->done);
+    LP_CHECK_LAUNCH();
+    uint64_t* ks;
+    uint32_t* vs;
+    LP_CHECK(radix_sort_pairs(ka, va, kb, vb, &ctl->count, n, G + nbits, &ks, &vs, sc));
+    const unsigned ga = grid_for(n, 256, 8192);
+    hipLaunchKernelGGL(k_admit_prep, dim3(ga), dim3(256), 0, s, ks, vs, &ctl->count, G, g->vwgt, seg, wv);
+    LP_CHECK_LAUNCH();
+    LP_CHECK(seg_scan_incl_i64(seg, wv, pref, &ctl->count, n, sc));
+    hipLaunchKernelGGL(k_admit, dim3(ga), dim3(256), 0, s, seg, pref, &ctl->count, W, cap, flag);
+    LP_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_apply, dim3(ga), dim3(256), 0, s, seg, vs, flag, wv, &ctl->count, labels, W, ctl->stats, r);
+    LP_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, s, &ctl->count, &ctl->done, ctl->stats, r, &ctl->rounds_run);
+    LP_CHECK_LAUNCH();
+    LP_CHECK(end());
+  }
+  if (stats_out) {
+    Ctl h;
+    LP_CHECK_HIP(hipMemcpyAsync(&h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    LP_CHECK_HIP(hipStreamSynchronize(s));
+    stats_out->rounds_run = h.rounds_run;
+    stats_out->n_lane = bn[0];
+    stats_out->n_wave = bn[1];
+    stats_out->n_block = bn[2];
+    stats_out->n_hub = bn[3];
+    for (int i = 0; i < 64; ++i) {
+      stats_out->proposals[i] = h.stats[i];
+      stats_out->moves[i] = h.stats[64 + i];
+    }
+    for (int b = 0; b < kNumBuckets; ++b) {
+      stats_out->bucket_edges[b] = h.bsums[b];
+      stats_out->bucket_bytes[b] = h.bsums[kNumBuckets + b];
+    }
+    for (auto& m : marks) {
+      float ms = 0;
+      LP_CHECK_HIP(hipEventElapsedTime(&ms, m.a, m.b));
+      stats_out->phase_ms[m.phase] += ms;
+      stats_out->phase_launches[m.phase] += 1;
+    }
+  }
+  return LP_OK;
+}
+
+extern "C" lp_status lp_cluster(const lp_graph* g, int64_t cap, int32_t rounds, uint64_t seed, int32_t* labels,
+                                void* stream) {
+  clear_error();
+  return lp_cluster_ex(g, cap, rounds, seed, labels, nullptr, nullptr, stream);
+}

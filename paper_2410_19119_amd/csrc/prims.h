@@ -1,0 +1,100 @@
+// Host-side launchers of the device-wide primitives (prims.hip) and the
+// scratch-memory helper used by every entry point.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "lp_common.h"
+
+namespace lp {
+
+// Reports a failed HIP call on stderr when LPGPU_DEBUG is set in the
+// environment, then maps it to a status code.
+lp_status hip_fail(hipError_t e, const char* what, const char* file, int line);
+
+// Clears a pending error left by earlier runtime calls of the caller, so that
+// launch checks only see this library's errors.
+inline void clear_error() { (void)hipGetLastError(); }
+
+// Stream-ordered scratch allocations released (on the same stream) when the
+// object goes out of scope. A failed allocation sets `failed`.
+class Scratch {
+ public:
+  explicit Scratch(hipStream_t s) : stream_(s) {}
+  ~Scratch() {
+    for (void* p : ptrs_) (void)hipFreeAsync(p, stream_);
+  }
+  template <typename T>
+  T* alloc(size_t count) {
+    void* p = nullptr;
+    size_t bytes = (count ? count : 1) * sizeof(T);
+    bytes = (bytes + 255) & ~size_t(255);
+    const hipError_t e = hipMallocAsync(&p, bytes, stream_);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hip_fail(e, "hipMallocAsync", __FILE__, __LINE__);
+      failed = true;
+      return nullptr;
+    }
+    ptrs_.push_back(p);
+    return static_cast<T*>(p);
+  }
+  hipStream_t stream() const { return stream_; }
+  bool failed = false;
+
+ private:
+  hipStream_t stream_;
+  std::vector<void*> ptrs_;
+};
+
+// Exclusive prefix sum of in[0..n) into out[0..n); *total_dev (if not null)
+// receives the sum of all n inputs. out may alias in.
+lp_status scan_exclusive_u64(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* total_dev,
+                             Scratch& sc);
+lp_status scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total_dev,
+                             Scratch& sc);
+
+// Segmented inclusive prefix sum: out[i] = sum of val[j] for j in the run of
+// equal seg[] values that ends at i (runs are maximal stretches of equal
+// consecutive seg values). count is read from *count_dev (<= max_n).
+lp_status seg_scan_incl_i64(const uint32_t* seg, const int64_t* val, int64_t* out,
+                            const uint32_t* count_dev, int64_t max_n, Scratch& sc);
+
+// Stable LSD radix sort of (key, val) pairs on key bits [0, bits). The
+// number of valid pairs is *count_dev (<= max_n). Sorts in place using the
+// two buffer pairs; returns the buffers that hold the result in *keys_out,
+// *vals_out.
+lp_status radix_sort_pairs(uint64_t* keys_a, uint32_t* vals_a, uint64_t* keys_b, uint32_t* vals_b,
+                           const uint32_t* count_dev, int64_t max_n, int bits, uint64_t** keys_out,
+                           uint32_t** vals_out, Scratch& sc);
+
+#define last_error() ::lp::hip_fail(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
+
+inline unsigned grid_for(int64_t items, int per_block, unsigned cap = 1u << 20) {
+  int64_t b = (items + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > (int64_t)cap) b = cap;
+  return (unsigned)b;
+}
+
+#define LP_CHECK_HIP(call)                                            \
+  do {                                                                \
+    hipError_t e_ = (call);                                           \
+    if (e_ != hipSuccess) {                                           \
+      (void)hipGetLastError();                                        \
+      return ::lp::hip_fail(e_, #call, __FILE__, __LINE__);           \
+    }                                                                 \
+  } while (0)
+
+#define LP_CHECK(st)                  \
+  do {                                \
+    lp_status s_ = (st);              \
+    if (s_ != LP_OK) return s_;       \
+  } while (0)
+
+#define LP_CHECK_LAUNCH() LP_CHECK(last_error())
+
+}  // namespace lp

@@ -1,0 +1,249 @@
+"""GPU library vs CPU oracle, element by element (all-integer work: the
+tolerance is zero). Every call goes through the C ABI of liblpgpu.so."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _gpu_graph(lp, g, compressed=True):
+    make = lp.lp_compress if compressed else lp.lp_graph_from_csr
+    return make(g.n, g.xadj.view(np.int64), g.adjncy, g.adjwgt, g.vwgt)
+
+
+def _star(synth_mod, d, center=0, weights=False):
+    n = d + 1
+    edges = [(center, v) for v in range(n) if v != center]
+    w = [1 + (i * 7919) % 1000 for i in range(len(edges))] if weights else None
+    return synth_mod.from_edges(n, edges, w)
+
+
+def _graphs(synth_mod):
+    out = {}
+    out["rgg2d-16k"] = synth_mod.rgg2d_16k()
+    out["rmat-s13-ef16"] = synth_mod.rmat_scale(13, 16, seed=3)
+    g = synth_mod.rmat_scale(12, 8, seed=5)
+    g.adjwgt = synth_mod.edge_weights(g, 1, 100, 5)
+    g.vwgt = synth_mod.vertex_weights(g.n, 1, 4, 5)
+    out["rmat-s12-weighted"] = g
+    out["star-25000"] = _star(synth_mod, 25000, center=7)
+    out["star-10001-w"] = _star(synth_mod, 10001, center=5000, weights=True)
+    return out
+
+
+@pytest.fixture(scope="module")
+def graphs(synth_mod):
+    return _graphs(synth_mod)
+
+
+# ------------------------------------------------------------------ codec --
+
+@pytest.mark.parametrize("name", ["rgg2d-16k", "rmat-s13-ef16", "rmat-s12-weighted", "star-25000", "star-10001-w"])
+def test_compress_bytes_match_oracle(lp, oracle_mod, graphs, name):
+    g = graphs[name]
+    G = _gpu_graph(lp, g)
+    offs, data = lp.lp_graph_export(G)
+    o_offs, o_data = oracle_mod.compress(g.n, g.xadj, g.adjncy, g.adjwgt)
+    assert np.array_equal(_np(offs).view(np.uint64), o_offs)
+    assert np.array_equal(_np(data), o_data)
+
+
+@pytest.mark.parametrize("name", ["rgg2d-16k", "rmat-s13-ef16", "rmat-s12-weighted", "star-25000", "star-10001-w"])
+def test_decompress_roundtrip(lp, graphs, name):
+    g = graphs[name]
+    G = _gpu_graph(lp, g)
+    x, a, w, v = lp.lp_decompress(G)
+    assert np.array_equal(_np(x).view(np.uint64), g.xadj)
+    assert np.array_equal(_np(a), g.adjncy)
+    assert np.array_equal(_np(w), g.adjwgt if g.adjwgt is not None else np.ones(g.two_m, np.int32))
+    assert np.array_equal(_np(v), g.vwgt if g.vwgt is not None else np.ones(g.n, np.int32))
+
+
+def test_compress_rejects_bad_input(lp, synth_mod):
+    g = synth_mod.from_edges(3, [(0, 1), (1, 2)])
+    adj = g.adjncy.copy()
+    adj[0] = 7  # out of range
+    with pytest.raises(lp.LPError):
+        lp.lp_compress(g.n, g.xadj.view(np.int64), adj)
+    adj = g.adjncy.copy()
+    adj[0] = 0  # self-loop
+    with pytest.raises(lp.LPError):
+        lp.lp_compress(g.n, g.xadj.view(np.int64), adj)
+    with pytest.raises(lp.LPError):
+        lp.lp_compress(g.n, g.xadj.view(np.int64), g.adjncy, np.array([1, 0, 1, 1], np.int32))
+    h = synth_mod.from_edges(4, [(0, 1), (0, 2)])
+    adj = h.adjncy.copy()
+    adj[0], adj[1] = adj[1], adj[0]  # unsorted neighbourhood
+    with pytest.raises(lp.LPError):
+        lp.lp_compress(h.n, h.xadj.view(np.int64), adj)
+
+
+# ----------------------------------------------------------------- cluster --
+
+CASES = [
+    ("rgg2d-16k", 32, 5, 1),
+    ("rmat-s13-ef16", 256, 5, 1),
+    ("rmat-s13-ef16", 20, 5, 7),
+    ("rmat-s12-weighted", 60, 5, 3),
+    ("star-25000", 300, 3, 2),
+    ("star-10001-w", 5000, 3, 2),
+]
+
+
+@pytest.mark.parametrize("name,cap,rounds,seed", CASES)
+@pytest.mark.parametrize("compressed", [True, False])
+def test_cluster_matches_oracle(lp, oracle_mod, graphs, name, cap, rounds, seed, compressed):
+    g = graphs[name]
+    G = _gpu_graph(lp, g, compressed)
+    lab, st = lp.lp_cluster(G, cap, rounds, seed, stats=True)
+    exp, ost = oracle_mod.lp_cluster(g, cap, rounds, seed)
+    assert np.array_equal(_np(lab), exp)
+    assert st.rounds_run == ost.rounds_run
+    assert st.proposals == ost.proposals and st.moves == ost.moves
+
+
+KNOBS = [
+    dict(t_lane=1, t_wave=1, t_block=1, hub_part=256),        # almost everything on the hub path
+    dict(t_lane=16, t_wave=16, t_block=16, hub_part=512),
+    dict(t_lane=4, t_wave=64, t_block=64, hub_part=1024),
+    dict(t_lane=16, t_wave=512, t_block=8192, hub_part=8192),
+]
+
+
+@pytest.mark.parametrize("knobs", KNOBS)
+@pytest.mark.parametrize("name", ["rmat-s13-ef16", "rmat-s12-weighted", "star-25000"])
+def test_bucket_thresholds_do_not_change_results(lp, oracle_mod, graphs, knobs, name):
+    g = graphs[name]
+    G = _gpu_graph(lp, g)
+    exp, _ = oracle_mod.lp_cluster(g, 64, 4, 11)
+    lab = lp.lp_cluster(G, 64, 4, 11, config=knobs)
+    assert np.array_equal(_np(lab), exp)
+
+
+def test_wide_ratings_path(lp, oracle_mod, synth_mod):
+    # weighted degrees above 2^31 switch the LDS tables to 64-bit ratings
+    g = synth_mod.rmat_scale(12, 8, seed=9)
+    g.adjwgt = synth_mod.edge_weights(g, 2**29, 2**31 - 1, 9)
+    G = _gpu_graph(lp, g)
+    exp, _ = oracle_mod.lp_cluster(g, 40, 5, 2)
+    assert np.array_equal(_np(lp.lp_cluster(G, 40, 5, 2)), exp)
+
+
+@pytest.mark.parametrize("case", ["single", "no-edges", "cap1", "zero-rounds", "matching"])
+def test_degenerate_cases(lp, oracle_mod, synth_mod, case):
+    if case == "single":
+        g, cap, r = synth_mod.from_edges(1, []), 5, 5
+    elif case == "no-edges":
+        g, cap, r = synth_mod.from_edges(100, []), 5, 5
+    elif case == "cap1":
+        g, cap, r = synth_mod.rgg2d_16k(), 1, 5
+    elif case == "zero-rounds":
+        g, cap, r = synth_mod.rgg2d_16k(), 32, 0
+    else:
+        g, cap, r = synth_mod.from_edges(200, [(2 * i, 2 * i + 1) for i in range(100)]), 2, 3
+    G = _gpu_graph(lp, g)
+    exp, _ = oracle_mod.lp_cluster(g, cap, r, 1)
+    assert np.array_equal(_np(lp.lp_cluster(G, cap, r, 1)), exp)
+
+
+def test_cluster_argument_errors(lp, graphs):
+    G = _gpu_graph(lp, graphs["rgg2d-16k"])
+    with pytest.raises(lp.LPError):
+        lp.lp_cluster(G, 0, 5, 1)
+    with pytest.raises(lp.LPError):
+        lp.lp_cluster(G, 5, -1, 1)
+    with pytest.raises(lp.LPError):
+        lp.lp_cluster(G, 5, 1, 1, config=dict(t_lane=17))
+
+
+def test_repeatable(lp, graphs):
+    G = _gpu_graph(lp, graphs["rmat-s13-ef16"])
+    a = _np(lp.lp_cluster(G, 100, 5, 5))
+    for _ in range(3):
+        assert np.array_equal(_np(lp.lp_cluster(G, 100, 5, 5)), a)
+
+
+# ---------------------------------------------------------------- contract --
+
+@pytest.mark.parametrize("name,cap", [("rgg2d-16k", 32), ("rmat-s13-ef16", 256), ("rmat-s13-ef16", 5000),
+                                      ("rmat-s12-weighted", 200), ("star-25000", 30000)])
+@pytest.mark.parametrize("compressed", [True, False])
+def test_contract_matches_oracle(lp, oracle_mod, graphs, name, cap, compressed):
+    g = graphs[name]
+    exp_lab, _ = oracle_mod.lp_cluster(g, cap, 5, 1)
+    cg, mp = oracle_mod.contract(g, exp_lab)
+    G = _gpu_graph(lp, g, compressed)
+    C, M = lp.lp_contract(G, exp_lab)
+    assert C.n == cg.n and C.two_m == cg.two_m and not C.compressed
+    x, a, w, v = lp.lp_decompress(C)
+    assert np.array_equal(_np(M), mp)
+    assert np.array_equal(_np(x).view(np.uint64), cg.xadj)
+    assert np.array_equal(_np(a), cg.adjncy)
+    assert np.array_equal(_np(w), cg.adjwgt)
+    assert np.array_equal(_np(v), cg.vwgt)
+    assert lp.lp_edge_cut(G, exp_lab) == oracle_mod.edge_cut(g, exp_lab)
+
+
+def test_contract_identity_and_all_in_one(lp, oracle_mod, graphs):
+    g = graphs["rmat-s13-ef16"]
+    G = _gpu_graph(lp, g)
+    C, M = lp.lp_contract(G, np.arange(g.n, dtype=np.int32))
+    x, a, w, v = lp.lp_decompress(C)
+    assert np.array_equal(_np(a), g.adjncy) and (_np(w) == 1).all()
+    C, M = lp.lp_contract(G, np.full(g.n, 3, dtype=np.int32))
+    assert C.n == 1 and C.two_m == 0 and int(_np(lp.lp_decompress(C)[3])[0]) == g.n
+
+
+def test_contract_heavy_windows(lp, oracle_mod, synth_mod):
+    # random labels with few clusters: every cluster is heavy (large member
+    # degree) and has many distinct coarse neighbours
+    g = synth_mod.rmat_scale(14, 16, seed=8)
+    rng = np.random.default_rng(3)
+    lab = rng.integers(0, 20000, g.n).astype(np.int32) % g.n
+    cg, mp = oracle_mod.contract(g, lab)
+    C, M = lp.lp_contract(_gpu_graph(lp, g), lab)
+    x, a, w, v = lp.lp_decompress(C)
+    assert np.array_equal(_np(a), cg.adjncy) and np.array_equal(_np(w), cg.adjwgt)
+    assert np.array_equal(_np(x).view(np.uint64), cg.xadj)
+
+
+def test_contract_errors(lp, synth_mod):
+    g = synth_mod.from_edges(4, [(0, 2), (1, 3)], [2**31 - 1, 2**31 - 1])
+    G = _gpu_graph(lp, g)
+    with pytest.raises(lp.LPError) as e:
+        lp.lp_contract(G, np.array([0, 0, 2, 2], dtype=np.int32))
+    assert e.value.status == lp.LP_EOVERFLOW
+    with pytest.raises(lp.LPError) as e:
+        lp.lp_contract(G, np.array([0, 9, 2, 2], dtype=np.int32))
+    assert e.value.status == lp.LP_EINVAL
+
+
+def test_cut_matches_oracle(lp, oracle_mod, graphs):
+    for name in ("rgg2d-16k", "rmat-s12-weighted", "star-10001-w"):
+        g = graphs[name]
+        lab = (np.arange(g.n) * 2654435761 % 97).astype(np.int32)
+        for comp in (True, False):
+            assert lp.lp_edge_cut(_gpu_graph(lp, g, comp), lab) == oracle_mod.edge_cut(g, lab)
+
+
+# ---------------------------------------------------------------- coarsen --
+
+@pytest.mark.parametrize("which", ["rgg2d", "rmat"])
+def test_coarsening_matches_oracle(lp, oracle_mod, synth_mod, which):
+    if which == "rgg2d":
+        g = synth_mod.rgg(2, 1 << 16, synth_mod.rgg_radius(2, 1 << 16, 8.0), 4)
+    else:
+        g = synth_mod.rmat_scale(15, 16, seed=4)
+    levels, final, n_target, cap = oracle_mod.coarsen(g, 1)
+    glev, gfinal, gt, gcap = lp.coarsen(_gpu_graph(lp, g), 1)
+    assert (gt, gcap) == (n_target, cap)
+    assert [G.n for G, _, _ in glev] == [lv[0].n for lv in levels]
+    for (G, lab, mp), (og, olab, omp) in zip(glev, levels):
+        assert np.array_equal(_np(lab), olab) and np.array_equal(_np(mp), omp)
+    x, a, w, v = lp.lp_decompress(gfinal)
+    assert np.array_equal(_np(a), final.adjncy) and np.array_equal(_np(w), final.adjwgt)
+    assert np.array_equal(_np(v), final.vwgt)
