@@ -50,6 +50,27 @@ struct CsrIn {
   const int32_t* vwgt;
 };
 
+// Block-wide maxima of two values, then one atomic per block (256 threads).
+__device__ __forceinline__ void block_max2(unsigned long long a, unsigned long long b, unsigned long long* ga,
+                                           unsigned long long* gb) {
+  __shared__ unsigned long long sa[4], sb[4];
+  a = wave_reduce_max(a);
+  b = wave_reduce_max(b);
+  if (lane_id() == 0) {
+    sa[threadIdx.x / kWave] = a;
+    sb[threadIdx.x / kWave] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < 4; ++i) {
+      a = max(a, sa[i]);
+      b = max(b, sb[i]);
+    }
+    atomicMax(ga, a);
+    atomicMax(gb, b);
+  }
+}
+
 // One wave per vertex: range / self-loop / weight / order checks, weighted
 // degree and degree maxima.
 __global__ __launch_bounds__(256) void k_validate(CsrIn g, uint32_t* err, unsigned long long* max_wdeg,
@@ -58,6 +79,7 @@ __global__ __launch_bounds__(256) void k_validate(CsrIn g, uint32_t* err, unsign
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
   uint32_t bad = 0;
+  unsigned long long mw = 0, md = 0;
   for (int64_t u = wid; u < g.n; u += nw) {
     const uint64_t b = g.xadj[u], e = g.xadj[u + 1];
     if (e < b) {
@@ -79,12 +101,11 @@ __global__ __launch_bounds__(256) void k_validate(CsrIn g, uint32_t* err, unsign
       wsum += w;
     }
     wsum = wave_reduce_add(wsum);
-    if (lane == 0) {
-      atomicMax(max_wdeg, (unsigned long long)wsum);
-      atomicMax(max_deg, (unsigned long long)(e - b));
-    }
+    mw = max(mw, (unsigned long long)wsum);
+    md = max(md, (unsigned long long)(e - b));
   }
   if (bad) atomicOr(err, bad);
+  block_max2(mw, md, max_wdeg, max_deg);
 }
 
 __global__ __launch_bounds__(256) void k_vwgt_check(const int32_t* vwgt, int32_t n, uint32_t* err,
@@ -254,7 +275,7 @@ lp_status check_csr(const CsrIn& in, hipStream_t s, uint64_t* two_m, int64_t* ma
   if (!acc) return LP_ENOMEM;
   LP_CHECK_HIP(hipMemsetAsync(acc, 0, sizeof(Acc), s));
   if (in.n > 0) {
-    hipLaunchKernelGGL(k_validate, dim3(grid_for((int64_t)in.n * kWave, 256, 65536)), dim3(256), 0, s, in,
+    hipLaunchKernelGGL(k_validate, dim3(grid_for((int64_t)in.n * kWave, 256, 4096)), dim3(256), 0, s, in,
                        &acc->err, &acc->wdeg, &acc->deg);
     LP_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_vwgt_check, dim3(grid_for(in.n, 256, 4096)), dim3(256), 0, s, in.vwgt, in.n, &acc->err,

@@ -247,3 +247,24 @@ def test_coarsening_matches_oracle(lp, oracle_mod, synth_mod, which):
     x, a, w, v = lp.lp_decompress(gfinal)
     assert np.array_equal(_np(a), final.adjncy) and np.array_equal(_np(w), final.adjwgt)
     assert np.array_equal(_np(v), final.vwgt)
+
+
+@pytest.mark.parametrize("labels_kind", ["star-identity", "blocks-64", "blocks-4096"])
+def test_contract_light_to_heavy_handover(lp, oracle_mod, synth_mod, labels_kind):
+    # star-identity: one cluster with 3000 distinct coarse neighbours and
+    # member degree 3000 (large light class, handed to the heavy path);
+    # blocks-k: clusters of k consecutive R-MAT vertices (many members each)
+    if labels_kind == "star-identity":
+        g = _star(synth_mod, 3000, center=11)
+        lab = np.arange(g.n, dtype=np.int32)
+    else:
+        g = synth_mod.rmat_scale(14, 16, seed=6)
+        k = int(labels_kind.split("-")[1])
+        lab = ((np.arange(g.n) // k) * k).astype(np.int32)
+    cg, mp = oracle_mod.contract(g, lab)
+    for comp in (True, False):
+        C, M = lp.lp_contract(_gpu_graph(lp, g, comp), lab)
+        x, a, w, v = lp.lp_decompress(C)
+        assert np.array_equal(_np(x).view(np.uint64), cg.xadj)
+        assert np.array_equal(_np(a), cg.adjncy) and np.array_equal(_np(w), cg.adjwgt)
+        assert np.array_equal(_np(v), cg.vwgt) and np.array_equal(_np(M), mp)
