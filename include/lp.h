@@ -134,7 +134,7 @@ lp_status lp_decompress(const lp_graph *g, uint64_t *xadj_dev, int32_t *adjncy_d
 typedef struct {
   int32_t t_lane;   /* 0..16, default 16 */
   int32_t t_wave;   /* t_lane..512, default 256 */
-  int32_t t_block;  /* t_wave..8192, default 8192 (4096 if ratings need 64 bits) */
+  int32_t t_block;  /* t_wave..4096, default 4096 */
   int32_t hub_part; /* target edges per hub partition, 256..8192, default 4096 */
   int32_t timing;   /* nonzero: time each phase with HIP events (stats must be given) */
 } lp_config;

@@ -35,6 +35,18 @@ struct RoundCtx {
   const uint32_t* done;
 };
 
+// Per listed vertex, built once per call: (vertex, degree, byte position of
+// its first code [compressed] or first edge [plain]) and the length of the
+// code bytes (compressed only).
+struct VDesc {
+  const int4* d;      // {u, deg, pos_lo, pos_hi}
+  const uint32_t* len;
+};
+
+__device__ __forceinline__ uint64_t vd_pos(const int4 v) {
+  return (uint64_t)(uint32_t)v.z | ((uint64_t)(uint32_t)v.w << 32);
+}
+
 __device__ __forceinline__ void emit(const RoundCtx& x, int32_t u, const Cand& best, int64_t own) {
   if (best.c >= 0 && best.r > own) {
     x.ptgt[u] = best.c;
@@ -54,18 +66,17 @@ __device__ __forceinline__ void consider(const RoundCtx& x, int32_t c, int64_t r
 
 // ------------------------------------------------------- lane per vertex --
 template <bool COMP>
-__global__ __launch_bounds__(256) void k_rate_lane(RoundCtx x, const int32_t* __restrict__ list, int32_t cnt,
-                                                   const int32_t* __restrict__ deg) {
+__global__ __launch_bounds__(256) void k_rate_lane(RoundCtx x, VDesc vd, int32_t cnt) {
   if (*x.done) return;
   const int32_t i = blockIdx.x * 256 + threadIdx.x;
   if (i >= cnt) return;
-  const int32_t u = list[i];
-  const int32_t d = deg[u];
+  const int4 v4 = vd.d[i];
+  const int32_t u = v4.x;
+  const int32_t d = v4.y;
   int32_t lab[kMaxLane];
   int32_t wt[kMaxLane];
   if constexpr (COMP) {
-    uint64_t pos;
-    (void)read_header(x.g, u, pos);
+    uint64_t pos = vd_pos(v4);
     int32_t v = 0, w = 0;
 #pragma unroll
     for (int k = 0; k < kMaxLane; ++k) {
@@ -81,7 +92,7 @@ __global__ __launch_bounds__(256) void k_rate_lane(RoundCtx x, const int32_t* __
       }
     }
   } else {
-    const uint64_t b = x.g.xadj[u];
+    const uint64_t b = vd_pos(v4);
 #pragma unroll
     for (int k = 0; k < kMaxLane; ++k) {
       lab[k] = -1;
@@ -154,56 +165,102 @@ struct GroupSmem {
   int64_t red[NT / kWave > 0 ? NT / kWave : 1];
 };
 
-// One group (wavefront or workgroup) per vertex; the LDS table holds the
-// vertex's ratings. Table capacity = next power of two >= 2 * deg.
-template <int NT, typename V, bool COMP>
-__global__ __launch_bounds__(NT == kWave ? 256 : NT) void k_rate_group(RoundCtx x, const int32_t* __restrict__ list,
-                                                                       int32_t cnt, const int32_t* __restrict__ deg,
-                                                                       uint32_t tmax) {
+// LDS of one rating group: region A (the record bytes while decoding, then
+// the rating table), neighbour IDs (replaced by their clusters), weights.
+struct GroupLayout {
+  uint32_t tmax;    // table entries
+  uint32_t abytes;  // size of region A
+  uint32_t dmax;    // max degree of the bucket
+  uint32_t per;     // LDS bytes per group
+};
+
+// One group (wavefront or workgroup) per vertex: stage the vertex's code
+// bytes in LDS with independent 16-byte loads, decode them there into
+// neighbour IDs, fetch all neighbour clusters at once, aggregate the ratings
+// in an LDS table (capacity = next power of two >= 2 * deg) and pick the
+// best feasible move.
+template <int NT, typename V, bool COMP, int MAXD>
+__global__ __launch_bounds__(NT == kWave ? 256 : NT) void k_rate_group(RoundCtx x, VDesc vd, int32_t cnt,
+                                                                       GroupLayout L) {
   extern __shared__ __align__(16) uint8_t smem_raw[];
   constexpr int G = (NT == kWave) ? 4 : 1;
   const int gi = (NT == kWave) ? (int)(threadIdx.x / kWave) : 0;
   const int tid = group_tid<NT>();
-  const size_t per = (size_t)tmax * (4 + sizeof(V)) + sizeof(GroupSmem<NT>);
-  uint8_t* base = smem_raw + gi * ((per + 15) & ~size_t(15));
-  int32_t* keys = (int32_t*)base;
-  V* vals = (V*)(base + (size_t)tmax * 4);
-  GroupSmem<NT>& sm = *(GroupSmem<NT>*)(base + (size_t)tmax * (4 + sizeof(V)));
+  uint8_t* base = smem_raw + (size_t)gi * L.per;
+  uint8_t* abuf = base;
+  int32_t* keys = (int32_t*)abuf;
+  V* vals = (V*)(abuf + (size_t)L.tmax * 4);
+  int32_t* ids = (int32_t*)(base + L.abytes);
+  int32_t* wts = x.g.weighted ? ids + L.dmax : nullptr;
+  GroupSmem<NT>& sm = *(GroupSmem<NT>*)(base + L.abytes + (size_t)L.dmax * 4 * (x.g.weighted ? 2 : 1));
   if (*x.done) return;
   for (int64_t it = (int64_t)blockIdx.x * G + gi; it < cnt; it += (int64_t)gridDim.x * G) {
-    const int32_t u = list[it];
-    const uint32_t d = (uint32_t)deg[u];
+    const int4 v4 = vd.d[it];
+    const int32_t u = v4.x;
+    const uint32_t d = (uint32_t)v4.y;
+    const uint64_t pos0 = vd_pos(v4);
+    const int32_t own_c = x.C[u];
+    // 1. neighbour IDs (and weights) into LDS
+    auto put = [&](uint32_t i, int32_t v, int32_t w) {
+      ids[i] = v;
+      if (wts) wts[i] = w;
+    };
+    if constexpr (COMP) {
+      const uint64_t a0 = pos0 & ~15ull;
+      const uint64_t nb = pos0 + vd.len[it] - a0;
+      int32_t pv, pw;
+      if (nb + 16 <= L.abytes && d <= (uint32_t)(NT * MAXD)) {
+        const uint4* src = (const uint4*)(x.g.bytes + a0);
+        uint4* dst = (uint4*)abuf;
+        for (uint32_t i = tid; i < (uint32_t)((nb + 15) / 16); i += NT) dst[i] = src[i];
+        group_sync<NT>();
+        group_decode_record<NT, MAXD>(abuf, (uint32_t)(pos0 - a0), vd.len[it], u, d, x.g.weighted, (uint32_t*)ids,
+                                      ids, wts, sm.dec.scan);
+      } else {
+        uint64_t pos = pos0;
+        (void)group_decode<NT>(x.g.bytes, pos, u, d, x.g.weighted, true, pv, pw, sm.dec, put);
+      }
+    } else {
+      for (uint32_t k = tid; k < d; k += NT) put(k, x.g.adjncy[pos0 + k], x.g.adjwgt ? x.g.adjwgt[pos0 + k] : 1);
+    }
+    group_sync<NT>();
+    // 2. all neighbour clusters at once; clear the table (region A is free)
+    for (uint32_t k = tid; k < d; k += NT) ids[k] = x.C[ids[k]];
     const uint32_t logc = max(6u, ceil_log2(2 * d));
     const uint32_t cap = 1u << logc, mask = cap - 1, shift = 32 - logc;
-    for (uint32_t s = tid; s < cap; s += NT) {
-      keys[s] = kEmpty;
-      vals[s] = 0;
+    for (uint32_t q = tid; q < cap; q += NT) {
+      keys[q] = kEmpty;
+      vals[q] = 0;
     }
     group_sync<NT>();
-    auto ins = [&](uint32_t, int32_t v, int32_t w) { tbl_insert<V>(keys, vals, mask, shift, x.C[v], (V)w); };
-    if constexpr (COMP) {
-      const Nbh h = nbh_locate(x.g, u, d);
-      uint64_t pos = h.codes;
-      int32_t pv, pw;
-      (void)group_decode<NT>(x.g.bytes, pos, u, d, x.g.weighted, true, pv, pw, sm.dec, ins);
-    } else {
-      const uint64_t b = x.g.xadj[u];
-      for (uint32_t k = tid; k < d; k += NT) ins(k, x.g.adjncy[b + k], x.g.adjwgt ? x.g.adjwgt[b + k] : 1);
-    }
+    // 3. ratings
+    for (uint32_t k = tid; k < d; k += NT) tbl_insert<V>(keys, vals, mask, shift, ids[k], wts ? (V)wts[k] : (V)1);
     group_sync<NT>();
-    const int32_t own_c = x.C[u];
+    // 4. best feasible move: each thread's best slot ignoring the cap, one
+    // cluster-weight read per thread; only if that one is full does the
+    // thread rescan its slots with the cap.
     const int64_t wu = vweight(x.g, u);
     Cand best = cand_none();
     int64_t own = 0;
-    for (uint32_t s = tid; s < cap; s += NT) {
-      const int32_t c = keys[s];
+    for (uint32_t q = tid; q < cap; q += NT) {
+      const int32_t c = keys[q];
       if (c == kEmpty) continue;
-      const int64_t r = (int64_t)vals[s];
+      const int64_t r = (int64_t)vals[q];
       if (c == own_c) {
         own = r;
         continue;
       }
-      consider(x, c, r, wu, best);
+      if (r < best.r) continue;
+      const Cand cd{r, tiebreak_key(x.seed, x.round, (uint32_t)c), c};
+      if (cand_better(cd, best)) best = cd;
+    }
+    if (best.c >= 0 && x.W[best.c] + wu > x.cap) {
+      best = cand_none();
+      for (uint32_t q = tid; q < cap; q += NT) {
+        const int32_t c = keys[q];
+        if (c == kEmpty || c == own_c) continue;
+        consider(x, c, (int64_t)vals[q], wu, best);
+      }
     }
     if constexpr (NT == kWave) {
       best = wave_best(best);
@@ -332,19 +389,32 @@ __global__ __launch_bounds__(256) void k_hub_scatter(RoundCtx x, HubMeta hm, int
   }
 }
 
+constexpr uint32_t kHubTable = 8192;  // LDS entries of a (hub, partition) task
+
+struct HubReduceSmem {
+  Cand best[kHubThreads / kWave];
+  int64_t red[kHubThreads / kWave];
+  int32_t scan[kHubThreads / kWave];
+  uint32_t distinct;
+  uint32_t overflow;
+  uint32_t ra[kHubThreads];
+  int32_t pre[kHubThreads + 1];
+};
+
+// One workgroup per (hub, partition). The partition's records of all the
+// hub's segments are walked as one flat range per batch of kHubThreads
+// segments and aggregated in LDS; if more distinct clusters show up than half
+// the table, the partition is re-read in label-range sub-passes.
 template <typename V>
-__global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta hm, int32_t ntasks, uint32_t tcap) {
+__global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta hm, int32_t ntasks) {
   extern __shared__ __align__(16) uint8_t smem_raw[];
+  constexpr uint32_t tcap = kHubTable;
+  constexpr int NT = kHubThreads;
   int32_t* keys = (int32_t*)smem_raw;
   V* vals = (V*)(smem_raw + (size_t)tcap * 4);
-  __shared__ Cand sbest[kHubThreads / kWave];
-  __shared__ int64_t sred[kHubThreads / kWave];
-  __shared__ uint32_t distinct;
-  __shared__ uint32_t overflow;
+  HubReduceSmem& sm = *(HubReduceSmem*)(smem_raw + (size_t)tcap * (4 + sizeof(V)));
   if (*x.done) return;
   const int tid = threadIdx.x;
-  const int lane = lane_id();
-  const int wv = tid / kWave;
   const uint32_t mask = tcap - 1, shift = 32 - ceil_log2(tcap);
   const uint32_t limit = tcap / 2;
   for (int64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
@@ -354,7 +424,7 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta 
     const int32_t u = hm.u[h];
     const uint32_t P = (uint32_t)hm.nparts[h];
     const uint32_t nseg = (uint32_t)hm.nseg[h];
-    const uint64_t rb = hm.rec_base[h];
+    const uint64_t rb0 = hm.rec_base[h];
     const uint32_t* po = hm.poff + hm.poff_base[h];
     const int32_t own_c = x.C[u];
     const int64_t wu = vweight(x.g, u);
@@ -366,40 +436,56 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta 
       own = 0;
       bool over = false;
       for (uint32_t sp = 0; sp < S; ++sp) {
-        for (uint32_t s = tid; s < tcap; s += kHubThreads) {
-          keys[s] = kEmpty;
-          vals[s] = 0;
+        for (uint32_t q = tid; q < tcap; q += NT) {
+          keys[q] = kEmpty;
+          vals[q] = 0;
         }
         if (tid == 0) {
-          distinct = 0;
-          overflow = 0;
+          sm.distinct = 0;
+          sm.overflow = 0;
         }
         __syncthreads();
-        for (uint32_t k = wv; k < nseg; k += kHubThreads / kWave) {
-          const uint32_t a = po[(uint64_t)k * (P + 1) + p], b = po[(uint64_t)k * (P + 1) + p + 1];
-          const uint64_t base = rb + (uint64_t)k * LP_CHUNK_LEN;
-          for (uint32_t i = a + lane; i < b; i += kWave) {
-            const int32_t c = hm.rec_c[base + i];
-            if (S > 1 && (uint32_t)(((uint64_t)(uint32_t)c * S) / (uint64_t)x.g.n) != sp) continue;
-            const V w = hm.rec_w ? (V)hm.rec_w[base + i] : (V)1;
-            uint32_t hs = slot_hash((uint32_t)c) >> shift;
+        for (uint32_t kb = 0; kb < nseg; kb += NT) {
+          const uint32_t k = kb + tid;
+          uint32_t ra = 0, c = 0;
+          if (k < nseg) {
+            ra = po[(uint64_t)k * (P + 1) + p];
+            c = po[(uint64_t)k * (P + 1) + p + 1] - ra;
+          }
+          int32_t total;
+          const int32_t incl = block_incl_scan_add<NT, int32_t>((int32_t)c, sm.scan, &total);
+          sm.ra[tid] = ra;
+          sm.pre[tid] = incl - (int32_t)c;
+          __syncthreads();
+          for (int32_t j = tid; j < total; j += NT) {
+            int32_t lo = 0, hi = NT;
+            while (hi - lo > 1) {
+              const int32_t mid = (lo + hi) >> 1;
+              if (sm.pre[mid] <= j) lo = mid;
+              else hi = mid;
+            }
+            const uint64_t r = rb0 + (uint64_t)(kb + lo) * LP_CHUNK_LEN + sm.ra[lo] + (uint32_t)(j - sm.pre[lo]);
+            const int32_t c2 = hm.rec_c[r];
+            if (S > 1 && (uint32_t)(((uint64_t)(uint32_t)c2 * S) / (uint64_t)x.g.n) != sp) continue;
+            const V w = hm.rec_w ? (V)hm.rec_w[r] : (V)1;
+            uint32_t hs = slot_hash((uint32_t)c2) >> shift;
             bool reserved = false;
             while (true) {
               const int32_t kk = keys[hs];
-              if (kk == c) {
+              if (kk == c2) {
                 lds_add(&vals[hs], w);
                 break;
               }
               if (kk == kEmpty) {
                 if (!reserved) {
-                  if (atomicAdd(&distinct, 1u) >= limit) {
-                    overflow = 1;
+                  if (atomicAdd(&sm.distinct, 1u) >= limit) {
+                    sm.overflow = 1;
                     break;
                   }
                   reserved = true;
                 }
-                const int32_t old = atomicCAS(&keys[hs], kEmpty, c);
-                if (old == kEmpty || old == c) {
+                const int32_t old = atomicCAS(&keys[hs], kEmpty, c2);
+                if (old == kEmpty || old == c2) {
                   lds_add(&vals[hs], w);
                   break;
                 }
@@ -407,16 +493,16 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta 
               hs = (hs + 1) & mask;
             }
           }
+          __syncthreads();
         }
-        __syncthreads();
-        if (overflow) {
+        if (sm.overflow) {
           over = true;
           break;
         }
-        for (uint32_t s = tid; s < tcap; s += kHubThreads) {
-          const int32_t c = keys[s];
+        for (uint32_t q = tid; q < tcap; q += NT) {
+          const int32_t c = keys[q];
           if (c == kEmpty) continue;
-          const int64_t r = (int64_t)vals[s];
+          const int64_t r = (int64_t)vals[q];
           if (c == own_c) {
             own = r;
             continue;
@@ -429,8 +515,8 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta 
       __syncthreads();
       S *= 2;
     }
-    best = block_best<kHubThreads>(best, sbest);
-    own = block_reduce_add<kHubThreads, int64_t>(own, sred);
+    best = block_best<NT>(best, sm.best);
+    own = block_reduce_add<NT, int64_t>(own, sm.red);
     if (tid == 0) {
       hm.res_r[t] = best.r;
       hm.res_key[t] = best.key;
@@ -466,14 +552,36 @@ __global__ __launch_bounds__(256) void k_hub_combine(RoundCtx x, HubMeta hm, int
 constexpr int kBkThreads = 256;
 constexpr int kBkItems = 8;
 constexpr int kBkTile = kBkThreads * kBkItems;
-constexpr int kNumBuckets = 4;
+constexpr int kNumBuckets = 5;  // lane, wave, block (small), block (large), hub
+constexpr int32_t kBlockSplit = 1024;
 
 __device__ __forceinline__ int bucket_of(int32_t d, int32_t t_lane, int32_t t_wave, int32_t t_block) {
   if (d <= 0) return -1;
   if (d <= t_lane) return 0;
   if (d <= t_wave) return 1;
-  if (d <= t_block) return 2;
-  return 3;
+  if (d <= t_block && d <= kBlockSplit) return 2;
+  if (d <= t_block) return 3;
+  return 4;
+}
+
+// Descriptor of every listed (non-hub) vertex: degree and the position of its
+// first code (compressed: after the first-edge header; these degrees are
+// never chunked) or first edge (plain).
+__global__ void k_build_desc(GraphView g, const int32_t* order, const int32_t* deg, int32_t cnt, int4* vdesc,
+                             uint32_t* vlen) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = order[i];
+    uint64_t pos;
+    uint32_t len = 0;
+    if (g.offs) {
+      (void)read_header(g, u, pos);
+      len = (uint32_t)(g.offs[u + 1] - pos);
+    } else {
+      pos = g.xadj[u];
+    }
+    vdesc[i] = make_int4(u, deg[u], (int)(uint32_t)pos, (int)(uint32_t)(pos >> 32));
+    vlen[i] = len;
+  }
 }
 
 __global__ __launch_bounds__(kBkThreads) void k_bucket_count(const int32_t* deg, int32_t n, int32_t t_lane,
@@ -638,6 +746,11 @@ __global__ void k_round_end(const uint32_t* count, uint32_t* done, int64_t* stat
   else *rounds_run = round + 1;
 }
 
+__global__ void k_gather_i32(const int32_t* src, const int32_t* idx, int32_t cnt, int32_t* out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = src[idx[i]];
+}
+
 __global__ void k_init(int32_t n, const int32_t* vwgt, int32_t* C, int64_t* W, int32_t* ptgt) {
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
     C[u] = (int32_t)u;
@@ -654,21 +767,43 @@ lp_status set_lds(F* kern, size_t bytes) {
   return LP_OK;
 }
 
+// LDS layout of a rating group for degrees up to dmax.
+template <int NT, typename V>
+GroupLayout group_layout(uint32_t dmax, bool weighted) {
+  GroupLayout L;
+  L.dmax = dmax;
+  L.tmax = 1u << ceil_log2(2 * std::max<uint32_t>(dmax, 32));
+  const uint64_t table = (uint64_t)L.tmax * (4 + sizeof(V));
+  const uint64_t stage = (uint64_t)dmax * (weighted ? 10 : 5) + 16 + 4ull * NT + 32;
+  L.abytes = (uint32_t)((std::max(table, stage) + 15) & ~15ull);
+  L.per = (uint32_t)((L.abytes + (uint64_t)dmax * 4 * (weighted ? 2 : 1) + sizeof(GroupSmem<NT>) + 15) & ~15ull);
+  return L;
+}
+
 // Launch of one group-rating kernel, templated on group size, rating width
 // and representation.
 template <int NT, typename V, bool COMP>
-lp_status launch_group(const RoundCtx& x, const int32_t* list, int32_t cnt, const int32_t* deg, uint32_t tmax,
-                       hipStream_t s) {
+lp_status launch_group(const RoundCtx& x, VDesc vd, int32_t cnt, uint32_t dmax, bool weighted, hipStream_t s) {
   if (cnt <= 0) return LP_OK;
   constexpr int G = (NT == kWave) ? 4 : 1;
-  const size_t per = ((size_t)tmax * (4 + sizeof(V)) + sizeof(GroupSmem<NT>) + 15) & ~size_t(15);
-  const size_t bytes = per * G;
-  auto kern = k_rate_group<NT, V, COMP>;
+  const GroupLayout L = group_layout<NT, V>(dmax, weighted);
+  const size_t bytes = (size_t)L.per * G;
+  // per-thread slice of the record decoder: dmax / NT neighbours
+  auto kern = (dmax <= (uint32_t)NT * 4) ? k_rate_group<NT, V, COMP, 4>
+              : (dmax <= (uint32_t)NT * 8) ? k_rate_group<NT, V, COMP, 8>
+                                           : k_rate_group<NT, V, COMP, 16>;
   LP_CHECK(set_lds(kern, bytes));
   const int threads = (NT == kWave) ? 256 : NT;
   const unsigned grid = grid_for(cnt, G, 1u << 20);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), bytes, s, x, list, cnt, deg, tmax);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), bytes, s, x, vd, cnt, L);
   return last_error();
+}
+
+template <int NT, bool COMP>
+lp_status launch_group_w(bool wide, const RoundCtx& x, VDesc vd, int32_t cnt, uint32_t dmax, bool weighted,
+                         hipStream_t s) {
+  return wide ? launch_group<NT, int64_t, COMP>(x, vd, cnt, dmax, weighted, s)
+              : launch_group<NT, int32_t, COMP>(x, vd, cnt, dmax, weighted, s);
 }
 
 }  // namespace
@@ -687,14 +822,14 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
   if (n == 0) return LP_OK;
   // knobs (results do not depend on them)
   const bool wide = g->max_wdeg > 0x7FFFFFFFll;
-  int32_t t_lane = 16, t_wave = 256, t_block = wide ? 4096 : 8192, hub_part = 4096;
+  int32_t t_lane = 16, t_wave = 256, t_block = kMaxBlock, hub_part = 4096;
   if (cfg_in) {
     if (cfg_in->t_lane) t_lane = cfg_in->t_lane;
     if (cfg_in->t_wave) t_wave = cfg_in->t_wave;
     if (cfg_in->t_block) t_block = cfg_in->t_block;
     if (cfg_in->hub_part) hub_part = cfg_in->hub_part;
   }
-  const int32_t block_max = wide ? kMaxBlock / 2 : kMaxBlock;
+  const int32_t block_max = kMaxBlock;
   if (t_lane < 0 || t_lane > kMaxLane || t_wave < t_lane || t_wave > kMaxWave || t_block < t_wave ||
       t_block > block_max || hub_part < 256 || hub_part > 8192)
     return LP_EINVAL;
@@ -728,7 +863,7 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
     uint32_t pad;
     uint32_t bucket_tot[4];
     int64_t stats[128];
-    unsigned long long bsums[8];
+    unsigned long long bsums[2 * kNumBuckets];
   };
   Ctl* ctl = sc.alloc<Ctl>(1);
   if (sc.failed) return LP_ENOMEM;
@@ -790,18 +925,30 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
   int32_t bn[kNumBuckets];
   for (int b = 0; b < kNumBuckets; ++b) bn[b] = (int32_t)(bstart[b + 1] - bstart[b]);
 
+  // descriptors of the non-hub buckets
+  const int32_t nlisted = (int32_t)bstart[4];
+  int4* vdesc = sc.alloc<int4>(nlisted);
+  uint32_t* vlen = sc.alloc<uint32_t>(nlisted);
+  if (sc.failed) return LP_ENOMEM;
+  if (nlisted > 0) {
+    hipLaunchKernelGGL(k_build_desc, dim3(grid_for(nlisted, 256, 65536)), dim3(256), 0, s, g->view(), order, deg,
+                       nlisted, vdesc, vlen);
+    LP_CHECK_LAUNCH();
+  }
+  auto vd_of = [&](int b) { return VDesc{vdesc + bstart[b], vlen + bstart[b]}; };
+
   // hub metadata (host-built, small)
-  const int32_t H = bn[3];
+  const int32_t H = bn[4];
   HubMeta hm{};
   int32_t npieces = 0, ntasks = 0;
-  uint32_t tcap_hub = wide ? 8192 : 16384;
   if (H > 0) {
     std::vector<int32_t> hu(H), hd(H);
-    LP_CHECK_HIP(hipMemcpyAsync(hu.data(), order + bstart[3], H * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    LP_CHECK_HIP(hipStreamSynchronize(s));
-    std::vector<int32_t> all_deg(H);
-    for (int h = 0; h < H; ++h)
-      LP_CHECK_HIP(hipMemcpyAsync(&hd[h], deg + hu[h], sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    int32_t* hdeg_dev = sc.alloc<int32_t>(H);
+    if (!hdeg_dev) return LP_ENOMEM;
+    hipLaunchKernelGGL(k_gather_i32, dim3(grid_for(H, 256, 4096)), dim3(256), 0, s, deg, order + bstart[4], H, hdeg_dev);
+    LP_CHECK_LAUNCH();
+    LP_CHECK_HIP(hipMemcpyAsync(hu.data(), order + bstart[4], H * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LP_CHECK_HIP(hipMemcpyAsync(hd.data(), hdeg_dev, H * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     LP_CHECK_HIP(hipStreamSynchronize(s));
     int64_t maxd = 0;
     for (int h = 0; h < H; ++h) maxd = std::max<int64_t>(maxd, hd[h]);
@@ -879,15 +1026,11 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
   x.ptgt = ptgt;
   x.pgain = pgain;
   x.done = &ctl->done;
-  const int32_t* lists[kNumBuckets];
-  for (int b = 0; b < kNumBuckets; ++b) lists[b] = order + bstart[b];
-  const uint32_t wave_tmax = 1u << ceil_log2(2 * (uint32_t)std::max(t_wave, 32));
-  const uint32_t block_tmax = 1u << ceil_log2(2 * (uint32_t)std::max(t_block, 32));
   const size_t piece_lds = sizeof(HubPieceSmem) * 4;
   if (H > 0) {
     LP_CHECK(set_lds(k_hub_scatter, piece_lds));
-    if (wide) LP_CHECK(set_lds(k_hub_reduce<int64_t>, (size_t)tcap_hub * 12));
-    else LP_CHECK(set_lds(k_hub_reduce<int32_t>, (size_t)tcap_hub * 8));
+    if (wide) LP_CHECK(set_lds(k_hub_reduce<int64_t>, (size_t)kHubTable * 12 + sizeof(HubReduceSmem)));
+    else LP_CHECK(set_lds(k_hub_reduce<int32_t>, (size_t)kHubTable * 8 + sizeof(HubReduceSmem)));
   }
 
   for (int32_t r = 0; r < rounds; ++r) {
@@ -896,35 +1039,27 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
     if (bn[0] > 0) {
       LP_CHECK(begin(LP_PHASE_LANE));
       if (g->compressed)
-        hipLaunchKernelGGL(k_rate_lane<true>, dim3(grid_for(bn[0], 256)), dim3(256), 0, s, x, lists[0], bn[0], deg);
+        hipLaunchKernelGGL(k_rate_lane<true>, dim3(grid_for(bn[0], 256)), dim3(256), 0, s, x, vd_of(0), bn[0]);
       else
-        hipLaunchKernelGGL(k_rate_lane<false>, dim3(grid_for(bn[0], 256)), dim3(256), 0, s, x, lists[0], bn[0], deg);
+        hipLaunchKernelGGL(k_rate_lane<false>, dim3(grid_for(bn[0], 256)), dim3(256), 0, s, x, vd_of(0), bn[0]);
       LP_CHECK_LAUNCH();
       LP_CHECK(end());
     }
     if (bn[1] > 0) {
       LP_CHECK(begin(LP_PHASE_WAVE));
-      if (wide) {
-        if (g->compressed) LP_CHECK((launch_group<kWave, int64_t, true>(x, lists[1], bn[1], deg, wave_tmax, s)));
-        else LP_CHECK((launch_group<kWave, int64_t, false>(x, lists[1], bn[1], deg, wave_tmax, s)));
-      } else {
-        if (g->compressed) LP_CHECK((launch_group<kWave, int32_t, true>(x, lists[1], bn[1], deg, wave_tmax, s)));
-        else LP_CHECK((launch_group<kWave, int32_t, false>(x, lists[1], bn[1], deg, wave_tmax, s)));
-      }
+      if (g->compressed) LP_CHECK((launch_group_w<kWave, true>(wide, x, vd_of(1), bn[1], t_wave, g->weighted, s)));
+      else LP_CHECK((launch_group_w<kWave, false>(wide, x, vd_of(1), bn[1], t_wave, g->weighted, s)));
       LP_CHECK(end());
     }
-    if (bn[2] > 0) {
+    if (bn[2] + bn[3] > 0) {
       LP_CHECK(begin(LP_PHASE_BLOCK));
-      if (wide) {
-        if (g->compressed)
-          LP_CHECK((launch_group<kBlockThreads, int64_t, true>(x, lists[2], bn[2], deg, block_tmax, s)));
-        else
-          LP_CHECK((launch_group<kBlockThreads, int64_t, false>(x, lists[2], bn[2], deg, block_tmax, s)));
+      const uint32_t split = (uint32_t)std::min(t_block, kBlockSplit);
+      if (g->compressed) {
+        LP_CHECK((launch_group_w<kGroupThreads, true>(wide, x, vd_of(2), bn[2], split, g->weighted, s)));
+        LP_CHECK((launch_group_w<kGroupThreads, true>(wide, x, vd_of(3), bn[3], t_block, g->weighted, s)));
       } else {
-        if (g->compressed)
-          LP_CHECK((launch_group<kBlockThreads, int32_t, true>(x, lists[2], bn[2], deg, block_tmax, s)));
-        else
-          LP_CHECK((launch_group<kBlockThreads, int32_t, false>(x, lists[2], bn[2], deg, block_tmax, s)));
+        LP_CHECK((launch_group_w<kGroupThreads, false>(wide, x, vd_of(2), bn[2], split, g->weighted, s)));
+        LP_CHECK((launch_group_w<kGroupThreads, false>(wide, x, vd_of(3), bn[3], t_block, g->weighted, s)));
       }
       LP_CHECK(end());
     }
@@ -933,11 +1068,11 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
       hipLaunchKernelGGL(k_hub_scatter, dim3(grid_for(npieces, 4)), dim3(256), piece_lds, s, x, hm, npieces);
       LP_CHECK_LAUNCH();
       if (wide)
-        hipLaunchKernelGGL(k_hub_reduce<int64_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads), (size_t)tcap_hub * 12,
-                           s, x, hm, ntasks, tcap_hub);
+        hipLaunchKernelGGL(k_hub_reduce<int64_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads),
+                           (size_t)kHubTable * 12 + sizeof(HubReduceSmem), s, x, hm, ntasks);
       else
-        hipLaunchKernelGGL(k_hub_reduce<int32_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads), (size_t)tcap_hub * 8,
-                           s, x, hm, ntasks, tcap_hub);
+        hipLaunchKernelGGL(k_hub_reduce<int32_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads),
+                           (size_t)kHubTable * 8 + sizeof(HubReduceSmem), s, x, hm, ntasks);
       LP_CHECK_LAUNCH();
       hipLaunchKernelGGL(k_hub_combine, dim3(grid_for(H, 4)), dim3(256), 0, s, x, hm, H);
       LP_CHECK_LAUNCH();
@@ -972,15 +1107,16 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
     stats_out->rounds_run = h.rounds_run;
     stats_out->n_lane = bn[0];
     stats_out->n_wave = bn[1];
-    stats_out->n_block = bn[2];
-    stats_out->n_hub = bn[3];
+    stats_out->n_block = bn[2] + bn[3];
+    stats_out->n_hub = bn[4];
     for (int i = 0; i < 64; ++i) {
       stats_out->proposals[i] = h.stats[i];
       stats_out->moves[i] = h.stats[64 + i];
     }
     for (int b = 0; b < kNumBuckets; ++b) {
-      stats_out->bucket_edges[b] = h.bsums[b];
-      stats_out->bucket_bytes[b] = h.bsums[kNumBuckets + b];
+      const int o = b < 3 ? b : b - 1;  // both block buckets report as "block"
+      stats_out->bucket_edges[o] += h.bsums[b];
+      stats_out->bucket_bytes[o] += h.bsums[kNumBuckets + b];
     }
     for (auto& m : marks) {
       float ms = 0;

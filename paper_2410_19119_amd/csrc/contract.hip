@@ -1,20 +1,23 @@
 // Cluster contraction (Section IV-B of the paper).
 //
-// Coarse IDs are the ranks of the nonempty labels (increasing label order);
-// members are grouped per coarse vertex. Each coarse neighbourhood (summed
-// weights of the fine edges leaving the cluster, keyed by the coarse ID of
-// the other end) is built with the paper's two-phase aggregation
-// (Section IV-B1), re-planned for gfx950:
-//  - light clusters (small total member degree): one wavefront or one
-//    workgroup per cluster aggregates into an LDS hash table; short members
-//    are walked by one lane each, long members by a whole wavefront; the
-//    table is compacted in place, bitonic-sorted in LDS and staged;
-//  - heavy clusters: every member neighbourhood is cut into segments of
-//    LP_CHUNK_LEN edges; a wavefront per segment writes its (coarse ID,
-//    weight) records grouped by coarse-ID range partition; a workgroup per
-//    (cluster, partition) aggregates that partition in LDS and emits it
-//    sorted. Partitions are ranges, so their outputs concatenate in order.
-// A prefix sum over the coarse degrees then places all neighbourhoods.
+// Coarse IDs are the ranks of the nonempty labels (increasing label order).
+// The coarse neighbourhood of a coarse vertex a is the summed weight of the
+// fine edges leaving cluster a, keyed by the coarse ID of the other end,
+// sorted by that ID. Re-planned for gfx950 in three passes:
+//  1. record pass (edge-parallel): every fine vertex reserves a slice of its
+//     cluster's record region with one atomic and writes one (coarse ID,
+//     weight) record per neighbour (coarse ID -1 for edges inside the
+//     cluster). Short neighbourhoods are decoded by one lane, long ones by a
+//     wavefront per chunk of the compressed format.
+//  2. aggregation, following the paper's two-phase aggregation
+//     (Section IV-B1): light clusters are aggregated by one wavefront or
+//     workgroup from their contiguous records in an LDS hash table, sorted
+//     in LDS and written back in place; heavy clusters (large records or
+//     too many distinct neighbours) first group their records by coarse-ID
+//     range partition in 4096-record chunks, then one workgroup per
+//     (cluster, partition) aggregates and sorts that partition. Partitions
+//     are ranges, so their outputs concatenate in order.
+//  3. a prefix sum over the coarse degrees places every neighbourhood.
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -28,15 +31,22 @@ namespace lp {
 namespace {
 
 constexpr uint32_t kErrLabel = 1, kErrOverflow = 2, kErrFormat = 4;
-constexpr uint32_t kShortMember = 32;   // members up to this degree: one lane each
-constexpr uint32_t kClassWave = 256;    // total member degree per wavefront-cluster
-constexpr uint32_t kClassBlockS = 1024; // ... per workgroup-cluster, small table
-constexpr uint32_t kClassBlockL = 4096; // ... per workgroup-cluster, large table
-constexpr uint32_t kHeavyTable = 4096;  // LDS entries of a heavy (cluster, partition) task
-constexpr uint32_t kHeavyPart = 1024;   // expected distinct coarse IDs per heavy partition
-constexpr int kReduceThreads = 256;
+constexpr uint32_t kShortNbh = 32;       // neighbourhoods up to this length: one lane each
+constexpr uint32_t kPiece = LP_CHUNK_LEN;  // long neighbourhoods: one wavefront per piece
+constexpr uint32_t kClassWave = 256;     // records per wavefront-cluster
+constexpr uint32_t kClassBlockS = 1024;  // records per workgroup-cluster, small table
+constexpr uint32_t kClassBlockL = 4096;  // records per workgroup-cluster, large table
+constexpr uint32_t kHeavyChunk = 4096;   // records per partitioning chunk
+constexpr uint32_t kHeavyTable = 4096;   // LDS entries of a heavy (cluster, partition) task
+constexpr uint32_t kHeavyPart = 1024;    // expected distinct coarse IDs per heavy partition
 constexpr uint32_t kMaxHeavyParts = 1024;
 constexpr int kLightThreads = 256;
+constexpr int kReduceThreads = 256;
+
+struct Rec {
+  int32_t b;  // coarse neighbour, -1 = edge inside the cluster
+  int32_t w;
+};
 
 // ------------------------------------------------------------- setup -----
 __global__ void k_check_mark(const int32_t* C, int32_t n, uint32_t* flags, uint32_t* err) {
@@ -48,32 +58,33 @@ __global__ void k_check_mark(const int32_t* C, int32_t n, uint32_t* flags, uint3
 }
 
 __global__ void k_map(const int32_t* C, int32_t n, const uint32_t* id, const int32_t* deg, const int32_t* vwgt,
-                      int32_t* map, uint32_t* cnt, unsigned long long* vw, unsigned long long* dsum) {
+                      int32_t* map, unsigned long long* vw, unsigned long long* dsum) {
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
     const int32_t a = (int32_t)id[C[u]];
     map[u] = a;
-    atomicAdd(&cnt[a], 1u);
     atomicAdd(&vw[a], (unsigned long long)(vwgt ? vwgt[u] : 1));
     if (deg[u]) atomicAdd(&dsum[a], (unsigned long long)deg[u]);
   }
 }
 
-__global__ void k_members(const int32_t* map, int32_t n, const uint32_t* mstart, uint32_t* cursor, int32_t* members) {
+// Reserves each vertex's slice of its cluster's record region.
+__global__ void k_reserve(const int32_t* map, const int32_t* deg, int32_t n, unsigned long long* cursor,
+                          uint64_t* voff) {
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t a = map[u];
-    members[mstart[a] + atomicAdd(&cursor[a], 1u)] = (int32_t)u;
+    const int32_t d = deg[u];
+    if (d) voff[u] = atomicAdd(&cursor[map[u]], (unsigned long long)d);
   }
 }
 
-// Class 0: no edges; 1: wavefront; 2, 3: workgroup (small / large table);
-// 4: heavy. Light classes get a staging capacity of min(dsum, nc - 1).
+// Class 0: no records; 1: wavefront; 2, 3: workgroup (small / large table);
+// 4: heavy. Staging capacity of light classes = min(dsum, nc - 1).
 __global__ void k_cclass(const unsigned long long* dsum, const unsigned long long* vw, int32_t nc, uint64_t* tcap,
                          uint8_t* cls, int32_t* vwgt_out, uint32_t* err) {
   for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < nc; a += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t d = dsum[a];
     const uint8_t c = d == 0 ? 0 : d <= kClassWave ? 1 : d <= kClassBlockS ? 2 : d <= kClassBlockL ? 3 : 4;
     cls[a] = c;
-    tcap[a] = (c >= 1 && c <= 3) ? std::min<uint64_t>(d, (uint64_t)nc - 1) : 0;
+    tcap[a] = std::min<uint64_t>(d, (uint64_t)nc - 1);
     const unsigned long long w = vw[a];
     if (w > 0x7FFFFFFFull) atomicOr(err, kErrOverflow);
     vwgt_out[a] = (int32_t)w;
@@ -102,27 +113,100 @@ __global__ void k_class_list(const uint8_t* cls, int32_t nc, uint32_t* counters,
 
 __device__ __forceinline__ uint32_t ceil_log2(uint32_t x) { return x <= 1 ? 0 : 32 - __clz(x - 1); }
 
-// ------------------------------------------------------- LDS helpers -----
-__device__ __forceinline__ void tbl_add(int32_t* keys, int64_t* vals, uint32_t mask, uint32_t shift, int32_t b,
-                                        int64_t w) {
-  uint32_t h = slot_hash((uint32_t)b) >> shift;
-  while (true) {
-    const int32_t k = keys[h];
-    if (k == b) {
-      atomicAdd((unsigned long long*)&vals[h], (unsigned long long)w);
-      return;
+// ------------------------------------------------------- record pass -----
+struct GenArgs {
+  GraphView g;
+  const int32_t* map;
+  const int32_t* deg;
+  const uint64_t* rbase;  // record region of each cluster
+  const uint64_t* voff;   // slice of each vertex inside its cluster's region
+  Rec* rec;
+  int2* pieces;           // long neighbourhoods: (vertex, piece)
+  uint32_t* npieces;
+  uint32_t* err;
+};
+
+__device__ __forceinline__ uint32_t pieces_of(uint32_t d, bool comp) {
+  if (comp && d <= LP_CHUNK_THRESHOLD) return 1;
+  return (d + kPiece - 1) / kPiece;
+}
+
+// Thread per vertex: short neighbourhoods are written directly, long ones are
+// listed as pieces (one atomic per wavefront).
+template <bool COMP>
+__global__ __launch_bounds__(256) void k_gen_short(GenArgs x) {
+  const int64_t step = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < x.g.n; base += step) {
+    const int64_t u = base + threadIdx.x;
+    const uint32_t d = u < x.g.n ? (uint32_t)x.deg[u] : 0;
+    const uint32_t np = d > kShortNbh ? pieces_of(d, COMP) : 0;
+    const uint32_t incl = wave_incl_scan_add(np);
+    const uint32_t tot = __shfl(incl, kWave - 1, kWave);
+    if (tot) {
+      uint32_t b = 0;
+      if (lane_id() == kWave - 1) b = atomicAdd(x.npieces, tot);
+      b = __shfl(b, kWave - 1, kWave);
+      for (uint32_t k = 0; k < np; ++k) x.pieces[b + incl - np + k] = make_int2((int)u, (int)k);
     }
-    if (k == kEmpty) {
-      const int32_t old = atomicCAS(&keys[h], kEmpty, b);
-      if (old == kEmpty || old == b) {
-        atomicAdd((unsigned long long*)&vals[h], (unsigned long long)w);
-        return;
-      }
+    if (d == 0 || d > kShortNbh) continue;
+    const int32_t a = x.map[u];
+    Rec* out = x.rec + x.rbase[a] + x.voff[u];
+    auto put = [&](uint32_t i, int32_t v, int32_t w) {
+      const int32_t b = x.map[v];
+      out[i] = Rec{b == a ? -1 : b, w};
+    };
+    if constexpr (COMP) {
+      lane_decode(x.g, (int32_t)u, d, put);
+    } else {
+      const uint64_t e = x.g.xadj[u];
+      for (uint32_t k = 0; k < d; ++k) put(k, x.g.adjncy[e + k], x.g.adjwgt ? x.g.adjwgt[e + k] : 1);
     }
-    h = (h + 1) & mask;
   }
 }
 
+// Wavefront per piece of a long neighbourhood.
+template <bool COMP>
+__global__ __launch_bounds__(256) void k_gen_long(GenArgs x) {
+  __shared__ DecodeSmem<kWave> dsm[4];
+  const int w = threadIdx.x / kWave;
+  const int lane = lane_id();
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  const int64_t cnt = *x.npieces;
+  for (int64_t i = wid; i < cnt; i += nw) {
+    const int2 pc = x.pieces[i];
+    const int32_t u = pc.x;
+    const uint32_t d = (uint32_t)x.deg[u];
+    const int32_t a = x.map[u];
+    Rec* out = x.rec + x.rbase[a] + x.voff[u];
+    auto put = [&](uint32_t j, int32_t v, int32_t wt) {
+      const int32_t b = x.map[v];
+      out[j] = Rec{b == a ? -1 : b, wt};
+    };
+    if constexpr (COMP) {
+      const Nbh h = nbh_locate(x.g, u, d);
+      const uint32_t k = (uint32_t)pc.y;
+      uint64_t pos = nbh_chunk_pos(x.g, h, k);
+      const uint32_t first = h.nchunks > 1 ? k * LP_CHUNK_LEN : 0;
+      const uint32_t len = h.nchunks > 1 ? min((uint32_t)LP_CHUNK_LEN, d - first) : d;
+      int32_t pv, pw;
+      Rec* o2 = out + first;
+      const bool ok = group_decode<kWave>(x.g.bytes, pos, u, len, x.g.weighted, true, pv, pw, dsm[w],
+                                          [&](uint32_t j, int32_t v, int32_t wt) {
+                                            const int32_t b = x.map[v];
+                                            o2[j] = Rec{b == a ? -1 : b, wt};
+                                          });
+      if (!ok && lane == 0) atomicOr(x.err, kErrFormat);
+    } else {
+      const uint32_t first = (uint32_t)pc.y * kPiece;
+      const uint32_t len = min(kPiece, d - first);
+      const uint64_t e = x.g.xadj[u] + first;
+      for (uint32_t j = lane; j < len; j += kWave) put(first + j, x.g.adjncy[e + j], x.g.adjwgt ? x.g.adjwgt[e + j] : 1);
+    }
+  }
+}
+
+// ------------------------------------------------------- LDS helpers -----
 // Insert with a reservation guard: at most `limit` distinct keys enter the
 // table; a further new key sets *overflow instead.
 __device__ __forceinline__ void tbl_add_guarded(int32_t* keys, int64_t* vals, uint32_t mask, uint32_t shift,
@@ -179,114 +263,84 @@ __device__ __forceinline__ void lds_bitonic(int32_t* keys, int64_t* vals, uint32
   }
 }
 
-// Compacts the table's entries to its front (in place, NT slots per step:
-// every write position is at or before a slot already read in that step),
-// sorts them by key and writes them to (ob, ow). Returns the entry count.
-template <int NT>
-__device__ uint32_t compact_sort_write(int32_t* keys, int64_t* vals, uint32_t cap, int32_t* ob, int64_t* ow,
-                                       uint32_t* err, int32_t* scan_sm) {
+// Writes the table's entries to `out` sorted by key: every thread takes its
+// (strided) slots into registers, a prefix count compacts the entries to the
+// front of the table, which is then bitonic-sorted in LDS. Returns the entry
+// count. cap <= NT * SLOTS.
+template <int NT, int SLOTS>
+__device__ uint32_t compact_sort_write(int32_t* keys, int64_t* vals, uint32_t cap, Rec* out, uint32_t* err,
+                                       int32_t* scan_sm) {
   const int tid = group_tid<NT>();
-  uint32_t cnt = 0;
-  for (uint32_t r = 0; r < cap; r += NT) {
-    const uint32_t s = r + tid;
-    const int32_t k = s < cap ? keys[s] : kEmpty;
-    const int64_t v = s < cap ? vals[s] : 0;
-    const int32_t f = k != kEmpty;
-    int32_t tot;
-    const int32_t incl = block_incl_scan_add<NT, int32_t>(f, scan_sm, &tot);
-    group_sync<NT>();
-    if (f) {
-      keys[cnt + incl - 1] = k;
-      vals[cnt + incl - 1] = v;
+  int32_t kk[SLOTS];
+  int64_t vv[SLOTS];
+  int32_t c = 0;
+#pragma unroll
+  for (int i = 0; i < SLOTS; ++i) {
+    const uint32_t q = (uint32_t)tid + (uint32_t)i * NT;
+    kk[i] = kEmpty;
+    vv[i] = 0;
+    if (q < cap) {
+      kk[i] = keys[q];
+      vv[i] = vals[q];
+      c += kk[i] != kEmpty;
     }
-    cnt += (uint32_t)tot;
-    group_sync<NT>();
   }
+  int32_t tot;
+  int32_t o = block_incl_scan_add<NT, int32_t>(c, scan_sm, &tot) - c;
+  group_sync<NT>();
+#pragma unroll
+  for (int i = 0; i < SLOTS; ++i)
+    if (kk[i] != kEmpty) {
+      keys[o] = kk[i];
+      vals[o] = vv[i];
+      ++o;
+    }
+  const uint32_t cnt = (uint32_t)tot;
   uint32_t p2 = 1;
   while (p2 < cnt) p2 <<= 1;
-  for (uint32_t s = cnt + tid; s < p2; s += NT) keys[s] = 0x7FFFFFFF;
+  for (uint32_t q = cnt + tid; q < p2; q += NT) keys[q] = 0x7FFFFFFF;
   group_sync<NT>();
   lds_bitonic<NT>(keys, vals, p2);
   for (uint32_t i = tid; i < cnt; i += NT) {
-    ob[i] = keys[i];
-    ow[i] = vals[i];
-    if (vals[i] > 0x7FFFFFFFll) atomicOr(err, kErrOverflow);
+    const int64_t v = vals[i];
+    if (v > 0x7FFFFFFFll) atomicOr(err, kErrOverflow);
+    out[i] = Rec{keys[i], (int32_t)v};
   }
   group_sync<NT>();
   return cnt;
 }
 
-struct CArgs {
-  GraphView g;
-  const int32_t* map;
-  const int32_t* deg;
-  const int32_t* members;
-  const uint32_t* mstart;
-  const uint64_t* tbase;
+// ------------------------------------------------------------- light -----
+struct AggArgs {
+  const uint64_t* rbase;
+  const unsigned long long* dsum;
   const uint64_t* tcap;
-  int32_t* tb;     // light staging: coarse neighbour
-  int64_t* tw;     // light staging: weight
+  Rec* rec;
   uint64_t* cdeg;  // coarse degree per coarse vertex
   uint32_t* err;
   int32_t nc;
 };
 
-// Walks one short neighbourhood with one lane.
-template <bool COMP, typename F>
-__device__ __forceinline__ void lane_walk(const GraphView& g, int32_t u, uint32_t d, F&& f) {
-  if constexpr (COMP) {
-    lane_decode(g, u, d, f);
-  } else {
-    const uint64_t b = g.xadj[u];
-    for (uint32_t k = 0; k < d; ++k) f(k, g.adjncy[b + k], g.adjwgt ? g.adjwgt[b + k] : 1);
-  }
-}
-
-// Walks one neighbourhood with one wavefront.
-template <bool COMP, typename F>
-__device__ __forceinline__ bool wave_walk(const GraphView& g, int32_t u, uint32_t d, DecodeSmem<kWave>& dsm, F&& f) {
-  if constexpr (COMP) {
-    const Nbh h = nbh_locate(g, u, d);
-    bool ok = true;
-    for (uint32_t ch = 0; ch < h.nchunks; ++ch) {
-      uint64_t pos = nbh_chunk_pos(g, h, ch);
-      const uint32_t first = ch * LP_CHUNK_LEN;
-      const uint32_t cnt = (h.nchunks > 1) ? min((uint32_t)LP_CHUNK_LEN, d - first) : d;
-      int32_t pv, pw;
-      ok &= group_decode<kWave>(g.bytes, pos, u, cnt, g.weighted, true, pv, pw, dsm, f);
-    }
-    return ok;
-  } else {
-    const uint64_t b = g.xadj[u];
-    for (uint32_t k = lane_id(); k < d; k += kWave) f(k, g.adjncy[b + k], g.adjwgt ? g.adjwgt[b + k] : 1);
-    return true;
-  }
-}
-
 template <int NT>
 struct LightSmem {
-  DecodeSmem<kWave> dec[NT / kWave];
   int32_t scan[NT / kWave];
   uint32_t distinct;
   uint32_t overflow;
 };
 
-// Light clusters. NT = 64: one cluster per wavefront (4 per workgroup);
-// NT = 256: one cluster per workgroup. Table capacity = next power of two
-// >= 2 * min(dsum, nc - 1), at most tmax. A cluster whose distinct count
-// would exceed half the capacity (possible only when the capacity is
-// clipped to tmax) is appended to the heavy list (*nheavy entries at
-// heavy_list) instead, with its staging capacity cleared.
-template <int NT, bool COMP>
-__global__ __launch_bounds__(kLightThreads) void k_contract_light(CArgs A, const int32_t* list, int32_t cnt,
+// Light clusters: NT = 64, one cluster per wavefront (4 per workgroup);
+// NT = 256, one cluster per workgroup. The table has the next power of two
+// >= 2 * min(dsum, nc - 1) entries, at most tmax; if that capacity was
+// clipped and the cluster turns out to have more than half of it distinct
+// neighbours, the cluster is appended to the heavy list instead.
+template <int NT>
+__global__ __launch_bounds__(kLightThreads) void k_contract_light(AggArgs A, const int32_t* list, int32_t cnt,
                                                                   uint32_t tmax, int32_t* heavy_list,
-                                                                  uint32_t* nheavy, uint64_t* tcap_rw) {
+                                                                  uint32_t* nheavy) {
   extern __shared__ __align__(16) uint8_t smem_raw[];
   constexpr int G = kLightThreads / NT;
-  constexpr int NW = NT / kWave;
   const int gi = (int)(threadIdx.x / NT);
   const int tid = group_tid<NT>();
-  const int wig = (int)((threadIdx.x % NT) / kWave);  // wave index inside the group
   const size_t per = ((size_t)tmax * 12 + sizeof(LightSmem<NT>) + 15) & ~size_t(15);
   uint8_t* base = smem_raw + gi * per;
   int64_t* vals = (int64_t*)base;
@@ -307,249 +361,110 @@ __global__ __launch_bounds__(kLightThreads) void k_contract_light(CArgs A, const
       sm.overflow = 0;
     }
     group_sync<NT>();
-    const uint32_t m0 = A.mstart[a], m1 = A.mstart[a + 1];
-    auto ins = [&](uint32_t, int32_t v, int32_t w) {
-      const int32_t b = A.map[v];
-      if (b != a) tbl_add_guarded(keys, vals, mask, shift, b, (int64_t)w, limit, &sm.distinct, &sm.overflow);
-    };
-    // short members: one thread each
-    for (uint32_t m = m0 + tid; m < m1; m += NT) {
-      const int32_t u = A.members[m];
-      const uint32_t d = (uint32_t)A.deg[u];
-      if (d > 0 && d <= kShortMember) lane_walk<COMP>(A.g, u, d, ins);
+    Rec* r = A.rec + A.rbase[a];
+    const uint32_t d = (uint32_t)A.dsum[a];
+    for (uint32_t i = tid; i < d; i += NT) {
+      const Rec x = r[i];
+      if (x.b >= 0) tbl_add_guarded(keys, vals, mask, shift, x.b, (int64_t)x.w, limit, &sm.distinct, &sm.overflow);
     }
-    // long members: one wavefront each
-    bool ok = true;
-    for (uint32_t mb = m0 + wig * kWave; mb < m1; mb += NW * kWave) {
-      const uint32_t m = mb + lane_id();
-      const int32_t um = m < m1 ? A.members[m] : 0;
-      uint64_t big = __ballot(m < m1 && (uint32_t)A.deg[um] > kShortMember);
-      while (big) {
-        const int l = __ffsll((long long)big) - 1;
-        big &= big - 1;
-        const int32_t u = __shfl(um, l, kWave);
-        ok &= wave_walk<COMP>(A.g, u, (uint32_t)A.deg[u], sm.dec[wig], ins);
-      }
-    }
-    if (!ok && lane_id() == 0) atomicOr(A.err, kErrFormat);
     group_sync<NT>();
     if (sm.overflow) {
-      if (tid == 0) {
-        heavy_list[atomicAdd(nheavy, 1u)] = a;
-        tcap_rw[a] = 0;
-      }
+      if (tid == 0) heavy_list[atomicAdd(nheavy, 1u)] = a;
       group_sync<NT>();
       continue;
     }
-    const uint32_t k = compact_sort_write<NT>(keys, vals, cap, A.tb + A.tbase[a], A.tw + A.tbase[a], A.err, sm.scan);
+    const uint32_t k = compact_sort_write<NT, (NT == kWave ? 8 : 16)>(keys, vals, cap, r, A.err, sm.scan);
     if (tid == 0) A.cdeg[a] = k;
     group_sync<NT>();
   }
 }
 
-// Final placement of the light staging (wave per light coarse vertex).
-__global__ __launch_bounds__(256) void k_place_light(const uint64_t* cx, const uint64_t* tbase, const uint64_t* tcap,
-                                                     const int32_t* tb, const int64_t* tw, int32_t nc,
-                                                     int32_t* adjncy, int32_t* adjwgt) {
-  const int lane = lane_id();
-  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  for (int64_t a = wid; a < nc; a += nw) {
-    if (tcap[a] == 0) continue;
-    const uint64_t o = cx[a], d = cx[a + 1] - o, t = tbase[a];
-    for (uint64_t i = lane; i < d; i += kWave) {
-      adjncy[o + i] = tb[t + i];
-      adjwgt[o + i] = (int32_t)tw[t + i];
-    }
-  }
-}
-
-// ------------------------------------------------------------ heavy -----
+// ------------------------------------------------------------- heavy -----
 struct Heavy {
   const int32_t* clusters;  // heavy cluster -> coarse vertex
   const int32_t* parts;     // P per heavy cluster
-  const uint32_t* mbase;    // first heavy member of each heavy cluster (H + 1)
+  const uint32_t* cbase;    // first chunk of each heavy cluster (H + 1)
   const uint32_t* tbase;    // first task of each heavy cluster (H + 1)
-  const int32_t* mu;        // heavy member -> fine vertex
-  const int32_t* mh;        // heavy member -> heavy cluster
-  const uint32_t* sbase;    // first segment of each heavy member (M + 1)
-  const uint64_t* rbase;    // first record of each heavy member
-  const uint64_t* pbase;    // first partition-table entry of each heavy member
-  const int2* pieces;       // (heavy member, first segment of that member)
-  uint64_t* seg_rb;         // first record of each segment
-  uint64_t* seg_pt;         // partition table of each segment
-  int32_t* rec_b;           // records: coarse ID
-  int32_t* rec_w;           // records: weight
-  uint32_t* ptab;           // per segment: P + 1 partition offsets
+  const uint64_t* pbase;    // first chunk-table entry of each heavy cluster
+  const int2* chunks;       // (heavy cluster, chunk index)
   const int2* tasks;        // (heavy cluster, partition)
+  Rec* rec2;                // records regrouped by partition inside each chunk
+  uint32_t* ctab;           // per chunk: P + 1 partition offsets
   uint64_t* tcnt;           // records per task, then (scanned) staging base
-  int32_t* ob;              // heavy staging
-  int64_t* ow;
+  Rec* out;                 // heavy staging
   uint64_t* tdeg;           // distinct coarse neighbours per task
 };
 
-__global__ void k_heavy_meta(const int32_t* hl, int32_t H, const uint32_t* mstart, const unsigned long long* dsum,
-                             int32_t nc, int32_t* parts, uint32_t* mcount, uint32_t* pcount) {
+__global__ void k_heavy_meta(const int32_t* hl, int32_t H, const unsigned long long* dsum, int32_t nc, int32_t* parts,
+                             uint32_t* ccount, uint32_t* pcount, uint64_t* tabcount) {
   for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < H; h += (int64_t)gridDim.x * blockDim.x) {
     const int32_t a = hl[h];
-    const uint64_t distinct = std::min<uint64_t>(dsum[a], (uint64_t)nc - 1);
+    const uint64_t d = dsum[a];
+    const uint64_t distinct = std::min<uint64_t>(d, (uint64_t)nc - 1);
     const uint64_t part = std::max<uint64_t>(kHeavyPart, (distinct + kMaxHeavyParts - 1) / kMaxHeavyParts);
-    const int32_t P = (int32_t)std::max<uint64_t>(1, (distinct + part - 1) / part);
-    parts[h] = P;
-    pcount[h] = (uint32_t)P;
-    mcount[h] = mstart[a + 1] - mstart[a];
+    const uint32_t P = (uint32_t)std::max<uint64_t>(1, (distinct + part - 1) / part);
+    const uint32_t nch = (uint32_t)((d + kHeavyChunk - 1) / kHeavyChunk);
+    parts[h] = (int32_t)P;
+    pcount[h] = P;
+    ccount[h] = nch;
+    tabcount[h] = (uint64_t)nch * (P + 1);
   }
 }
 
-// Heavy members (wave per heavy cluster): vertex, cluster, segments,
-// records, partition-table entries and pieces of each member.
-__global__ __launch_bounds__(256) void k_heavy_members(const int32_t* hl, int32_t H, const uint32_t* mstart,
-                                                       const int32_t* members, const int32_t* deg,
-                                                       const int32_t* parts, const uint32_t* mbase, int32_t* mu,
-                                                       int32_t* mh, uint32_t* nseg, uint64_t* nrec, uint64_t* npt,
-                                                       uint32_t* npiece, int compressed) {
-  const int lane = lane_id();
-  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  for (int64_t h = wid; h < H; h += nw) {
-    const int32_t a = hl[h];
-    const uint32_t m0 = mstart[a], cnt = mstart[a + 1] - m0;
-    const uint32_t P = (uint32_t)parts[h];
-    for (uint32_t i = lane; i < cnt; i += kWave) {
-      const int32_t u = members[m0 + i];
-      const uint32_t d = (uint32_t)deg[u];
-      const uint32_t s = (d + LP_CHUNK_LEN - 1) / LP_CHUNK_LEN;
-      const uint32_t o = mbase[h] + i;
-      mu[o] = u;
-      mh[o] = (int32_t)h;
-      nseg[o] = s;
-      nrec[o] = d;
-      npt[o] = (uint64_t)s * (P + 1);
-      npiece[o] = (compressed && d <= LP_CHUNK_THRESHOLD) ? (s ? 1u : 0u) : s;
-    }
-  }
-}
-
-__global__ void k_heavy_pieces(int32_t M, const uint32_t* npiece_scan, const uint32_t* sbase, const uint64_t* rbase,
-                               const uint64_t* pbase, const int32_t* mh, const int32_t* parts, const int32_t* mu,
-                               const int32_t* deg, int compressed, int2* pieces, uint64_t* seg_rb, uint64_t* seg_pt) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t d = (uint32_t)deg[mu[i]];
-    const uint32_t b = npiece_scan[i];
-    const uint32_t ns = sbase[i + 1] - sbase[i];
-    const uint32_t P = (uint32_t)parts[mh[i]];
-    for (uint32_t k = 0; k < ns; ++k) {
-      seg_rb[sbase[i] + k] = rbase[i] + (uint64_t)k * LP_CHUNK_LEN;
-      seg_pt[sbase[i] + k] = pbase[i] + (uint64_t)k * (P + 1);
-    }
-    if (compressed && d <= LP_CHUNK_THRESHOLD) {
-      if (ns) pieces[b] = make_int2((int)i, 0);
-    } else {
-      for (uint32_t k = 0; k < ns; ++k) pieces[b + k] = make_int2((int)i, (int)k);
-    }
-  }
-}
-
-__global__ void k_heavy_tasks(int32_t H, const int32_t* parts, const uint32_t* tbase, int2* tasks) {
-  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < H; h += (int64_t)gridDim.x * blockDim.x)
+__global__ void k_heavy_lists(int32_t H, const int32_t* parts, const uint32_t* cbase, const uint32_t* tbase,
+                              int2* chunks, int2* tasks) {
+  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < H; h += (int64_t)gridDim.x * blockDim.x) {
+    for (uint32_t c = cbase[h]; c < cbase[h + 1]; ++c) chunks[c] = make_int2((int)h, (int)(c - cbase[h]));
     for (int32_t p = 0; p < parts[h]; ++p) tasks[tbase[h] + p] = make_int2((int)h, p);
+  }
 }
-
-struct ScatterSmem {
-  DecodeSmem<kWave> dec;
-  int32_t b[LP_CHUNK_LEN];
-  int32_t w[LP_CHUNK_LEN];
-  uint16_t p[LP_CHUNK_LEN];
-  uint32_t hist[kMaxHeavyParts];
-  uint32_t cnt;
-};
 
 // Range partition of coarse ID b among P parts of [0, nc).
 __device__ __forceinline__ uint32_t range_part(int32_t b, uint32_t P, int32_t nc) {
   return (uint32_t)(((uint64_t)(uint32_t)b * P) / (uint64_t)nc);
 }
 
-// One wavefront per piece: decode the piece's segment(s), keep edges that
-// leave the cluster, group the records of each segment by partition.
-template <bool COMP>
-__global__ __launch_bounds__(256) void k_heavy_scatter(CArgs A, Heavy hv, int32_t npieces) {
-  extern __shared__ __align__(16) uint8_t smem_raw[];
-  ScatterSmem& sm = ((ScatterSmem*)smem_raw)[threadIdx.x / kWave];
-  const int lane = lane_id();
-  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  for (int64_t pc = wid; pc < npieces; pc += nw) {
-    const int2 piece = hv.pieces[pc];
-    const int32_t i = piece.x;
-    const int32_t u = hv.mu[i];
-    const int32_t h = hv.mh[i];
+// One workgroup per chunk: group the chunk's records by partition
+// (records inside the cluster are dropped).
+__global__ __launch_bounds__(256) void k_heavy_partition(AggArgs A, Heavy hv, int32_t nchunks) {
+  __shared__ uint32_t hist[kMaxHeavyParts];
+  for (int64_t ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {
+    const int2 ch = hv.chunks[ci];
+    const int32_t h = ch.x;
     const int32_t a = hv.clusters[h];
     const uint32_t P = (uint32_t)hv.parts[h];
-    const uint32_t d = (uint32_t)A.deg[u];
-    const uint32_t nseg_m = hv.sbase[i + 1] - hv.sbase[i];
-    bool chunked = true;
-    uint32_t nseg_here = 1;
-    uint64_t pos = 0;
-    if constexpr (COMP) {
-      const Nbh hb = nbh_locate(A.g, u, d);
-      chunked = hb.nchunks > 1;
-      nseg_here = chunked ? 1u : nseg_m;
-      pos = chunked ? nbh_chunk_pos(A.g, hb, (uint32_t)piece.y) : hb.codes;
+    const uint64_t off = (uint64_t)ch.y * kHeavyChunk;
+    const uint32_t len = (uint32_t)std::min<uint64_t>(kHeavyChunk, A.dsum[a] - off);
+    const Rec* src = A.rec + A.rbase[a] + off;
+    Rec* dst = hv.rec2 + A.rbase[a] + off;
+    uint32_t* tab = hv.ctab + hv.pbase[h] + (uint64_t)ch.y * (P + 1);
+    for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) hist[j] = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+      const Rec x = src[i];
+      if (x.b >= 0) atomicAdd(&hist[range_part(x.b, P, A.nc)], 1u);
     }
-    int32_t pv = 0, pw = 0;
-    for (uint32_t s = 0; s < nseg_here; ++s) {
-      const uint32_t k = (uint32_t)piece.y + s;
-      const uint32_t first = k * LP_CHUNK_LEN;
-      const uint32_t cnt = min((uint32_t)LP_CHUNK_LEN, d - first);
-      if (lane == 0) sm.cnt = 0;
-      wave_sync_lds();
-      auto keep = [&](uint32_t, int32_t v, int32_t w) {
-        const int32_t b = A.map[v];
-        if (b != a) {
-          const uint32_t slot = atomicAdd(&sm.cnt, 1u);
-          sm.b[slot] = b;
-          sm.w[slot] = w;
-        }
-      };
-      if constexpr (COMP) {
-        if (!group_decode<kWave>(A.g.bytes, pos, u, cnt, A.g.weighted, chunked || s == 0, pv, pw, sm.dec, keep) &&
-            lane == 0)
-          atomicOr(A.err, kErrFormat);
-      } else {
-        const uint64_t e0 = A.g.xadj[u] + first;
-        for (uint32_t j = lane; j < cnt; j += kWave) keep(j, A.g.adjncy[e0 + j], A.g.adjwgt ? A.g.adjwgt[e0 + j] : 1);
-      }
-      for (uint32_t j = lane; j < P; j += kWave) sm.hist[j] = 0;
-      wave_sync_lds();
-      const uint32_t kept = sm.cnt;
-      for (uint32_t j = lane; j < kept; j += kWave) {
-        const uint32_t p = range_part(sm.b[j], P, A.nc);
-        sm.p[j] = (uint16_t)p;
-        atomicAdd(&sm.hist[p], 1u);
-      }
-      wave_sync_lds();
-      uint32_t* pt = hv.ptab + hv.pbase[i] + (uint64_t)k * (P + 1);
+    __syncthreads();
+    if (threadIdx.x < kWave) {  // one wavefront scans the histogram
       uint32_t carry = 0;
       for (uint32_t b0 = 0; b0 < P; b0 += kWave) {
-        const uint32_t j = b0 + lane;
-        const uint32_t v = j < P ? sm.hist[j] : 0;
+        const uint32_t j = b0 + lane_id();
+        const uint32_t v = j < P ? hist[j] : 0;
         const uint32_t inc = wave_incl_scan_add(v);
         if (j < P) {
-          sm.hist[j] = carry + inc - v;
-          pt[j] = carry + inc - v;
+          hist[j] = carry + inc - v;
+          tab[j] = carry + inc - v;
         }
         carry += __shfl(inc, kWave - 1, kWave);
       }
-      if (lane == 0) pt[P] = kept;
-      wave_sync_lds();
-      const uint64_t out = hv.rbase[i] + first;
-      for (uint32_t j = lane; j < kept; j += kWave) {
-        const uint32_t slot = atomicAdd(&sm.hist[sm.p[j]], 1u);
-        hv.rec_b[out + slot] = sm.b[j];
-        hv.rec_w[out + slot] = sm.w[j];
-      }
-      wave_sync_lds();
+      if (lane_id() == 0) tab[P] = carry;
     }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
+      const Rec x = src[i];
+      if (x.b >= 0) dst[atomicAdd(&hist[range_part(x.b, P, A.nc)], 1u)] = x;
+    }
+    __syncthreads();
   }
 }
 
@@ -563,12 +478,10 @@ __global__ __launch_bounds__(256) void k_heavy_count(Heavy hv, int32_t ntasks) {
     const int32_t h = task.x;
     const uint32_t p = (uint32_t)task.y;
     const uint32_t P = (uint32_t)hv.parts[h];
+    const uint32_t nch = hv.cbase[h + 1] - hv.cbase[h];
+    const uint32_t* tab = hv.ctab + hv.pbase[h];
     uint64_t c = 0;
-    const uint32_t s0 = hv.sbase[hv.mbase[h]], s1 = hv.sbase[hv.mbase[h + 1]];
-    for (uint32_t sg = s0 + lane; sg < s1; sg += kWave) {
-      const uint32_t* pt = hv.ptab + hv.seg_pt[sg];
-      c += pt[p + 1] - pt[p];
-    }
+    for (uint32_t k = lane; k < nch; k += kWave) c += tab[(uint64_t)k * (P + 1) + p + 1] - tab[(uint64_t)k * (P + 1) + p];
     c = wave_reduce_add(c);
     if (lane == 0) hv.tcnt[t] = c;
   }
@@ -578,25 +491,26 @@ struct ReduceSmem {
   int32_t scan[kReduceThreads / kWave];
   uint32_t distinct;
   uint32_t overflow;
+  uint32_t ra[kReduceThreads];    // per chunk of the current batch: first record of partition p
+  int32_t pre[kReduceThreads + 1];  // exclusive prefix of the record counts
 };
 
 // One workgroup per (cluster, partition): aggregate the partition's records
 // in LDS over coarse-ID windows (a window whose distinct count exceeds half
 // the table is halved and retried), emitting each window sorted. The table
 // is sized by the task's record count.
-__global__ __launch_bounds__(kReduceThreads) void k_heavy_reduce(CArgs A, Heavy hv, int32_t ntasks) {
+__global__ __launch_bounds__(kReduceThreads) void k_heavy_reduce(AggArgs A, Heavy hv, int32_t ntasks) {
   extern __shared__ __align__(16) uint8_t smem_raw[];
   constexpr int NT = kReduceThreads;
   int64_t* vals = (int64_t*)smem_raw;
   int32_t* keys = (int32_t*)(smem_raw + (size_t)kHeavyTable * 8);
   ReduceSmem& sm = *(ReduceSmem*)(smem_raw + (size_t)kHeavyTable * 12);
   const int tid = threadIdx.x;
-  const int lane = lane_id();
-  const int wv = tid / kWave;
   const uint64_t nc = (uint64_t)A.nc;
   for (int64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
     const int2 task = hv.tasks[t];
     const int32_t h = task.x;
+    const int32_t a = hv.clusters[h];
     const uint32_t p = (uint32_t)task.y;
     const uint32_t P = (uint32_t)hv.parts[h];
     const uint64_t lo_p = ((uint64_t)p * nc + P - 1) / P, hi_p = ((uint64_t)(p + 1) * nc + P - 1) / P;
@@ -606,7 +520,9 @@ __global__ __launch_bounds__(kReduceThreads) void k_heavy_reduce(CArgs A, Heavy 
         min(ceil_log2(kHeavyTable), max(6u, ceil_log2((uint32_t)std::min<uint64_t>(2 * nrec + 2, kHeavyTable))));
     const uint32_t tcap = 1u << logc, mask = tcap - 1, shift = 32 - logc;
     const uint32_t limit = tcap / 2;
-    const uint32_t s0 = hv.sbase[hv.mbase[h]], s1 = hv.sbase[hv.mbase[h + 1]];
+    const uint32_t nch = hv.cbase[h + 1] - hv.cbase[h];
+    const uint32_t* tab = hv.ctab + hv.pbase[h];
+    const Rec* src = hv.rec2 + A.rbase[a];
     uint64_t written = 0;
     uint64_t lo = lo_p, width = hi_p - lo_p;
     while (lo < hi_p) {
@@ -620,26 +536,41 @@ __global__ __launch_bounds__(kReduceThreads) void k_heavy_reduce(CArgs A, Heavy 
         sm.overflow = 0;
       }
       __syncthreads();
-      // one wavefront per segment, lanes over its records of partition p
-      for (uint32_t sg = s0 + wv; sg < s1; sg += NT / kWave) {
-        const uint32_t* pt = hv.ptab + hv.seg_pt[sg];
-        const uint32_t ra = pt[p], rb = pt[p + 1];
-        const uint64_t rbase = hv.seg_rb[sg];
-        for (uint32_t j = ra + lane; j < rb; j += kWave) {
-          const int32_t b = hv.rec_b[rbase + j];
-          if ((uint64_t)b >= lo && (uint64_t)b < hi)
-            tbl_add_guarded(keys, vals, mask, shift, b, (int64_t)hv.rec_w[rbase + j], limit, &sm.distinct,
-                            &sm.overflow);
+      // chunks in batches of NT: every thread loads one chunk's range of
+      // partition p, then the batch's records are walked as one flat range
+      for (uint32_t cb = 0; cb < nch; cb += NT) {
+        const uint32_t k = cb + tid;
+        uint32_t ra = 0, c = 0;
+        if (k < nch) {
+          ra = tab[(uint64_t)k * (P + 1) + p];
+          c = tab[(uint64_t)k * (P + 1) + p + 1] - ra;
         }
+        int32_t total;
+        const int32_t incl = block_incl_scan_add<NT, int32_t>((int32_t)c, sm.scan, &total);
+        sm.ra[tid] = ra;
+        sm.pre[tid] = incl - (int32_t)c;
+        if (tid == 0) sm.pre[NT] = total;
+        __syncthreads();
+        for (int32_t j = tid; j < total; j += NT) {
+          int32_t lo_i = 0, hi_i = NT;  // last chunk with pre <= j
+          while (hi_i - lo_i > 1) {
+            const int32_t mid = (lo_i + hi_i) >> 1;
+            if (sm.pre[mid] <= j) lo_i = mid;
+            else hi_i = mid;
+          }
+          const Rec x = src[(uint64_t)(cb + lo_i) * kHeavyChunk + sm.ra[lo_i] + (uint32_t)(j - sm.pre[lo_i])];
+          if ((uint64_t)x.b >= lo && (uint64_t)x.b < hi)
+            tbl_add_guarded(keys, vals, mask, shift, x.b, (int64_t)x.w, limit, &sm.distinct, &sm.overflow);
+        }
+        __syncthreads();
       }
-      __syncthreads();
       if (sm.overflow && hi - lo > 1) {
         width = std::max<uint64_t>(1, (hi - lo) / 2);
         __syncthreads();
         continue;
       }
-      const uint32_t k = compact_sort_write<NT>(keys, vals, tcap, hv.ob + obase + written, hv.ow + obase + written,
-                                                A.err, sm.scan);
+      const uint32_t k = compact_sort_write<NT, kHeavyTable / NT>(keys, vals, tcap, hv.out + obase + written, A.err,
+                                                                  sm.scan);
       written += k;
       lo = hi;
       width = hi_p - lo;  // try the rest of the partition in one window again
@@ -658,8 +589,33 @@ __global__ void k_heavy_cdeg(Heavy hv, int32_t H, uint64_t* cdeg) {
   }
 }
 
-// Places heavy neighbourhoods: task t of cluster h goes after the outputs
-// of the cluster's earlier partitions (wave per task).
+// ---------------------------------------------------------- placement ----
+// Light clusters: their aggregated neighbourhood sits at the start of their
+// record region (wave per coarse vertex; heavy clusters are skipped).
+__global__ __launch_bounds__(256) void k_place_light(const uint64_t* cx, const uint64_t* rbase, const uint8_t* heavy,
+                                                     const Rec* rec, int32_t nc, int32_t* adjncy, int32_t* adjwgt) {
+  const int lane = lane_id();
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t a = wid; a < nc; a += nw) {
+    const uint64_t o = cx[a], d = cx[a + 1] - o;
+    if (d == 0 || heavy[a]) continue;
+    const Rec* r = rec + rbase[a];
+    for (uint64_t i = lane; i < d; i += kWave) {
+      const Rec x = r[i];
+      adjncy[o + i] = x.b;
+      adjwgt[o + i] = x.w;
+    }
+  }
+}
+
+__global__ void k_mark_heavy(const int32_t* hl, int32_t H, uint8_t* heavy) {
+  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < H; h += (int64_t)gridDim.x * blockDim.x)
+    heavy[hl[h]] = 1;
+}
+
+// Heavy clusters: task t of cluster h goes after the outputs of the
+// cluster's earlier partitions (wave per task).
 __global__ __launch_bounds__(256) void k_place_heavy(Heavy hv, int32_t ntasks, const uint64_t* tdeg_scan,
                                                      const uint64_t* cx, int32_t* adjncy, int32_t* adjwgt) {
   const int lane = lane_id();
@@ -671,8 +627,9 @@ __global__ __launch_bounds__(256) void k_place_heavy(Heavy hv, int32_t ntasks, c
     const uint64_t dst = cx[a] + (tdeg_scan[t] - tdeg_scan[hv.tbase[h]]);
     const uint64_t src = hv.tcnt[t], d = hv.tdeg[t];
     for (uint64_t j = lane; j < d; j += kWave) {
-      adjncy[dst + j] = hv.ob[src + j];
-      adjwgt[dst + j] = (int32_t)hv.ow[src + j];
+      const Rec x = hv.out[src + j];
+      adjncy[dst + j] = x.b;
+      adjwgt[dst + j] = x.w;
     }
   }
 }
@@ -719,114 +676,82 @@ lp_status set_lds(F* kern, size_t bytes) {
   return LP_OK;
 }
 
-template <int NT, bool COMP>
-lp_status launch_light(const CArgs& A, const int32_t* list, uint32_t cnt, uint32_t tmax, int32_t* heavy_list,
-                       uint32_t* nheavy, uint64_t* tcap_rw, hipStream_t s) {
+template <int NT>
+lp_status launch_light(const AggArgs& A, const int32_t* list, uint32_t cnt, uint32_t tmax, int32_t* heavy_list,
+                       uint32_t* nheavy, hipStream_t s) {
   if (cnt == 0) return LP_OK;
   const size_t per = ((size_t)tmax * 12 + sizeof(LightSmem<NT>) + 15) & ~size_t(15);
   const size_t bytes = per * (kLightThreads / NT);
-  auto k = k_contract_light<NT, COMP>;
+  auto k = k_contract_light<NT>;
   LP_CHECK(set_lds(k, bytes));
   hipLaunchKernelGGL(k, dim3(grid_for(cnt, kLightThreads / NT, 1u << 20)), dim3(kLightThreads), bytes, s, A, list,
-                     (int32_t)cnt, tmax, heavy_list, nheavy, tcap_rw);
+                     (int32_t)cnt, tmax, heavy_list, nheavy);
   return last_error();
 }
 
-// Heavy clusters: metadata, scatter, count, reduce. Fills cdeg of heavy
-// clusters and leaves what placement needs in *hv_out.
-template <bool COMP>
-lp_status contract_heavy(const CArgs& A, const int32_t* hl, int32_t H, const unsigned long long* dsum,
-                         Heavy* hv_out, int32_t* ntasks_out, uint64_t** tdeg_scan_out, Scratch& sc) {
+// Heavy clusters: metadata, partitioning, counts, reduction. Fills the coarse
+// degrees of heavy clusters and leaves what placement needs in *hv_out.
+// rec2 has the layout of the record buffer.
+lp_status contract_heavy(const AggArgs& A, const int32_t* hl, int32_t H, Rec* rec2, Heavy* hv_out,
+                         int32_t* ntasks_out, uint64_t** tdeg_scan_out, Scratch& sc) {
   hipStream_t s = sc.stream();
   Heavy hv{};
   int32_t* parts = sc.alloc<int32_t>(H);
-  uint32_t* mbase = sc.alloc<uint32_t>((size_t)H + 1);
+  uint32_t* cbase = sc.alloc<uint32_t>((size_t)H + 1);
   uint32_t* tbase = sc.alloc<uint32_t>((size_t)H + 1);
+  uint64_t* pbase = sc.alloc<uint64_t>((size_t)H + 1);
   uint64_t* tot = sc.alloc<uint64_t>(4);
   uint32_t* tot32 = sc.alloc<uint32_t>(4);
   if (sc.failed) return LP_ENOMEM;
-  LP_CHECK_HIP(hipMemsetAsync(mbase + H, 0, 4, s));
+  LP_CHECK_HIP(hipMemsetAsync(cbase + H, 0, 4, s));
   LP_CHECK_HIP(hipMemsetAsync(tbase + H, 0, 4, s));
-  hipLaunchKernelGGL(k_heavy_meta, dim3(grid_for(H, 256, 4096)), dim3(256), 0, s, hl, H, A.mstart, dsum, A.nc, parts,
-                     mbase, tbase);
+  LP_CHECK_HIP(hipMemsetAsync(pbase + H, 0, 8, s));
+  hipLaunchKernelGGL(k_heavy_meta, dim3(grid_for(H, 256, 4096)), dim3(256), 0, s, hl, H, A.dsum, A.nc, parts, cbase,
+                     tbase, pbase);
   LP_CHECK_LAUNCH();
-  LP_CHECK(scan_exclusive_u32(mbase, mbase, (int64_t)H + 1, &tot32[0], sc));
+  LP_CHECK(scan_exclusive_u32(cbase, cbase, (int64_t)H + 1, &tot32[0], sc));
   LP_CHECK(scan_exclusive_u32(tbase, tbase, (int64_t)H + 1, &tot32[1], sc));
+  LP_CHECK(scan_exclusive_u64(pbase, pbase, (int64_t)H + 1, &tot[0], sc));
   uint32_t ht[2];
+  uint64_t hp = 0;
   LP_CHECK_HIP(hipMemcpyAsync(ht, tot32, 8, hipMemcpyDeviceToHost, s));
+  LP_CHECK_HIP(hipMemcpyAsync(&hp, tot, 8, hipMemcpyDeviceToHost, s));
   LP_CHECK_HIP(hipStreamSynchronize(s));
-  const int32_t M = (int32_t)ht[0], T = (int32_t)ht[1];
-  int32_t* mu = sc.alloc<int32_t>(M);
-  int32_t* mh = sc.alloc<int32_t>(M);
-  uint32_t* sbase = sc.alloc<uint32_t>((size_t)M + 1);
-  uint64_t* rbase = sc.alloc<uint64_t>((size_t)M + 1);
-  uint64_t* pbase = sc.alloc<uint64_t>((size_t)M + 1);
-  uint32_t* npiece = sc.alloc<uint32_t>((size_t)M + 1);
+  const int32_t NCH = (int32_t)ht[0], T = (int32_t)ht[1];
+  int2* chunks = sc.alloc<int2>(NCH);
   int2* tasks = sc.alloc<int2>(T);
   uint64_t* tcnt = sc.alloc<uint64_t>((size_t)T + 1);
   uint64_t* tdeg = sc.alloc<uint64_t>((size_t)T + 1);
+  hv.ctab = sc.alloc<uint32_t>(hp);
   if (sc.failed) return LP_ENOMEM;
-  LP_CHECK_HIP(hipMemsetAsync(sbase + M, 0, 4, s));
-  LP_CHECK_HIP(hipMemsetAsync(rbase + M, 0, 8, s));
-  LP_CHECK_HIP(hipMemsetAsync(pbase + M, 0, 8, s));
-  LP_CHECK_HIP(hipMemsetAsync(npiece + M, 0, 4, s));
   LP_CHECK_HIP(hipMemsetAsync(tcnt + T, 0, 8, s));
-  hipLaunchKernelGGL(k_heavy_members, dim3(grid_for((int64_t)H * kWave, 256, 16384)), dim3(256), 0, s, hl, H,
-                     A.mstart, A.members, A.deg, parts, mbase, mu, mh, sbase, rbase, pbase, npiece, COMP ? 1 : 0);
-  LP_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_heavy_tasks, dim3(grid_for(H, 256, 4096)), dim3(256), 0, s, H, parts, tbase, tasks);
-  LP_CHECK_LAUNCH();
-  LP_CHECK(scan_exclusive_u32(sbase, sbase, (int64_t)M + 1, &tot32[2], sc));
-  LP_CHECK(scan_exclusive_u64(rbase, rbase, (int64_t)M + 1, &tot[0], sc));
-  LP_CHECK(scan_exclusive_u64(pbase, pbase, (int64_t)M + 1, &tot[1], sc));
-  LP_CHECK(scan_exclusive_u32(npiece, npiece, (int64_t)M + 1, &tot32[3], sc));
-  uint64_t h64[2];
-  uint32_t h32[4];
-  LP_CHECK_HIP(hipMemcpyAsync(h64, tot, 16, hipMemcpyDeviceToHost, s));
-  LP_CHECK_HIP(hipMemcpyAsync(h32, tot32, 16, hipMemcpyDeviceToHost, s));
-  LP_CHECK_HIP(hipStreamSynchronize(s));
-  const uint64_t R = h64[0], PT = h64[1];
-  const int32_t NP = (int32_t)h32[3];
-  if (getenv("LPGPU_DEBUG"))
-    fprintf(stderr, "[lpgpu] contract heavy: clusters %d members %d tasks %d segments %u pieces %d records %llu\n", H,
-            M, T, h32[2], NP, (unsigned long long)R);
-  const uint32_t S = h32[2];
-  int2* pieces = sc.alloc<int2>(NP);
-  hv.seg_rb = sc.alloc<uint64_t>(S);
-  hv.seg_pt = sc.alloc<uint64_t>(S);
-  hv.rec_b = sc.alloc<int32_t>(R);
-  hv.rec_w = sc.alloc<int32_t>(R);
-  hv.ptab = sc.alloc<uint32_t>(PT);
-  if (sc.failed) return LP_ENOMEM;
-  hipLaunchKernelGGL(k_heavy_pieces, dim3(grid_for(M, 256, 65536)), dim3(256), 0, s, M, npiece, sbase, rbase, pbase,
-                     mh, parts, mu, A.deg, COMP ? 1 : 0, pieces, hv.seg_rb, hv.seg_pt);
+  hipLaunchKernelGGL(k_heavy_lists, dim3(grid_for(H, 256, 4096)), dim3(256), 0, s, H, parts, cbase, tbase, chunks,
+                     tasks);
   LP_CHECK_LAUNCH();
   hv.clusters = hl;
   hv.parts = parts;
-  hv.mbase = mbase;
+  hv.cbase = cbase;
   hv.tbase = tbase;
-  hv.mu = mu;
-  hv.mh = mh;
-  hv.sbase = sbase;
-  hv.rbase = rbase;
   hv.pbase = pbase;
-  hv.pieces = pieces;
+  hv.chunks = chunks;
   hv.tasks = tasks;
   hv.tcnt = tcnt;
   hv.tdeg = tdeg;
-  if (NP > 0) {
-    const size_t sbytes = sizeof(ScatterSmem) * 4;
-    LP_CHECK(set_lds(k_heavy_scatter<COMP>, sbytes));
-    hipLaunchKernelGGL(k_heavy_scatter<COMP>, dim3(grid_for(NP, 4, 1u << 20)), dim3(256), sbytes, s, A, hv, NP);
+  hv.rec2 = rec2;
+  if (NCH > 0) {
+    hipLaunchKernelGGL(k_heavy_partition, dim3(grid_for(NCH, 1, 1u << 20)), dim3(256), 0, s, A, hv, NCH);
     LP_CHECK_LAUNCH();
   }
   hipLaunchKernelGGL(k_heavy_count, dim3(grid_for((int64_t)T, 4, 65536)), dim3(256), 0, s, hv, T);
   LP_CHECK_LAUNCH();
   LP_CHECK(scan_exclusive_u64(tcnt, tcnt, (int64_t)T + 1, &tot[2], sc));
-  LP_CHECK_HIP(hipMemcpyAsync(h64, tot + 2, 8, hipMemcpyDeviceToHost, s));
+  uint64_t nout = 0;
+  LP_CHECK_HIP(hipMemcpyAsync(&nout, tot + 2, 8, hipMemcpyDeviceToHost, s));
   LP_CHECK_HIP(hipStreamSynchronize(s));
-  hv.ob = sc.alloc<int32_t>(h64[0]);
-  hv.ow = sc.alloc<int64_t>(h64[0]);
+  if (getenv("LPGPU_DEBUG"))
+    fprintf(stderr, "[lpgpu] contract heavy: clusters %d chunks %d tasks %d records %llu\n", H, NCH, T,
+            (unsigned long long)nout);
+  hv.out = sc.alloc<Rec>(nout);
   if (sc.failed) return LP_ENOMEM;
   const size_t rbytes = (size_t)kHeavyTable * 12 + sizeof(ReduceSmem);
   LP_CHECK(set_lds(k_heavy_reduce, rbytes));
@@ -856,13 +781,16 @@ extern "C" lp_status lp_contract(const lp_graph* g, const int32_t* labels, int32
   *coarse_out = nullptr;
   hipStream_t s = (hipStream_t)stream;
   const int32_t n = g->n;
+  const bool debug = getenv("LPGPU_DEBUG") != nullptr;
   Scratch sc(s);
   struct Ctl {
     uint32_t err;
     uint32_t nc;
     uint32_t ccount[8];
+    uint32_t npieces;
+    uint32_t pad;
     uint64_t two_mc;
-    uint64_t tsum;
+    uint64_t nrec;
   };
   Ctl* ctl = sc.alloc<Ctl>(1);
   int32_t* deg = sc.alloc<int32_t>(n);
@@ -893,99 +821,114 @@ extern "C" lp_status lp_contract(const lp_graph* g, const int32_t* labels, int32
     if (h.err) { st = LP_EINVAL; break; }
     const int32_t nc = (int32_t)h.nc;
     cg->n = nc;
-    uint32_t* cnt = sc.alloc<uint32_t>((size_t)nc + 1);
-    uint32_t* cursor = sc.alloc<uint32_t>(nc);
     unsigned long long* vw = sc.alloc<unsigned long long>(nc);
     unsigned long long* dsum = sc.alloc<unsigned long long>(nc);
-    int32_t* members = sc.alloc<int32_t>(n);
+    unsigned long long* cursor = sc.alloc<unsigned long long>(nc);
+    uint64_t* voff = sc.alloc<uint64_t>(n);
+    uint64_t* rbase = sc.alloc<uint64_t>((size_t)nc + 1);
     uint64_t* tcap = sc.alloc<uint64_t>(nc);
-    uint64_t* tbase = sc.alloc<uint64_t>(nc);
     uint64_t* cdeg = sc.alloc<uint64_t>((size_t)nc + 1);
     uint8_t* cls = sc.alloc<uint8_t>(nc);
+    uint8_t* heavy = sc.alloc<uint8_t>(nc);
     int32_t* lists = sc.alloc<int32_t>((size_t)4 * nc);
+    const uint64_t piece_cap = (uint64_t)n + g->two_m / kPiece + 1;
+    int2* pieces = sc.alloc<int2>(piece_cap);
     if (sc.failed) { st = LP_ENOMEM; break; }
     if (hipMalloc((void**)&cg->vwgt, (size_t)nc * sizeof(int32_t)) != hipSuccess ||
         hipMalloc((void**)&cg->xadj, ((size_t)nc + 1) * sizeof(uint64_t)) != hipSuccess) { st = LP_ENOMEM; break; }
-    (void)hipMemsetAsync(cnt, 0, ((size_t)nc + 1) * sizeof(uint32_t), s);
-    (void)hipMemsetAsync(cursor, 0, (size_t)nc * sizeof(uint32_t), s);
     (void)hipMemsetAsync(vw, 0, (size_t)nc * 8, s);
     (void)hipMemsetAsync(dsum, 0, (size_t)nc * 8, s);
+    (void)hipMemsetAsync(cursor, 0, (size_t)nc * 8, s);
     (void)hipMemsetAsync(cdeg, 0, ((size_t)nc + 1) * sizeof(uint64_t), s);
-    hipLaunchKernelGGL(k_map, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, labels, n, flags, deg, g->vwgt, map, cnt,
-                       vw, dsum);
+    (void)hipMemsetAsync(heavy, 0, (size_t)nc, s);
+    hipLaunchKernelGGL(k_map, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, labels, n, flags, deg, g->vwgt, map, vw,
+                       dsum);
     st = last_error();
     if (st) break;
-    st = scan_exclusive_u32(cnt, cnt, (int64_t)nc + 1, nullptr, sc);
+    st = scan_exclusive_u64((const uint64_t*)dsum, rbase, nc, &ctl->nrec, sc);
     if (st) break;
-    hipLaunchKernelGGL(k_members, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, map, n, cnt, cursor, members);
+    hipLaunchKernelGGL(k_reserve, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, map, deg, n, cursor, voff);
     hipLaunchKernelGGL(k_cclass, dim3(grid_for(nc, 256, 65536)), dim3(256), 0, s, dsum, vw, nc, tcap, cls, cg->vwgt,
                        &ctl->err);
     hipLaunchKernelGGL(k_class_list, dim3(grid_for(nc, 256, 65536)), dim3(256), 0, s, cls, nc, ctl->ccount, lists,
                        (int64_t)nc);
     st = last_error();
     if (st) break;
-    st = scan_exclusive_u64(tcap, tbase, nc, &ctl->tsum, sc);
+    // record pass
+    Rec* rec = sc.alloc<Rec>(g->two_m);
+    if (sc.failed) { st = LP_ENOMEM; break; }
+    GenArgs G;
+    G.g = g->view();
+    G.map = map;
+    G.deg = deg;
+    G.rbase = rbase;
+    G.voff = voff;
+    G.rec = rec;
+    G.pieces = pieces;
+    G.npieces = &ctl->npieces;
+    G.err = &ctl->err;
+    if (g->compressed) {
+      hipLaunchKernelGGL(k_gen_short<true>, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, G);
+      hipLaunchKernelGGL(k_gen_long<true>, dim3(8192), dim3(256), 0, s, G);
+    } else {
+      hipLaunchKernelGGL(k_gen_short<false>, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, G);
+      hipLaunchKernelGGL(k_gen_long<false>, dim3(8192), dim3(256), 0, s, G);
+    }
+    st = last_error();
     if (st) break;
     if (hipMemcpyAsync(&h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) { st = LP_EDEVICE; break; }
+    if (h.err & kErrFormat) { st = LP_EINVAL; break; }
     if (h.err) { st = LP_EOVERFLOW; break; }
-    int32_t* tb = sc.alloc<int32_t>(h.tsum);
-    int64_t* tw = sc.alloc<int64_t>(h.tsum);
-    if (sc.failed) { st = LP_ENOMEM; break; }
-    CArgs A;
-    A.g = g->view();
-    A.map = map;
-    A.deg = deg;
-    A.members = members;
-    A.mstart = cnt;
-    A.tbase = tbase;
+    // aggregation
+    AggArgs A;
+    A.rbase = rbase;
+    A.dsum = dsum;
     A.tcap = tcap;
-    A.tb = tb;
-    A.tw = tw;
+    A.rec = rec;
     A.cdeg = cdeg;
     A.err = &ctl->err;
     A.nc = nc;
     const int64_t stride = nc;
     int32_t* hlist = lists + 3 * stride;
     uint32_t* nheavy = &ctl->ccount[4];
-    if (g->compressed) {
-      st = launch_light<kWave, true>(A, lists, h.ccount[1], 2 * kClassWave, hlist, nheavy, tcap, s);
-      if (!st) st = launch_light<kLightThreads, true>(A, lists + stride, h.ccount[2], 2 * kClassBlockS, hlist, nheavy, tcap, s);
-      if (!st) st = launch_light<kLightThreads, true>(A, lists + 2 * stride, h.ccount[3], kClassBlockL, hlist, nheavy, tcap, s);
-    } else {
-      st = launch_light<kWave, false>(A, lists, h.ccount[1], 2 * kClassWave, hlist, nheavy, tcap, s);
-      if (!st) st = launch_light<kLightThreads, false>(A, lists + stride, h.ccount[2], 2 * kClassBlockS, hlist, nheavy, tcap, s);
-      if (!st) st = launch_light<kLightThreads, false>(A, lists + 2 * stride, h.ccount[3], kClassBlockL, hlist, nheavy, tcap, s);
-    }
+    st = launch_light<kWave>(A, lists, h.ccount[1], 2 * kClassWave, hlist, nheavy, s);
+    if (!st) st = launch_light<kLightThreads>(A, lists + stride, h.ccount[2], 2 * kClassBlockS, hlist, nheavy, s);
+    if (!st) st = launch_light<kLightThreads>(A, lists + 2 * stride, h.ccount[3], kClassBlockL, hlist, nheavy, s);
     if (st) break;
-    // heavy count after the light passes (they may hand clusters over)
     const uint32_t heavy0 = h.ccount[4];
     if (hipMemcpyAsync(&h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) { st = LP_EDEVICE; break; }
-    if (getenv("LPGPU_DEBUG"))
-      fprintf(stderr, "[lpgpu] contract n=%d nc=%d classes wave %u blockS %u blockL %u heavy %u (+%u handed over)\n",
-              n, nc, h.ccount[1], h.ccount[2], h.ccount[3], heavy0, h.ccount[4] - heavy0);
+    if (debug)
+      fprintf(stderr,
+              "[lpgpu] contract n=%d nc=%d records %llu pieces %u classes wave %u blockS %u blockL %u heavy %u "
+              "(+%u handed over)\n",
+              n, nc, (unsigned long long)h.nrec, h.npieces, h.ccount[1], h.ccount[2], h.ccount[3], heavy0,
+              h.ccount[4] - heavy0);
     Heavy hv{};
     int32_t T = 0;
     uint64_t* tscan = nullptr;
     const int32_t H = (int32_t)h.ccount[4];
     if (H > 0) {
-      st = g->compressed ? contract_heavy<true>(A, lists + 3 * stride, H, dsum, &hv, &T, &tscan, sc)
-                         : contract_heavy<false>(A, lists + 3 * stride, H, dsum, &hv, &T, &tscan, sc);
+      Rec* rec2 = sc.alloc<Rec>(g->two_m);
+      if (!rec2) { st = LP_ENOMEM; break; }
+      st = contract_heavy(A, hlist, H, rec2, &hv, &T, &tscan, sc);
+      if (st) break;
+      hipLaunchKernelGGL(k_mark_heavy, dim3(grid_for(H, 256, 4096)), dim3(256), 0, s, hlist, H, heavy);
+      st = last_error();
       if (st) break;
     }
     st = scan_exclusive_u64(cdeg, cg->xadj, (int64_t)nc + 1, &ctl->two_mc, sc);
     if (st) break;
     if (hipMemcpyAsync(&h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) { st = LP_EDEVICE; break; }
-    if (h.err & kErrFormat) { st = LP_EINVAL; break; }
     if (h.err) { st = LP_EOVERFLOW; break; }
     cg->two_m = h.two_mc;
     cg->weighted = 1;
     if (hipMalloc((void**)&cg->adjncy, (h.two_mc ? h.two_mc : 1) * sizeof(int32_t)) != hipSuccess ||
         hipMalloc((void**)&cg->adjwgt, (h.two_mc ? h.two_mc : 1) * sizeof(int32_t)) != hipSuccess) { st = LP_ENOMEM; break; }
     hipLaunchKernelGGL(k_place_light, dim3(grid_for((int64_t)nc * kWave, 256, 65536)), dim3(256), 0, s, cg->xadj,
-                       tbase, tcap, tb, tw, nc, cg->adjncy, cg->adjwgt);
+                       rbase, heavy, rec, nc, cg->adjncy, cg->adjwgt);
     if (T > 0)
       hipLaunchKernelGGL(k_place_heavy, dim3(grid_for((int64_t)T * kWave, 256, 65536)), dim3(256), 0, s, hv, T, tscan,
                          cg->xadj, cg->adjncy, cg->adjwgt);

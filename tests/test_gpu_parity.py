@@ -110,7 +110,8 @@ KNOBS = [
     dict(t_lane=1, t_wave=1, t_block=1, hub_part=256),        # almost everything on the hub path
     dict(t_lane=16, t_wave=16, t_block=16, hub_part=512),
     dict(t_lane=4, t_wave=64, t_block=64, hub_part=1024),
-    dict(t_lane=16, t_wave=512, t_block=8192, hub_part=8192),
+    dict(t_lane=16, t_wave=512, t_block=4096, hub_part=8192),
+    dict(t_lane=8, t_wave=100, t_block=1000, hub_part=300),
 ]
 
 
@@ -158,6 +159,8 @@ def test_cluster_argument_errors(lp, graphs):
         lp.lp_cluster(G, 5, -1, 1)
     with pytest.raises(lp.LPError):
         lp.lp_cluster(G, 5, 1, 1, config=dict(t_lane=17))
+    with pytest.raises(lp.LPError):
+        lp.lp_cluster(G, 5, 1, 1, config=dict(t_block=8192))
 
 
 def test_repeatable(lp, graphs):
