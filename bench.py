@@ -34,8 +34,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 PHASE_KERNEL = {
     "lane": "k_rate_lane",
-    "wave": "k_rate_group<64>",
-    "block": "k_rate_group<512>",
+    "tile": "k_rate_tile (small tiles)",
+    "block": "k_rate_tile (large tiles)",
     "hub": "k_hub_scatter+k_hub_reduce+k_hub_combine",
     "accept": "acceptance (compaction, radix sort, segmented scan, admit, apply)",
 }
@@ -58,7 +58,7 @@ def workload(name: str):
 
 def phase_bytes(st, phase: str, n_per_bucket, proposals) -> float:
     """Algorithmic bytes of one launch of a phase (one round)."""
-    idx = {"lane": 0, "wave": 1, "block": 2, "hub": 3}
+    idx = {"lane": 0, "tile": 1, "block": 2, "hub": 3}
     if phase in idx:
         b = idx[phase]
         nv = n_per_bucket[b]
@@ -129,7 +129,7 @@ def main() -> int:
     value = g.two_m * rounds_run * args.steps / total
 
     # LP-only round rate and per-phase breakdown (event-timed, last step)
-    round_phases = ("lane", "wave", "block", "hub", "accept")
+    round_phases = ("lane", "tile", "block", "hub", "accept")
     lp_ms = sum(st.phase_ms[p] for p in round_phases)
     lp_round_rate = g.two_m * rounds_run / (lp_ms / 1e3) if lp_ms > 0 else None
     nb = st.buckets

@@ -125,24 +125,25 @@ lp_status lp_decompress(const lp_graph *g, uint64_t *xadj_dev, int32_t *adjncy_d
 
 /*
  * Result-invariant tuning knobs of lp_cluster: degree-bucket thresholds.
- * Vertices of degree 1..t_lane are rated one per lane, up to t_wave one per
- * wavefront, up to t_block one per workgroup (LDS rating tables, Section
- * IV-A2 first phase); higher-degree vertices go to the chunk-parallel hub
- * path (second phase). Any valid setting gives identical labels.
- * Zero fields mean "default".
+ * Vertices of degree 1..t_lane are rated one per lane; up to t_tile in
+ * edge-balanced tiles (one workgroup rates up to 2048 neighbours of up to
+ * 128 vertices at once); up to t_block one vertex per workgroup (all with LDS
+ * rating tables, Section IV-A2 first phase); higher-degree vertices go to
+ * the chunk-parallel hub path (second phase). Any valid setting gives
+ * identical labels. Zero fields mean "default".
  */
 typedef struct {
   int32_t t_lane;   /* 0..16, default 16 */
-  int32_t t_wave;   /* t_lane..512, default 256 */
-  int32_t t_block;  /* t_wave..4096, default 4096 */
+  int32_t t_tile;   /* t_lane..2048, default 2048 */
+  int32_t t_block;  /* t_tile..4096, default 4096 */
   int32_t hub_part; /* target edges per hub partition, 256..8192, default 4096 */
   int32_t timing;   /* nonzero: time each phase with HIP events (stats must be given) */
 } lp_config;
 
 /* Phases timed when lp_config.timing is set (milliseconds summed over rounds). */
-#define LP_PHASE_SETUP 0  /* degrees, buckets, hub metadata, initial labels */
+#define LP_PHASE_SETUP 0  /* degrees, buckets, tiles, hub metadata, initial labels */
 #define LP_PHASE_LANE 1   /* rating, lane-per-vertex bucket */
-#define LP_PHASE_WAVE 2   /* rating, wavefront-per-vertex bucket */
+#define LP_PHASE_TILE 2   /* rating, edge-balanced tile bucket */
 #define LP_PHASE_BLOCK 3  /* rating, workgroup-per-vertex bucket */
 #define LP_PHASE_HUB 4    /* rating, hub path (scatter, reduce, combine) */
 #define LP_PHASE_ACCEPT 5 /* proposal compaction, sort, admission, apply */
@@ -151,10 +152,10 @@ typedef struct {
 /* Per-call statistics (host struct, filled when requested). */
 typedef struct {
   int32_t rounds_run;         /* rounds that had at least one proposal */
-  int32_t n_lane, n_wave, n_block, n_hub; /* bucket sizes (vertices) */
+  int32_t n_lane, n_tile, n_block, n_hub; /* bucket sizes (vertices) */
   int64_t proposals[64];      /* per round */
   int64_t moves[64];          /* per round */
-  uint64_t bucket_edges[4];   /* adjacency entries per bucket (lane, wave, block, hub) */
+  uint64_t bucket_edges[4];   /* adjacency entries per bucket (lane, tile, block, hub) */
   uint64_t bucket_bytes[4];   /* compressed record bytes per bucket (0 for plain graphs) */
   float phase_ms[LP_NUM_PHASES]; /* filled when lp_config.timing is set */
   int32_t phase_launches[LP_NUM_PHASES]; /* rounds in which the phase ran */

@@ -36,16 +36,16 @@ class LPError(RuntimeError):
         super().__init__(f"{where}: {msg} ({status})")
 
 
-PHASES = ("setup", "lane", "wave", "block", "hub", "accept")
+PHASES = ("setup", "lane", "tile", "block", "hub", "accept")
 
 
 class lp_config(ctypes.Structure):
-    _fields_ = [("t_lane", ctypes.c_int32), ("t_wave", ctypes.c_int32),
+    _fields_ = [("t_lane", ctypes.c_int32), ("t_tile", ctypes.c_int32),
                 ("t_block", ctypes.c_int32), ("hub_part", ctypes.c_int32), ("timing", ctypes.c_int32)]
 
 
 class lp_cluster_stats(ctypes.Structure):
-    _fields_ = [("rounds_run", ctypes.c_int32), ("n_lane", ctypes.c_int32), ("n_wave", ctypes.c_int32),
+    _fields_ = [("rounds_run", ctypes.c_int32), ("n_lane", ctypes.c_int32), ("n_tile", ctypes.c_int32),
                 ("n_block", ctypes.c_int32), ("n_hub", ctypes.c_int32),
                 ("proposals", ctypes.c_int64 * 64), ("moves", ctypes.c_int64 * 64),
                 ("bucket_edges", ctypes.c_uint64 * 4), ("bucket_bytes", ctypes.c_uint64 * 4),
@@ -252,7 +252,7 @@ def lp_cluster(g: Graph, max_cluster_weight: int, rounds: int = 5, seed: int = 1
     out = labels[: g.n]
     if stats:
         k = min(st_obj.rounds_run, 64)
-        return out, ClusterStats(st_obj.rounds_run, (st_obj.n_lane, st_obj.n_wave, st_obj.n_block, st_obj.n_hub),
+        return out, ClusterStats(st_obj.rounds_run, (st_obj.n_lane, st_obj.n_tile, st_obj.n_block, st_obj.n_hub),
                                  list(st_obj.proposals[:k]), list(st_obj.moves[:k]),
                                  tuple(st_obj.bucket_edges), tuple(st_obj.bucket_bytes),
                                  dict(zip(PHASES, st_obj.phase_ms)), dict(zip(PHASES, st_obj.phase_launches)))

@@ -132,146 +132,497 @@ __device__ __forceinline__ void lds_add(V* p, V w) {
   else atomicAdd((int*)p, (int)w);
 }
 
-template <typename V>
-__device__ __forceinline__ void tbl_insert(int32_t* keys, V* vals, uint32_t mask, uint32_t shift, int32_t c, V w) {
-  uint32_t h = slot_hash((uint32_t)c) >> shift;
-  while (true) {
-    const int32_t k = keys[h];
-    if (k == c) {
-      lds_add(&vals[h], w);
-      return;
-    }
-    if (k == kEmpty) {
-      const int32_t old = atomicCAS(&keys[h], kEmpty, c);
-      if (old == kEmpty || old == c) {
-        lds_add(&vals[h], w);
-        return;
-      }
-    }
-    h = (h + 1) & mask;
-  }
-}
-
 __host__ __device__ __forceinline__ uint32_t ceil_log2(uint32_t x) {
   uint32_t k = 0;
   while ((1u << k) < x) ++k;
   return k;
 }
 
-template <int NT>
-struct GroupSmem {
-  DecodeSmem<NT> dec;
-  Cand best[NT / kWave > 0 ? NT / kWave : 1];
-  int64_t red[NT / kWave > 0 ? NT / kWave : 1];
+// ------------------------------------ edge-balanced tiles (phase one) -----
+// Vertices of a tile bucket are cut, in bucket order, into tiles of at most
+// E neighbours and VT vertices. One workgroup rates a whole tile, so that
+// the loads of each step are independent of one another:
+//   1. the tile's code bytes are copied to LDS as aligned dwords; bytes of a
+//      dword outside a vertex's codes are set to 0, so each of them decodes
+//      as one extra (ignored) number;
+//   2. every thread takes a contiguous run of dwords and extracts the numbers
+//      that end in it from an 8-byte register window (a VarInt has at most
+//      five bytes), placing them by a prefix count of terminators;
+//   3. every thread takes a contiguous slice of the tile's neighbours; a
+//      segmented prefix sum (segments = vertices) turns gaps and weight
+//      differences into IDs and weights, and all neighbour labels are
+//      fetched at once;
+//   4. each vertex owns a region of 1.5 * deg + 1 slots of an LDS hash table
+//      (aliasing the bytes and numbers of steps 1-2) in which its ratings
+//      are summed;
+//   5. a selection group (a wavefront, or the whole workgroup for tiles of
+//      very few vertices) walks a vertex's slots once: own rating and best
+//      other cluster by (rating desc, tie-break key asc), reduced across the
+//      group; the winner is checked against the cap, and only vertices whose
+//      winner is full repeat the walk with the cap applied to every
+//      candidate that beats the own rating.
+template <int NT, int E, int VT>
+struct TileCfg {
+  static constexpr int kThreads = NT;
+  static constexpr int kEdges = E;
+  static constexpr int kVerts = VT;
+  static constexpr int kItems = E / NT;
+  static constexpr int kSlots = E + E / 2 + VT;
+  static constexpr int kSelGroup = VT > 8 ? kWave : NT;  // threads per selected vertex
+};
+using TileSmall = TileCfg<256, 2048, 80>;
+using TileLarge = TileCfg<512, 4096, 4>;
+constexpr int kTileSeg = 128;  // vertices walked by one thread of the tiling pass
+
+template <int NT, int VT>
+struct TileShared {
+  int32_t u[VT];
+  int32_t own_c[VT];
+  int32_t wu[VT];
+  int32_t best_c[VT];
+  uint64_t pos[VT];  // compressed: byte of the first code; plain: first edge
+  uint32_t len[VT];  // compressed: code bytes
+  uint32_t ebase[VT + 1];
+  uint32_t dwbase[VT + 1];
+  uint32_t rstart[VT + 1];  // index of the vertex's first real number
+  uint32_t tbase[VT + 1];
+  int64_t own_r[VT];
+  int64_t gain[VT];
+  int32_t scan[NT / kWave];
+  int32_t scan2[NT / kWave];
+  Cand cb[NT / kWave];
+  int64_t red[NT / kWave];
+  uint32_t seg_flags;
+  uint32_t any_redo;
 };
 
-// LDS of one rating group: region A (the record bytes while decoding, then
-// the rating table), neighbour IDs (replaced by their clusters), weights.
-struct GroupLayout {
-  uint32_t tmax;    // table entries
-  uint32_t abytes;  // size of region A
-  uint32_t dmax;    // max degree of the bucket
-  uint32_t per;     // LDS bytes per group
+// LDS layout of a tile workgroup: region A holds the staged bytes followed by
+// the decoded numbers, and later the rating table (keys, then values).
+struct TileLayout {
+  uint32_t table_bytes;  // kSlots * (4 + sizeof(V))
+  uint32_t nums_off;     // byte offset of the numbers in region A
+  uint32_t stage_bytes;  // staged-byte budget of a tile
+  uint32_t abytes;       // size of region A
 };
 
-// One group (wavefront or workgroup) per vertex: stage the vertex's code
-// bytes in LDS with independent 16-byte loads, decode them there into
-// neighbour IDs, fetch all neighbour clusters at once, aggregate the ratings
-// in an LDS table (capacity = next power of two >= 2 * deg) and pick the
-// best feasible move.
-template <int NT, typename V, bool COMP, int MAXD>
-__global__ __launch_bounds__(NT == kWave ? 256 : NT) void k_rate_group(RoundCtx x, VDesc vd, int32_t cnt,
-                                                                       GroupLayout L) {
-  extern __shared__ __align__(16) uint8_t smem_raw[];
-  constexpr int G = (NT == kWave) ? 4 : 1;
-  const int gi = (NT == kWave) ? (int)(threadIdx.x / kWave) : 0;
-  const int tid = group_tid<NT>();
-  uint8_t* base = smem_raw + (size_t)gi * L.per;
-  uint8_t* abuf = base;
-  int32_t* keys = (int32_t*)abuf;
-  V* vals = (V*)(abuf + (size_t)L.tmax * 4);
-  int32_t* ids = (int32_t*)(base + L.abytes);
-  int32_t* wts = x.g.weighted ? ids + L.dmax : nullptr;
-  GroupSmem<NT>& sm = *(GroupSmem<NT>*)(base + L.abytes + (size_t)L.dmax * 4 * (x.g.weighted ? 2 : 1));
-  if (*x.done) return;
-  for (int64_t it = (int64_t)blockIdx.x * G + gi; it < cnt; it += (int64_t)gridDim.x * G) {
-    const int4 v4 = vd.d[it];
-    const int32_t u = v4.x;
-    const uint32_t d = (uint32_t)v4.y;
-    const uint64_t pos0 = vd_pos(v4);
-    const int32_t own_c = x.C[u];
-    // 1. neighbour IDs (and weights) into LDS
-    auto put = [&](uint32_t i, int32_t v, int32_t w) {
-      ids[i] = v;
-      if (wts) wts[i] = w;
-    };
-    if constexpr (COMP) {
-      const uint64_t a0 = pos0 & ~15ull;
-      const uint64_t nb = pos0 + vd.len[it] - a0;
-      int32_t pv, pw;
-      if (nb + 16 <= L.abytes && d <= (uint32_t)(NT * MAXD)) {
-        const uint4* src = (const uint4*)(x.g.bytes + a0);
-        uint4* dst = (uint4*)abuf;
-        for (uint32_t i = tid; i < (uint32_t)((nb + 15) / 16); i += NT) dst[i] = src[i];
-        group_sync<NT>();
-        group_decode_record<NT, MAXD>(abuf, (uint32_t)(pos0 - a0), vd.len[it], u, d, x.g.weighted, (uint32_t*)ids,
-                                      ids, wts, sm.dec.scan);
-      } else {
-        uint64_t pos = pos0;
-        (void)group_decode<NT>(x.g.bytes, pos, u, d, x.g.weighted, true, pv, pw, sm.dec, put);
-      }
-    } else {
-      for (uint32_t k = tid; k < d; k += NT) put(k, x.g.adjncy[pos0 + k], x.g.adjwgt ? x.g.adjwgt[pos0 + k] : 1);
-    }
-    group_sync<NT>();
-    // 2. all neighbour clusters at once; clear the table (region A is free)
-    for (uint32_t k = tid; k < d; k += NT) ids[k] = x.C[ids[k]];
-    const uint32_t logc = max(6u, ceil_log2(2 * d));
-    const uint32_t cap = 1u << logc, mask = cap - 1, shift = 32 - logc;
-    for (uint32_t q = tid; q < cap; q += NT) {
-      keys[q] = kEmpty;
-      vals[q] = 0;
-    }
-    group_sync<NT>();
-    // 3. ratings
-    for (uint32_t k = tid; k < d; k += NT) tbl_insert<V>(keys, vals, mask, shift, ids[k], wts ? (V)wts[k] : (V)1);
-    group_sync<NT>();
-    // 4. best feasible move: each thread's best slot ignoring the cap, one
-    // cluster-weight read per thread; only if that one is full does the
-    // thread rescan its slots with the cap.
-    const int64_t wu = vweight(x.g, u);
-    Cand best = cand_none();
-    int64_t own = 0;
-    for (uint32_t q = tid; q < cap; q += NT) {
-      const int32_t c = keys[q];
-      if (c == kEmpty) continue;
-      const int64_t r = (int64_t)vals[q];
-      if (c == own_c) {
-        own = r;
-        continue;
-      }
-      if (r < best.r) continue;
-      const Cand cd{r, tiebreak_key(x.seed, x.round, (uint32_t)c), c};
-      if (cand_better(cd, best)) best = cd;
-    }
-    if (best.c >= 0 && x.W[best.c] + wu > x.cap) {
-      best = cand_none();
-      for (uint32_t q = tid; q < cap; q += NT) {
-        const int32_t c = keys[q];
-        if (c == kEmpty || c == own_c) continue;
-        consider(x, c, (int64_t)vals[q], wu, best);
-      }
-    }
-    if constexpr (NT == kWave) {
-      best = wave_best(best);
-      own = wave_reduce_add(own);
-    } else {
-      best = block_best<NT>(best, sm.best);
-      own = block_reduce_add<NT, int64_t>(own, sm.red);
-    }
-    if (tid == 0) emit(x, u, best, own);
-    group_sync<NT>();
+template <class T, typename V>
+__host__ __device__ inline TileLayout tile_layout(bool comp, bool weighted) {
+  TileLayout L;
+  const uint32_t per = weighted ? 2u : 1u;
+  L.table_bytes = (uint32_t)T::kSlots * (4u + (uint32_t)sizeof(V));
+  const uint32_t nums = comp ? (per * T::kEdges + 6u * T::kVerts) * 4u : 0u;
+  // any single vertex of the bucket must fit: <= 5 bytes per number
+  const uint32_t worst = comp ? 5u * per * T::kEdges + 8u : 0u;
+  uint32_t sb = L.table_bytes > nums ? L.table_bytes - nums : 0u;
+  if (sb < worst) sb = worst;
+  sb = (sb + 15u) & ~15u;
+  L.stage_bytes = comp ? sb : 0u;
+  L.nums_off = L.stage_bytes;
+  L.abytes = L.stage_bytes + nums;
+  if (L.abytes < L.table_bytes) L.abytes = L.table_bytes;
+  L.abytes = (L.abytes + 15u) & ~15u;
+  return L;
+}
+
+// Index i in [0, cnt) with base[i] <= x < base[i + 1].
+__device__ __forceinline__ int32_t tile_find(const uint32_t* base, int32_t cnt, uint32_t x) {
+  int32_t lo = 0, hi = cnt;
+  while (hi - lo > 1) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (base[mid] <= x) lo = mid;
+    else hi = mid;
   }
+  return lo;
+}
+
+__device__ __forceinline__ uint32_t tile_slots(uint32_t d) { return d + (d >> 1) + 1; }
+
+template <typename V>
+__device__ __forceinline__ void tile_insert(int32_t* keys, V* vals, uint32_t base, uint32_t size, int32_t c, V w) {
+  uint32_t h = __umulhi(slot_hash((uint32_t)c), size);
+  while (true) {
+    const int32_t old = atomicCAS(&keys[base + h], kEmpty, c);
+    if (old == kEmpty || old == c) break;
+    if (++h == size) h = 0;
+  }
+  lds_add(&vals[base + h], w);
+}
+
+// Segmented scan over the workgroup of (head, s, s2): a head restarts the
+// sums. Gives the exclusive prefix of this thread.
+template <int NT>
+__device__ __forceinline__ void tile_seg_scan(bool head, int32_t s, int32_t s2, int32_t* sm, int32_t* sm2,
+                                             uint32_t* smf, int32_t& ex, int32_t& ex2) {
+  const int lane = lane_id();
+  int32_t f = head ? 1 : 0;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int32_t fu = __shfl_up(f, d, kWave);
+    const int32_t su = __shfl_up(s, d, kWave);
+    const int32_t su2 = __shfl_up(s2, d, kWave);
+    if (lane >= d) {
+      if (!f) {
+        s += su;
+        s2 += su2;
+      }
+      f |= fu;
+    }
+  }
+  int32_t ef = __shfl_up(f, 1, kWave), es = __shfl_up(s, 1, kWave), es2 = __shfl_up(s2, 1, kWave);
+  if (lane == 0) {
+    ef = 0;
+    es = 0;
+    es2 = 0;
+  }
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == kWave - 1) {
+    sm[w] = s;
+    sm2[w] = s2;
+    atomicOr(smf, (uint32_t)f << w);
+  }
+  __syncthreads();
+  int32_t cs = 0, cs2 = 0;
+  const uint32_t flags = *smf;
+  for (int k = 0; k < w; ++k) {
+    if ((flags >> k) & 1u) {
+      cs = sm[k];
+      cs2 = sm2[k];
+    } else {
+      cs += sm[k];
+      cs2 += sm2[k];
+    }
+  }
+  ex = ef ? es : cs + es;
+  ex2 = ef ? es2 : cs2 + es2;
+}
+
+// Value of the VarInt whose last byte is byte b (4..7) of the 8-byte window
+// w (bytes 0..3 = previous dword, 4..7 = current); term = terminator bits
+// (bit 7 of every byte with its top bit clear) of the window.
+__device__ __forceinline__ uint32_t window_value(uint64_t w, uint64_t term, uint32_t b) {
+  const uint64_t below = term & ((1ull << (8 * b)) - 1ull);
+  const uint32_t s = below ? (uint32_t)((63 - __clzll(below)) >> 3) + 1u : (b >= 4 ? b - 4 : 0u);
+  uint32_t v = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < 5; ++k) {
+    const uint32_t p = s + k;
+    if (p <= b) v |= (uint32_t)((w >> (8 * p)) & 0x7Full) << (7 * k);
+  }
+  return v;
+}
+
+template <class T, typename V, bool COMP>
+__global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd, const int32_t* tiles,
+                                                           const uint32_t* ntiles_p, TileLayout L) {
+  constexpr int NT = T::kThreads, VT = T::kVerts, ITEMS = T::kItems, SG = T::kSelGroup;
+  constexpr int NSG = NT / SG;  // selection groups per workgroup
+  extern __shared__ __align__(16) uint8_t smem_raw[];
+  if (*x.done) return;
+  const int tid = threadIdx.x;
+  const bool weighted = x.g.weighted;
+  const uint32_t per = weighted ? 2u : 1u;
+  uint8_t* A = smem_raw;
+  uint32_t* A32 = (uint32_t*)A;
+  int32_t* keys = (int32_t*)A;
+  V* vals = (V*)(A + (size_t)T::kSlots * 4);
+  uint32_t* nums = (uint32_t*)(A + L.nums_off);
+  TileShared<NT, VT>& sh = *(TileShared<NT, VT>*)(A + L.abytes);
+  const int sgi = tid / SG;           // selection group of this thread
+  const int sl = tid % SG;            // lane within the selection group
+
+  // XCD-aware order: the workgroups of one XCD take a contiguous range of tiles
+  const uint32_t T_ = *ntiles_p;
+  const uint32_t xcd = blockIdx.x & 7u, gx = gridDim.x >> 3;
+  const uint32_t lo = (uint32_t)(((uint64_t)T_ * xcd) >> 3), hi = (uint32_t)(((uint64_t)T_ * (xcd + 1)) >> 3);
+  for (uint32_t t = lo + (blockIdx.x >> 3); t < hi; t += gx) {
+    const int32_t t0 = tiles[t];
+    const int32_t nv = tiles[t + 1] - t0;
+    // 0. vertex descriptors and bases
+    uint32_t d = 0, ndw = 0, nnum = 0, nsl = 0;
+    if (tid < nv) {
+      const int4 v4 = vd.d[t0 + tid];
+      const int32_t u = v4.x;
+      d = (uint32_t)v4.y;
+      const uint64_t pos = vd_pos(v4);
+      sh.u[tid] = u;
+      sh.own_c[tid] = x.C[u];
+      sh.wu[tid] = x.g.vwgt ? x.g.vwgt[u] : 1;
+      sh.pos[tid] = pos;
+      if constexpr (COMP) {
+        const uint32_t len = vd.len[t0 + tid];
+        const uint32_t pre = (uint32_t)(pos & 3u);
+        ndw = (pre + len + 3u) >> 2;
+        nnum = per * d + 4u * ndw - len;
+        sh.len[tid] = len;
+      }
+      nsl = tile_slots(d);
+    }
+    {
+      int32_t tot1, tot2;
+      const int32_t p1 = (int32_t)(d | (ndw << 16));
+      const int32_t p2 = (int32_t)(nnum | (nsl << 16));
+      const int32_t i1 = block_incl_scan_add<NT, int32_t>(p1, sh.scan, &tot1);
+      const int32_t i2 = block_incl_scan_add<NT, int32_t>(p2, sh.scan2, &tot2);
+      const uint32_t e1 = (uint32_t)(i1 - p1), e2 = (uint32_t)(i2 - p2);
+      if (tid < nv) {
+        sh.ebase[tid] = e1 & 0xFFFFu;
+        sh.dwbase[tid] = e1 >> 16;
+        sh.rstart[tid] = (e2 & 0xFFFFu) + (COMP ? (uint32_t)(sh.pos[tid] & 3u) : 0u);
+        sh.tbase[tid] = e2 >> 16;
+      }
+      if (tid == 0) {
+        sh.ebase[nv] = (uint32_t)tot1 & 0xFFFFu;
+        sh.dwbase[nv] = (uint32_t)tot1 >> 16;
+        sh.rstart[nv] = (uint32_t)tot2 & 0xFFFFu;
+        sh.tbase[nv] = (uint32_t)tot2 >> 16;
+        sh.any_redo = 0;
+        sh.seg_flags = 0;
+      }
+    }
+    __syncthreads();
+    const uint32_t Et = sh.ebase[nv];
+    const uint32_t St = sh.tbase[nv];
+    if constexpr (COMP) {
+      // 1. stage the code bytes (four independent loads in flight per thread)
+      const uint32_t Dt = sh.dwbase[nv];
+      for (uint32_t j0 = tid; j0 < Dt; j0 += 4 * NT) {
+        uint32_t w[4], off[4];
+        int32_t vi4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t j = j0 + (uint32_t)k * NT;
+          vi4[k] = -1;
+          w[k] = 0;
+          off[k] = 0;
+          if (j < Dt) {
+            const int32_t i = tile_find(sh.dwbase, nv, j);
+            vi4[k] = i;
+            off[k] = 4u * (j - sh.dwbase[i]);
+            w[k] = *(const uint32_t*)(x.g.bytes + (sh.pos[i] & ~3ull) + off[k]);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (vi4[k] < 0) continue;
+          const int32_t i = vi4[k];
+          const uint32_t b0 = (uint32_t)(sh.pos[i] & 3u), b1 = b0 + sh.len[i];
+          uint32_t v = w[k];
+#pragma unroll
+          for (uint32_t b = 0; b < 4; ++b)
+            if (off[k] + b < b0 || off[k] + b >= b1) v &= ~(0xFFu << (8 * b));
+          A32[j0 + (uint32_t)k * NT] = v;
+        }
+      }
+      __syncthreads();
+      // 2. numbers in stream order
+      {
+        const uint32_t Q = (Dt + NT - 1) / NT;
+        const uint32_t j0 = min(Dt, tid * Q), j1 = min(Dt, j0 + Q);
+        int32_t cnt = 0;
+        for (uint32_t j = j0; j < j1; ++j) cnt += __popc(~A32[j] & 0x80808080u);
+        int32_t tot;
+        uint32_t idx = (uint32_t)(block_incl_scan_add<NT, int32_t>(cnt, sh.scan, &tot) - cnt);
+        uint32_t prev = j0 > 0 ? A32[j0 - 1] : 0u;
+        for (uint32_t j = j0; j < j1; ++j) {
+          const uint32_t cur = A32[j];
+          const uint64_t w = ((uint64_t)cur << 32) | prev;
+          const uint64_t term = ~w & 0x8080808080808080ull;
+          uint32_t tc = (uint32_t)(term >> 32);
+          while (tc) {
+            const uint32_t b = 4u + (((uint32_t)__ffs(tc) - 1u) >> 3);
+            tc &= tc - 1u;
+            nums[idx++] = window_value(w, term, b);
+          }
+          prev = cur;
+        }
+      }
+      __syncthreads();
+    }
+    // 3. neighbour IDs, weights and labels of this thread's slice
+    const uint32_t Dd = (Et + NT - 1) / NT;
+    const uint32_t e0 = tid * Dd;
+    int32_t vi[ITEMS], nb[ITEMS], wt[ITEMS];
+    {
+      int32_t i = e0 < Et ? tile_find(sh.ebase, nv, e0) : 0;
+      bool any_head = false;
+      int32_t s = 0, s2 = 0;
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t e = e0 + k;
+        vi[k] = -1;
+        nb[k] = 0;
+        wt[k] = 1;
+        if ((uint32_t)k < Dd && e < Et) {
+          while (e >= sh.ebase[i + 1]) ++i;
+          vi[k] = i;
+          const uint32_t loc = e - sh.ebase[i];
+          if constexpr (COMP) {
+            const uint32_t ci = sh.rstart[i] + per * loc;
+            const uint32_t code = nums[ci];
+            const bool head = loc == 0;
+            const int32_t dv = head ? sh.u[i] + unzigzag32(code) : (int32_t)code;
+            const int32_t dw = weighted ? unzigzag32(nums[ci + 1]) : 0;
+            if (head) {
+              any_head = true;
+              s = dv;
+              s2 = dw;
+            } else {
+              s += dv;
+              s2 += dw;
+            }
+            nb[k] = s;
+            wt[k] = s2;
+          } else {
+            const uint64_t ge = sh.pos[i] + loc;
+            nb[k] = x.g.adjncy[ge];
+            if (weighted) wt[k] = x.g.adjwgt[ge];
+          }
+        }
+      }
+      if constexpr (COMP) {
+        int32_t ex, ex2;
+        tile_seg_scan<NT>(any_head, s, s2, sh.scan, sh.scan2, &sh.seg_flags, ex, ex2);
+        bool before = true;
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+          if (vi[k] < 0) continue;
+          if (e0 + k == sh.ebase[vi[k]]) before = false;
+          if (before) {
+            nb[k] += ex;
+            wt[k] += ex2;
+          }
+          if (!weighted) wt[k] = 1;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      if (vi[k] < 0) continue;
+      if ((uint32_t)nb[k] < (uint32_t)x.g.n) nb[k] = x.C[nb[k]];
+      else vi[k] = -1;  // unreachable for a valid handle; keeps the gather in bounds
+    }
+    __syncthreads();  // numbers consumed: region A becomes the table
+    for (uint32_t q = tid; q < St; q += NT) keys[q] = kEmpty;
+    for (uint32_t q = tid; q < St; q += NT) vals[q] = 0;
+    __syncthreads();
+    // 4. ratings
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      if (vi[k] < 0) continue;
+      const int32_t i = vi[k];
+      tile_insert<V>(keys, vals, sh.tbase[i], sh.tbase[i + 1] - sh.tbase[i], nb[k], (V)wt[k]);
+    }
+    __syncthreads();
+    // 5. selection: one walk over the slots of each vertex
+    for (int32_t i = sgi; i < nv; i += NSG) {
+      const uint32_t b0 = sh.tbase[i], b1 = sh.tbase[i + 1];
+      const int32_t oc = sh.own_c[i];
+      int64_t own = 0;
+      Cand best = cand_none();
+      for (uint32_t q = b0 + sl; q < b1; q += SG) {
+        const int32_t c = keys[q];
+        if (c == kEmpty) continue;
+        const int64_t r = (int64_t)vals[q];
+        if (c == oc) {
+          own = r;
+          continue;
+        }
+        if (r < best.r) continue;
+        const Cand cd{r, tiebreak_key(x.seed, x.round, (uint32_t)c), c};
+        if (cand_better(cd, best)) best = cd;
+      }
+      if constexpr (SG == kWave) {
+        best = wave_best(best);
+        own = wave_reduce_add(own);
+      } else {
+        best = block_best<NT>(best, sh.cb);
+        own = block_reduce_add<NT, int64_t>(own, sh.red);
+      }
+      if (sl == 0) {
+        sh.own_r[i] = own;
+        sh.best_c[i] = best.r > own ? best.c : -1;
+        sh.gain[i] = best.r - own;
+      }
+    }
+    __syncthreads();
+    if (tid < nv) {
+      const int32_t u = sh.u[tid];
+      const int32_t c = sh.best_c[tid];
+      if (c < 0) {
+        x.ptgt[u] = -1;
+      } else if (x.W[c] + sh.wu[tid] <= x.cap) {
+        x.ptgt[u] = c;
+        x.pgain[u] = sh.gain[tid];
+      } else {
+        sh.best_c[tid] = -2;  // walk again with the cap
+        atomicOr(&sh.any_redo, 1u);
+      }
+    }
+    __syncthreads();
+    if (sh.any_redo) {
+      for (int32_t i = sgi; i < nv; i += NSG) {
+        if (sh.best_c[i] != -2) continue;  // uniform across the selection group
+        const uint32_t b0 = sh.tbase[i], b1 = sh.tbase[i + 1];
+        const int32_t oc = sh.own_c[i];
+        const int64_t own = sh.own_r[i];
+        const int64_t wu = sh.wu[i];
+        Cand best = cand_none();
+        for (uint32_t q = b0 + sl; q < b1; q += SG) {
+          const int32_t c = keys[q];
+          if (c == kEmpty || c == oc) continue;
+          const int64_t r = (int64_t)vals[q];
+          if (r <= own || r < best.r) continue;
+          const Cand cd{r, tiebreak_key(x.seed, x.round, (uint32_t)c), c};
+          if (cand_better(cd, best) && x.W[c] + wu <= x.cap) best = cd;
+        }
+        if constexpr (SG == kWave) best = wave_best(best);
+        else best = block_best<NT>(best, sh.cb);
+        if (sl == 0) {
+          const int32_t u = sh.u[i];
+          if (best.c >= 0) {
+            x.ptgt[u] = best.c;
+            x.pgain[u] = best.r - own;
+          } else {
+            x.ptgt[u] = -1;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Greedy tiling of a tile bucket: each thread walks kTileSeg consecutive
+// vertices and starts a new tile whenever the next vertex would exceed the
+// tile's edge, vertex or staged-byte budget. COUNT: tiles per segment;
+// otherwise the first vertex of every tile (and the end sentinel).
+template <bool COUNT>
+__global__ void k_tile_plan(VDesc vd, int32_t cnt, uint32_t emax, uint32_t vmax, uint32_t bmax, bool comp,
+                            uint32_t* counts, const uint32_t* offs, int32_t* tiles) {
+  const int64_t sgi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t a = sgi * kTileSeg;
+  if (a >= cnt) return;
+  const int64_t b = a + kTileSeg < (int64_t)cnt ? a + kTileSeg : (int64_t)cnt;
+  uint32_t e = 0, nvv = 0, by = 0, nt = 0;
+  const uint32_t o = COUNT ? 0u : offs[sgi];
+  for (int64_t i = a; i < b; ++i) {
+    const int4 v4 = vd.d[i];
+    const uint32_t d = (uint32_t)v4.y;
+    const uint32_t sb = comp ? 4u * ((((uint32_t)v4.z & 3u) + vd.len[i] + 3u) / 4u) : 0u;
+    if (nvv == 0 || e + d > emax || nvv == vmax || by + sb > bmax) {
+      if (!COUNT) tiles[o + nt] = (int32_t)i;
+      ++nt;
+      e = 0;
+      nvv = 0;
+      by = 0;
+    }
+    e += d;
+    ++nvv;
+    by += sb;
+  }
+  if (COUNT) counts[sgi] = nt;
+  else if (b == cnt) tiles[o + nt] = (int32_t)cnt;
 }
 
 // --------------------------------------------------- hub path (phase two) --
@@ -552,16 +903,14 @@ __global__ __launch_bounds__(256) void k_hub_combine(RoundCtx x, HubMeta hm, int
 constexpr int kBkThreads = 256;
 constexpr int kBkItems = 8;
 constexpr int kBkTile = kBkThreads * kBkItems;
-constexpr int kNumBuckets = 5;  // lane, wave, block (small), block (large), hub
-constexpr int32_t kBlockSplit = 1024;
+constexpr int kNumBuckets = 4;  // lane, small tiles, large tiles, hub
 
-__device__ __forceinline__ int bucket_of(int32_t d, int32_t t_lane, int32_t t_wave, int32_t t_block) {
+__device__ __forceinline__ int bucket_of(int32_t d, int32_t t_lane, int32_t t_tile, int32_t t_block) {
   if (d <= 0) return -1;
   if (d <= t_lane) return 0;
-  if (d <= t_wave) return 1;
-  if (d <= t_block && d <= kBlockSplit) return 2;
-  if (d <= t_block) return 3;
-  return 4;
+  if (d <= t_tile) return 1;
+  if (d <= t_block) return 2;
+  return 3;
 }
 
 // Descriptor of every listed (non-hub) vertex: degree and the position of its
@@ -585,7 +934,7 @@ __global__ void k_build_desc(GraphView g, const int32_t* order, const int32_t* d
 }
 
 __global__ __launch_bounds__(kBkThreads) void k_bucket_count(const int32_t* deg, int32_t n, int32_t t_lane,
-                                                             int32_t t_wave, int32_t t_block, uint32_t* counts,
+                                                             int32_t t_tile, int32_t t_block, uint32_t* counts,
                                                              uint32_t nb) {
   __shared__ uint32_t c[kNumBuckets];
   if (threadIdx.x < kNumBuckets) c[threadIdx.x] = 0;
@@ -594,7 +943,7 @@ __global__ __launch_bounds__(kBkThreads) void k_bucket_count(const int32_t* deg,
   for (int i = 0; i < kBkItems; ++i) {
     const int64_t u = base + (int64_t)i * kBkThreads + threadIdx.x;
     if (u < n) {
-      const int b = bucket_of(deg[u], t_lane, t_wave, t_block);
+      const int b = bucket_of(deg[u], t_lane, t_tile, t_block);
       if (b >= 0) atomicAdd(&c[b], 1u);
     }
   }
@@ -604,7 +953,7 @@ __global__ __launch_bounds__(kBkThreads) void k_bucket_count(const int32_t* deg,
 
 // Stable: within a block, vertices keep increasing order per bucket.
 __global__ __launch_bounds__(kBkThreads) void k_bucket_scatter(const int32_t* deg, int32_t n, int32_t t_lane,
-                                                               int32_t t_wave, int32_t t_block,
+                                                               int32_t t_tile, int32_t t_block,
                                                                const uint32_t* offs, uint32_t nb, int32_t* order) {
   __shared__ uint32_t run[kNumBuckets];
   __shared__ uint32_t wc[kBkThreads / kWave][kNumBuckets];
@@ -614,7 +963,7 @@ __global__ __launch_bounds__(kBkThreads) void k_bucket_scatter(const int32_t* de
   const uint64_t lt = lanemask_lt();
   for (int i = 0; i < kBkItems; ++i) {
     const int64_t u = base + (int64_t)i * kBkThreads + threadIdx.x;
-    const int b = (u < n) ? bucket_of(deg[u], t_lane, t_wave, t_block) : -1;
+    const int b = (u < n) ? bucket_of(deg[u], t_lane, t_tile, t_block) : -1;
     uint64_t m[kNumBuckets];
 #pragma unroll
     for (int k = 0; k < kNumBuckets; ++k) m[k] = __ballot(b == k);
@@ -636,14 +985,14 @@ __global__ __launch_bounds__(kBkThreads) void k_bucket_scatter(const int32_t* de
 }
 
 // Per-bucket adjacency entries and compressed record bytes (statistics).
-__global__ __launch_bounds__(256) void k_bucket_sums(const int32_t* deg, int32_t n, int32_t t_lane, int32_t t_wave,
+__global__ __launch_bounds__(256) void k_bucket_sums(const int32_t* deg, int32_t n, int32_t t_lane, int32_t t_tile,
                                                      int32_t t_block, const uint64_t* offs,
                                                      unsigned long long* sums) {
   __shared__ unsigned long long sm[2 * kNumBuckets];
   if (threadIdx.x < 2 * kNumBuckets) sm[threadIdx.x] = 0;
   __syncthreads();
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
-    const int b = bucket_of(deg[u], t_lane, t_wave, t_block);
+    const int b = bucket_of(deg[u], t_lane, t_tile, t_block);
     if (b < 0) continue;
     atomicAdd(&sm[b], (unsigned long long)deg[u]);
     if (offs) atomicAdd(&sm[kNumBuckets + b], (unsigned long long)(offs[u + 1] - offs[u]));
@@ -768,42 +1117,54 @@ lp_status set_lds(F* kern, size_t bytes) {
 }
 
 // LDS layout of a rating group for degrees up to dmax.
-template <int NT, typename V>
-GroupLayout group_layout(uint32_t dmax, bool weighted) {
-  GroupLayout L;
-  L.dmax = dmax;
-  L.tmax = 1u << ceil_log2(2 * std::max<uint32_t>(dmax, 32));
-  const uint64_t table = (uint64_t)L.tmax * (4 + sizeof(V));
-  const uint64_t stage = (uint64_t)dmax * (weighted ? 10 : 5) + 16 + 4ull * NT + 32;
-  L.abytes = (uint32_t)((std::max(table, stage) + 15) & ~15ull);
-  L.per = (uint32_t)((L.abytes + (uint64_t)dmax * 4 * (weighted ? 2 : 1) + sizeof(GroupSmem<NT>) + 15) & ~15ull);
-  return L;
-}
-
-// Launch of one group-rating kernel, templated on group size, rating width
-// and representation.
-template <int NT, typename V, bool COMP>
-lp_status launch_group(const RoundCtx& x, VDesc vd, int32_t cnt, uint32_t dmax, bool weighted, hipStream_t s) {
-  if (cnt <= 0) return LP_OK;
-  constexpr int G = (NT == kWave) ? 4 : 1;
-  const GroupLayout L = group_layout<NT, V>(dmax, weighted);
-  const size_t bytes = (size_t)L.per * G;
-  // per-thread slice of the record decoder: dmax / NT neighbours
-  auto kern = (dmax <= (uint32_t)NT * 4) ? k_rate_group<NT, V, COMP, 4>
-              : (dmax <= (uint32_t)NT * 8) ? k_rate_group<NT, V, COMP, 8>
-                                           : k_rate_group<NT, V, COMP, 16>;
+template <class T, typename V, bool COMP>
+lp_status launch_tile(const RoundCtx& x, VDesc vd, const int32_t* tiles, const uint32_t* ntiles, unsigned grid,
+                      bool weighted, hipStream_t s) {
+  const TileLayout L = tile_layout<T, V>(COMP, weighted);
+  const size_t bytes = (size_t)L.abytes + sizeof(TileShared<T::kThreads, T::kVerts>);
+  auto kern = k_rate_tile<T, V, COMP>;
   LP_CHECK(set_lds(kern, bytes));
-  const int threads = (NT == kWave) ? 256 : NT;
-  const unsigned grid = grid_for(cnt, G, 1u << 20);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), bytes, s, x, vd, cnt, L);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(T::kThreads), bytes, s, x, vd, tiles, ntiles, L);
   return last_error();
 }
 
-template <int NT, bool COMP>
-lp_status launch_group_w(bool wide, const RoundCtx& x, VDesc vd, int32_t cnt, uint32_t dmax, bool weighted,
-                         hipStream_t s) {
-  return wide ? launch_group<NT, int64_t, COMP>(x, vd, cnt, dmax, weighted, s)
-              : launch_group<NT, int32_t, COMP>(x, vd, cnt, dmax, weighted, s);
+template <class T>
+lp_status launch_tile_any(bool comp, bool wide, const RoundCtx& x, VDesc vd, const int32_t* tiles,
+                          const uint32_t* ntiles, unsigned grid, bool weighted, hipStream_t s) {
+  if (comp) {
+    return wide ? launch_tile<T, int64_t, true>(x, vd, tiles, ntiles, grid, weighted, s)
+                : launch_tile<T, int32_t, true>(x, vd, tiles, ntiles, grid, weighted, s);
+  }
+  return wide ? launch_tile<T, int64_t, false>(x, vd, tiles, ntiles, grid, weighted, s)
+              : launch_tile<T, int32_t, false>(x, vd, tiles, ntiles, grid, weighted, s);
+}
+
+// Tiles of one tile bucket, planned on the device (the count stays there).
+struct TilePlan {
+  int32_t* tiles = nullptr;
+  uint32_t* ntiles = nullptr;
+  unsigned grid = 0;
+};
+
+template <class T>
+lp_status plan_tiles(VDesc vd, int32_t cnt, bool comp, bool wide, bool weighted, Scratch& sc, TilePlan& tp) {
+  if (cnt <= 0) return LP_OK;
+  const TileLayout L = wide ? tile_layout<T, int64_t>(comp, weighted) : tile_layout<T, int32_t>(comp, weighted);
+  const int64_t nseg = ((int64_t)cnt + kTileSeg - 1) / kTileSeg;
+  uint32_t* tcnt = sc.alloc<uint32_t>(nseg);
+  tp.ntiles = sc.alloc<uint32_t>(1);
+  tp.tiles = sc.alloc<int32_t>((size_t)cnt + 1);
+  if (sc.failed) return LP_ENOMEM;
+  hipStream_t s = sc.stream();
+  hipLaunchKernelGGL(k_tile_plan<true>, dim3(grid_for(nseg, 256)), dim3(256), 0, s, vd, cnt, (uint32_t)T::kEdges,
+                     (uint32_t)T::kVerts, L.stage_bytes, comp, tcnt, (const uint32_t*)nullptr, (int32_t*)nullptr);
+  LP_CHECK_LAUNCH();
+  LP_CHECK(scan_exclusive_u32(tcnt, tcnt, nseg, tp.ntiles, sc));
+  hipLaunchKernelGGL(k_tile_plan<false>, dim3(grid_for(nseg, 256)), dim3(256), 0, s, vd, cnt, (uint32_t)T::kEdges,
+                     (uint32_t)T::kVerts, L.stage_bytes, comp, (uint32_t*)nullptr, (const uint32_t*)tcnt, tp.tiles);
+  LP_CHECK_LAUNCH();
+  tp.grid = (unsigned)std::min<int64_t>(2048, ((int64_t)cnt + 7) / 8 * 8);
+  return LP_OK;
 }
 
 }  // namespace
@@ -822,16 +1183,15 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
   if (n == 0) return LP_OK;
   // knobs (results do not depend on them)
   const bool wide = g->max_wdeg > 0x7FFFFFFFll;
-  int32_t t_lane = 16, t_wave = 256, t_block = kMaxBlock, hub_part = 4096;
+  int32_t t_lane = 16, t_tile = TileSmall::kEdges, t_block = TileLarge::kEdges, hub_part = 4096;
   if (cfg_in) {
     if (cfg_in->t_lane) t_lane = cfg_in->t_lane;
-    if (cfg_in->t_wave) t_wave = cfg_in->t_wave;
+    if (cfg_in->t_tile) t_tile = cfg_in->t_tile;
     if (cfg_in->t_block) t_block = cfg_in->t_block;
     if (cfg_in->hub_part) hub_part = cfg_in->hub_part;
   }
-  const int32_t block_max = kMaxBlock;
-  if (t_lane < 0 || t_lane > kMaxLane || t_wave < t_lane || t_wave > kMaxWave || t_block < t_wave ||
-      t_block > block_max || hub_part < 256 || hub_part > 8192)
+  if (t_lane < 0 || t_lane > kMaxLane || t_tile < t_lane || t_tile > TileSmall::kEdges || t_block < t_tile ||
+      t_block > TileLarge::kEdges || hub_part < 256 || hub_part > 8192)
     return LP_EINVAL;
   // proposal sort key: target bits + gain bits
   const int G = std::max(1, bitlen((uint64_t)g->max_wdeg));
@@ -903,16 +1263,16 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
   LP_CHECK(begin(LP_PHASE_SETUP));
   LP_CHECK(compute_degrees(g, deg, s));
   // degree buckets: one stable list ordered by (bucket, vertex)
-  hipLaunchKernelGGL(k_bucket_count, dim3(nbk), dim3(kBkThreads), 0, s, deg, n, t_lane, t_wave, t_block, bcnt, nbk);
+  hipLaunchKernelGGL(k_bucket_count, dim3(nbk), dim3(kBkThreads), 0, s, deg, n, t_lane, t_tile, t_block, bcnt, nbk);
   LP_CHECK_LAUNCH();
   uint32_t* btot = sc.alloc<uint32_t>(1);
   if (!btot) return LP_ENOMEM;
   LP_CHECK(scan_exclusive_u32(bcnt, bcnt, (int64_t)kNumBuckets * nbk, btot, sc));
-  hipLaunchKernelGGL(k_bucket_scatter, dim3(nbk), dim3(kBkThreads), 0, s, deg, n, t_lane, t_wave, t_block, bcnt, nbk,
+  hipLaunchKernelGGL(k_bucket_scatter, dim3(nbk), dim3(kBkThreads), 0, s, deg, n, t_lane, t_tile, t_block, bcnt, nbk,
                      order);
   LP_CHECK_LAUNCH();
   if (stats_out) {
-    hipLaunchKernelGGL(k_bucket_sums, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, deg, n, t_lane, t_wave, t_block,
+    hipLaunchKernelGGL(k_bucket_sums, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, deg, n, t_lane, t_tile, t_block,
                        g->compressed ? g->offs : nullptr, ctl->bsums);
     LP_CHECK_LAUNCH();
   }
@@ -926,7 +1286,7 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
   for (int b = 0; b < kNumBuckets; ++b) bn[b] = (int32_t)(bstart[b + 1] - bstart[b]);
 
   // descriptors of the non-hub buckets
-  const int32_t nlisted = (int32_t)bstart[4];
+  const int32_t nlisted = (int32_t)bstart[3];
   int4* vdesc = sc.alloc<int4>(nlisted);
   uint32_t* vlen = sc.alloc<uint32_t>(nlisted);
   if (sc.failed) return LP_ENOMEM;
@@ -937,17 +1297,22 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
   }
   auto vd_of = [&](int b) { return VDesc{vdesc + bstart[b], vlen + bstart[b]}; };
 
+  // tiles of the two tile buckets
+  TilePlan tps, tpl;
+  LP_CHECK(plan_tiles<TileSmall>(vd_of(1), bn[1], g->compressed, wide, g->weighted, sc, tps));
+  LP_CHECK(plan_tiles<TileLarge>(vd_of(2), bn[2], g->compressed, wide, g->weighted, sc, tpl));
+
   // hub metadata (host-built, small)
-  const int32_t H = bn[4];
+  const int32_t H = bn[3];
   HubMeta hm{};
   int32_t npieces = 0, ntasks = 0;
   if (H > 0) {
     std::vector<int32_t> hu(H), hd(H);
     int32_t* hdeg_dev = sc.alloc<int32_t>(H);
     if (!hdeg_dev) return LP_ENOMEM;
-    hipLaunchKernelGGL(k_gather_i32, dim3(grid_for(H, 256, 4096)), dim3(256), 0, s, deg, order + bstart[4], H, hdeg_dev);
+    hipLaunchKernelGGL(k_gather_i32, dim3(grid_for(H, 256, 4096)), dim3(256), 0, s, deg, order + bstart[3], H, hdeg_dev);
     LP_CHECK_LAUNCH();
-    LP_CHECK_HIP(hipMemcpyAsync(hu.data(), order + bstart[4], H * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LP_CHECK_HIP(hipMemcpyAsync(hu.data(), order + bstart[3], H * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     LP_CHECK_HIP(hipMemcpyAsync(hd.data(), hdeg_dev, H * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     LP_CHECK_HIP(hipStreamSynchronize(s));
     int64_t maxd = 0;
@@ -1046,21 +1411,15 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
       LP_CHECK(end());
     }
     if (bn[1] > 0) {
-      LP_CHECK(begin(LP_PHASE_WAVE));
-      if (g->compressed) LP_CHECK((launch_group_w<kWave, true>(wide, x, vd_of(1), bn[1], t_wave, g->weighted, s)));
-      else LP_CHECK((launch_group_w<kWave, false>(wide, x, vd_of(1), bn[1], t_wave, g->weighted, s)));
+      LP_CHECK(begin(LP_PHASE_TILE));
+      LP_CHECK(launch_tile_any<TileSmall>(g->compressed, wide, x, vd_of(1), tps.tiles, tps.ntiles, tps.grid,
+                                          g->weighted, s));
       LP_CHECK(end());
     }
-    if (bn[2] + bn[3] > 0) {
+    if (bn[2] > 0) {
       LP_CHECK(begin(LP_PHASE_BLOCK));
-      const uint32_t split = (uint32_t)std::min(t_block, kBlockSplit);
-      if (g->compressed) {
-        LP_CHECK((launch_group_w<kGroupThreads, true>(wide, x, vd_of(2), bn[2], split, g->weighted, s)));
-        LP_CHECK((launch_group_w<kGroupThreads, true>(wide, x, vd_of(3), bn[3], t_block, g->weighted, s)));
-      } else {
-        LP_CHECK((launch_group_w<kGroupThreads, false>(wide, x, vd_of(2), bn[2], split, g->weighted, s)));
-        LP_CHECK((launch_group_w<kGroupThreads, false>(wide, x, vd_of(3), bn[3], t_block, g->weighted, s)));
-      }
+      LP_CHECK(launch_tile_any<TileLarge>(g->compressed, wide, x, vd_of(2), tpl.tiles, tpl.ntiles, tpl.grid,
+                                          g->weighted, s));
       LP_CHECK(end());
     }
     if (H > 0) {
@@ -1106,17 +1465,16 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
     LP_CHECK_HIP(hipStreamSynchronize(s));
     stats_out->rounds_run = h.rounds_run;
     stats_out->n_lane = bn[0];
-    stats_out->n_wave = bn[1];
-    stats_out->n_block = bn[2] + bn[3];
-    stats_out->n_hub = bn[4];
+    stats_out->n_tile = bn[1];
+    stats_out->n_block = bn[2];
+    stats_out->n_hub = bn[3];
     for (int i = 0; i < 64; ++i) {
       stats_out->proposals[i] = h.stats[i];
       stats_out->moves[i] = h.stats[64 + i];
     }
     for (int b = 0; b < kNumBuckets; ++b) {
-      const int o = b < 3 ? b : b - 1;  // both block buckets report as "block"
-      stats_out->bucket_edges[o] += h.bsums[b];
-      stats_out->bucket_bytes[o] += h.bsums[kNumBuckets + b];
+      stats_out->bucket_edges[b] = h.bsums[b];
+      stats_out->bucket_bytes[b] = h.bsums[kNumBuckets + b];
     }
     for (auto& m : marks) {
       float ms = 0;

@@ -156,70 +156,6 @@ __device__ bool group_decode(const uint8_t* __restrict__ bytes, uint64_t& pos, i
   return true;
 }
 
-// Decodes the complete code stream of one unchunked neighbourhood staged in
-// LDS (codes of d neighbours at lds[pos, pos + len)) by NT cooperating
-// threads in two group-wide scans: thread t takes a contiguous byte range,
-// counts the terminator bytes in it, and after a prefix count writes each
-// number it terminates (whose bytes may start in the previous range) to
-// tmp[]; then every thread takes a contiguous slice of at most MAXD
-// neighbours and a prefix sum turns gaps (and weight differences) into
-// neighbour IDs (and weights). tmp must hold d (unweighted) or 2d
-// (weighted) numbers and may alias ids / ids..wts.
-template <int NT, int MAXD>
-__device__ void group_decode_record(const uint8_t* lds, uint32_t pos, uint32_t len, int32_t u, uint32_t d,
-                                    bool weighted, uint32_t* tmp, int32_t* ids, int32_t* wts, int32_t* scan_sm) {
-  const int tid = group_tid<NT>();
-  const uint32_t B = (len + NT - 1) / NT;
-  const uint32_t b0 = pos + min(len, (uint32_t)tid * B), b1 = pos + min(len, (uint32_t)(tid + 1) * B);
-  int32_t cnt = 0;
-  for (uint32_t q = b0; q < b1; ++q) cnt += !(lds[q] & 0x80);
-  int32_t tot;
-  uint32_t idx = (uint32_t)(block_incl_scan_add<NT, int32_t>(cnt, scan_sm, &tot) - cnt);
-  for (uint32_t q = b0; q < b1; ++q) {
-    if (lds[q] & 0x80) continue;
-    uint32_t st = q;
-    while (st > pos && st + 4 > q && (lds[st - 1] & 0x80)) --st;
-    uint32_t v = 0;
-    for (uint32_t k = st; k <= q; ++k) v |= (uint32_t)(lds[k] & 0x7F) << (7 * (k - st));
-    tmp[idx++] = v;
-  }
-  group_sync<NT>();
-  const uint32_t D = (d + NT - 1) / NT;
-  const uint32_t i0 = (uint32_t)tid * D;
-  int32_t dv[MAXD], dw[MAXD];
-  int32_t sv = 0, sw = 0;
-#pragma unroll
-  for (int k = 0; k < MAXD; ++k) {
-    const uint32_t i = i0 + k;
-    dv[k] = 0;
-    dw[k] = 0;
-    if ((uint32_t)k < D && i < d) {
-      const uint32_t cv = weighted ? tmp[2 * i] : tmp[i];
-      dv[k] = (i == 0) ? u + unzigzag32(cv) : (int32_t)cv;
-      if (weighted) dw[k] = unzigzag32(tmp[2 * i + 1]);
-    }
-    sv += dv[k];
-    sw += dw[k];
-  }
-  int32_t tv, tw;
-  int32_t ev = block_incl_scan_add<NT, int32_t>(sv, scan_sm, &tv) - sv;
-  int32_t ew = 0;
-  if (weighted) ew = block_incl_scan_add<NT, int32_t>(sw, scan_sm, &tw) - sw;
-  group_sync<NT>();
-#pragma unroll
-  for (int k = 0; k < MAXD; ++k) {
-    const uint32_t i = i0 + k;
-    if ((uint32_t)k < D && i < d) {
-      ev += dv[k];
-      ids[i] = ev;
-      if (weighted) {
-        ew += dw[k];
-        wts[i] = ew;
-      }
-    }
-  }
-}
-
 // Serial decode of a short (unchunked) neighbourhood by one lane; calls
 // f(i, v, w) for i = 0..deg-1 in order.
 template <typename F>

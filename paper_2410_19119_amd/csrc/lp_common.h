@@ -7,14 +7,10 @@
 
 namespace lp {
 
-// Degree buckets used by the rating kernels (result-invariant knobs).
-constexpr int kMaxLane = 16;     // lane-per-vertex register capacity
-constexpr int kMaxWave = 512;    // wave-per-vertex LDS table is 2 * kMaxWave entries
-constexpr int kMaxBlock = 4096;  // block-per-vertex LDS table is 2 * kMaxBlock entries
+// Lane-per-vertex rating keeps up to this many neighbours in registers.
+constexpr int kMaxLane = 16;
 
-// Threads per workgroup of the block-per-vertex and hub kernels.
-constexpr int kBlockThreads = 512;
-constexpr int kGroupThreads = 256;  // workgroup-per-vertex rating
+// Threads per workgroup of the hub kernels.
 constexpr int kHubThreads = 256;
 
 // Empty slot marker of LDS / global rating tables (labels are >= 0).

@@ -32,7 +32,22 @@ def _graphs(synth_mod):
     out["rmat-s12-weighted"] = g
     out["star-25000"] = _star(synth_mod, 25000, center=7)
     out["star-10001-w"] = _star(synth_mod, 10001, center=5000, weights=True)
+    out["bip-5x2048"] = _bipartite(synth_mod, 5, 2048)
+    out["bip-5x2048-heavy"] = _bipartite(synth_mod, 5, 2048, heavy=True)
     return out
+
+
+def _bipartite(synth_mod, a, b, heavy=False):
+    # complete bipartite K_{a,b} plus a path over the b side: the a side has
+    # degree b exactly (the largest degree rated in tiles); with heavy random
+    # weights each of its records takes about 6 bytes per neighbour, so tiles
+    # are cut by their byte budget
+    edges = [(i, a + j) for i in range(a) for j in range(b)]
+    edges += [(a + j, a + j + 1) for j in range(b - 1)]
+    w = None
+    if heavy:
+        w = [2**29 + (k * 2654435761) % (2**31 - 2**29 - 1) for k in range(len(edges))]
+    return synth_mod.from_edges(a + b, edges, w)
 
 
 @pytest.fixture(scope="module")
@@ -91,6 +106,8 @@ CASES = [
     ("rmat-s12-weighted", 60, 5, 3),
     ("star-25000", 300, 3, 2),
     ("star-10001-w", 5000, 3, 2),
+    ("bip-5x2048", 700, 4, 3),
+    ("bip-5x2048-heavy", 900, 4, 4),
 ]
 
 
@@ -107,19 +124,21 @@ def test_cluster_matches_oracle(lp, oracle_mod, graphs, name, cap, rounds, seed,
 
 
 KNOBS = [
-    dict(t_lane=1, t_wave=1, t_block=1, hub_part=256),        # almost everything on the hub path
-    dict(t_lane=16, t_wave=16, t_block=16, hub_part=512),
-    dict(t_lane=4, t_wave=64, t_block=64, hub_part=1024),
-    dict(t_lane=16, t_wave=512, t_block=4096, hub_part=8192),
-    dict(t_lane=8, t_wave=100, t_block=1000, hub_part=300),
+    dict(t_lane=1, t_tile=1, t_block=1, hub_part=256),        # almost everything on the hub path
+    dict(t_lane=16, t_tile=16, t_block=16, hub_part=512),
+    dict(t_lane=4, t_tile=64, t_block=64, hub_part=1024),
+    dict(t_lane=16, t_tile=512, t_block=4096, hub_part=8192),
+    dict(t_lane=8, t_tile=100, t_block=1000, hub_part=300),
+    dict(t_lane=1, t_tile=2048, t_block=2048, hub_part=4096),   # tiles of up to 128 vertices
 ]
 
 
 @pytest.mark.parametrize("knobs", KNOBS)
-@pytest.mark.parametrize("name", ["rmat-s13-ef16", "rmat-s12-weighted", "star-25000"])
-def test_bucket_thresholds_do_not_change_results(lp, oracle_mod, graphs, knobs, name):
+@pytest.mark.parametrize("name", ["rmat-s13-ef16", "rmat-s12-weighted", "star-25000", "bip-5x2048-heavy"])
+@pytest.mark.parametrize("compressed", [True, False])
+def test_bucket_thresholds_do_not_change_results(lp, oracle_mod, graphs, knobs, name, compressed):
     g = graphs[name]
-    G = _gpu_graph(lp, g)
+    G = _gpu_graph(lp, g, compressed)
     exp, _ = oracle_mod.lp_cluster(g, 64, 4, 11)
     lab = lp.lp_cluster(G, 64, 4, 11, config=knobs)
     assert np.array_equal(_np(lab), exp)
@@ -161,6 +180,10 @@ def test_cluster_argument_errors(lp, graphs):
         lp.lp_cluster(G, 5, 1, 1, config=dict(t_lane=17))
     with pytest.raises(lp.LPError):
         lp.lp_cluster(G, 5, 1, 1, config=dict(t_block=8192))
+    with pytest.raises(lp.LPError):
+        lp.lp_cluster(G, 5, 1, 1, config=dict(t_tile=4096, t_block=4096))
+    with pytest.raises(lp.LPError):
+        lp.lp_cluster(G, 5, 1, 1, config=dict(t_tile=64, t_block=32))
 
 
 def test_repeatable(lp, graphs):
