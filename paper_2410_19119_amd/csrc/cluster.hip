@@ -626,121 +626,341 @@ __global__ void k_tile_plan(VDesc vd, int32_t cnt, uint32_t emax, uint32_t vmax,
 }
 
 // --------------------------------------------------- hub path (phase two) --
-// A hub's neighbours are cut into segments of LP_CHUNK_LEN (the format's
-// chunks, or consecutive runs of an unsplit neighbourhood). Step H1 decodes
-// every segment, looks up the neighbours' clusters and writes the
-// (cluster, weight) records of the segment grouped by a hash partition of the
-// cluster ID. Step H2 aggregates each (hub, partition) in an LDS table and
-// reports the partition's best feasible cluster and the hub's own rating if
-// its cluster hashes there. Step H3 combines the partitions of a hub.
+// A hub's neighbours are cut into pieces of kHubPiece (four of the format's
+// chunks, or, for an unchunked record, runs whose decoder state at the cut
+// is recorded once per call). Step H1 rates every piece like a tile: staged
+// bytes, register-window VarInt extraction, segmented decode, all label
+// gathers at once, summing in an LDS table; the piece then writes its
+// distinct (cluster, partial rating) pairs grouped by a hash partition of
+// the cluster ID. Step H2 sums each (hub, partition) over the hub's pieces in
+// an LDS table and reports the partition's best feasible cluster and the
+// hub's own rating if its cluster hashes there. Step H3 combines the
+// partitions of a hub.
+constexpr int kHubPiece = 4 * LP_CHUNK_LEN;
+constexpr int kHubStreams = 4;  // code streams per piece
+constexpr int kPieceThreads = 512;
+constexpr int kPieceItems = (kHubPiece + kPieceThreads - 1) / kPieceThreads;
+constexpr int kPieceSlots = kHubPiece + kHubPiece / 2 + 16;
+constexpr int kMaxParts = 1024;
+constexpr uint32_t kStreamZig = 0x80000000u;  // first code is zigzag(v - base_v)
+
+// One code stream of a piece: a chunk of a split record, or a run of an
+// unsplit one starting at a recorded decoder state.
+struct HubStream {
+  uint64_t pos;    // compressed: byte of the first code; plain: first edge
+  uint32_t len;    // compressed: code bytes
+  uint32_t cnt;    // neighbours | kStreamZig
+  int32_t base_v;  // the first neighbour is base_v + (zigzag or gap) code
+  int32_t base_w;  // the first weight is base_w + unzigzag(code)
+};
+
 struct HubMeta {
-  const int32_t* u;         // hub vertex
+  const int32_t* u;          // hub vertex
   const int32_t* deg;
-  const int32_t* nparts;    // P_h
-  const int32_t* nseg;      // segments
-  const uint64_t* rec_base; // first record of the hub
-  const uint64_t* poff_base;
-  const int32_t* task_base; // first (hub, partition) task
-  const int2* pieces;       // (hub, first segment)
-  const int2* tasks;        // (hub, partition)
-  int32_t* rec_c;           // records: cluster
-  int32_t* rec_w;           // records: weight (weighted graphs only)
-  uint32_t* poff;           // per segment: P_h + 1 partition offsets
-  int64_t* res_r;           // per task
+  const int32_t* nparts;     // P_h
+  const int32_t* npieces;    // pieces of the hub
+  const int32_t* piece_base; // first piece of the hub (global index)
+  const uint64_t* rec_base;  // first record of the hub (piece j at + j * kHubPiece)
+  const uint64_t* poff_base; // piece j's P_h + 1 partition offsets at + j * (P_h + 1)
+  const int32_t* task_base;  // first (hub, partition) task
+  const int2* pieces;        // (hub, piece within the hub)
+  const int2* tasks;         // (hub, partition)
+  HubStream* streams;        // kHubStreams per piece
+  int32_t* rec_c;            // records: cluster
+  void* rec_r;               // records: partial rating (int32 or int64)
+  uint32_t* poff;
+  int64_t* res_r;            // per task
   uint64_t* res_key;
   int32_t* res_c;
   int64_t* res_own;
 };
 
-constexpr int kMaxParts = 1024;
-
-struct HubPieceSmem {
-  DecodeSmem<kWave> dec;
-  int32_t c[LP_CHUNK_LEN];
-  int32_t w[LP_CHUNK_LEN];
-  uint16_t p[LP_CHUNK_LEN];
-  uint32_t hist[kMaxParts];
-};
-
-__global__ __launch_bounds__(256) void k_hub_scatter(RoundCtx x, HubMeta hm, int32_t npieces) {
-  extern __shared__ __align__(16) uint8_t smem_raw[];
-  HubPieceSmem& sm = ((HubPieceSmem*)smem_raw)[threadIdx.x / kWave];
-  if (*x.done) return;
+// Stream descriptors of every hub piece, once per call: one wavefront per
+// hub. Split records take their chunk table; unsplit records are decoded
+// once to record the decoder state at every piece boundary.
+__global__ __launch_bounds__(256) void k_hub_streams(GraphView g, HubMeta hm, int32_t nhubs) {
+  __shared__ DecodeSmem<kWave> dsm[4];
   const int lane = lane_id();
+  const int w = threadIdx.x / kWave;
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  for (int64_t pc = wid; pc < npieces; pc += nw) {
-    const int2 piece = hm.pieces[pc];
-    const int h = piece.x;
+  for (int64_t h = wid; h < nhubs; h += nw) {
     const int32_t u = hm.u[h];
     const uint32_t d = (uint32_t)hm.deg[h];
-    const uint32_t P = (uint32_t)hm.nparts[h];
-    const uint64_t rb = hm.rec_base[h];
-    const uint64_t pb = hm.poff_base[h];
-    bool chunked = true;
-    uint32_t nseg_here = 1;
-    uint64_t pos = 0;
-    uint64_t ebase = 0;  // plain CSR: first edge of u
-    if (x.g.offs) {
-      const Nbh hb = nbh_locate(x.g, u, d);
-      chunked = hb.nchunks > 1;
-      nseg_here = chunked ? 1u : (uint32_t)hm.nseg[h];
-      pos = chunked ? nbh_chunk_pos(x.g, hb, (uint32_t)piece.y) : hb.codes;
-    } else {
-      ebase = x.g.xadj[u];
-    }
-    int32_t pv = 0, pw = 0;
-    for (uint32_t s = 0; s < nseg_here; ++s) {
-      const uint32_t k = (uint32_t)piece.y + s;
-      const uint32_t first = k * LP_CHUNK_LEN;
-      const uint32_t cnt = min((uint32_t)LP_CHUNK_LEN, d - first);
-      if (x.g.offs) {
-        (void)group_decode<kWave>(x.g.bytes, pos, u, cnt, x.g.weighted, chunked || s == 0, pv, pw, sm.dec,
-                                  [&](uint32_t i, int32_t v, int32_t w) {
-                                    sm.c[i] = x.C[v];
-                                    sm.w[i] = w;
-                                  });
+    const uint32_t npc = (uint32_t)hm.npieces[h];
+    HubStream* st = hm.streams + (uint64_t)hm.piece_base[h] * kHubStreams;
+    const HubStream none{0, 0, 0, 0, 0};
+    if (g.offs) {
+      const Nbh hb = nbh_locate(g, u, d);
+      if (hb.nchunks > 1) {
+        // chunk k is stream k % 4 of piece k / 4; unused slots of the last piece are empty
+        for (uint32_t k = lane; k < npc * kHubStreams; k += kWave) {
+          if (k < hb.nchunks) {
+            const uint64_t p0 = nbh_chunk_pos(g, hb, k);
+            const uint64_t p1 = k + 1 < hb.nchunks ? nbh_chunk_pos(g, hb, k + 1) : g.offs[u + 1];
+            const uint32_t cnt = min((uint32_t)LP_CHUNK_LEN, d - k * LP_CHUNK_LEN);
+            st[k] = HubStream{p0, (uint32_t)(p1 - p0), cnt | kStreamZig, u, 0};
+          } else {
+            st[k] = none;
+          }
+        }
       } else {
-        for (uint32_t i = lane; i < cnt; i += kWave) {
-          const uint64_t e = ebase + first + i;
-          sm.c[i] = x.C[x.g.adjncy[e]];
-          sm.w[i] = x.g.adjwgt ? x.g.adjwgt[e] : 1;
+        uint64_t pos = hb.codes;
+        int32_t pv = 0, pw = 0;
+        for (uint32_t j = 0; j < npc; ++j) {
+          const uint32_t cnt = min((uint32_t)kHubPiece, d - j * kHubPiece);
+          const uint64_t p0 = pos;
+          const int32_t bv = j == 0 ? u : pv, bw = j == 0 ? 0 : pw;
+          (void)group_decode<kWave>(g.bytes, pos, u, cnt, g.weighted, j == 0, pv, pw, dsm[w],
+                                    [](uint32_t, int32_t, int32_t) {});
+          if (lane < kHubStreams)
+            st[(uint64_t)j * kHubStreams + lane] =
+                lane == 0 ? HubStream{p0, (uint32_t)(pos - p0), cnt | (j == 0 ? kStreamZig : 0u), bv, bw} : none;
         }
       }
-      for (uint32_t j = lane; j < P; j += kWave) sm.hist[j] = 0;
-      wave_sync_lds();
-      for (uint32_t i = lane; i < cnt; i += kWave) {
-        const uint32_t p = part_hash((uint32_t)sm.c[i]) % P;
-        sm.p[i] = (uint16_t)p;
-        atomicAdd(&sm.hist[p], 1u);
+    } else {
+      const uint64_t e0 = g.xadj[u];
+      for (uint32_t k = lane; k < npc * kHubStreams; k += kWave) {
+        const uint32_t j = k / kHubStreams;
+        const uint32_t cnt = min((uint32_t)kHubPiece, d - j * kHubPiece);
+        st[k] = (k % kHubStreams == 0) ? HubStream{e0 + (uint64_t)j * kHubPiece, 0, cnt, 0, 0} : none;
       }
-      wave_sync_lds();
-      uint32_t* po = hm.poff + pb + (uint64_t)k * (P + 1);
-      uint32_t carry = 0;
-      for (uint32_t b0 = 0; b0 < P; b0 += kWave) {
-        const uint32_t j = b0 + lane;
-        const uint32_t v = j < P ? sm.hist[j] : 0;
-        const uint32_t inc = wave_incl_scan_add(v);
-        if (j < P) {
-          sm.hist[j] = carry + inc - v;
-          po[j] = carry + inc - v;
-        }
-        carry += __shfl(inc, kWave - 1, kWave);
-      }
-      if (lane == 0) po[P] = cnt;
-      wave_sync_lds();
-      const uint64_t out = rb + first;
-      for (uint32_t i = lane; i < cnt; i += kWave) {
-        const uint32_t slot = atomicAdd(&sm.hist[sm.p[i]], 1u);
-        hm.rec_c[out + slot] = sm.c[i];
-        if (hm.rec_w) hm.rec_w[out + slot] = sm.w[i];
-      }
-      wave_sync_lds();
     }
   }
 }
 
-constexpr uint32_t kHubTable = 8192;  // LDS entries of a (hub, partition) task
+struct PieceShared {
+  uint64_t pos[kHubStreams];
+  uint32_t len[kHubStreams];
+  int32_t base_v[kHubStreams];
+  int32_t base_w[kHubStreams];
+  uint32_t zig[kHubStreams];
+  uint32_t ebase[kHubStreams + 1];
+  uint32_t dwbase[kHubStreams + 1];
+  uint32_t rstart[kHubStreams + 1];
+  uint32_t hist[kMaxParts];
+  int32_t scan[kPieceThreads / kWave];
+  int32_t scan2[kPieceThreads / kWave];
+  uint32_t seg_flags;
+};
+
+// H1: one workgroup per hub piece.
+template <typename V, bool COMP>
+__global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta hm, int32_t npieces,
+                                                            TileLayout L) {
+  constexpr int NT = kPieceThreads, ITEMS = kPieceItems, NS = kHubStreams;
+  extern __shared__ __align__(16) uint8_t smem_raw[];
+  if (*x.done) return;
+  const int tid = threadIdx.x;
+  const bool weighted = x.g.weighted;
+  const uint32_t per = weighted ? 2u : 1u;
+  uint8_t* A = smem_raw;
+  uint32_t* A32 = (uint32_t*)A;
+  int32_t* keys = (int32_t*)A;
+  V* vals = (V*)(A + (size_t)kPieceSlots * 4);
+  uint32_t* nums = (uint32_t*)(A + L.nums_off);
+  PieceShared& sh = *(PieceShared*)(A + L.abytes);
+  V* rec_r = (V*)hm.rec_r;
+  for (int64_t pc = blockIdx.x; pc < npieces; pc += gridDim.x) {
+    const int2 pj = hm.pieces[pc];
+    const int h = pj.x;
+    const uint32_t P = (uint32_t)hm.nparts[h];
+    const uint64_t rbase = hm.rec_base[h] + (uint64_t)pj.y * kHubPiece;
+    uint32_t* po = hm.poff + hm.poff_base[h] + (uint64_t)pj.y * (P + 1);
+    // 0. streams
+    if (tid == 0) {
+      uint32_t e = 0, dw = 0, nn = 0;
+      for (int s = 0; s < NS; ++s) {
+        const HubStream hs = hm.streams[pc * NS + s];
+        const uint32_t cnt = hs.cnt & ~kStreamZig;
+        sh.pos[s] = hs.pos;
+        sh.len[s] = hs.len;
+        sh.base_v[s] = hs.base_v;
+        sh.base_w[s] = hs.base_w;
+        sh.zig[s] = (hs.cnt & kStreamZig) ? 1u : 0u;
+        sh.ebase[s] = e;
+        sh.dwbase[s] = dw;
+        const uint32_t pre = COMP ? (uint32_t)(hs.pos & 3u) : 0u;
+        sh.rstart[s] = nn + pre;
+        e += cnt;
+        if (COMP && cnt > 0) {
+          const uint32_t ndw = (pre + hs.len + 3u) >> 2;
+          dw += ndw;
+          nn += per * cnt + 4u * ndw - hs.len;
+        }
+      }
+      sh.ebase[NS] = e;
+      sh.dwbase[NS] = dw;
+      sh.rstart[NS] = nn;
+      sh.seg_flags = 0;
+    }
+    for (uint32_t p = tid; p < P; p += NT) sh.hist[p] = 0;
+    __syncthreads();
+    const uint32_t Et = sh.ebase[NS];
+    if constexpr (COMP) {
+      const uint32_t Dt = sh.dwbase[NS];
+      for (uint32_t j0 = tid; j0 < Dt; j0 += 4 * NT) {
+        uint32_t w[4], off[4];
+        int32_t si[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t j = j0 + (uint32_t)k * NT;
+          si[k] = -1;
+          w[k] = 0;
+          off[k] = 0;
+          if (j < Dt) {
+            int32_t s = 0;
+            while (j >= sh.dwbase[s + 1]) ++s;
+            si[k] = s;
+            off[k] = 4u * (j - sh.dwbase[s]);
+            w[k] = *(const uint32_t*)(x.g.bytes + (sh.pos[s] & ~3ull) + off[k]);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (si[k] < 0) continue;
+          const int32_t s = si[k];
+          const uint32_t b0 = (uint32_t)(sh.pos[s] & 3u), b1 = b0 + sh.len[s];
+          uint32_t v = w[k];
+#pragma unroll
+          for (uint32_t b = 0; b < 4; ++b)
+            if (off[k] + b < b0 || off[k] + b >= b1) v &= ~(0xFFu << (8 * b));
+          A32[j0 + (uint32_t)k * NT] = v;
+        }
+      }
+      __syncthreads();
+      {
+        const uint32_t Q = (Dt + NT - 1) / NT;
+        const uint32_t j0 = min(Dt, tid * Q), j1 = min(Dt, j0 + Q);
+        int32_t cnt = 0;
+        for (uint32_t j = j0; j < j1; ++j) cnt += __popc(~A32[j] & 0x80808080u);
+        int32_t tot;
+        uint32_t idx = (uint32_t)(block_incl_scan_add<NT, int32_t>(cnt, sh.scan, &tot) - cnt);
+        uint32_t prev = j0 > 0 ? A32[j0 - 1] : 0u;
+        for (uint32_t j = j0; j < j1; ++j) {
+          const uint32_t cur = A32[j];
+          const uint64_t w = ((uint64_t)cur << 32) | prev;
+          const uint64_t term = ~w & 0x8080808080808080ull;
+          uint32_t tc = (uint32_t)(term >> 32);
+          while (tc) {
+            const uint32_t b = 4u + (((uint32_t)__ffs(tc) - 1u) >> 3);
+            tc &= tc - 1u;
+            nums[idx++] = window_value(w, term, b);
+          }
+          prev = cur;
+        }
+      }
+      __syncthreads();
+    }
+    // neighbour IDs, weights and labels of this thread's slice
+    const uint32_t Dd = (Et + NT - 1) / NT;
+    const uint32_t e0 = tid * Dd;
+    int32_t vi[ITEMS], nb[ITEMS], wt[ITEMS];
+    {
+      int32_t s = 0;
+      if (e0 < Et)
+        while (e0 >= sh.ebase[s + 1]) ++s;
+      bool any_head = false;
+      int32_t a = 0, a2 = 0;
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t e = e0 + k;
+        vi[k] = -1;
+        nb[k] = 0;
+        wt[k] = 1;
+        if ((uint32_t)k < Dd && e < Et) {
+          while (e >= sh.ebase[s + 1]) ++s;
+          vi[k] = s;
+          const uint32_t loc = e - sh.ebase[s];
+          if constexpr (COMP) {
+            const uint32_t ci = sh.rstart[s] + per * loc;
+            const uint32_t code = nums[ci];
+            const bool head = loc == 0;
+            const int32_t dv =
+                head ? sh.base_v[s] + (sh.zig[s] ? unzigzag32(code) : (int32_t)code) : (int32_t)code;
+            const int32_t dw = weighted ? (head ? sh.base_w[s] : 0) + unzigzag32(nums[ci + 1]) : 0;
+            if (head) {
+              any_head = true;
+              a = dv;
+              a2 = dw;
+            } else {
+              a += dv;
+              a2 += dw;
+            }
+            nb[k] = a;
+            wt[k] = a2;
+          } else {
+            const uint64_t ge = sh.pos[s] + loc;
+            nb[k] = x.g.adjncy[ge];
+            if (weighted) wt[k] = x.g.adjwgt[ge];
+          }
+        }
+      }
+      if constexpr (COMP) {
+        int32_t ex, ex2;
+        tile_seg_scan<NT>(any_head, a, a2, sh.scan, sh.scan2, &sh.seg_flags, ex, ex2);
+        bool before = true;
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+          if (vi[k] < 0) continue;
+          if (e0 + k == sh.ebase[vi[k]]) before = false;
+          if (before) {
+            nb[k] += ex;
+            wt[k] += ex2;
+          }
+          if (!weighted) wt[k] = 1;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+      if (vi[k] < 0) continue;
+      if ((uint32_t)nb[k] < (uint32_t)x.g.n) nb[k] = x.C[nb[k]];
+      else vi[k] = -1;  // unreachable for a valid handle; keeps the gather in bounds
+    }
+    __syncthreads();  // numbers consumed: region A becomes the table
+    const uint32_t S = tile_slots(Et);
+    for (uint32_t q = tid; q < S; q += NT) keys[q] = kEmpty;
+    for (uint32_t q = tid; q < S; q += NT) vals[q] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k)
+      if (vi[k] >= 0) tile_insert<V>(keys, vals, 0, S, nb[k], (V)wt[k]);
+    __syncthreads();
+    // distinct clusters grouped by partition
+    for (uint32_t q = tid; q < S; q += NT) {
+      const int32_t c = keys[q];
+      if (c != kEmpty) atomicAdd(&sh.hist[part_hash((uint32_t)c) % P], 1u);
+    }
+    __syncthreads();
+    {
+      uint32_t carry = 0;
+      for (uint32_t b0 = 0; b0 < P; b0 += NT) {
+        const uint32_t p = b0 + tid;
+        const int32_t v = p < P ? (int32_t)sh.hist[p] : 0;
+        int32_t tot;
+        const int32_t inc = block_incl_scan_add<NT, int32_t>(v, sh.scan, &tot);
+        if (p < P) {
+          sh.hist[p] = carry + (uint32_t)(inc - v);
+          po[p] = carry + (uint32_t)(inc - v);
+        }
+        carry += (uint32_t)tot;
+      }
+      if (tid == 0) po[P] = carry;
+    }
+    __syncthreads();
+    for (uint32_t q = tid; q < S; q += NT) {
+      const int32_t c = keys[q];
+      if (c == kEmpty) continue;
+      const uint32_t slot = atomicAdd(&sh.hist[part_hash((uint32_t)c) % P], 1u);
+      hm.rec_c[rbase + slot] = c;
+      rec_r[rbase + slot] = vals[q];
+    }
+    __syncthreads();
+  }
+}
+
+constexpr uint32_t kHubTable = 4096;  // max LDS entries of a (hub, partition) task
 
 struct HubReduceSmem {
   Cand best[kHubThreads / kWave];
@@ -752,34 +972,47 @@ struct HubReduceSmem {
   int32_t pre[kHubThreads + 1];
 };
 
-// One workgroup per (hub, partition). The partition's records of all the
-// hub's segments are walked as one flat range per batch of kHubThreads
-// segments and aggregated in LDS; if more distinct clusters show up than half
-// the table, the partition is re-read in label-range sub-passes.
+// H2: one workgroup per (hub, partition). The table is sized to the
+// partition's record count (a power of two >= 2 * count, at most kHubTable);
+// the partition's records of all the hub's pieces are walked as one flat
+// range per batch of kHubThreads pieces and summed in LDS. A partition with
+// more records than half the table is split into label-range sub-passes
+// (doubled again if a sub-pass still sees too many distinct clusters).
 template <typename V>
 __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta hm, int32_t ntasks) {
   extern __shared__ __align__(16) uint8_t smem_raw[];
-  constexpr uint32_t tcap = kHubTable;
   constexpr int NT = kHubThreads;
   int32_t* keys = (int32_t*)smem_raw;
-  V* vals = (V*)(smem_raw + (size_t)tcap * 4);
-  HubReduceSmem& sm = *(HubReduceSmem*)(smem_raw + (size_t)tcap * (4 + sizeof(V)));
+  V* vals = (V*)(smem_raw + (size_t)kHubTable * 4);
+  HubReduceSmem& sm = *(HubReduceSmem*)(smem_raw + (size_t)kHubTable * (4 + sizeof(V)));
+  const V* rec_r = (const V*)hm.rec_r;
   if (*x.done) return;
   const int tid = threadIdx.x;
-  const uint32_t mask = tcap - 1, shift = 32 - ceil_log2(tcap);
-  const uint32_t limit = tcap / 2;
   for (int64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
     const int2 task = hm.tasks[t];
     const int h = task.x;
     const uint32_t p = (uint32_t)task.y;
     const int32_t u = hm.u[h];
     const uint32_t P = (uint32_t)hm.nparts[h];
-    const uint32_t nseg = (uint32_t)hm.nseg[h];
+    const uint32_t nseg = (uint32_t)hm.npieces[h];
     const uint64_t rb0 = hm.rec_base[h];
     const uint32_t* po = hm.poff + hm.poff_base[h];
     const int32_t own_c = x.C[u];
     const int64_t wu = vweight(x.g, u);
-    uint32_t S = 1;  // label-range sub-passes; doubled if a table overflows
+    // records of this partition
+    int64_t cnt = 0;
+    for (uint32_t k = tid; k < nseg; k += NT)
+      cnt += po[(uint64_t)k * (P + 1) + p + 1] - po[(uint64_t)k * (P + 1) + p];
+    cnt = block_reduce_add<NT, int64_t>(cnt, sm.red);
+    uint32_t logc = 6;
+    while ((1ull << logc) < 2ull * (uint64_t)cnt && logc < 40) ++logc;
+    uint32_t S = 1;  // label-range sub-passes
+    if ((1ull << logc) > kHubTable) {
+      S = (uint32_t)((1ull << logc) / kHubTable);
+      logc = ceil_log2(kHubTable);
+    }
+    const uint32_t tcap = 1u << logc, mask = tcap - 1, shift = 32 - logc;
+    const uint32_t limit = tcap / 2;
     Cand best;
     int64_t own;
     while (true) {
@@ -815,10 +1048,10 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta 
               if (sm.pre[mid] <= j) lo = mid;
               else hi = mid;
             }
-            const uint64_t r = rb0 + (uint64_t)(kb + lo) * LP_CHUNK_LEN + sm.ra[lo] + (uint32_t)(j - sm.pre[lo]);
+            const uint64_t r = rb0 + (uint64_t)(kb + lo) * kHubPiece + sm.ra[lo] + (uint32_t)(j - sm.pre[lo]);
             const int32_t c2 = hm.rec_c[r];
             if (S > 1 && (uint32_t)(((uint64_t)(uint32_t)c2 * S) / (uint64_t)x.g.n) != sp) continue;
-            const V w = hm.rec_w ? (V)hm.rec_w[r] : (V)1;
+            const V w = rec_r[r];
             uint32_t hs = slot_hash((uint32_t)c2) >> shift;
             bool reserved = false;
             while (true) {
@@ -850,6 +1083,9 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta 
           over = true;
           break;
         }
+        // this thread's best slot ignoring the cap; one cluster-weight read;
+        // only if that cluster is full are the slots rescanned with the cap
+        Cand lb = cand_none();
         for (uint32_t q = tid; q < tcap; q += NT) {
           const int32_t c = keys[q];
           if (c == kEmpty) continue;
@@ -858,7 +1094,20 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta 
             own = r;
             continue;
           }
-          consider(x, c, r, wu, best);
+          if (r < lb.r) continue;
+          const Cand cd{r, tiebreak_key(x.seed, x.round, (uint32_t)c), c};
+          if (cand_better(cd, lb)) lb = cd;
+        }
+        if (lb.c >= 0 && cand_better(lb, best)) {
+          if (x.W[lb.c] + wu <= x.cap) {
+            best = lb;
+          } else {
+            for (uint32_t q = tid; q < tcap; q += NT) {
+              const int32_t c = keys[q];
+              if (c == kEmpty || c == own_c) continue;
+              consider(x, c, (int64_t)vals[q], wu, best);
+            }
+          }
         }
         __syncthreads();
       }
@@ -1139,6 +1388,30 @@ lp_status launch_tile_any(bool comp, bool wide, const RoundCtx& x, VDesc vd, con
               : launch_tile<T, int32_t, false>(x, vd, tiles, ntiles, grid, weighted, s);
 }
 
+template <typename V>
+TileLayout piece_layout_of(bool comp, bool weighted) {
+  TileLayout L;
+  const uint32_t per = weighted ? 2u : 1u;
+  L.table_bytes = (uint32_t)kPieceSlots * (4u + (uint32_t)sizeof(V));
+  const uint32_t nums = comp ? (per * kHubPiece + 6u * kHubStreams) * 4u : 0u;
+  const uint32_t worst = comp ? 5u * per * kHubPiece + 8u * kHubStreams : 0u;
+  L.stage_bytes = comp ? ((worst + 15u) & ~15u) : 0u;
+  L.nums_off = L.stage_bytes;
+  L.abytes = std::max(L.table_bytes, L.stage_bytes + nums);
+  L.abytes = (L.abytes + 15u) & ~15u;
+  return L;
+}
+
+lp_status launch_piece(bool comp, bool wide, const RoundCtx& x, const HubMeta& hm, int32_t npieces,
+                       const TileLayout& L, size_t lds, hipStream_t s) {
+  auto kern = comp ? (wide ? k_hub_piece<int64_t, true> : k_hub_piece<int32_t, true>)
+                   : (wide ? k_hub_piece<int64_t, false> : k_hub_piece<int32_t, false>);
+  LP_CHECK(set_lds(kern, lds));
+  const unsigned grid = grid_for(npieces, 1, 2048);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kPieceThreads), lds, s, x, hm, npieces, L);
+  return last_error();
+}
+
 // Tiles of one tile bucket, planned on the device (the count stays there).
 struct TilePlan {
   int32_t* tiles = nullptr;
@@ -1183,7 +1456,7 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
   if (n == 0) return LP_OK;
   // knobs (results do not depend on them)
   const bool wide = g->max_wdeg > 0x7FFFFFFFll;
-  int32_t t_lane = 16, t_tile = TileSmall::kEdges, t_block = TileLarge::kEdges, hub_part = 4096;
+  int32_t t_lane = 16, t_tile = TileSmall::kEdges, t_block = TileLarge::kEdges, hub_part = 1024;
   if (cfg_in) {
     if (cfg_in->t_lane) t_lane = cfg_in->t_lane;
     if (cfg_in->t_tile) t_tile = cfg_in->t_tile;
@@ -1302,7 +1575,7 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
   LP_CHECK(plan_tiles<TileSmall>(vd_of(1), bn[1], g->compressed, wide, g->weighted, sc, tps));
   LP_CHECK(plan_tiles<TileLarge>(vd_of(2), bn[2], g->compressed, wide, g->weighted, sc, tpl));
 
-  // hub metadata (host-built, small)
+  // hub metadata (host-built, small) and the stream descriptors of the pieces
   const int32_t H = bn[3];
   HubMeta hm{};
   int32_t npieces = 0, ntasks = 0;
@@ -1318,39 +1591,38 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
     int64_t maxd = 0;
     for (int h = 0; h < H; ++h) maxd = std::max<int64_t>(maxd, hd[h]);
     const int64_t part = std::max<int64_t>(hub_part, (maxd + kMaxParts - 1) / kMaxParts);
-    std::vector<int32_t> np(H), ns(H), tb(H);
+    std::vector<int32_t> np(H), npc(H), pcb(H), tb(H);
     std::vector<uint64_t> rbase(H), pbase(H);
     std::vector<int2> pieces, tasks;
     uint64_t rsum = 0, psum = 0;
     for (int h = 0; h < H; ++h) {
       const int64_t d = hd[h];
       np[h] = (int32_t)std::max<int64_t>(1, (d + part - 1) / part);
-      ns[h] = (int32_t)((d + LP_CHUNK_LEN - 1) / LP_CHUNK_LEN);
+      npc[h] = (int32_t)((d + kHubPiece - 1) / kHubPiece);
+      pcb[h] = (int32_t)pieces.size();
       rbase[h] = rsum;
       pbase[h] = psum;
       tb[h] = ntasks;
       rsum += (uint64_t)d;
-      psum += (uint64_t)ns[h] * (np[h] + 1);
+      psum += (uint64_t)npc[h] * (np[h] + 1);
       ntasks += np[h];
-      const bool chunked = g->compressed ? (d > LP_CHUNK_THRESHOLD) : true;
-      if (chunked)
-        for (int k = 0; k < ns[h]; ++k) pieces.push_back(make_int2(h, k));
-      else
-        pieces.push_back(make_int2(h, 0));
+      for (int k = 0; k < npc[h]; ++k) pieces.push_back(make_int2(h, k));
       for (int p = 0; p < np[h]; ++p) tasks.push_back(make_int2(h, p));
     }
     npieces = (int32_t)pieces.size();
     int32_t* d_u = sc.alloc<int32_t>(H);
     int32_t* d_deg = sc.alloc<int32_t>(H);
     int32_t* d_np = sc.alloc<int32_t>(H);
-    int32_t* d_ns = sc.alloc<int32_t>(H);
+    int32_t* d_npc = sc.alloc<int32_t>(H);
+    int32_t* d_pcb = sc.alloc<int32_t>(H);
     int32_t* d_tb = sc.alloc<int32_t>(H);
     uint64_t* d_rb = sc.alloc<uint64_t>(H);
     uint64_t* d_pb = sc.alloc<uint64_t>(H);
     int2* d_pieces = sc.alloc<int2>(npieces);
     int2* d_tasks = sc.alloc<int2>(ntasks);
+    hm.streams = sc.alloc<HubStream>((size_t)npieces * kHubStreams);
     hm.rec_c = sc.alloc<int32_t>(rsum);
-    hm.rec_w = g->weighted ? sc.alloc<int32_t>(rsum) : nullptr;
+    hm.rec_r = wide ? (void*)sc.alloc<int64_t>(rsum) : (void*)sc.alloc<int32_t>(rsum);
     hm.poff = sc.alloc<uint32_t>(psum);
     hm.res_r = sc.alloc<int64_t>(ntasks);
     hm.res_key = sc.alloc<uint64_t>(ntasks);
@@ -1360,22 +1632,26 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
     LP_CHECK_HIP(hipMemcpyAsync(d_u, hu.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
     LP_CHECK_HIP(hipMemcpyAsync(d_deg, hd.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
     LP_CHECK_HIP(hipMemcpyAsync(d_np, np.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_ns, ns.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_npc, npc.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_pcb, pcb.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
     LP_CHECK_HIP(hipMemcpyAsync(d_tb, tb.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
     LP_CHECK_HIP(hipMemcpyAsync(d_rb, rbase.data(), H * sizeof(uint64_t), hipMemcpyHostToDevice, s));
     LP_CHECK_HIP(hipMemcpyAsync(d_pb, pbase.data(), H * sizeof(uint64_t), hipMemcpyHostToDevice, s));
     LP_CHECK_HIP(hipMemcpyAsync(d_pieces, pieces.data(), npieces * sizeof(int2), hipMemcpyHostToDevice, s));
     LP_CHECK_HIP(hipMemcpyAsync(d_tasks, tasks.data(), ntasks * sizeof(int2), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
     hm.u = d_u;
     hm.deg = d_deg;
     hm.nparts = d_np;
-    hm.nseg = d_ns;
+    hm.npieces = d_npc;
+    hm.piece_base = d_pcb;
     hm.rec_base = d_rb;
     hm.poff_base = d_pb;
     hm.task_base = d_tb;
     hm.pieces = d_pieces;
     hm.tasks = d_tasks;
+    hipLaunchKernelGGL(k_hub_streams, dim3(grid_for(H, 4, 4096)), dim3(256), 0, s, g->view(), hm, H);
+    LP_CHECK_LAUNCH();
+    LP_CHECK_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
   }
 
   hipLaunchKernelGGL(k_init, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, g->vwgt, labels, W, ptgt);
@@ -1391,9 +1667,10 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
   x.ptgt = ptgt;
   x.pgain = pgain;
   x.done = &ctl->done;
-  const size_t piece_lds = sizeof(HubPieceSmem) * 4;
+  const TileLayout piece_layout = wide ? piece_layout_of<int64_t>(g->compressed, g->weighted)
+                                      : piece_layout_of<int32_t>(g->compressed, g->weighted);
+  const size_t piece_lds = (size_t)piece_layout.abytes + sizeof(PieceShared);
   if (H > 0) {
-    LP_CHECK(set_lds(k_hub_scatter, piece_lds));
     if (wide) LP_CHECK(set_lds(k_hub_reduce<int64_t>, (size_t)kHubTable * 12 + sizeof(HubReduceSmem)));
     else LP_CHECK(set_lds(k_hub_reduce<int32_t>, (size_t)kHubTable * 8 + sizeof(HubReduceSmem)));
   }
@@ -1424,8 +1701,7 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
     }
     if (H > 0) {
       LP_CHECK(begin(LP_PHASE_HUB));
-      hipLaunchKernelGGL(k_hub_scatter, dim3(grid_for(npieces, 4)), dim3(256), piece_lds, s, x, hm, npieces);
-      LP_CHECK_LAUNCH();
+      LP_CHECK(launch_piece(g->compressed, wide, x, hm, npieces, piece_layout, piece_lds, s));
       if (wide)
         hipLaunchKernelGGL(k_hub_reduce<int64_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads),
                            (size_t)kHubTable * 12 + sizeof(HubReduceSmem), s, x, hm, ntasks);

@@ -34,10 +34,11 @@ def _graphs(synth_mod):
     out["star-10001-w"] = _star(synth_mod, 10001, center=5000, weights=True)
     out["bip-5x2048"] = _bipartite(synth_mod, 5, 2048)
     out["bip-5x2048-heavy"] = _bipartite(synth_mod, 5, 2048, heavy=True)
+    out["bip-3x9000-w"] = _bipartite(synth_mod, 3, 9000, small=True)  # unsplit hubs cut into pieces
     return out
 
 
-def _bipartite(synth_mod, a, b, heavy=False):
+def _bipartite(synth_mod, a, b, heavy=False, small=False):
     # complete bipartite K_{a,b} plus a path over the b side: the a side has
     # degree b exactly (the largest degree rated in tiles); with heavy random
     # weights each of its records takes about 6 bytes per neighbour, so tiles
@@ -47,6 +48,8 @@ def _bipartite(synth_mod, a, b, heavy=False):
     w = None
     if heavy:
         w = [2**29 + (k * 2654435761) % (2**31 - 2**29 - 1) for k in range(len(edges))]
+    elif small:
+        w = [1 + (k * 7919) % 100 for k in range(len(edges))]
     return synth_mod.from_edges(a + b, edges, w)
 
 
@@ -108,6 +111,7 @@ CASES = [
     ("star-10001-w", 5000, 3, 2),
     ("bip-5x2048", 700, 4, 3),
     ("bip-5x2048-heavy", 900, 4, 4),
+    ("bip-3x9000-w", 30000, 4, 5),
 ]
 
 
@@ -134,7 +138,8 @@ KNOBS = [
 
 
 @pytest.mark.parametrize("knobs", KNOBS)
-@pytest.mark.parametrize("name", ["rmat-s13-ef16", "rmat-s12-weighted", "star-25000", "bip-5x2048-heavy"])
+@pytest.mark.parametrize("name", ["rmat-s13-ef16", "rmat-s12-weighted", "star-25000", "bip-5x2048-heavy",
+                                  "bip-3x9000-w"])
 @pytest.mark.parametrize("compressed", [True, False])
 def test_bucket_thresholds_do_not_change_results(lp, oracle_mod, graphs, knobs, name, compressed):
     g = graphs[name]
