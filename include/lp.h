@@ -194,6 +194,48 @@ lp_status lp_cluster_ex(const lp_graph *g, int64_t max_cluster_weight, int32_t r
                         void *stream);
 
 /*
+ * Batches of graphs (many uneven graphs in one launch sequence).
+ *
+ * lp_batch_create — the disjoint union of G >= 1 graph handles as one batch
+ * handle (all compressed or all plain, all with or all without edge
+ * weights, else LP_EUNSUPPORTED; total vertices < 2^31). Graph i's vertices
+ * occupy [vbase[i], vbase[i+1]) of the union. The inputs are copied (they
+ * stay owned by the caller and may be freed afterwards); the batch handle is
+ * freed with lp_graph_free. The call synchronises `stream`.
+ * A batch handle is accepted by lp_batch_cluster_ex, lp_contract and
+ * lp_edge_cut (which see the union as one graph); lp_cluster(_ex),
+ * lp_decompress and lp_graph_export reject it (LP_EINVAL / LP_EUNSUPPORTED).
+ */
+lp_status lp_batch_create(int32_t G, const lp_graph *const *graphs, void *stream, lp_graph **batch_out);
+
+/* Number of graphs of a batch handle (0 for a single graph) and, if vbase is
+ * not NULL, their first vertices (host int32[G + 1]). */
+lp_status lp_batch_info(const lp_graph *batch, int32_t *G, int32_t *vbase);
+
+/*
+ * lp_batch_cluster_ex — lp_cluster on every graph of a batch at once.
+ * caps, seeds: host arrays of G values (cap of graph i >= 1). Each graph
+ * follows the rules of lp_cluster with its own cap and seed, and its
+ * tie-break keys use labels local to the graph, so the labels of graph i are
+ * exactly those lp_cluster gives for it alone. labels_dev: int32[n of the
+ * union]; graph i's labels are written at [vbase[i], vbase[i+1]) as IDs
+ * local to graph i. A round without proposals in any graph ends the call
+ * (graphs without proposals are at a fixed point and stay there). Knobs and
+ * statistics as in lp_cluster_ex (statistics sum over the graphs).
+ */
+lp_status lp_batch_cluster_ex(const lp_graph *batch, const int64_t *caps, int32_t rounds,
+                              const uint64_t *seeds, int32_t *labels_dev, const lp_config *cfg,
+                              lp_cluster_stats *stats, void *stream);
+
+/*
+ * lp_batch_cluster — G separate handles in, G label arrays out: builds the
+ * batch, clusters it and writes graph i's labels to labels_dev[i] (host
+ * array of G device pointers, int32[n_i] each). Synchronises `stream`.
+ */
+lp_status lp_batch_cluster(int32_t G, const lp_graph *const *graphs, const int64_t *caps, int32_t rounds,
+                           const uint64_t *seeds, int32_t *const *labels_dev, void *stream);
+
+/*
  * lp_contract — quotient graph of a clustering (Section IV-B).
  * Coarse vertex IDs are the ranks of the nonempty labels in increasing order;
  * the weight of a coarse vertex is the sum of its members' weights; the

@@ -95,6 +95,15 @@ def _load():
     lib.lp_edge_cut.restype = S
     lib.lp_graph_free.argtypes = [_P]
     lib.lp_graph_free.restype = None
+    lib.lp_batch_create.argtypes = [ctypes.c_int32, _P, _P, ctypes.POINTER(_P)]
+    lib.lp_batch_create.restype = S
+    lib.lp_batch_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int32), _P]
+    lib.lp_batch_info.restype = S
+    lib.lp_batch_cluster_ex.argtypes = [_P, _P, ctypes.c_int32, _P, _P, ctypes.POINTER(lp_config),
+                                        ctypes.POINTER(lp_cluster_stats), _P]
+    lib.lp_batch_cluster_ex.restype = S
+    lib.lp_batch_cluster.argtypes = [ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P, _P]
+    lib.lp_batch_cluster.restype = S
     _lib = lib
     return lib
 
@@ -102,7 +111,8 @@ def _load():
 def exported_symbols() -> list[str]:
     return ["lp_strerror", "lp_version", "lp_compress", "lp_graph_from_csr", "lp_graph_info",
             "lp_graph_export", "lp_decompress", "lp_cluster", "lp_cluster_ex", "lp_contract",
-            "lp_edge_cut", "lp_graph_free"]
+            "lp_edge_cut", "lp_graph_free", "lp_batch_create", "lp_batch_info", "lp_batch_cluster_ex",
+            "lp_batch_cluster"]
 
 
 def _check(st: int, where: str) -> None:
@@ -250,13 +260,72 @@ def lp_cluster(g: Graph, max_cluster_weight: int, rounds: int = 5, seed: int = 1
                                ctypes.byref(st_obj) if st_obj is not None else None, _stream(stream))
     _check(st, "lp_cluster")
     out = labels[: g.n]
-    if stats:
-        k = min(st_obj.rounds_run, 64)
-        return out, ClusterStats(st_obj.rounds_run, (st_obj.n_lane, st_obj.n_tile, st_obj.n_block, st_obj.n_hub),
-                                 list(st_obj.proposals[:k]), list(st_obj.moves[:k]),
-                                 tuple(st_obj.bucket_edges), tuple(st_obj.bucket_bytes),
-                                 dict(zip(PHASES, st_obj.phase_ms)), dict(zip(PHASES, st_obj.phase_launches)))
-    return out
+    return (out, _stats_of(st_obj)) if stats else out
+
+
+def _stats_of(st_obj) -> ClusterStats:
+    k = min(st_obj.rounds_run, 64)
+    return ClusterStats(st_obj.rounds_run, (st_obj.n_lane, st_obj.n_tile, st_obj.n_block, st_obj.n_hub),
+                        list(st_obj.proposals[:k]), list(st_obj.moves[:k]),
+                        tuple(st_obj.bucket_edges), tuple(st_obj.bucket_bytes),
+                        dict(zip(PHASES, st_obj.phase_ms)), dict(zip(PHASES, st_obj.phase_launches)))
+
+
+class Batch(Graph):
+    """Disjoint union of several graph handles (lp_batch_create); graph i owns
+    vertices [vbase[i], vbase[i + 1]) of the union."""
+
+    def __init__(self, handle):
+        super().__init__(handle)
+        G = ctypes.c_int32()
+        _check(_load().lp_batch_info(self.handle, ctypes.byref(G), None), "lp_batch_info")
+        vb = (ctypes.c_int32 * (G.value + 1))()
+        _check(_load().lp_batch_info(self.handle, None, vb), "lp_batch_info")
+        self.G = G.value
+        self.vbase = list(vb)
+
+    def split(self, labels):
+        """Per-graph views of a union-sized array."""
+        return [labels[self.vbase[i]: self.vbase[i + 1]] for i in range(self.G)]
+
+
+def lp_batch_create(graphs, stream=None) -> Batch:
+    """One batch handle over the given graph handles (they stay usable)."""
+    arr = (_P * len(graphs))(*[g.handle for g in graphs])
+    h = _P()
+    _check(_load().lp_batch_create(len(graphs), arr, _stream(stream), ctypes.byref(h)), "lp_batch_create")
+    return Batch(h)
+
+
+def lp_batch_cluster_ex(b: Batch, caps, rounds: int, seeds, labels=None, config: dict | None = None,
+                        stats: bool = False, stream=None):
+    """Labels of every graph of a batch (union-sized int32 tensor, local IDs per graph)."""
+    torch = _torch()
+    if labels is None:
+        labels = torch.empty(max(b.n, 1), dtype=torch.int32, device="cuda")
+    c = (ctypes.c_int64 * b.G)(*[int(v) for v in caps])
+    sd = (ctypes.c_uint64 * b.G)(*[int(v) & (2**64 - 1) for v in seeds])
+    cfg = lp_config(**{k: int(v) for k, v in config.items()}) if config else None
+    st_obj = lp_cluster_stats() if stats else None
+    st = _load().lp_batch_cluster_ex(b.handle, c, int(rounds), sd, _ptr(labels), ctypes.byref(cfg) if cfg else None,
+                                     ctypes.byref(st_obj) if st_obj is not None else None, _stream(stream))
+    _check(st, "lp_batch_cluster_ex")
+    out = labels[: b.n]
+    return (out, _stats_of(st_obj)) if stats else out
+
+
+def lp_batch_cluster(graphs, caps, rounds: int, seeds, labels=None, stream=None):
+    """G handles in, G label tensors out (one batched run)."""
+    torch = _torch()
+    G = len(graphs)
+    if labels is None:
+        labels = [torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda") for g in graphs]
+    arr = (_P * G)(*[g.handle for g in graphs])
+    outs = (_P * G)(*[_ptr(t) for t in labels])
+    c = (ctypes.c_int64 * G)(*[int(v) for v in caps])
+    sd = (ctypes.c_uint64 * G)(*[int(v) & (2**64 - 1) for v in seeds])
+    _check(_load().lp_batch_cluster(G, arr, c, int(rounds), sd, outs, _stream(stream)), "lp_batch_cluster")
+    return [t[: g.n] for t, g in zip(labels, graphs)]
 
 
 def lp_contract(g: Graph, labels, want_map: bool = True, stream=None):

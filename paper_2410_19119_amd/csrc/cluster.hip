@@ -33,7 +33,32 @@ struct RoundCtx {
   int32_t* ptgt;     // proposal target per vertex, -1 = none
   int64_t* pgain;    // proposal gain per vertex
   const uint32_t* done;
+  // batches of graphs (disjoint union): graph of each vertex, first vertex,
+  // cap and seed of each graph; gid == nullptr for a single graph
+  const int32_t* gid;
+  const int32_t* gbase;
+  const int64_t* gcap;
+  const uint64_t* gseed;
 };
+
+// Cap, seed and label offset that apply to vertex u: a graph of a batch keeps
+// its own cap and seed, and its tie-break keys use labels local to the graph,
+// so every graph gets exactly the labels it would get alone.
+struct VParams {
+  int64_t cap;
+  uint64_t seed;
+  int32_t base;
+};
+
+__device__ __forceinline__ VParams vparams(const RoundCtx& x, int32_t u) {
+  if (!x.gid) return VParams{x.cap, x.seed, 0};
+  const int32_t g = x.gid[u];
+  return VParams{x.gcap[g], x.gseed[g], x.gbase[g]};
+}
+
+__device__ __forceinline__ uint64_t cluster_key(const RoundCtx& x, const VParams& p, int32_t c) {
+  return tiebreak_key(p.seed, x.round, (uint32_t)(c - p.base));
+}
 
 // Per listed vertex, built once per call: (vertex, degree, byte position of
 // its first code [compressed] or first edge [plain]) and the length of the
@@ -58,10 +83,11 @@ __device__ __forceinline__ void emit(const RoundCtx& x, int32_t u, const Cand& b
 
 // Candidate update with lazy feasibility: the cluster weight is only read
 // when the candidate would beat the current best.
-__device__ __forceinline__ void consider(const RoundCtx& x, int32_t c, int64_t r, int64_t wu, Cand& best) {
+__device__ __forceinline__ void consider(const RoundCtx& x, const VParams& p, int32_t c, int64_t r, int64_t wu,
+                                         Cand& best) {
   if (r < best.r) return;
-  Cand cd{r, tiebreak_key(x.seed, x.round, (uint32_t)c), c};
-  if (cand_better(cd, best) && x.W[c] + wu <= x.cap) best = cd;
+  Cand cd{r, cluster_key(x, p, c), c};
+  if (cand_better(cd, best) && x.W[c] + wu <= p.cap) best = cd;
 }
 
 // ------------------------------------------------------- lane per vertex --
@@ -105,6 +131,7 @@ __global__ __launch_bounds__(256) void k_rate_lane(RoundCtx x, VDesc vd, int32_t
   }
   const int32_t own_c = x.C[u];
   const int64_t wu = vweight(x.g, u);
+  const VParams vp = vparams(x, u);
   int64_t own = 0;
 #pragma unroll
   for (int k = 0; k < kMaxLane; ++k) own += (lab[k] == own_c) ? wt[k] : 0;
@@ -119,7 +146,7 @@ __global__ __launch_bounds__(256) void k_rate_lane(RoundCtx x, VDesc vd, int32_t
       int64_t r = 0;
 #pragma unroll
       for (int j = k; j < kMaxLane; ++j) r += (lab[j] == c) ? wt[j] : 0;
-      consider(x, c, r, wu, best);
+      consider(x, vp, c, r, wu, best);
     }
   }
   emit(x, u, best, own);
@@ -188,6 +215,7 @@ struct TileShared {
   uint32_t tbase[VT + 1];
   int64_t own_r[VT];
   int64_t gain[VT];
+  VParams vp;  // the tile's graph (tiles never span two graphs of a batch)
   int32_t scan[NT / kWave];
   int32_t scan2[NT / kWave];
   Cand cb[NT / kWave];
@@ -378,6 +406,7 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
         sh.tbase[nv] = (uint32_t)tot2 >> 16;
         sh.any_redo = 0;
         sh.seg_flags = 0;
+        sh.vp = vparams(x, sh.u[0]);
       }
     }
     __syncthreads();
@@ -529,7 +558,7 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
           continue;
         }
         if (r < best.r) continue;
-        const Cand cd{r, tiebreak_key(x.seed, x.round, (uint32_t)c), c};
+        const Cand cd{r, cluster_key(x, sh.vp, c), c};
         if (cand_better(cd, best)) best = cd;
       }
       if constexpr (SG == kWave) {
@@ -551,7 +580,7 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
       const int32_t c = sh.best_c[tid];
       if (c < 0) {
         x.ptgt[u] = -1;
-      } else if (x.W[c] + sh.wu[tid] <= x.cap) {
+      } else if (x.W[c] + sh.wu[tid] <= sh.vp.cap) {
         x.ptgt[u] = c;
         x.pgain[u] = sh.gain[tid];
       } else {
@@ -573,8 +602,8 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
           if (c == kEmpty || c == oc) continue;
           const int64_t r = (int64_t)vals[q];
           if (r <= own || r < best.r) continue;
-          const Cand cd{r, tiebreak_key(x.seed, x.round, (uint32_t)c), c};
-          if (cand_better(cd, best) && x.W[c] + wu <= x.cap) best = cd;
+          const Cand cd{r, cluster_key(x, sh.vp, c), c};
+          if (cand_better(cd, best) && x.W[c] + wu <= sh.vp.cap) best = cd;
         }
         if constexpr (SG == kWave) best = wave_best(best);
         else best = block_best<NT>(best, sh.cb);
@@ -599,18 +628,21 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
 // otherwise the first vertex of every tile (and the end sentinel).
 template <bool COUNT>
 __global__ void k_tile_plan(VDesc vd, int32_t cnt, uint32_t emax, uint32_t vmax, uint32_t bmax, bool comp,
-                            uint32_t* counts, const uint32_t* offs, int32_t* tiles) {
+                            const int32_t* gid, uint32_t* counts, const uint32_t* offs, int32_t* tiles) {
   const int64_t sgi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t a = sgi * kTileSeg;
   if (a >= cnt) return;
   const int64_t b = a + kTileSeg < (int64_t)cnt ? a + kTileSeg : (int64_t)cnt;
   uint32_t e = 0, nvv = 0, by = 0, nt = 0;
+  int32_t g0 = -1;
   const uint32_t o = COUNT ? 0u : offs[sgi];
   for (int64_t i = a; i < b; ++i) {
     const int4 v4 = vd.d[i];
     const uint32_t d = (uint32_t)v4.y;
     const uint32_t sb = comp ? 4u * ((((uint32_t)v4.z & 3u) + vd.len[i] + 3u) / 4u) : 0u;
-    if (nvv == 0 || e + d > emax || nvv == vmax || by + sb > bmax) {
+    const int32_t gv = gid ? gid[v4.x] : 0;
+    if (nvv == 0 || e + d > emax || nvv == vmax || by + sb > bmax || gv != g0) {
+      g0 = gv;
       if (!COUNT) tiles[o + nt] = (int32_t)i;
       ++nt;
       e = 0;
@@ -999,6 +1031,7 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta 
     const uint32_t* po = hm.poff + hm.poff_base[h];
     const int32_t own_c = x.C[u];
     const int64_t wu = vweight(x.g, u);
+    const VParams vp = vparams(x, u);
     // records of this partition
     int64_t cnt = 0;
     for (uint32_t k = tid; k < nseg; k += NT)
@@ -1095,17 +1128,17 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta 
             continue;
           }
           if (r < lb.r) continue;
-          const Cand cd{r, tiebreak_key(x.seed, x.round, (uint32_t)c), c};
+          const Cand cd{r, cluster_key(x, vp, c), c};
           if (cand_better(cd, lb)) lb = cd;
         }
         if (lb.c >= 0 && cand_better(lb, best)) {
-          if (x.W[lb.c] + wu <= x.cap) {
+          if (x.W[lb.c] + wu <= vp.cap) {
             best = lb;
           } else {
             for (uint32_t q = tid; q < tcap; q += NT) {
               const int32_t c = keys[q];
               if (c == kEmpty || c == own_c) continue;
-              consider(x, c, (int64_t)vals[q], wu, best);
+              consider(x, vp, c, (int64_t)vals[q], wu, best);
             }
           }
         }
@@ -1308,10 +1341,13 @@ __global__ void k_admit_prep(const uint64_t* keys, const uint32_t* vals, const u
 }
 
 __global__ void k_admit(const uint32_t* seg, const int64_t* prefix, const uint32_t* count, const int64_t* W,
-                        int64_t cap, uint8_t* flag) {
+                        int64_t cap, const int32_t* gid, const int64_t* gcap, uint8_t* flag) {
   const int64_t n = *count;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    flag[i] = (W[seg[i]] + prefix[i] <= cap) ? 1 : 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t t = seg[i];
+    const int64_t c = gid ? gcap[gid[t]] : cap;
+    flag[i] = (W[t] + prefix[i] <= c) ? 1 : 0;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_apply(const uint32_t* seg, const uint32_t* vals, const uint8_t* flag,
@@ -1420,7 +1456,8 @@ struct TilePlan {
 };
 
 template <class T>
-lp_status plan_tiles(VDesc vd, int32_t cnt, bool comp, bool wide, bool weighted, Scratch& sc, TilePlan& tp) {
+lp_status plan_tiles(VDesc vd, int32_t cnt, bool comp, bool wide, bool weighted, const int32_t* gid, Scratch& sc,
+                     TilePlan& tp) {
   if (cnt <= 0) return LP_OK;
   const TileLayout L = wide ? tile_layout<T, int64_t>(comp, weighted) : tile_layout<T, int32_t>(comp, weighted);
   const int64_t nseg = ((int64_t)cnt + kTileSeg - 1) / kTileSeg;
@@ -1430,11 +1467,11 @@ lp_status plan_tiles(VDesc vd, int32_t cnt, bool comp, bool wide, bool weighted,
   if (sc.failed) return LP_ENOMEM;
   hipStream_t s = sc.stream();
   hipLaunchKernelGGL(k_tile_plan<true>, dim3(grid_for(nseg, 256)), dim3(256), 0, s, vd, cnt, (uint32_t)T::kEdges,
-                     (uint32_t)T::kVerts, L.stage_bytes, comp, tcnt, (const uint32_t*)nullptr, (int32_t*)nullptr);
+                     (uint32_t)T::kVerts, L.stage_bytes, comp, gid, tcnt, (const uint32_t*)nullptr, (int32_t*)nullptr);
   LP_CHECK_LAUNCH();
   LP_CHECK(scan_exclusive_u32(tcnt, tcnt, nseg, tp.ntiles, sc));
   hipLaunchKernelGGL(k_tile_plan<false>, dim3(grid_for(nseg, 256)), dim3(256), 0, s, vd, cnt, (uint32_t)T::kEdges,
-                     (uint32_t)T::kVerts, L.stage_bytes, comp, (uint32_t*)nullptr, (const uint32_t*)tcnt, tp.tiles);
+                     (uint32_t)T::kVerts, L.stage_bytes, comp, gid, (uint32_t*)nullptr, (const uint32_t*)tcnt, tp.tiles);
   LP_CHECK_LAUNCH();
   tp.grid = (unsigned)std::min<int64_t>(2048, ((int64_t)cnt + 7) / 8 * 8);
   return LP_OK;
@@ -1446,11 +1483,27 @@ lp_status plan_tiles(VDesc vd, int32_t cnt, bool comp, bool wide, bool weighted,
 
 using namespace lp;
 
-extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t rounds, uint64_t seed, int32_t* labels,
-                                   const lp_config* cfg_in, lp_cluster_stats* stats_out, void* stream) {
-  clear_error();
-  if (!g || cap < 1 || rounds < 0 || (!labels && g->n > 0)) return LP_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
+namespace lp {
+lp_status batch_localize(const lp_graph* b, const int32_t* lab, int32_t* out, int32_t* const* outs_dev,
+                         hipStream_t s);
+}
+
+// One clustering call. For a batch handle, caps / seeds hold one value per
+// graph (host arrays) and the labels come out local to each graph: written to
+// `labels` (one array over the union) or, if labels_each is given, to each
+// graph's own device array.
+static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* caps, int32_t rounds, uint64_t seed,
+                              const uint64_t* seeds, int32_t* labels, int32_t* const* labels_each,
+                              const lp_config* cfg_in, lp_cluster_stats* stats_out, hipStream_t s) {
+  const bool batch = g->nbatch > 0;
+  if (batch) {
+    if (!caps || !seeds) return LP_EINVAL;
+    for (int32_t i = 0; i < g->nbatch; ++i)
+      if (caps[i] < 1) return LP_EINVAL;
+  } else if (cap < 1) {
+    return LP_EINVAL;
+  }
+  if (rounds < 0 || (!labels && !labels_each && g->n > 0)) return LP_EINVAL;
   if (stats_out) memset(stats_out, 0, sizeof(*stats_out));
   const int32_t n = g->n;
   if (n == 0) return LP_OK;
@@ -1472,6 +1525,10 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
   if (G + nbits > 64) return LP_EUNSUPPORTED;
 
   Scratch sc(s);
+  int32_t* out_labels = labels;
+  if (batch) labels = sc.alloc<int32_t>(n);  // global cluster IDs while the rounds run
+  int64_t* gcap = batch ? sc.alloc<int64_t>(g->nbatch) : nullptr;
+  uint64_t* gseed = batch ? sc.alloc<uint64_t>(g->nbatch) : nullptr;
   int32_t* deg = sc.alloc<int32_t>(n);
   int32_t* order = sc.alloc<int32_t>(n);
   int64_t* W = sc.alloc<int64_t>(n);
@@ -1501,6 +1558,10 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
   Ctl* ctl = sc.alloc<Ctl>(1);
   if (sc.failed) return LP_ENOMEM;
   LP_CHECK_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), s));
+  if (batch) {
+    LP_CHECK_HIP(hipMemcpyAsync(gcap, caps, g->nbatch * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(gseed, seeds, g->nbatch * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  }
 
   // optional per-phase timing with events on the call's stream
   const bool timing = cfg_in && cfg_in->timing && stats_out;
@@ -1572,8 +1633,9 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
 
   // tiles of the two tile buckets
   TilePlan tps, tpl;
-  LP_CHECK(plan_tiles<TileSmall>(vd_of(1), bn[1], g->compressed, wide, g->weighted, sc, tps));
-  LP_CHECK(plan_tiles<TileLarge>(vd_of(2), bn[2], g->compressed, wide, g->weighted, sc, tpl));
+  const int32_t* gid = batch ? g->gid : nullptr;
+  LP_CHECK(plan_tiles<TileSmall>(vd_of(1), bn[1], g->compressed, wide, g->weighted, gid, sc, tps));
+  LP_CHECK(plan_tiles<TileLarge>(vd_of(2), bn[2], g->compressed, wide, g->weighted, gid, sc, tpl));
 
   // hub metadata (host-built, small) and the stream descriptors of the pieces
   const int32_t H = bn[3];
@@ -1667,6 +1729,10 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
   x.ptgt = ptgt;
   x.pgain = pgain;
   x.done = &ctl->done;
+  x.gid = batch ? g->gid : nullptr;
+  x.gbase = batch ? g->gbase : nullptr;
+  x.gcap = gcap;
+  x.gseed = gseed;
   const TileLayout piece_layout = wide ? piece_layout_of<int64_t>(g->compressed, g->weighted)
                                       : piece_layout_of<int32_t>(g->compressed, g->weighted);
   const size_t piece_lds = (size_t)piece_layout.abytes + sizeof(PieceShared);
@@ -1727,7 +1793,7 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
     hipLaunchKernelGGL(k_admit_prep, dim3(ga), dim3(256), 0, s, ks, vs, &ctl->count, G, g->vwgt, seg, wv);
     LP_CHECK_LAUNCH();
     LP_CHECK(seg_scan_incl_i64(seg, wv, pref, &ctl->count, n, sc));
-    hipLaunchKernelGGL(k_admit, dim3(ga), dim3(256), 0, s, seg, pref, &ctl->count, W, cap, flag);
+    hipLaunchKernelGGL(k_admit, dim3(ga), dim3(256), 0, s, seg, pref, &ctl->count, W, cap, x.gid, gcap, flag);
     LP_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_apply, dim3(ga), dim3(256), 0, s, seg, vs, flag, wv, &ctl->count, labels, W, ctl->stats, r);
     LP_CHECK_LAUNCH();
@@ -1735,6 +1801,7 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
     LP_CHECK_LAUNCH();
     LP_CHECK(end());
   }
+  if (batch) LP_CHECK(batch_localize(g, labels, out_labels, labels_each, s));
   if (stats_out) {
     Ctl h;
     LP_CHECK_HIP(hipMemcpyAsync(&h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -1760,6 +1827,42 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
     }
   }
   return LP_OK;
+}
+
+extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t rounds, uint64_t seed, int32_t* labels,
+                                   const lp_config* cfg, lp_cluster_stats* stats, void* stream) {
+  clear_error();
+  if (!g || g->nbatch) return LP_EINVAL;
+  return cluster_impl(g, cap, nullptr, rounds, seed, nullptr, labels, nullptr, cfg, stats, (hipStream_t)stream);
+}
+
+extern "C" lp_status lp_batch_cluster_ex(const lp_graph* b, const int64_t* caps, int32_t rounds, const uint64_t* seeds,
+                                         int32_t* labels, const lp_config* cfg, lp_cluster_stats* stats,
+                                         void* stream) {
+  clear_error();
+  if (!b || !b->nbatch) return LP_EINVAL;
+  return cluster_impl(b, 0, caps, rounds, 0, seeds, labels, nullptr, cfg, stats, (hipStream_t)stream);
+}
+
+extern "C" lp_status lp_batch_cluster(int32_t G, const lp_graph* const* gs, const int64_t* caps, int32_t rounds,
+                                      const uint64_t* seeds, int32_t* const* labels_each, void* stream) {
+  clear_error();
+  if (G < 1 || !gs || !caps || !seeds || !labels_each) return LP_EINVAL;
+  for (int32_t i = 0; i < G; ++i)
+    if (!gs[i] || (gs[i]->n > 0 && !labels_each[i])) return LP_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  lp_graph* b = nullptr;
+  LP_CHECK(lp_batch_create(G, gs, stream, &b));
+  int32_t** outs = nullptr;
+  lp_status st = LP_OK;
+  if (hipMalloc((void**)&outs, G * sizeof(int32_t*)) != hipSuccess) st = LP_ENOMEM;
+  if (!st && hipMemcpyAsync(outs, labels_each, G * sizeof(int32_t*), hipMemcpyHostToDevice, s) != hipSuccess)
+    st = LP_EDEVICE;
+  if (!st) st = cluster_impl(b, 0, caps, rounds, 0, seeds, nullptr, outs, nullptr, nullptr, s);
+  if (!st && hipStreamSynchronize(s) != hipSuccess) st = LP_EDEVICE;
+  (void)hipFree(outs);
+  lp_graph_free(b);
+  return st;
 }
 
 extern "C" lp_status lp_cluster(const lp_graph* g, int64_t cap, int32_t rounds, uint64_t seed, int32_t* labels,

@@ -307,6 +307,10 @@ lp_status dev_copy(T** dst, const T* src, size_t count, hipStream_t s, size_t pa
 
 lp_status compute_degrees(const lp_graph* g, int32_t* deg, hipStream_t s) {
   if (g->n == 0) return LP_OK;
+  if (g->deg) {
+    LP_CHECK_HIP(hipMemcpyAsync(deg, g->deg, (size_t)g->n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    return LP_OK;
+  }
   if (g->compressed)
     hipLaunchKernelGGL(k_degrees_comp, dim3(grid_for(g->n, 256, 65536)), dim3(256), 0, s, g->view(), deg);
   else
@@ -421,6 +425,7 @@ extern "C" lp_status lp_graph_from_csr(int32_t n, const uint64_t* xadj, const in
 extern "C" lp_status lp_graph_export(const lp_graph* g, uint64_t* offs_dev, uint8_t* bytes_dev, void* stream) {
   clear_error();
   if (!g || !g->compressed || !offs_dev || (!bytes_dev && g->nbytes)) return LP_EINVAL;
+  if (g->nbatch) return LP_EUNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   LP_CHECK_HIP(hipMemcpyAsync(offs_dev, g->offs, ((size_t)g->n + 1) * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
   if (g->nbytes) LP_CHECK_HIP(hipMemcpyAsync(bytes_dev, g->bytes, g->nbytes, hipMemcpyDeviceToDevice, s));
@@ -431,6 +436,7 @@ extern "C" lp_status lp_decompress(const lp_graph* g, uint64_t* xadj, int32_t* a
                                    int32_t* vwgt, void* stream) {
   clear_error();
   if (!g || !xadj || (!adjncy && g->two_m)) return LP_EINVAL;
+  if (g->nbatch) return LP_EUNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   Scratch sc(s);
   if (vwgt) {
@@ -496,6 +502,9 @@ extern "C" void lp_graph_free(lp_graph* g) {
   (void)hipFree(g->adjncy);
   (void)hipFree(g->adjwgt);
   (void)hipFree(g->vwgt);
+  (void)hipFree(g->gid);
+  (void)hipFree(g->gbase);
+  (void)hipFree(g->deg);
   delete g;
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "lp_device.h"
 #include "prims.h"
 
@@ -26,6 +28,12 @@ struct lp_graph {
   int32_t* adjncy = nullptr;  // two_m
   int32_t* adjwgt = nullptr;  // two_m or null
   int32_t* vwgt = nullptr;    // n or null (unit)
+  // disjoint union of several graphs (lp_batch_create); nbatch == 0 otherwise
+  int32_t nbatch = 0;
+  int32_t* gid = nullptr;     // n: graph of each vertex
+  int32_t* gbase = nullptr;   // nbatch + 1: first vertex of each graph
+  int32_t* deg = nullptr;     // n: degrees (first-edge headers restart per graph)
+  std::vector<int32_t> vbase; // host copy of gbase
 
   lp::GraphView view() const {
     lp::GraphView v;
