@@ -70,6 +70,122 @@ def phase_bytes(st, phase: str, n_per_bucket, proposals) -> float:
     return 0.0
 
 
+def bench_batch(args) -> dict:
+    """Many uneven graphs: one batched launch sequence vs sequential plain calls."""
+    import math
+
+    import torch
+
+    import paper_2410_19119_amd as lp
+    import synth
+    from paper_2410_19119_amd import autotune
+
+    count = args.batch_graphs
+    t0 = time.time()
+    recipe = synth.batch_recipe(count, 1000)
+    gs = [synth.batch_graph(*r) for r in recipe]
+    tot_n = sum(g.n for g in gs)
+    tot_m = sum(g.two_m for g in gs)
+    log(f"[batch] generated {count} graphs: n={tot_n} 2m={tot_m} in {time.time() - t0:.1f}s")
+    hs = [lp.lp_compress(g.n, g.xadj.view(np.int64), g.adjncy) for g in gs]
+    caps = [3 * max(1, math.ceil(g.two_m / max(g.n, 1))) for g in gs]
+    seeds = [r[3] for r in recipe]
+    rounds = args.rounds
+    out_plain = [torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda") for g in gs]
+    out_batch = [torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda") for g in gs]
+    union_lab = torch.empty(max(tot_n, 1), dtype=torch.int32, device="cuda")
+
+    def plain():
+        for i, h in enumerate(hs):
+            lp.lp_cluster(h, caps[i], rounds, seeds[i], labels=out_plain[i])
+
+    def batched():
+        lp.lp_batch_cluster(hs, caps, rounds, seeds, labels=out_batch)
+
+    b = lp.lp_batch_create(hs)
+    cfg = {}
+
+    def resident():
+        lp.lp_batch_cluster_ex(b, caps, rounds, seeds, labels=union_lab, config=cfg or None)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        return sum(ts) / len(ts)
+
+    t_plain = timed(plain, args.batch_reps)
+    log(f"[batch] plain: {t_plain * 1e3:.1f} ms for {count} graphs")
+    t_batch = timed(batched, args.batch_reps)
+    log(f"[batch] batched (union built per call): {t_batch * 1e3:.1f} ms")
+    t_res = timed(resident, args.batch_reps)
+    log(f"[batch] batched (resident union, default knobs): {t_res * 1e3:.1f} ms")
+    best, table = autotune.tune_batch(lp, b, caps, seeds, rounds=1)
+    cfg.update(best)
+    t_tuned = timed(resident, args.batch_reps)
+    log(f"[batch] batched (resident union, autotuned {best}): {t_tuned * 1e3:.1f} ms")
+    same = all(torch.equal(out_plain[i][: g.n], out_batch[i][: g.n]) for i, g in enumerate(gs))
+    parts = b.split(union_lab)
+    same = same and all(torch.equal(out_plain[i][: g.n], parts[i]) for i, g in enumerate(gs))
+    log(f"[batch] identical labels batched vs plain: {same}")
+    return {
+        "graphs": count, "n": tot_n, "two_m": tot_m, "rounds": rounds,
+        "plain_graphs_per_s": count / t_plain,
+        "batched_graphs_per_s": count / t_batch,
+        "resident_graphs_per_s": count / t_res,
+        "autotuned_graphs_per_s": count / t_tuned,
+        "autotuned_knobs": best,
+        "speedup_vs_plain": t_plain / t_batch,
+        "identical_labels": bool(same),
+        "plain_ms": t_plain * 1e3, "batched_ms": t_batch * 1e3, "resident_ms": t_res * 1e3,
+        "autotuned_ms": t_tuned * 1e3,
+    }
+
+
+def bench_serve(args) -> dict:
+    """Poisson request stream of coarsening jobs on resident compressed graphs:
+    continuous batching vs sequential plain calls, same arrival trace."""
+    import torch
+
+    import paper_2410_19119_amd as lp
+    import synth
+    from paper_2410_19119_amd import serve
+
+    t0 = time.time()
+    recipe = synth.serve_pool(args.serve_pool, 5000)
+    gs = [synth.batch_graph(*r) for r in recipe]
+    pool = [lp.lp_compress(g.n, g.xadj.view(np.int64), g.adjncy) for g in gs]
+    torch.cuda.synchronize()
+    log(f"[serve] pool of {len(pool)} graphs, 2m from {min(g.two_m for g in gs)} to "
+        f"{max(g.two_m for g in gs)} (total {sum(g.two_m for g in gs)}) in {time.time() - t0:.1f}s")
+    del gs
+    # warm-up: one job of each graph
+    for h in pool:
+        lp.coarsen(h, seed=1)
+    torch.cuda.synchronize()
+    rates = [float(r) for r in args.serve_rates.split(",")]
+    out = {"pool": len(pool), "requests_per_rate": args.serve_requests, "budget_bytes": 200 * 10**9, "rates": {}}
+    for rate in rates:
+        reqs = serve.requests(synth.serve_trace(rate, args.serve_requests, len(pool), seed=7))
+        seq = serve.summarize(serve.run_sequential(pool, reqs))
+        srv_obj = serve.Server(pool, budget_bytes=200 * 10**9, max_active=args.serve_slots)
+        res = srv_obj.run(reqs)
+        srv = serve.summarize(res)
+        srv["peak_active"] = srv_obj.peak_active
+        srv["steps"] = srv_obj.steps
+        out["rates"][str(rate)] = {"sequential": seq, "served": srv}
+        log(f"[serve] rate {rate}/s: sequential {seq['throughput_per_s']:.1f} jobs/s p50 {seq['p50_ms']:.1f} ms "
+            f"p99 {seq['p99_ms']:.1f} ms | served {srv['throughput_per_s']:.1f} jobs/s p50 {srv['p50_ms']:.1f} ms "
+            f"p99 {srv['p99_ms']:.1f} ms (peak {srv_obj.peak_active} active)")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +195,12 @@ def main() -> int:
     ap.add_argument("--rounds", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rounds", type=int, default=1, help="oracle rounds timed for the baseline")
+    ap.add_argument("--batch-graphs", type=int, default=512)
+    ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--serve-pool", type=int, default=24)
+    ap.add_argument("--serve-requests", type=int, default=100)
+    ap.add_argument("--serve-rates", default="10,30,100,300,1000")
+    ap.add_argument("--serve-slots", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a design "
@@ -89,6 +211,22 @@ def main() -> int:
     import paper_2410_19119_amd as lp
 
     torch.cuda.set_device(0)
+    if args.workload == "batch512":
+        res = bench_batch(args)
+        print(json.dumps({"metric": "graphs/s batched vs plain", "value": res["batched_graphs_per_s"],
+                          "unit": "graphs/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+                          "dtype": "int32", "config": {"workload": "batch of uneven RGG-2D / R-MAT graphs"},
+                          "batched": res}))
+        return 0
+    if args.workload == "serve":
+        res = bench_serve(args)
+        top = res["rates"][max(res["rates"], key=float)]
+        print(json.dumps({"metric": "coarsening jobs/s and p99 latency, served vs sequential",
+                          "value": top["served"]["throughput_per_s"], "unit": "jobs/s", "n_gpus": 1,
+                          "higher_is_better": True, "data": "synthetic", "dtype": "int32",
+                          "config": {"workload": "Poisson stream of coarsening jobs on resident RGG-2D / R-MAT"},
+                          "served": res}))
+        return 0
     t0 = time.time()
     g, cap, desc = workload(args.workload)
     log(f"[bench] generated {desc}: n={g.n} 2m={g.two_m} in {time.time() - t0:.1f}s")

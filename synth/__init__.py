@@ -220,3 +220,31 @@ def batch_graph(kind: str, n: int, param: int, seed: int) -> Graph:
         return rgg(2, n, rgg_radius(2, n, float(param)), seed, name=f"rgg2d-n{n}-s{seed}")
     scale = max(1, math.ceil(math.log2(n)))
     return rmat(scale, param * n, 0.57, 0.19, 0.19, seed, n_limit=n, name=f"rmat-n{n}-ef{param}-s{seed}")
+
+
+def serve_pool(count: int = 24, base_seed: int = 5000):
+    """Resident graphs of the serving workload: directed edge counts
+    log-uniform in [1e4, 1e8], RGG-2D (degree 8) or R-MAT (edge factor
+    8..16) by a fair coin; entries as in batch_recipe."""
+    out = []
+    for i in range(count):
+        s = base_seed + i
+        m2 = math.exp(math.log(1e4) + unit(s, 0) * (math.log(1e8) - math.log(1e4)))
+        if unit(s, 1) < 0.5:
+            out.append(("rgg2d", max(64, int(m2 / 8)), 8, s))
+        else:
+            ef = 8 + int(draw(s, 2) % 9)
+            out.append(("rmat", max(64, int(m2 / (2 * ef))), ef, s))
+    return out
+
+
+def serve_trace(rate: float, count: int, pool_size: int, seed: int = 7):
+    """Arrival trace of the serving workload: (arrival seconds, pool graph,
+    job seed) with exponential gaps at `rate` per second."""
+    t = 0.0
+    out = []
+    for i in range(count):
+        u = unit(seed, 3 * i)
+        t += -math.log(max(u, 1e-300)) / rate
+        out.append((t, int(draw(seed, 3 * i + 1) % pool_size), int(draw(seed, 3 * i + 2) % 1000003)))
+    return out
