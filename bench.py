@@ -169,7 +169,7 @@ def bench_serve(args) -> dict:
     for h in pool:
         lp.coarsen(h, seed=1)
     torch.cuda.synchronize()
-    rates = [float(r) for r in args.serve_rates.split(",")]
+    rates = [float(r) for r in (args.serve_rates or "10,30,100,300,1000").split(",")]
     out = {"pool": len(pool), "requests_per_rate": args.serve_requests, "budget_bytes": 200 * 10**9, "rates": {}}
     for rate in rates:
         reqs = serve.requests(synth.serve_trace(rate, args.serve_requests, len(pool), seed=7))
@@ -194,12 +194,15 @@ def main() -> int:
     ap.add_argument("--workload", default="rmat24")
     ap.add_argument("--rounds", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-rounds", type=int, default=1, help="oracle rounds timed for the baseline")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched and served comparisons")
+    ap.add_argument("--cpu-rounds", type=int, default=5, help="oracle rounds timed for the baseline")
     ap.add_argument("--batch-graphs", type=int, default=512)
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--serve-pool", type=int, default=24)
     ap.add_argument("--serve-requests", type=int, default=100)
-    ap.add_argument("--serve-rates", default="10,30,100,300,1000")
+    ap.add_argument("--serve-rates", default=None,
+                    help="comma-separated request rates (default: 10..1000 for --workload serve, "
+                         "100,1000 inside the default run)")
     ap.add_argument("--serve-slots", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -299,10 +302,20 @@ def main() -> int:
         t = time.perf_counter()
         _, ost = oracle.lp_cluster(g, cap, args.cpu_rounds, 1)
         dt = time.perf_counter() - t
-        cpu = {"value": g.two_m * args.cpu_rounds / dt, "unit": "edges/s", "cores": threads, "kind": "oracle",
-               "sample": f"oracle lp_cluster, first {args.cpu_rounds} round(s) over the full graph "
-                         f"({dt:.1f} s wall)"}
+        done = ost.rounds_run
+        cpu = {"value": g.two_m * done / dt, "unit": "edges/s", "cores": threads, "kind": "oracle",
+               "sample": f"oracle lp_cluster on the full graph, {done} round(s) ({dt:.1f} s wall, "
+                         f"rating + acceptance + apply, no contraction)"}
         log(f"[bench] cpu oracle: {args.cpu_rounds} round(s) in {dt:.1f}s with {threads} threads")
+
+    forms = {}
+    if not args.no_forms:
+        b = bench_batch(args)
+        forms["batched"] = {k: b[k] for k in ("graphs", "two_m", "plain_graphs_per_s", "batched_graphs_per_s",
+                                              "autotuned_graphs_per_s", "speedup_vs_plain", "identical_labels")}
+        if args.serve_rates is None:
+            args.serve_rates = "100,1000"
+        forms["served"] = bench_serve(args)["rates"]
 
     out = {
         "metric": "LP-round edges/s",
@@ -328,6 +341,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    out.update(forms)
     print(json.dumps(out))
     return 0
 

@@ -91,23 +91,52 @@ __global__ void k_cclass(const unsigned long long* dsum, const unsigned long lon
   }
 }
 
-// Appends every coarse vertex of class 1..4 to its class list; one atomic
-// per wavefront and class.
-__global__ void k_class_list(const uint8_t* cls, int32_t nc, uint32_t* counters, int32_t* lists, int64_t stride) {
-  const int64_t step = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nc; base += step) {
-    const int64_t a = base + threadIdx.x;
-    const int c = a < nc ? cls[a] : 0;
+// Appends every coarse vertex of class 1..4 to its class list: a workgroup
+// ranks 2048 vertices per step with wavefront ballots and takes one global
+// atomic per class per step.
+__global__ __launch_bounds__(256) void k_class_list(const uint8_t* cls, int32_t nc, uint32_t* counters, int32_t* lists,
+                                                    int64_t stride) {
+  constexpr int kItems = 8;
+  __shared__ uint32_t wcnt[4][4];  // [wave][class - 1], then exclusive offsets
+  __shared__ uint32_t gbase[4];
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  for (int64_t blk = (int64_t)blockIdx.x * 256 * kItems; blk < nc; blk += (int64_t)gridDim.x * 256 * kItems) {
+    int c[kItems];
+    uint32_t pos[kItems];
+    uint32_t run[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int k = 1; k <= 4; ++k) {
-      const uint64_t m = __ballot(c == k);
-      if (!m) continue;
-      const int leader = __ffsll((long long)m) - 1;
-      uint32_t b = 0;
-      if (lane_id() == leader) b = atomicAdd(&counters[k], (uint32_t)__popcll(m));
-      b = __shfl(b, leader, kWave);
-      if (c == k) lists[(int64_t)(k - 1) * stride + b + __popcll(m & lanemask_lt())] = (int32_t)a;
+    for (int i = 0; i < kItems; ++i) {
+      const int64_t a = blk + (int64_t)i * 256 + threadIdx.x;
+      c[i] = a < nc ? cls[a] : 0;
+      pos[i] = 0;
+#pragma unroll
+      for (int k = 1; k <= 4; ++k) {
+        const uint64_t m = __ballot(c[i] == k);
+        if (c[i] == k) pos[i] = run[k - 1] + (uint32_t)__popcll(m & lanemask_lt());
+        run[k - 1] += (uint32_t)__popcll(m);
+      }
     }
+    if (lane == 0)
+      for (int k = 0; k < 4; ++k) wcnt[w][k] = run[k];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+      const int k = threadIdx.x;
+      uint32_t tot = 0;
+      for (int v = 0; v < 4; ++v) {
+        const uint32_t x = wcnt[v][k];
+        wcnt[v][k] = tot;
+        tot += x;
+      }
+      gbase[k] = tot ? atomicAdd(&counters[k + 1], tot) : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+      if (c[i] == 0) continue;
+      const int k = c[i] - 1;
+      lists[(int64_t)k * stride + gbase[k] + wcnt[w][k] + pos[i]] = (int32_t)(blk + (int64_t)i * 256 + threadIdx.x);
+    }
+    __syncthreads();
   }
 }
 
@@ -265,15 +294,24 @@ __device__ __forceinline__ void lds_bitonic(int32_t* keys, int64_t* vals, uint32
 
 // Writes the table's entries to `out` sorted by key: every thread takes its
 // (strided) slots into registers, a prefix count compacts the entries to the
-// front of the table, which is then bitonic-sorted in LDS. Returns the entry
-// count. cap <= NT * SLOTS.
+// front of the table, and the k entries are sorted by a monotone bucket sort:
+// bucket = (key - min) * k / (max - min + 1), a prefix sum of the bucket
+// sizes, a scatter of (key, value) pairs packed into 64 bits behind the
+// entries, and an insertion sort inside every bucket. If a bucket holds more
+// than kBucketMax entries (very skewed keys), a bitonic sort of the front of
+// the table is used instead. Returns k. cap <= NT * SLOTS and the table never
+// holds more than cap / 2 entries, so the bucket counters (keys[k, 2k)) and
+// the packed pairs (vals[k, 2k)) fit behind the entries. aux: 4 LDS words.
+constexpr uint32_t kBucketMax = 16;
+
 template <int NT, int SLOTS>
 __device__ uint32_t compact_sort_write(int32_t* keys, int64_t* vals, uint32_t cap, Rec* out, uint32_t* err,
-                                       int32_t* scan_sm) {
+                                       int32_t* scan_sm, uint32_t* aux) {
   const int tid = group_tid<NT>();
   int32_t kk[SLOTS];
   int64_t vv[SLOTS];
   int32_t c = 0;
+  uint32_t kmin = 0xFFFFFFFFu, kmax = 0;
 #pragma unroll
   for (int i = 0; i < SLOTS; ++i) {
     const uint32_t q = (uint32_t)tid + (uint32_t)i * NT;
@@ -282,12 +320,25 @@ __device__ uint32_t compact_sort_write(int32_t* keys, int64_t* vals, uint32_t ca
     if (q < cap) {
       kk[i] = keys[q];
       vv[i] = vals[q];
-      c += kk[i] != kEmpty;
+      if (kk[i] != kEmpty) {
+        ++c;
+        kmin = min(kmin, (uint32_t)kk[i]);
+        kmax = max(kmax, (uint32_t)kk[i]);
+      }
     }
+  }
+  if (tid == 0) {
+    aux[0] = 0xFFFFFFFFu;
+    aux[1] = 0;
+    aux[2] = 0;
   }
   int32_t tot;
   int32_t o = block_incl_scan_add<NT, int32_t>(c, scan_sm, &tot) - c;
   group_sync<NT>();
+  if (c) {
+    atomicMin(&aux[0], kmin);
+    atomicMax(&aux[1], kmax);
+  }
 #pragma unroll
   for (int i = 0; i < SLOTS; ++i)
     if (kk[i] != kEmpty) {
@@ -296,11 +347,82 @@ __device__ uint32_t compact_sort_write(int32_t* keys, int64_t* vals, uint32_t ca
       ++o;
     }
   const uint32_t cnt = (uint32_t)tot;
-  uint32_t p2 = 1;
-  while (p2 < cnt) p2 <<= 1;
-  for (uint32_t q = cnt + tid; q < p2; q += NT) keys[q] = 0x7FFFFFFF;
+  uint32_t* bc = (uint32_t*)(keys + cnt);             // bucket counters, then cursors
+  unsigned long long* pk = (unsigned long long*)(vals + cnt);  // packed pairs in bucket order
+  for (uint32_t q = tid; q < cnt; q += NT) bc[q] = 0;
   group_sync<NT>();
-  lds_bitonic<NT>(keys, vals, p2);
+  const uint32_t lo = aux[0];
+  const uint64_t span = (uint64_t)aux[1] - lo + 1;
+  bool bitonic = cnt > 1 && cnt <= 64;
+  if (cnt > 64) {
+    for (uint32_t i = tid; i < cnt; i += NT) {
+      const uint32_t bk = (uint32_t)(((uint64_t)((uint32_t)keys[i] - lo) * cnt) / span);
+      const uint32_t sz = atomicAdd(&bc[bk], 1u) + 1u;
+      if (sz > kBucketMax) aux[2] = 1;
+    }
+    group_sync<NT>();
+    bitonic = aux[2] != 0;
+  }
+  if (bitonic) {
+    uint32_t p2 = 1;
+    while (p2 < cnt) p2 <<= 1;
+    for (uint32_t q = cnt + tid; q < p2; q += NT) keys[q] = 0x7FFFFFFF;
+    group_sync<NT>();
+    lds_bitonic<NT>(keys, vals, p2);
+    for (uint32_t i = tid; i < cnt; i += NT) {
+      const int64_t v = vals[i];
+      if (v > 0x7FFFFFFFll) atomicOr(err, kErrOverflow);
+      out[i] = Rec{keys[i], (int32_t)v};
+    }
+    group_sync<NT>();
+    return cnt;
+  }
+  if (cnt > 64) {
+    // exclusive offsets of the buckets (contiguous slice per thread)
+    const uint32_t per = (cnt + NT - 1) / NT;
+    const uint32_t b0 = min(cnt, (uint32_t)tid * per), b1 = min(cnt, b0 + per);
+    int32_t s = 0;
+    for (uint32_t q = b0; q < b1; ++q) s += (int32_t)bc[q];
+    int32_t t2;
+    int32_t e = block_incl_scan_add<NT, int32_t>(s, scan_sm, &t2) - s;
+    group_sync<NT>();
+    for (uint32_t q = b0; q < b1; ++q) {
+      const uint32_t v = bc[q];
+      bc[q] = (uint32_t)e;
+      e += (int32_t)v;
+    }
+    group_sync<NT>();
+    for (uint32_t i = tid; i < cnt; i += NT) {
+      const uint32_t key = (uint32_t)keys[i];
+      const uint32_t bk = (uint32_t)(((uint64_t)(key - lo) * cnt) / span);
+      const int64_t v = vals[i];
+      if (v > 0x7FFFFFFFll) atomicOr(err, kErrOverflow);
+      const uint32_t pos = atomicAdd(&bc[bk], 1u);
+      pk[pos] = ((unsigned long long)key << 32) | (uint32_t)(int32_t)v;
+    }
+    group_sync<NT>();
+    // bc[q] is now the end of bucket q; sort inside every bucket
+    for (uint32_t q = tid; q < cnt; q += NT) {
+      const uint32_t end = bc[q], beg = q ? bc[q - 1] : 0u;
+      for (uint32_t i = beg + 1; i < end; ++i) {
+        const unsigned long long x = pk[i];
+        uint32_t j = i;
+        while (j > beg && pk[j - 1] > x) {
+          pk[j] = pk[j - 1];
+          --j;
+        }
+        pk[j] = x;
+      }
+    }
+    group_sync<NT>();
+    for (uint32_t i = tid; i < cnt; i += NT) {
+      const unsigned long long x = pk[i];
+      out[i] = Rec{(int32_t)(x >> 32), (int32_t)(uint32_t)x};
+    }
+    group_sync<NT>();
+    return cnt;
+  }
+  // zero or one entry
   for (uint32_t i = tid; i < cnt; i += NT) {
     const int64_t v = vals[i];
     if (v > 0x7FFFFFFFll) atomicOr(err, kErrOverflow);
@@ -308,6 +430,28 @@ __device__ uint32_t compact_sort_write(int32_t* keys, int64_t* vals, uint32_t ca
   }
   group_sync<NT>();
   return cnt;
+}
+
+// Writes the nonzero entries of a direct array over coarse IDs [lo, lo +
+// width) in ID order; returns their number.
+template <int NT>
+__device__ uint32_t dense_write(const int64_t* vals, uint32_t width, uint64_t lo, Rec* out, uint32_t* err,
+                                int32_t* scan_sm) {
+  const int tid = group_tid<NT>();
+  const uint32_t per = (width + NT - 1) / NT;
+  const uint32_t q0 = min(width, (uint32_t)tid * per), q1 = min(width, q0 + per);
+  int32_t c = 0;
+  for (uint32_t q = q0; q < q1; ++q) c += vals[q] != 0;
+  int32_t tot;
+  int32_t o = block_incl_scan_add<NT, int32_t>(c, scan_sm, &tot) - c;
+  for (uint32_t q = q0; q < q1; ++q) {
+    const int64_t v = vals[q];
+    if (!v) continue;
+    if (v > 0x7FFFFFFFll) atomicOr(err, kErrOverflow);
+    out[o++] = Rec{(int32_t)(lo + q), (int32_t)v};
+  }
+  group_sync<NT>();
+  return (uint32_t)tot;
 }
 
 // ------------------------------------------------------------- light -----
@@ -326,6 +470,7 @@ struct LightSmem {
   int32_t scan[NT / kWave];
   uint32_t distinct;
   uint32_t overflow;
+  uint32_t aux[4];
 };
 
 // Light clusters: NT = 64, one cluster per wavefront (4 per workgroup);
@@ -373,7 +518,7 @@ __global__ __launch_bounds__(kLightThreads) void k_contract_light(AggArgs A, con
       group_sync<NT>();
       continue;
     }
-    const uint32_t k = compact_sort_write<NT, (NT == kWave ? 8 : 16)>(keys, vals, cap, r, A.err, sm.scan);
+    const uint32_t k = compact_sort_write<NT, (NT == kWave ? 8 : 16)>(keys, vals, cap, r, A.err, sm.scan, sm.aux);
     if (tid == 0) A.cdeg[a] = k;
     group_sync<NT>();
   }
@@ -491,6 +636,7 @@ struct ReduceSmem {
   int32_t scan[kReduceThreads / kWave];
   uint32_t distinct;
   uint32_t overflow;
+  uint32_t aux[4];
   uint32_t ra[kReduceThreads];    // per chunk of the current batch: first record of partition p
   int32_t pre[kReduceThreads + 1];  // exclusive prefix of the record counts
 };
@@ -527,9 +673,16 @@ __global__ __launch_bounds__(kReduceThreads) void k_heavy_reduce(AggArgs A, Heav
     uint64_t lo = lo_p, width = hi_p - lo_p;
     while (lo < hi_p) {
       const uint64_t hi = std::min<uint64_t>(hi_p, lo + width);
-      for (uint32_t q = tid; q < tcap; q += NT) {
-        keys[q] = kEmpty;
-        vals[q] = 0;
+      // a window at most kHeavyTable IDs wide is summed in a direct array
+      // indexed by b - lo: no hashing, no overflow, no sort
+      const bool dense = hi - lo <= kHeavyTable;
+      if (dense) {
+        for (uint32_t q = tid; q < (uint32_t)(hi - lo); q += NT) vals[q] = 0;
+      } else {
+        for (uint32_t q = tid; q < tcap; q += NT) {
+          keys[q] = kEmpty;
+          vals[q] = 0;
+        }
       }
       if (tid == 0) {
         sm.distinct = 0;
@@ -559,18 +712,23 @@ __global__ __launch_bounds__(kReduceThreads) void k_heavy_reduce(AggArgs A, Heav
             else hi_i = mid;
           }
           const Rec x = src[(uint64_t)(cb + lo_i) * kHeavyChunk + sm.ra[lo_i] + (uint32_t)(j - sm.pre[lo_i])];
-          if ((uint64_t)x.b >= lo && (uint64_t)x.b < hi)
-            tbl_add_guarded(keys, vals, mask, shift, x.b, (int64_t)x.w, limit, &sm.distinct, &sm.overflow);
+          if ((uint64_t)x.b >= lo && (uint64_t)x.b < hi) {
+            if (dense)
+              atomicAdd((unsigned long long*)&vals[(uint64_t)x.b - lo], (unsigned long long)(int64_t)x.w);
+            else
+              tbl_add_guarded(keys, vals, mask, shift, x.b, (int64_t)x.w, limit, &sm.distinct, &sm.overflow);
+          }
         }
         __syncthreads();
       }
-      if (sm.overflow && hi - lo > 1) {
-        width = std::max<uint64_t>(1, (hi - lo) / 2);
+      if (!dense && sm.overflow) {
+        width = std::max<uint64_t>(kHeavyTable, (hi - lo) / 2);
         __syncthreads();
         continue;
       }
-      const uint32_t k = compact_sort_write<NT, kHeavyTable / NT>(keys, vals, tcap, hv.out + obase + written, A.err,
-                                                                  sm.scan);
+      Rec* dst = hv.out + obase + written;
+      const uint32_t k = dense ? dense_write<NT>(vals, (uint32_t)(hi - lo), lo, dst, A.err, sm.scan)
+                               : compact_sort_write<NT, kHeavyTable / NT>(keys, vals, tcap, dst, A.err, sm.scan, sm.aux);
       written += k;
       lo = hi;
       width = hi_p - lo;  // try the rest of the partition in one window again
@@ -591,21 +749,44 @@ __global__ void k_heavy_cdeg(Heavy hv, int32_t H, uint64_t* cdeg) {
 
 // ---------------------------------------------------------- placement ----
 // Light clusters: their aggregated neighbourhood sits at the start of their
-// record region (wave per coarse vertex; heavy clusters are skipped).
+// record region (wave per coarse vertex; heavy clusters are skipped). Also
+// gathers the largest weighted degree and degree of the light coarse vertices
+// (mx[0], mx[1]).
 __global__ __launch_bounds__(256) void k_place_light(const uint64_t* cx, const uint64_t* rbase, const uint8_t* heavy,
-                                                     const Rec* rec, int32_t nc, int32_t* adjncy, int32_t* adjwgt) {
+                                                     const Rec* rec, int32_t nc, int32_t* adjncy, int32_t* adjwgt,
+                                                     unsigned long long* mx) {
+  __shared__ unsigned long long sa[4], sb[4];
   const int lane = lane_id();
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  unsigned long long mw = 0, md = 0;
   for (int64_t a = wid; a < nc; a += nw) {
     const uint64_t o = cx[a], d = cx[a + 1] - o;
     if (d == 0 || heavy[a]) continue;
     const Rec* r = rec + rbase[a];
+    int64_t sw = 0;
     for (uint64_t i = lane; i < d; i += kWave) {
       const Rec x = r[i];
       adjncy[o + i] = x.b;
       adjwgt[o + i] = x.w;
+      sw += x.w;
     }
+    sw = wave_reduce_add(sw);
+    mw = max(mw, (unsigned long long)sw);
+    md = max(md, (unsigned long long)d);
+  }
+  if (lane == 0) {
+    sa[threadIdx.x / kWave] = mw;
+    sb[threadIdx.x / kWave] = md;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < 4; ++i) {
+      mw = max(mw, sa[i]);
+      md = max(md, sb[i]);
+    }
+    if (mw) atomicMax(&mx[0], mw);
+    if (md) atomicMax(&mx[1], md);
   }
 }
 
@@ -615,9 +796,11 @@ __global__ void k_mark_heavy(const int32_t* hl, int32_t H, uint8_t* heavy) {
 }
 
 // Heavy clusters: task t of cluster h goes after the outputs of the
-// cluster's earlier partitions (wave per task).
+// cluster's earlier partitions (wave per task); the task's weight sum is
+// added to its cluster's (hsum).
 __global__ __launch_bounds__(256) void k_place_heavy(Heavy hv, int32_t ntasks, const uint64_t* tdeg_scan,
-                                                     const uint64_t* cx, int32_t* adjncy, int32_t* adjwgt) {
+                                                     const uint64_t* cx, int32_t* adjncy, int32_t* adjwgt,
+                                                     unsigned long long* hsum) {
   const int lane = lane_id();
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
@@ -626,11 +809,25 @@ __global__ __launch_bounds__(256) void k_place_heavy(Heavy hv, int32_t ntasks, c
     const int32_t a = hv.clusters[h];
     const uint64_t dst = cx[a] + (tdeg_scan[t] - tdeg_scan[hv.tbase[h]]);
     const uint64_t src = hv.tcnt[t], d = hv.tdeg[t];
+    int64_t sw = 0;
     for (uint64_t j = lane; j < d; j += kWave) {
       const Rec x = hv.out[src + j];
       adjncy[dst + j] = x.b;
       adjwgt[dst + j] = x.w;
+      sw += x.w;
     }
+    sw = wave_reduce_add(sw);
+    if (lane == 0 && sw) atomicAdd(&hsum[h], (unsigned long long)sw);
+  }
+}
+
+// Largest weighted degree and degree over the heavy coarse vertices.
+__global__ void k_heavy_max(Heavy hv, int32_t H, const unsigned long long* hsum, const uint64_t* cx,
+                            unsigned long long* mx) {
+  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < H; h += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t a = hv.clusters[h];
+    atomicMax(&mx[0], hsum[h]);
+    atomicMax(&mx[1], (unsigned long long)(cx[a + 1] - cx[a]));
   }
 }
 
@@ -801,6 +998,8 @@ extern "C" lp_status lp_contract(const lp_graph* g, const int32_t* labels, int32
   lp_graph* cg = new lp_graph();
   (void)hipGetDevice(&cg->device);
   lp_status st = LP_OK;
+  unsigned long long* mx = nullptr;
+  unsigned long long mxh[2] = {0, 0};
   do {
     if (n == 0) {
       if (hipMalloc((void**)&cg->xadj, sizeof(uint64_t)) != hipSuccess) { st = LP_ENOMEM; break; }
@@ -850,7 +1049,7 @@ extern "C" lp_status lp_contract(const lp_graph* g, const int32_t* labels, int32
     hipLaunchKernelGGL(k_reserve, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, map, deg, n, cursor, voff);
     hipLaunchKernelGGL(k_cclass, dim3(grid_for(nc, 256, 65536)), dim3(256), 0, s, dsum, vw, nc, tcap, cls, cg->vwgt,
                        &ctl->err);
-    hipLaunchKernelGGL(k_class_list, dim3(grid_for(nc, 256, 65536)), dim3(256), 0, s, cls, nc, ctl->ccount, lists,
+    hipLaunchKernelGGL(k_class_list, dim3(grid_for(nc, 256 * 8, 65536)), dim3(256), 0, s, cls, nc, ctl->ccount, lists,
                        (int64_t)nc);
     st = last_error();
     if (st) break;
@@ -927,13 +1126,24 @@ extern "C" lp_status lp_contract(const lp_graph* g, const int32_t* labels, int32
     cg->weighted = 1;
     if (hipMalloc((void**)&cg->adjncy, (h.two_mc ? h.two_mc : 1) * sizeof(int32_t)) != hipSuccess ||
         hipMalloc((void**)&cg->adjwgt, (h.two_mc ? h.two_mc : 1) * sizeof(int32_t)) != hipSuccess) { st = LP_ENOMEM; break; }
+    mx = sc.alloc<unsigned long long>(2);
+    unsigned long long* hsum = H > 0 ? sc.alloc<unsigned long long>(H) : nullptr;
+    if (!mx || (H > 0 && !hsum)) { st = LP_ENOMEM; break; }
+    if (hipMemsetAsync(mx, 0, 16, s) != hipSuccess ||
+        (H > 0 && hipMemsetAsync(hsum, 0, (size_t)H * sizeof(unsigned long long), s) != hipSuccess)) {
+      st = LP_EDEVICE;
+      break;
+    }
     hipLaunchKernelGGL(k_place_light, dim3(grid_for((int64_t)nc * kWave, 256, 65536)), dim3(256), 0, s, cg->xadj,
-                       rbase, heavy, rec, nc, cg->adjncy, cg->adjwgt);
-    if (T > 0)
+                       rbase, heavy, rec, nc, cg->adjncy, cg->adjwgt, mx);
+    if (T > 0) {
       hipLaunchKernelGGL(k_place_heavy, dim3(grid_for((int64_t)T * kWave, 256, 65536)), dim3(256), 0, s, hv, T, tscan,
-                         cg->xadj, cg->adjncy, cg->adjwgt);
+                         cg->xadj, cg->adjncy, cg->adjwgt, hsum);
+      hipLaunchKernelGGL(k_heavy_max, dim3(grid_for(H, 256, 4096)), dim3(256), 0, s, hv, H, hsum, cg->xadj, mx);
+    }
     st = last_error();
     if (st) break;
+    if (hipMemcpyAsync(mxh, mx, 16, hipMemcpyDeviceToHost, s) != hipSuccess) { st = LP_EDEVICE; break; }
   } while (0);
   if (st == LP_OK && hipStreamSynchronize(s) != hipSuccess) st = LP_EDEVICE;
   if (st != LP_OK) {
@@ -941,25 +1151,9 @@ extern "C" lp_status lp_contract(const lp_graph* g, const int32_t* labels, int32
     return st;
   }
   // coarse metadata used by later calls: total weight, degree maxima
-  {
-    Scratch sc2(s);
-    unsigned long long* mx = sc2.alloc<unsigned long long>(2);
-    if (!mx) {
-      lp_graph_free(cg);
-      return LP_ENOMEM;
-    }
-    unsigned long long hm[2] = {0, 0};
-    if (hipMemsetAsync(mx, 0, 16, s) == hipSuccess && cg->n > 0)
-      hipLaunchKernelGGL(k_wdeg, dim3(grid_for((int64_t)cg->n * kWave, 256, 4096)), dim3(256), 0, s, cg->xadj,
-                         cg->adjwgt, cg->n, mx, mx + 1);
-    if (hipMemcpyAsync(hm, mx, 16, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
-      lp_graph_free(cg);
-      return LP_EDEVICE;
-    }
-    cg->max_wdeg = (int64_t)hm[0];
-    cg->max_deg = (int64_t)hm[1];
-    cg->total_vwgt = g->total_vwgt;
-  }
+  cg->max_wdeg = (int64_t)mxh[0];
+  cg->max_deg = (int64_t)mxh[1];
+  cg->total_vwgt = g->total_vwgt;
   *coarse_out = cg;
   return LP_OK;
 }
