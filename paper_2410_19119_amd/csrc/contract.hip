@@ -38,8 +38,9 @@ constexpr uint32_t kClassBlockS = 1024;  // records per workgroup-cluster, small
 constexpr uint32_t kClassBlockL = 4096;  // records per workgroup-cluster, large table
 constexpr uint32_t kHeavyChunk = 4096;   // records per partitioning chunk
 constexpr uint32_t kHeavyTable = 4096;   // LDS entries of a heavy (cluster, partition) task
-constexpr uint32_t kHeavyPart = 1024;    // expected distinct coarse IDs per heavy partition
-constexpr uint32_t kMaxHeavyParts = 1024;
+constexpr uint32_t kHeavyPart = 1024;    // records per heavy partition (target)
+constexpr uint32_t kMaxHeavyParts = 4096;
+constexpr uint32_t kHeavySample = 2048;  // records sampled per heavy cluster for the partition splitters
 constexpr int kLightThreads = 256;
 constexpr int kReduceThreads = 256;
 
@@ -267,51 +268,77 @@ __device__ __forceinline__ void tbl_add_guarded(int32_t* keys, int64_t* vals, ui
   }
 }
 
-// Bitonic sort of (keys, vals)[0..cnt) by key in LDS; cnt is a power of two.
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long x, int m) {
+  const uint32_t lo = __shfl_xor((uint32_t)x, m, kWave), hi = __shfl_xor((uint32_t)(x >> 32), m, kWave);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Sorts k distinct 64-bit values a[0..k) ascending in LDS: every wavefront
+// sorts runs of 64 in registers (bitonic network over lane shuffles), then
+// runs are merged pairwise, each element placed at its run position plus its
+// rank in the partner run (binary search), alternating between a and b.
+// Returns the buffer that holds the result; b needs k entries.
 template <int NT>
-__device__ __forceinline__ void lds_bitonic(int32_t* keys, int64_t* vals, uint32_t cnt) {
-  const int tid = group_tid<NT>();
-  for (uint32_t k = 2; k <= cnt; k <<= 1) {
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t i = tid; i < cnt; i += NT) {
-        const uint32_t ixj = i ^ j;
-        if (ixj > i) {
-          const bool up = (i & k) == 0;
-          const int32_t ki = keys[i], kj = keys[ixj];
-          if ((ki > kj) == up) {
-            keys[i] = kj;
-            keys[ixj] = ki;
-            const int64_t t = vals[i];
-            vals[i] = vals[ixj];
-            vals[ixj] = t;
-          }
-        }
+__device__ unsigned long long* lds_sort_u64(unsigned long long* a, unsigned long long* b, uint32_t k) {
+  constexpr int NW = NT / kWave;
+  const int lane = lane_id();
+  const int w = NT == kWave ? 0 : (int)(threadIdx.x / kWave);
+  for (uint32_t c = (uint32_t)w * kWave; c < k; c += NW * kWave) {
+    const uint32_t i = c + lane;
+    unsigned long long x = i < k ? a[i] : ~0ull;
+#pragma unroll
+    for (int size = 2; size <= kWave; size <<= 1) {
+#pragma unroll
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        const unsigned long long y = shfl_xor_u64(x, stride);
+        const bool up = (lane & size) == 0;
+        const bool lower = (lane & stride) == 0;
+        x = (lower == up) ? (x < y ? x : y) : (x < y ? y : x);
       }
-      group_sync<NT>();
     }
+    if (i < k) a[i] = x;
   }
+  group_sync<NT>();
+  const int tid = group_tid<NT>();
+  unsigned long long *src = a, *dst = b;
+  for (uint32_t R = kWave; R < k; R <<= 1) {
+    for (uint32_t i = tid; i < k; i += NT) {
+      const unsigned long long x = src[i];
+      const uint32_t r = i / R, p = i - r * R;
+      const uint32_t ps = (r ^ 1u) * R;
+      uint32_t rank = 0;
+      if (ps < k) {
+        uint32_t lo = 0, hi = min(R, k - ps);
+        const unsigned long long* q = src + ps;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (q[mid] < x) lo = mid + 1;
+          else hi = mid;
+        }
+        rank = lo;
+      }
+      dst[(r & ~1u) * R + p + rank] = x;
+    }
+    group_sync<NT>();
+    unsigned long long* t = src;
+    src = dst;
+    dst = t;
+  }
+  return src;
 }
 
 // Writes the table's entries to `out` sorted by key: every thread takes its
 // (strided) slots into registers, a prefix count compacts the entries to the
-// front of the table, and the k entries are sorted by a monotone bucket sort:
-// bucket = (key - min) * k / (max - min + 1), a prefix sum of the bucket
-// sizes, a scatter of (key, value) pairs packed into 64 bits behind the
-// entries, and an insertion sort inside every bucket. If a bucket holds more
-// than kBucketMax entries (very skewed keys), a bitonic sort of the front of
-// the table is used instead. Returns k. cap <= NT * SLOTS and the table never
-// holds more than cap / 2 entries, so the bucket counters (keys[k, 2k)) and
-// the packed pairs (vals[k, 2k)) fit behind the entries. aux: 4 LDS words.
-constexpr uint32_t kBucketMax = 16;
-
+// front of the table as (key << 32 | value) pairs, which lds_sort_u64 sorts.
+// Returns the entry count. cap <= NT * SLOTS and the table never holds more
+// than cap / 2 entries, so the second sort buffer fits behind the entries.
 template <int NT, int SLOTS>
 __device__ uint32_t compact_sort_write(int32_t* keys, int64_t* vals, uint32_t cap, Rec* out, uint32_t* err,
-                                       int32_t* scan_sm, uint32_t* aux) {
+                                       int32_t* scan_sm) {
   const int tid = group_tid<NT>();
   int32_t kk[SLOTS];
   int64_t vv[SLOTS];
   int32_t c = 0;
-  uint32_t kmin = 0xFFFFFFFFu, kmax = 0;
 #pragma unroll
   for (int i = 0; i < SLOTS; ++i) {
     const uint32_t q = (uint32_t)tid + (uint32_t)i * NT;
@@ -320,113 +347,25 @@ __device__ uint32_t compact_sort_write(int32_t* keys, int64_t* vals, uint32_t ca
     if (q < cap) {
       kk[i] = keys[q];
       vv[i] = vals[q];
-      if (kk[i] != kEmpty) {
-        ++c;
-        kmin = min(kmin, (uint32_t)kk[i]);
-        kmax = max(kmax, (uint32_t)kk[i]);
-      }
+      c += kk[i] != kEmpty;
     }
-  }
-  if (tid == 0) {
-    aux[0] = 0xFFFFFFFFu;
-    aux[1] = 0;
-    aux[2] = 0;
   }
   int32_t tot;
   int32_t o = block_incl_scan_add<NT, int32_t>(c, scan_sm, &tot) - c;
   group_sync<NT>();
-  if (c) {
-    atomicMin(&aux[0], kmin);
-    atomicMax(&aux[1], kmax);
-  }
+  unsigned long long* pk = (unsigned long long*)vals;
 #pragma unroll
   for (int i = 0; i < SLOTS; ++i)
     if (kk[i] != kEmpty) {
-      keys[o] = kk[i];
-      vals[o] = vv[i];
-      ++o;
+      if (vv[i] > 0x7FFFFFFFll) atomicOr(err, kErrOverflow);
+      pk[o++] = ((unsigned long long)(uint32_t)kk[i] << 32) | (uint32_t)(int32_t)vv[i];
     }
   const uint32_t cnt = (uint32_t)tot;
-  uint32_t* bc = (uint32_t*)(keys + cnt);             // bucket counters, then cursors
-  unsigned long long* pk = (unsigned long long*)(vals + cnt);  // packed pairs in bucket order
-  for (uint32_t q = tid; q < cnt; q += NT) bc[q] = 0;
   group_sync<NT>();
-  const uint32_t lo = aux[0];
-  const uint64_t span = (uint64_t)aux[1] - lo + 1;
-  bool bitonic = cnt > 1 && cnt <= 64;
-  if (cnt > 64) {
-    for (uint32_t i = tid; i < cnt; i += NT) {
-      const uint32_t bk = (uint32_t)(((uint64_t)((uint32_t)keys[i] - lo) * cnt) / span);
-      const uint32_t sz = atomicAdd(&bc[bk], 1u) + 1u;
-      if (sz > kBucketMax) aux[2] = 1;
-    }
-    group_sync<NT>();
-    bitonic = aux[2] != 0;
-  }
-  if (bitonic) {
-    uint32_t p2 = 1;
-    while (p2 < cnt) p2 <<= 1;
-    for (uint32_t q = cnt + tid; q < p2; q += NT) keys[q] = 0x7FFFFFFF;
-    group_sync<NT>();
-    lds_bitonic<NT>(keys, vals, p2);
-    for (uint32_t i = tid; i < cnt; i += NT) {
-      const int64_t v = vals[i];
-      if (v > 0x7FFFFFFFll) atomicOr(err, kErrOverflow);
-      out[i] = Rec{keys[i], (int32_t)v};
-    }
-    group_sync<NT>();
-    return cnt;
-  }
-  if (cnt > 64) {
-    // exclusive offsets of the buckets (contiguous slice per thread)
-    const uint32_t per = (cnt + NT - 1) / NT;
-    const uint32_t b0 = min(cnt, (uint32_t)tid * per), b1 = min(cnt, b0 + per);
-    int32_t s = 0;
-    for (uint32_t q = b0; q < b1; ++q) s += (int32_t)bc[q];
-    int32_t t2;
-    int32_t e = block_incl_scan_add<NT, int32_t>(s, scan_sm, &t2) - s;
-    group_sync<NT>();
-    for (uint32_t q = b0; q < b1; ++q) {
-      const uint32_t v = bc[q];
-      bc[q] = (uint32_t)e;
-      e += (int32_t)v;
-    }
-    group_sync<NT>();
-    for (uint32_t i = tid; i < cnt; i += NT) {
-      const uint32_t key = (uint32_t)keys[i];
-      const uint32_t bk = (uint32_t)(((uint64_t)(key - lo) * cnt) / span);
-      const int64_t v = vals[i];
-      if (v > 0x7FFFFFFFll) atomicOr(err, kErrOverflow);
-      const uint32_t pos = atomicAdd(&bc[bk], 1u);
-      pk[pos] = ((unsigned long long)key << 32) | (uint32_t)(int32_t)v;
-    }
-    group_sync<NT>();
-    // bc[q] is now the end of bucket q; sort inside every bucket
-    for (uint32_t q = tid; q < cnt; q += NT) {
-      const uint32_t end = bc[q], beg = q ? bc[q - 1] : 0u;
-      for (uint32_t i = beg + 1; i < end; ++i) {
-        const unsigned long long x = pk[i];
-        uint32_t j = i;
-        while (j > beg && pk[j - 1] > x) {
-          pk[j] = pk[j - 1];
-          --j;
-        }
-        pk[j] = x;
-      }
-    }
-    group_sync<NT>();
-    for (uint32_t i = tid; i < cnt; i += NT) {
-      const unsigned long long x = pk[i];
-      out[i] = Rec{(int32_t)(x >> 32), (int32_t)(uint32_t)x};
-    }
-    group_sync<NT>();
-    return cnt;
-  }
-  // zero or one entry
+  const unsigned long long* sorted = lds_sort_u64<NT>(pk, pk + cnt, cnt);
   for (uint32_t i = tid; i < cnt; i += NT) {
-    const int64_t v = vals[i];
-    if (v > 0x7FFFFFFFll) atomicOr(err, kErrOverflow);
-    out[i] = Rec{keys[i], (int32_t)v};
+    const unsigned long long x = sorted[i];
+    out[i] = Rec{(int32_t)(x >> 32), (int32_t)(uint32_t)x};
   }
   group_sync<NT>();
   return cnt;
@@ -470,7 +409,6 @@ struct LightSmem {
   int32_t scan[NT / kWave];
   uint32_t distinct;
   uint32_t overflow;
-  uint32_t aux[4];
 };
 
 // Light clusters: NT = 64, one cluster per wavefront (4 per workgroup);
@@ -518,7 +456,7 @@ __global__ __launch_bounds__(kLightThreads) void k_contract_light(AggArgs A, con
       group_sync<NT>();
       continue;
     }
-    const uint32_t k = compact_sort_write<NT, (NT == kWave ? 8 : 16)>(keys, vals, cap, r, A.err, sm.scan, sm.aux);
+    const uint32_t k = compact_sort_write<NT, (NT == kWave ? 8 : 16)>(keys, vals, cap, r, A.err, sm.scan);
     if (tid == 0) A.cdeg[a] = k;
     group_sync<NT>();
   }
@@ -538,6 +476,7 @@ struct Heavy {
   uint64_t* tcnt;           // records per task, then (scanned) staging base
   Rec* out;                 // heavy staging
   uint64_t* tdeg;           // distinct coarse neighbours per task
+  int32_t* bnd;             // P + 1 coarse-ID boundaries per heavy cluster (at tbase[h] + h)
 };
 
 __global__ void k_heavy_meta(const int32_t* hl, int32_t H, const unsigned long long* dsum, int32_t nc, int32_t* parts,
@@ -545,9 +484,7 @@ __global__ void k_heavy_meta(const int32_t* hl, int32_t H, const unsigned long l
   for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < H; h += (int64_t)gridDim.x * blockDim.x) {
     const int32_t a = hl[h];
     const uint64_t d = dsum[a];
-    const uint64_t distinct = std::min<uint64_t>(d, (uint64_t)nc - 1);
-    const uint64_t part = std::max<uint64_t>(kHeavyPart, (distinct + kMaxHeavyParts - 1) / kMaxHeavyParts);
-    const uint32_t P = (uint32_t)std::max<uint64_t>(1, (distinct + part - 1) / part);
+    const uint32_t P = (uint32_t)std::min<uint64_t>(kMaxHeavyParts, std::max<uint64_t>(1, (d + kHeavyPart - 1) / kHeavyPart));
     const uint32_t nch = (uint32_t)((d + kHeavyChunk - 1) / kHeavyChunk);
     parts[h] = (int32_t)P;
     pcount[h] = P;
@@ -564,15 +501,58 @@ __global__ void k_heavy_lists(int32_t H, const int32_t* parts, const uint32_t* c
   }
 }
 
-// Range partition of coarse ID b among P parts of [0, nc).
-__device__ __forceinline__ uint32_t range_part(int32_t b, uint32_t P, int32_t nc) {
-  return (uint32_t)(((uint64_t)(uint32_t)b * P) / (uint64_t)nc);
+// Partition splitters of every heavy cluster: a sample of kHeavySample
+// records (evenly spaced over the cluster's records) is sorted and cut at P
+// quantiles, so the partitions hold about equal numbers of records however
+// skewed the coarse IDs are. Partition p holds IDs [bnd[p], bnd[p+1]).
+__global__ __launch_bounds__(256) void k_heavy_splitters(AggArgs A, Heavy hv, int32_t H) {
+  __shared__ unsigned long long sa[kHeavySample], sb[kHeavySample];
+  __shared__ int32_t scan[4];
+  for (int64_t h = blockIdx.x; h < H; h += gridDim.x) {
+    const int32_t a = hv.clusters[h];
+    const uint32_t P = (uint32_t)hv.parts[h];
+    const uint64_t d = A.dsum[a];
+    const uint32_t S = (uint32_t)std::min<uint64_t>(kHeavySample, d);
+    const Rec* r = A.rec + A.rbase[a];
+    int32_t* bnd = hv.bnd + hv.tbase[h] + h;
+    int32_t valid = 0;
+    for (uint32_t j = threadIdx.x; j < S; j += 256) {
+      const int32_t b = r[(uint64_t)j * d / S].b;
+      valid += b >= 0;
+      // intra-cluster records (b < 0) sort last and are not counted
+      sa[j] = ((unsigned long long)(b >= 0 ? (uint32_t)b : 0xFFFFFFFFu) << 32) | j;
+    }
+    int32_t V;
+    (void)block_incl_scan_add<256, int32_t>(valid, scan, &V);
+    __syncthreads();
+    const unsigned long long* srt = lds_sort_u64<256>(sa, sb, S);
+    for (uint32_t p = threadIdx.x; p <= P; p += 256) {
+      int32_t v;
+      if (p == 0) v = 0;
+      else if (p == P || V == 0) v = A.nc;
+      else v = (int32_t)(srt[(uint64_t)p * V / P] >> 32);
+      bnd[p] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// Partition of coarse ID b: the number of inner boundaries <= b.
+__device__ __forceinline__ uint32_t split_part(int32_t b, const int32_t* bnd, uint32_t P) {
+  uint32_t lo = 1, hi = P;  // first inner boundary > b
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (bnd[mid] <= b) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo - 1;
 }
 
 // One workgroup per chunk: group the chunk's records by partition
 // (records inside the cluster are dropped).
 __global__ __launch_bounds__(256) void k_heavy_partition(AggArgs A, Heavy hv, int32_t nchunks) {
   __shared__ uint32_t hist[kMaxHeavyParts];
+  __shared__ int32_t sbnd[kMaxHeavyParts + 1];
   for (int64_t ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {
     const int2 ch = hv.chunks[ci];
     const int32_t h = ch.x;
@@ -583,11 +563,13 @@ __global__ __launch_bounds__(256) void k_heavy_partition(AggArgs A, Heavy hv, in
     const Rec* src = A.rec + A.rbase[a] + off;
     Rec* dst = hv.rec2 + A.rbase[a] + off;
     uint32_t* tab = hv.ctab + hv.pbase[h] + (uint64_t)ch.y * (P + 1);
+    const int32_t* bnd = hv.bnd + hv.tbase[h] + h;
     for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) hist[j] = 0;
+    for (uint32_t j = threadIdx.x; j <= P; j += blockDim.x) sbnd[j] = bnd[j];
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
       const Rec x = src[i];
-      if (x.b >= 0) atomicAdd(&hist[range_part(x.b, P, A.nc)], 1u);
+      if (x.b >= 0) atomicAdd(&hist[split_part(x.b, sbnd, P)], 1u);
     }
     __syncthreads();
     if (threadIdx.x < kWave) {  // one wavefront scans the histogram
@@ -607,7 +589,7 @@ __global__ __launch_bounds__(256) void k_heavy_partition(AggArgs A, Heavy hv, in
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
       const Rec x = src[i];
-      if (x.b >= 0) dst[atomicAdd(&hist[range_part(x.b, P, A.nc)], 1u)] = x;
+      if (x.b >= 0) dst[atomicAdd(&hist[split_part(x.b, sbnd, P)], 1u)] = x;
     }
     __syncthreads();
   }
@@ -636,7 +618,6 @@ struct ReduceSmem {
   int32_t scan[kReduceThreads / kWave];
   uint32_t distinct;
   uint32_t overflow;
-  uint32_t aux[4];
   uint32_t ra[kReduceThreads];    // per chunk of the current batch: first record of partition p
   int32_t pre[kReduceThreads + 1];  // exclusive prefix of the record counts
 };
@@ -659,7 +640,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_heavy_reduce(AggArgs A, Heav
     const int32_t a = hv.clusters[h];
     const uint32_t p = (uint32_t)task.y;
     const uint32_t P = (uint32_t)hv.parts[h];
-    const uint64_t lo_p = ((uint64_t)p * nc + P - 1) / P, hi_p = ((uint64_t)(p + 1) * nc + P - 1) / P;
+    const int32_t* bnd = hv.bnd + hv.tbase[h] + h;
+    const uint64_t lo_p = (uint64_t)bnd[p], hi_p = (uint64_t)bnd[p + 1];
     const uint64_t obase = hv.tcnt[t];
     const uint64_t nrec = hv.tcnt[t + 1] - obase;
     const uint32_t logc =
@@ -728,7 +710,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_heavy_reduce(AggArgs A, Heav
       }
       Rec* dst = hv.out + obase + written;
       const uint32_t k = dense ? dense_write<NT>(vals, (uint32_t)(hi - lo), lo, dst, A.err, sm.scan)
-                               : compact_sort_write<NT, kHeavyTable / NT>(keys, vals, tcap, dst, A.err, sm.scan, sm.aux);
+                               : compact_sort_write<NT, kHeavyTable / NT>(keys, vals, tcap, dst, A.err, sm.scan);
       written += k;
       lo = hi;
       width = hi_p - lo;  // try the rest of the partition in one window again
@@ -920,6 +902,7 @@ lp_status contract_heavy(const AggArgs& A, const int32_t* hl, int32_t H, Rec* re
   uint64_t* tcnt = sc.alloc<uint64_t>((size_t)T + 1);
   uint64_t* tdeg = sc.alloc<uint64_t>((size_t)T + 1);
   hv.ctab = sc.alloc<uint32_t>(hp);
+  hv.bnd = sc.alloc<int32_t>((size_t)T + H);
   if (sc.failed) return LP_ENOMEM;
   LP_CHECK_HIP(hipMemsetAsync(tcnt + T, 0, 8, s));
   hipLaunchKernelGGL(k_heavy_lists, dim3(grid_for(H, 256, 4096)), dim3(256), 0, s, H, parts, cbase, tbase, chunks,
@@ -935,6 +918,8 @@ lp_status contract_heavy(const AggArgs& A, const int32_t* hl, int32_t H, Rec* re
   hv.tcnt = tcnt;
   hv.tdeg = tdeg;
   hv.rec2 = rec2;
+  hipLaunchKernelGGL(k_heavy_splitters, dim3(grid_for(H, 1, 1u << 20)), dim3(256), 0, s, A, hv, H);
+  LP_CHECK_LAUNCH();
   if (NCH > 0) {
     hipLaunchKernelGGL(k_heavy_partition, dim3(grid_for(NCH, 1, 1u << 20)), dim3(256), 0, s, A, hv, NCH);
     LP_CHECK_LAUNCH();
