@@ -147,7 +147,8 @@ typedef struct {
 #define LP_PHASE_BLOCK 3  /* rating, workgroup-per-vertex bucket */
 #define LP_PHASE_HUB 4    /* rating, hub path (scatter, reduce, combine) */
 #define LP_PHASE_ACCEPT 5 /* proposal compaction, sort, admission, apply */
-#define LP_NUM_PHASES 6
+#define LP_PHASE_ROUND 6  /* whole rounds: the four rating paths run on concurrent streams */
+#define LP_NUM_PHASES 7
 
 /* Per-call statistics (host struct, filled when requested). */
 typedef struct {

@@ -36,7 +36,7 @@ class LPError(RuntimeError):
         super().__init__(f"{where}: {msg} ({status})")
 
 
-PHASES = ("setup", "lane", "tile", "block", "hub", "accept")
+PHASES = ("setup", "lane", "tile", "block", "hub", "accept", "round")
 
 
 class lp_config(ctypes.Structure):
@@ -49,7 +49,7 @@ class lp_cluster_stats(ctypes.Structure):
                 ("n_block", ctypes.c_int32), ("n_hub", ctypes.c_int32),
                 ("proposals", ctypes.c_int64 * 64), ("moves", ctypes.c_int64 * 64),
                 ("bucket_edges", ctypes.c_uint64 * 4), ("bucket_bytes", ctypes.c_uint64 * 4),
-                ("phase_ms", ctypes.c_float * 6), ("phase_launches", ctypes.c_int32 * 6)]
+                ("phase_ms", ctypes.c_float * len(PHASES)), ("phase_launches", ctypes.c_int32 * len(PHASES))]
 
 
 def build() -> str:

@@ -29,7 +29,7 @@ def candidates(grid: dict = GRID):
 
 
 def _round_ms(stats) -> float:
-    return sum(v for k, v in stats.phase_ms.items() if k != "setup") + stats.phase_ms.get("setup", 0.0)
+    return stats.phase_ms.get("round", 0.0) + stats.phase_ms.get("setup", 0.0)
 
 
 def tune(run, grid: dict = GRID, repeats: int = 2):

@@ -14,6 +14,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "decode.h"
@@ -1402,6 +1403,22 @@ lp_status set_lds(F* kern, size_t bytes) {
 }
 
 // LDS layout of a rating group for degrees up to dmax.
+// Side streams of the current device (created once, default priority, kept
+// until the process ends); several host threads may share them, which only
+// adds ordering.
+lp_status side_stream(int i, hipStream_t* out) {
+  constexpr int kMaxDev = 64;
+  static std::mutex mu;
+  static hipStream_t pool[kMaxDev][3] = {};
+  int dev = 0;
+  LP_CHECK_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDev) return LP_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!pool[dev][i]) LP_CHECK_HIP(hipStreamCreateWithFlags(&pool[dev][i], hipStreamNonBlocking));
+  *out = pool[dev][i];
+  return LP_OK;
+}
+
 template <class T, typename V, bool COMP>
 lp_status launch_tile(const RoundCtx& x, VDesc vd, const int32_t* tiles, const uint32_t* ntiles, unsigned grid,
                       bool weighted, hipStream_t s) {
@@ -1579,20 +1596,33 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
       }
     }
   } guard{&marks};
-  auto begin = [&](int phase) -> lp_status {
+  auto begin = [&](int phase, hipStream_t on = nullptr) -> lp_status {
     if (!timing) return LP_OK;
     Mark m{phase, nullptr, nullptr};
     LP_CHECK_HIP(hipEventCreate(&m.a));
     LP_CHECK_HIP(hipEventCreate(&m.b));
     marks.push_back(m);
-    LP_CHECK_HIP(hipEventRecord(m.a, s));
+    LP_CHECK_HIP(hipEventRecord(m.a, on ? on : s));
     return LP_OK;
   };
-  auto end = [&]() -> lp_status {
+  auto end = [&](hipStream_t on = nullptr) -> lp_status {
     if (!timing) return LP_OK;
-    LP_CHECK_HIP(hipEventRecord(marks.back().b, s));
+    LP_CHECK_HIP(hipEventRecord(marks.back().b, on ? on : s));
     return LP_OK;
   };
+  // The rating paths of a round are independent (they read the snapshot and
+  // write disjoint vertices): they run on side streams forked from and joined
+  // back into the call's stream, so that their kernels overlap.
+  hipStream_t side[3];
+  for (int i = 0; i < 3; ++i) LP_CHECK(side_stream(i, &side[i]));
+  struct EvGuard {
+    hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+    ~EvGuard() {
+      for (auto x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev;
+  for (int i = 0; i < 4; ++i) LP_CHECK_HIP(hipEventCreateWithFlags(&ev.e[i], hipEventDisableTiming));
 
   LP_CHECK(begin(LP_PHASE_SETUP));
   LP_CHECK(compute_degrees(g, deg, s));
@@ -1743,41 +1773,54 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
 
   for (int32_t r = 0; r < rounds; ++r) {
     x.round = (uint32_t)r;
-    // rating (all buckets) -> ptgt / pgain
-    if (bn[0] > 0) {
-      LP_CHECK(begin(LP_PHASE_LANE));
-      if (g->compressed)
-        hipLaunchKernelGGL(k_rate_lane<true>, dim3(grid_for(bn[0], 256)), dim3(256), 0, s, x, vd_of(0), bn[0]);
-      else
-        hipLaunchKernelGGL(k_rate_lane<false>, dim3(grid_for(bn[0], 256)), dim3(256), 0, s, x, vd_of(0), bn[0]);
-      LP_CHECK_LAUNCH();
-      LP_CHECK(end());
-    }
+    const size_t round_mark = marks.size();
+    LP_CHECK(begin(LP_PHASE_ROUND));
+    // rating (all buckets) -> ptgt / pgain; fork the side streams
+    LP_CHECK_HIP(hipEventRecord(ev.e[3], s));
+    for (int i = 0; i < 3; ++i) LP_CHECK_HIP(hipStreamWaitEvent(side[i], ev.e[3], 0));
+    // the longest path first: it takes the CUs it needs, the others fill in
     if (bn[1] > 0) {
       LP_CHECK(begin(LP_PHASE_TILE));
       LP_CHECK(launch_tile_any<TileSmall>(g->compressed, wide, x, vd_of(1), tps.tiles, tps.ntiles, tps.grid,
                                           g->weighted, s));
       LP_CHECK(end());
     }
-    if (bn[2] > 0) {
-      LP_CHECK(begin(LP_PHASE_BLOCK));
-      LP_CHECK(launch_tile_any<TileLarge>(g->compressed, wide, x, vd_of(2), tpl.tiles, tpl.ntiles, tpl.grid,
-                                          g->weighted, s));
-      LP_CHECK(end());
-    }
     if (H > 0) {
-      LP_CHECK(begin(LP_PHASE_HUB));
-      LP_CHECK(launch_piece(g->compressed, wide, x, hm, npieces, piece_layout, piece_lds, s));
+      hipStream_t hs = side[0];
+      LP_CHECK(begin(LP_PHASE_HUB, hs));
+      LP_CHECK(launch_piece(g->compressed, wide, x, hm, npieces, piece_layout, piece_lds, hs));
       if (wide)
         hipLaunchKernelGGL(k_hub_reduce<int64_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads),
-                           (size_t)kHubTable * 12 + sizeof(HubReduceSmem), s, x, hm, ntasks);
+                           (size_t)kHubTable * 12 + sizeof(HubReduceSmem), hs, x, hm, ntasks);
       else
         hipLaunchKernelGGL(k_hub_reduce<int32_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads),
-                           (size_t)kHubTable * 8 + sizeof(HubReduceSmem), s, x, hm, ntasks);
+                           (size_t)kHubTable * 8 + sizeof(HubReduceSmem), hs, x, hm, ntasks);
       LP_CHECK_LAUNCH();
-      hipLaunchKernelGGL(k_hub_combine, dim3(grid_for(H, 4)), dim3(256), 0, s, x, hm, H);
+      hipLaunchKernelGGL(k_hub_combine, dim3(grid_for(H, 4)), dim3(256), 0, hs, x, hm, H);
       LP_CHECK_LAUNCH();
-      LP_CHECK(end());
+      LP_CHECK(end(hs));
+    }
+    if (bn[2] > 0) {
+      LP_CHECK(begin(LP_PHASE_BLOCK, side[1]));
+      LP_CHECK(launch_tile_any<TileLarge>(g->compressed, wide, x, vd_of(2), tpl.tiles, tpl.ntiles, tpl.grid,
+                                          g->weighted, side[1]));
+      LP_CHECK(end(side[1]));
+    }
+    if (bn[0] > 0) {
+      LP_CHECK(begin(LP_PHASE_LANE, side[2]));
+      if (g->compressed)
+        hipLaunchKernelGGL(k_rate_lane<true>, dim3(grid_for(bn[0], 256)), dim3(256), 0, side[2], x, vd_of(0),
+                           bn[0]);
+      else
+        hipLaunchKernelGGL(k_rate_lane<false>, dim3(grid_for(bn[0], 256)), dim3(256), 0, side[2], x, vd_of(0),
+                           bn[0]);
+      LP_CHECK_LAUNCH();
+      LP_CHECK(end(side[2]));
+    }
+    // join
+    for (int i = 0; i < 3; ++i) {
+      LP_CHECK_HIP(hipEventRecord(ev.e[i], side[i]));
+      LP_CHECK_HIP(hipStreamWaitEvent(s, ev.e[i], 0));
     }
     // acceptance: compact in vertex order, sort by (target, gain desc)
     LP_CHECK(begin(LP_PHASE_ACCEPT));
@@ -1800,6 +1843,7 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
     hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, s, &ctl->count, &ctl->done, ctl->stats, r, &ctl->rounds_run);
     LP_CHECK_LAUNCH();
     LP_CHECK(end());
+    if (timing) LP_CHECK_HIP(hipEventRecord(marks[round_mark].b, s));
   }
   if (batch) LP_CHECK(batch_localize(g, labels, out_labels, labels_each, s));
   if (stats_out) {

@@ -16,6 +16,7 @@
  * every neighbourhood sorted by increasing ID.
  */
 #include <math.h>
+#include <stdio.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -35,6 +36,13 @@ static inline uint64_t sm_draw(uint64_t seed, uint64_t k) {
 
 static inline double sm_unit(uint64_t seed, uint64_t k) {
   return (double)(sm_draw(seed, k) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/* Phase messages on stderr for long generations (SYNTH_PROGRESS set). */
+static void progress(const char *what, int64_t a, int64_t b) {
+  if (!getenv("SYNTH_PROGRESS")) return;
+  fprintf(stderr, "[synth] %s %lld %lld\n", what, (long long)a, (long long)b);
+  fflush(stderr);
 }
 
 typedef struct {
@@ -70,6 +78,7 @@ static int build_csr(int64_t n, int64_t npairs, pair_fn emit, const void *ctx,
   }
   for (int64_t u = 0; u < n; ++u) cnt[u + 1] += cnt[u];
   uint64_t total = cnt[n];
+  progress("degrees counted: vertices, directed pairs", n, (int64_t)total);
   int32_t *tmp = (int32_t *)malloc((total ? total : 1) * sizeof(int32_t));
   uint64_t *pos = (uint64_t *)malloc(((size_t)n + 1) * sizeof(uint64_t));
   if (!tmp || !pos) { free(cnt); free(tmp); free(pos); return -1; }
@@ -83,6 +92,7 @@ static int build_csr(int64_t n, int64_t npairs, pair_fn emit, const void *ctx,
     tmp[pu] = v;
     tmp[pv] = u;
   }
+  progress("pairs scattered", n, (int64_t)total);
   /* sort + dedupe each neighbourhood in place; record new degrees */
   uint64_t *deg = pos; /* reuse */
 #pragma omp parallel for schedule(dynamic, 1024)
@@ -95,6 +105,7 @@ static int build_csr(int64_t n, int64_t npairs, pair_fn emit, const void *ctx,
       if (k == 0 || tmp[b + j] != tmp[b + k - 1]) tmp[b + k++] = tmp[b + j];
     deg[u] = k;
   }
+  progress("neighbourhoods sorted", n, 0);
   uint64_t *xadj = (uint64_t *)malloc(((size_t)n + 1) * sizeof(uint64_t));
   if (!xadj) { free(cnt); free(tmp); free(pos); return -1; }
   xadj[0] = 0;
@@ -221,7 +232,9 @@ int synth_rgg(int dim, int64_t n, double r, uint64_t seed, synth_csr *out) {
     rec[i].x = raw[i * dim + 0];
     rec[i].idx = i;
   }
+  progress("points drawn", n, ncell);
   qsort(rec, (size_t)n, sizeof(rgg_rec), cmp_rec);
+  progress("points ordered by cell", n, ncell);
   double *pt = (double *)malloc((size_t)n * dim * sizeof(double));
   int64_t *cstart = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
   if (!pt || !cstart) { free(raw); free(rec); free(pt); free(cstart); return -1; }
@@ -273,6 +286,7 @@ int synth_rgg(int dim, int64_t n, double r, uint64_t seed, synth_csr *out) {
       if (pass == 0) xadj[i + 1] = k;
       else if (k > 1) qsort(adj + xadj[i], k, sizeof(int32_t), cmp_i32);
     }
+    progress(pass == 0 ? "neighbours counted" : "neighbours written", n, pass);
   }
   free(pt);
   free(cstart);
