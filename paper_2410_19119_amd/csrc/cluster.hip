@@ -14,6 +14,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -40,7 +41,17 @@ struct RoundCtx {
   const int32_t* gbase;
   const int64_t* gcap;
   const uint64_t* gseed;
+  // edge visits other than rating (C then holds the labels for a cut, the
+  // fine -> coarse map for contraction records)
+  const uint64_t* rbase;    // records: first record of every coarse vertex
+  const uint64_t* voff;     // records: slice of every fine vertex in its coarse vertex's region
+  Rec* rec;                 // records: output, {coarse neighbour or -1, weight} per fine edge
+  unsigned long long* cut;  // cut: accumulator of the weights of edges between clusters
 };
+
+// What an edge visit computes: ratings and proposals, the cut, or the
+// contraction records.
+constexpr int kModeRate = 0, kModeCut = 1, kModeRec = 2;
 
 // Cap, seed and label offset that apply to vertex u: a graph of a batch keeps
 // its own cap and seed, and its tie-break keys use labels local to the graph,
@@ -92,10 +103,36 @@ __device__ __forceinline__ void consider(const RoundCtx& x, const VParams& p, in
 }
 
 // ------------------------------------------------------- lane per vertex --
-template <bool COMP>
+template <bool COMP, int MODE = kModeRate>
 __global__ __launch_bounds__(256) void k_rate_lane(RoundCtx x, VDesc vd, int32_t cnt) {
   if (*x.done) return;
   const int32_t i = blockIdx.x * 256 + threadIdx.x;
+  if constexpr (MODE == kModeCut) {
+    __shared__ unsigned long long red[4];
+    unsigned long long c = 0;
+    if (i < cnt) {
+      const int4 v4 = vd.d[i];
+      const int32_t u = v4.x, d = v4.y;
+      const int32_t own_c = x.C[u];
+      uint64_t pos = vd_pos(v4);
+      int32_t v = 0, w = 0;
+      for (int k = 0; k < d; ++k) {
+        if constexpr (COMP) {
+          const uint64_t code = varint_read(x.g.bytes, pos);
+          v = (k == 0) ? u + (int32_t)unzigzag(code) : v + (int32_t)code;
+          if (x.g.weighted) w = (k == 0 ? 0 : w) + (int32_t)unzigzag(varint_read(x.g.bytes, pos));
+          else w = 1;
+        } else {
+          v = x.g.adjncy[pos + k];
+          w = x.g.adjwgt ? x.g.adjwgt[pos + k] : 1;
+        }
+        if (x.C[v] != own_c) c += (unsigned long long)w;
+      }
+    }
+    c = block_reduce_add<256, unsigned long long>(c, red);
+    if (threadIdx.x == 0 && c) atomicAdd(x.cut, c);
+    return;
+  }
   if (i >= cnt) return;
   const int4 v4 = vd.d[i];
   const int32_t u = v4.x;
@@ -131,6 +168,13 @@ __global__ __launch_bounds__(256) void k_rate_lane(RoundCtx x, VDesc vd, int32_t
     }
   }
   const int32_t own_c = x.C[u];
+  if constexpr (MODE == kModeRec) {
+    Rec* r = x.rec + x.rbase[own_c] + x.voff[u];
+#pragma unroll
+    for (int k = 0; k < kMaxLane; ++k)
+      if (k < d) r[k] = Rec{lab[k] == own_c ? -1 : lab[k], wt[k]};
+    return;
+  }
   const int64_t wu = vweight(x.g, u);
   const VParams vp = vparams(x, u);
   int64_t own = 0;
@@ -217,6 +261,8 @@ struct TileShared {
   int64_t own_r[VT];
   int64_t gain[VT];
   VParams vp;  // the tile's graph (tiles never span two graphs of a batch)
+  uint64_t rb[VT];  // records: first record of every vertex
+  unsigned long long red_u[NT / kWave];
   int32_t scan[NT / kWave];
   int32_t scan2[NT / kWave];
   Cand cb[NT / kWave];
@@ -341,7 +387,7 @@ __device__ __forceinline__ uint32_t window_value(uint64_t w, uint64_t term, uint
   return v;
 }
 
-template <class T, typename V, bool COMP>
+template <class T, typename V, bool COMP, int MODE = kModeRate>
 __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd, const int32_t* tiles,
                                                            const uint32_t* ntiles_p, TileLayout L) {
   constexpr int NT = T::kThreads, VT = T::kVerts, ITEMS = T::kItems, SG = T::kSelGroup;
@@ -378,6 +424,7 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
       sh.own_c[tid] = x.C[u];
       sh.wu[tid] = x.g.vwgt ? x.g.vwgt[u] : 1;
       sh.pos[tid] = pos;
+      if constexpr (MODE == kModeRec) sh.rb[tid] = x.rbase[sh.own_c[tid]] + x.voff[u];
       if constexpr (COMP) {
         const uint32_t len = vd.len[t0 + tid];
         const uint32_t pre = (uint32_t)(pos & 3u);
@@ -531,6 +578,27 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
       if (vi[k] < 0) continue;
       if ((uint32_t)nb[k] < (uint32_t)x.g.n) nb[k] = x.C[nb[k]];
       else vi[k] = -1;  // unreachable for a valid handle; keeps the gather in bounds
+    }
+    if constexpr (MODE == kModeCut) {
+      unsigned long long c = 0;
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k)
+        if (vi[k] >= 0 && nb[k] != sh.own_c[vi[k]]) c += (unsigned long long)wt[k];
+      c = block_reduce_add<NT, unsigned long long>(c, sh.red_u);
+      if (tid == 0 && c) atomicAdd(x.cut, c);
+      __syncthreads();
+      continue;
+    }
+    if constexpr (MODE == kModeRec) {
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        if (vi[k] < 0) continue;
+        const int32_t i = vi[k];
+        const uint32_t loc = e0 + k - sh.ebase[i];
+        x.rec[sh.rb[i] + loc] = Rec{nb[k] == sh.own_c[i] ? -1 : nb[k], wt[k]};
+      }
+      __syncthreads();
+      continue;
     }
     __syncthreads();  // numbers consumed: region A becomes the table
     for (uint32_t q = tid; q < St; q += NT) keys[q] = kEmpty;
@@ -772,13 +840,14 @@ struct PieceShared {
   uint32_t dwbase[kHubStreams + 1];
   uint32_t rstart[kHubStreams + 1];
   uint32_t hist[kMaxParts];
+  unsigned long long red_u[kPieceThreads / kWave];
   int32_t scan[kPieceThreads / kWave];
   int32_t scan2[kPieceThreads / kWave];
   uint32_t seg_flags;
 };
 
 // H1: one workgroup per hub piece.
-template <typename V, bool COMP>
+template <typename V, bool COMP, int MODE = kModeRate>
 __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta hm, int32_t npieces,
                                                             TileLayout L) {
   constexpr int NT = kPieceThreads, ITEMS = kPieceItems, NS = kHubStreams;
@@ -950,6 +1019,25 @@ __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta
       if (vi[k] < 0) continue;
       if ((uint32_t)nb[k] < (uint32_t)x.g.n) nb[k] = x.C[nb[k]];
       else vi[k] = -1;  // unreachable for a valid handle; keeps the gather in bounds
+    }
+    if constexpr (MODE != kModeRate) {
+      const int32_t u = hm.u[h];
+      const int32_t own = x.C[u];
+      if constexpr (MODE == kModeCut) {
+        unsigned long long c = 0;
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+          if (vi[k] >= 0 && nb[k] != own) c += (unsigned long long)wt[k];
+        c = block_reduce_add<NT, unsigned long long>(c, sh.red_u);
+        if (tid == 0 && c) atomicAdd(x.cut, c);
+      } else {
+        Rec* r = x.rec + x.rbase[own] + x.voff[u] + (uint64_t)pj.y * kHubPiece;
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+          if (vi[k] >= 0) r[e0 + k] = Rec{nb[k] == own ? -1 : nb[k], wt[k]};
+      }
+      __syncthreads();
+      continue;
     }
     __syncthreads();  // numbers consumed: region A becomes the table
     const uint32_t S = tile_slots(Et);
@@ -1419,12 +1507,12 @@ lp_status side_stream(int i, hipStream_t* out) {
   return LP_OK;
 }
 
-template <class T, typename V, bool COMP>
+template <class T, typename V, bool COMP, int MODE = kModeRate>
 lp_status launch_tile(const RoundCtx& x, VDesc vd, const int32_t* tiles, const uint32_t* ntiles, unsigned grid,
                       bool weighted, hipStream_t s) {
   const TileLayout L = tile_layout<T, V>(COMP, weighted);
   const size_t bytes = (size_t)L.abytes + sizeof(TileShared<T::kThreads, T::kVerts>);
-  auto kern = k_rate_tile<T, V, COMP>;
+  auto kern = k_rate_tile<T, V, COMP, MODE>;
   LP_CHECK(set_lds(kern, bytes));
   hipLaunchKernelGGL(kern, dim3(grid), dim3(T::kThreads), bytes, s, x, vd, tiles, ntiles, L);
   return last_error();
@@ -1455,10 +1543,11 @@ TileLayout piece_layout_of(bool comp, bool weighted) {
   return L;
 }
 
+template <int MODE = kModeRate>
 lp_status launch_piece(bool comp, bool wide, const RoundCtx& x, const HubMeta& hm, int32_t npieces,
                        const TileLayout& L, size_t lds, hipStream_t s) {
-  auto kern = comp ? (wide ? k_hub_piece<int64_t, true> : k_hub_piece<int32_t, true>)
-                   : (wide ? k_hub_piece<int64_t, false> : k_hub_piece<int32_t, false>);
+  auto kern = comp ? (wide ? k_hub_piece<int64_t, true, MODE> : k_hub_piece<int32_t, true, MODE>)
+                   : (wide ? k_hub_piece<int64_t, false, MODE> : k_hub_piece<int32_t, false, MODE>);
   LP_CHECK(set_lds(kern, lds));
   const unsigned grid = grid_for(npieces, 1, 2048);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kPieceThreads), lds, s, x, hm, npieces, L);
@@ -1472,16 +1561,35 @@ struct TilePlan {
   unsigned grid = 0;
 };
 
+// Device memory of a plan: plain allocations freed with the plan.
+struct PlanMem {
+  std::vector<void*> ptrs;
+  bool failed = false;
+  template <typename T>
+  T* alloc(size_t n) {
+    void* p = nullptr;
+    if (hipMalloc(&p, (n ? n : 1) * sizeof(T)) != hipSuccess) {
+      failed = true;
+      return nullptr;
+    }
+    ptrs.push_back(p);
+    return (T*)p;
+  }
+  ~PlanMem() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
 template <class T>
 lp_status plan_tiles(VDesc vd, int32_t cnt, bool comp, bool wide, bool weighted, const int32_t* gid, Scratch& sc,
-                     TilePlan& tp) {
+                     PlanMem& mem, TilePlan& tp) {
   if (cnt <= 0) return LP_OK;
   const TileLayout L = wide ? tile_layout<T, int64_t>(comp, weighted) : tile_layout<T, int32_t>(comp, weighted);
   const int64_t nseg = ((int64_t)cnt + kTileSeg - 1) / kTileSeg;
   uint32_t* tcnt = sc.alloc<uint32_t>(nseg);
-  tp.ntiles = sc.alloc<uint32_t>(1);
-  tp.tiles = sc.alloc<int32_t>((size_t)cnt + 1);
-  if (sc.failed) return LP_ENOMEM;
+  tp.ntiles = mem.alloc<uint32_t>(1);
+  tp.tiles = mem.alloc<int32_t>((size_t)cnt + 1);
+  if (sc.failed || mem.failed) return LP_ENOMEM;
   hipStream_t s = sc.stream();
   hipLaunchKernelGGL(k_tile_plan<true>, dim3(grid_for(nseg, 256)), dim3(256), 0, s, vd, cnt, (uint32_t)T::kEdges,
                      (uint32_t)T::kVerts, L.stage_bytes, comp, gid, tcnt, (const uint32_t*)nullptr, (int32_t*)nullptr);
@@ -1501,8 +1609,255 @@ lp_status plan_tiles(VDesc vd, int32_t cnt, bool comp, bool wide, bool weighted,
 using namespace lp;
 
 namespace lp {
+namespace {
+
+// Everything about a graph that the rating, cut and record paths need and
+// that depends only on the graph and the bucket thresholds: degree buckets
+// (one stable vertex list ordered by (bucket, vertex)), vertex descriptors,
+// the tiles of both tile buckets, and the hubs' pieces with their code
+// streams. Built once per graph for the default thresholds and kept in the
+// handle; other thresholds get a plan of their own for one call.
+struct Plan {
+  int32_t t_lane = 0, t_tile = 0, t_block = 0, hub_part = 0;
+  bool wide = false;
+  int32_t bn[kNumBuckets] = {};
+  uint32_t bstart[kNumBuckets + 1] = {};
+  int32_t* order = nullptr;
+  int4* vdesc = nullptr;
+  uint32_t* vlen = nullptr;
+  TilePlan tps, tpl;
+  HubMeta hm{};  // static parts only; per-call buffers are set by the caller
+  int32_t H = 0, npieces = 0, ntasks = 0;
+  uint64_t rsum = 0, psum = 0;
+  unsigned long long bsums[2 * kNumBuckets] = {};
+  PlanMem mem;
+  VDesc vd(int b) const { return VDesc{vdesc + bstart[b], vlen + bstart[b]}; }
+};
+
+lp_status build_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t t_block, int32_t hub_part,
+                     hipStream_t s, Plan& P) {
+  const int32_t n = g->n;
+  P.t_lane = t_lane;
+  P.t_tile = t_tile;
+  P.t_block = t_block;
+  P.hub_part = hub_part;
+  P.wide = g->max_wdeg > 0x7FFFFFFFll;
+  const bool batch = g->nbatch > 0;
+  Scratch sc(s);
+  int32_t* deg = sc.alloc<int32_t>(n);
+  const unsigned nbk = grid_for(n, kBkTile, 0x7FFFFFFF);
+  uint32_t* bcnt = sc.alloc<uint32_t>((size_t)kNumBuckets * nbk);
+  uint32_t* btot = sc.alloc<uint32_t>(1);
+  unsigned long long* bsums = sc.alloc<unsigned long long>(2 * kNumBuckets);
+  P.order = P.mem.alloc<int32_t>(n);
+  if (sc.failed || P.mem.failed) return LP_ENOMEM;
+  LP_CHECK_HIP(hipMemsetAsync(bsums, 0, 2 * kNumBuckets * sizeof(unsigned long long), s));
+  LP_CHECK(compute_degrees(g, deg, s));
+  hipLaunchKernelGGL(k_bucket_count, dim3(nbk), dim3(kBkThreads), 0, s, deg, n, t_lane, t_tile, t_block, bcnt, nbk);
+  LP_CHECK_LAUNCH();
+  LP_CHECK(scan_exclusive_u32(bcnt, bcnt, (int64_t)kNumBuckets * nbk, btot, sc));
+  hipLaunchKernelGGL(k_bucket_scatter, dim3(nbk), dim3(kBkThreads), 0, s, deg, n, t_lane, t_tile, t_block, bcnt, nbk,
+                     P.order);
+  LP_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_bucket_sums, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, deg, n, t_lane, t_tile, t_block,
+                     g->compressed ? g->offs : nullptr, bsums);
+  LP_CHECK_LAUNCH();
+  for (int b = 0; b < kNumBuckets; ++b)
+    LP_CHECK_HIP(hipMemcpyAsync(&P.bstart[b], bcnt + (size_t)b * nbk, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  LP_CHECK_HIP(hipMemcpyAsync(&P.bstart[kNumBuckets], btot, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  LP_CHECK_HIP(hipMemcpyAsync(P.bsums, bsums, sizeof(P.bsums), hipMemcpyDeviceToHost, s));
+  LP_CHECK_HIP(hipStreamSynchronize(s));
+  for (int b = 0; b < kNumBuckets; ++b) P.bn[b] = (int32_t)(P.bstart[b + 1] - P.bstart[b]);
+
+  // descriptors of the non-hub buckets
+  const int32_t nlisted = (int32_t)P.bstart[3];
+  P.vdesc = P.mem.alloc<int4>(nlisted);
+  P.vlen = P.mem.alloc<uint32_t>(nlisted);
+  if (P.mem.failed) return LP_ENOMEM;
+  if (nlisted > 0) {
+    hipLaunchKernelGGL(k_build_desc, dim3(grid_for(nlisted, 256, 65536)), dim3(256), 0, s, g->view(), P.order, deg,
+                       nlisted, P.vdesc, P.vlen);
+    LP_CHECK_LAUNCH();
+  }
+  // tiles of the two tile buckets
+  const int32_t* gid = batch ? g->gid : nullptr;
+  LP_CHECK(plan_tiles<TileSmall>(P.vd(1), P.bn[1], g->compressed, P.wide, g->weighted, gid, sc, P.mem, P.tps));
+  LP_CHECK(plan_tiles<TileLarge>(P.vd(2), P.bn[2], g->compressed, P.wide, g->weighted, gid, sc, P.mem, P.tpl));
+
+  // hubs: metadata (host-built, small) and the code streams of their pieces
+  const int32_t H = P.bn[3];
+  P.H = H;
+  if (H > 0) {
+    std::vector<int32_t> hu(H), hd(H);
+    int32_t* hdeg_dev = sc.alloc<int32_t>(H);
+    if (!hdeg_dev) return LP_ENOMEM;
+    hipLaunchKernelGGL(k_gather_i32, dim3(grid_for(H, 256, 4096)), dim3(256), 0, s, deg, P.order + P.bstart[3], H,
+                       hdeg_dev);
+    LP_CHECK_LAUNCH();
+    LP_CHECK_HIP(hipMemcpyAsync(hu.data(), P.order + P.bstart[3], H * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LP_CHECK_HIP(hipMemcpyAsync(hd.data(), hdeg_dev, H * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LP_CHECK_HIP(hipStreamSynchronize(s));
+    int64_t maxd = 0;
+    for (int h = 0; h < H; ++h) maxd = std::max<int64_t>(maxd, hd[h]);
+    const int64_t part = std::max<int64_t>(hub_part, (maxd + kMaxParts - 1) / kMaxParts);
+    std::vector<int32_t> np(H), npc(H), pcb(H), tb(H);
+    std::vector<uint64_t> rbase(H), pbase(H);
+    std::vector<int2> pieces, tasks;
+    uint64_t rsum = 0, psum = 0;
+    int32_t ntasks = 0;
+    for (int h = 0; h < H; ++h) {
+      const int64_t d = hd[h];
+      np[h] = (int32_t)std::max<int64_t>(1, (d + part - 1) / part);
+      npc[h] = (int32_t)((d + kHubPiece - 1) / kHubPiece);
+      pcb[h] = (int32_t)pieces.size();
+      rbase[h] = rsum;
+      pbase[h] = psum;
+      tb[h] = ntasks;
+      rsum += (uint64_t)d;
+      psum += (uint64_t)npc[h] * (np[h] + 1);
+      ntasks += np[h];
+      for (int k = 0; k < npc[h]; ++k) pieces.push_back(make_int2(h, k));
+      for (int p = 0; p < np[h]; ++p) tasks.push_back(make_int2(h, p));
+    }
+    P.npieces = (int32_t)pieces.size();
+    P.ntasks = ntasks;
+    P.rsum = rsum;
+    P.psum = psum;
+    HubMeta& hm = P.hm;
+    int32_t* d_u = P.mem.alloc<int32_t>(H);
+    int32_t* d_deg = P.mem.alloc<int32_t>(H);
+    int32_t* d_np = P.mem.alloc<int32_t>(H);
+    int32_t* d_npc = P.mem.alloc<int32_t>(H);
+    int32_t* d_pcb = P.mem.alloc<int32_t>(H);
+    int32_t* d_tb = P.mem.alloc<int32_t>(H);
+    uint64_t* d_rb = P.mem.alloc<uint64_t>(H);
+    uint64_t* d_pb = P.mem.alloc<uint64_t>(H);
+    int2* d_pieces = P.mem.alloc<int2>(P.npieces);
+    int2* d_tasks = P.mem.alloc<int2>(ntasks);
+    hm.streams = P.mem.alloc<HubStream>((size_t)P.npieces * kHubStreams);
+    if (P.mem.failed) return LP_ENOMEM;
+    LP_CHECK_HIP(hipMemcpyAsync(d_u, hu.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_deg, hd.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_np, np.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_npc, npc.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_pcb, pcb.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_tb, tb.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_rb, rbase.data(), H * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_pb, pbase.data(), H * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_pieces, pieces.data(), P.npieces * sizeof(int2), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_tasks, tasks.data(), ntasks * sizeof(int2), hipMemcpyHostToDevice, s));
+    hm.u = d_u;
+    hm.deg = d_deg;
+    hm.nparts = d_np;
+    hm.npieces = d_npc;
+    hm.piece_base = d_pcb;
+    hm.rec_base = d_rb;
+    hm.poff_base = d_pb;
+    hm.task_base = d_tb;
+    hm.pieces = d_pieces;
+    hm.tasks = d_tasks;
+    hipLaunchKernelGGL(k_hub_streams, dim3(grid_for(H, 4, 4096)), dim3(256), 0, s, g->view(), hm, H);
+    LP_CHECK_LAUNCH();
+  }
+  LP_CHECK_HIP(hipStreamSynchronize(s));  // host vectors go out of scope; the plan is complete
+  return LP_OK;
+}
+
+void plan_delete(void* p) { delete (Plan*)p; }
+
+lp_status get_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t t_block, int32_t hub_part,
+                   hipStream_t s, const Plan** out, std::unique_ptr<Plan>& tmp);
+
+// One visit of every edge with the default plan: the cut (MODE == kModeCut)
+// or the contraction records (kModeRec). The lane, tile and piece kernels
+// decode exactly as for rating and stop after the label (or map) gather.
+template <int MODE>
+lp_status visit_edges_mode(const lp_graph* g, const int32_t* C, const uint64_t* rbase, const uint64_t* voff, Rec* rec,
+                           unsigned long long* cut, hipStream_t s) {
+  const Plan* plan = nullptr;
+  std::unique_ptr<Plan> tmp;
+  LP_CHECK(get_plan(g, 16, TileSmall::kEdges, TileLarge::kEdges, 1024, s, &plan, tmp));
+  Scratch sc(s);
+  uint32_t* zero = sc.alloc<uint32_t>(1);
+  if (!zero) return LP_ENOMEM;
+  LP_CHECK_HIP(hipMemsetAsync(zero, 0, sizeof(uint32_t), s));
+  RoundCtx x{};
+  x.g = g->view();
+  x.C = C;
+  x.done = zero;
+  x.rbase = rbase;
+  x.voff = voff;
+  x.rec = rec;
+  x.cut = cut;
+  const bool comp = g->compressed;
+  if (plan->bn[0] > 0) {
+    const VDesc vd = plan->vd(0);
+    const int32_t c = plan->bn[0];
+    if (comp) hipLaunchKernelGGL((k_rate_lane<true, MODE>), dim3(grid_for(c, 256)), dim3(256), 0, s, x, vd, c);
+    else hipLaunchKernelGGL((k_rate_lane<false, MODE>), dim3(grid_for(c, 256)), dim3(256), 0, s, x, vd, c);
+    LP_CHECK_LAUNCH();
+  }
+  if (plan->bn[1] > 0) {
+    if (comp)
+      LP_CHECK((launch_tile<TileSmall, int32_t, true, MODE>(x, plan->vd(1), plan->tps.tiles, plan->tps.ntiles,
+                                                            plan->tps.grid, g->weighted, s)));
+    else
+      LP_CHECK((launch_tile<TileSmall, int32_t, false, MODE>(x, plan->vd(1), plan->tps.tiles, plan->tps.ntiles,
+                                                             plan->tps.grid, g->weighted, s)));
+  }
+  if (plan->bn[2] > 0) {
+    if (comp)
+      LP_CHECK((launch_tile<TileLarge, int32_t, true, MODE>(x, plan->vd(2), plan->tpl.tiles, plan->tpl.ntiles,
+                                                            plan->tpl.grid, g->weighted, s)));
+    else
+      LP_CHECK((launch_tile<TileLarge, int32_t, false, MODE>(x, plan->vd(2), plan->tpl.tiles, plan->tpl.ntiles,
+                                                             plan->tpl.grid, g->weighted, s)));
+  }
+  if (plan->H > 0) {
+    const TileLayout L = piece_layout_of<int32_t>(comp, g->weighted);
+    LP_CHECK(launch_piece<MODE>(comp, false, x, plan->hm, plan->npieces, L, (size_t)L.abytes + sizeof(PieceShared),
+                                s));
+  }
+  return LP_OK;
+}
+
+// The plan for these thresholds: the handle's cached one for the defaults
+// (built on first use), otherwise a new one owned by `tmp`.
+lp_status get_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t t_block, int32_t hub_part,
+                   hipStream_t s, const Plan** out, std::unique_ptr<Plan>& tmp) {
+  const bool dflt = t_lane == 16 && t_tile == TileSmall::kEdges && t_block == TileLarge::kEdges && hub_part == 1024;
+  if (!dflt) {
+    tmp.reset(new Plan());
+    LP_CHECK(build_plan(g, t_lane, t_tile, t_block, hub_part, s, *tmp));
+    *out = tmp.get();
+    return LP_OK;
+  }
+  std::lock_guard<std::mutex> lock(g->plan_mu);
+  if (!g->plan) {
+    std::unique_ptr<Plan> p(new Plan());
+    LP_CHECK(build_plan(g, t_lane, t_tile, t_block, hub_part, s, *p));
+    g->plan = p.release();
+    const_cast<lp_graph*>(g)->plan_free = plan_delete;
+  }
+  *out = (const Plan*)g->plan;
+  return LP_OK;
+}
+
+}  // namespace
+
 lp_status batch_localize(const lp_graph* b, const int32_t* lab, int32_t* out, int32_t* const* outs_dev,
                          hipStream_t s);
+
+lp_status visit_edges_cut(const lp_graph* g, const int32_t* labels, unsigned long long* cut, hipStream_t s) {
+  if (g->n == 0) return LP_OK;
+  return visit_edges_mode<kModeCut>(g, labels, nullptr, nullptr, nullptr, cut, s);
+}
+
+lp_status visit_edges_records(const lp_graph* g, const int32_t* map, const uint64_t* rbase, const uint64_t* voff,
+                              Rec* rec, hipStream_t s) {
+  if (g->n == 0) return LP_OK;
+  return visit_edges_mode<kModeRec>(g, map, rbase, voff, rec, nullptr, s);
+}
 }
 
 // One clustering call. For a batch handle, caps / seeds hold one value per
@@ -1546,8 +1901,6 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
   if (batch) labels = sc.alloc<int32_t>(n);  // global cluster IDs while the rounds run
   int64_t* gcap = batch ? sc.alloc<int64_t>(g->nbatch) : nullptr;
   uint64_t* gseed = batch ? sc.alloc<uint64_t>(g->nbatch) : nullptr;
-  int32_t* deg = sc.alloc<int32_t>(n);
-  int32_t* order = sc.alloc<int32_t>(n);
   int64_t* W = sc.alloc<int64_t>(n);
   int32_t* ptgt = sc.alloc<int32_t>(n);
   int64_t* pgain = sc.alloc<int64_t>(n);
@@ -1559,8 +1912,6 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
   int64_t* wv = sc.alloc<int64_t>(n);
   int64_t* pref = sc.alloc<int64_t>(n);
   uint8_t* flag = sc.alloc<uint8_t>(n);
-  const unsigned nbk = grid_for(n, kBkTile, 0x7FFFFFFF);
-  uint32_t* bcnt = sc.alloc<uint32_t>((size_t)kNumBuckets * nbk);
   const unsigned ncp = grid_for(n, kCpTile, 0x7FFFFFFF);
   uint32_t* pcnt = sc.alloc<uint32_t>(ncp);
   struct Ctl {
@@ -1570,7 +1921,6 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
     uint32_t pad;
     uint32_t bucket_tot[4];
     int64_t stats[128];
-    unsigned long long bsums[2 * kNumBuckets];
   };
   Ctl* ctl = sc.alloc<Ctl>(1);
   if (sc.failed) return LP_ENOMEM;
@@ -1625,125 +1975,24 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
   for (int i = 0; i < 4; ++i) LP_CHECK_HIP(hipEventCreateWithFlags(&ev.e[i], hipEventDisableTiming));
 
   LP_CHECK(begin(LP_PHASE_SETUP));
-  LP_CHECK(compute_degrees(g, deg, s));
-  // degree buckets: one stable list ordered by (bucket, vertex)
-  hipLaunchKernelGGL(k_bucket_count, dim3(nbk), dim3(kBkThreads), 0, s, deg, n, t_lane, t_tile, t_block, bcnt, nbk);
-  LP_CHECK_LAUNCH();
-  uint32_t* btot = sc.alloc<uint32_t>(1);
-  if (!btot) return LP_ENOMEM;
-  LP_CHECK(scan_exclusive_u32(bcnt, bcnt, (int64_t)kNumBuckets * nbk, btot, sc));
-  hipLaunchKernelGGL(k_bucket_scatter, dim3(nbk), dim3(kBkThreads), 0, s, deg, n, t_lane, t_tile, t_block, bcnt, nbk,
-                     order);
-  LP_CHECK_LAUNCH();
-  if (stats_out) {
-    hipLaunchKernelGGL(k_bucket_sums, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, deg, n, t_lane, t_tile, t_block,
-                       g->compressed ? g->offs : nullptr, ctl->bsums);
-    LP_CHECK_LAUNCH();
-  }
-  // bucket boundaries: offs of bucket b = bcnt[b * nbk]
-  uint32_t bstart[kNumBuckets + 1];
-  for (int b = 0; b < kNumBuckets; ++b)
-    LP_CHECK_HIP(hipMemcpyAsync(&bstart[b], bcnt + (size_t)b * nbk, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  LP_CHECK_HIP(hipMemcpyAsync(&bstart[kNumBuckets], btot, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  LP_CHECK_HIP(hipStreamSynchronize(s));
-  int32_t bn[kNumBuckets];
-  for (int b = 0; b < kNumBuckets; ++b) bn[b] = (int32_t)(bstart[b + 1] - bstart[b]);
-
-  // descriptors of the non-hub buckets
-  const int32_t nlisted = (int32_t)bstart[3];
-  int4* vdesc = sc.alloc<int4>(nlisted);
-  uint32_t* vlen = sc.alloc<uint32_t>(nlisted);
-  if (sc.failed) return LP_ENOMEM;
-  if (nlisted > 0) {
-    hipLaunchKernelGGL(k_build_desc, dim3(grid_for(nlisted, 256, 65536)), dim3(256), 0, s, g->view(), order, deg,
-                       nlisted, vdesc, vlen);
-    LP_CHECK_LAUNCH();
-  }
-  auto vd_of = [&](int b) { return VDesc{vdesc + bstart[b], vlen + bstart[b]}; };
-
-  // tiles of the two tile buckets
-  TilePlan tps, tpl;
-  const int32_t* gid = batch ? g->gid : nullptr;
-  LP_CHECK(plan_tiles<TileSmall>(vd_of(1), bn[1], g->compressed, wide, g->weighted, gid, sc, tps));
-  LP_CHECK(plan_tiles<TileLarge>(vd_of(2), bn[2], g->compressed, wide, g->weighted, gid, sc, tpl));
-
-  // hub metadata (host-built, small) and the stream descriptors of the pieces
-  const int32_t H = bn[3];
-  HubMeta hm{};
-  int32_t npieces = 0, ntasks = 0;
-  if (H > 0) {
-    std::vector<int32_t> hu(H), hd(H);
-    int32_t* hdeg_dev = sc.alloc<int32_t>(H);
-    if (!hdeg_dev) return LP_ENOMEM;
-    hipLaunchKernelGGL(k_gather_i32, dim3(grid_for(H, 256, 4096)), dim3(256), 0, s, deg, order + bstart[3], H, hdeg_dev);
-    LP_CHECK_LAUNCH();
-    LP_CHECK_HIP(hipMemcpyAsync(hu.data(), order + bstart[3], H * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    LP_CHECK_HIP(hipMemcpyAsync(hd.data(), hdeg_dev, H * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    LP_CHECK_HIP(hipStreamSynchronize(s));
-    int64_t maxd = 0;
-    for (int h = 0; h < H; ++h) maxd = std::max<int64_t>(maxd, hd[h]);
-    const int64_t part = std::max<int64_t>(hub_part, (maxd + kMaxParts - 1) / kMaxParts);
-    std::vector<int32_t> np(H), npc(H), pcb(H), tb(H);
-    std::vector<uint64_t> rbase(H), pbase(H);
-    std::vector<int2> pieces, tasks;
-    uint64_t rsum = 0, psum = 0;
-    for (int h = 0; h < H; ++h) {
-      const int64_t d = hd[h];
-      np[h] = (int32_t)std::max<int64_t>(1, (d + part - 1) / part);
-      npc[h] = (int32_t)((d + kHubPiece - 1) / kHubPiece);
-      pcb[h] = (int32_t)pieces.size();
-      rbase[h] = rsum;
-      pbase[h] = psum;
-      tb[h] = ntasks;
-      rsum += (uint64_t)d;
-      psum += (uint64_t)npc[h] * (np[h] + 1);
-      ntasks += np[h];
-      for (int k = 0; k < npc[h]; ++k) pieces.push_back(make_int2(h, k));
-      for (int p = 0; p < np[h]; ++p) tasks.push_back(make_int2(h, p));
-    }
-    npieces = (int32_t)pieces.size();
-    int32_t* d_u = sc.alloc<int32_t>(H);
-    int32_t* d_deg = sc.alloc<int32_t>(H);
-    int32_t* d_np = sc.alloc<int32_t>(H);
-    int32_t* d_npc = sc.alloc<int32_t>(H);
-    int32_t* d_pcb = sc.alloc<int32_t>(H);
-    int32_t* d_tb = sc.alloc<int32_t>(H);
-    uint64_t* d_rb = sc.alloc<uint64_t>(H);
-    uint64_t* d_pb = sc.alloc<uint64_t>(H);
-    int2* d_pieces = sc.alloc<int2>(npieces);
-    int2* d_tasks = sc.alloc<int2>(ntasks);
-    hm.streams = sc.alloc<HubStream>((size_t)npieces * kHubStreams);
-    hm.rec_c = sc.alloc<int32_t>(rsum);
-    hm.rec_r = wide ? (void*)sc.alloc<int64_t>(rsum) : (void*)sc.alloc<int32_t>(rsum);
-    hm.poff = sc.alloc<uint32_t>(psum);
+  const Plan* plan = nullptr;
+  std::unique_ptr<Plan> plan_tmp;
+  LP_CHECK(get_plan(g, t_lane, t_tile, t_block, hub_part, s, &plan, plan_tmp));
+  const int32_t* bn = plan->bn;
+  auto vd_of = [&](int b) { return plan->vd(b); };
+  const TilePlan& tps = plan->tps;
+  const TilePlan& tpl = plan->tpl;
+  const int32_t H = plan->H, npieces = plan->npieces, ntasks = plan->ntasks;
+  HubMeta hm = plan->hm;
+  if (H > 0) {  // per-call hub buffers
+    hm.rec_c = sc.alloc<int32_t>(plan->rsum);
+    hm.rec_r = wide ? (void*)sc.alloc<int64_t>(plan->rsum) : (void*)sc.alloc<int32_t>(plan->rsum);
+    hm.poff = sc.alloc<uint32_t>(plan->psum);
     hm.res_r = sc.alloc<int64_t>(ntasks);
     hm.res_key = sc.alloc<uint64_t>(ntasks);
     hm.res_c = sc.alloc<int32_t>(ntasks);
     hm.res_own = sc.alloc<int64_t>(ntasks);
     if (sc.failed) return LP_ENOMEM;
-    LP_CHECK_HIP(hipMemcpyAsync(d_u, hu.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_deg, hd.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_np, np.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_npc, npc.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_pcb, pcb.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_tb, tb.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_rb, rbase.data(), H * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_pb, pbase.data(), H * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_pieces, pieces.data(), npieces * sizeof(int2), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_tasks, tasks.data(), ntasks * sizeof(int2), hipMemcpyHostToDevice, s));
-    hm.u = d_u;
-    hm.deg = d_deg;
-    hm.nparts = d_np;
-    hm.npieces = d_npc;
-    hm.piece_base = d_pcb;
-    hm.rec_base = d_rb;
-    hm.poff_base = d_pb;
-    hm.task_base = d_tb;
-    hm.pieces = d_pieces;
-    hm.tasks = d_tasks;
-    hipLaunchKernelGGL(k_hub_streams, dim3(grid_for(H, 4, 4096)), dim3(256), 0, s, g->view(), hm, H);
-    LP_CHECK_LAUNCH();
-    LP_CHECK_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
   }
 
   hipLaunchKernelGGL(k_init, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, g->vwgt, labels, W, ptgt);
@@ -1860,8 +2109,8 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
       stats_out->moves[i] = h.stats[64 + i];
     }
     for (int b = 0; b < kNumBuckets; ++b) {
-      stats_out->bucket_edges[b] = h.bsums[b];
-      stats_out->bucket_bytes[b] = h.bsums[kNumBuckets + b];
+      stats_out->bucket_edges[b] = plan->bsums[b];
+      stats_out->bucket_bytes[b] = plan->bsums[kNumBuckets + b];
     }
     for (auto& m : marks) {
       float ms = 0;

@@ -505,6 +505,7 @@ extern "C" void lp_graph_free(lp_graph* g) {
   (void)hipFree(g->gid);
   (void)hipFree(g->gbase);
   (void)hipFree(g->deg);
+  if (g->plan && g->plan_free) g->plan_free(g->plan);
   delete g;
 }
 

@@ -4,19 +4,19 @@
 // The coarse neighbourhood of a coarse vertex a is the summed weight of the
 // fine edges leaving cluster a, keyed by the coarse ID of the other end,
 // sorted by that ID. Re-planned for gfx950 in three passes:
-//  1. record pass (edge-parallel): every fine vertex reserves a slice of its
-//     cluster's record region with one atomic and writes one (coarse ID,
-//     weight) record per neighbour (coarse ID -1 for edges inside the
-//     cluster). Short neighbourhoods are decoded by one lane, long ones by a
-//     wavefront per chunk of the compressed format.
+//  1. record pass: every fine vertex reserves a slice of its cluster's record
+//     region with one atomic, and the edge visitor of the rating path (lane,
+//     tile and hub-piece decoders over the graph's cached plan) writes one
+//     (coarse ID, weight) record per neighbour (coarse ID -1 for edges inside
+//     the cluster).
 //  2. aggregation, following the paper's two-phase aggregation
 //     (Section IV-B1): light clusters are aggregated by one wavefront or
 //     workgroup from their contiguous records in an LDS hash table, sorted
-//     in LDS and written back in place; heavy clusters (large records or
-//     too many distinct neighbours) first group their records by coarse-ID
-//     range partition in 4096-record chunks, then one workgroup per
-//     (cluster, partition) aggregates and sorts that partition. Partitions
-//     are ranges, so their outputs concatenate in order.
+//     in LDS and written back in place; heavy clusters first group their
+//     records by coarse-ID partition (cut at quantiles of a sample of their
+//     IDs) in 4096-record chunks, then one workgroup per (cluster, partition)
+//     aggregates and sorts that partition. Partitions are ID ranges, so their
+//     outputs concatenate in order.
 //  3. a prefix sum over the coarse degrees places every neighbourhood.
 #include <stdio.h>
 #include <stdlib.h>
@@ -27,12 +27,12 @@
 #include "graph.h"
 
 namespace lp {
+lp_status visit_edges_records(const lp_graph* g, const int32_t* map, const uint64_t* rbase, const uint64_t* voff,
+                              Rec* rec, hipStream_t s);
 
 namespace {
 
 constexpr uint32_t kErrLabel = 1, kErrOverflow = 2, kErrFormat = 4;
-constexpr uint32_t kShortNbh = 32;       // neighbourhoods up to this length: one lane each
-constexpr uint32_t kPiece = LP_CHUNK_LEN;  // long neighbourhoods: one wavefront per piece
 constexpr uint32_t kClassWave = 256;     // records per wavefront-cluster
 constexpr uint32_t kClassBlockS = 1024;  // records per workgroup-cluster, small table
 constexpr uint32_t kClassBlockL = 4096;  // records per workgroup-cluster, large table
@@ -44,10 +44,6 @@ constexpr uint32_t kHeavySample = 2048;  // records sampled per heavy cluster fo
 constexpr int kLightThreads = 256;
 constexpr int kReduceThreads = 256;
 
-struct Rec {
-  int32_t b;  // coarse neighbour, -1 = edge inside the cluster
-  int32_t w;
-};
 
 // ------------------------------------------------------------- setup -----
 __global__ void k_check_mark(const int32_t* C, int32_t n, uint32_t* flags, uint32_t* err) {
@@ -143,102 +139,6 @@ __global__ __launch_bounds__(256) void k_class_list(const uint8_t* cls, int32_t 
 
 __device__ __forceinline__ uint32_t ceil_log2(uint32_t x) { return x <= 1 ? 0 : 32 - __clz(x - 1); }
 
-// ------------------------------------------------------- record pass -----
-struct GenArgs {
-  GraphView g;
-  const int32_t* map;
-  const int32_t* deg;
-  const uint64_t* rbase;  // record region of each cluster
-  const uint64_t* voff;   // slice of each vertex inside its cluster's region
-  Rec* rec;
-  int2* pieces;           // long neighbourhoods: (vertex, piece)
-  uint32_t* npieces;
-  uint32_t* err;
-};
-
-__device__ __forceinline__ uint32_t pieces_of(uint32_t d, bool comp) {
-  if (comp && d <= LP_CHUNK_THRESHOLD) return 1;
-  return (d + kPiece - 1) / kPiece;
-}
-
-// Thread per vertex: short neighbourhoods are written directly, long ones are
-// listed as pieces (one atomic per wavefront).
-template <bool COMP>
-__global__ __launch_bounds__(256) void k_gen_short(GenArgs x) {
-  const int64_t step = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < x.g.n; base += step) {
-    const int64_t u = base + threadIdx.x;
-    const uint32_t d = u < x.g.n ? (uint32_t)x.deg[u] : 0;
-    const uint32_t np = d > kShortNbh ? pieces_of(d, COMP) : 0;
-    const uint32_t incl = wave_incl_scan_add(np);
-    const uint32_t tot = __shfl(incl, kWave - 1, kWave);
-    if (tot) {
-      uint32_t b = 0;
-      if (lane_id() == kWave - 1) b = atomicAdd(x.npieces, tot);
-      b = __shfl(b, kWave - 1, kWave);
-      for (uint32_t k = 0; k < np; ++k) x.pieces[b + incl - np + k] = make_int2((int)u, (int)k);
-    }
-    if (d == 0 || d > kShortNbh) continue;
-    const int32_t a = x.map[u];
-    Rec* out = x.rec + x.rbase[a] + x.voff[u];
-    auto put = [&](uint32_t i, int32_t v, int32_t w) {
-      const int32_t b = x.map[v];
-      out[i] = Rec{b == a ? -1 : b, w};
-    };
-    if constexpr (COMP) {
-      lane_decode(x.g, (int32_t)u, d, put);
-    } else {
-      const uint64_t e = x.g.xadj[u];
-      for (uint32_t k = 0; k < d; ++k) put(k, x.g.adjncy[e + k], x.g.adjwgt ? x.g.adjwgt[e + k] : 1);
-    }
-  }
-}
-
-// Wavefront per piece of a long neighbourhood.
-template <bool COMP>
-__global__ __launch_bounds__(256) void k_gen_long(GenArgs x) {
-  __shared__ DecodeSmem<kWave> dsm[4];
-  const int w = threadIdx.x / kWave;
-  const int lane = lane_id();
-  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  const int64_t cnt = *x.npieces;
-  for (int64_t i = wid; i < cnt; i += nw) {
-    const int2 pc = x.pieces[i];
-    const int32_t u = pc.x;
-    const uint32_t d = (uint32_t)x.deg[u];
-    const int32_t a = x.map[u];
-    Rec* out = x.rec + x.rbase[a] + x.voff[u];
-    auto put = [&](uint32_t j, int32_t v, int32_t wt) {
-      const int32_t b = x.map[v];
-      out[j] = Rec{b == a ? -1 : b, wt};
-    };
-    if constexpr (COMP) {
-      const Nbh h = nbh_locate(x.g, u, d);
-      const uint32_t k = (uint32_t)pc.y;
-      uint64_t pos = nbh_chunk_pos(x.g, h, k);
-      const uint32_t first = h.nchunks > 1 ? k * LP_CHUNK_LEN : 0;
-      const uint32_t len = h.nchunks > 1 ? min((uint32_t)LP_CHUNK_LEN, d - first) : d;
-      int32_t pv, pw;
-      Rec* o2 = out + first;
-      const bool ok = group_decode<kWave>(x.g.bytes, pos, u, len, x.g.weighted, true, pv, pw, dsm[w],
-                                          [&](uint32_t j, int32_t v, int32_t wt) {
-                                            const int32_t b = x.map[v];
-                                            o2[j] = Rec{b == a ? -1 : b, wt};
-                                          });
-      if (!ok && lane == 0) atomicOr(x.err, kErrFormat);
-    } else {
-      const uint32_t first = (uint32_t)pc.y * kPiece;
-      const uint32_t len = min(kPiece, d - first);
-      const uint64_t e = x.g.xadj[u] + first;
-      for (uint32_t j = lane; j < len; j += kWave) put(first + j, x.g.adjncy[e + j], x.g.adjwgt ? x.g.adjwgt[e + j] : 1);
-    }
-  }
-}
-
-// ------------------------------------------------------- LDS helpers -----
-// Insert with a reservation guard: at most `limit` distinct keys enter the
-// table; a further new key sets *overflow instead.
 __device__ __forceinline__ void tbl_add_guarded(int32_t* keys, int64_t* vals, uint32_t mask, uint32_t shift,
                                                 int32_t b, int64_t w, uint32_t limit, uint32_t* distinct,
                                                 uint32_t* overflow) {
@@ -1015,9 +915,6 @@ extern "C" lp_status lp_contract(const lp_graph* g, const int32_t* labels, int32
     uint8_t* cls = sc.alloc<uint8_t>(nc);
     uint8_t* heavy = sc.alloc<uint8_t>(nc);
     int32_t* lists = sc.alloc<int32_t>((size_t)4 * nc);
-    const uint64_t piece_cap = (uint64_t)n + g->two_m / kPiece + 1;
-    int2* pieces = sc.alloc<int2>(piece_cap);
-    if (sc.failed) { st = LP_ENOMEM; break; }
     if (hipMalloc((void**)&cg->vwgt, (size_t)nc * sizeof(int32_t)) != hipSuccess ||
         hipMalloc((void**)&cg->xadj, ((size_t)nc + 1) * sizeof(uint64_t)) != hipSuccess) { st = LP_ENOMEM; break; }
     (void)hipMemsetAsync(vw, 0, (size_t)nc * 8, s);
@@ -1038,27 +935,10 @@ extern "C" lp_status lp_contract(const lp_graph* g, const int32_t* labels, int32
                        (int64_t)nc);
     st = last_error();
     if (st) break;
-    // record pass
+    // record pass: the edge visitor shared with rating and the cut
     Rec* rec = sc.alloc<Rec>(g->two_m);
     if (sc.failed) { st = LP_ENOMEM; break; }
-    GenArgs G;
-    G.g = g->view();
-    G.map = map;
-    G.deg = deg;
-    G.rbase = rbase;
-    G.voff = voff;
-    G.rec = rec;
-    G.pieces = pieces;
-    G.npieces = &ctl->npieces;
-    G.err = &ctl->err;
-    if (g->compressed) {
-      hipLaunchKernelGGL(k_gen_short<true>, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, G);
-      hipLaunchKernelGGL(k_gen_long<true>, dim3(8192), dim3(256), 0, s, G);
-    } else {
-      hipLaunchKernelGGL(k_gen_short<false>, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, G);
-      hipLaunchKernelGGL(k_gen_long<false>, dim3(8192), dim3(256), 0, s, G);
-    }
-    st = last_error();
+    st = visit_edges_records(g, map, rbase, voff, rec, s);
     if (st) break;
     if (hipMemcpyAsync(&h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) { st = LP_EDEVICE; break; }

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <vector>
 
 #include "lp_device.h"
@@ -34,6 +35,11 @@ struct lp_graph {
   int32_t* gbase = nullptr;   // nbatch + 1: first vertex of each graph
   int32_t* deg = nullptr;     // n: degrees (first-edge headers restart per graph)
   std::vector<int32_t> vbase; // host copy of gbase
+  // degree buckets, tiles and hub pieces for the default thresholds, built on
+  // first use (a derived, result-free cache; the graph itself never changes)
+  mutable void* plan = nullptr;
+  void (*plan_free)(void*) = nullptr;
+  mutable std::mutex plan_mu;
 
   lp::GraphView view() const {
     lp::GraphView v;

@@ -75,6 +75,13 @@ __device__ __forceinline__ uint64_t read_header(const GraphView& g, int32_t u, u
   return varint_read(g.bytes, pos);
 }
 
+// One contraction record per fine edge: the coarse vertex of the neighbour
+// (-1 for an edge inside the cluster) and the edge weight.
+struct Rec {
+  int32_t b;
+  int32_t w;
+};
+
 // ------------------------------------------------------------ wave ops ----
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
