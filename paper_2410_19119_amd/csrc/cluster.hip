@@ -261,6 +261,7 @@ struct TileShared {
   int64_t own_r[VT];
   int64_t gain[VT];
   VParams vp;  // the tile's graph (tiles never span two graphs of a batch)
+  uint32_t max_nsl;  // most table slots of one vertex of the tile
   uint64_t rb[VT];  // records: first record of every vertex
   unsigned long long red_u[NT / kWave];
   int32_t scan[NT / kWave];
@@ -387,6 +388,83 @@ __device__ __forceinline__ uint32_t window_value(uint64_t w, uint64_t term, uint
   return v;
 }
 
+// Best candidate and sum over groups of G lanes of a wavefront (G <= 64).
+template <int G>
+__device__ __forceinline__ Cand group_best_lanes(Cand x) {
+#pragma unroll
+  for (int d = G / 2; d > 0; d >>= 1) {
+    Cand y;
+    y.r = __shfl_xor(x.r, d, G);
+    y.key = __shfl_xor(x.key, d, G);
+    y.c = __shfl_xor(x.c, d, G);
+    if (cand_better(y, x)) x = y;
+  }
+  return x;
+}
+
+template <int G>
+__device__ __forceinline__ int64_t group_sum_lanes(int64_t v) {
+#pragma unroll
+  for (int d = G / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, G);
+  return v;
+}
+
+// Selection over the tile's vertices by groups of G threads (G lanes of a
+// wavefront, or the whole workgroup when G == NT): a group walks one
+// vertex's slots. First walk (redo == false): own rating and best other
+// cluster by (rating desc, key asc). Capped walk (redo == true), only for the
+// vertices marked -2: the best cluster beating the own rating whose weight
+// leaves room for the vertex.
+template <int G, int NT, typename V, class SH>
+__device__ __forceinline__ void tile_select(const RoundCtx& x, const int32_t* keys, const V* vals, SH& sh,
+                                            int32_t nv, int tid, bool redo) {
+  constexpr int NG = NT / G;
+  const int gi = tid / G, gl = tid % G;
+  for (int32_t i = gi; i < nv; i += NG) {
+    if (redo && sh.best_c[i] != -2) continue;  // uniform across the group
+    const uint32_t b0 = sh.tbase[i], b1 = sh.tbase[i + 1];
+    const int32_t oc = sh.own_c[i];
+    const int64_t own0 = redo ? sh.own_r[i] : 0;
+    const int64_t wu = sh.wu[i];
+    int64_t own = 0;
+    Cand best = cand_none();
+    for (uint32_t q = b0 + gl; q < b1; q += G) {
+      const int32_t c = keys[q];
+      if (c == kEmpty) continue;
+      const int64_t r = (int64_t)vals[q];
+      if (c == oc) {
+        own = r;
+        continue;
+      }
+      if (r < best.r || (redo && r <= own0)) continue;
+      const Cand cd{r, cluster_key(x, sh.vp, c), c};
+      if (cand_better(cd, best) && (!redo || x.W[c] + wu <= sh.vp.cap)) best = cd;
+    }
+    if constexpr (G == NT && NT > kWave) {
+      best = block_best<NT>(best, sh.cb);
+      own = block_reduce_add<NT, int64_t>(own, sh.red);
+    } else {
+      best = group_best_lanes<G>(best);
+      own = group_sum_lanes<G>(own);
+    }
+    if (gl == 0) {
+      if (!redo) {
+        sh.own_r[i] = own;
+        sh.best_c[i] = best.r > own ? best.c : -1;
+        sh.gain[i] = best.r - own;
+      } else {
+        const int32_t u = sh.u[i];
+        if (best.c >= 0) {
+          x.ptgt[u] = best.c;
+          x.pgain[u] = best.r - own0;
+        } else {
+          x.ptgt[u] = -1;
+        }
+      }
+    }
+  }
+}
+
 template <class T, typename V, bool COMP, int MODE = kModeRate>
 __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd, const int32_t* tiles,
                                                            const uint32_t* ntiles_p, TileLayout L) {
@@ -454,6 +532,7 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
         sh.tbase[nv] = (uint32_t)tot2 >> 16;
         sh.any_redo = 0;
         sh.seg_flags = 0;
+        sh.max_nsl = 0;
         sh.vp = vparams(x, sh.u[0]);
       }
     }
@@ -601,6 +680,7 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
       continue;
     }
     __syncthreads();  // numbers consumed: region A becomes the table
+    if (tid < nv) atomicMax(&sh.max_nsl, sh.tbase[tid + 1] - sh.tbase[tid]);
     for (uint32_t q = tid; q < St; q += NT) keys[q] = kEmpty;
     for (uint32_t q = tid; q < St; q += NT) vals[q] = 0;
     __syncthreads();
@@ -612,37 +692,11 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
       tile_insert<V>(keys, vals, sh.tbase[i], sh.tbase[i + 1] - sh.tbase[i], nb[k], (V)wt[k]);
     }
     __syncthreads();
-    // 5. selection: one walk over the slots of each vertex
-    for (int32_t i = sgi; i < nv; i += NSG) {
-      const uint32_t b0 = sh.tbase[i], b1 = sh.tbase[i + 1];
-      const int32_t oc = sh.own_c[i];
-      int64_t own = 0;
-      Cand best = cand_none();
-      for (uint32_t q = b0 + sl; q < b1; q += SG) {
-        const int32_t c = keys[q];
-        if (c == kEmpty) continue;
-        const int64_t r = (int64_t)vals[q];
-        if (c == oc) {
-          own = r;
-          continue;
-        }
-        if (r < best.r) continue;
-        const Cand cd{r, cluster_key(x, sh.vp, c), c};
-        if (cand_better(cd, best)) best = cd;
-      }
-      if constexpr (SG == kWave) {
-        best = wave_best(best);
-        own = wave_reduce_add(own);
-      } else {
-        best = block_best<NT>(best, sh.cb);
-        own = block_reduce_add<NT, int64_t>(own, sh.red);
-      }
-      if (sl == 0) {
-        sh.own_r[i] = own;
-        sh.best_c[i] = best.r > own ? best.c : -1;
-        sh.gain[i] = best.r - own;
-      }
-    }
+    // 5. selection: one walk over the slots of each vertex; tiles of small
+    // vertices use 16-lane groups (four vertices per wavefront at a time)
+    const bool small_v = SG == kWave && sh.max_nsl <= 256;
+    if (small_v) tile_select<16, NT, V>(x, keys, vals, sh, nv, tid, false);
+    else tile_select<SG, NT, V>(x, keys, vals, sh, nv, tid, false);
     __syncthreads();
     if (tid < nv) {
       const int32_t u = sh.u[tid];
@@ -659,33 +713,8 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
     }
     __syncthreads();
     if (sh.any_redo) {
-      for (int32_t i = sgi; i < nv; i += NSG) {
-        if (sh.best_c[i] != -2) continue;  // uniform across the selection group
-        const uint32_t b0 = sh.tbase[i], b1 = sh.tbase[i + 1];
-        const int32_t oc = sh.own_c[i];
-        const int64_t own = sh.own_r[i];
-        const int64_t wu = sh.wu[i];
-        Cand best = cand_none();
-        for (uint32_t q = b0 + sl; q < b1; q += SG) {
-          const int32_t c = keys[q];
-          if (c == kEmpty || c == oc) continue;
-          const int64_t r = (int64_t)vals[q];
-          if (r <= own || r < best.r) continue;
-          const Cand cd{r, cluster_key(x, sh.vp, c), c};
-          if (cand_better(cd, best) && x.W[c] + wu <= sh.vp.cap) best = cd;
-        }
-        if constexpr (SG == kWave) best = wave_best(best);
-        else best = block_best<NT>(best, sh.cb);
-        if (sl == 0) {
-          const int32_t u = sh.u[i];
-          if (best.c >= 0) {
-            x.ptgt[u] = best.c;
-            x.pgain[u] = best.r - own;
-          } else {
-            x.ptgt[u] = -1;
-          }
-        }
-      }
+      if (small_v) tile_select<16, NT, V>(x, keys, vals, sh, nv, tid, true);
+      else tile_select<SG, NT, V>(x, keys, vals, sh, nv, tid, true);
     }
     __syncthreads();
   }
