@@ -205,11 +205,13 @@ def bench_serve(args) -> dict:
         lp.coarsen(h, seed=1)
     torch.cuda.synchronize()
     rates = [float(r) for r in (args.serve_rates or "10,30,100,300,1000").split(",")]
-    out = {"pool": len(pool), "requests_per_rate": args.serve_requests, "budget_bytes": 200 * 10**9, "rates": {}}
+    out = {"pool": len(pool), "requests_per_rate": args.serve_requests, "budget_bytes": 200 * 10**9,
+           "split_edges": args.serve_split, "rates": {}}
     for rate in rates:
         reqs = serve.requests(synth.serve_trace(rate, args.serve_requests, len(pool), seed=7))
         seq = serve.summarize(serve.run_sequential(pool, reqs))
-        srv_obj = serve.Server(pool, budget_bytes=200 * 10**9, max_active=args.serve_slots)
+        srv_obj = serve.Server(pool, budget_bytes=200 * 10**9, max_active=args.serve_slots,
+                               split_edges=args.serve_split)
         res = srv_obj.run(reqs)
         srv = serve.summarize(res)
         srv["peak_active"] = srv_obj.peak_active
@@ -342,6 +344,8 @@ def main() -> int:
                     help="comma-separated request rates (default: 10..1000 for --workload serve, "
                          "100,1000 inside the default run)")
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-split", type=int, default=0,
+                    help="directed edges from which a job runs in the big-job lane (0: one lane)")
     ap.add_argument("--coarsen-graph", default="rmat", choices=["rmat", "rgg3d"])
     ap.add_argument("--coarsen-scale", type=int, default=26)
     ap.add_argument("--no-checks", action="store_true")

@@ -25,6 +25,13 @@
  *    fault surfaces as LP_EDEVICE from the next synchronising call.
  *  - Handles are immutable after creation; one handle may be used from
  *    several streams at once. Each handle must be freed with lp_graph_free.
+ *    Handles made by lp_compress and lp_graph_import use plain device
+ *    allocations. Handles made inside a call on a stream (lp_contract's
+ *    coarse graph, lp_batch_create's batch) take their buffers from the
+ *    device's stream-ordered pool on that stream ("its stream") and are
+ *    released in that stream's order: work on any other stream that uses
+ *    such a handle must be ordered before its stream (an event, or a
+ *    synchronisation) by the caller before lp_graph_free.
  *  - Integer widths: vertex IDs and labels int32 (n < 2^31), edge counts
  *    and offsets uint64, input edge / vertex weights int32 >= 1, ratings,
  *    gains, cluster weights and caps int64.
@@ -259,7 +266,10 @@ lp_status lp_contract(const lp_graph *g, const int32_t *labels_dev, int32_t *map
  */
 lp_status lp_edge_cut(const lp_graph *g, const int32_t *labels_dev, int64_t *cut_out, void *stream);
 
-/* Frees a handle (NULL is ignored). Waits for the device to be idle first. */
+/* Frees a handle (NULL is ignored). A handle with plain allocations waits
+ * for the device to be idle first; a handle made on a stream is released on
+ * its stream (hipFreeAsync) without waiting, so later work on that stream
+ * runs after the release and work already queued on it before. */
 void lp_graph_free(lp_graph *g);
 
 #ifdef __cplusplus

@@ -160,12 +160,14 @@ extern "C" lp_status lp_batch_create(int32_t G, const lp_graph* const* gs, void*
   b->nbytes = comp ? nb : 0;
   b->nbatch = G;
   b->vbase = vbase;
+  b->stream_mem = true;
+  b->mem_stream = s;
   lp_status st = LP_OK;
   Scratch sc(s);
   std::vector<const void*> all;  // per-graph pointer tables (live until the final synchronisation)
   do {
     auto dmalloc = [&](void** p, size_t bytes) {
-      if (st == LP_OK && hipMalloc(p, bytes ? bytes : 1) != hipSuccess) st = LP_ENOMEM;
+      if (st == LP_OK && graph_alloc(b, p, bytes) != hipSuccess) st = LP_ENOMEM;
     };
     dmalloc((void**)&b->gid, (size_t)n * sizeof(int32_t));
     dmalloc((void**)&b->deg, (size_t)n * sizeof(int32_t));

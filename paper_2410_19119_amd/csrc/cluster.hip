@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <memory>
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -1520,19 +1521,26 @@ lp_status set_lds(F* kern, size_t bytes) {
 }
 
 // LDS layout of a rating group for degrees up to dmax.
-// Side streams of the current device (created once, default priority, kept
-// until the process ends); several host threads may share them, which only
-// adds ordering.
+// Side streams of the current device (created on first use, default
+// priority, kept until the process ends). Host threads take sets in turn, so
+// calls made at the same time from different threads (up to kSideSets of
+// them) do not queue behind each other's side work; threads that share a set
+// only add ordering, never a wrong result (every wait is on an event the same
+// call recorded before).
+constexpr int kSideSets = 4;
 lp_status side_stream(int i, hipStream_t* out) {
   constexpr int kMaxDev = 64;
   static std::mutex mu;
-  static hipStream_t pool[kMaxDev][3] = {};
+  static hipStream_t pool[kMaxDev][kSideSets][3] = {};
+  static std::atomic<unsigned> next_set{0};
+  thread_local const unsigned set = next_set.fetch_add(1) % kSideSets;
   int dev = 0;
   LP_CHECK_HIP(hipGetDevice(&dev));
   if (dev < 0 || dev >= kMaxDev) return LP_EUNSUPPORTED;
   std::lock_guard<std::mutex> lock(mu);
-  if (!pool[dev][i]) LP_CHECK_HIP(hipStreamCreateWithFlags(&pool[dev][i], hipStreamNonBlocking));
-  *out = pool[dev][i];
+  hipStream_t& st = pool[dev][set][i];
+  if (!st) LP_CHECK_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  *out = st;
   return LP_OK;
 }
 
@@ -1590,14 +1598,21 @@ struct TilePlan {
   unsigned grid = 0;
 };
 
-// Device memory of a plan: plain allocations freed with the plan.
+// Device memory of a plan, freed with the plan. For a handle whose buffers
+// are stream-ordered the plan is too: allocated on the building call's stream
+// (which is synchronised before the plan is used elsewhere) and released in
+// the order of the handle's stream.
 struct PlanMem {
   std::vector<void*> ptrs;
   bool failed = false;
+  bool stream_mem = false;
+  hipStream_t alloc_stream = nullptr, free_stream = nullptr;
   template <typename T>
   T* alloc(size_t n) {
     void* p = nullptr;
-    if (hipMalloc(&p, (n ? n : 1) * sizeof(T)) != hipSuccess) {
+    const size_t bytes = (n ? n : 1) * sizeof(T);
+    const hipError_t e = stream_mem ? hipMallocAsync(&p, bytes, alloc_stream) : hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
       failed = true;
       return nullptr;
     }
@@ -1605,7 +1620,10 @@ struct PlanMem {
     return (T*)p;
   }
   ~PlanMem() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) {
+      if (stream_mem) (void)hipFreeAsync(p, free_stream);
+      else (void)hipFree(p);
+    }
   }
 };
 
@@ -1672,6 +1690,9 @@ lp_status build_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t 
   P.hub_part = hub_part;
   P.wide = g->max_wdeg > 0x7FFFFFFFll;
   const bool batch = g->nbatch > 0;
+  P.mem.stream_mem = g->stream_mem;
+  P.mem.alloc_stream = s;
+  P.mem.free_stream = g->mem_stream;
   Scratch sc(s);
   int32_t* deg = sc.alloc<int32_t>(n);
   const unsigned nbk = grid_for(n, kBkTile, 0x7FFFFFFF);
@@ -1858,6 +1879,7 @@ lp_status get_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t t_
   if (!dflt) {
     tmp.reset(new Plan());
     LP_CHECK(build_plan(g, t_lane, t_tile, t_block, hub_part, s, *tmp));
+    tmp->mem.free_stream = s;  // used by this call only
     *out = tmp.get();
     return LP_OK;
   }

@@ -495,17 +495,17 @@ extern "C" lp_status lp_graph_info(const lp_graph* g, int32_t* n, uint64_t* two_
 
 extern "C" void lp_graph_free(lp_graph* g) {
   if (!g) return;
-  (void)hipDeviceSynchronize();
-  (void)hipFree(g->offs);
-  (void)hipFree(g->bytes);
-  (void)hipFree(g->xadj);
-  (void)hipFree(g->adjncy);
-  (void)hipFree(g->adjwgt);
-  (void)hipFree(g->vwgt);
-  (void)hipFree(g->gid);
-  (void)hipFree(g->gbase);
-  (void)hipFree(g->deg);
-  if (g->plan && g->plan_free) g->plan_free(g->plan);
+  void* bufs[] = {g->offs, g->bytes, g->xadj, g->adjncy, g->adjwgt, g->vwgt, g->gid, g->gbase, g->deg};
+  if (g->stream_mem) {
+    // released in the order of the stream that made the handle
+    if (g->plan && g->plan_free) g->plan_free(g->plan);
+    for (void* p : bufs)
+      if (p) (void)hipFreeAsync(p, g->mem_stream);
+  } else {
+    (void)hipDeviceSynchronize();
+    if (g->plan && g->plan_free) g->plan_free(g->plan);
+    for (void* p : bufs) (void)hipFree(p);
+  }
   delete g;
 }
 

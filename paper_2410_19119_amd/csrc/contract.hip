@@ -882,12 +882,14 @@ extern "C" lp_status lp_contract(const lp_graph* g, const int32_t* labels, int32
   LP_CHECK_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), s));
   lp_graph* cg = new lp_graph();
   (void)hipGetDevice(&cg->device);
+  cg->stream_mem = true;
+  cg->mem_stream = s;
   lp_status st = LP_OK;
   unsigned long long* mx = nullptr;
   unsigned long long mxh[2] = {0, 0};
   do {
     if (n == 0) {
-      if (hipMalloc((void**)&cg->xadj, sizeof(uint64_t)) != hipSuccess) { st = LP_ENOMEM; break; }
+      if (graph_alloc(cg, (void**)&cg->xadj, sizeof(uint64_t)) != hipSuccess) { st = LP_ENOMEM; break; }
       if (hipMemsetAsync(cg->xadj, 0, sizeof(uint64_t), s) != hipSuccess) { st = LP_EDEVICE; break; }
       break;
     }
@@ -915,8 +917,8 @@ extern "C" lp_status lp_contract(const lp_graph* g, const int32_t* labels, int32
     uint8_t* cls = sc.alloc<uint8_t>(nc);
     uint8_t* heavy = sc.alloc<uint8_t>(nc);
     int32_t* lists = sc.alloc<int32_t>((size_t)4 * nc);
-    if (hipMalloc((void**)&cg->vwgt, (size_t)nc * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc((void**)&cg->xadj, ((size_t)nc + 1) * sizeof(uint64_t)) != hipSuccess) { st = LP_ENOMEM; break; }
+    if (graph_alloc(cg, (void**)&cg->vwgt, (size_t)nc * sizeof(int32_t)) != hipSuccess ||
+        graph_alloc(cg, (void**)&cg->xadj, ((size_t)nc + 1) * sizeof(uint64_t)) != hipSuccess) { st = LP_ENOMEM; break; }
     (void)hipMemsetAsync(vw, 0, (size_t)nc * 8, s);
     (void)hipMemsetAsync(dsum, 0, (size_t)nc * 8, s);
     (void)hipMemsetAsync(cursor, 0, (size_t)nc * 8, s);
@@ -989,8 +991,8 @@ extern "C" lp_status lp_contract(const lp_graph* g, const int32_t* labels, int32
     if (h.err) { st = LP_EOVERFLOW; break; }
     cg->two_m = h.two_mc;
     cg->weighted = 1;
-    if (hipMalloc((void**)&cg->adjncy, (h.two_mc ? h.two_mc : 1) * sizeof(int32_t)) != hipSuccess ||
-        hipMalloc((void**)&cg->adjwgt, (h.two_mc ? h.two_mc : 1) * sizeof(int32_t)) != hipSuccess) { st = LP_ENOMEM; break; }
+    if (graph_alloc(cg, (void**)&cg->adjncy, (h.two_mc ? h.two_mc : 1) * sizeof(int32_t)) != hipSuccess ||
+        graph_alloc(cg, (void**)&cg->adjwgt, (h.two_mc ? h.two_mc : 1) * sizeof(int32_t)) != hipSuccess) { st = LP_ENOMEM; break; }
     mx = sc.alloc<unsigned long long>(2);
     unsigned long long* hsum = H > 0 ? sc.alloc<unsigned long long>(H) : nullptr;
     if (!mx || (H > 0 && !hsum)) { st = LP_ENOMEM; break; }

@@ -15,6 +15,10 @@ meanwhile join at the next step. A job's result does not depend on the mix:
 the batched clustering gives every graph exactly the labels of a run alone,
 and each job's seeds, caps and stop rule are its own.
 
+Optionally, jobs are split by size into two such loops, each on its own host
+thread and stream (big graphs, and the rest), so small jobs do not wait for
+the levels of big ones and both share the device.
+
 The sequential baseline runs the same requests one at a time in arrival order
 (``coarsen`` per request). Both report throughput and latency percentiles of
 completion time minus arrival time under the same arrival trace.
@@ -22,6 +26,7 @@ completion time minus arrival time under the same arrival trace.
 from __future__ import annotations
 
 import math
+import threading
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -107,94 +112,143 @@ def run_sequential(pool: list[Graph], reqs: list[Request], rounds: int = 5, keep
 
 
 class Server:
-    """Continuous-batching server over a resident pool of graphs."""
+    """Continuous-batching server over a resident pool of graphs.
+
+    With ``split_edges > 0`` jobs are split by size into two lanes: jobs on
+    graphs with at least ``split_edges`` directed edges, and the rest. Each
+    lane is its own continuous-batching loop on its own host thread and
+    stream, so a step of small jobs never waits for the level of a big one,
+    and the two lanes' kernels share the device; this lowers the median
+    latency but costs throughput, so the default is one lane. The slot limit
+    holds per lane; the memory budget is shared."""
 
     def __init__(self, pool: list[Graph], budget_bytes: int = 200 * 10**9, max_active: int = 64,
-                 rounds: int = 5, max_levels: int = 32, keep_labels: bool = False):
+                 rounds: int = 5, max_levels: int = 32, keep_labels: bool = False, split_edges: int = 0):
         self.pool = pool
         self.budget = budget_bytes - sum(g.nbytes + 8 * (g.n + 1) for g in pool)
         self.max_active = max_active
         self.rounds = rounds
         self.max_levels = max_levels
         self.keep_labels = keep_labels
+        self.split_edges = split_edges
         self.peak_active = 0
         self.steps = 0
+        self._mu = threading.Lock()
+        self._used = 0
+        self._active = 0
 
     def run(self, reqs: list[Request]) -> list[Result]:
-        import torch
-
-        pending = deque(sorted(reqs, key=lambda q: q.arrival))
-        active: list[_Job] = []
-        used = 0
-        results = []
+        if self.split_edges > 0:
+            big = [r for r in reqs if self.pool[r.graph].two_m >= self.split_edges]
+            lanes = [[r for r in reqs if self.pool[r.graph].two_m < self.split_edges], big]
+        else:
+            lanes = [list(reqs)]
+        lanes = [ln for ln in lanes if ln]
+        results: list[Result] = []
+        errors: list[BaseException] = []
         t0 = time.perf_counter()
-        while pending or active:
-            now = time.perf_counter() - t0
-            # admission: arrived, a free slot, and the memory estimate fits
-            while pending and pending[0].arrival <= now and len(active) < self.max_active:
-                r = pending[0]
-                g = self.pool[r.graph]
-                est = job_bytes(g)
-                if used + est > self.budget and active:
-                    break
-                pending.popleft()
-                used += est
-                n_target, cap = coarsen_params(g.n, g.total_vwgt)
-                active.append(_Job(r, g, False, n_target, cap, 0, est, Result(r.rid, r.arrival, now, 0.0)))
-            if not active:
-                _wait_until(t0, pending[0].arrival)
-                continue
-            self.peak_active = max(self.peak_active, len(active))
-            self.steps += 1
-            # jobs already at their target leave without another level
-            still = []
-            for j in active:
-                if j.cur.n <= j.n_target or j.level >= self.max_levels:
-                    self._finish(j, t0, results)
-                    used -= j.est
-                else:
-                    still.append(j)
-            active = still
-            if not active:
-                continue
-            # one level for every active job: batched clustering per representation
-            labels = {}
-            kinds = sorted({(j.cur.compressed, j.cur.weighted) for j in active})
-            for kind in kinds:
-                grp = [j for j in active if (j.cur.compressed, j.cur.weighted) == kind]
-                outs = lp_batch_cluster([j.cur for j in grp], [j.cap for j in grp], self.rounds,
-                                        [j.req.seed + j.level for j in grp])
-                for j, lab in zip(grp, outs):
-                    labels[id(j)] = lab
-            still = []
-            for j in active:
-                lab = labels[id(j)]
-                nxt, _ = lp_contract(j.cur, lab, want_map=False)
-                j.result.levels.append((j.cur.n, j.cur.two_m))
-                if self.keep_labels:
-                    j.result.labels.append(lab.clone())
-                prev_n = j.cur.n
-                if j.owned:
-                    j.cur.free()
-                j.cur, j.owned = nxt, True
-                j.level += 1
-                if 100 * j.cur.n > 95 * prev_n or j.cur.n <= j.n_target or j.level >= self.max_levels:
-                    self._finish(j, t0, results)
-                    used -= j.est
-                else:
-                    still.append(j)
-            active = still
+
+        def lane(rs):
+            try:
+                self._lane(rs, t0, results)
+            except BaseException as e:  # re-raised by run()
+                errors.append(e)
+
+        threads = [threading.Thread(target=lane, args=(rs,)) for rs in lanes[1:]]
+        for t in threads:
+            t.start()
+        if lanes:
+            lane(lanes[0])
+        for t in threads:
+            t.join()
+        if errors:
+            raise errors[0]
         return sorted(results, key=lambda r: r.rid)
 
-    def _finish(self, j: _Job, t0: float, results: list) -> None:
+    def _admit(self, est: int, lane_active: int) -> bool:
+        with self._mu:
+            if self._used + est > self.budget and lane_active:
+                return False
+            self._used += est
+            self._active += 1
+            self.peak_active = max(self.peak_active, self._active)
+            return True
+
+    def _release(self, est: int) -> None:
+        with self._mu:
+            self._used -= est
+            self._active -= 1
+
+    def _lane(self, reqs: list[Request], t0: float, results: list) -> None:
         import torch
 
-        torch.cuda.synchronize()
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            pending = deque(sorted(reqs, key=lambda q: q.arrival))
+            active: list[_Job] = []
+            while pending or active:
+                now = time.perf_counter() - t0
+                # admission: arrived, a free slot, and the memory estimate fits
+                while pending and pending[0].arrival <= now and len(active) < self.max_active:
+                    r = pending[0]
+                    g = self.pool[r.graph]
+                    est = job_bytes(g)
+                    if not self._admit(est, len(active)):
+                        break
+                    pending.popleft()
+                    n_target, cap = coarsen_params(g.n, g.total_vwgt)
+                    active.append(_Job(r, g, False, n_target, cap, 0, est, Result(r.rid, r.arrival, now, 0.0)))
+                if not active:
+                    _wait_until(t0, pending[0].arrival)
+                    continue
+                with self._mu:
+                    self.steps += 1
+                # jobs already at their target leave without another level
+                still = []
+                for j in active:
+                    if j.cur.n <= j.n_target or j.level >= self.max_levels:
+                        self._finish(j, t0, results, stream)
+                    else:
+                        still.append(j)
+                active = still
+                if not active:
+                    continue
+                # one level for every active job: batched clustering per representation
+                labels = {}
+                kinds = sorted({(j.cur.compressed, j.cur.weighted) for j in active})
+                for kind in kinds:
+                    grp = [j for j in active if (j.cur.compressed, j.cur.weighted) == kind]
+                    outs = lp_batch_cluster([j.cur for j in grp], [j.cap for j in grp], self.rounds,
+                                            [j.req.seed + j.level for j in grp])
+                    for j, lab in zip(grp, outs):
+                        labels[id(j)] = lab
+                still = []
+                for j in active:
+                    lab = labels[id(j)]
+                    nxt, _ = lp_contract(j.cur, lab, want_map=False)
+                    j.result.levels.append((j.cur.n, j.cur.two_m))
+                    if self.keep_labels:
+                        j.result.labels.append(lab.clone())
+                    prev_n = j.cur.n
+                    if j.owned:
+                        j.cur.free()  # made on this stream: released in its order
+                    j.cur, j.owned = nxt, True
+                    j.level += 1
+                    if 100 * j.cur.n > 95 * prev_n or j.cur.n <= j.n_target or j.level >= self.max_levels:
+                        self._finish(j, t0, results, stream)
+                    else:
+                        still.append(j)
+                active = still
+
+    def _finish(self, j: _Job, t0: float, results: list, stream) -> None:
+        stream.synchronize()
         j.result.final_n = j.cur.n
         j.result.done = time.perf_counter() - t0
         if j.owned:
             j.cur.free()
-        results.append(j.result)
+        self._release(j.est)
+        with self._mu:
+            results.append(j.result)
 
 
 def summarize(results: list[Result]) -> dict:

@@ -13,13 +13,17 @@ def _pool(lp, synth_mod):
     return gs, [lp.lp_compress(g.n, g.xadj.view(np.int64), g.adjncy) for g in gs]
 
 
-@pytest.mark.parametrize("slots,budget", [(64, 200 * 10**9), (3, 200 * 10**9), (64, 1)])
-def test_served_results_equal_alone(lp, synth_mod, slots, budget):
+@pytest.mark.parametrize("slots,budget,split", [(64, 200 * 10**9, 1 << 22), (3, 200 * 10**9, 1 << 22),
+                                                (64, 1, 1 << 22), (64, 200 * 10**9, 60000),
+                                                (2, 200 * 10**9, 60000), (64, 1, 60000), (64, 200 * 10**9, 0)])
+def test_served_results_equal_alone(lp, synth_mod, slots, budget, split):
     from paper_2410_19119_amd import serve
 
     gs, pool = _pool(lp, synth_mod)
+    if 0 < split < 1 << 22:  # both lanes get jobs
+        assert min(g.two_m for g in pool) < split <= max(g.two_m for g in pool)
     reqs = serve.requests(synth_mod.serve_trace(2000.0, 25, len(pool), seed=3))
-    srv = serve.Server(pool, budget_bytes=budget, max_active=slots, keep_labels=True)
+    srv = serve.Server(pool, budget_bytes=budget, max_active=slots, keep_labels=True, split_edges=split)
     res = srv.run(reqs)
     assert [r.rid for r in res] == list(range(len(reqs)))
     if slots > 3 and budget > 1:
