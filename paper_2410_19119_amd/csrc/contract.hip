@@ -36,7 +36,8 @@ constexpr uint32_t kErrLabel = 1, kErrOverflow = 2, kErrFormat = 4;
 constexpr uint32_t kClassWave = 256;     // records per wavefront-cluster
 constexpr uint32_t kClassBlockS = 1024;  // records per workgroup-cluster, small table
 constexpr uint32_t kClassBlockL = 4096;  // records per workgroup-cluster, large table
-constexpr uint32_t kHeavyChunk = 4096;   // records per partitioning chunk
+constexpr uint32_t kHeavyChunk = 16384;  // records per partitioning chunk
+constexpr int kHeavyUnroll = 8;          // records in flight per thread while partitioning
 constexpr uint32_t kHeavyTable = 4096;   // LDS entries of a heavy (cluster, partition) task
 constexpr uint32_t kHeavyPart = 1024;    // records per heavy partition (target)
 constexpr uint32_t kMaxHeavyParts = 4096;
@@ -371,8 +372,8 @@ struct Heavy {
   const uint64_t* pbase;    // first chunk-table entry of each heavy cluster
   const int2* chunks;       // (heavy cluster, chunk index)
   const int2* tasks;        // (heavy cluster, partition)
-  Rec* rec2;                // records regrouped by partition inside each chunk
-  uint32_t* ctab;           // per chunk: P + 1 partition offsets
+  Rec* rec2;                // records regrouped by task, at the task's staging base
+  uint32_t* ctab;           // per chunk: P counts, then the chunk's first position inside each task
   uint64_t* tcnt;           // records per task, then (scanned) staging base
   Rec* out;                 // heavy staging
   uint64_t* tdeg;           // distinct coarse neighbours per task
@@ -389,7 +390,7 @@ __global__ void k_heavy_meta(const int32_t* hl, int32_t H, const unsigned long l
     parts[h] = (int32_t)P;
     pcount[h] = P;
     ccount[h] = nch;
-    tabcount[h] = (uint64_t)nch * (P + 1);
+    tabcount[h] = (uint64_t)nch * P;
   }
 }
 
@@ -448,9 +449,9 @@ __device__ __forceinline__ uint32_t split_part(int32_t b, const int32_t* bnd, ui
   return lo - 1;
 }
 
-// One workgroup per chunk: group the chunk's records by partition
-// (records inside the cluster are dropped).
-__global__ __launch_bounds__(256) void k_heavy_partition(AggArgs A, Heavy hv, int32_t nchunks) {
+// One workgroup per chunk: the chunk's records per partition (records inside
+// the cluster are not counted), written to the chunk's row of the table.
+__global__ __launch_bounds__(256) void k_heavy_hist(AggArgs A, Heavy hv, int32_t nchunks) {
   __shared__ uint32_t hist[kMaxHeavyParts];
   __shared__ int32_t sbnd[kMaxHeavyParts + 1];
   for (int64_t ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {
@@ -461,41 +462,31 @@ __global__ __launch_bounds__(256) void k_heavy_partition(AggArgs A, Heavy hv, in
     const uint64_t off = (uint64_t)ch.y * kHeavyChunk;
     const uint32_t len = (uint32_t)std::min<uint64_t>(kHeavyChunk, A.dsum[a] - off);
     const Rec* src = A.rec + A.rbase[a] + off;
-    Rec* dst = hv.rec2 + A.rbase[a] + off;
-    uint32_t* tab = hv.ctab + hv.pbase[h] + (uint64_t)ch.y * (P + 1);
     const int32_t* bnd = hv.bnd + hv.tbase[h] + h;
     for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) hist[j] = 0;
     for (uint32_t j = threadIdx.x; j <= P; j += blockDim.x) sbnd[j] = bnd[j];
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
-      const Rec x = src[i];
-      if (x.b >= 0) atomicAdd(&hist[split_part(x.b, sbnd, P)], 1u);
-    }
-    __syncthreads();
-    if (threadIdx.x < kWave) {  // one wavefront scans the histogram
-      uint32_t carry = 0;
-      for (uint32_t b0 = 0; b0 < P; b0 += kWave) {
-        const uint32_t j = b0 + lane_id();
-        const uint32_t v = j < P ? hist[j] : 0;
-        const uint32_t inc = wave_incl_scan_add(v);
-        if (j < P) {
-          hist[j] = carry + inc - v;
-          tab[j] = carry + inc - v;
-        }
-        carry += __shfl(inc, kWave - 1, kWave);
+    for (uint32_t i0 = 0; i0 < len; i0 += 256 * kHeavyUnroll) {
+      Rec x[kHeavyUnroll];
+#pragma unroll
+      for (int u = 0; u < kHeavyUnroll; ++u) {
+        const uint32_t i = i0 + u * 256 + threadIdx.x;
+        x[u] = i < len ? src[i] : Rec{-1, 0};
       }
-      if (lane_id() == 0) tab[P] = carry;
+#pragma unroll
+      for (int u = 0; u < kHeavyUnroll; ++u)
+        if (x[u].b >= 0) atomicAdd(&hist[split_part(x[u].b, sbnd, P)], 1u);
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) {
-      const Rec x = src[i];
-      if (x.b >= 0) dst[atomicAdd(&hist[split_part(x.b, sbnd, P)], 1u)] = x;
-    }
+    uint32_t* tab = hv.ctab + hv.pbase[h] + (uint64_t)ch.y * P;
+    for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) tab[j] = hist[j];
     __syncthreads();
   }
 }
 
-// Records per (cluster, partition) task (wave per task).
+// Per (cluster, partition) task (wave per task): its record count, and in
+// place of each chunk's count the chunk's first position inside the task
+// (exclusive scan over the cluster's chunks).
 __global__ __launch_bounds__(256) void k_heavy_count(Heavy hv, int32_t ntasks) {
   const int lane = lane_id();
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -506,11 +497,52 @@ __global__ __launch_bounds__(256) void k_heavy_count(Heavy hv, int32_t ntasks) {
     const uint32_t p = (uint32_t)task.y;
     const uint32_t P = (uint32_t)hv.parts[h];
     const uint32_t nch = hv.cbase[h + 1] - hv.cbase[h];
-    const uint32_t* tab = hv.ctab + hv.pbase[h];
-    uint64_t c = 0;
-    for (uint32_t k = lane; k < nch; k += kWave) c += tab[(uint64_t)k * (P + 1) + p + 1] - tab[(uint64_t)k * (P + 1) + p];
-    c = wave_reduce_add(c);
-    if (lane == 0) hv.tcnt[t] = c;
+    uint32_t* tab = hv.ctab + hv.pbase[h];
+    uint64_t carry = 0;
+    for (uint32_t k0 = 0; k0 < nch; k0 += kWave) {
+      const uint32_t k = k0 + lane;
+      const uint64_t v = k < nch ? tab[(uint64_t)k * P + p] : 0;
+      const uint64_t inc = wave_incl_scan_add(v);
+      if (k < nch) tab[(uint64_t)k * P + p] = (uint32_t)(carry + inc - v);
+      carry += __shfl(inc, kWave - 1, kWave);
+    }
+    if (lane == 0) hv.tcnt[t] = carry;
+  }
+}
+
+// One workgroup per chunk: every record of the chunk goes to its task's
+// contiguous range of rec2 (task base + the chunk's position inside the task
+// + its rank among the chunk's records of that partition). The order inside
+// a task varies from run to run; the reduction does not depend on it.
+__global__ __launch_bounds__(256) void k_heavy_scatter(AggArgs A, Heavy hv, int32_t nchunks) {
+  __shared__ unsigned long long cur[kMaxHeavyParts];
+  __shared__ int32_t sbnd[kMaxHeavyParts + 1];
+  for (int64_t ci = blockIdx.x; ci < nchunks; ci += gridDim.x) {
+    const int2 ch = hv.chunks[ci];
+    const int32_t h = ch.x;
+    const int32_t a = hv.clusters[h];
+    const uint32_t P = (uint32_t)hv.parts[h];
+    const uint64_t off = (uint64_t)ch.y * kHeavyChunk;
+    const uint32_t len = (uint32_t)std::min<uint64_t>(kHeavyChunk, A.dsum[a] - off);
+    const Rec* src = A.rec + A.rbase[a] + off;
+    const int32_t* bnd = hv.bnd + hv.tbase[h] + h;
+    const uint32_t* tab = hv.ctab + hv.pbase[h] + (uint64_t)ch.y * P;
+    const uint64_t* tb = hv.tcnt + hv.tbase[h];
+    for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) cur[j] = tb[j] + tab[j];
+    for (uint32_t j = threadIdx.x; j <= P; j += blockDim.x) sbnd[j] = bnd[j];
+    __syncthreads();
+    for (uint32_t i0 = 0; i0 < len; i0 += 256 * kHeavyUnroll) {
+      Rec x[kHeavyUnroll];
+#pragma unroll
+      for (int u = 0; u < kHeavyUnroll; ++u) {
+        const uint32_t i = i0 + u * 256 + threadIdx.x;
+        x[u] = i < len ? src[i] : Rec{-1, 0};
+      }
+#pragma unroll
+      for (int u = 0; u < kHeavyUnroll; ++u)
+        if (x[u].b >= 0) hv.rec2[atomicAdd(&cur[split_part(x[u].b, sbnd, P)], 1ull)] = x[u];
+    }
+    __syncthreads();
   }
 }
 
@@ -518,8 +550,6 @@ struct ReduceSmem {
   int32_t scan[kReduceThreads / kWave];
   uint32_t distinct;
   uint32_t overflow;
-  uint32_t ra[kReduceThreads];    // per chunk of the current batch: first record of partition p
-  int32_t pre[kReduceThreads + 1];  // exclusive prefix of the record counts
 };
 
 // One workgroup per (cluster, partition): aggregate the partition's records
@@ -537,9 +567,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_heavy_reduce(AggArgs A, Heav
   for (int64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
     const int2 task = hv.tasks[t];
     const int32_t h = task.x;
-    const int32_t a = hv.clusters[h];
     const uint32_t p = (uint32_t)task.y;
-    const uint32_t P = (uint32_t)hv.parts[h];
     const int32_t* bnd = hv.bnd + hv.tbase[h] + h;
     const uint64_t lo_p = (uint64_t)bnd[p], hi_p = (uint64_t)bnd[p + 1];
     const uint64_t obase = hv.tcnt[t];
@@ -548,9 +576,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_heavy_reduce(AggArgs A, Heav
         min(ceil_log2(kHeavyTable), max(6u, ceil_log2((uint32_t)std::min<uint64_t>(2 * nrec + 2, kHeavyTable))));
     const uint32_t tcap = 1u << logc, mask = tcap - 1, shift = 32 - logc;
     const uint32_t limit = tcap / 2;
-    const uint32_t nch = hv.cbase[h + 1] - hv.cbase[h];
-    const uint32_t* tab = hv.ctab + hv.pbase[h];
-    const Rec* src = hv.rec2 + A.rbase[a];
+    const Rec* src = hv.rec2 + obase;
     uint64_t written = 0;
     uint64_t lo = lo_p, width = hi_p - lo_p;
     while (lo < hi_p) {
@@ -571,38 +597,16 @@ __global__ __launch_bounds__(kReduceThreads) void k_heavy_reduce(AggArgs A, Heav
         sm.overflow = 0;
       }
       __syncthreads();
-      // chunks in batches of NT: every thread loads one chunk's range of
-      // partition p, then the batch's records are walked as one flat range
-      for (uint32_t cb = 0; cb < nch; cb += NT) {
-        const uint32_t k = cb + tid;
-        uint32_t ra = 0, c = 0;
-        if (k < nch) {
-          ra = tab[(uint64_t)k * (P + 1) + p];
-          c = tab[(uint64_t)k * (P + 1) + p + 1] - ra;
+      for (uint64_t j = tid; j < nrec; j += NT) {
+        const Rec x = src[j];
+        if ((uint64_t)x.b >= lo && (uint64_t)x.b < hi) {
+          if (dense)
+            atomicAdd((unsigned long long*)&vals[(uint64_t)x.b - lo], (unsigned long long)(int64_t)x.w);
+          else
+            tbl_add_guarded(keys, vals, mask, shift, x.b, (int64_t)x.w, limit, &sm.distinct, &sm.overflow);
         }
-        int32_t total;
-        const int32_t incl = block_incl_scan_add<NT, int32_t>((int32_t)c, sm.scan, &total);
-        sm.ra[tid] = ra;
-        sm.pre[tid] = incl - (int32_t)c;
-        if (tid == 0) sm.pre[NT] = total;
-        __syncthreads();
-        for (int32_t j = tid; j < total; j += NT) {
-          int32_t lo_i = 0, hi_i = NT;  // last chunk with pre <= j
-          while (hi_i - lo_i > 1) {
-            const int32_t mid = (lo_i + hi_i) >> 1;
-            if (sm.pre[mid] <= j) lo_i = mid;
-            else hi_i = mid;
-          }
-          const Rec x = src[(uint64_t)(cb + lo_i) * kHeavyChunk + sm.ra[lo_i] + (uint32_t)(j - sm.pre[lo_i])];
-          if ((uint64_t)x.b >= lo && (uint64_t)x.b < hi) {
-            if (dense)
-              atomicAdd((unsigned long long*)&vals[(uint64_t)x.b - lo], (unsigned long long)(int64_t)x.w);
-            else
-              tbl_add_guarded(keys, vals, mask, shift, x.b, (int64_t)x.w, limit, &sm.distinct, &sm.overflow);
-          }
-        }
-        __syncthreads();
       }
+      __syncthreads();
       if (!dense && sm.overflow) {
         width = std::max<uint64_t>(kHeavyTable, (hi - lo) / 2);
         __syncthreads();
@@ -821,12 +825,16 @@ lp_status contract_heavy(const AggArgs& A, const int32_t* hl, int32_t H, Rec* re
   hipLaunchKernelGGL(k_heavy_splitters, dim3(grid_for(H, 1, 1u << 20)), dim3(256), 0, s, A, hv, H);
   LP_CHECK_LAUNCH();
   if (NCH > 0) {
-    hipLaunchKernelGGL(k_heavy_partition, dim3(grid_for(NCH, 1, 1u << 20)), dim3(256), 0, s, A, hv, NCH);
+    hipLaunchKernelGGL(k_heavy_hist, dim3(grid_for(NCH, 1, 1u << 20)), dim3(256), 0, s, A, hv, NCH);
     LP_CHECK_LAUNCH();
   }
   hipLaunchKernelGGL(k_heavy_count, dim3(grid_for((int64_t)T, 4, 65536)), dim3(256), 0, s, hv, T);
   LP_CHECK_LAUNCH();
   LP_CHECK(scan_exclusive_u64(tcnt, tcnt, (int64_t)T + 1, &tot[2], sc));
+  if (NCH > 0) {
+    hipLaunchKernelGGL(k_heavy_scatter, dim3(grid_for(NCH, 1, 1u << 20)), dim3(256), 0, s, A, hv, NCH);
+    LP_CHECK_LAUNCH();
+  }
   uint64_t nout = 0;
   LP_CHECK_HIP(hipMemcpyAsync(&nout, tot + 2, 8, hipMemcpyDeviceToHost, s));
   LP_CHECK_HIP(hipStreamSynchronize(s));
