@@ -405,10 +405,21 @@ def main() -> int:
     labels = torch.empty(g.n, dtype=torch.int32, device="cuda")
     cfg = dict(timing=1)
 
+    split = {"cluster": 0.0, "contract": 0.0, "cut": 0.0}
+
     def step():
+        # each call synchronises its stream before returning (statistics,
+        # coarse size, cut), so host clocks split the step between them
+        t = time.perf_counter()
         lab, st = lp.lp_cluster(G, cap, args.rounds, 1, labels=labels, config=cfg, stats=True)
+        t1 = time.perf_counter()
         C, _ = lp.lp_contract(G, lab, want_map=False)
+        t2 = time.perf_counter()
         cut = lp.lp_edge_cut(G, lab)
+        t3 = time.perf_counter()
+        split["cluster"] += t1 - t
+        split["contract"] += t2 - t1
+        split["cut"] += t3 - t2
         n_coarse = C.n
         C.free()
         return st, cut, n_coarse
@@ -417,6 +428,8 @@ def main() -> int:
         step()
         log(f"[bench] warmup {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
+    for k in split:
+        split[k] = 0.0
     times, stats = [], []
     for i in range(args.steps):
         torch.cuda.synchronize()
@@ -508,6 +521,7 @@ def main() -> int:
                         "frac_hbm": round(round_bytes / (round_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if round_ms else None},
         "phases": phases,
         "setup_ms": round(st.phase_ms["setup"], 3),
+        "step_split_ms": {k: round(1e3 * v / args.steps, 2) for k, v in split.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

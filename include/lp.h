@@ -18,20 +18,24 @@
  *    stream has reached that point. Calls that return host values
  *    (lp_graph_info, lp_edge_cut, lp_cluster_ex with stats, lp_compress,
  *    lp_contract) synchronise the stream before returning.
- *  - Scratch memory is taken from the device's stream-ordered pool
- *    (hipMallocAsync on `stream`) and released before the call returns.
+ *  - Scratch memory comes from the library's per-device memory cache in
+ *    the order of `stream` and goes back to it before the call returns;
+ *    memory released by one call is handed to the next (at once on the same
+ *    stream, on another stream once the release has completed) instead of
+ *    being returned to HIP, up to a quarter of the device's memory
+ *    (lp_trim_memory returns it).
  *  - Errors are returned as lp_status codes; no exception crosses the ABI.
  *    Argument errors are detected before any work is enqueued. A device
  *    fault surfaces as LP_EDEVICE from the next synchronising call.
  *  - Handles are immutable after creation; one handle may be used from
  *    several streams at once. Each handle must be freed with lp_graph_free.
- *    Handles made by lp_compress and lp_graph_import use plain device
+ *    Handles made by lp_compress and lp_graph_from_csr use plain device
  *    allocations. Handles made inside a call on a stream (lp_contract's
  *    coarse graph, lp_batch_create's batch) take their buffers from the
- *    device's stream-ordered pool on that stream ("its stream") and are
- *    released in that stream's order: work on any other stream that uses
- *    such a handle must be ordered before its stream (an event, or a
- *    synchronisation) by the caller before lp_graph_free.
+ *    memory cache on that stream ("its stream") and are released in that
+ *    stream's order: work on any other stream that uses such a handle must
+ *    be ordered before its stream (an event, or a synchronisation) by the
+ *    caller before lp_graph_free.
  *  - Integer widths: vertex IDs and labels int32 (n < 2^31), edge counts
  *    and offsets uint64, input edge / vertex weights int32 >= 1, ratings,
  *    gains, cluster weights and caps int64.
@@ -265,6 +269,12 @@ lp_status lp_contract(const lp_graph *g, const int32_t *labels_dev, int32_t *map
  * *cut_out is a host int64. Synchronises `stream`.
  */
 lp_status lp_edge_cut(const lp_graph *g, const int32_t *labels_dev, int64_t *cut_out, void *stream);
+
+/* Returns every block of the library's memory cache to HIP, on every device
+ * (waiting for each device to be idle first). Handles stay valid; later calls
+ * fill the cache again. For callers that share the device with other
+ * allocators, e.g. between phases of a job. */
+void lp_trim_memory(void);
 
 /* Frees a handle (NULL is ignored). A handle with plain allocations waits
  * for the device to be idle first; a handle made on a stream is released on

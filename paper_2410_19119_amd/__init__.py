@@ -95,6 +95,8 @@ def _load():
     lib.lp_edge_cut.restype = S
     lib.lp_graph_free.argtypes = [_P]
     lib.lp_graph_free.restype = None
+    lib.lp_trim_memory.argtypes = []
+    lib.lp_trim_memory.restype = None
     lib.lp_batch_create.argtypes = [ctypes.c_int32, _P, _P, ctypes.POINTER(_P)]
     lib.lp_batch_create.restype = S
     lib.lp_batch_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int32), _P]
@@ -112,7 +114,7 @@ def exported_symbols() -> list[str]:
     return ["lp_strerror", "lp_version", "lp_compress", "lp_graph_from_csr", "lp_graph_info",
             "lp_graph_export", "lp_decompress", "lp_cluster", "lp_cluster_ex", "lp_contract",
             "lp_edge_cut", "lp_graph_free", "lp_batch_create", "lp_batch_info", "lp_batch_cluster_ex",
-            "lp_batch_cluster"]
+            "lp_batch_cluster", "lp_trim_memory"]
 
 
 def _check(st: int, where: str) -> None:
@@ -336,6 +338,11 @@ def lp_contract(g: Graph, labels, want_map: bool = True, stream=None):
     h = _P()
     _check(_load().lp_contract(g.handle, _ptr(lab), _ptr(mp), _stream(stream), ctypes.byref(h)), "lp_contract")
     return Graph(h), (mp[: g.n] if mp is not None else None)
+
+
+def lp_trim_memory() -> None:
+    """Returns the library's cached device memory to HIP (waits for the device)."""
+    _load().lp_trim_memory()
 
 
 def lp_edge_cut(g: Graph, labels, stream=None) -> int:

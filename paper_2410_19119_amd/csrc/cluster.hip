@@ -1599,9 +1599,9 @@ struct TilePlan {
 };
 
 // Device memory of a plan, freed with the plan. For a handle whose buffers
-// are stream-ordered the plan is too: allocated on the building call's stream
-// (which is synchronised before the plan is used elsewhere) and released in
-// the order of the handle's stream.
+// are stream-ordered the plan is too: taken from the memory cache on the
+// building call's stream (which is synchronised before the plan is used
+// elsewhere) and released in the order of the handle's stream.
 struct PlanMem {
   std::vector<void*> ptrs;
   bool failed = false;
@@ -1611,8 +1611,10 @@ struct PlanMem {
   T* alloc(size_t n) {
     void* p = nullptr;
     const size_t bytes = (n ? n : 1) * sizeof(T);
-    const hipError_t e = stream_mem ? hipMallocAsync(&p, bytes, alloc_stream) : hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
+    if (stream_mem) p = cache_alloc(bytes, alloc_stream);
+    else if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    if (!p) {
+      clear_error();
       failed = true;
       return nullptr;
     }
@@ -1621,7 +1623,7 @@ struct PlanMem {
   }
   ~PlanMem() {
     for (void* p : ptrs) {
-      if (stream_mem) (void)hipFreeAsync(p, free_stream);
+      if (stream_mem) cache_free(p, free_stream);
       else (void)hipFree(p);
     }
   }
@@ -2199,12 +2201,13 @@ extern "C" lp_status lp_batch_cluster(int32_t G, const lp_graph* const* gs, cons
   LP_CHECK(lp_batch_create(G, gs, stream, &b));
   int32_t** outs = nullptr;
   lp_status st = LP_OK;
-  if (hipMalloc((void**)&outs, G * sizeof(int32_t*)) != hipSuccess) st = LP_ENOMEM;
+  outs = (int32_t**)cache_alloc(G * sizeof(int32_t*), s);
+  if (!outs) st = LP_ENOMEM;
   if (!st && hipMemcpyAsync(outs, labels_each, G * sizeof(int32_t*), hipMemcpyHostToDevice, s) != hipSuccess)
     st = LP_EDEVICE;
   if (!st) st = cluster_impl(b, 0, caps, rounds, 0, seeds, nullptr, outs, nullptr, nullptr, s);
   if (!st && hipStreamSynchronize(s) != hipSuccess) st = LP_EDEVICE;
-  (void)hipFree(outs);
+  cache_free(outs, s);
   lp_graph_free(b);
   return st;
 }

@@ -497,10 +497,15 @@ extern "C" void lp_graph_free(lp_graph* g) {
   if (!g) return;
   void* bufs[] = {g->offs, g->bytes, g->xadj, g->adjncy, g->adjwgt, g->vwgt, g->gid, g->gbase, g->deg};
   if (g->stream_mem) {
-    // released in the order of the stream that made the handle
+    // released in the order of the stream that made the handle, to the
+    // memory cache of the handle's device
+    int cur = g->device;
+    (void)hipGetDevice(&cur);
+    if (cur != g->device) (void)hipSetDevice(g->device);
     if (g->plan && g->plan_free) g->plan_free(g->plan);
-    for (void* p : bufs)
-      if (p) (void)hipFreeAsync(p, g->mem_stream);
+    for (void* p : bufs) cache_free(p, g->mem_stream);
+    if (cur != g->device) (void)hipSetDevice(cur);
+    clear_error();
   } else {
     (void)hipDeviceSynchronize();
     if (g->plan && g->plan_free) g->plan_free(g->plan);
@@ -508,6 +513,8 @@ extern "C" void lp_graph_free(lp_graph* g) {
   }
   delete g;
 }
+
+extern "C" void lp_trim_memory(void) { cache_trim_all(); }
 
 extern "C" const char* lp_strerror(lp_status s) {
   switch (s) {

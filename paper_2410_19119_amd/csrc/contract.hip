@@ -35,11 +35,11 @@ namespace {
 constexpr uint32_t kErrLabel = 1, kErrOverflow = 2, kErrFormat = 4;
 constexpr uint32_t kClassWave = 256;     // records per wavefront-cluster
 constexpr uint32_t kClassBlockS = 1024;  // records per workgroup-cluster, small table
-constexpr uint32_t kClassBlockL = 4096;  // records per workgroup-cluster, large table
+constexpr uint32_t kClassBlockL = 2048;  // records per workgroup-cluster, large table
 constexpr uint32_t kHeavyChunk = 16384;  // records per partitioning chunk
 constexpr int kHeavyUnroll = 8;          // records in flight per thread while partitioning
-constexpr uint32_t kHeavyTable = 4096;   // LDS entries of a heavy (cluster, partition) task
-constexpr uint32_t kHeavyPart = 1024;    // records per heavy partition (target)
+constexpr uint32_t kHeavyTable = 2048;   // LDS entries of a heavy (cluster, partition) task
+constexpr uint32_t kHeavyPart = 896;     // records per heavy partition (target; below kHeavyTable / 2)
 constexpr uint32_t kMaxHeavyParts = 4096;
 constexpr uint32_t kHeavySample = 2048;  // records sampled per heavy cluster for the partition splitters
 constexpr int kLightThreads = 256;
@@ -402,8 +402,8 @@ __global__ void k_heavy_lists(int32_t H, const int32_t* parts, const uint32_t* c
   }
 }
 
-// Partition splitters of every heavy cluster: a sample of kHeavySample
-// records (evenly spaced over the cluster's records) is sorted and cut at P
+// Partition splitters of every heavy cluster: a sample of up to kHeavySample
+// records, 256 per partition (evenly spaced over the cluster's records), is sorted and cut at P
 // quantiles, so the partitions hold about equal numbers of records however
 // skewed the coarse IDs are. Partition p holds IDs [bnd[p], bnd[p+1]).
 __global__ __launch_bounds__(256) void k_heavy_splitters(AggArgs A, Heavy hv, int32_t H) {
@@ -413,7 +413,7 @@ __global__ __launch_bounds__(256) void k_heavy_splitters(AggArgs A, Heavy hv, in
     const int32_t a = hv.clusters[h];
     const uint32_t P = (uint32_t)hv.parts[h];
     const uint64_t d = A.dsum[a];
-    const uint32_t S = (uint32_t)std::min<uint64_t>(kHeavySample, d);
+    const uint32_t S = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(kHeavySample, 256ull * P), d);
     const Rec* r = A.rec + A.rbase[a];
     int32_t* bnd = hv.bnd + hv.tbase[h] + h;
     int32_t valid = 0;
@@ -968,7 +968,7 @@ extern "C" lp_status lp_contract(const lp_graph* g, const int32_t* labels, int32
     uint32_t* nheavy = &ctl->ccount[4];
     st = launch_light<kWave>(A, lists, h.ccount[1], 2 * kClassWave, hlist, nheavy, s);
     if (!st) st = launch_light<kLightThreads>(A, lists + stride, h.ccount[2], 2 * kClassBlockS, hlist, nheavy, s);
-    if (!st) st = launch_light<kLightThreads>(A, lists + 2 * stride, h.ccount[3], kClassBlockL, hlist, nheavy, s);
+    if (!st) st = launch_light<kLightThreads>(A, lists + 2 * stride, h.ccount[3], 2 * kClassBlockL, hlist, nheavy, s);
     if (st) break;
     const uint32_t heavy0 = h.ccount[4];
     if (hipMemcpyAsync(&h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s) != hipSuccess ||

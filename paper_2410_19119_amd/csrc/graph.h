@@ -36,7 +36,7 @@ struct lp_graph {
   int32_t* deg = nullptr;     // n: degrees (first-edge headers restart per graph)
   std::vector<int32_t> vbase; // host copy of gbase
   // handles made inside a call (coarse graphs, batches) take their buffers from
-  // the stream-ordered pool of that call's stream and release them in its order
+  // the library's memory cache on that call's stream and release them in its order
   bool stream_mem = false;
   hipStream_t mem_stream = nullptr;
   // degree buckets, tiles and hub pieces for the default thresholds, built on
@@ -65,7 +65,9 @@ namespace lp {
 // Device buffer of a handle (see stream_mem).
 inline hipError_t graph_alloc(const lp_graph* g, void** p, size_t bytes) {
   if (!bytes) bytes = 1;
-  return g->stream_mem ? hipMallocAsync(p, bytes, g->mem_stream) : hipMalloc(p, bytes);
+  if (!g->stream_mem) return hipMalloc(p, bytes);
+  *p = cache_alloc(bytes, g->mem_stream);
+  return *p ? hipSuccess : hipErrorOutOfMemory;
 }
 
 // Readable padding after the compressed bytes, so that cooperative window

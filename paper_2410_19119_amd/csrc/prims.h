@@ -19,23 +19,32 @@ lp_status hip_fail(hipError_t e, const char* what, const char* file, int line);
 // launch checks only see this library's errors.
 inline void clear_error() { (void)hipGetLastError(); }
 
-// Stream-ordered scratch allocations released (on the same stream) when the
-// object goes out of scope. A failed allocation sets `failed`.
+// The library's device-memory cache (one per device). A block released on
+// stream s is kept and handed out again: to work on s at once (stream order
+// puts the new use after the old one), to another stream once the event
+// recorded at the release has completed. Steady-state calls therefore make no
+// HIP allocation and never wait for the allocator. cache_alloc returns
+// nullptr when the device is out of memory even after the cache was emptied.
+void* cache_alloc(size_t bytes, hipStream_t s);
+void cache_free(void* p, hipStream_t s);
+// Frees every cached block of every device (waits for each device first).
+void cache_trim_all();
+
+// Stream-ordered scratch allocations from the cache, released (on the same
+// stream) when the object goes out of scope. A failed allocation sets
+// `failed`.
 class Scratch {
  public:
   explicit Scratch(hipStream_t s) : stream_(s) {}
   ~Scratch() {
-    for (void* p : ptrs_) (void)hipFreeAsync(p, stream_);
+    for (void* p : ptrs_) cache_free(p, stream_);
   }
   template <typename T>
   T* alloc(size_t count) {
-    void* p = nullptr;
-    size_t bytes = (count ? count : 1) * sizeof(T);
-    bytes = (bytes + 255) & ~size_t(255);
-    const hipError_t e = hipMallocAsync(&p, bytes, stream_);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      (void)hip_fail(e, "hipMallocAsync", __FILE__, __LINE__);
+    const size_t bytes = (count ? count : 1) * sizeof(T);
+    void* p = cache_alloc(bytes, stream_);
+    if (!p) {
+      (void)hip_fail(hipErrorOutOfMemory, "cache_alloc", __FILE__, __LINE__);
       failed = true;
       return nullptr;
     }

@@ -1,6 +1,12 @@
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
 // Device-wide primitives written for wave64 / gfx950: reduce-then-scan prefix
 // sums (plain and segmented) and a stable LSD radix sort of (key, value)
 // pairs with 8-bit digits. The LP acceptance step and contraction use them.
@@ -14,6 +20,163 @@ lp_status hip_fail(hipError_t e, const char* what, const char* file, int line) {
   static const bool debug = getenv("LPGPU_DEBUG") != nullptr;
   if (debug) fprintf(stderr, "[lpgpu] %s failed at %s:%d: %s\n", what, file, line, hipGetErrorString(e));
   return e == hipErrorOutOfMemory ? LP_ENOMEM : LP_EDEVICE;
+}
+
+// ----------------------------------------------------------- memory cache --
+namespace {
+
+struct CBlock {
+  void* p;
+  hipStream_t s;   // stream of the release
+  hipEvent_t ev;   // recorded on s at the release
+};
+
+struct DevCache {
+  std::mutex mu;
+  std::multimap<size_t, CBlock> free_;    // by size
+  std::unordered_map<void*, size_t> live;  // handed-out blocks
+  std::vector<hipEvent_t> spare;           // events of reused blocks
+  size_t cached = 0, limit = 0;
+};
+
+constexpr int kCacheDevices = 64;
+
+DevCache* cache_of(int* dev_out) {
+  static DevCache caches[kCacheDevices];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kCacheDevices) {
+    clear_error();
+    return nullptr;
+  }
+  if (dev_out) *dev_out = dev;
+  return &caches[dev];
+}
+
+// Sizes are rounded up to eight classes per power of two (at least 512
+// bytes), so a block serves later requests of the same class.
+size_t size_class(size_t b) {
+  if (b <= 512) return 512;
+  const int e = 63 - __builtin_clzll((unsigned long long)(b - 1));  // 2^e < b <= 2^(e+1)
+  const size_t step = (size_t)1 << (e - 3);
+  return (b + step - 1) / step * step;
+}
+
+// Frees cached blocks (largest first) whose release has completed until at
+// most `keep` bytes stay cached. Caller holds c.mu.
+void trim_locked(DevCache& c, size_t keep) {
+  for (auto it = c.free_.end(); c.cached > keep && it != c.free_.begin();) {
+    --it;
+    if (hipEventQuery(it->second.ev) != hipSuccess) continue;
+    (void)hipFree(it->second.p);
+    (void)hipEventDestroy(it->second.ev);
+    c.cached -= it->first;
+    it = c.free_.erase(it);
+  }
+  clear_error();
+}
+
+}  // namespace
+
+void* cache_alloc(size_t bytes, hipStream_t s) {
+  DevCache* c = cache_of(nullptr);
+  if (!c) return nullptr;
+  const size_t need = size_class(bytes);
+  std::lock_guard<std::mutex> lock(c->mu);
+  if (!c->limit) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) tot = 0;
+    clear_error();
+    c->limit = std::max<size_t>(tot / 4, (size_t)2 << 30);
+  }
+  for (auto it = c->free_.lower_bound(need); it != c->free_.end() && it->first <= need + need / 4; ++it) {
+    CBlock& b = it->second;
+    const bool done = hipEventQuery(b.ev) == hipSuccess;
+    clear_error();
+    if (!done && b.s != s) continue;
+    // on the releasing stream the wait is implied by stream order; it is
+    // enqueued anyway so that a recycled stream handle stays safe
+    if (!done && hipStreamWaitEvent(s, b.ev, 0) != hipSuccess) {
+      clear_error();
+      continue;
+    }
+    void* p = b.p;
+    c->spare.push_back(b.ev);
+    c->cached -= it->first;
+    c->live[p] = it->first;
+    c->free_.erase(it);
+    return p;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, need) != hipSuccess) {
+    clear_error();
+    // out of memory: wait for the device, empty the cache, try once more
+    (void)hipDeviceSynchronize();
+    trim_locked(*c, 0);
+    if (hipMalloc(&p, need) != hipSuccess) {
+      clear_error();
+      return nullptr;
+    }
+  }
+  c->live[p] = need;
+  return p;
+}
+
+void cache_free(void* p, hipStream_t s) {
+  if (!p) return;
+  DevCache* c = cache_of(nullptr);
+  if (!c) return;
+  std::lock_guard<std::mutex> lock(c->mu);
+  auto lv = c->live.find(p);
+  if (lv == c->live.end()) return;  // not a cache block
+  const size_t size = lv->second;
+  c->live.erase(lv);
+  hipEvent_t ev = nullptr;
+  if (!c->spare.empty()) {
+    ev = c->spare.back();
+    c->spare.pop_back();
+  } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+    clear_error();
+    (void)hipStreamSynchronize(s);  // no event: release synchronously
+    (void)hipFree(p);
+    clear_error();
+    return;
+  }
+  if (hipEventRecord(ev, s) != hipSuccess) {
+    clear_error();
+    c->spare.push_back(ev);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(p);
+    clear_error();
+    return;
+  }
+  c->free_.insert({size, CBlock{p, s, ev}});
+  c->cached += size;
+  if (c->cached > c->limit) trim_locked(*c, c->limit);
+}
+
+void cache_trim_all() {
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) {
+    clear_error();
+    return;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess) ndev = 0;
+  clear_error();
+  for (int d = 0; d < ndev && d < kCacheDevices; ++d) {
+    if (hipSetDevice(d) != hipSuccess) {
+      clear_error();
+      continue;
+    }
+    DevCache* c = cache_of(nullptr);
+    if (!c) continue;
+    std::lock_guard<std::mutex> lock(c->mu);
+    if (c->free_.empty()) continue;
+    (void)hipDeviceSynchronize();
+    trim_locked(*c, 0);
+  }
+  (void)hipSetDevice(cur);
+  clear_error();
 }
 
 namespace {

@@ -61,3 +61,23 @@ def test_batch_made_on_a_stream(lp, oracle_mod, synth_mod):
         for o, e, part in zip(outs, exp, B.split(_np(lab))):
             assert np.array_equal(_np(o), e) and np.array_equal(part, e), it
         assert cut == sum(oracle_mod.edge_cut(g, e) for g, e in zip(gs, exp)), it
+
+
+def test_results_stable_across_cache_reuse_and_trim(lp, oracle_mod, synth_mod):
+    # calls reuse cached blocks that still hold earlier calls' data; emptying
+    # the cache in between must not change anything either
+    g = synth_mod.rmat_scale(13, 12, seed=9)
+    exp_lab, _ = oracle_mod.lp_cluster(g, 100, 5, 3)
+    cg, mp = oracle_mod.contract(g, exp_lab)
+    G = lp.lp_compress(g.n, g.xadj.view(np.int64), g.adjncy)
+    for it in range(4):
+        lab = lp.lp_cluster(G, 100, 5, 3)
+        C, M = lp.lp_contract(G, lab)
+        x, a, w, v = lp.lp_decompress(C)
+        assert np.array_equal(_np(lab), exp_lab), it
+        assert np.array_equal(_np(x).view(np.uint64), cg.xadj) and np.array_equal(_np(a), cg.adjncy), it
+        assert np.array_equal(_np(w), cg.adjwgt) and np.array_equal(_np(M), mp), it
+        assert lp.lp_edge_cut(G, lab) == oracle_mod.edge_cut(g, exp_lab), it
+        C.free()
+        if it == 1:
+            lp.lp_trim_memory()
