@@ -147,7 +147,7 @@ typedef struct {
   int32_t t_lane;   /* 0..16, default 16 */
   int32_t t_tile;   /* t_lane..2048, default 2048 */
   int32_t t_block;  /* t_tile..4096, default 4096 */
-  int32_t hub_part; /* target edges per hub partition, 256..8192, default 1024 */
+  int32_t hub_part; /* target edges per hub partition, 256..8192, default 2048 */
   int32_t timing;   /* nonzero: time each phase with HIP events (stats must be given) */
 } lp_config;
 

@@ -10,13 +10,13 @@ from __future__ import annotations
 
 import itertools
 
-DEFAULT = dict(t_lane=16, t_tile=2048, t_block=4096, hub_part=1024)
+DEFAULT = dict(t_lane=16, t_tile=2048, t_block=4096, hub_part=2048)
 
 GRID = dict(
     t_lane=(8, 16),
     t_tile=(512, 2048),
     t_block=(2048, 4096),
-    hub_part=(512, 1024, 4096),
+    hub_part=(1024, 2048, 4096),
 )
 
 

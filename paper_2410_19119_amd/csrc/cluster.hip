@@ -322,7 +322,14 @@ __device__ __forceinline__ void tile_insert(int32_t* keys, V* vals, uint32_t bas
     if (old == kEmpty || old == c) break;
     if (++h == size) h = 0;
   }
-  lds_add(&vals[base + h], w);
+  if constexpr (sizeof(V) == 2) {
+    // 16-bit ratings (unit edge weights: a rating is at most the vertex's
+    // degree, below 2^16) share 32-bit words; no carry crosses a half
+    const uint32_t q = base + h;
+    atomicAdd(reinterpret_cast<unsigned*>(vals) + (q >> 1), (unsigned)(uint16_t)w << ((q & 1u) * 16u));
+  } else {
+    lds_add(&vals[base + h], w);
+  }
 }
 
 // Segmented scan over the workgroup of (head, s, s2): a head restarts the
@@ -773,6 +780,7 @@ constexpr int kPieceThreads = 512;
 constexpr int kPieceItems = (kHubPiece + kPieceThreads - 1) / kPieceThreads;
 constexpr int kPieceSlots = kHubPiece + kHubPiece / 2 + 16;
 constexpr int kMaxParts = 1024;
+constexpr int kDefaultHubPart = 2048;  // target partial records per (hub, partition) task
 constexpr uint32_t kStreamZig = 0x80000000u;  // first code is zigzag(v - base_v)
 
 // One code stream of a piece: a chunk of a split record, or a run of an
@@ -1544,6 +1552,16 @@ lp_status side_stream(int i, hipStream_t* out) {
   return LP_OK;
 }
 
+// Width of the LDS ratings of tiles: 16 bits for unit edge weights (a
+// rating is at most the vertex's degree, at most 4096 on the tile paths),
+// 64 bits when a weighted degree can exceed 2^31 - 1, else 32 bits. The
+// narrower the table, the more workgroups share a compute unit.
+enum class RateWidth { k16, k32, k64 };
+inline RateWidth rate_width(const lp_graph* g) {
+  if (g->max_wdeg > 0x7FFFFFFFll) return RateWidth::k64;
+  return g->weighted ? RateWidth::k32 : RateWidth::k16;
+}
+
 template <class T, typename V, bool COMP, int MODE = kModeRate>
 lp_status launch_tile(const RoundCtx& x, VDesc vd, const int32_t* tiles, const uint32_t* ntiles, unsigned grid,
                       bool weighted, hipStream_t s) {
@@ -1556,14 +1574,16 @@ lp_status launch_tile(const RoundCtx& x, VDesc vd, const int32_t* tiles, const u
 }
 
 template <class T>
-lp_status launch_tile_any(bool comp, bool wide, const RoundCtx& x, VDesc vd, const int32_t* tiles,
+lp_status launch_tile_any(bool comp, RateWidth rw, const RoundCtx& x, VDesc vd, const int32_t* tiles,
                           const uint32_t* ntiles, unsigned grid, bool weighted, hipStream_t s) {
   if (comp) {
-    return wide ? launch_tile<T, int64_t, true>(x, vd, tiles, ntiles, grid, weighted, s)
-                : launch_tile<T, int32_t, true>(x, vd, tiles, ntiles, grid, weighted, s);
+    if (rw == RateWidth::k16) return launch_tile<T, uint16_t, true>(x, vd, tiles, ntiles, grid, weighted, s);
+    if (rw == RateWidth::k64) return launch_tile<T, int64_t, true>(x, vd, tiles, ntiles, grid, weighted, s);
+    return launch_tile<T, int32_t, true>(x, vd, tiles, ntiles, grid, weighted, s);
   }
-  return wide ? launch_tile<T, int64_t, false>(x, vd, tiles, ntiles, grid, weighted, s)
-              : launch_tile<T, int32_t, false>(x, vd, tiles, ntiles, grid, weighted, s);
+  if (rw == RateWidth::k16) return launch_tile<T, uint16_t, false>(x, vd, tiles, ntiles, grid, weighted, s);
+  if (rw == RateWidth::k64) return launch_tile<T, int64_t, false>(x, vd, tiles, ntiles, grid, weighted, s);
+  return launch_tile<T, int32_t, false>(x, vd, tiles, ntiles, grid, weighted, s);
 }
 
 template <typename V>
@@ -1630,10 +1650,16 @@ struct PlanMem {
 };
 
 template <class T>
-lp_status plan_tiles(VDesc vd, int32_t cnt, bool comp, bool wide, bool weighted, const int32_t* gid, Scratch& sc,
-                     PlanMem& mem, TilePlan& tp) {
+lp_status plan_tiles(VDesc vd, int32_t cnt, bool comp, RateWidth rw, bool weighted, const int32_t* gid,
+                     Scratch& sc, PlanMem& mem, TilePlan& tp) {
   if (cnt <= 0) return LP_OK;
-  const TileLayout L = wide ? tile_layout<T, int64_t>(comp, weighted) : tile_layout<T, int32_t>(comp, weighted);
+  // the tiles run with the rating layout and, for the cut and the contraction
+  // records, with the 32-bit one: the staged bytes must fit both
+  TileLayout L = tile_layout<T, int32_t>(comp, weighted);
+  const TileLayout Lr = rw == RateWidth::k16   ? tile_layout<T, uint16_t>(comp, weighted)
+                        : rw == RateWidth::k64 ? tile_layout<T, int64_t>(comp, weighted)
+                                               : L;
+  L.stage_bytes = std::min(L.stage_bytes, Lr.stage_bytes);
   const int64_t nseg = ((int64_t)cnt + kTileSeg - 1) / kTileSeg;
   uint32_t* tcnt = sc.alloc<uint32_t>(nseg);
   tp.ntiles = mem.alloc<uint32_t>(1);
@@ -1733,8 +1759,8 @@ lp_status build_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t 
   }
   // tiles of the two tile buckets
   const int32_t* gid = batch ? g->gid : nullptr;
-  LP_CHECK(plan_tiles<TileSmall>(P.vd(1), P.bn[1], g->compressed, P.wide, g->weighted, gid, sc, P.mem, P.tps));
-  LP_CHECK(plan_tiles<TileLarge>(P.vd(2), P.bn[2], g->compressed, P.wide, g->weighted, gid, sc, P.mem, P.tpl));
+  LP_CHECK(plan_tiles<TileSmall>(P.vd(1), P.bn[1], g->compressed, rate_width(g), g->weighted, gid, sc, P.mem, P.tps));
+  LP_CHECK(plan_tiles<TileLarge>(P.vd(2), P.bn[2], g->compressed, rate_width(g), g->weighted, gid, sc, P.mem, P.tpl));
 
   // hubs: metadata (host-built, small) and the code streams of their pieces
   const int32_t H = P.bn[3];
@@ -1828,7 +1854,7 @@ lp_status visit_edges_mode(const lp_graph* g, const int32_t* C, const uint64_t* 
                            unsigned long long* cut, hipStream_t s) {
   const Plan* plan = nullptr;
   std::unique_ptr<Plan> tmp;
-  LP_CHECK(get_plan(g, 16, TileSmall::kEdges, TileLarge::kEdges, 1024, s, &plan, tmp));
+  LP_CHECK(get_plan(g, 16, TileSmall::kEdges, TileLarge::kEdges, kDefaultHubPart, s, &plan, tmp));
   Scratch sc(s);
   uint32_t* zero = sc.alloc<uint32_t>(1);
   if (!zero) return LP_ENOMEM;
@@ -1877,7 +1903,8 @@ lp_status visit_edges_mode(const lp_graph* g, const int32_t* C, const uint64_t* 
 // (built on first use), otherwise a new one owned by `tmp`.
 lp_status get_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t t_block, int32_t hub_part,
                    hipStream_t s, const Plan** out, std::unique_ptr<Plan>& tmp) {
-  const bool dflt = t_lane == 16 && t_tile == TileSmall::kEdges && t_block == TileLarge::kEdges && hub_part == 1024;
+  const bool dflt = t_lane == 16 && t_tile == TileSmall::kEdges && t_block == TileLarge::kEdges &&
+                    hub_part == kDefaultHubPart;
   if (!dflt) {
     tmp.reset(new Plan());
     LP_CHECK(build_plan(g, t_lane, t_tile, t_block, hub_part, s, *tmp));
@@ -1934,7 +1961,7 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
   if (n == 0) return LP_OK;
   // knobs (results do not depend on them)
   const bool wide = g->max_wdeg > 0x7FFFFFFFll;
-  int32_t t_lane = 16, t_tile = TileSmall::kEdges, t_block = TileLarge::kEdges, hub_part = 1024;
+  int32_t t_lane = 16, t_tile = TileSmall::kEdges, t_block = TileLarge::kEdges, hub_part = kDefaultHubPart;
   if (cfg_in) {
     if (cfg_in->t_lane) t_lane = cfg_in->t_lane;
     if (cfg_in->t_tile) t_tile = cfg_in->t_tile;
@@ -2077,20 +2104,17 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
     x.round = (uint32_t)r;
     const size_t round_mark = marks.size();
     LP_CHECK(begin(LP_PHASE_ROUND));
-    // rating (all buckets) -> ptgt / pgain; fork the side streams
+    // rating (all buckets) -> ptgt / pgain. The hub pieces run first, alone:
+    // they are the head of the longest chain (pieces, then their reduction),
+    // which then overlaps with the tiles and lanes on the side streams.
+    if (H > 0) {
+      LP_CHECK(begin(LP_PHASE_HUB));
+      LP_CHECK(launch_piece(g->compressed, wide, x, hm, npieces, piece_layout, piece_lds, s));
+    }
     LP_CHECK_HIP(hipEventRecord(ev.e[3], s));
     for (int i = 0; i < 3; ++i) LP_CHECK_HIP(hipStreamWaitEvent(side[i], ev.e[3], 0));
-    // the longest path first: it takes the CUs it needs, the others fill in
-    if (bn[1] > 0) {
-      LP_CHECK(begin(LP_PHASE_TILE));
-      LP_CHECK(launch_tile_any<TileSmall>(g->compressed, wide, x, vd_of(1), tps.tiles, tps.ntiles, tps.grid,
-                                          g->weighted, s));
-      LP_CHECK(end());
-    }
     if (H > 0) {
       hipStream_t hs = side[0];
-      LP_CHECK(begin(LP_PHASE_HUB, hs));
-      LP_CHECK(launch_piece(g->compressed, wide, x, hm, npieces, piece_layout, piece_lds, hs));
       if (wide)
         hipLaunchKernelGGL(k_hub_reduce<int64_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads),
                            (size_t)kHubTable * 12 + sizeof(HubReduceSmem), hs, x, hm, ntasks);
@@ -2104,7 +2128,7 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
     }
     if (bn[2] > 0) {
       LP_CHECK(begin(LP_PHASE_BLOCK, side[1]));
-      LP_CHECK(launch_tile_any<TileLarge>(g->compressed, wide, x, vd_of(2), tpl.tiles, tpl.ntiles, tpl.grid,
+      LP_CHECK(launch_tile_any<TileLarge>(g->compressed, rate_width(g), x, vd_of(2), tpl.tiles, tpl.ntiles, tpl.grid,
                                           g->weighted, side[1]));
       LP_CHECK(end(side[1]));
     }
@@ -2118,6 +2142,12 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
                            bn[0]);
       LP_CHECK_LAUNCH();
       LP_CHECK(end(side[2]));
+    }
+    if (bn[1] > 0) {
+      LP_CHECK(begin(LP_PHASE_TILE));
+      LP_CHECK(launch_tile_any<TileSmall>(g->compressed, rate_width(g), x, vd_of(1), tps.tiles, tps.ntiles, tps.grid,
+                                          g->weighted, s));
+      LP_CHECK(end());
     }
     // join
     for (int i = 0; i < 3; ++i) {
