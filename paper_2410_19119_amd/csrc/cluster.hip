@@ -271,6 +271,7 @@ struct TileShared {
   int64_t red[NT / kWave];
   uint32_t seg_flags;
   uint32_t any_redo;
+  uint32_t next;  // tile handed to the workgroup
 };
 
 // LDS layout of a tile workgroup: region A holds the staged bytes followed by
@@ -475,7 +476,7 @@ __device__ __forceinline__ void tile_select(const RoundCtx& x, const int32_t* ke
 
 template <class T, typename V, bool COMP, int MODE = kModeRate>
 __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd, const int32_t* tiles,
-                                                           const uint32_t* ntiles_p, TileLayout L) {
+                                                           const uint32_t* ntiles_p, uint32_t* ctr, TileLayout L) {
   constexpr int NT = T::kThreads, VT = T::kVerts, ITEMS = T::kItems, SG = T::kSelGroup;
   constexpr int NSG = NT / SG;  // selection groups per workgroup
   extern __shared__ __align__(16) uint8_t smem_raw[];
@@ -492,239 +493,250 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
   const int sgi = tid / SG;           // selection group of this thread
   const int sl = tid % SG;            // lane within the selection group
 
-  // XCD-aware order: the workgroups of one XCD take a contiguous range of tiles
+  // Tiles are handed out at run time: the workgroups of one XCD first take
+  // tiles of their own eighth of the list (one counter per eighth), then help
+  // with the other eighths, so that workgroups that become resident late (the
+  // kernel shares the device with the other rating paths) take fewer tiles.
   const uint32_t T_ = *ntiles_p;
-  const uint32_t xcd = blockIdx.x & 7u, gx = gridDim.x >> 3;
-  const uint32_t lo = (uint32_t)(((uint64_t)T_ * xcd) >> 3), hi = (uint32_t)(((uint64_t)T_ * (xcd + 1)) >> 3);
-  for (uint32_t t = lo + (blockIdx.x >> 3); t < hi; t += gx) {
-    const int32_t t0 = tiles[t];
-    const int32_t nv = tiles[t + 1] - t0;
-    // 0. vertex descriptors and bases
-    uint32_t d = 0, ndw = 0, nnum = 0, nsl = 0;
-    if (tid < nv) {
-      const int4 v4 = vd.d[t0 + tid];
-      const int32_t u = v4.x;
-      d = (uint32_t)v4.y;
-      const uint64_t pos = vd_pos(v4);
-      sh.u[tid] = u;
-      sh.own_c[tid] = x.C[u];
-      sh.wu[tid] = x.g.vwgt ? x.g.vwgt[u] : 1;
-      sh.pos[tid] = pos;
-      if constexpr (MODE == kModeRec) sh.rb[tid] = x.rbase[sh.own_c[tid]] + x.voff[u];
-      if constexpr (COMP) {
-        const uint32_t len = vd.len[t0 + tid];
-        const uint32_t pre = (uint32_t)(pos & 3u);
-        ndw = (pre + len + 3u) >> 2;
-        nnum = per * d + 4u * ndw - len;
-        sh.len[tid] = len;
-      }
-      nsl = tile_slots(d);
-    }
-    {
-      int32_t tot1, tot2;
-      const int32_t p1 = (int32_t)(d | (ndw << 16));
-      const int32_t p2 = (int32_t)(nnum | (nsl << 16));
-      const int32_t i1 = block_incl_scan_add<NT, int32_t>(p1, sh.scan, &tot1);
-      const int32_t i2 = block_incl_scan_add<NT, int32_t>(p2, sh.scan2, &tot2);
-      const uint32_t e1 = (uint32_t)(i1 - p1), e2 = (uint32_t)(i2 - p2);
-      if (tid < nv) {
-        sh.ebase[tid] = e1 & 0xFFFFu;
-        sh.dwbase[tid] = e1 >> 16;
-        sh.rstart[tid] = (e2 & 0xFFFFu) + (COMP ? (uint32_t)(sh.pos[tid] & 3u) : 0u);
-        sh.tbase[tid] = e2 >> 16;
-      }
-      if (tid == 0) {
-        sh.ebase[nv] = (uint32_t)tot1 & 0xFFFFu;
-        sh.dwbase[nv] = (uint32_t)tot1 >> 16;
-        sh.rstart[nv] = (uint32_t)tot2 & 0xFFFFu;
-        sh.tbase[nv] = (uint32_t)tot2 >> 16;
-        sh.any_redo = 0;
-        sh.seg_flags = 0;
-        sh.max_nsl = 0;
-        sh.vp = vparams(x, sh.u[0]);
-      }
-    }
-    __syncthreads();
-    const uint32_t Et = sh.ebase[nv];
-    const uint32_t St = sh.tbase[nv];
-    if constexpr (COMP) {
-      // 1. stage the code bytes (four independent loads in flight per thread)
-      const uint32_t Dt = sh.dwbase[nv];
-      for (uint32_t j0 = tid; j0 < Dt; j0 += 4 * NT) {
-        uint32_t w[4], off[4];
-        int32_t vi4[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const uint32_t j = j0 + (uint32_t)k * NT;
-          vi4[k] = -1;
-          w[k] = 0;
-          off[k] = 0;
-          if (j < Dt) {
-            const int32_t i = tile_find(sh.dwbase, nv, j);
-            vi4[k] = i;
-            off[k] = 4u * (j - sh.dwbase[i]);
-            w[k] = *(const uint32_t*)(x.g.bytes + (sh.pos[i] & ~3ull) + off[k]);
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (vi4[k] < 0) continue;
-          const int32_t i = vi4[k];
-          const uint32_t b0 = (uint32_t)(sh.pos[i] & 3u), b1 = b0 + sh.len[i];
-          uint32_t v = w[k];
-#pragma unroll
-          for (uint32_t b = 0; b < 4; ++b)
-            if (off[k] + b < b0 || off[k] + b >= b1) v &= ~(0xFFu << (8 * b));
-          A32[j0 + (uint32_t)k * NT] = v;
-        }
-      }
+  const uint32_t xcd = blockIdx.x & 7u;
+  for (uint32_t k8 = 0; k8 < 8; ++k8) {
+    const uint32_t xr = (xcd + k8) & 7u;
+    const uint32_t lo = (uint32_t)(((uint64_t)T_ * xr) >> 3), hi = (uint32_t)(((uint64_t)T_ * (xr + 1)) >> 3);
+    while (true) {
+      if (tid == 0) sh.next = lo + atomicAdd(&ctr[xr], 1u);
       __syncthreads();
-      // 2. numbers in stream order
-      {
-        const uint32_t Q = (Dt + NT - 1) / NT;
-        const uint32_t j0 = min(Dt, tid * Q), j1 = min(Dt, j0 + Q);
-        int32_t cnt = 0;
-        for (uint32_t j = j0; j < j1; ++j) cnt += __popc(~A32[j] & 0x80808080u);
-        int32_t tot;
-        uint32_t idx = (uint32_t)(block_incl_scan_add<NT, int32_t>(cnt, sh.scan, &tot) - cnt);
-        uint32_t prev = j0 > 0 ? A32[j0 - 1] : 0u;
-        for (uint32_t j = j0; j < j1; ++j) {
-          const uint32_t cur = A32[j];
-          const uint64_t w = ((uint64_t)cur << 32) | prev;
-          const uint64_t term = ~w & 0x8080808080808080ull;
-          uint32_t tc = (uint32_t)(term >> 32);
-          while (tc) {
-            const uint32_t b = 4u + (((uint32_t)__ffs(tc) - 1u) >> 3);
-            tc &= tc - 1u;
-            nums[idx++] = window_value(w, term, b);
-          }
-          prev = cur;
-        }
-      }
+      const uint32_t t = sh.next;
       __syncthreads();
-    }
-    // 3. neighbour IDs, weights and labels of this thread's slice
-    const uint32_t Dd = (Et + NT - 1) / NT;
-    const uint32_t e0 = tid * Dd;
-    int32_t vi[ITEMS], nb[ITEMS], wt[ITEMS];
-    {
-      int32_t i = e0 < Et ? tile_find(sh.ebase, nv, e0) : 0;
-      bool any_head = false;
-      int32_t s = 0, s2 = 0;
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        const uint32_t e = e0 + k;
-        vi[k] = -1;
-        nb[k] = 0;
-        wt[k] = 1;
-        if ((uint32_t)k < Dd && e < Et) {
-          while (e >= sh.ebase[i + 1]) ++i;
-          vi[k] = i;
-          const uint32_t loc = e - sh.ebase[i];
+      if (t >= hi) break;
+        const int32_t t0 = tiles[t];
+        const int32_t nv = tiles[t + 1] - t0;
+        // 0. vertex descriptors and bases
+        uint32_t d = 0, ndw = 0, nnum = 0, nsl = 0;
+        if (tid < nv) {
+          const int4 v4 = vd.d[t0 + tid];
+          const int32_t u = v4.x;
+          d = (uint32_t)v4.y;
+          const uint64_t pos = vd_pos(v4);
+          sh.u[tid] = u;
+          sh.own_c[tid] = x.C[u];
+          sh.wu[tid] = x.g.vwgt ? x.g.vwgt[u] : 1;
+          sh.pos[tid] = pos;
+          if constexpr (MODE == kModeRec) sh.rb[tid] = x.rbase[sh.own_c[tid]] + x.voff[u];
           if constexpr (COMP) {
-            const uint32_t ci = sh.rstart[i] + per * loc;
-            const uint32_t code = nums[ci];
-            const bool head = loc == 0;
-            const int32_t dv = head ? sh.u[i] + unzigzag32(code) : (int32_t)code;
-            const int32_t dw = weighted ? unzigzag32(nums[ci + 1]) : 0;
-            if (head) {
-              any_head = true;
-              s = dv;
-              s2 = dw;
-            } else {
-              s += dv;
-              s2 += dw;
-            }
-            nb[k] = s;
-            wt[k] = s2;
-          } else {
-            const uint64_t ge = sh.pos[i] + loc;
-            nb[k] = x.g.adjncy[ge];
-            if (weighted) wt[k] = x.g.adjwgt[ge];
+            const uint32_t len = vd.len[t0 + tid];
+            const uint32_t pre = (uint32_t)(pos & 3u);
+            ndw = (pre + len + 3u) >> 2;
+            nnum = per * d + 4u * ndw - len;
+            sh.len[tid] = len;
+          }
+          nsl = tile_slots(d);
+        }
+        {
+          int32_t tot1, tot2;
+          const int32_t p1 = (int32_t)(d | (ndw << 16));
+          const int32_t p2 = (int32_t)(nnum | (nsl << 16));
+          const int32_t i1 = block_incl_scan_add<NT, int32_t>(p1, sh.scan, &tot1);
+          const int32_t i2 = block_incl_scan_add<NT, int32_t>(p2, sh.scan2, &tot2);
+          const uint32_t e1 = (uint32_t)(i1 - p1), e2 = (uint32_t)(i2 - p2);
+          if (tid < nv) {
+            sh.ebase[tid] = e1 & 0xFFFFu;
+            sh.dwbase[tid] = e1 >> 16;
+            sh.rstart[tid] = (e2 & 0xFFFFu) + (COMP ? (uint32_t)(sh.pos[tid] & 3u) : 0u);
+            sh.tbase[tid] = e2 >> 16;
+          }
+          if (tid == 0) {
+            sh.ebase[nv] = (uint32_t)tot1 & 0xFFFFu;
+            sh.dwbase[nv] = (uint32_t)tot1 >> 16;
+            sh.rstart[nv] = (uint32_t)tot2 & 0xFFFFu;
+            sh.tbase[nv] = (uint32_t)tot2 >> 16;
+            sh.any_redo = 0;
+            sh.seg_flags = 0;
+            sh.max_nsl = 0;
+            sh.vp = vparams(x, sh.u[0]);
           }
         }
-      }
-      if constexpr (COMP) {
-        int32_t ex, ex2;
-        tile_seg_scan<NT>(any_head, s, s2, sh.scan, sh.scan2, &sh.seg_flags, ex, ex2);
-        bool before = true;
-#pragma unroll
+        __syncthreads();
+        const uint32_t Et = sh.ebase[nv];
+        const uint32_t St = sh.tbase[nv];
+        if constexpr (COMP) {
+          // 1. stage the code bytes (four independent loads in flight per thread)
+          const uint32_t Dt = sh.dwbase[nv];
+          for (uint32_t j0 = tid; j0 < Dt; j0 += 4 * NT) {
+            uint32_t w[4], off[4];
+            int32_t vi4[4];
+    #pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const uint32_t j = j0 + (uint32_t)k * NT;
+              vi4[k] = -1;
+              w[k] = 0;
+              off[k] = 0;
+              if (j < Dt) {
+                const int32_t i = tile_find(sh.dwbase, nv, j);
+                vi4[k] = i;
+                off[k] = 4u * (j - sh.dwbase[i]);
+                w[k] = *(const uint32_t*)(x.g.bytes + (sh.pos[i] & ~3ull) + off[k]);
+              }
+            }
+    #pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              if (vi4[k] < 0) continue;
+              const int32_t i = vi4[k];
+              const uint32_t b0 = (uint32_t)(sh.pos[i] & 3u), b1 = b0 + sh.len[i];
+              uint32_t v = w[k];
+    #pragma unroll
+              for (uint32_t b = 0; b < 4; ++b)
+                if (off[k] + b < b0 || off[k] + b >= b1) v &= ~(0xFFu << (8 * b));
+              A32[j0 + (uint32_t)k * NT] = v;
+            }
+          }
+          __syncthreads();
+          // 2. numbers in stream order
+          {
+            const uint32_t Q = (Dt + NT - 1) / NT;
+            const uint32_t j0 = min(Dt, tid * Q), j1 = min(Dt, j0 + Q);
+            int32_t cnt = 0;
+            for (uint32_t j = j0; j < j1; ++j) cnt += __popc(~A32[j] & 0x80808080u);
+            int32_t tot;
+            uint32_t idx = (uint32_t)(block_incl_scan_add<NT, int32_t>(cnt, sh.scan, &tot) - cnt);
+            uint32_t prev = j0 > 0 ? A32[j0 - 1] : 0u;
+            for (uint32_t j = j0; j < j1; ++j) {
+              const uint32_t cur = A32[j];
+              const uint64_t w = ((uint64_t)cur << 32) | prev;
+              const uint64_t term = ~w & 0x8080808080808080ull;
+              uint32_t tc = (uint32_t)(term >> 32);
+              while (tc) {
+                const uint32_t b = 4u + (((uint32_t)__ffs(tc) - 1u) >> 3);
+                tc &= tc - 1u;
+                nums[idx++] = window_value(w, term, b);
+              }
+              prev = cur;
+            }
+          }
+          __syncthreads();
+        }
+        // 3. neighbour IDs, weights and labels of this thread's slice
+        const uint32_t Dd = (Et + NT - 1) / NT;
+        const uint32_t e0 = tid * Dd;
+        int32_t vi[ITEMS], nb[ITEMS], wt[ITEMS];
+        {
+          int32_t i = e0 < Et ? tile_find(sh.ebase, nv, e0) : 0;
+          bool any_head = false;
+          int32_t s = 0, s2 = 0;
+    #pragma unroll
+          for (int k = 0; k < ITEMS; ++k) {
+            const uint32_t e = e0 + k;
+            vi[k] = -1;
+            nb[k] = 0;
+            wt[k] = 1;
+            if ((uint32_t)k < Dd && e < Et) {
+              while (e >= sh.ebase[i + 1]) ++i;
+              vi[k] = i;
+              const uint32_t loc = e - sh.ebase[i];
+              if constexpr (COMP) {
+                const uint32_t ci = sh.rstart[i] + per * loc;
+                const uint32_t code = nums[ci];
+                const bool head = loc == 0;
+                const int32_t dv = head ? sh.u[i] + unzigzag32(code) : (int32_t)code;
+                const int32_t dw = weighted ? unzigzag32(nums[ci + 1]) : 0;
+                if (head) {
+                  any_head = true;
+                  s = dv;
+                  s2 = dw;
+                } else {
+                  s += dv;
+                  s2 += dw;
+                }
+                nb[k] = s;
+                wt[k] = s2;
+              } else {
+                const uint64_t ge = sh.pos[i] + loc;
+                nb[k] = x.g.adjncy[ge];
+                if (weighted) wt[k] = x.g.adjwgt[ge];
+              }
+            }
+          }
+          if constexpr (COMP) {
+            int32_t ex, ex2;
+            tile_seg_scan<NT>(any_head, s, s2, sh.scan, sh.scan2, &sh.seg_flags, ex, ex2);
+            bool before = true;
+    #pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+              if (vi[k] < 0) continue;
+              if (e0 + k == sh.ebase[vi[k]]) before = false;
+              if (before) {
+                nb[k] += ex;
+                wt[k] += ex2;
+              }
+              if (!weighted) wt[k] = 1;
+            }
+          }
+        }
+    #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
           if (vi[k] < 0) continue;
-          if (e0 + k == sh.ebase[vi[k]]) before = false;
-          if (before) {
-            nb[k] += ex;
-            wt[k] += ex2;
-          }
-          if (!weighted) wt[k] = 1;
+          if ((uint32_t)nb[k] < (uint32_t)x.g.n) nb[k] = x.C[nb[k]];
+          else vi[k] = -1;  // unreachable for a valid handle; keeps the gather in bounds
         }
-      }
+        if constexpr (MODE == kModeCut) {
+          unsigned long long c = 0;
+    #pragma unroll
+          for (int k = 0; k < ITEMS; ++k)
+            if (vi[k] >= 0 && nb[k] != sh.own_c[vi[k]]) c += (unsigned long long)wt[k];
+          c = block_reduce_add<NT, unsigned long long>(c, sh.red_u);
+          if (tid == 0 && c) atomicAdd(x.cut, c);
+          __syncthreads();
+          continue;
+        }
+        if constexpr (MODE == kModeRec) {
+    #pragma unroll
+          for (int k = 0; k < ITEMS; ++k) {
+            if (vi[k] < 0) continue;
+            const int32_t i = vi[k];
+            const uint32_t loc = e0 + k - sh.ebase[i];
+            x.rec[sh.rb[i] + loc] = Rec{nb[k] == sh.own_c[i] ? -1 : nb[k], wt[k]};
+          }
+          __syncthreads();
+          continue;
+        }
+        __syncthreads();  // numbers consumed: region A becomes the table
+        if (tid < nv) atomicMax(&sh.max_nsl, sh.tbase[tid + 1] - sh.tbase[tid]);
+        for (uint32_t q = tid; q < St; q += NT) keys[q] = kEmpty;
+        for (uint32_t q = tid; q < St; q += NT) vals[q] = 0;
+        __syncthreads();
+        // 4. ratings
+    #pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+          if (vi[k] < 0) continue;
+          const int32_t i = vi[k];
+          tile_insert<V>(keys, vals, sh.tbase[i], sh.tbase[i + 1] - sh.tbase[i], nb[k], (V)wt[k]);
+        }
+        __syncthreads();
+        // 5. selection: one walk over the slots of each vertex; tiles of small
+        // vertices use 16-lane groups (four vertices per wavefront at a time)
+        const bool small_v = SG == kWave && sh.max_nsl <= 256;
+        if (small_v) tile_select<16, NT, V>(x, keys, vals, sh, nv, tid, false);
+        else tile_select<SG, NT, V>(x, keys, vals, sh, nv, tid, false);
+        __syncthreads();
+        if (tid < nv) {
+          const int32_t u = sh.u[tid];
+          const int32_t c = sh.best_c[tid];
+          if (c < 0) {
+            x.ptgt[u] = -1;
+          } else if (x.W[c] + sh.wu[tid] <= sh.vp.cap) {
+            x.ptgt[u] = c;
+            x.pgain[u] = sh.gain[tid];
+          } else {
+            sh.best_c[tid] = -2;  // walk again with the cap
+            atomicOr(&sh.any_redo, 1u);
+          }
+        }
+        __syncthreads();
+        if (sh.any_redo) {
+          if (small_v) tile_select<16, NT, V>(x, keys, vals, sh, nv, tid, true);
+          else tile_select<SG, NT, V>(x, keys, vals, sh, nv, tid, true);
+        }
+        __syncthreads();
     }
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      if (vi[k] < 0) continue;
-      if ((uint32_t)nb[k] < (uint32_t)x.g.n) nb[k] = x.C[nb[k]];
-      else vi[k] = -1;  // unreachable for a valid handle; keeps the gather in bounds
-    }
-    if constexpr (MODE == kModeCut) {
-      unsigned long long c = 0;
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k)
-        if (vi[k] >= 0 && nb[k] != sh.own_c[vi[k]]) c += (unsigned long long)wt[k];
-      c = block_reduce_add<NT, unsigned long long>(c, sh.red_u);
-      if (tid == 0 && c) atomicAdd(x.cut, c);
-      __syncthreads();
-      continue;
-    }
-    if constexpr (MODE == kModeRec) {
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        if (vi[k] < 0) continue;
-        const int32_t i = vi[k];
-        const uint32_t loc = e0 + k - sh.ebase[i];
-        x.rec[sh.rb[i] + loc] = Rec{nb[k] == sh.own_c[i] ? -1 : nb[k], wt[k]};
-      }
-      __syncthreads();
-      continue;
-    }
-    __syncthreads();  // numbers consumed: region A becomes the table
-    if (tid < nv) atomicMax(&sh.max_nsl, sh.tbase[tid + 1] - sh.tbase[tid]);
-    for (uint32_t q = tid; q < St; q += NT) keys[q] = kEmpty;
-    for (uint32_t q = tid; q < St; q += NT) vals[q] = 0;
-    __syncthreads();
-    // 4. ratings
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-      if (vi[k] < 0) continue;
-      const int32_t i = vi[k];
-      tile_insert<V>(keys, vals, sh.tbase[i], sh.tbase[i + 1] - sh.tbase[i], nb[k], (V)wt[k]);
-    }
-    __syncthreads();
-    // 5. selection: one walk over the slots of each vertex; tiles of small
-    // vertices use 16-lane groups (four vertices per wavefront at a time)
-    const bool small_v = SG == kWave && sh.max_nsl <= 256;
-    if (small_v) tile_select<16, NT, V>(x, keys, vals, sh, nv, tid, false);
-    else tile_select<SG, NT, V>(x, keys, vals, sh, nv, tid, false);
-    __syncthreads();
-    if (tid < nv) {
-      const int32_t u = sh.u[tid];
-      const int32_t c = sh.best_c[tid];
-      if (c < 0) {
-        x.ptgt[u] = -1;
-      } else if (x.W[c] + sh.wu[tid] <= sh.vp.cap) {
-        x.ptgt[u] = c;
-        x.pgain[u] = sh.gain[tid];
-      } else {
-        sh.best_c[tid] = -2;  // walk again with the cap
-        atomicOr(&sh.any_redo, 1u);
-      }
-    }
-    __syncthreads();
-    if (sh.any_redo) {
-      if (small_v) tile_select<16, NT, V>(x, keys, vals, sh, nv, tid, true);
-      else tile_select<SG, NT, V>(x, keys, vals, sh, nv, tid, true);
-    }
-    __syncthreads();
   }
 }
 
@@ -882,12 +894,13 @@ struct PieceShared {
   int32_t scan[kPieceThreads / kWave];
   int32_t scan2[kPieceThreads / kWave];
   uint32_t seg_flags;
+  uint32_t next;  // piece handed to the workgroup
 };
 
 // H1: one workgroup per hub piece.
 template <typename V, bool COMP, int MODE = kModeRate>
 __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta hm, int32_t npieces,
-                                                            TileLayout L) {
+                                                            uint32_t* ctr, TileLayout L) {
   constexpr int NT = kPieceThreads, ITEMS = kPieceItems, NS = kHubStreams;
   extern __shared__ __align__(16) uint8_t smem_raw[];
   if (*x.done) return;
@@ -901,7 +914,13 @@ __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta
   uint32_t* nums = (uint32_t*)(A + L.nums_off);
   PieceShared& sh = *(PieceShared*)(A + L.abytes);
   V* rec_r = (V*)hm.rec_r;
-  for (int64_t pc = blockIdx.x; pc < npieces; pc += gridDim.x) {
+  // pieces are handed out at run time (one counter)
+  while (true) {
+    if (tid == 0) sh.next = atomicAdd(ctr, 1u);
+    __syncthreads();
+    const int64_t pc = sh.next;
+    __syncthreads();
+    if (pc >= npieces) break;
     const int2 pj = hm.pieces[pc];
     const int h = pj.x;
     const uint32_t P = (uint32_t)hm.nparts[h];
@@ -1563,27 +1582,27 @@ inline RateWidth rate_width(const lp_graph* g) {
 }
 
 template <class T, typename V, bool COMP, int MODE = kModeRate>
-lp_status launch_tile(const RoundCtx& x, VDesc vd, const int32_t* tiles, const uint32_t* ntiles, unsigned grid,
-                      bool weighted, hipStream_t s) {
+lp_status launch_tile(const RoundCtx& x, VDesc vd, const int32_t* tiles, const uint32_t* ntiles, uint32_t* ctr,
+                      unsigned grid, bool weighted, hipStream_t s) {
   const TileLayout L = tile_layout<T, V>(COMP, weighted);
   const size_t bytes = (size_t)L.abytes + sizeof(TileShared<T::kThreads, T::kVerts>);
   auto kern = k_rate_tile<T, V, COMP, MODE>;
   LP_CHECK(set_lds(kern, bytes));
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(T::kThreads), bytes, s, x, vd, tiles, ntiles, L);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(T::kThreads), bytes, s, x, vd, tiles, ntiles, ctr, L);
   return last_error();
 }
 
 template <class T>
 lp_status launch_tile_any(bool comp, RateWidth rw, const RoundCtx& x, VDesc vd, const int32_t* tiles,
-                          const uint32_t* ntiles, unsigned grid, bool weighted, hipStream_t s) {
+                          const uint32_t* ntiles, uint32_t* ctr, unsigned grid, bool weighted, hipStream_t s) {
   if (comp) {
-    if (rw == RateWidth::k16) return launch_tile<T, uint16_t, true>(x, vd, tiles, ntiles, grid, weighted, s);
-    if (rw == RateWidth::k64) return launch_tile<T, int64_t, true>(x, vd, tiles, ntiles, grid, weighted, s);
-    return launch_tile<T, int32_t, true>(x, vd, tiles, ntiles, grid, weighted, s);
+    if (rw == RateWidth::k16) return launch_tile<T, uint16_t, true>(x, vd, tiles, ntiles, ctr, grid, weighted, s);
+    if (rw == RateWidth::k64) return launch_tile<T, int64_t, true>(x, vd, tiles, ntiles, ctr, grid, weighted, s);
+    return launch_tile<T, int32_t, true>(x, vd, tiles, ntiles, ctr, grid, weighted, s);
   }
-  if (rw == RateWidth::k16) return launch_tile<T, uint16_t, false>(x, vd, tiles, ntiles, grid, weighted, s);
-  if (rw == RateWidth::k64) return launch_tile<T, int64_t, false>(x, vd, tiles, ntiles, grid, weighted, s);
-  return launch_tile<T, int32_t, false>(x, vd, tiles, ntiles, grid, weighted, s);
+  if (rw == RateWidth::k16) return launch_tile<T, uint16_t, false>(x, vd, tiles, ntiles, ctr, grid, weighted, s);
+  if (rw == RateWidth::k64) return launch_tile<T, int64_t, false>(x, vd, tiles, ntiles, ctr, grid, weighted, s);
+  return launch_tile<T, int32_t, false>(x, vd, tiles, ntiles, ctr, grid, weighted, s);
 }
 
 template <typename V>
@@ -1601,13 +1620,13 @@ TileLayout piece_layout_of(bool comp, bool weighted) {
 }
 
 template <int MODE = kModeRate>
-lp_status launch_piece(bool comp, bool wide, const RoundCtx& x, const HubMeta& hm, int32_t npieces,
+lp_status launch_piece(bool comp, bool wide, const RoundCtx& x, const HubMeta& hm, int32_t npieces, uint32_t* ctr,
                        const TileLayout& L, size_t lds, hipStream_t s) {
   auto kern = comp ? (wide ? k_hub_piece<int64_t, true, MODE> : k_hub_piece<int32_t, true, MODE>)
                    : (wide ? k_hub_piece<int64_t, false, MODE> : k_hub_piece<int32_t, false, MODE>);
   LP_CHECK(set_lds(kern, lds));
   const unsigned grid = grid_for(npieces, 1, 2048);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kPieceThreads), lds, s, x, hm, npieces, L);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kPieceThreads), lds, s, x, hm, npieces, ctr, L);
   return last_error();
 }
 
@@ -1846,6 +1865,10 @@ void plan_delete(void* p) { delete (Plan*)p; }
 lp_status get_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t t_block, int32_t hub_part,
                    hipStream_t s, const Plan** out, std::unique_ptr<Plan>& tmp);
 
+__global__ void k_zero_u32(uint32_t* a, int32_t n) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = 0;
+}
+
 // One visit of every edge with the default plan: the cut (MODE == kModeCut)
 // or the contraction records (kModeRec). The lane, tile and piece kernels
 // decode exactly as for rating and stop after the label (or map) gather.
@@ -1856,9 +1879,12 @@ lp_status visit_edges_mode(const lp_graph* g, const int32_t* C, const uint64_t* 
   std::unique_ptr<Plan> tmp;
   LP_CHECK(get_plan(g, 16, TileSmall::kEdges, TileLarge::kEdges, kDefaultHubPart, s, &plan, tmp));
   Scratch sc(s);
-  uint32_t* zero = sc.alloc<uint32_t>(1);
+  // zero[0]: the round's "done" flag (never set here); zero[8..32): hand-out
+  // counters of the small tiles, the large tiles and the pieces
+  uint32_t* zero = sc.alloc<uint32_t>(32);
   if (!zero) return LP_ENOMEM;
-  LP_CHECK_HIP(hipMemsetAsync(zero, 0, sizeof(uint32_t), s));
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, zero, 32);
+  LP_CHECK_LAUNCH();
   RoundCtx x{};
   x.g = g->view();
   x.C = C;
@@ -1878,23 +1904,23 @@ lp_status visit_edges_mode(const lp_graph* g, const int32_t* C, const uint64_t* 
   if (plan->bn[1] > 0) {
     if (comp)
       LP_CHECK((launch_tile<TileSmall, int32_t, true, MODE>(x, plan->vd(1), plan->tps.tiles, plan->tps.ntiles,
-                                                            plan->tps.grid, g->weighted, s)));
+                                                            zero + 8, plan->tps.grid, g->weighted, s)));
     else
       LP_CHECK((launch_tile<TileSmall, int32_t, false, MODE>(x, plan->vd(1), plan->tps.tiles, plan->tps.ntiles,
-                                                             plan->tps.grid, g->weighted, s)));
+                                                             zero + 8, plan->tps.grid, g->weighted, s)));
   }
   if (plan->bn[2] > 0) {
     if (comp)
       LP_CHECK((launch_tile<TileLarge, int32_t, true, MODE>(x, plan->vd(2), plan->tpl.tiles, plan->tpl.ntiles,
-                                                            plan->tpl.grid, g->weighted, s)));
+                                                            zero + 16, plan->tpl.grid, g->weighted, s)));
     else
       LP_CHECK((launch_tile<TileLarge, int32_t, false, MODE>(x, plan->vd(2), plan->tpl.tiles, plan->tpl.ntiles,
-                                                             plan->tpl.grid, g->weighted, s)));
+                                                             zero + 16, plan->tpl.grid, g->weighted, s)));
   }
   if (plan->H > 0) {
     const TileLayout L = piece_layout_of<int32_t>(comp, g->weighted);
-    LP_CHECK(launch_piece<MODE>(comp, false, x, plan->hm, plan->npieces, L, (size_t)L.abytes + sizeof(PieceShared),
-                                s));
+    LP_CHECK(launch_piece<MODE>(comp, false, x, plan->hm, plan->npieces, zero + 24, L,
+                                (size_t)L.abytes + sizeof(PieceShared), s));
   }
   return LP_OK;
 }
@@ -1994,6 +2020,8 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
   uint8_t* flag = sc.alloc<uint8_t>(n);
   const unsigned ncp = grid_for(n, kCpTile, 0x7FFFFFFF);
   uint32_t* pcnt = sc.alloc<uint32_t>(ncp);
+  // per round: hand-out counters of the small tiles, large tiles and pieces
+  uint32_t* hand = sc.alloc<uint32_t>((size_t)std::max(rounds, 1) * 24);
   struct Ctl {
     uint32_t done;
     uint32_t count;
@@ -2005,6 +2033,9 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
   Ctl* ctl = sc.alloc<Ctl>(1);
   if (sc.failed) return LP_ENOMEM;
   LP_CHECK_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), s));
+  hipLaunchKernelGGL(k_zero_u32, dim3(grid_for((int64_t)std::max(rounds, 1) * 24, 256, 64)), dim3(256), 0, s, hand,
+                     std::max(rounds, 1) * 24);
+  LP_CHECK_LAUNCH();
   if (batch) {
     LP_CHECK_HIP(hipMemcpyAsync(gcap, caps, g->nbatch * sizeof(int64_t), hipMemcpyHostToDevice, s));
     LP_CHECK_HIP(hipMemcpyAsync(gseed, seeds, g->nbatch * sizeof(uint64_t), hipMemcpyHostToDevice, s));
@@ -2109,7 +2140,7 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
     // which then overlaps with the tiles and lanes on the side streams.
     if (H > 0) {
       LP_CHECK(begin(LP_PHASE_HUB));
-      LP_CHECK(launch_piece(g->compressed, wide, x, hm, npieces, piece_layout, piece_lds, s));
+      LP_CHECK(launch_piece(g->compressed, wide, x, hm, npieces, hand + 24 * r + 16, piece_layout, piece_lds, s));
     }
     LP_CHECK_HIP(hipEventRecord(ev.e[3], s));
     for (int i = 0; i < 3; ++i) LP_CHECK_HIP(hipStreamWaitEvent(side[i], ev.e[3], 0));
@@ -2128,7 +2159,8 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
     }
     if (bn[2] > 0) {
       LP_CHECK(begin(LP_PHASE_BLOCK, side[1]));
-      LP_CHECK(launch_tile_any<TileLarge>(g->compressed, rate_width(g), x, vd_of(2), tpl.tiles, tpl.ntiles, tpl.grid,
+      LP_CHECK(launch_tile_any<TileLarge>(g->compressed, rate_width(g), x, vd_of(2), tpl.tiles, tpl.ntiles,
+                                          hand + 24 * r + 8, tpl.grid,
                                           g->weighted, side[1]));
       LP_CHECK(end(side[1]));
     }
@@ -2145,7 +2177,8 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
     }
     if (bn[1] > 0) {
       LP_CHECK(begin(LP_PHASE_TILE));
-      LP_CHECK(launch_tile_any<TileSmall>(g->compressed, rate_width(g), x, vd_of(1), tps.tiles, tps.ntiles, tps.grid,
+      LP_CHECK(launch_tile_any<TileSmall>(g->compressed, rate_width(g), x, vd_of(1), tps.tiles, tps.ntiles,
+                                          hand + 24 * r, tps.grid,
                                           g->weighted, s));
       LP_CHECK(end());
     }
