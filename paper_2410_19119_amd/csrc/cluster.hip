@@ -508,234 +508,234 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
       const uint32_t t = sh.next;
       __syncthreads();
       if (t >= hi) break;
-        const int32_t t0 = tiles[t];
-        const int32_t nv = tiles[t + 1] - t0;
-        // 0. vertex descriptors and bases
-        uint32_t d = 0, ndw = 0, nnum = 0, nsl = 0;
-        if (tid < nv) {
-          const int4 v4 = vd.d[t0 + tid];
-          const int32_t u = v4.x;
-          d = (uint32_t)v4.y;
-          const uint64_t pos = vd_pos(v4);
-          sh.u[tid] = u;
-          sh.own_c[tid] = x.C[u];
-          sh.wu[tid] = x.g.vwgt ? x.g.vwgt[u] : 1;
-          sh.pos[tid] = pos;
-          if constexpr (MODE == kModeRec) sh.rb[tid] = x.rbase[sh.own_c[tid]] + x.voff[u];
-          if constexpr (COMP) {
-            const uint32_t len = vd.len[t0 + tid];
-            const uint32_t pre = (uint32_t)(pos & 3u);
-            ndw = (pre + len + 3u) >> 2;
-            nnum = per * d + 4u * ndw - len;
-            sh.len[tid] = len;
-          }
-          nsl = tile_slots(d);
+      const int32_t t0 = tiles[t];
+      const int32_t nv = tiles[t + 1] - t0;
+      // 0. vertex descriptors and bases
+      uint32_t d = 0, ndw = 0, nnum = 0, nsl = 0;
+      if (tid < nv) {
+        const int4 v4 = vd.d[t0 + tid];
+        const int32_t u = v4.x;
+        d = (uint32_t)v4.y;
+        const uint64_t pos = vd_pos(v4);
+        sh.u[tid] = u;
+        sh.own_c[tid] = x.C[u];
+        sh.wu[tid] = x.g.vwgt ? x.g.vwgt[u] : 1;
+        sh.pos[tid] = pos;
+        if constexpr (MODE == kModeRec) sh.rb[tid] = x.rbase[sh.own_c[tid]] + x.voff[u];
+        if constexpr (COMP) {
+          const uint32_t len = vd.len[t0 + tid];
+          const uint32_t pre = (uint32_t)(pos & 3u);
+          ndw = (pre + len + 3u) >> 2;
+          nnum = per * d + 4u * ndw - len;
+          sh.len[tid] = len;
         }
-        {
-          int32_t tot1, tot2;
-          const int32_t p1 = (int32_t)(d | (ndw << 16));
-          const int32_t p2 = (int32_t)(nnum | (nsl << 16));
-          const int32_t i1 = block_incl_scan_add<NT, int32_t>(p1, sh.scan, &tot1);
-          const int32_t i2 = block_incl_scan_add<NT, int32_t>(p2, sh.scan2, &tot2);
-          const uint32_t e1 = (uint32_t)(i1 - p1), e2 = (uint32_t)(i2 - p2);
-          if (tid < nv) {
-            sh.ebase[tid] = e1 & 0xFFFFu;
-            sh.dwbase[tid] = e1 >> 16;
-            sh.rstart[tid] = (e2 & 0xFFFFu) + (COMP ? (uint32_t)(sh.pos[tid] & 3u) : 0u);
-            sh.tbase[tid] = e2 >> 16;
+        nsl = tile_slots(d);
+      }
+      {
+        int32_t tot1, tot2;
+        const int32_t p1 = (int32_t)(d | (ndw << 16));
+        const int32_t p2 = (int32_t)(nnum | (nsl << 16));
+        const int32_t i1 = block_incl_scan_add<NT, int32_t>(p1, sh.scan, &tot1);
+        const int32_t i2 = block_incl_scan_add<NT, int32_t>(p2, sh.scan2, &tot2);
+        const uint32_t e1 = (uint32_t)(i1 - p1), e2 = (uint32_t)(i2 - p2);
+        if (tid < nv) {
+          sh.ebase[tid] = e1 & 0xFFFFu;
+          sh.dwbase[tid] = e1 >> 16;
+          sh.rstart[tid] = (e2 & 0xFFFFu) + (COMP ? (uint32_t)(sh.pos[tid] & 3u) : 0u);
+          sh.tbase[tid] = e2 >> 16;
+        }
+        if (tid == 0) {
+          sh.ebase[nv] = (uint32_t)tot1 & 0xFFFFu;
+          sh.dwbase[nv] = (uint32_t)tot1 >> 16;
+          sh.rstart[nv] = (uint32_t)tot2 & 0xFFFFu;
+          sh.tbase[nv] = (uint32_t)tot2 >> 16;
+          sh.any_redo = 0;
+          sh.seg_flags = 0;
+          sh.max_nsl = 0;
+          sh.vp = vparams(x, sh.u[0]);
+        }
+      }
+      __syncthreads();
+      const uint32_t Et = sh.ebase[nv];
+      const uint32_t St = sh.tbase[nv];
+      if constexpr (COMP) {
+        // 1. stage the code bytes (four independent loads in flight per thread)
+        const uint32_t Dt = sh.dwbase[nv];
+        for (uint32_t j0 = tid; j0 < Dt; j0 += 4 * NT) {
+          uint32_t w[4], off[4];
+          int32_t vi4[4];
+  #pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const uint32_t j = j0 + (uint32_t)k * NT;
+            vi4[k] = -1;
+            w[k] = 0;
+            off[k] = 0;
+            if (j < Dt) {
+              const int32_t i = tile_find(sh.dwbase, nv, j);
+              vi4[k] = i;
+              off[k] = 4u * (j - sh.dwbase[i]);
+              w[k] = *(const uint32_t*)(x.g.bytes + (sh.pos[i] & ~3ull) + off[k]);
+            }
           }
-          if (tid == 0) {
-            sh.ebase[nv] = (uint32_t)tot1 & 0xFFFFu;
-            sh.dwbase[nv] = (uint32_t)tot1 >> 16;
-            sh.rstart[nv] = (uint32_t)tot2 & 0xFFFFu;
-            sh.tbase[nv] = (uint32_t)tot2 >> 16;
-            sh.any_redo = 0;
-            sh.seg_flags = 0;
-            sh.max_nsl = 0;
-            sh.vp = vparams(x, sh.u[0]);
+  #pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            if (vi4[k] < 0) continue;
+            const int32_t i = vi4[k];
+            const uint32_t b0 = (uint32_t)(sh.pos[i] & 3u), b1 = b0 + sh.len[i];
+            uint32_t v = w[k];
+  #pragma unroll
+            for (uint32_t b = 0; b < 4; ++b)
+              if (off[k] + b < b0 || off[k] + b >= b1) v &= ~(0xFFu << (8 * b));
+            A32[j0 + (uint32_t)k * NT] = v;
           }
         }
         __syncthreads();
-        const uint32_t Et = sh.ebase[nv];
-        const uint32_t St = sh.tbase[nv];
-        if constexpr (COMP) {
-          // 1. stage the code bytes (four independent loads in flight per thread)
-          const uint32_t Dt = sh.dwbase[nv];
-          for (uint32_t j0 = tid; j0 < Dt; j0 += 4 * NT) {
-            uint32_t w[4], off[4];
-            int32_t vi4[4];
-    #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const uint32_t j = j0 + (uint32_t)k * NT;
-              vi4[k] = -1;
-              w[k] = 0;
-              off[k] = 0;
-              if (j < Dt) {
-                const int32_t i = tile_find(sh.dwbase, nv, j);
-                vi4[k] = i;
-                off[k] = 4u * (j - sh.dwbase[i]);
-                w[k] = *(const uint32_t*)(x.g.bytes + (sh.pos[i] & ~3ull) + off[k]);
-              }
-            }
-    #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              if (vi4[k] < 0) continue;
-              const int32_t i = vi4[k];
-              const uint32_t b0 = (uint32_t)(sh.pos[i] & 3u), b1 = b0 + sh.len[i];
-              uint32_t v = w[k];
-    #pragma unroll
-              for (uint32_t b = 0; b < 4; ++b)
-                if (off[k] + b < b0 || off[k] + b >= b1) v &= ~(0xFFu << (8 * b));
-              A32[j0 + (uint32_t)k * NT] = v;
-            }
-          }
-          __syncthreads();
-          // 2. numbers in stream order
-          {
-            const uint32_t Q = (Dt + NT - 1) / NT;
-            const uint32_t j0 = min(Dt, tid * Q), j1 = min(Dt, j0 + Q);
-            int32_t cnt = 0;
-            for (uint32_t j = j0; j < j1; ++j) cnt += __popc(~A32[j] & 0x80808080u);
-            int32_t tot;
-            uint32_t idx = (uint32_t)(block_incl_scan_add<NT, int32_t>(cnt, sh.scan, &tot) - cnt);
-            uint32_t prev = j0 > 0 ? A32[j0 - 1] : 0u;
-            for (uint32_t j = j0; j < j1; ++j) {
-              const uint32_t cur = A32[j];
-              const uint64_t w = ((uint64_t)cur << 32) | prev;
-              const uint64_t term = ~w & 0x8080808080808080ull;
-              uint32_t tc = (uint32_t)(term >> 32);
-              while (tc) {
-                const uint32_t b = 4u + (((uint32_t)__ffs(tc) - 1u) >> 3);
-                tc &= tc - 1u;
-                nums[idx++] = window_value(w, term, b);
-              }
-              prev = cur;
-            }
-          }
-          __syncthreads();
-        }
-        // 3. neighbour IDs, weights and labels of this thread's slice
-        const uint32_t Dd = (Et + NT - 1) / NT;
-        const uint32_t e0 = tid * Dd;
-        int32_t vi[ITEMS], nb[ITEMS], wt[ITEMS];
+        // 2. numbers in stream order
         {
-          int32_t i = e0 < Et ? tile_find(sh.ebase, nv, e0) : 0;
-          bool any_head = false;
-          int32_t s = 0, s2 = 0;
-    #pragma unroll
-          for (int k = 0; k < ITEMS; ++k) {
-            const uint32_t e = e0 + k;
-            vi[k] = -1;
-            nb[k] = 0;
-            wt[k] = 1;
-            if ((uint32_t)k < Dd && e < Et) {
-              while (e >= sh.ebase[i + 1]) ++i;
-              vi[k] = i;
-              const uint32_t loc = e - sh.ebase[i];
-              if constexpr (COMP) {
-                const uint32_t ci = sh.rstart[i] + per * loc;
-                const uint32_t code = nums[ci];
-                const bool head = loc == 0;
-                const int32_t dv = head ? sh.u[i] + unzigzag32(code) : (int32_t)code;
-                const int32_t dw = weighted ? unzigzag32(nums[ci + 1]) : 0;
-                if (head) {
-                  any_head = true;
-                  s = dv;
-                  s2 = dw;
-                } else {
-                  s += dv;
-                  s2 += dw;
-                }
-                nb[k] = s;
-                wt[k] = s2;
-              } else {
-                const uint64_t ge = sh.pos[i] + loc;
-                nb[k] = x.g.adjncy[ge];
-                if (weighted) wt[k] = x.g.adjwgt[ge];
-              }
+          const uint32_t Q = (Dt + NT - 1) / NT;
+          const uint32_t j0 = min(Dt, tid * Q), j1 = min(Dt, j0 + Q);
+          int32_t cnt = 0;
+          for (uint32_t j = j0; j < j1; ++j) cnt += __popc(~A32[j] & 0x80808080u);
+          int32_t tot;
+          uint32_t idx = (uint32_t)(block_incl_scan_add<NT, int32_t>(cnt, sh.scan, &tot) - cnt);
+          uint32_t prev = j0 > 0 ? A32[j0 - 1] : 0u;
+          for (uint32_t j = j0; j < j1; ++j) {
+            const uint32_t cur = A32[j];
+            const uint64_t w = ((uint64_t)cur << 32) | prev;
+            const uint64_t term = ~w & 0x8080808080808080ull;
+            uint32_t tc = (uint32_t)(term >> 32);
+            while (tc) {
+              const uint32_t b = 4u + (((uint32_t)__ffs(tc) - 1u) >> 3);
+              tc &= tc - 1u;
+              nums[idx++] = window_value(w, term, b);
             }
-          }
-          if constexpr (COMP) {
-            int32_t ex, ex2;
-            tile_seg_scan<NT>(any_head, s, s2, sh.scan, sh.scan2, &sh.seg_flags, ex, ex2);
-            bool before = true;
-    #pragma unroll
-            for (int k = 0; k < ITEMS; ++k) {
-              if (vi[k] < 0) continue;
-              if (e0 + k == sh.ebase[vi[k]]) before = false;
-              if (before) {
-                nb[k] += ex;
-                wt[k] += ex2;
-              }
-              if (!weighted) wt[k] = 1;
-            }
+            prev = cur;
           }
         }
-    #pragma unroll
+        __syncthreads();
+      }
+      // 3. neighbour IDs, weights and labels of this thread's slice
+      const uint32_t Dd = (Et + NT - 1) / NT;
+      const uint32_t e0 = tid * Dd;
+      int32_t vi[ITEMS], nb[ITEMS], wt[ITEMS];
+      {
+        int32_t i = e0 < Et ? tile_find(sh.ebase, nv, e0) : 0;
+        bool any_head = false;
+        int32_t s = 0, s2 = 0;
+  #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
-          if (vi[k] < 0) continue;
-          if ((uint32_t)nb[k] < (uint32_t)x.g.n) nb[k] = x.C[nb[k]];
-          else vi[k] = -1;  // unreachable for a valid handle; keeps the gather in bounds
+          const uint32_t e = e0 + k;
+          vi[k] = -1;
+          nb[k] = 0;
+          wt[k] = 1;
+          if ((uint32_t)k < Dd && e < Et) {
+            while (e >= sh.ebase[i + 1]) ++i;
+            vi[k] = i;
+            const uint32_t loc = e - sh.ebase[i];
+            if constexpr (COMP) {
+              const uint32_t ci = sh.rstart[i] + per * loc;
+              const uint32_t code = nums[ci];
+              const bool head = loc == 0;
+              const int32_t dv = head ? sh.u[i] + unzigzag32(code) : (int32_t)code;
+              const int32_t dw = weighted ? unzigzag32(nums[ci + 1]) : 0;
+              if (head) {
+                any_head = true;
+                s = dv;
+                s2 = dw;
+              } else {
+                s += dv;
+                s2 += dw;
+              }
+              nb[k] = s;
+              wt[k] = s2;
+            } else {
+              const uint64_t ge = sh.pos[i] + loc;
+              nb[k] = x.g.adjncy[ge];
+              if (weighted) wt[k] = x.g.adjwgt[ge];
+            }
+          }
         }
-        if constexpr (MODE == kModeCut) {
-          unsigned long long c = 0;
-    #pragma unroll
-          for (int k = 0; k < ITEMS; ++k)
-            if (vi[k] >= 0 && nb[k] != sh.own_c[vi[k]]) c += (unsigned long long)wt[k];
-          c = block_reduce_add<NT, unsigned long long>(c, sh.red_u);
-          if (tid == 0 && c) atomicAdd(x.cut, c);
-          __syncthreads();
-          continue;
-        }
-        if constexpr (MODE == kModeRec) {
-    #pragma unroll
+        if constexpr (COMP) {
+          int32_t ex, ex2;
+          tile_seg_scan<NT>(any_head, s, s2, sh.scan, sh.scan2, &sh.seg_flags, ex, ex2);
+          bool before = true;
+  #pragma unroll
           for (int k = 0; k < ITEMS; ++k) {
             if (vi[k] < 0) continue;
-            const int32_t i = vi[k];
-            const uint32_t loc = e0 + k - sh.ebase[i];
-            x.rec[sh.rb[i] + loc] = Rec{nb[k] == sh.own_c[i] ? -1 : nb[k], wt[k]};
+            if (e0 + k == sh.ebase[vi[k]]) before = false;
+            if (before) {
+              nb[k] += ex;
+              wt[k] += ex2;
+            }
+            if (!weighted) wt[k] = 1;
           }
-          __syncthreads();
-          continue;
         }
-        __syncthreads();  // numbers consumed: region A becomes the table
-        if (tid < nv) atomicMax(&sh.max_nsl, sh.tbase[tid + 1] - sh.tbase[tid]);
-        for (uint32_t q = tid; q < St; q += NT) keys[q] = kEmpty;
-        for (uint32_t q = tid; q < St; q += NT) vals[q] = 0;
+      }
+  #pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        if (vi[k] < 0) continue;
+        if ((uint32_t)nb[k] < (uint32_t)x.g.n) nb[k] = x.C[nb[k]];
+        else vi[k] = -1;  // unreachable for a valid handle; keeps the gather in bounds
+      }
+      if constexpr (MODE == kModeCut) {
+        unsigned long long c = 0;
+  #pragma unroll
+        for (int k = 0; k < ITEMS; ++k)
+          if (vi[k] >= 0 && nb[k] != sh.own_c[vi[k]]) c += (unsigned long long)wt[k];
+        c = block_reduce_add<NT, unsigned long long>(c, sh.red_u);
+        if (tid == 0 && c) atomicAdd(x.cut, c);
         __syncthreads();
-        // 4. ratings
-    #pragma unroll
+        continue;
+      }
+      if constexpr (MODE == kModeRec) {
+  #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
           if (vi[k] < 0) continue;
           const int32_t i = vi[k];
-          tile_insert<V>(keys, vals, sh.tbase[i], sh.tbase[i + 1] - sh.tbase[i], nb[k], (V)wt[k]);
+          const uint32_t loc = e0 + k - sh.ebase[i];
+          x.rec[sh.rb[i] + loc] = Rec{nb[k] == sh.own_c[i] ? -1 : nb[k], wt[k]};
         }
         __syncthreads();
-        // 5. selection: one walk over the slots of each vertex; tiles of small
-        // vertices use 16-lane groups (four vertices per wavefront at a time)
-        const bool small_v = SG == kWave && sh.max_nsl <= 256;
-        if (small_v) tile_select<16, NT, V>(x, keys, vals, sh, nv, tid, false);
-        else tile_select<SG, NT, V>(x, keys, vals, sh, nv, tid, false);
-        __syncthreads();
-        if (tid < nv) {
-          const int32_t u = sh.u[tid];
-          const int32_t c = sh.best_c[tid];
-          if (c < 0) {
-            x.ptgt[u] = -1;
-          } else if (x.W[c] + sh.wu[tid] <= sh.vp.cap) {
-            x.ptgt[u] = c;
-            x.pgain[u] = sh.gain[tid];
-          } else {
-            sh.best_c[tid] = -2;  // walk again with the cap
-            atomicOr(&sh.any_redo, 1u);
-          }
+        continue;
+      }
+      __syncthreads();  // numbers consumed: region A becomes the table
+      if (tid < nv) atomicMax(&sh.max_nsl, sh.tbase[tid + 1] - sh.tbase[tid]);
+      for (uint32_t q = tid; q < St; q += NT) keys[q] = kEmpty;
+      for (uint32_t q = tid; q < St; q += NT) vals[q] = 0;
+      __syncthreads();
+      // 4. ratings
+  #pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        if (vi[k] < 0) continue;
+        const int32_t i = vi[k];
+        tile_insert<V>(keys, vals, sh.tbase[i], sh.tbase[i + 1] - sh.tbase[i], nb[k], (V)wt[k]);
+      }
+      __syncthreads();
+      // 5. selection: one walk over the slots of each vertex; tiles of small
+      // vertices use 16-lane groups (four vertices per wavefront at a time)
+      const bool small_v = SG == kWave && sh.max_nsl <= 256;
+      if (small_v) tile_select<16, NT, V>(x, keys, vals, sh, nv, tid, false);
+      else tile_select<SG, NT, V>(x, keys, vals, sh, nv, tid, false);
+      __syncthreads();
+      if (tid < nv) {
+        const int32_t u = sh.u[tid];
+        const int32_t c = sh.best_c[tid];
+        if (c < 0) {
+          x.ptgt[u] = -1;
+        } else if (x.W[c] + sh.wu[tid] <= sh.vp.cap) {
+          x.ptgt[u] = c;
+          x.pgain[u] = sh.gain[tid];
+        } else {
+          sh.best_c[tid] = -2;  // walk again with the cap
+          atomicOr(&sh.any_redo, 1u);
         }
-        __syncthreads();
-        if (sh.any_redo) {
-          if (small_v) tile_select<16, NT, V>(x, keys, vals, sh, nv, tid, true);
-          else tile_select<SG, NT, V>(x, keys, vals, sh, nv, tid, true);
-        }
-        __syncthreads();
+      }
+      __syncthreads();
+      if (sh.any_redo) {
+        if (small_v) tile_select<16, NT, V>(x, keys, vals, sh, nv, tid, true);
+        else tile_select<SG, NT, V>(x, keys, vals, sh, nv, tid, true);
+      }
+      __syncthreads();
     }
   }
 }
@@ -1232,7 +1232,10 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta 
             if (S > 1 && (uint32_t)(((uint64_t)(uint32_t)c2 * S) / (uint64_t)x.g.n) != sp) continue;
             const V w = rec_r[r];
             uint32_t hs = slot_hash((uint32_t)c2) >> shift;
-            bool reserved = false;
+            // one sub-pass: the table has at least twice as many slots as
+            // the partition has records, so it cannot fill and the distinct
+            // count (one contended LDS atomic per new cluster) is not needed
+            bool reserved = S == 1;
             while (true) {
               const int32_t kk = keys[hs];
               if (kk == c2) {

@@ -140,11 +140,15 @@ __global__ __launch_bounds__(256) void k_class_list(const uint8_t* cls, int32_t 
 
 __device__ __forceinline__ uint32_t ceil_log2(uint32_t x) { return x <= 1 ? 0 : 32 - __clz(x - 1); }
 
+// Adds w to key b's slot. With `guard`, a new key first reserves one of
+// `limit` entries (a shared counter) and sets *overflow when none is left;
+// without it the caller guarantees that the table cannot fill (at most half
+// its slots distinct keys), and the contended counter is skipped.
 __device__ __forceinline__ void tbl_add_guarded(int32_t* keys, int64_t* vals, uint32_t mask, uint32_t shift,
                                                 int32_t b, int64_t w, uint32_t limit, uint32_t* distinct,
-                                                uint32_t* overflow) {
+                                                uint32_t* overflow, bool guard = true) {
   uint32_t h = slot_hash((uint32_t)b) >> shift;
-  bool reserved = false;
+  bool reserved = !guard;
   while (true) {
     const int32_t k = keys[h];
     if (k == b) {
@@ -349,7 +353,8 @@ __global__ __launch_bounds__(kLightThreads) void k_contract_light(AggArgs A, con
     const uint32_t d = (uint32_t)A.dsum[a];
     for (uint32_t i = tid; i < d; i += NT) {
       const Rec x = r[i];
-      if (x.b >= 0) tbl_add_guarded(keys, vals, mask, shift, x.b, (int64_t)x.w, limit, &sm.distinct, &sm.overflow);
+      if (x.b >= 0)
+        tbl_add_guarded(keys, vals, mask, shift, x.b, (int64_t)x.w, limit, &sm.distinct, &sm.overflow, limit < cap);
     }
     group_sync<NT>();
     if (sm.overflow) {
@@ -603,7 +608,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_heavy_reduce(AggArgs A, Heav
           if (dense)
             atomicAdd((unsigned long long*)&vals[(uint64_t)x.b - lo], (unsigned long long)(int64_t)x.w);
           else
-            tbl_add_guarded(keys, vals, mask, shift, x.b, (int64_t)x.w, limit, &sm.distinct, &sm.overflow);
+            tbl_add_guarded(keys, vals, mask, shift, x.b, (int64_t)x.w, limit, &sm.distinct, &sm.overflow,
+                            2 * nrec + 2 > tcap);
         }
       }
       __syncthreads();
