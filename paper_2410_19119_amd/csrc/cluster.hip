@@ -246,6 +246,7 @@ struct TileCfg {
 using TileSmall = TileCfg<256, 2048, 80>;
 using TileLarge = TileCfg<512, 4096, 4>;
 constexpr int kTileSeg = 128;  // vertices walked by one thread of the tiling pass
+constexpr int kTileMaxDeg = 2048;  // largest degree of the small-tile bucket (default and bound of t_tile)
 
 template <int NT, int VT>
 struct TileShared {
@@ -1880,7 +1881,7 @@ lp_status visit_edges_mode(const lp_graph* g, const int32_t* C, const uint64_t* 
                            unsigned long long* cut, hipStream_t s) {
   const Plan* plan = nullptr;
   std::unique_ptr<Plan> tmp;
-  LP_CHECK(get_plan(g, 16, TileSmall::kEdges, TileLarge::kEdges, kDefaultHubPart, s, &plan, tmp));
+  LP_CHECK(get_plan(g, 16, kTileMaxDeg, TileLarge::kEdges, kDefaultHubPart, s, &plan, tmp));
   Scratch sc(s);
   // zero[0]: the round's "done" flag (never set here); zero[8..32): hand-out
   // counters of the small tiles, the large tiles and the pieces
@@ -1932,7 +1933,7 @@ lp_status visit_edges_mode(const lp_graph* g, const int32_t* C, const uint64_t* 
 // (built on first use), otherwise a new one owned by `tmp`.
 lp_status get_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t t_block, int32_t hub_part,
                    hipStream_t s, const Plan** out, std::unique_ptr<Plan>& tmp) {
-  const bool dflt = t_lane == 16 && t_tile == TileSmall::kEdges && t_block == TileLarge::kEdges &&
+  const bool dflt = t_lane == 16 && t_tile == kTileMaxDeg && t_block == TileLarge::kEdges &&
                     hub_part == kDefaultHubPart;
   if (!dflt) {
     tmp.reset(new Plan());
@@ -1990,14 +1991,14 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
   if (n == 0) return LP_OK;
   // knobs (results do not depend on them)
   const bool wide = g->max_wdeg > 0x7FFFFFFFll;
-  int32_t t_lane = 16, t_tile = TileSmall::kEdges, t_block = TileLarge::kEdges, hub_part = kDefaultHubPart;
+  int32_t t_lane = 16, t_tile = kTileMaxDeg, t_block = TileLarge::kEdges, hub_part = kDefaultHubPart;
   if (cfg_in) {
     if (cfg_in->t_lane) t_lane = cfg_in->t_lane;
     if (cfg_in->t_tile) t_tile = cfg_in->t_tile;
     if (cfg_in->t_block) t_block = cfg_in->t_block;
     if (cfg_in->hub_part) hub_part = cfg_in->hub_part;
   }
-  if (t_lane < 0 || t_lane > kMaxLane || t_tile < t_lane || t_tile > TileSmall::kEdges || t_block < t_tile ||
+  if (t_lane < 0 || t_lane > kMaxLane || t_tile < t_lane || t_tile > kTileMaxDeg || t_block < t_tile ||
       t_block > TileLarge::kEdges || hub_part < 256 || hub_part > 8192)
     return LP_EINVAL;
   // proposal sort key: target bits + gain bits
