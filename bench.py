@@ -36,7 +36,7 @@ PHASE_KERNEL = {
     "lane": "k_rate_lane",
     "tile": "k_rate_tile (small tiles)",
     "block": "k_rate_tile (large tiles)",
-    "hub": "k_hub_scatter+k_hub_reduce+k_hub_combine",
+    "hub": "k_hub_piece+k_hub_reduce+k_hub_combine",
     "accept": "acceptance (compaction, radix sort, segmented scan, admit, apply)",
 }
 
