@@ -1721,6 +1721,7 @@ struct Plan {
   int32_t bn[kNumBuckets] = {};
   uint32_t bstart[kNumBuckets + 1] = {};
   int32_t* order = nullptr;
+  int32_t* deg = nullptr;  // degree of every vertex (also read by the contraction)
   int4* vdesc = nullptr;
   uint32_t* vlen = nullptr;
   TilePlan tps, tpl;
@@ -1745,7 +1746,8 @@ lp_status build_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t 
   P.mem.alloc_stream = s;
   P.mem.free_stream = g->mem_stream;
   Scratch sc(s);
-  int32_t* deg = sc.alloc<int32_t>(n);
+  int32_t* deg = P.mem.alloc<int32_t>(n);
+  P.deg = deg;
   const unsigned nbk = grid_for(n, kBkTile, 0x7FFFFFFF);
   uint32_t* bcnt = sc.alloc<uint32_t>((size_t)kNumBuckets * nbk);
   uint32_t* btot = sc.alloc<uint32_t>(1);
@@ -1957,6 +1959,14 @@ lp_status get_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t t_
 
 lp_status batch_localize(const lp_graph* b, const int32_t* lab, int32_t* out, int32_t* const* outs_dev,
                          hipStream_t s);
+
+lp_status plan_degrees(const lp_graph* g, const int32_t** deg, hipStream_t s) {
+  const Plan* plan = nullptr;
+  std::unique_ptr<Plan> tmp;
+  LP_CHECK(get_plan(g, 16, kTileMaxDeg, TileLarge::kEdges, kDefaultHubPart, s, &plan, tmp));
+  *deg = plan->deg;
+  return LP_OK;
+}
 
 lp_status visit_edges_cut(const lp_graph* g, const int32_t* labels, unsigned long long* cut, hipStream_t s) {
   if (g->n == 0) return LP_OK;

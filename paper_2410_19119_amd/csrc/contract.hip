@@ -27,6 +27,8 @@
 #include "graph.h"
 
 namespace lp {
+// Degrees of g's vertices, kept in g's cached plan (built here if needed).
+lp_status plan_degrees(const lp_graph* g, const int32_t** deg, hipStream_t s);
 lp_status visit_edges_records(const lp_graph* g, const int32_t* map, const uint64_t* rbase, const uint64_t* voff,
                               Rec* rec, hipStream_t s);
 
@@ -140,19 +142,30 @@ __global__ __launch_bounds__(256) void k_class_list(const uint8_t* cls, int32_t 
 
 __device__ __forceinline__ uint32_t ceil_log2(uint32_t x) { return x <= 1 ? 0 : 32 - __clz(x - 1); }
 
+// Table values: 64-bit sums, or 32-bit sums where no sum can reach 2^31 (a
+// graph with unit edge weights and fewer than 2^31 directed edges).
+__device__ __forceinline__ void tbl_val_add(unsigned long long* v, int64_t w) {
+  atomicAdd(v, (unsigned long long)w);
+}
+__device__ __forceinline__ void tbl_val_add(int64_t* v, int64_t w) {
+  atomicAdd((unsigned long long*)v, (unsigned long long)w);
+}
+__device__ __forceinline__ void tbl_val_add(uint32_t* v, int64_t w) { atomicAdd(v, (uint32_t)w); }
+
 // Adds w to key b's slot. With `guard`, a new key first reserves one of
 // `limit` entries (a shared counter) and sets *overflow when none is left;
 // without it the caller guarantees that the table cannot fill (at most half
 // its slots distinct keys), and the contended counter is skipped.
-__device__ __forceinline__ void tbl_add_guarded(int32_t* keys, int64_t* vals, uint32_t mask, uint32_t shift,
-                                                int32_t b, int64_t w, uint32_t limit, uint32_t* distinct,
-                                                uint32_t* overflow, bool guard = true) {
+template <typename V>
+__device__ __forceinline__ void tbl_add_guarded(int32_t* keys, V* vals, uint32_t mask, uint32_t shift, int32_t b,
+                                                int64_t w, uint32_t limit, uint32_t* distinct, uint32_t* overflow,
+                                                bool guard = true) {
   uint32_t h = slot_hash((uint32_t)b) >> shift;
   bool reserved = !guard;
   while (true) {
     const int32_t k = keys[h];
     if (k == b) {
-      atomicAdd((unsigned long long*)&vals[h], (unsigned long long)w);
+      tbl_val_add(&vals[h], w);
       return;
     }
     if (k == kEmpty) {
@@ -165,7 +178,7 @@ __device__ __forceinline__ void tbl_add_guarded(int32_t* keys, int64_t* vals, ui
       }
       const int32_t old = atomicCAS(&keys[h], kEmpty, b);
       if (old == kEmpty || old == b) {
-        atomicAdd((unsigned long long*)&vals[h], (unsigned long long)w);
+        tbl_val_add(&vals[h], w);
         return;
       }
     }
@@ -233,13 +246,14 @@ __device__ unsigned long long* lds_sort_u64(unsigned long long* a, unsigned long
 }
 
 // Writes the table's entries to `out` sorted by key: every thread takes its
-// (strided) slots into registers, a prefix count compacts the entries to the
-// front of the table as (key << 32 | value) pairs, which lds_sort_u64 sorts.
-// Returns the entry count. cap <= NT * SLOTS and the table never holds more
-// than cap / 2 entries, so the second sort buffer fits behind the entries.
-template <int NT, int SLOTS>
-__device__ uint32_t compact_sort_write(int32_t* keys, int64_t* vals, uint32_t cap, Rec* out, uint32_t* err,
-                                       int32_t* scan_sm) {
+// (strided) slots into registers, a prefix count compacts the entries to pk
+// as (key << 32 | value) pairs, which lds_sort_u64 sorts. Returns the entry
+// count. cap <= NT * SLOTS and the table never holds more than cap / 2
+// entries; pk is the start of the table's LDS region (cap * 8 bytes or more:
+// keys and values), so both sort buffers fit in it once the slots are read.
+template <int NT, int SLOTS, typename V>
+__device__ uint32_t compact_sort_write(int32_t* keys, V* vals, uint32_t cap, Rec* out, uint32_t* err,
+                                       int32_t* scan_sm, unsigned long long* pk) {
   const int tid = group_tid<NT>();
   int32_t kk[SLOTS];
   int64_t vv[SLOTS];
@@ -251,14 +265,13 @@ __device__ uint32_t compact_sort_write(int32_t* keys, int64_t* vals, uint32_t ca
     vv[i] = 0;
     if (q < cap) {
       kk[i] = keys[q];
-      vv[i] = vals[q];
+      vv[i] = (int64_t)vals[q];
       c += kk[i] != kEmpty;
     }
   }
   int32_t tot;
   int32_t o = block_incl_scan_add<NT, int32_t>(c, scan_sm, &tot) - c;
   group_sync<NT>();
-  unsigned long long* pk = (unsigned long long*)vals;
 #pragma unroll
   for (int i = 0; i < SLOTS; ++i)
     if (kk[i] != kEmpty) {
@@ -278,8 +291,8 @@ __device__ uint32_t compact_sort_write(int32_t* keys, int64_t* vals, uint32_t ca
 
 // Writes the nonzero entries of a direct array over coarse IDs [lo, lo +
 // width) in ID order; returns their number.
-template <int NT>
-__device__ uint32_t dense_write(const int64_t* vals, uint32_t width, uint64_t lo, Rec* out, uint32_t* err,
+template <int NT, typename V>
+__device__ uint32_t dense_write(const V* vals, uint32_t width, uint64_t lo, Rec* out, uint32_t* err,
                                 int32_t* scan_sm) {
   const int tid = group_tid<NT>();
   const uint32_t per = (width + NT - 1) / NT;
@@ -289,7 +302,7 @@ __device__ uint32_t dense_write(const int64_t* vals, uint32_t width, uint64_t lo
   int32_t tot;
   int32_t o = block_incl_scan_add<NT, int32_t>(c, scan_sm, &tot) - c;
   for (uint32_t q = q0; q < q1; ++q) {
-    const int64_t v = vals[q];
+    const int64_t v = (int64_t)vals[q];
     if (!v) continue;
     if (v > 0x7FFFFFFFll) atomicOr(err, kErrOverflow);
     out[o++] = Rec{(int32_t)(lo + q), (int32_t)v};
@@ -321,7 +334,7 @@ struct LightSmem {
 // >= 2 * min(dsum, nc - 1) entries, at most tmax; if that capacity was
 // clipped and the cluster turns out to have more than half of it distinct
 // neighbours, the cluster is appended to the heavy list instead.
-template <int NT>
+template <int NT, typename V>
 __global__ __launch_bounds__(kLightThreads) void k_contract_light(AggArgs A, const int32_t* list, int32_t cnt,
                                                                   uint32_t tmax, int32_t* heavy_list,
                                                                   uint32_t* nheavy) {
@@ -329,11 +342,11 @@ __global__ __launch_bounds__(kLightThreads) void k_contract_light(AggArgs A, con
   constexpr int G = kLightThreads / NT;
   const int gi = (int)(threadIdx.x / NT);
   const int tid = group_tid<NT>();
-  const size_t per = ((size_t)tmax * 12 + sizeof(LightSmem<NT>) + 15) & ~size_t(15);
+  const size_t per = ((size_t)tmax * (4 + sizeof(V)) + sizeof(LightSmem<NT>) + 15) & ~size_t(15);
   uint8_t* base = smem_raw + gi * per;
-  int64_t* vals = (int64_t*)base;
-  int32_t* keys = (int32_t*)(base + (size_t)tmax * 8);
-  LightSmem<NT>& sm = *(LightSmem<NT>*)(base + (size_t)tmax * 12);
+  V* vals = (V*)base;
+  int32_t* keys = (int32_t*)(base + (size_t)tmax * sizeof(V));
+  LightSmem<NT>& sm = *(LightSmem<NT>*)(base + (size_t)tmax * (4 + sizeof(V)));
   for (int64_t it = (int64_t)blockIdx.x * G + gi; it < cnt; it += (int64_t)gridDim.x * G) {
     const int32_t a = list[it];
     const uint32_t want = (uint32_t)A.tcap[a];
@@ -362,7 +375,8 @@ __global__ __launch_bounds__(kLightThreads) void k_contract_light(AggArgs A, con
       group_sync<NT>();
       continue;
     }
-    const uint32_t k = compact_sort_write<NT, (NT == kWave ? 8 : 16)>(keys, vals, cap, r, A.err, sm.scan);
+    constexpr int kSlots = NT == kWave ? 8 : 16;
+    const uint32_t k = compact_sort_write<NT, kSlots, V>(keys, vals, cap, r, A.err, sm.scan, (unsigned long long*)base);
     if (tid == 0) A.cdeg[a] = k;
     group_sync<NT>();
   }
@@ -561,12 +575,13 @@ struct ReduceSmem {
 // in LDS over coarse-ID windows (a window whose distinct count exceeds half
 // the table is halved and retried), emitting each window sorted. The table
 // is sized by the task's record count.
+template <typename V>
 __global__ __launch_bounds__(kReduceThreads) void k_heavy_reduce(AggArgs A, Heavy hv, int32_t ntasks) {
   extern __shared__ __align__(16) uint8_t smem_raw[];
   constexpr int NT = kReduceThreads;
-  int64_t* vals = (int64_t*)smem_raw;
-  int32_t* keys = (int32_t*)(smem_raw + (size_t)kHeavyTable * 8);
-  ReduceSmem& sm = *(ReduceSmem*)(smem_raw + (size_t)kHeavyTable * 12);
+  V* vals = (V*)smem_raw;
+  int32_t* keys = (int32_t*)(smem_raw + (size_t)kHeavyTable * sizeof(V));
+  ReduceSmem& sm = *(ReduceSmem*)(smem_raw + (size_t)kHeavyTable * (4 + sizeof(V)));
   const int tid = threadIdx.x;
   const uint64_t nc = (uint64_t)A.nc;
   for (int64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
@@ -606,7 +621,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_heavy_reduce(AggArgs A, Heav
         const Rec x = src[j];
         if ((uint64_t)x.b >= lo && (uint64_t)x.b < hi) {
           if (dense)
-            atomicAdd((unsigned long long*)&vals[(uint64_t)x.b - lo], (unsigned long long)(int64_t)x.w);
+            tbl_val_add(&vals[(uint64_t)x.b - lo], (int64_t)x.w);
           else
             tbl_add_guarded(keys, vals, mask, shift, x.b, (int64_t)x.w, limit, &sm.distinct, &sm.overflow,
                             2 * nrec + 2 > tcap);
@@ -619,8 +634,9 @@ __global__ __launch_bounds__(kReduceThreads) void k_heavy_reduce(AggArgs A, Heav
         continue;
       }
       Rec* dst = hv.out + obase + written;
-      const uint32_t k = dense ? dense_write<NT>(vals, (uint32_t)(hi - lo), lo, dst, A.err, sm.scan)
-                               : compact_sort_write<NT, kHeavyTable / NT>(keys, vals, tcap, dst, A.err, sm.scan);
+      const uint32_t k = dense ? dense_write<NT, V>(vals, (uint32_t)(hi - lo), lo, dst, A.err, sm.scan)
+                               : compact_sort_write<NT, kHeavyTable / NT, V>(keys, vals, tcap, dst, A.err, sm.scan,
+                                                                             (unsigned long long*)smem_raw);
       written += k;
       lo = hi;
       width = hi_p - lo;  // try the rest of the partition in one window again
@@ -765,13 +781,13 @@ lp_status set_lds(F* kern, size_t bytes) {
   return LP_OK;
 }
 
-template <int NT>
+template <int NT, typename V>
 lp_status launch_light(const AggArgs& A, const int32_t* list, uint32_t cnt, uint32_t tmax, int32_t* heavy_list,
                        uint32_t* nheavy, hipStream_t s) {
   if (cnt == 0) return LP_OK;
-  const size_t per = ((size_t)tmax * 12 + sizeof(LightSmem<NT>) + 15) & ~size_t(15);
+  const size_t per = ((size_t)tmax * (4 + sizeof(V)) + sizeof(LightSmem<NT>) + 15) & ~size_t(15);
   const size_t bytes = per * (kLightThreads / NT);
-  auto k = k_contract_light<NT>;
+  auto k = k_contract_light<NT, V>;
   LP_CHECK(set_lds(k, bytes));
   hipLaunchKernelGGL(k, dim3(grid_for(cnt, kLightThreads / NT, 1u << 20)), dim3(kLightThreads), bytes, s, A, list,
                      (int32_t)cnt, tmax, heavy_list, nheavy);
@@ -781,7 +797,7 @@ lp_status launch_light(const AggArgs& A, const int32_t* list, uint32_t cnt, uint
 // Heavy clusters: metadata, partitioning, counts, reduction. Fills the coarse
 // degrees of heavy clusters and leaves what placement needs in *hv_out.
 // rec2 has the layout of the record buffer.
-lp_status contract_heavy(const AggArgs& A, const int32_t* hl, int32_t H, Rec* rec2, Heavy* hv_out,
+lp_status contract_heavy(const AggArgs& A, const int32_t* hl, int32_t H, Rec* rec2, bool narrow, Heavy* hv_out,
                          int32_t* ntasks_out, uint64_t** tdeg_scan_out, Scratch& sc) {
   hipStream_t s = sc.stream();
   Heavy hv{};
@@ -849,9 +865,17 @@ lp_status contract_heavy(const AggArgs& A, const int32_t* hl, int32_t H, Rec* re
             (unsigned long long)nout);
   hv.out = sc.alloc<Rec>(nout);
   if (sc.failed) return LP_ENOMEM;
-  const size_t rbytes = (size_t)kHeavyTable * 12 + sizeof(ReduceSmem);
-  LP_CHECK(set_lds(k_heavy_reduce, rbytes));
-  hipLaunchKernelGGL(k_heavy_reduce, dim3(grid_for(T, 1, 1u << 20)), dim3(kReduceThreads), rbytes, s, A, hv, T);
+  if (narrow) {
+    const size_t rbytes = (size_t)kHeavyTable * 8 + sizeof(ReduceSmem);
+    LP_CHECK(set_lds(k_heavy_reduce<uint32_t>, rbytes));
+    hipLaunchKernelGGL(k_heavy_reduce<uint32_t>, dim3(grid_for(T, 1, 1u << 20)), dim3(kReduceThreads), rbytes, s, A,
+                       hv, T);
+  } else {
+    const size_t rbytes = (size_t)kHeavyTable * 12 + sizeof(ReduceSmem);
+    LP_CHECK(set_lds(k_heavy_reduce<int64_t>, rbytes));
+    hipLaunchKernelGGL(k_heavy_reduce<int64_t>, dim3(grid_for(T, 1, 1u << 20)), dim3(kReduceThreads), rbytes, s, A,
+                       hv, T);
+  }
   LP_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_heavy_cdeg, dim3(grid_for(H, 256, 4096)), dim3(256), 0, s, hv, H, A.cdeg);
   LP_CHECK_LAUNCH();
@@ -889,7 +913,7 @@ extern "C" lp_status lp_contract(const lp_graph* g, const int32_t* labels, int32
     uint64_t nrec;
   };
   Ctl* ctl = sc.alloc<Ctl>(1);
-  int32_t* deg = sc.alloc<int32_t>(n);
+  const int32_t* deg = nullptr;
   uint32_t* flags = sc.alloc<uint32_t>(n);
   int32_t* map = map_out ? map_out : sc.alloc<int32_t>(n);
   if (sc.failed) return LP_ENOMEM;
@@ -907,7 +931,7 @@ extern "C" lp_status lp_contract(const lp_graph* g, const int32_t* labels, int32
       if (hipMemsetAsync(cg->xadj, 0, sizeof(uint64_t), s) != hipSuccess) { st = LP_EDEVICE; break; }
       break;
     }
-    st = compute_degrees(g, deg, s);
+    st = plan_degrees(g, &deg, s);
     if (st) break;
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, flags, (int64_t)n, 0u);
     hipLaunchKernelGGL(k_check_mark, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, labels, n, flags, &ctl->err);
@@ -972,9 +996,23 @@ extern "C" lp_status lp_contract(const lp_graph* g, const int32_t* labels, int32
     const int64_t stride = nc;
     int32_t* hlist = lists + 3 * stride;
     uint32_t* nheavy = &ctl->ccount[4];
-    st = launch_light<kWave>(A, lists, h.ccount[1], 2 * kClassWave, hlist, nheavy, s);
-    if (!st) st = launch_light<kLightThreads>(A, lists + stride, h.ccount[2], 2 * kClassBlockS, hlist, nheavy, s);
-    if (!st) st = launch_light<kLightThreads>(A, lists + 2 * stride, h.ccount[3], 2 * kClassBlockL, hlist, nheavy, s);
+    // 32-bit table sums where no coarse edge weight can reach 2^31
+    const bool narrow = !g->weighted && g->two_m < (1ull << 31);
+    if (narrow) {
+      st = launch_light<kWave, uint32_t>(A, lists, h.ccount[1], 2 * kClassWave, hlist, nheavy, s);
+      if (!st)
+        st = launch_light<kLightThreads, uint32_t>(A, lists + stride, h.ccount[2], 2 * kClassBlockS, hlist, nheavy, s);
+      if (!st)
+        st = launch_light<kLightThreads, uint32_t>(A, lists + 2 * stride, h.ccount[3], 2 * kClassBlockL, hlist, nheavy,
+                                                   s);
+    } else {
+      st = launch_light<kWave, int64_t>(A, lists, h.ccount[1], 2 * kClassWave, hlist, nheavy, s);
+      if (!st)
+        st = launch_light<kLightThreads, int64_t>(A, lists + stride, h.ccount[2], 2 * kClassBlockS, hlist, nheavy, s);
+      if (!st)
+        st = launch_light<kLightThreads, int64_t>(A, lists + 2 * stride, h.ccount[3], 2 * kClassBlockL, hlist, nheavy,
+                                                  s);
+    }
     if (st) break;
     const uint32_t heavy0 = h.ccount[4];
     if (hipMemcpyAsync(&h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -992,7 +1030,7 @@ extern "C" lp_status lp_contract(const lp_graph* g, const int32_t* labels, int32
     if (H > 0) {
       Rec* rec2 = sc.alloc<Rec>(g->two_m);
       if (!rec2) { st = LP_ENOMEM; break; }
-      st = contract_heavy(A, hlist, H, rec2, &hv, &T, &tscan, sc);
+      st = contract_heavy(A, hlist, H, rec2, narrow, &hv, &T, &tscan, sc);
       if (st) break;
       hipLaunchKernelGGL(k_mark_heavy, dim3(grid_for(H, 256, 4096)), dim3(256), 0, s, hlist, H, heavy);
       st = last_error();
