@@ -1140,6 +1140,7 @@ __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta
 }
 
 constexpr uint32_t kHubTable = 4096;  // max LDS entries of a (hub, partition) task
+constexpr int kRedItems = 8;          // records loaded per thread before inserting
 
 struct HubReduceSmem {
   Cand best[kHubThreads / kWave];
@@ -1221,43 +1222,61 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta 
           sm.ra[tid] = ra;
           sm.pre[tid] = incl - (int32_t)c;
           __syncthreads();
-          for (int32_t j = tid; j < total; j += NT) {
-            int32_t lo = 0, hi = NT;
-            while (hi - lo > 1) {
-              const int32_t mid = (lo + hi) >> 1;
-              if (sm.pre[mid] <= j) lo = mid;
-              else hi = mid;
-            }
-            const uint64_t r = rb0 + (uint64_t)(kb + lo) * kHubPiece + sm.ra[lo] + (uint32_t)(j - sm.pre[lo]);
-            const int32_t c2 = hm.rec_c[r];
-            if (S > 1 && (uint32_t)(((uint64_t)(uint32_t)c2 * S) / (uint64_t)x.g.n) != sp) continue;
-            const V w = rec_r[r];
-            uint32_t hs = slot_hash((uint32_t)c2) >> shift;
-            // one sub-pass: the table has at least twice as many slots as
-            // the partition has records, so it cannot fill and the distinct
-            // count (one contended LDS atomic per new cluster) is not needed
-            bool reserved = S == 1;
-            while (true) {
-              const int32_t kk = keys[hs];
-              if (kk == c2) {
-                lds_add(&vals[hs], w);
-                break;
-              }
-              if (kk == kEmpty) {
-                if (!reserved) {
-                  if (atomicAdd(&sm.distinct, 1u) >= limit) {
-                    sm.overflow = 1;
-                    break;
-                  }
-                  reserved = true;
+          // the batch's records in rounds of kRedItems per thread: all loads of
+          // a round are issued before any insertion
+          for (int32_t j0 = 0; j0 < total; j0 += NT * kRedItems) {
+            int32_t cc[kRedItems];
+            V ww[kRedItems];
+#pragma unroll
+            for (int q = 0; q < kRedItems; ++q) {
+              const int32_t j = j0 + q * NT + tid;
+              cc[q] = kEmpty;
+              ww[q] = 0;
+              if (j < total) {
+                int32_t lo = 0, hi = NT;
+                while (hi - lo > 1) {
+                  const int32_t mid = (lo + hi) >> 1;
+                  if (sm.pre[mid] <= j) lo = mid;
+                  else hi = mid;
                 }
-                const int32_t old = atomicCAS(&keys[hs], kEmpty, c2);
-                if (old == kEmpty || old == c2) {
+                const uint64_t r = rb0 + (uint64_t)(kb + lo) * kHubPiece + sm.ra[lo] + (uint32_t)(j - sm.pre[lo]);
+                cc[q] = hm.rec_c[r];
+                ww[q] = rec_r[r];
+              }
+            }
+#pragma unroll
+            for (int q = 0; q < kRedItems; ++q) {
+              const int32_t c2 = cc[q];
+              if (c2 == kEmpty) continue;
+              if (S > 1 && (uint32_t)(((uint64_t)(uint32_t)c2 * S) / (uint64_t)x.g.n) != sp) continue;
+              const V w = ww[q];
+              uint32_t hs = slot_hash((uint32_t)c2) >> shift;
+              // one sub-pass: the table has at least twice as many slots as
+              // the partition has records, so it cannot fill and the distinct
+              // count (one contended LDS atomic per new cluster) is not needed
+              bool reserved = S == 1;
+              while (true) {
+                const int32_t kk = keys[hs];
+                if (kk == c2) {
                   lds_add(&vals[hs], w);
                   break;
                 }
+                if (kk == kEmpty) {
+                  if (!reserved) {
+                    if (atomicAdd(&sm.distinct, 1u) >= limit) {
+                      sm.overflow = 1;
+                      break;
+                    }
+                    reserved = true;
+                  }
+                  const int32_t old = atomicCAS(&keys[hs], kEmpty, c2);
+                  if (old == kEmpty || old == c2) {
+                    lds_add(&vals[hs], w);
+                    break;
+                  }
+                }
+                hs = (hs + 1) & mask;
               }
-              hs = (hs + 1) & mask;
             }
           }
           __syncthreads();
@@ -1500,9 +1519,12 @@ __global__ void k_admit(const uint32_t* seg, const int64_t* prefix, const uint32
   }
 }
 
+// The admitted proposals of a target are a prefix of its segment (the
+// inclusive weight prefix grows along it), so the target's weight grows by
+// the prefix at the last admitted one: one atomic per target, not per move.
 __global__ __launch_bounds__(256) void k_apply(const uint32_t* seg, const uint32_t* vals, const uint8_t* flag,
-                                               const int64_t* wv, const uint32_t* count, int32_t* C, int64_t* W,
-                                               int64_t* stats, int round) {
+                                               const int64_t* wv, const int64_t* prefix, const uint32_t* count,
+                                               int32_t* C, int64_t* W, int64_t* stats, int round) {
   __shared__ int64_t sm[4];
   const int64_t n = *count;
   int64_t moves = 0;
@@ -1511,10 +1533,10 @@ __global__ __launch_bounds__(256) void k_apply(const uint32_t* seg, const uint32
     const int32_t u = (int32_t)vals[i];
     const int32_t t = (int32_t)seg[i];
     const int32_t old = C[u];
-    const int64_t w = wv[i];
     C[u] = t;
-    atomicAdd((unsigned long long*)&W[t], (unsigned long long)w);
-    atomicAdd((unsigned long long*)&W[old], (unsigned long long)(-w));
+    if (i + 1 == n || seg[i + 1] != (uint32_t)t || !flag[i + 1])
+      atomicAdd((unsigned long long*)&W[t], (unsigned long long)prefix[i]);
+    atomicAdd((unsigned long long*)&W[old], (unsigned long long)(-wv[i]));
     ++moves;
   }
   moves = block_reduce_add<256, int64_t>(moves, sm);
@@ -2217,7 +2239,8 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
     LP_CHECK(seg_scan_incl_i64(seg, wv, pref, &ctl->count, n, sc));
     hipLaunchKernelGGL(k_admit, dim3(ga), dim3(256), 0, s, seg, pref, &ctl->count, W, cap, x.gid, gcap, flag);
     LP_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_apply, dim3(ga), dim3(256), 0, s, seg, vs, flag, wv, &ctl->count, labels, W, ctl->stats, r);
+    hipLaunchKernelGGL(k_apply, dim3(ga), dim3(256), 0, s, seg, vs, flag, wv, pref, &ctl->count, labels, W, ctl->stats,
+                       r);
     LP_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, s, &ctl->count, &ctl->done, ctl->stats, r, &ctl->rounds_run);
     LP_CHECK_LAUNCH();
