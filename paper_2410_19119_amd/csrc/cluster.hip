@@ -565,7 +565,7 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
         for (uint32_t j0 = tid; j0 < Dt; j0 += 4 * NT) {
           uint32_t w[4], off[4];
           int32_t vi4[4];
-  #pragma unroll
+#pragma unroll
           for (int k = 0; k < 4; ++k) {
             const uint32_t j = j0 + (uint32_t)k * NT;
             vi4[k] = -1;
@@ -578,13 +578,13 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
               w[k] = *(const uint32_t*)(x.g.bytes + (sh.pos[i] & ~3ull) + off[k]);
             }
           }
-  #pragma unroll
+#pragma unroll
           for (int k = 0; k < 4; ++k) {
             if (vi4[k] < 0) continue;
             const int32_t i = vi4[k];
             const uint32_t b0 = (uint32_t)(sh.pos[i] & 3u), b1 = b0 + sh.len[i];
             uint32_t v = w[k];
-  #pragma unroll
+#pragma unroll
             for (uint32_t b = 0; b < 4; ++b)
               if (off[k] + b < b0 || off[k] + b >= b1) v &= ~(0xFFu << (8 * b));
             A32[j0 + (uint32_t)k * NT] = v;
@@ -623,7 +623,7 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
         int32_t i = e0 < Et ? tile_find(sh.ebase, nv, e0) : 0;
         bool any_head = false;
         int32_t s = 0, s2 = 0;
-  #pragma unroll
+#pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
           const uint32_t e = e0 + k;
           vi[k] = -1;
@@ -660,7 +660,7 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
           int32_t ex, ex2;
           tile_seg_scan<NT>(any_head, s, s2, sh.scan, sh.scan2, &sh.seg_flags, ex, ex2);
           bool before = true;
-  #pragma unroll
+#pragma unroll
           for (int k = 0; k < ITEMS; ++k) {
             if (vi[k] < 0) continue;
             if (e0 + k == sh.ebase[vi[k]]) before = false;
@@ -672,7 +672,7 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
           }
         }
       }
-  #pragma unroll
+#pragma unroll
       for (int k = 0; k < ITEMS; ++k) {
         if (vi[k] < 0) continue;
         if ((uint32_t)nb[k] < (uint32_t)x.g.n) nb[k] = x.C[nb[k]];
@@ -680,7 +680,7 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
       }
       if constexpr (MODE == kModeCut) {
         unsigned long long c = 0;
-  #pragma unroll
+#pragma unroll
         for (int k = 0; k < ITEMS; ++k)
           if (vi[k] >= 0 && nb[k] != sh.own_c[vi[k]]) c += (unsigned long long)wt[k];
         c = block_reduce_add<NT, unsigned long long>(c, sh.red_u);
@@ -689,7 +689,7 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
         continue;
       }
       if constexpr (MODE == kModeRec) {
-  #pragma unroll
+#pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
           if (vi[k] < 0) continue;
           const int32_t i = vi[k];
@@ -705,7 +705,7 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
       for (uint32_t q = tid; q < St; q += NT) vals[q] = 0;
       __syncthreads();
       // 4. ratings
-  #pragma unroll
+#pragma unroll
       for (int k = 0; k < ITEMS; ++k) {
         if (vi[k] < 0) continue;
         const int32_t i = vi[k];
