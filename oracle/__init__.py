@@ -69,6 +69,10 @@ def _load():
     lib.orc_tiebreak_key.restype = ctypes.c_uint64
     lib.orc_lp_cluster.argtypes = [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32,
                                    ctypes.c_uint64, _P, ctypes.POINTER(_Stats)]
+    lib.orc_lp_cluster_sub.argtypes = [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_uint64, _P, ctypes.POINTER(_Stats)]
+    lib.orc_subround.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+    lib.orc_subround.restype = ctypes.c_uint32
     lib.orc_lp_proposals.argtypes = [ctypes.c_int32, _P, _P, _P, _P, _P, _P, ctypes.c_int64,
                                      ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64, _P, _P, _P]
     lib.orc_contract.argtypes = [ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_int32),
@@ -172,14 +176,21 @@ class LPStats:
     moves: list
 
 
-def lp_cluster(g, cap: int, rounds: int, seed: int):
-    """Labels (int32[n]) of synchronous size-constrained LP, plus per-round stats."""
+def subround(u: int, S: int) -> int:
+    """Sub-round of vertex u among S (fixed for a whole call)."""
+    return int(_load().orc_subround(u, S))
+
+
+def lp_cluster(g, cap: int, rounds: int, seed: int, subrounds: int = 1):
+    """Labels (int32[n]) of synchronous size-constrained LP, plus per-round stats.
+    With subrounds = S > 1 every round is split into S sub-rounds over the
+    vertices of each sub-round (see orc_lp_cluster_sub)."""
     lib = _load()
     labels = np.empty(max(g.n, 1), dtype=np.int32)
     st = _Stats()
-    rc = lib.orc_lp_cluster(g.n, _ptr(_arr(g.xadj, np.uint64)), _ptr(_arr(g.adjncy, np.int32)),
-                            _ptr(_arr(g.adjwgt, np.int32)), _ptr(_arr(g.vwgt, np.int32)), cap, rounds,
-                            seed, _ptr(labels), ctypes.byref(st))
+    rc = lib.orc_lp_cluster_sub(g.n, _ptr(_arr(g.xadj, np.uint64)), _ptr(_arr(g.adjncy, np.int32)),
+                                _ptr(_arr(g.adjwgt, np.int32)), _ptr(_arr(g.vwgt, np.int32)), cap, rounds,
+                                subrounds, seed, _ptr(labels), ctypes.byref(st))
     if rc != OK:
         raise ValueError(f"orc_lp_cluster: {rc}")
     k = min(st.rounds_run, 64)

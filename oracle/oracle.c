@@ -304,19 +304,32 @@ static int best_move(int32_t u, const uint64_t *xadj, const int32_t *adjncy, con
   return 1;
 }
 
-/* Size-constrained LP clustering, synchronous rounds.
+/* Sub-round of vertex u among S: the tie-break mix above applied to the
+ * fixed salt ORC_SUBROUND_SALT and u (round 0), modulo S. It depends on u
+ * only, so a vertex keeps its sub-round for the whole call. */
+#define ORC_SUBROUND_SALT 0x6A09E667F3BCC909ull
+uint32_t orc_subround(uint32_t u, uint32_t S) {
+  return (uint32_t)(orc_tiebreak_key(ORC_SUBROUND_SALT, 0, u) % S);
+}
+
+/* Size-constrained LP clustering, synchronous rounds, each split into S
+ * sub-rounds (S = 1: one synchronous step per round).
  * Start: every vertex in its own cluster (C[u] = u, Section IV-A).
- * Per round: every vertex computes its best move against the snapshot of
- * the previous round; then, for each target cluster, the proposals are taken
+ * Per sub-round s of round r: the vertices of sub-round s compute their best
+ * move against the snapshot taken at the start of the sub-round (tie-break
+ * keys of round r); then, for each target cluster, the proposals are taken
  * in (gain descending, vertex ascending) order and admitted while the
  * running sum of their weights, added to the cluster's weight at the start of
- * the round, stays within the cap; admitted vertices move. A round with no
- * proposal is a fixed point, so the loop stops there.
+ * the sub-round, stays within the cap; admitted vertices move. A later
+ * sub-round sees the moves of the earlier ones, as the paper's in-place
+ * updates let later vertices see earlier moves (Algorithms 1 and 2), but in
+ * a fixed order. A round with no proposal in any sub-round is a fixed point,
+ * so the loop stops there.
  * labels (out): n cluster IDs in [0, n); not renumbered. */
-int orc_lp_cluster(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
-                   const int32_t *vwgt, int64_t cap, int32_t rounds, uint64_t seed, int32_t *labels,
-                   orc_lp_stats *stats) {
-  if (n < 0 || cap < 1 || rounds < 0) return ORC_EINVAL;
+int orc_lp_cluster_sub(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
+                       const int32_t *vwgt, int64_t cap, int32_t rounds, int32_t subrounds, uint64_t seed,
+                       int32_t *labels, orc_lp_stats *stats) {
+  if (n < 0 || cap < 1 || rounds < 0 || subrounds < 1 || subrounds > 64) return ORC_EINVAL;
   if (stats) memset(stats, 0, sizeof(*stats));
   int32_t *C0 = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
   int64_t *W = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
@@ -335,68 +348,79 @@ int orc_lp_cluster(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const
     if (xadj[u + 1] - xadj[u] > maxdeg) maxdeg = xadj[u + 1] - xadj[u];
   }
   int status = ORC_OK;
+  const uint32_t S = (uint32_t)subrounds;
   for (int32_t r = 0; r < rounds; ++r) {
-    memcpy(C0, labels, (size_t)n * sizeof(int32_t));
-    memcpy(W0, W, (size_t)n * sizeof(int64_t));
-    int fail = 0;
+    int64_t round_props = 0;
+    for (uint32_t sr = 0; sr < S; ++sr) {
+      memcpy(C0, labels, (size_t)n * sizeof(int32_t));
+      memcpy(W0, W, (size_t)n * sizeof(int64_t));
+      int fail = 0;
 #pragma omp parallel
-    {
-      orc_rating *buf = (orc_rating *)malloc((maxdeg ? maxdeg : 1) * sizeof(orc_rating));
-      if (!buf) {
+      {
+        orc_rating *buf = (orc_rating *)malloc((maxdeg ? maxdeg : 1) * sizeof(orc_rating));
+        if (!buf) {
 #pragma omp atomic write
-        fail = 1;
-      }
-#pragma omp for schedule(dynamic, 256)
-      for (int32_t u = 0; u < n; ++u) {
-        ptarget[u] = -1;
-        if (buf && best_move(u, xadj, adjncy, adjwgt, vwgt, C0, W0, cap, seed, (uint32_t)r, buf,
-                             &ptarget[u], &pgain[u]) == 0)
-          ptarget[u] = -1;
-      }
-      free(buf);
-    }
-    if (fail) { status = ORC_ENOMEM; break; }
-    int64_t np = 0;
-    for (int32_t u = 0; u < n; ++u) {
-      if (ptarget[u] < 0) continue;
-      props[np].u = u;
-      props[np].target = ptarget[u];
-      props[np].gain = pgain[u];
-      props[np].w = vwgt ? vwgt[u] : 1;
-      ++np;
-    }
-    if (np == 0) break;
-    qsort(props, (size_t)np, sizeof(orc_prop), cmp_prop);
-    int64_t moves = 0;
-    for (int64_t i = 0; i < np;) {
-      int32_t c = props[i].target;
-      int64_t sum = 0;
-      int open = 1;
-      int64_t j = i;
-      for (; j < np && props[j].target == c; ++j) {
-        sum += props[j].w;
-        if (open && W0[c] + sum <= cap) {
-          labels[props[j].u] = c;
-          ++moves;
-        } else {
-          open = 0; /* longest admissible prefix: nothing after a rejection */
+          fail = 1;
         }
+#pragma omp for schedule(dynamic, 256)
+        for (int32_t u = 0; u < n; ++u) {
+          ptarget[u] = -1;
+          if (S > 1 && orc_subround((uint32_t)u, S) != sr) continue;
+          if (buf && best_move(u, xadj, adjncy, adjwgt, vwgt, C0, W0, cap, seed, (uint32_t)r, buf,
+                               &ptarget[u], &pgain[u]) == 0)
+            ptarget[u] = -1;
+        }
+        free(buf);
       }
-      i = j;
-    }
-    /* cluster weights from scratch: W[c] = sum of w(u) over members of c */
-    for (int32_t c = 0; c < n; ++c) W[c] = 0;
-    for (int32_t u = 0; u < n; ++u) W[labels[u]] += vwgt ? vwgt[u] : 1;
-    if (stats) {
-      stats->rounds_run = r + 1;
-      if (r < 64) {
-        stats->proposals[r] = np;
-        stats->moves[r] = moves;
+      if (fail) { status = ORC_ENOMEM; break; }
+      int64_t np = 0;
+      for (int32_t u = 0; u < n; ++u) {
+        if (ptarget[u] < 0) continue;
+        props[np].u = u;
+        props[np].target = ptarget[u];
+        props[np].gain = pgain[u];
+        props[np].w = vwgt ? vwgt[u] : 1;
+        ++np;
+      }
+      if (np == 0) continue; /* nothing moves in this sub-round */
+      round_props += np;
+      qsort(props, (size_t)np, sizeof(orc_prop), cmp_prop);
+      int64_t moves = 0;
+      for (int64_t i = 0; i < np;) {
+        int32_t c = props[i].target;
+        int64_t sum = 0;
+        int open = 1;
+        int64_t j = i;
+        for (; j < np && props[j].target == c; ++j) {
+          sum += props[j].w;
+          if (open && W0[c] + sum <= cap) {
+            labels[props[j].u] = c;
+            ++moves;
+          } else {
+            open = 0; /* longest admissible prefix: nothing after a rejection */
+          }
+        }
+        i = j;
+      }
+      /* cluster weights from scratch: W[c] = sum of w(u) over members of c */
+      for (int32_t c = 0; c < n; ++c) W[c] = 0;
+      for (int32_t u = 0; u < n; ++u) W[labels[u]] += vwgt ? vwgt[u] : 1;
+      if (stats && r < 64) {
+        stats->proposals[r] += np;
+        stats->moves[r] += moves;
       }
     }
+    if (status != ORC_OK || round_props == 0) break;
+    if (stats) stats->rounds_run = r + 1;
   }
   free(C0); free(W); free(W0); free(ptarget); free(pgain); free(props);
   return status;
+}
+
+int orc_lp_cluster(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
+                   const int32_t *vwgt, int64_t cap, int32_t rounds, uint64_t seed, int32_t *labels,
+                   orc_lp_stats *stats) {
+  return orc_lp_cluster_sub(n, xadj, adjncy, adjwgt, vwgt, cap, rounds, 1, seed, labels, stats);
 }
 
 /* One LP round from an arbitrary snapshot, for sampled checks: fills the

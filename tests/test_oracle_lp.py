@@ -184,3 +184,98 @@ def test_invariants_rmat(oracle_mod, synth_mod):
             assert tgt[i] == -1
         else:
             assert feas[tgt[i]] == max(feas.values()) and gain[i] == feas[tgt[i]] - own
+
+
+# ----------------------------------------------------------- sub-rounds ----
+# Each round is split into S sub-rounds; vertex u acts in sub-round sub(u),
+# a fixed mix of u (the tie-break function, pinned above, on a constant
+# salt), and every sub-round is one synchronous step over its vertices
+# against the state left by the sub-rounds before it.
+
+def test_subround_is_the_tiebreak_mix_of_a_fixed_salt(oracle_mod):
+    salt = 0x6A09E667F3BCC909
+    for S in (2, 3, 7, 64):
+        subs = [oracle_mod.subround(u, S) for u in range(4000)]
+        assert subs == [oracle_mod.tiebreak_key(salt, 0, u) % S for u in range(4000)]
+        counts = np.bincount(subs, minlength=S)
+        assert counts.min() > 0.7 * 4000 / S  # a balanced split
+
+
+def _subround_runs(oracle_mod, g, cap, rounds, seed, S):
+    """Labels after 0..rounds rounds by enumeration: every sub-round takes the
+    enumerated best moves of its own vertices under the current labels and
+    admits them per target like one synchronous round."""
+    w = bf.vweights(g)
+    C = np.arange(g.n, dtype=np.int64)
+    out = [C.copy()]
+    sub = np.array([oracle_mod.subround(u, S) for u in range(g.n)])
+    for r in range(rounds):
+        moved_any = False
+        for s in range(S):
+            tgt, gain = bf.expected_proposals(g, C, cap, seed, r, oracle_mod.tiebreak_key)
+            tgt = np.where(sub == s, tgt, -1)
+            if (tgt >= 0).any():
+                moved_any = True
+            W0 = bf.cluster_weights(g, C)
+            nxt = C.copy()
+            for c in sorted(set(int(t) for t in tgt if t >= 0)):
+                run = W0[c]
+                for _, u in sorted((-int(gain[u]), u) for u in range(g.n) if tgt[u] == c):
+                    run += w[u]
+                    if run > cap:
+                        break
+                    nxt[u] = c
+            C = nxt
+        out.append(C.copy())
+        if not moved_any:  # a fixed point: later rounds repeat it
+            out.extend(C.copy() for _ in range(rounds - r - 1))
+            break
+    return out
+
+
+@pytest.mark.parametrize("seed", range(10))
+@pytest.mark.parametrize("S", [2, 3])
+def test_subrounds_match_enumeration_small_random(oracle_mod, synth_mod, seed, S):
+    n = 6 + seed % 7
+    g = synth_mod.random_small(n, 0.45, seed)
+    if seed % 3 == 1:
+        g.adjwgt = synth_mod.edge_weights(g, 1, 5, seed)
+    if seed % 4 == 2:
+        g.vwgt = synth_mod.vertex_weights(n, 1, 3, seed)
+    cap = 2 + seed % 4
+    exp = _subround_runs(oracle_mod, g, cap, 4, seed, S)
+    for r in range(5):
+        lab, _ = oracle_mod.lp_cluster(g, cap, r, seed, subrounds=S)
+        assert np.array_equal(lab, exp[r]), (seed, S, r)
+        bf.check_valid_clustering(g, lab, cap)
+
+
+@pytest.mark.parametrize("rounds", [1, 2, 3])
+@pytest.mark.parametrize("S", [1, 2, 5])
+def test_perfect_matching_with_subrounds(oracle_mod, synth_mod, rounds, S):
+    # pair (a, b): in the same sub-round both move at once and swap every
+    # round (the synchronous pathology); in different sub-rounds the earlier
+    # one joins the other's cluster, the later one then stays, and the pair
+    # is merged under the label of its later member for good
+    k = 60
+    g = synth_mod.from_edges(2 * k, [(2 * i, 2 * i + 1) for i in range(k)])
+    lab, _ = oracle_mod.lp_cluster(g, 2, rounds, 3, subrounds=S)
+    exp = np.empty(2 * k, dtype=np.int64)
+    for i in range(k):
+        a, b = 2 * i, 2 * i + 1
+        sa, sb = oracle_mod.subround(a, S), oracle_mod.subround(b, S)
+        if S == 1 or sa == sb:
+            exp[a], exp[b] = (b, a) if rounds % 2 else (a, b)
+        else:
+            exp[a] = exp[b] = b if sa < sb else a
+    assert np.array_equal(lab, exp)
+    if S > 1:
+        merged = sum(oracle_mod.subround(2 * i, S) != oracle_mod.subround(2 * i + 1, S) for i in range(k))
+        assert merged > 0 and oracle_mod.edge_cut(g, lab) == k - merged
+
+
+def test_subround_argument_checks(oracle_mod, synth_mod):
+    g = synth_mod.from_edges(4, [(0, 1), (2, 3)])
+    for S in (0, 65):
+        with pytest.raises(ValueError):
+            oracle_mod.lp_cluster(g, 2, 1, 1, subrounds=S)
