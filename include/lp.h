@@ -135,20 +135,31 @@ lp_status lp_decompress(const lp_graph *g, uint64_t *xadj_dev, int32_t *adjncy_d
                         int32_t *adjwgt_dev, int32_t *vwgt_dev, void *stream);
 
 /*
- * Result-invariant tuning knobs of lp_cluster: degree-bucket thresholds.
- * Vertices of degree 1..t_lane are rated one per lane; up to t_tile in
- * edge-balanced tiles (one workgroup rates up to 2048 neighbours of up to
- * 128 vertices at once); up to t_block one vertex per workgroup (all with LDS
- * rating tables, Section IV-A2 first phase); higher-degree vertices go to
- * the chunk-parallel hub path (second phase). Any valid setting gives
- * identical labels. Zero fields mean "default".
+ * Options of lp_cluster_ex. The first four are result-invariant tuning
+ * knobs, the degree-bucket thresholds: vertices of degree 1..t_lane are
+ * rated one per lane; up to t_tile in edge-balanced tiles (one workgroup
+ * rates up to 2048 neighbours of up to 80 vertices at once); up to t_block in
+ * tiles of up to 4096 neighbours of up to 4 vertices (all with LDS rating
+ * tables, Section IV-A2 first phase); higher-degree vertices go to the
+ * chunk-parallel hub path (second phase). Any valid setting gives identical
+ * labels. `subrounds` changes the method: with S > 1 every round is split
+ * into S sub-rounds, vertex u (its ID inside its graph) acting in sub-round
+ * sub(u) = SplitMix64 output of (0x6A09E667F3BCC909 xor u), the mix of the
+ * tie-break keys, modulo S; each sub-round is one synchronous step (rating
+ * with the round's tie-break keys, acceptance, moves) over its vertices
+ * against the labels and weights the earlier sub-rounds left, so that
+ * neighbours in different sub-rounds no longer move at once (a pair of
+ * vertices then merges instead of swapping every round). A round without a
+ * proposal in any sub-round ends the call; statistics sum over the
+ * sub-rounds of a round. Zero fields mean "default".
  */
 typedef struct {
-  int32_t t_lane;   /* 0..16, default 16 */
-  int32_t t_tile;   /* t_lane..2048, default 2048 */
-  int32_t t_block;  /* t_tile..4096, default 4096 */
-  int32_t hub_part; /* target edges per hub partition, 256..8192, default 2048 */
-  int32_t timing;   /* nonzero: time each phase with HIP events (stats must be given) */
+  int32_t t_lane;    /* 0..16, default 16 */
+  int32_t t_tile;    /* t_lane..2048, default 2048 */
+  int32_t t_block;   /* t_tile..4096, default 4096 */
+  int32_t hub_part;  /* target edges per hub partition, 256..8192, default 2048 */
+  int32_t timing;    /* nonzero: time each phase with HIP events (stats must be given) */
+  int32_t subrounds; /* sub-rounds per round, 1..64, default 1 (plain synchronous rounds) */
 } lp_config;
 
 /* Phases timed when lp_config.timing is set (milliseconds summed over rounds). */

@@ -41,7 +41,8 @@ PHASES = ("setup", "lane", "tile", "block", "hub", "accept", "round")
 
 class lp_config(ctypes.Structure):
     _fields_ = [("t_lane", ctypes.c_int32), ("t_tile", ctypes.c_int32),
-                ("t_block", ctypes.c_int32), ("hub_part", ctypes.c_int32), ("timing", ctypes.c_int32)]
+                ("t_block", ctypes.c_int32), ("hub_part", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("subrounds", ctypes.c_int32)]
 
 
 class lp_cluster_stats(ctypes.Structure):
@@ -360,17 +361,19 @@ def coarsen_params(n0: int, total_weight: int):
     return n_target, cap
 
 
-def coarsen(g: Graph, seed: int = 1, rounds: int = 5, max_levels: int = 32, stream=None):
+def coarsen(g: Graph, seed: int = 1, rounds: int = 5, max_levels: int = 32, stream=None, subrounds: int = 1):
     """Repeated lp_cluster + lp_contract (all on the device; the host reads n' only).
     Stops at n' <= n_target, when a level shrinks by less than 5 %, or after
-    max_levels levels. Level l clusters with seed + l. Returns
+    max_levels levels. Level l clusters with seed + l (and `subrounds`
+    sub-rounds per round). Returns
     (levels: list of (Graph, labels, map), final Graph, n_target, cap)."""
     n_target, cap = coarsen_params(g.n, g.total_vwgt)
     levels = []
     cur = g
     lvl = 0
+    cfg = dict(subrounds=subrounds) if subrounds > 1 else None
     while lvl < max_levels and cur.n > n_target:
-        labels = lp_cluster(cur, cap, rounds, seed + lvl, stream=stream)
+        labels = lp_cluster(cur, cap, rounds, seed + lvl, stream=stream, config=cfg)
         nxt, mp = lp_contract(cur, labels, stream=stream)
         levels.append((cur, labels, mp))
         prev_n = cur.n

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <memory>
 #include <atomic>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -793,7 +794,8 @@ constexpr int kPieceThreads = 512;
 constexpr int kPieceItems = (kHubPiece + kPieceThreads - 1) / kPieceThreads;
 constexpr int kPieceSlots = kHubPiece + kHubPiece / 2 + 16;
 constexpr int kMaxParts = 1024;
-constexpr int kDefaultHubPart = 2048;  // target partial records per (hub, partition) task
+constexpr int kDefaultHubPart = 2048;
+constexpr int kMaxSubrounds = 64;  // target partial records per (hub, partition) task
 constexpr uint32_t kStreamZig = 0x80000000u;  // first code is zigzag(v - base_v)
 
 // One code stream of a piece: a chunk of a split record, or a run of an
@@ -1364,6 +1366,23 @@ __device__ __forceinline__ int bucket_of(int32_t d, int32_t t_lane, int32_t t_ti
   return 3;
 }
 
+// Sub-round of a vertex among S: the tie-break mix on a fixed salt and the
+// vertex's ID inside its graph, modulo S (fixed for a whole call).
+constexpr uint64_t kSubroundSalt = 0x6A09E667F3BCC909ull;
+__device__ __forceinline__ uint32_t subround_of(uint32_t u_local, uint32_t S) {
+  return (uint32_t)(tiebreak_key(kSubroundSalt, 0, u_local) % S);
+}
+
+// Degrees as seen by the plan of sub-round `sr`: vertices of other
+// sub-rounds get degree 0 and so fall in no bucket.
+__global__ void k_subround_deg(const int32_t* deg, int32_t n, uint32_t S, uint32_t sr, const int32_t* gid,
+                               const int32_t* gbase, int32_t* out) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t loc = gid ? (uint32_t)(u - gbase[gid[u]]) : (uint32_t)u;
+    out[u] = subround_of(loc, S) == sr ? deg[u] : 0;
+  }
+}
+
 // Descriptor of every listed (non-hub) vertex: degree and the position of its
 // first code (compressed: after the first-edge header; these degrees are
 // never chunked) or first edge (plain).
@@ -1471,8 +1490,8 @@ __global__ __launch_bounds__(kCpThreads) void k_prop_count(const int32_t* ptgt, 
 }
 
 // Writes the proposals in increasing vertex order: key = target << G |
-// (2^G - 1 - gain), value = vertex.
-__global__ __launch_bounds__(kCpThreads) void k_prop_write(const int32_t* ptgt, const int64_t* pgain, int32_t n,
+// (2^G - 1 - gain), value = vertex; clears the proposal slots it took.
+__global__ __launch_bounds__(kCpThreads) void k_prop_write(int32_t* ptgt, const int64_t* pgain, int32_t n,
                                                            const uint32_t* boff, int G, uint64_t* keys,
                                                            uint32_t* vals, const uint32_t* done) {
   __shared__ uint32_t sm[kCpThreads / kWave];
@@ -1495,6 +1514,7 @@ __global__ __launch_bounds__(kCpThreads) void k_prop_write(const int32_t* ptgt, 
         keys[o] = ((uint64_t)(uint32_t)t << G) | (dmax - (uint64_t)pgain[u]);
         vals[o] = (uint32_t)u;
         ++o;
+        ptgt[u] = -1;  // taken: a later sub-round rates other vertices only
       }
     }
   }
@@ -1544,12 +1564,18 @@ __global__ __launch_bounds__(256) void k_apply(const uint32_t* seg, const uint32
     atomicAdd((unsigned long long*)&stats[64 + round], (unsigned long long)moves);
 }
 
-__global__ void k_round_end(const uint32_t* count, uint32_t* done, int64_t* stats, int round, int32_t* rounds_run) {
+// End of a sub-round: its proposals count towards the round; after the
+// round's last sub-round, a round without any proposal ends the call.
+__global__ void k_round_end(const uint32_t* count, uint32_t* done, int64_t* stats, int round, int32_t* rounds_run,
+                            unsigned long long* round_props, int last) {
   if (*done) return;
   const uint32_t c = *count;
-  if (round < 64) stats[round] = c;
-  if (c == 0) *done = 1;
+  if (round < 64) stats[round] += c;
+  *round_props += c;
+  if (!last) return;
+  if (*round_props == 0) *done = 1;
   else *rounds_run = round + 1;
+  *round_props = 0;
 }
 
 __global__ void k_gather_i32(const int32_t* src, const int32_t* idx, int32_t cnt, int32_t* out) {
@@ -1739,6 +1765,10 @@ namespace {
 // handle; other thresholds get a plan of their own for one call.
 struct Plan {
   int32_t t_lane = 0, t_tile = 0, t_block = 0, hub_part = 0;
+  int32_t sub_S = 1, sub_r = 0;  // the vertices of sub-round sub_r of sub_S (all when sub_S == 1)
+  // plans of the sub-rounds, per sub-round count (kept by a cached plan; entries are never removed, so
+  // pointers handed out stay valid while the handle lives)
+  std::map<int32_t, std::vector<std::unique_ptr<Plan>>> subs;
   bool wide = false;
   int32_t bn[kNumBuckets] = {};
   uint32_t bstart[kNumBuckets + 1] = {};
@@ -1756,8 +1786,10 @@ struct Plan {
 };
 
 lp_status build_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t t_block, int32_t hub_part,
-                     hipStream_t s, Plan& P) {
+                     hipStream_t s, Plan& P, int32_t sub_S = 1, int32_t sub_r = 0) {
   const int32_t n = g->n;
+  P.sub_S = sub_S;
+  P.sub_r = sub_r;
   P.t_lane = t_lane;
   P.t_tile = t_tile;
   P.t_block = t_block;
@@ -1768,8 +1800,8 @@ lp_status build_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t 
   P.mem.alloc_stream = s;
   P.mem.free_stream = g->mem_stream;
   Scratch sc(s);
-  int32_t* deg = P.mem.alloc<int32_t>(n);
-  P.deg = deg;
+  int32_t* deg = sub_S > 1 ? sc.alloc<int32_t>(n) : P.mem.alloc<int32_t>(n);
+  if (sub_S == 1) P.deg = deg;
   const unsigned nbk = grid_for(n, kBkTile, 0x7FFFFFFF);
   uint32_t* bcnt = sc.alloc<uint32_t>((size_t)kNumBuckets * nbk);
   uint32_t* btot = sc.alloc<uint32_t>(1);
@@ -1778,6 +1810,14 @@ lp_status build_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t 
   if (sc.failed || P.mem.failed) return LP_ENOMEM;
   LP_CHECK_HIP(hipMemsetAsync(bsums, 0, 2 * kNumBuckets * sizeof(unsigned long long), s));
   LP_CHECK(compute_degrees(g, deg, s));
+  if (sub_S > 1) {  // bucket only this sub-round's vertices; P.deg keeps every degree
+    int32_t* dsub = sc.alloc<int32_t>(n);
+    if (!dsub) return LP_ENOMEM;
+    hipLaunchKernelGGL(k_subround_deg, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, deg, n, (uint32_t)sub_S,
+                       (uint32_t)sub_r, batch ? g->gid : nullptr, batch ? g->gbase : nullptr, dsub);
+    LP_CHECK_LAUNCH();
+    deg = dsub;
+  }
   hipLaunchKernelGGL(k_bucket_count, dim3(nbk), dim3(kBkThreads), 0, s, deg, n, t_lane, t_tile, t_block, bcnt, nbk);
   LP_CHECK_LAUNCH();
   LP_CHECK(scan_exclusive_u32(bcnt, bcnt, (int64_t)kNumBuckets * nbk, btot, sc));
@@ -1982,6 +2022,36 @@ lp_status get_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t t_
 lp_status batch_localize(const lp_graph* b, const int32_t* lab, int32_t* out, int32_t* const* outs_dev,
                          hipStream_t s);
 
+// The plans of a call with S sub-rounds: the plan itself for S == 1, else
+// one plan per sub-round over that sub-round's vertices (kept with the
+// handle's cached plan for the default thresholds, owned by `tmp` otherwise).
+lp_status get_plans(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t t_block, int32_t hub_part, int32_t S,
+                    hipStream_t s, std::vector<const Plan*>& out, std::unique_ptr<Plan>& tmp) {
+  out.clear();
+  const Plan* base = nullptr;
+  LP_CHECK(get_plan(g, t_lane, t_tile, t_block, hub_part, s, &base, tmp));
+  if (S == 1) {
+    out.push_back(base);
+    return LP_OK;
+  }
+  Plan* owner = const_cast<Plan*>(base);  // sub-plans only ever get added
+  std::unique_lock<std::mutex> lock(g->plan_mu, std::defer_lock);
+  if (!tmp) lock.lock();  // the handle's cached plan is shared
+  auto& v = owner->subs[S];
+  if (v.empty()) {
+    std::vector<std::unique_ptr<Plan>> built;
+    for (int32_t r = 0; r < S; ++r) {
+      std::unique_ptr<Plan> p(new Plan());
+      LP_CHECK(build_plan(g, t_lane, t_tile, t_block, hub_part, s, *p, S, r));
+      if (tmp) p->mem.free_stream = s;  // used by this call only
+      built.push_back(std::move(p));
+    }
+    v = std::move(built);
+  }
+  for (auto& p : v) out.push_back(p.get());
+  return LP_OK;
+}
+
 lp_status plan_degrees(const lp_graph* g, const int32_t** deg, hipStream_t s) {
   const Plan* plan = nullptr;
   std::unique_ptr<Plan> tmp;
@@ -2024,14 +2094,16 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
   // knobs (results do not depend on them)
   const bool wide = g->max_wdeg > 0x7FFFFFFFll;
   int32_t t_lane = 16, t_tile = kTileMaxDeg, t_block = TileLarge::kEdges, hub_part = kDefaultHubPart;
+  int32_t S = 1;  // sub-rounds per round (this one changes the result)
   if (cfg_in) {
     if (cfg_in->t_lane) t_lane = cfg_in->t_lane;
     if (cfg_in->t_tile) t_tile = cfg_in->t_tile;
     if (cfg_in->t_block) t_block = cfg_in->t_block;
     if (cfg_in->hub_part) hub_part = cfg_in->hub_part;
+    if (cfg_in->subrounds) S = cfg_in->subrounds;
   }
   if (t_lane < 0 || t_lane > kMaxLane || t_tile < t_lane || t_tile > kTileMaxDeg || t_block < t_tile ||
-      t_block > TileLarge::kEdges || hub_part < 256 || hub_part > 8192)
+      t_block > TileLarge::kEdges || hub_part < 256 || hub_part > 8192 || S < 1 || S > kMaxSubrounds)
     return LP_EINVAL;
   // proposal sort key: target bits + gain bits
   const int G = std::max(1, bitlen((uint64_t)g->max_wdeg));
@@ -2056,21 +2128,22 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
   uint8_t* flag = sc.alloc<uint8_t>(n);
   const unsigned ncp = grid_for(n, kCpTile, 0x7FFFFFFF);
   uint32_t* pcnt = sc.alloc<uint32_t>(ncp);
-  // per round: hand-out counters of the small tiles, large tiles and pieces
-  uint32_t* hand = sc.alloc<uint32_t>((size_t)std::max(rounds, 1) * 24);
+  // per sub-round: hand-out counters of the small tiles, large tiles and pieces
+  const int64_t nhand = (int64_t)std::max(rounds, 1) * S * 24;
+  uint32_t* hand = sc.alloc<uint32_t>(nhand);
   struct Ctl {
     uint32_t done;
     uint32_t count;
     int32_t rounds_run;
     uint32_t pad;
     uint32_t bucket_tot[4];
+    unsigned long long round_props;
     int64_t stats[128];
   };
   Ctl* ctl = sc.alloc<Ctl>(1);
   if (sc.failed) return LP_ENOMEM;
   LP_CHECK_HIP(hipMemsetAsync(ctl, 0, sizeof(Ctl), s));
-  hipLaunchKernelGGL(k_zero_u32, dim3(grid_for((int64_t)std::max(rounds, 1) * 24, 256, 64)), dim3(256), 0, s, hand,
-                     std::max(rounds, 1) * 24);
+  hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(nhand, 256, 64)), dim3(256), 0, s, hand, (int32_t)nhand);
   LP_CHECK_LAUNCH();
   if (batch) {
     LP_CHECK_HIP(hipMemcpyAsync(gcap, caps, g->nbatch * sizeof(int64_t), hipMemcpyHostToDevice, s));
@@ -2122,23 +2195,26 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
   for (int i = 0; i < 4; ++i) LP_CHECK_HIP(hipEventCreateWithFlags(&ev.e[i], hipEventDisableTiming));
 
   LP_CHECK(begin(LP_PHASE_SETUP));
-  const Plan* plan = nullptr;
+  std::vector<const Plan*> plans;  // one per sub-round
   std::unique_ptr<Plan> plan_tmp;
-  LP_CHECK(get_plan(g, t_lane, t_tile, t_block, hub_part, s, &plan, plan_tmp));
-  const int32_t* bn = plan->bn;
-  auto vd_of = [&](int b) { return plan->vd(b); };
-  const TilePlan& tps = plan->tps;
-  const TilePlan& tpl = plan->tpl;
-  const int32_t H = plan->H, npieces = plan->npieces, ntasks = plan->ntasks;
-  HubMeta hm = plan->hm;
-  if (H > 0) {  // per-call hub buffers
-    hm.rec_c = sc.alloc<int32_t>(plan->rsum);
-    hm.rec_r = wide ? (void*)sc.alloc<int64_t>(plan->rsum) : (void*)sc.alloc<int32_t>(plan->rsum);
-    hm.poff = sc.alloc<uint32_t>(plan->psum);
-    hm.res_r = sc.alloc<int64_t>(ntasks);
-    hm.res_key = sc.alloc<uint64_t>(ntasks);
-    hm.res_c = sc.alloc<int32_t>(ntasks);
-    hm.res_own = sc.alloc<int64_t>(ntasks);
+  LP_CHECK(get_plans(g, t_lane, t_tile, t_block, hub_part, S, s, plans, plan_tmp));
+  uint64_t rsum = 0, psum = 0;
+  int32_t tmax = 0, hmax = 0;
+  for (const Plan* p : plans) {
+    rsum = std::max(rsum, p->rsum);
+    psum = std::max(psum, p->psum);
+    tmax = std::max(tmax, p->ntasks);
+    hmax = std::max(hmax, p->H);
+  }
+  HubMeta hbuf{};  // per-call hub buffers, shared by the sub-rounds
+  if (hmax > 0) {
+    hbuf.rec_c = sc.alloc<int32_t>(rsum);
+    hbuf.rec_r = wide ? (void*)sc.alloc<int64_t>(rsum) : (void*)sc.alloc<int32_t>(rsum);
+    hbuf.poff = sc.alloc<uint32_t>(psum);
+    hbuf.res_r = sc.alloc<int64_t>(tmax);
+    hbuf.res_key = sc.alloc<uint64_t>(tmax);
+    hbuf.res_c = sc.alloc<int32_t>(tmax);
+    hbuf.res_own = sc.alloc<int64_t>(tmax);
     if (sc.failed) return LP_ENOMEM;
   }
 
@@ -2162,7 +2238,7 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
   const TileLayout piece_layout = wide ? piece_layout_of<int64_t>(g->compressed, g->weighted)
                                       : piece_layout_of<int32_t>(g->compressed, g->weighted);
   const size_t piece_lds = (size_t)piece_layout.abytes + sizeof(PieceShared);
-  if (H > 0) {
+  if (hmax > 0) {
     if (wide) LP_CHECK(set_lds(k_hub_reduce<int64_t>, (size_t)kHubTable * 12 + sizeof(HubReduceSmem)));
     else LP_CHECK(set_lds(k_hub_reduce<int32_t>, (size_t)kHubTable * 8 + sizeof(HubReduceSmem)));
   }
@@ -2171,80 +2247,98 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
     x.round = (uint32_t)r;
     const size_t round_mark = marks.size();
     LP_CHECK(begin(LP_PHASE_ROUND));
-    // rating (all buckets) -> ptgt / pgain. The hub pieces run first, alone:
-    // they are the head of the longest chain (pieces, then their reduction),
-    // which then overlaps with the tiles and lanes on the side streams.
-    if (H > 0) {
-      LP_CHECK(begin(LP_PHASE_HUB));
-      LP_CHECK(launch_piece(g->compressed, wide, x, hm, npieces, hand + 24 * r + 16, piece_layout, piece_lds, s));
-    }
-    LP_CHECK_HIP(hipEventRecord(ev.e[3], s));
-    for (int i = 0; i < 3; ++i) LP_CHECK_HIP(hipStreamWaitEvent(side[i], ev.e[3], 0));
-    if (H > 0) {
-      hipStream_t hs = side[0];
-      if (wide)
-        hipLaunchKernelGGL(k_hub_reduce<int64_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads),
-                           (size_t)kHubTable * 12 + sizeof(HubReduceSmem), hs, x, hm, ntasks);
-      else
-        hipLaunchKernelGGL(k_hub_reduce<int32_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads),
-                           (size_t)kHubTable * 8 + sizeof(HubReduceSmem), hs, x, hm, ntasks);
+    for (int32_t sr = 0; sr < S; ++sr) {
+      const Plan* plan = plans[sr];
+      const int32_t* bn = plan->bn;
+      auto vd_of = [&](int b) { return plan->vd(b); };
+      const TilePlan& tps = plan->tps;
+      const TilePlan& tpl = plan->tpl;
+      const int32_t H = plan->H, npieces = plan->npieces, ntasks = plan->ntasks;
+      HubMeta hm = plan->hm;
+      hm.rec_c = hbuf.rec_c;
+      hm.rec_r = hbuf.rec_r;
+      hm.poff = hbuf.poff;
+      hm.res_r = hbuf.res_r;
+      hm.res_key = hbuf.res_key;
+      hm.res_c = hbuf.res_c;
+      hm.res_own = hbuf.res_own;
+      uint32_t* hand_r = hand + 24 * ((int64_t)r * S + sr);
+      // rating (all buckets) -> ptgt / pgain. The hub pieces run first, alone:
+      // they are the head of the longest chain (pieces, then their reduction),
+      // which then overlaps with the tiles and lanes on the side streams.
+      if (H > 0) {
+        LP_CHECK(begin(LP_PHASE_HUB));
+        LP_CHECK(launch_piece(g->compressed, wide, x, hm, npieces, hand_r + 16, piece_layout, piece_lds, s));
+      }
+      LP_CHECK_HIP(hipEventRecord(ev.e[3], s));
+      for (int i = 0; i < 3; ++i) LP_CHECK_HIP(hipStreamWaitEvent(side[i], ev.e[3], 0));
+      if (H > 0) {
+        hipStream_t hs = side[0];
+        if (wide)
+          hipLaunchKernelGGL(k_hub_reduce<int64_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads),
+                             (size_t)kHubTable * 12 + sizeof(HubReduceSmem), hs, x, hm, ntasks);
+        else
+          hipLaunchKernelGGL(k_hub_reduce<int32_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads),
+                             (size_t)kHubTable * 8 + sizeof(HubReduceSmem), hs, x, hm, ntasks);
+        LP_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_hub_combine, dim3(grid_for(H, 4)), dim3(256), 0, hs, x, hm, H);
+        LP_CHECK_LAUNCH();
+        LP_CHECK(end(hs));
+      }
+      if (bn[2] > 0) {
+        LP_CHECK(begin(LP_PHASE_BLOCK, side[1]));
+        LP_CHECK(launch_tile_any<TileLarge>(g->compressed, rate_width(g), x, vd_of(2), tpl.tiles, tpl.ntiles,
+                                            hand_r + 8, tpl.grid,
+                                            g->weighted, side[1]));
+        LP_CHECK(end(side[1]));
+      }
+      if (bn[0] > 0) {
+        LP_CHECK(begin(LP_PHASE_LANE, side[2]));
+        if (g->compressed)
+          hipLaunchKernelGGL(k_rate_lane<true>, dim3(grid_for(bn[0], 256)), dim3(256), 0, side[2], x, vd_of(0),
+                             bn[0]);
+        else
+          hipLaunchKernelGGL(k_rate_lane<false>, dim3(grid_for(bn[0], 256)), dim3(256), 0, side[2], x, vd_of(0),
+                             bn[0]);
+        LP_CHECK_LAUNCH();
+        LP_CHECK(end(side[2]));
+      }
+      if (bn[1] > 0) {
+        LP_CHECK(begin(LP_PHASE_TILE));
+        LP_CHECK(launch_tile_any<TileSmall>(g->compressed, rate_width(g), x, vd_of(1), tps.tiles, tps.ntiles,
+                                            hand_r, tps.grid,
+                                            g->weighted, s));
+        LP_CHECK(end());
+      }
+      // join
+      for (int i = 0; i < 3; ++i) {
+        LP_CHECK_HIP(hipEventRecord(ev.e[i], side[i]));
+        LP_CHECK_HIP(hipStreamWaitEvent(s, ev.e[i], 0));
+      }
+      // acceptance: compact in vertex order, sort by (target, gain desc)
+      LP_CHECK(begin(LP_PHASE_ACCEPT));
+      hipLaunchKernelGGL(k_prop_count, dim3(ncp), dim3(kCpThreads), 0, s, ptgt, n, pcnt, &ctl->done);
       LP_CHECK_LAUNCH();
-      hipLaunchKernelGGL(k_hub_combine, dim3(grid_for(H, 4)), dim3(256), 0, hs, x, hm, H);
+      LP_CHECK(scan_exclusive_u32(pcnt, pcnt, ncp, &ctl->count, sc));
+      hipLaunchKernelGGL(k_prop_write, dim3(ncp), dim3(kCpThreads), 0, s, ptgt, pgain, n, pcnt, G, ka, va, &ctl->done);
       LP_CHECK_LAUNCH();
-      LP_CHECK(end(hs));
-    }
-    if (bn[2] > 0) {
-      LP_CHECK(begin(LP_PHASE_BLOCK, side[1]));
-      LP_CHECK(launch_tile_any<TileLarge>(g->compressed, rate_width(g), x, vd_of(2), tpl.tiles, tpl.ntiles,
-                                          hand + 24 * r + 8, tpl.grid,
-                                          g->weighted, side[1]));
-      LP_CHECK(end(side[1]));
-    }
-    if (bn[0] > 0) {
-      LP_CHECK(begin(LP_PHASE_LANE, side[2]));
-      if (g->compressed)
-        hipLaunchKernelGGL(k_rate_lane<true>, dim3(grid_for(bn[0], 256)), dim3(256), 0, side[2], x, vd_of(0),
-                           bn[0]);
-      else
-        hipLaunchKernelGGL(k_rate_lane<false>, dim3(grid_for(bn[0], 256)), dim3(256), 0, side[2], x, vd_of(0),
-                           bn[0]);
+      uint64_t* ks;
+      uint32_t* vs;
+      LP_CHECK(radix_sort_pairs(ka, va, kb, vb, &ctl->count, n, G + nbits, &ks, &vs, sc));
+      const unsigned ga = grid_for(n, 256, 8192);
+      hipLaunchKernelGGL(k_admit_prep, dim3(ga), dim3(256), 0, s, ks, vs, &ctl->count, G, g->vwgt, seg, wv);
       LP_CHECK_LAUNCH();
-      LP_CHECK(end(side[2]));
-    }
-    if (bn[1] > 0) {
-      LP_CHECK(begin(LP_PHASE_TILE));
-      LP_CHECK(launch_tile_any<TileSmall>(g->compressed, rate_width(g), x, vd_of(1), tps.tiles, tps.ntiles,
-                                          hand + 24 * r, tps.grid,
-                                          g->weighted, s));
+      LP_CHECK(seg_scan_incl_i64(seg, wv, pref, &ctl->count, n, sc));
+      hipLaunchKernelGGL(k_admit, dim3(ga), dim3(256), 0, s, seg, pref, &ctl->count, W, cap, x.gid, gcap, flag);
+      LP_CHECK_LAUNCH();
+      hipLaunchKernelGGL(k_apply, dim3(ga), dim3(256), 0, s, seg, vs, flag, wv, pref, &ctl->count, labels, W,
+                         ctl->stats, r);
+      LP_CHECK_LAUNCH();
+      hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, s, &ctl->count, &ctl->done, ctl->stats, r, &ctl->rounds_run,
+                         &ctl->round_props, sr == S - 1 ? 1 : 0);
+      LP_CHECK_LAUNCH();
       LP_CHECK(end());
     }
-    // join
-    for (int i = 0; i < 3; ++i) {
-      LP_CHECK_HIP(hipEventRecord(ev.e[i], side[i]));
-      LP_CHECK_HIP(hipStreamWaitEvent(s, ev.e[i], 0));
-    }
-    // acceptance: compact in vertex order, sort by (target, gain desc)
-    LP_CHECK(begin(LP_PHASE_ACCEPT));
-    hipLaunchKernelGGL(k_prop_count, dim3(ncp), dim3(kCpThreads), 0, s, ptgt, n, pcnt, &ctl->done);
-    LP_CHECK_LAUNCH();
-    LP_CHECK(scan_exclusive_u32(pcnt, pcnt, ncp, &ctl->count, sc));
-    hipLaunchKernelGGL(k_prop_write, dim3(ncp), dim3(kCpThreads), 0, s, ptgt, pgain, n, pcnt, G, ka, va, &ctl->done);
-    LP_CHECK_LAUNCH();
-    uint64_t* ks;
-    uint32_t* vs;
-    LP_CHECK(radix_sort_pairs(ka, va, kb, vb, &ctl->count, n, G + nbits, &ks, &vs, sc));
-    const unsigned ga = grid_for(n, 256, 8192);
-    hipLaunchKernelGGL(k_admit_prep, dim3(ga), dim3(256), 0, s, ks, vs, &ctl->count, G, g->vwgt, seg, wv);
-    LP_CHECK_LAUNCH();
-    LP_CHECK(seg_scan_incl_i64(seg, wv, pref, &ctl->count, n, sc));
-    hipLaunchKernelGGL(k_admit, dim3(ga), dim3(256), 0, s, seg, pref, &ctl->count, W, cap, x.gid, gcap, flag);
-    LP_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_apply, dim3(ga), dim3(256), 0, s, seg, vs, flag, wv, pref, &ctl->count, labels, W, ctl->stats,
-                       r);
-    LP_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, s, &ctl->count, &ctl->done, ctl->stats, r, &ctl->rounds_run);
-    LP_CHECK_LAUNCH();
-    LP_CHECK(end());
     if (timing) LP_CHECK_HIP(hipEventRecord(marks[round_mark].b, s));
   }
   if (batch) LP_CHECK(batch_localize(g, labels, out_labels, labels_each, s));
@@ -2253,17 +2347,19 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
     LP_CHECK_HIP(hipMemcpyAsync(&h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     LP_CHECK_HIP(hipStreamSynchronize(s));
     stats_out->rounds_run = h.rounds_run;
-    stats_out->n_lane = bn[0];
-    stats_out->n_tile = bn[1];
-    stats_out->n_block = bn[2];
-    stats_out->n_hub = bn[3];
+    for (const Plan* p : plans) {
+      stats_out->n_lane += p->bn[0];
+      stats_out->n_tile += p->bn[1];
+      stats_out->n_block += p->bn[2];
+      stats_out->n_hub += p->bn[3];
+      for (int b = 0; b < kNumBuckets; ++b) {
+        stats_out->bucket_edges[b] += p->bsums[b];
+        stats_out->bucket_bytes[b] += p->bsums[kNumBuckets + b];
+      }
+    }
     for (int i = 0; i < 64; ++i) {
       stats_out->proposals[i] = h.stats[i];
       stats_out->moves[i] = h.stats[64 + i];
-    }
-    for (int b = 0; b < kNumBuckets; ++b) {
-      stats_out->bucket_edges[b] = plan->bsums[b];
-      stats_out->bucket_bytes[b] = plan->bsums[kNumBuckets + b];
     }
     for (auto& m : marks) {
       float ms = 0;
