@@ -263,6 +263,50 @@ def level_checks(lp, cur, labels, nxt, cap, total_vwgt, sample: int = 256) -> di
             "edge_weight_is_2cut": ok_cut, "symmetric_sample": ok_sym, "cut": cut}
 
 
+def bench_subrounds(args, G=None) -> dict:
+    """Sub-round LP (S sub-rounds per round) against plain synchronous rounds on
+    the R-MAT scale 24 graph: one clustering level (round time, moves, cut) and
+    the whole coarsening (levels, final size, and the cut of the composed
+    clustering, i.e. half the edge weight left in the coarsest graph)."""
+    import torch
+
+    import paper_2410_19119_amd as lp
+    import synth
+
+    if G is None:
+        g = synth.rmat_scale(24, 16, seed=1)
+        G = lp.lp_compress(g.n, g.xadj.view(np.int64), g.adjncy)
+        del g
+    out = {}
+    for S in [int(x) for x in args.subrounds.split(",")]:
+        cfg = dict(timing=1, subrounds=S)
+        lp.lp_cluster(G, 256, args.rounds, 1, config=cfg)  # builds and caches the sub-round plans
+        torch.cuda.synchronize()
+        lab, st = lp.lp_cluster(G, 256, args.rounds, 1, config=cfg, stats=True)
+        cut = lp.lp_edge_cut(G, lab)
+        C, _ = lp.lp_contract(G, lab, want_map=False)
+        level = {"round_ms": round(st.phase_ms["round"] / max(1, st.phase_launches["round"]), 3),
+                 "moves": int(sum(st.moves)), "cut": int(cut), "coarse_n": C.n}
+        C.free()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        levels, final, n_target, _ = lp.coarsen(G, seed=1, rounds=args.rounds, subrounds=S)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        _, _, w, _ = lp.lp_decompress(final) if not final.compressed else (None, None, None, None)
+        left = int(w.to(torch.int64).sum()) // 2 if w is not None else None
+        out[str(S)] = {"one_level": level, "coarsening": {"levels": len(levels), "final_n": final.n,
+                                                            "cut_of_hierarchy": left, "ms": round(1e3 * dt, 1)}}
+        for lv in levels[1:]:
+            lv[0].free()
+        if final is not G:
+            final.free()
+        log(f"[subrounds] S={S}: round {level['round_ms']} ms, cut {cut}, coarse n {level['coarse_n']} | "
+            f"coarsening {len(levels)} levels to n={out[str(S)]['coarsening']['final_n']}, cut {left}, "
+            f"{1e3 * dt:.0f} ms")
+    return out
+
+
 def bench_coarsen(args) -> dict:
     """Full coarsening of one large graph (cluster + contract until 2^14)."""
     import torch
@@ -344,6 +388,7 @@ def main() -> int:
                     help="comma-separated request rates (default: 10..1000 for --workload serve, "
                          "100,1000 inside the default run)")
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--subrounds", default="1,2,4", help="sub-round counts compared by the subrounds form")
     ap.add_argument("--serve-split", type=int, default=0,
                     help="directed edges from which a job runs in the big-job lane (0: one lane)")
     ap.add_argument("--coarsen-graph", default="rmat", choices=["rmat", "rgg3d"])
@@ -384,6 +429,13 @@ def main() -> int:
                           "value": lv0.get("lp_round_edges_per_s"), "unit": "edges/s", "n_gpus": 1,
                           "higher_is_better": True, "data": "synthetic", "dtype": "int32",
                           "config": {"workload": res["workload"]}, "coarsening": res}))
+        return 0
+    if args.workload == "subrounds":
+        res = bench_subrounds(args)
+        print(json.dumps({"metric": "cut of the coarsening hierarchy and LP round time, by sub-rounds per round",
+                          "value": res[max(res, key=int)]["coarsening"]["cut_of_hierarchy"], "unit": "edges",
+                          "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "int32",
+                          "config": {"workload": "rmat-s24-ef16, cap 256, 5 rounds"}, "subrounds": res}))
         return 0
     if args.workload == "serve":
         res = bench_serve(args)
@@ -499,6 +551,7 @@ def main() -> int:
         if args.serve_rates is None:
             args.serve_rates = "100,1000"
         forms["served"] = bench_serve(args)["rates"]
+        forms["subrounds"] = bench_subrounds(args, G)
 
     out = {
         "metric": "LP-round edges/s",
