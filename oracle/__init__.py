@@ -71,6 +71,8 @@ def _load():
                                    ctypes.c_uint64, _P, ctypes.POINTER(_Stats)]
     lib.orc_lp_cluster_sub.argtypes = [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32,
                                        ctypes.c_int32, ctypes.c_uint64, _P, ctypes.POINTER(_Stats)]
+    lib.orc_lp_cluster_async.argtypes = [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32,
+                                         ctypes.c_uint64, _P, ctypes.POINTER(_Stats)]
     lib.orc_subround.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
     lib.orc_subround.restype = ctypes.c_uint32
     lib.orc_lp_proposals.argtypes = [ctypes.c_int32, _P, _P, _P, _P, _P, _P, ctypes.c_int64,
@@ -197,6 +199,21 @@ def lp_cluster(g, cap: int, rounds: int, seed: int, subrounds: int = 1):
     return labels[: g.n], LPStats(st.rounds_run, list(st.proposals[:k]), list(st.moves[:k]))
 
 
+def lp_cluster_async(g, cap: int, rounds: int, seed: int):
+    """The paper's asynchronous LP (sequential, random vertex order per round,
+    moves applied at once) as a quality reference; labels and per-round moves."""
+    lib = _load()
+    labels = np.empty(max(g.n, 1), dtype=np.int32)
+    st = _Stats()
+    rc = lib.orc_lp_cluster_async(g.n, _ptr(_arr(g.xadj, np.uint64)), _ptr(_arr(g.adjncy, np.int32)),
+                                  _ptr(_arr(g.adjwgt, np.int32)), _ptr(_arr(g.vwgt, np.int32)), cap, rounds,
+                                  seed, _ptr(labels), ctypes.byref(st))
+    if rc != OK:
+        raise ValueError(f"orc_lp_cluster_async: {rc}")
+    k = min(st.rounds_run, 64)
+    return labels[: g.n], LPStats(st.rounds_run, list(st.proposals[:k]), list(st.moves[:k]))
+
+
 def lp_proposals(g, C0, W0, cap: int, seed: int, rnd: int, vertices):
     """Best move (target or -1, gain) of each listed vertex under snapshot (C0, W0)."""
     lib = _load()
@@ -274,18 +291,20 @@ def coarsen_params(n0: int, total_weight: int):
     return n_target, cap
 
 
-def coarsen(g, seed: int, rounds: int = 5, max_levels: int = 32):
+def coarsen(g, seed: int, rounds: int = 5, max_levels: int = 32, cluster=None):
     """Cluster-and-contract until the graph has at most n_target vertices, the
     graph shrinks by less than 5 % in a level (stall), or max_levels levels.
-    Level l clusters with seed + l. Returns the list of levels
+    Level l clusters with seed + l (by `cluster(graph, cap, rounds, seed)`,
+    default the synchronous lp_cluster). Returns the list of levels
     [(graph, labels, map)] and the final graph."""
+    cluster = cluster or lp_cluster
     total = int(g.n if g.vwgt is None else int(np.asarray(g.vwgt, dtype=np.int64).sum()))
     n_target, cap = coarsen_params(g.n, total)
     levels = []
     cur = g
     lvl = 0
     while lvl < max_levels and cur.n > n_target:
-        labels, _ = lp_cluster(cur, cap, rounds, seed + lvl)
+        labels, _ = cluster(cur, cap, rounds, seed + lvl)
         nxt, mp = contract(cur, labels)
         levels.append((cur, labels, mp))
         prev_n = cur.n

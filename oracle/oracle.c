@@ -423,6 +423,65 @@ int orc_lp_cluster(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const
   return orc_lp_cluster_sub(n, xadj, adjncy, adjwgt, vwgt, cap, rounds, 1, seed, labels, stats);
 }
 
+/* The paper's asynchronous LP as a quality reference (Algorithms 1 and 2,
+ * sequential): per round the vertices are visited in a random order (a
+ * Fisher-Yates shuffle drawing index j for position i as the tie-break mix of
+ * (seed ^ ORC_ORDER_SALT, round, i) modulo i + 1), and each moves at once to
+ * its best cluster under the current labels and weights (same rating, cap,
+ * tie-break and gain rules as the synchronous rounds). A round without a move
+ * ends the call. stats: proposals = moves per round. */
+#define ORC_ORDER_SALT 0xBB67AE8584CAA73Bull
+int orc_lp_cluster_async(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
+                         const int32_t *vwgt, int64_t cap, int32_t rounds, uint64_t seed, int32_t *labels,
+                         orc_lp_stats *stats) {
+  if (n < 0 || cap < 1 || rounds < 0) return ORC_EINVAL;
+  if (stats) memset(stats, 0, sizeof(*stats));
+  int64_t *W = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+  int32_t *order = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+  uint64_t maxdeg = 0;
+  for (int32_t u = 0; u < n; ++u)
+    if (xadj[u + 1] - xadj[u] > maxdeg) maxdeg = xadj[u + 1] - xadj[u];
+  orc_rating *buf = (orc_rating *)malloc((maxdeg ? maxdeg : 1) * sizeof(orc_rating));
+  if (!W || !order || !buf) {
+    free(W); free(order); free(buf);
+    return ORC_ENOMEM;
+  }
+  for (int32_t u = 0; u < n; ++u) {
+    labels[u] = u;
+    W[u] = vwgt ? vwgt[u] : 1;
+  }
+  for (int32_t r = 0; r < rounds; ++r) {
+    for (int32_t i = 0; i < n; ++i) order[i] = i;
+    for (int32_t i = n - 1; i > 0; --i) {
+      const int32_t j = (int32_t)(orc_tiebreak_key(seed ^ ORC_ORDER_SALT, (uint32_t)r, (uint32_t)i) %
+                                  (uint64_t)(i + 1));
+      const int32_t t = order[i];
+      order[i] = order[j];
+      order[j] = t;
+    }
+    int64_t moves = 0;
+    for (int32_t i = 0; i < n; ++i) {
+      const int32_t u = order[i];
+      int32_t target;
+      int64_t gain;
+      if (!best_move(u, xadj, adjncy, adjwgt, vwgt, labels, W, cap, seed, (uint32_t)r, buf, &target, &gain))
+        continue;
+      const int64_t wu = vwgt ? vwgt[u] : 1;
+      W[labels[u]] -= wu;
+      W[target] += wu;
+      labels[u] = target;
+      ++moves;
+    }
+    if (moves == 0) break;
+    if (stats) {
+      stats->rounds_run = r + 1;
+      if (r < 64) stats->proposals[r] = stats->moves[r] = moves;
+    }
+  }
+  free(W); free(order); free(buf);
+  return ORC_OK;
+}
+
 /* One LP round from an arbitrary snapshot, for sampled checks: fills the
  * proposal (target or -1, gain) of each listed vertex. */
 int orc_lp_proposals(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,

@@ -279,3 +279,42 @@ def test_subround_argument_checks(oracle_mod, synth_mod):
     for S in (0, 65):
         with pytest.raises(ValueError):
             oracle_mod.lp_cluster(g, 2, 1, 1, subrounds=S)
+
+
+# ------------------------------------------------- asynchronous reference ----
+
+def test_async_matching_merges_every_pair(oracle_mod, synth_mod):
+    # in place: whichever member of a pair comes first joins the other's
+    # cluster, and the other then stays (its neighbour is already with it)
+    k = 80
+    g = synth_mod.from_edges(2 * k, [(2 * i, 2 * i + 1) for i in range(k)])
+    lab, st = oracle_mod.lp_cluster_async(g, 2, 5, 9)
+    assert all(lab[2 * i] == lab[2 * i + 1] for i in range(k))
+    assert oracle_mod.edge_cut(g, lab) == 0
+    assert st.rounds_run == 1 and st.moves == [k]
+
+
+@pytest.mark.parametrize("n,seed", [(5, 1), (12, 4), (30, 9)])
+def test_async_complete_graph_one_cluster(oracle_mod, synth_mod, n, seed):
+    # K_n, cap >= n: the first mover joins some cluster, which then has the
+    # highest rating for every later vertex
+    g = synth_mod.from_edges(n, [(a, b) for a in range(n) for b in range(a + 1, n)])
+    lab, _ = oracle_mod.lp_cluster_async(g, n, 3, seed)
+    assert len(set(lab.tolist())) == 1
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_async_valid_and_cap(oracle_mod, synth_mod, seed):
+    g = synth_mod.random_small(40 + seed, 0.2, seed)
+    if seed % 2:
+        g.vwgt = synth_mod.vertex_weights(g.n, 1, 3, seed)
+    cap = 3 + seed
+    lab, _ = oracle_mod.lp_cluster_async(g, cap, 5, seed)
+    bf.check_valid_clustering(g, lab, cap)
+    # a fixed point of the in-place rule: after the last round nobody moves
+    lab2, st2 = oracle_mod.lp_cluster_async(g, cap, 40, seed)
+    assert st2.rounds_run < 40
+    W = bf.cluster_weights(g, lab2)
+    tgt, _ = bf.expected_proposals(g, lab2, cap, seed, st2.rounds_run, oracle_mod.tiebreak_key)
+    assert (tgt < 0).all()
+    assert W.sum() == bf.vweights(g).sum()
