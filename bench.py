@@ -307,6 +307,45 @@ def bench_subrounds(args, G=None) -> dict:
     return out
 
 
+def bench_quality(args) -> dict:
+    """Coarsening quality of plain synchronous rounds (S = 1) and of S
+    sub-rounds per round, on geometric graphs where synchronous moves stall:
+    the 16k-vertex RGG-2D graph and RGG-3D with 2^20 vertices. Per setting:
+    levels, final size and the cut of the composed clustering (half the edge
+    weight left in the coarsest graph)."""
+    import torch
+
+    import paper_2410_19119_amd as lp
+    import synth
+
+    out = {}
+    for name, g in (("rgg2d-16k", synth.rgg2d_16k()), ("rgg3d-2^20", synth.rgg3d(1 << 20, 27.0, seed=1))):
+        G = lp.lp_compress(g.n, g.xadj.view(np.int64), g.adjncy)
+        two_m = g.two_m
+        del g
+        res = {}
+        for S in (1, 2, 4):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            levels, final, n_target, _ = lp.coarsen(G, seed=1, rounds=args.rounds, subrounds=S)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            w = lp.lp_decompress(final)[2] if not final.compressed else None
+            cut = int(w.to(torch.int64).sum()) // 2 if w is not None else two_m // 2
+            res[str(S)] = {"levels": len(levels), "final_n": final.n, "n_target": n_target, "cut_of_hierarchy": cut,
+                           "ms": round(1e3 * dt, 1)}
+            for lv in levels[1:]:
+                lv[0].free()
+            if final is not G:
+                final.free()
+        out[name] = res
+        G.free()
+        log(f"[quality] {name}: " + "; ".join(f"S={k}: {v['levels']} levels, n={v['final_n']} "
+                                              f"(target {v['n_target']}), cut {v['cut_of_hierarchy']}, {v['ms']} ms"
+                                              for k, v in res.items()))
+    return out
+
+
 def bench_coarsen(args) -> dict:
     """Full coarsening of one large graph (cluster + contract until 2^14)."""
     import torch
@@ -429,6 +468,14 @@ def main() -> int:
                           "value": lv0.get("lp_round_edges_per_s"), "unit": "edges/s", "n_gpus": 1,
                           "higher_is_better": True, "data": "synthetic", "dtype": "int32",
                           "config": {"workload": res["workload"]}, "coarsening": res}))
+        return 0
+    if args.workload == "quality":
+        res = bench_quality(args)
+        print(json.dumps({"metric": "cut of the coarsening hierarchy by sub-rounds per round",
+                          "value": res["rgg3d-2^20"]["4"]["cut_of_hierarchy"], "unit": "edges",
+                          "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "int32",
+                          "config": {"workload": "rgg2d-16k and rgg3d n=2^20, 5 rounds per level"},
+                          "quality": res}))
         return 0
     if args.workload == "subrounds":
         res = bench_subrounds(args)
