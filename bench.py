@@ -378,7 +378,8 @@ def bench_coarsen(args) -> dict:
     while lvl < 32 and cur.n > n_target:
         torch.cuda.synchronize()
         t = time.perf_counter()
-        lab, st = lp.lp_cluster(cur, cap, args.rounds, 1 + lvl, config=dict(timing=1), stats=True)
+        lab, st = lp.lp_cluster(cur, cap, args.rounds, 1 + lvl, config=dict(timing=1, subrounds=args.coarsen_subrounds),
+                                stats=True)
         torch.cuda.synchronize()
         t_lp = time.perf_counter() - t
         t = time.perf_counter()
@@ -404,7 +405,8 @@ def bench_coarsen(args) -> dict:
         lvl += 1
         if 100 * cur.n > 95 * prev_n:
             break
-    return {"workload": desc, "n": n0, "two_m": m0, "compressed_bytes": G.nbytes, "n_target": n_target, "cap": cap,
+    return {"workload": desc, "subrounds": args.coarsen_subrounds, "n": n0, "two_m": m0, "compressed_bytes": G.nbytes,
+            "n_target": n_target, "cap": cap,
             "levels": levels, "end_to_end_ms": total_ms, "final_n": cur.n, "checks": checks,
             "all_checks_pass": all(all(v for k, v in c.items() if k != "cut") for c in checks)}
 
@@ -431,6 +433,7 @@ def main() -> int:
     ap.add_argument("--serve-split", type=int, default=0,
                     help="directed edges from which a job runs in the big-job lane (0: one lane)")
     ap.add_argument("--coarsen-graph", default="rmat", choices=["rmat", "rgg3d"])
+    ap.add_argument("--coarsen-subrounds", type=int, default=1, help="sub-rounds per LP round in the coarsening")
     ap.add_argument("--coarsen-scale", type=int, default=26)
     ap.add_argument("--no-checks", action="store_true")
     args = ap.parse_args()
