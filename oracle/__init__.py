@@ -73,6 +73,9 @@ def _load():
                                        ctypes.c_int32, ctypes.c_uint64, _P, ctypes.POINTER(_Stats)]
     lib.orc_lp_cluster_async.argtypes = [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32,
                                          ctypes.c_uint64, _P, ctypes.POINTER(_Stats)]
+    lib.orc_lp_refine.argtypes = [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64,
+                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, _P, ctypes.POINTER(_Stats)]
+    lib.orc_initial_partition.argtypes = [ctypes.c_int32, _P, ctypes.c_int32, _P]
     lib.orc_subround.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
     lib.orc_subround.restype = ctypes.c_uint32
     lib.orc_lp_proposals.argtypes = [ctypes.c_int32, _P, _P, _P, _P, _P, _P, ctypes.c_int64,
@@ -291,15 +294,17 @@ def coarsen_params(n0: int, total_weight: int):
     return n_target, cap
 
 
-def coarsen(g, seed: int, rounds: int = 5, max_levels: int = 32, cluster=None):
+def coarsen(g, seed: int, rounds: int = 5, max_levels: int = 32, cluster=None, cap=None):
     """Cluster-and-contract until the graph has at most n_target vertices, the
     graph shrinks by less than 5 % in a level (stall), or max_levels levels.
     Level l clusters with seed + l (by `cluster(graph, cap, rounds, seed)`,
-    default the synchronous lp_cluster). Returns the list of levels
+    default the synchronous lp_cluster); `cap`, if given, replaces the
+    loop's cluster-weight cap. Returns the list of levels
     [(graph, labels, map)] and the final graph."""
     cluster = cluster or lp_cluster
     total = int(g.n if g.vwgt is None else int(np.asarray(g.vwgt, dtype=np.int64).sum()))
-    n_target, cap = coarsen_params(g.n, total)
+    n_target, cap0 = coarsen_params(g.n, total)
+    cap = cap0 if cap is None else int(cap)
     levels = []
     cur = g
     lvl = 0
@@ -313,3 +318,87 @@ def coarsen(g, seed: int, rounds: int = 5, max_levels: int = 32, cluster=None):
         if 100 * cur.n > 95 * prev_n:
             break
     return levels, cur, n_target, cap
+
+
+# --------------------------------------------------------- uncoarsening ----
+
+def max_block_weight(total_weight: int, k: int, eps_permille: int = 30) -> int:
+    """Balance bound of a k-way partition: the paper's (1 + eps) * c(V) / k
+    (Section I; eps = 3 % in its experiments), with c(V) / k rounded up to a
+    whole weight so that a perfectly balanced partition always fits, and eps
+    in thousandths: L = ceil(c(V) / k) + floor(L0 * eps_permille / 1000)."""
+    base = -(-int(total_weight) // int(k))
+    return base + base * int(eps_permille) // 1000
+
+
+def partition_cap(n0: int, total_weight: int, k: int, eps_permille: int = 30) -> int:
+    """Cluster-weight cap of the coarsening that precedes a k-way partition:
+    the coarsening loop's own cap, but no more than the balance slack
+    L - ceil(c(V) / k) (at least 1), so that no coarse vertex is heavier than
+    what a block may exceed its share by. The contiguous initial partition of
+    the coarsest graph then respects L."""
+    _, cap = coarsen_params(n0, total_weight)
+    return min(cap, max(1, max_block_weight(total_weight, k, eps_permille) - (-(-int(total_weight) // int(k)))))
+
+
+def initial_partition(g, k: int):
+    """Contiguous-weight initial partition (see orc_initial_partition)."""
+    labels = np.empty(max(g.n, 1), dtype=np.int32)
+    rc = _load().orc_initial_partition(g.n, _ptr(_arr(g.vwgt, np.int32)), k, _ptr(labels))
+    if rc != OK:
+        raise ValueError(f"orc_initial_partition: {rc}")
+    return labels[: g.n]
+
+
+def lp_refine(g, blocks, k: int, max_weight: int, rounds: int, seed: int, subrounds: int = 1):
+    """Refined blocks (int32[n]) and per-round stats: synchronous
+    size-constrained LP started from `blocks` (see orc_lp_refine)."""
+    lib = _load()
+    labels = np.array(blocks, dtype=np.int32, copy=True)
+    if labels.size == 0:
+        labels = np.zeros(1, dtype=np.int32)
+    st = _Stats()
+    rc = lib.orc_lp_refine(g.n, _ptr(_arr(g.xadj, np.uint64)), _ptr(_arr(g.adjncy, np.int32)),
+                           _ptr(_arr(g.adjwgt, np.int32)), _ptr(_arr(g.vwgt, np.int32)), k, max_weight, rounds,
+                           subrounds, seed, _ptr(labels), ctypes.byref(st))
+    if rc != OK:
+        raise ValueError(f"orc_lp_refine: {rc}")
+    r = min(st.rounds_run, 64)
+    return labels[: g.n], LPStats(st.rounds_run, list(st.proposals[:r]), list(st.moves[:r]))
+
+
+def project(fine_to_coarse, coarse_blocks):
+    """Blocks of the finer graph: every vertex takes the block of the coarse
+    vertex it was contracted into (Section II-A, uncoarsening)."""
+    return np.asarray(coarse_blocks, dtype=np.int32)[np.asarray(fine_to_coarse, dtype=np.int64)]
+
+
+def block_weights(g, blocks, k: int):
+    w = np.ones(g.n, dtype=np.int64) if g.vwgt is None else np.asarray(g.vwgt, dtype=np.int64)
+    return np.bincount(np.asarray(blocks, dtype=np.int64), weights=w, minlength=k).astype(np.int64)
+
+
+def partition(g, k: int, seed: int = 1, rounds: int = 5, eps_permille: int = 30, subrounds: int = 1,
+              refine_subrounds: int = 1):
+    """Multilevel k-way partition (Section II-A): coarsen with LP clustering
+    under partition_cap, partition the coarsest graph (initial_partition, then lp_refine there),
+    then project to each finer level and refine it. Level l (0 = the input)
+    refines with seed + l. Returns (blocks int32[n], per-level list of
+    (n, cut after refinement) from the coarsest to the input)."""
+    total = int(g.n if g.vwgt is None else int(np.asarray(g.vwgt, dtype=np.int64).sum()))
+    lmax = max_block_weight(total, k, eps_permille)
+    cl = None
+    if subrounds > 1:
+        def cl(gr, cap, rnd, sd):
+            return lp_cluster(gr, cap, rnd, sd, subrounds=subrounds)
+    levels, coarsest, _, _ = coarsen(g, seed, rounds, cluster=cl, cap=partition_cap(g.n, total, k, eps_permille))
+    depth = len(levels)
+    blocks = initial_partition(coarsest, k)
+    blocks, _ = lp_refine(coarsest, blocks, k, lmax, rounds, seed + depth, refine_subrounds)
+    trace = [(coarsest.n, edge_cut(coarsest, blocks))]
+    for lvl in range(depth - 1, -1, -1):
+        fine, _, mp = levels[lvl]
+        blocks = project(mp, blocks)
+        blocks, _ = lp_refine(fine, blocks, k, lmax, rounds, seed + lvl, refine_subrounds)
+        trace.append((fine.n, edge_cut(fine, blocks)))
+    return blocks, trace

@@ -15,7 +15,11 @@
  *   - cluster contraction into a quotient graph (Section IV-B, the weight
  *     definition of a coarse edge);
  *   - the edge cut (Section I, the partitioning objective);
- *   - the coarsening loop (Sections I and II-A: cluster, contract, repeat).
+ *   - the coarsening loop (Sections I and II-A: cluster, contract, repeat);
+ *   - the uncoarsening slice (Section II-A: an initial partition of the
+ *     coarsest graph, projected level by level and refined there with
+ *     size-constrained LP as in Section II-B; the balance bound of
+ *     Section I).
  *
  * Floating point is never used: IDs are int32, offsets uint64, input weights
  * int32 >= 1, ratings / gains / cluster weights int64.
@@ -312,9 +316,9 @@ uint32_t orc_subround(uint32_t u, uint32_t S) {
   return (uint32_t)(orc_tiebreak_key(ORC_SUBROUND_SALT, 0, u) % S);
 }
 
-/* Size-constrained LP clustering, synchronous rounds, each split into S
+/* The synchronous rounds shared by clustering and refinement, starting from
+ * the labelling in `labels` (every label in [0, n)), each round split into S
  * sub-rounds (S = 1: one synchronous step per round).
- * Start: every vertex in its own cluster (C[u] = u, Section IV-A).
  * Per sub-round s of round r: the vertices of sub-round s compute their best
  * move against the snapshot taken at the start of the sub-round (tie-break
  * keys of round r); then, for each target cluster, the proposals are taken
@@ -324,12 +328,10 @@ uint32_t orc_subround(uint32_t u, uint32_t S) {
  * sub-round sees the moves of the earlier ones, as the paper's in-place
  * updates let later vertices see earlier moves (Algorithms 1 and 2), but in
  * a fixed order. A round with no proposal in any sub-round is a fixed point,
- * so the loop stops there.
- * labels (out): n cluster IDs in [0, n); not renumbered. */
-int orc_lp_cluster_sub(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
-                       const int32_t *vwgt, int64_t cap, int32_t rounds, int32_t subrounds, uint64_t seed,
-                       int32_t *labels, orc_lp_stats *stats) {
-  if (n < 0 || cap < 1 || rounds < 0 || subrounds < 1 || subrounds > 64) return ORC_EINVAL;
+ * so the loop stops there. Cluster weights are recomputed from the labels. */
+static int lp_rounds(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
+                     const int32_t *vwgt, int64_t cap, int32_t rounds, int32_t subrounds, uint64_t seed,
+                     int32_t *labels, orc_lp_stats *stats) {
   if (stats) memset(stats, 0, sizeof(*stats));
   int32_t *C0 = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
   int64_t *W = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
@@ -342,9 +344,9 @@ int orc_lp_cluster_sub(int32_t n, const uint64_t *xadj, const int32_t *adjncy, c
     return ORC_ENOMEM;
   }
   uint64_t maxdeg = 0;
+  for (int32_t c = 0; c < n; ++c) W[c] = 0;
   for (int32_t u = 0; u < n; ++u) {
-    labels[u] = u;
-    W[u] = vwgt ? vwgt[u] : 1;
+    W[labels[u]] += vwgt ? vwgt[u] : 1;
     if (xadj[u + 1] - xadj[u] > maxdeg) maxdeg = xadj[u + 1] - xadj[u];
   }
   int status = ORC_OK;
@@ -415,6 +417,52 @@ int orc_lp_cluster_sub(int32_t n, const uint64_t *xadj, const int32_t *adjncy, c
   }
   free(C0); free(W); free(W0); free(ptarget); free(pgain); free(props);
   return status;
+}
+
+/* Size-constrained LP clustering (Section IV-A): every vertex starts in its
+ * own cluster (C[u] = u), then the synchronous rounds above.
+ * labels (out): n cluster IDs in [0, n); not renumbered. */
+int orc_lp_cluster_sub(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
+                       const int32_t *vwgt, int64_t cap, int32_t rounds, int32_t subrounds, uint64_t seed,
+                       int32_t *labels, orc_lp_stats *stats) {
+  if (n < 0 || cap < 1 || rounds < 0 || subrounds < 1 || subrounds > 64) return ORC_EINVAL;
+  for (int32_t u = 0; u < n; ++u) labels[u] = u;
+  return lp_rounds(n, xadj, adjncy, adjwgt, vwgt, cap, rounds, subrounds, seed, labels, stats);
+}
+
+/* Size-constrained LP refinement of a k-way partition (Section II-B: the
+ * refinement runs label propagation from the given partition, with the
+ * blocks as the labels): the same synchronous rounds, started from the
+ * blocks in `labels`, with the maximum block weight as the cap. A vertex
+ * moves to the adjacent block with the most edge weight to it if that beats
+ * its own block and the block can take it; moves into a block are admitted
+ * while the block stays within the cap.
+ * labels (in/out): the block of every vertex, in [0, k); 1 <= k <= n. */
+int orc_lp_refine(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
+                  const int32_t *vwgt, int32_t k, int64_t max_block_weight, int32_t rounds, int32_t subrounds,
+                  uint64_t seed, int32_t *labels, orc_lp_stats *stats) {
+  if (n < 0 || k < 1 || (n > 0 && k > n) || max_block_weight < 1 || rounds < 0 || subrounds < 1 ||
+      subrounds > 64)
+    return ORC_EINVAL;
+  for (int32_t u = 0; u < n; ++u)
+    if (labels[u] < 0 || labels[u] >= k) return ORC_EINVAL;
+  return lp_rounds(n, xadj, adjncy, adjwgt, vwgt, max_block_weight, rounds, subrounds, seed, labels, stats);
+}
+
+/* Initial k-way partition by contiguous weight: the vertices, in ID order,
+ * fill the blocks one after another; vertex u goes to block
+ * floor(k * P_u / c(V)), where P_u is the total weight of the vertices
+ * before u and c(V) the total weight. Every block then weighs less than
+ * c(V)/k plus one vertex weight. k >= 1. */
+int orc_initial_partition(int32_t n, const int32_t *vwgt, int32_t k, int32_t *labels) {
+  if (n < 0 || k < 1) return ORC_EINVAL;
+  unsigned __int128 total = 0, P = 0;
+  for (int32_t u = 0; u < n; ++u) total += (unsigned __int128)(vwgt ? vwgt[u] : 1);
+  for (int32_t u = 0; u < n; ++u) {
+    labels[u] = (int32_t)(((unsigned __int128)k * P) / total);
+    P += (unsigned __int128)(vwgt ? vwgt[u] : 1);
+  }
+  return ORC_OK;
 }
 
 int orc_lp_cluster(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
