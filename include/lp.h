@@ -281,6 +281,58 @@ lp_status lp_contract(const lp_graph *g, const int32_t *labels_dev, int32_t *map
  */
 lp_status lp_edge_cut(const lp_graph *g, const int32_t *labels_dev, int64_t *cut_out, void *stream);
 
+/*
+ * Uncoarsening slice of the multilevel scheme (Section II-A): an initial
+ * partition of the coarsest graph, projected to each finer level and refined
+ * there by size-constrained label propagation (Section II-B). Blocks are
+ * labels in [0, k); a partition is balanced when every block weighs at most
+ * the bound of Section I, passed in as max_block_weight.
+ */
+
+/*
+ * lp_initial_partition — contiguous-weight k-way partition: the vertices, in
+ * ID order, fill blocks 0..k-1; vertex u goes to block floor(k * P_u / c(V)),
+ * where P_u is the total weight of the vertices before u and c(V) the total
+ * weight. Every block weighs less than c(V)/k plus one vertex weight.
+ * Arguments: g (single graph), k >= 1, labels_dev int32[n] (output).
+ * Errors: LP_EINVAL (k < 1, NULL labels, batch handle); LP_EUNSUPPORTED if
+ * k * c(V) >= 2^63.
+ */
+lp_status lp_initial_partition(const lp_graph *g, int32_t k, int32_t *labels_dev, void *stream);
+
+/*
+ * lp_project — blocks of a finer graph from those of its quotient graph
+ * (Section II-A, uncoarsening): labels_dev[u] = coarse_labels_dev[map_dev[u]]
+ * for u < n, with map_dev the fine-to-coarse map lp_contract writes. A map
+ * entry outside [0, coarse_n) gives -1, which lp_refine rejects.
+ * Errors: LP_EINVAL (n < 0, coarse_n < 0, NULL pointer with n > 0).
+ */
+lp_status lp_project(int32_t n, const int32_t *map_dev, int32_t coarse_n, const int32_t *coarse_labels_dev,
+                     int32_t *labels_dev, void *stream);
+
+/*
+ * lp_refine — size-constrained label-propagation refinement of a k-way
+ * partition (Section II-B): the rounds of lp_cluster (rating, tie-break keys
+ * of (seed, round, block), gain, admission in (gain desc, u asc) order and the
+ * early exit) started from the blocks in labels_dev instead of singletons,
+ * with max_block_weight as the cap and W starting as the block weights. A
+ * block that starts within max_block_weight stays within it (moves into a
+ * block are admitted against its weight at the start of the round;
+ * departures are not credited).
+ * Arguments: g (single graph), 1 <= k <= n, max_block_weight >= 1,
+ * rounds >= 0, seed, labels_dev int32[n] (in: the block of every vertex, in
+ * [0, k); out: the refined blocks). The call synchronises `stream` once,
+ * after checking the blocks on the device and before the first round.
+ * Errors: LP_EINVAL (k out of range, a block outside [0, k), cap < 1,
+ * rounds < 0, batch handle); LP_ENOMEM; LP_EUNSUPPORTED as lp_cluster.
+ */
+lp_status lp_refine(const lp_graph *g, int32_t k, int64_t max_block_weight, int32_t rounds, uint64_t seed,
+                    int32_t *labels_dev, void *stream);
+
+/* lp_refine with knobs and optional statistics, as lp_cluster_ex. */
+lp_status lp_refine_ex(const lp_graph *g, int32_t k, int64_t max_block_weight, int32_t rounds, uint64_t seed,
+                       int32_t *labels_dev, const lp_config *cfg, lp_cluster_stats *stats, void *stream);
+
 /* Returns every block of the library's memory cache to HIP, on every device
  * (waiting for each device to be idle first). Handles stay valid; later calls
  * fill the cache again. For callers that share the device with other
@@ -288,9 +340,10 @@ lp_status lp_edge_cut(const lp_graph *g, const int32_t *labels_dev, int64_t *cut
 void lp_trim_memory(void);
 
 /* Frees a handle (NULL is ignored). A handle with plain allocations waits
- * for the device to be idle first; a handle made on a stream is released on
- * its stream (hipFreeAsync) without waiting, so later work on that stream
- * runs after the release and work already queued on it before. */
+ * for the device to be idle first; a handle made on a stream returns its
+ * buffers to the library's memory cache in that stream's order, without
+ * waiting: work already queued on the stream runs first, and a later call
+ * reuses the buffers only after it. */
 void lp_graph_free(lp_graph *g);
 
 #ifdef __cplusplus

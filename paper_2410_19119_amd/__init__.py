@@ -107,6 +107,15 @@ def _load():
     lib.lp_batch_cluster_ex.restype = S
     lib.lp_batch_cluster.argtypes = [ctypes.c_int32, _P, _P, ctypes.c_int32, _P, _P, _P]
     lib.lp_batch_cluster.restype = S
+    lib.lp_initial_partition.argtypes = [_P, ctypes.c_int32, _P, _P]
+    lib.lp_initial_partition.restype = S
+    lib.lp_project.argtypes = [ctypes.c_int32, _P, ctypes.c_int32, _P, _P, _P]
+    lib.lp_project.restype = S
+    lib.lp_refine.argtypes = [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, _P, _P]
+    lib.lp_refine.restype = S
+    lib.lp_refine_ex.argtypes = [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, _P,
+                                 ctypes.POINTER(lp_config), ctypes.POINTER(lp_cluster_stats), _P]
+    lib.lp_refine_ex.restype = S
     _lib = lib
     return lib
 
@@ -115,7 +124,8 @@ def exported_symbols() -> list[str]:
     return ["lp_strerror", "lp_version", "lp_compress", "lp_graph_from_csr", "lp_graph_info",
             "lp_graph_export", "lp_decompress", "lp_cluster", "lp_cluster_ex", "lp_contract",
             "lp_edge_cut", "lp_graph_free", "lp_batch_create", "lp_batch_info", "lp_batch_cluster_ex",
-            "lp_batch_cluster", "lp_trim_memory"]
+            "lp_batch_cluster", "lp_trim_memory", "lp_initial_partition", "lp_project", "lp_refine",
+            "lp_refine_ex"]
 
 
 def _check(st: int, where: str) -> None:
@@ -382,3 +392,97 @@ def coarsen(g: Graph, seed: int = 1, rounds: int = 5, max_levels: int = 32, stre
         if 100 * cur.n > 95 * prev_n:
             break
     return levels, cur, n_target, cap
+
+
+# ------------------------------------------------------------ uncoarsening ----
+
+def max_block_weight(total_weight: int, k: int, eps_permille: int = 30) -> int:
+    """Balance bound (1 + eps) * c(V) / k of Section I, with c(V) / k rounded up
+    to a whole weight and eps in thousandths:
+    ceil(c(V) / k) + floor(ceil(c(V) / k) * eps_permille / 1000)."""
+    base = -(-int(total_weight) // int(k))
+    return base + base * int(eps_permille) // 1000
+
+
+def partition_cap(n0: int, total_weight: int, k: int, eps_permille: int = 30) -> int:
+    """Cluster-weight cap of the coarsening before a k-way partition: the
+    coarsening loop's cap, but at most the balance slack (at least 1), so that
+    no coarse vertex outweighs what a block may exceed its share by."""
+    _, cap = coarsen_params(n0, total_weight)
+    slack = max_block_weight(total_weight, k, eps_permille) - (-(-int(total_weight) // int(k)))
+    return min(cap, max(1, slack))
+
+
+def lp_initial_partition(g: Graph, k: int, labels=None, stream=None):
+    """Contiguous-weight k-way partition (int32 device tensor)."""
+    torch = _torch()
+    if labels is None:
+        labels = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda")
+    _check(_load().lp_initial_partition(g.handle, int(k), _ptr(labels), _stream(stream)), "lp_initial_partition")
+    return labels[: g.n]
+
+
+def lp_project(fine_to_coarse, coarse_labels, stream=None):
+    """Blocks of the finer graph: labels[u] = coarse_labels[map[u]]."""
+    torch = _torch()
+    mp = _dev(fine_to_coarse, torch.int32)
+    cl = _dev(coarse_labels, torch.int32)
+    n = int(mp.numel())
+    out = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+    _check(_load().lp_project(n, _ptr(mp), int(cl.numel()), _ptr(cl), _ptr(out), _stream(stream)), "lp_project")
+    return out[:n]
+
+
+def lp_refine(g: Graph, blocks, k: int, max_block_weight: int, rounds: int = 5, seed: int = 1,
+              config: dict | None = None, stats: bool = False, stream=None):
+    """Size-constrained LP refinement of a k-way partition; returns the refined
+    blocks (a new int32 device tensor) and, with stats=True, ClusterStats."""
+    torch = _torch()
+    labels = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda")
+    if g.n:
+        labels[: g.n].copy_(_dev(blocks, torch.int32)[: g.n])
+    cfg = lp_config(**{kk: int(v) for kk, v in config.items()}) if config else None
+    st_obj = lp_cluster_stats() if stats else None
+    st = _load().lp_refine_ex(g.handle, int(k), int(max_block_weight), int(rounds), int(seed) & (2**64 - 1),
+                              _ptr(labels), ctypes.byref(cfg) if cfg else None,
+                              ctypes.byref(st_obj) if st_obj is not None else None, _stream(stream))
+    _check(st, "lp_refine")
+    out = labels[: g.n]
+    return (out, _stats_of(st_obj)) if stats else out
+
+
+def partition(g: Graph, k: int, seed: int = 1, rounds: int = 5, eps_permille: int = 30, subrounds: int = 1,
+              refine_subrounds: int = 1, stream=None, trace: bool = False):
+    """Multilevel k-way partition (Section II-A), all steps on the device:
+    coarsen with LP clustering under partition_cap, partition the coarsest
+    graph (lp_initial_partition, then lp_refine there), then project to each
+    finer level and refine it; level l (0 = the input) refines with seed + l.
+    Returns the blocks of g (int32 device tensor); with trace=True also the
+    list of (n, cut after refinement) from the coarsest level to g."""
+    cap = partition_cap(g.n, g.total_vwgt, k, eps_permille)
+    lmax = max_block_weight(g.total_vwgt, k, eps_permille)
+    n_target, _ = coarsen_params(g.n, g.total_vwgt)
+    cfg = dict(subrounds=subrounds) if subrounds > 1 else None
+    rcfg = dict(subrounds=refine_subrounds) if refine_subrounds > 1 else None
+    levels = []
+    cur = g
+    while len(levels) < 32 and cur.n > n_target:
+        labels = lp_cluster(cur, cap, rounds, seed + len(levels), stream=stream, config=cfg)
+        nxt, mp = lp_contract(cur, labels, stream=stream)
+        levels.append((cur, mp))
+        prev_n, cur = cur.n, nxt
+        if 100 * cur.n > 95 * prev_n:
+            break
+    blocks = lp_initial_partition(cur, k, stream=stream)
+    blocks = lp_refine(cur, blocks, k, lmax, rounds, seed + len(levels), config=rcfg, stream=stream)
+    steps = [(cur.n, lp_edge_cut(cur, blocks, stream=stream))] if trace else None
+    for lvl in range(len(levels) - 1, -1, -1):
+        fine, mp = levels[lvl]
+        if cur is not g:
+            cur.free()
+        blocks = lp_project(mp, blocks, stream=stream)
+        blocks = lp_refine(fine, blocks, k, lmax, rounds, seed + lvl, config=rcfg, stream=stream)
+        cur = fine
+        if trace:
+            steps.append((fine.n, lp_edge_cut(fine, blocks, stream=stream)))
+    return (blocks, steps) if trace else blocks

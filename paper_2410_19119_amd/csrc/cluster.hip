@@ -1591,6 +1591,34 @@ __global__ void k_init(int32_t n, const int32_t* vwgt, int32_t* C, int64_t* W, i
   }
 }
 
+// Start of a refinement: the given blocks stay as the labels; W[b] = weight
+// of block b (W zeroed before), summed per workgroup in LDS when there are
+// few blocks. A block outside [0, k) sets *bad and is not counted.
+constexpr int kInitBins = 2048;
+__global__ __launch_bounds__(256) void k_init_blocks(int32_t n, const int32_t* vwgt, const int32_t* C, int32_t k,
+                                                     int64_t* W, int32_t* ptgt, uint32_t* bad) {
+  __shared__ unsigned long long hist[kInitBins];
+  const bool local = k <= kInitBins;
+  if (local)
+    for (int32_t i = threadIdx.x; i < k; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+    ptgt[u] = -1;
+    const int32_t c = C[u];
+    if ((uint32_t)c >= (uint32_t)k) {
+      *bad = 1u;
+      continue;
+    }
+    const unsigned long long w = vwgt ? (unsigned long long)vwgt[u] : 1ull;
+    if (local) atomicAdd(&hist[c], w);
+    else atomicAdd((unsigned long long*)&W[c], w);
+  }
+  __syncthreads();
+  if (local)
+    for (int32_t i = threadIdx.x; i < k; i += blockDim.x)
+      if (hist[i]) atomicAdd((unsigned long long*)&W[i], hist[i]);
+}
+
 int bitlen(uint64_t x) { return x ? 64 - __builtin_clzll(x) : 0; }
 
 template <typename F>
@@ -2076,9 +2104,12 @@ lp_status visit_edges_records(const lp_graph* g, const int32_t* map, const uint6
 // graph (host arrays) and the labels come out local to each graph: written to
 // `labels` (one array over the union) or, if labels_each is given, to each
 // graph's own device array.
+// init_k == 0: clustering, every vertex starts in its own cluster. init_k > 0:
+// refinement, labels hold a partition into init_k blocks on entry.
 static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* caps, int32_t rounds, uint64_t seed,
                               const uint64_t* seeds, int32_t* labels, int32_t* const* labels_each,
-                              const lp_config* cfg_in, lp_cluster_stats* stats_out, hipStream_t s) {
+                              const lp_config* cfg_in, lp_cluster_stats* stats_out, hipStream_t s,
+                              int32_t init_k = 0) {
   const bool batch = g->nbatch > 0;
   if (batch) {
     if (!caps || !seeds) return LP_EINVAL;
@@ -2090,6 +2121,7 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
   if (rounds < 0 || (!labels && !labels_each && g->n > 0)) return LP_EINVAL;
   if (stats_out) memset(stats_out, 0, sizeof(*stats_out));
   const int32_t n = g->n;
+  if (init_k < 0 || (init_k > 0 && (batch || init_k > std::max(n, 1)))) return LP_EINVAL;
   if (n == 0) return LP_OK;
   // knobs (results do not depend on them)
   const bool wide = g->max_wdeg > 0x7FFFFFFFll;
@@ -2135,7 +2167,7 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
     uint32_t done;
     uint32_t count;
     int32_t rounds_run;
-    uint32_t pad;
+    uint32_t bad;  // a refinement block out of range
     uint32_t bucket_tot[4];
     unsigned long long round_props;
     int64_t stats[128];
@@ -2218,8 +2250,19 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
     if (sc.failed) return LP_ENOMEM;
   }
 
-  hipLaunchKernelGGL(k_init, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, g->vwgt, labels, W, ptgt);
-  LP_CHECK_LAUNCH();
+  if (init_k > 0) {
+    LP_CHECK_HIP(hipMemsetAsync(W, 0, (size_t)n * sizeof(int64_t), s));
+    hipLaunchKernelGGL(k_init_blocks, dim3(grid_for(n, 256, 512)), dim3(256), 0, s, n, g->vwgt, labels, init_k, W,
+                       ptgt, &ctl->bad);
+    LP_CHECK_LAUNCH();
+    uint32_t bad = 0;
+    LP_CHECK_HIP(hipMemcpyAsync(&bad, &ctl->bad, sizeof(bad), hipMemcpyDeviceToHost, s));
+    LP_CHECK_HIP(hipStreamSynchronize(s));
+    if (bad) return LP_EINVAL;
+  } else {
+    hipLaunchKernelGGL(k_init, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, g->vwgt, labels, W, ptgt);
+    LP_CHECK_LAUNCH();
+  }
   LP_CHECK(end());
 
   RoundCtx x;
@@ -2376,6 +2419,21 @@ extern "C" lp_status lp_cluster_ex(const lp_graph* g, int64_t cap, int32_t round
   clear_error();
   if (!g || g->nbatch) return LP_EINVAL;
   return cluster_impl(g, cap, nullptr, rounds, seed, nullptr, labels, nullptr, cfg, stats, (hipStream_t)stream);
+}
+
+extern "C" lp_status lp_refine_ex(const lp_graph* g, int32_t k, int64_t max_block_weight, int32_t rounds,
+                                  uint64_t seed, int32_t* labels, const lp_config* cfg, lp_cluster_stats* stats,
+                                  void* stream) {
+  clear_error();
+  if (!g || g->nbatch || k < 1) return LP_EINVAL;
+  return cluster_impl(g, max_block_weight, nullptr, rounds, seed, nullptr, labels, nullptr, cfg, stats,
+                      (hipStream_t)stream, k);
+}
+
+extern "C" lp_status lp_refine(const lp_graph* g, int32_t k, int64_t max_block_weight, int32_t rounds, uint64_t seed,
+                               int32_t* labels, void* stream) {
+  clear_error();
+  return lp_refine_ex(g, k, max_block_weight, rounds, seed, labels, nullptr, nullptr, stream);
 }
 
 extern "C" lp_status lp_batch_cluster_ex(const lp_graph* b, const int64_t* caps, int32_t rounds, const uint64_t* seeds,

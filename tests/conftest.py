@@ -42,3 +42,9 @@ def lp():
     import torch
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     return m
+
+
+@pytest.fixture(scope="session")
+def rmat24(synth_mod):
+    """The benchmark graph: R-MAT scale 24, edge factor 16, seed 1 (generated once per session)."""
+    return synth_mod.rmat_scale(24, 16, seed=1)

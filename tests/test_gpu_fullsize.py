@@ -11,11 +11,6 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
-def rmat24(synth_mod):
-    return synth_mod.rmat_scale(24, 16, seed=1)
-
-
-@pytest.fixture(scope="module")
 def gpu_run(lp, rmat24):
     g = rmat24
     G = lp.lp_compress(g.n, g.xadj.view(np.int64), g.adjncy)
