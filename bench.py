@@ -307,6 +307,53 @@ def bench_subrounds(args, G=None) -> dict:
     return out
 
 
+def bench_partition(args, G=None) -> dict:
+    """Multilevel k-way partition of the R-MAT scale 24 graph, or of RGG-2D
+    with 2^24 vertices and average degree 8 (k from --partition-k, eps 3 %):
+    coarsening under the partition cap, contiguous initial partition and
+    refinement of the coarsest graph, then projection and refinement on every
+    finer level, all on the device. Reports the end-to-end time (after one
+    untimed run), the cut per level, the balance, and the refinement round
+    rate on the input graph."""
+    import torch
+
+    import paper_2410_19119_amd as lp
+    import synth
+
+    if G is None:
+        if args.partition_graph == "rgg2d":
+            g = synth.rgg(2, 1 << 24, synth.rgg_radius(2, 1 << 24, 8.0), seed=1)
+        else:
+            g = synth.rmat_scale(24, 16, seed=1)
+        G = lp.lp_compress(g.n, g.xadj.view(np.int64), g.adjncy)
+        del g
+    out = {}
+    for k in [int(x) for x in args.partition_k.split(",")]:
+        lmax = lp.max_block_weight(G.total_vwgt, k)
+        _, trace = lp.partition(G, k, seed=1, rounds=args.rounds, trace=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        blocks = lp.partition(G, k, seed=1, rounds=args.rounds)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        cut = lp.lp_edge_cut(G, blocks)
+        bw = torch.bincount(blocks.to(torch.int64), minlength=k)
+        ip = lp.lp_initial_partition(G, k)
+        _, st = lp.lp_refine(G, ip, k, lmax, args.rounds, 1, config=dict(timing=1), stats=True)
+        rms = st.phase_ms["round"] / max(1, st.phase_launches["round"])
+        out[str(k)] = {"ms": round(1e3 * dt, 1), "levels": len(trace) - 1, "coarsest_n": trace[0][0],
+                       "cut": int(cut), "cut_per_level": [int(c) for _, c in trace],
+                       "max_block_weight": int(bw.max()), "bound": lmax,
+                       "imbalance": round(float(bw.max()) * k / G.total_vwgt - 1.0, 5),
+                       "refine_round_ms_input": round(rms, 3),
+                       "refine_round_edges_per_s": G.two_m / (rms / 1e3) if rms else None,
+                       "refine_moves_input_from_ip": [int(x) for x in st.moves]}
+        log(f"[partition] k={k}: {1e3 * dt:.0f} ms, {len(trace) - 1} levels (coarsest n={trace[0][0]}), "
+            f"cut {cut} ({cut / (G.two_m // 2):.3f} of m), max block {int(bw.max())} / bound {lmax}, "
+            f"refinement round {rms:.2f} ms")
+    return out
+
+
 def bench_quality(args) -> dict:
     """Coarsening quality of plain synchronous rounds (S = 1) and of S
     sub-rounds per round, on geometric graphs where synchronous moves stall:
@@ -432,6 +479,8 @@ def main() -> int:
     ap.add_argument("--subrounds", default="1,2,4", help="sub-round counts compared by the subrounds form")
     ap.add_argument("--serve-split", type=int, default=0,
                     help="directed edges from which a job runs in the big-job lane (0: one lane)")
+    ap.add_argument("--partition-k", default="64", help="block counts of the partition form")
+    ap.add_argument("--partition-graph", default="rmat", choices=["rmat", "rgg2d"])
     ap.add_argument("--coarsen-graph", default="rmat", choices=["rmat", "rgg3d"])
     ap.add_argument("--coarsen-subrounds", type=int, default=1, help="sub-rounds per LP round in the coarsening")
     ap.add_argument("--coarsen-scale", type=int, default=26)
@@ -486,6 +535,16 @@ def main() -> int:
                           "value": res[max(res, key=int)]["coarsening"]["cut_of_hierarchy"], "unit": "edges",
                           "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "int32",
                           "config": {"workload": "rmat-s24-ef16, cap 256, 5 rounds"}, "subrounds": res}))
+        return 0
+    if args.workload == "partition":
+        res = bench_partition(args)
+        top = res[max(res, key=int)]
+        print(json.dumps({"metric": "multilevel k-way partition time and cut", "value": top["ms"], "unit": "ms",
+                          "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "int32",
+                          "config": {"workload": ("rgg2d n=2^24 avg-deg~8, cell-ordered"
+                                                  if args.partition_graph == "rgg2d" else "rmat-s24-ef16")
+                                                 + ", eps 3 %, 5 rounds per level"},
+                          "partition": res}))
         return 0
     if args.workload == "serve":
         res = bench_serve(args)
@@ -602,6 +661,7 @@ def main() -> int:
             args.serve_rates = "100,1000"
         forms["served"] = bench_serve(args)["rates"]
         forms["subrounds"] = bench_subrounds(args, G)
+        forms["partition"] = bench_partition(args, G)
 
     out = {
         "metric": "LP-round edges/s",
