@@ -402,3 +402,27 @@ def partition(g, k: int, seed: int = 1, rounds: int = 5, eps_permille: int = 30,
         blocks, _ = lp_refine(fine, blocks, k, lmax, rounds, seed + lvl, refine_subrounds)
         trace.append((fine.n, edge_cut(fine, blocks)))
     return blocks, trace
+
+
+# ------------------------------------------------------------ gain table ----
+
+def affinity(g, blocks, k: int):
+    """Affinities of every vertex to every block (Section V): A[u, b] = total
+    weight of the edges from u to vertices of block b. Dense int64[n, k],
+    by the definition (small graphs only)."""
+    blocks = np.asarray(blocks, dtype=np.int64)
+    deg = np.diff(np.asarray(g.xadj, dtype=np.int64))
+    src = np.repeat(np.arange(g.n, dtype=np.int64), deg)
+    dst = np.asarray(g.adjncy, dtype=np.int64)
+    w = np.ones(g.two_m, dtype=np.int64) if g.adjwgt is None else np.asarray(g.adjwgt, dtype=np.int64)
+    A = np.zeros((g.n, k), dtype=np.int64)
+    np.add.at(A, (src, blocks[dst]), w)
+    return A
+
+
+def move_gains(g, blocks, k: int):
+    """Gain of moving every vertex to every block: A[u, b] - A[u, block(u)]
+    (Section V)."""
+    A = affinity(g, blocks, k)
+    own = A[np.arange(g.n), np.asarray(blocks, dtype=np.int64)]
+    return A - own[:, None]
