@@ -104,6 +104,21 @@ def _ptr(a):
     return None if a is None else a.ctypes.data
 
 
+class _Args:
+    """Converted copies of array arguments, kept alive for one C call (a
+    pointer taken from a temporary copy would dangle once the copy is freed)."""
+
+    def __init__(self):
+        self._keep = []
+
+    def __call__(self, a, dtype):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=dtype)
+        self._keep.append(a)
+        return a.ctypes.data
+
+
 def _arr(a, dtype):
     return None if a is None else np.ascontiguousarray(a, dtype=dtype)
 
@@ -190,11 +205,12 @@ def lp_cluster(g, cap: int, rounds: int, seed: int, subrounds: int = 1):
     """Labels (int32[n]) of synchronous size-constrained LP, plus per-round stats.
     With subrounds = S > 1 every round is split into S sub-rounds over the
     vertices of each sub-round (see orc_lp_cluster_sub)."""
+    A = _Args()
     lib = _load()
     labels = np.empty(max(g.n, 1), dtype=np.int32)
     st = _Stats()
-    rc = lib.orc_lp_cluster_sub(g.n, _ptr(_arr(g.xadj, np.uint64)), _ptr(_arr(g.adjncy, np.int32)),
-                                _ptr(_arr(g.adjwgt, np.int32)), _ptr(_arr(g.vwgt, np.int32)), cap, rounds,
+    rc = lib.orc_lp_cluster_sub(g.n, A(g.xadj, np.uint64), A(g.adjncy, np.int32),
+                                A(g.adjwgt, np.int32), A(g.vwgt, np.int32), cap, rounds,
                                 subrounds, seed, _ptr(labels), ctypes.byref(st))
     if rc != OK:
         raise ValueError(f"orc_lp_cluster: {rc}")
@@ -205,11 +221,12 @@ def lp_cluster(g, cap: int, rounds: int, seed: int, subrounds: int = 1):
 def lp_cluster_async(g, cap: int, rounds: int, seed: int):
     """The paper's asynchronous LP (sequential, random vertex order per round,
     moves applied at once) as a quality reference; labels and per-round moves."""
+    A = _Args()
     lib = _load()
     labels = np.empty(max(g.n, 1), dtype=np.int32)
     st = _Stats()
-    rc = lib.orc_lp_cluster_async(g.n, _ptr(_arr(g.xadj, np.uint64)), _ptr(_arr(g.adjncy, np.int32)),
-                                  _ptr(_arr(g.adjwgt, np.int32)), _ptr(_arr(g.vwgt, np.int32)), cap, rounds,
+    rc = lib.orc_lp_cluster_async(g.n, A(g.xadj, np.uint64), A(g.adjncy, np.int32),
+                                  A(g.adjwgt, np.int32), A(g.vwgt, np.int32), cap, rounds,
                                   seed, _ptr(labels), ctypes.byref(st))
     if rc != OK:
         raise ValueError(f"orc_lp_cluster_async: {rc}")
@@ -219,14 +236,15 @@ def lp_cluster_async(g, cap: int, rounds: int, seed: int):
 
 def lp_proposals(g, C0, W0, cap: int, seed: int, rnd: int, vertices):
     """Best move (target or -1, gain) of each listed vertex under snapshot (C0, W0)."""
+    A = _Args()
     lib = _load()
     vertices = _arr(vertices, np.int32)
     tgt = np.empty(len(vertices), dtype=np.int32)
     gain = np.empty(len(vertices), dtype=np.int64)
     C0 = _arr(C0, np.int32)
     W0 = _arr(W0, np.int64)
-    rc = lib.orc_lp_proposals(g.n, _ptr(_arr(g.xadj, np.uint64)), _ptr(_arr(g.adjncy, np.int32)),
-                              _ptr(_arr(g.adjwgt, np.int32)), _ptr(_arr(g.vwgt, np.int32)), _ptr(C0),
+    rc = lib.orc_lp_proposals(g.n, A(g.xadj, np.uint64), A(g.adjncy, np.int32),
+                              A(g.adjwgt, np.int32), A(g.vwgt, np.int32), _ptr(C0),
                               _ptr(W0), cap, seed, rnd, len(vertices), _ptr(vertices), _ptr(tgt),
                               _ptr(gain))
     if rc != OK:
@@ -249,13 +267,14 @@ class Coarse:
 
 def contract(g, labels):
     """(coarse graph, map int32[n]); raises OverflowError on a coarse weight > INT32_MAX."""
+    A = _Args()
     lib = _load()
     labels = _arr(labels, np.int32)
     m = np.empty(max(g.n, 1), dtype=np.int32)
     nc = ctypes.c_int32(0)
     px, pa, pw, pv = _P(), _P(), _P(), _P()
-    rc = lib.orc_contract(g.n, _ptr(_arr(g.xadj, np.uint64)), _ptr(_arr(g.adjncy, np.int32)),
-                          _ptr(_arr(g.adjwgt, np.int32)), _ptr(_arr(g.vwgt, np.int32)), _ptr(labels),
+    rc = lib.orc_contract(g.n, A(g.xadj, np.uint64), A(g.adjncy, np.int32),
+                          A(g.adjwgt, np.int32), A(g.vwgt, np.int32), _ptr(labels),
                           ctypes.byref(nc), ctypes.byref(px), ctypes.byref(pa), ctypes.byref(pw),
                           ctypes.byref(pv), _ptr(m))
     if rc == EINVAL:
@@ -280,9 +299,10 @@ def contract(g, labels):
 
 
 def edge_cut(g, labels) -> int:
+    A = _Args()
     lib = _load()
-    return int(lib.orc_edge_cut(g.n, _ptr(_arr(g.xadj, np.uint64)), _ptr(_arr(g.adjncy, np.int32)),
-                                _ptr(_arr(g.adjwgt, np.int32)), _ptr(_arr(labels, np.int32))))
+    return int(lib.orc_edge_cut(g.n, A(g.xadj, np.uint64), A(g.adjncy, np.int32),
+                                A(g.adjwgt, np.int32), A(labels, np.int32)))
 
 
 # ----------------------------------------------------------- coarsening ----
@@ -343,8 +363,9 @@ def partition_cap(n0: int, total_weight: int, k: int, eps_permille: int = 30) ->
 
 def initial_partition(g, k: int):
     """Contiguous-weight initial partition (see orc_initial_partition)."""
+    A = _Args()
     labels = np.empty(max(g.n, 1), dtype=np.int32)
-    rc = _load().orc_initial_partition(g.n, _ptr(_arr(g.vwgt, np.int32)), k, _ptr(labels))
+    rc = _load().orc_initial_partition(g.n, A(g.vwgt, np.int32), k, _ptr(labels))
     if rc != OK:
         raise ValueError(f"orc_initial_partition: {rc}")
     return labels[: g.n]
@@ -353,13 +374,14 @@ def initial_partition(g, k: int):
 def lp_refine(g, blocks, k: int, max_weight: int, rounds: int, seed: int, subrounds: int = 1):
     """Refined blocks (int32[n]) and per-round stats: synchronous
     size-constrained LP started from `blocks` (see orc_lp_refine)."""
+    A = _Args()
     lib = _load()
     labels = np.array(blocks, dtype=np.int32, copy=True)
     if labels.size == 0:
         labels = np.zeros(1, dtype=np.int32)
     st = _Stats()
-    rc = lib.orc_lp_refine(g.n, _ptr(_arr(g.xadj, np.uint64)), _ptr(_arr(g.adjncy, np.int32)),
-                           _ptr(_arr(g.adjwgt, np.int32)), _ptr(_arr(g.vwgt, np.int32)), k, max_weight, rounds,
+    rc = lib.orc_lp_refine(g.n, A(g.xadj, np.uint64), A(g.adjncy, np.int32),
+                           A(g.adjwgt, np.int32), A(g.vwgt, np.int32), k, max_weight, rounds,
                            subrounds, seed, _ptr(labels), ctypes.byref(st))
     if rc != OK:
         raise ValueError(f"orc_lp_refine: {rc}")
