@@ -338,19 +338,35 @@ def bench_partition(args, G=None) -> dict:
         dt = time.perf_counter() - t
         cut = lp.lp_edge_cut(G, blocks)
         bw = torch.bincount(blocks.to(torch.int64), minlength=k)
+        # the same partition with every refinement rated from a sparse gain table
+        blocks_gt = lp.partition(G, k, seed=1, rounds=args.rounds, gain_table=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        blocks_gt = lp.partition(G, k, seed=1, rounds=args.rounds, gain_table=True)
+        torch.cuda.synchronize()
+        dt_gt = time.perf_counter() - t
+        same = bool(torch.equal(blocks_gt, blocks))
+        # refinement of the input graph from its contiguous split, rated from
+        # the graph and from the gain table (built in the call's setup)
         ip = lp.lp_initial_partition(G, k)
-        _, st = lp.lp_refine(G, ip, k, lmax, args.rounds, 1, config=dict(timing=1), stats=True)
-        rms = st.phase_ms["round"] / max(1, st.phase_launches["round"])
-        out[str(k)] = {"ms": round(1e3 * dt, 1), "levels": len(trace) - 1, "coarsest_n": trace[0][0],
+        ref = {}
+        for name, cfg in (("graph", dict(timing=1)), ("gain_table", dict(timing=1, gain_table=1))):
+            lp.lp_refine(G, ip, k, lmax, args.rounds, 1, config=cfg)
+            torch.cuda.synchronize()
+            _, st = lp.lp_refine(G, ip, k, lmax, args.rounds, 1, config=cfg, stats=True)
+            rms = st.phase_ms["round"] / max(1, st.phase_launches["round"])
+            ref[name] = {"round_ms": round(rms, 3), "setup_ms": round(st.phase_ms["setup"], 3),
+                         "moves": [int(x) for x in st.moves]}
+        out[str(k)] = {"ms": round(1e3 * dt, 1), "ms_gain_table": round(1e3 * dt_gt, 1), "identical_blocks": same,
+                       "levels": len(trace) - 1, "coarsest_n": trace[0][0],
                        "cut": int(cut), "cut_per_level": [int(c) for _, c in trace],
                        "max_block_weight": int(bw.max()), "bound": lmax,
                        "imbalance": round(float(bw.max()) * k / G.total_vwgt - 1.0, 5),
-                       "refine_round_ms_input": round(rms, 3),
-                       "refine_round_edges_per_s": G.two_m / (rms / 1e3) if rms else None,
-                       "refine_moves_input_from_ip": [int(x) for x in st.moves]}
-        log(f"[partition] k={k}: {1e3 * dt:.0f} ms, {len(trace) - 1} levels (coarsest n={trace[0][0]}), "
-            f"cut {cut} ({cut / (G.two_m // 2):.3f} of m), max block {int(bw.max())} / bound {lmax}, "
-            f"refinement round {rms:.2f} ms")
+                       "refine_input_from_ip": ref}
+        log(f"[partition] k={k}: {1e3 * dt:.0f} ms ({1e3 * dt_gt:.0f} ms with gain tables, identical {same}), "
+            f"{len(trace) - 1} levels (coarsest n={trace[0][0]}), cut {cut} ({cut / (G.two_m // 2):.3f} of m), "
+            f"max block {int(bw.max())} / bound {lmax}, refinement round {ref['graph']['round_ms']:.2f} ms "
+            f"(gain table {ref['gain_table']['round_ms']:.2f} ms after {ref['gain_table']['setup_ms']:.1f} ms setup)")
     return out
 
 
@@ -681,7 +697,8 @@ def main() -> int:
                    "step": "lp_cluster + lp_contract + lp_edge_cut"},
         "lp_round_edges_per_s": lp_round_rate,
         "round_model": {"alg_bytes": int(round_bytes), "ms": round(round_ms, 4),
-                        "frac_hbm": round(round_bytes / (round_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if round_ms else None},
+                        "frac_hbm": (round(round_bytes / (round_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                                     if round_ms else None)},
         "phases": phases,
         "setup_ms": round(st.phase_ms["setup"], 3),
         "step_split_ms": {k: round(1e3 * v / args.steps, 2) for k, v in split.items()},

@@ -160,6 +160,8 @@ typedef struct {
   int32_t hub_part;  /* target edges per hub partition, 256..8192, default 2048 */
   int32_t timing;    /* nonzero: time each phase with HIP events (stats must be given) */
   int32_t subrounds; /* sub-rounds per round, 1..64, default 1 (plain synchronous rounds) */
+  int32_t gain_table; /* lp_refine only: nonzero rates from a sparse gain table (see lp_gain_table);
+                         result-invariant; lp_cluster rejects it (LP_EINVAL) */
 } lp_config;
 
 /* Phases timed when lp_config.timing is set (milliseconds summed over rounds). */
@@ -332,6 +334,47 @@ lp_status lp_refine(const lp_graph *g, int32_t k, int64_t max_block_weight, int3
 /* lp_refine with knobs and optional statistics, as lp_cluster_ex. */
 lp_status lp_refine_ex(const lp_graph *g, int32_t k, int64_t max_block_weight, int32_t rounds, uint64_t seed,
                        int32_t *labels_dev, const lp_config *cfg, lp_cluster_stats *stats, void *stream);
+
+/*
+ * Sparse gain table (Section V): the affinity omega(u, b) of every vertex u
+ * to every block b, i.e. the total weight of u's edges into b, kept in O(m)
+ * memory. A vertex whose hash slice (pow2(2 deg(u)) slots of (block,
+ * affinity)) would hold at least k slots keeps a dense row of k affinities
+ * instead; affinities are int32 unless a weighted degree needs int64. The
+ * gain of moving u to b is omega(u, b) - omega(u, block(u)). lp_refine with
+ * lp_config.gain_table set builds one per call and rates from it, updating
+ * it after every round instead of decoding every neighbourhood again.
+ *
+ * lp_gain_table_create — builds the table of `g` (single graph) for the
+ * partition blocks_dev (int32[n] in [0, k), 1 <= k <= n; copied). The table
+ * refers to g, which must outlive it. Synchronises `stream` (block check and
+ * sizing). Errors: LP_EINVAL (bad k, a block out of range), LP_ENOMEM.
+ */
+typedef struct lp_gain_table lp_gain_table;
+lp_status lp_gain_table_create(const lp_graph *g, const int32_t *blocks_dev, int32_t k, void *stream,
+                               lp_gain_table **out);
+
+/* Affinities of count (vertex, block) pairs (device arrays) into out_dev
+ * int64[count]; -1 for a pair out of range. */
+lp_status lp_gain_table_affinity(const lp_gain_table *t, int64_t count, const int32_t *vertices_dev,
+                                 const int32_t *blocks_dev, int64_t *out_dev, void *stream);
+
+/* Moves count distinct vertices to the given blocks at once (device arrays)
+ * and updates the affinities of their neighbours. Synchronises `stream` to
+ * check the batch. Errors: LP_EINVAL (a vertex or block out of range, a
+ * vertex listed twice, count > n); nothing is changed then. */
+lp_status lp_gain_table_move(lp_gain_table *t, int64_t count, const int32_t *vertices_dev, const int32_t *to_dev,
+                             void *stream);
+
+/* Slots over all slices, device bytes held, the number of missing entries
+ * met by updates (0 unless the table is corrupt), and the number of slices
+ * rebuilt so far because stale zero entries had filled them (outputs may
+ * be NULL; synchronises when either count is asked for). */
+lp_status lp_gain_table_info(const lp_gain_table *t, uint64_t *entries, uint64_t *bytes, int64_t *missing,
+                             int64_t *rebuilds);
+
+/* Frees a table (NULL is ignored), in its stream's order. */
+void lp_gain_table_free(lp_gain_table *t);
 
 /* Returns every block of the library's memory cache to HIP, on every device
  * (waiting for each device to be idle first). Handles stay valid; later calls

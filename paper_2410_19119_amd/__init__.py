@@ -42,7 +42,7 @@ PHASES = ("setup", "lane", "tile", "block", "hub", "accept", "round")
 class lp_config(ctypes.Structure):
     _fields_ = [("t_lane", ctypes.c_int32), ("t_tile", ctypes.c_int32),
                 ("t_block", ctypes.c_int32), ("hub_part", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("subrounds", ctypes.c_int32)]
+                ("subrounds", ctypes.c_int32), ("gain_table", ctypes.c_int32)]
 
 
 class lp_cluster_stats(ctypes.Structure):
@@ -116,6 +116,17 @@ def _load():
     lib.lp_refine_ex.argtypes = [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, _P,
                                  ctypes.POINTER(lp_config), ctypes.POINTER(lp_cluster_stats), _P]
     lib.lp_refine_ex.restype = S
+    lib.lp_gain_table_create.argtypes = [_P, _P, ctypes.c_int32, _P, ctypes.POINTER(_P)]
+    lib.lp_gain_table_create.restype = S
+    lib.lp_gain_table_affinity.argtypes = [_P, ctypes.c_int64, _P, _P, _P, _P]
+    lib.lp_gain_table_affinity.restype = S
+    lib.lp_gain_table_move.argtypes = [_P, ctypes.c_int64, _P, _P, _P]
+    lib.lp_gain_table_move.restype = S
+    lib.lp_gain_table_info.argtypes = [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.lp_gain_table_info.restype = S
+    lib.lp_gain_table_free.argtypes = [_P]
+    lib.lp_gain_table_free.restype = None
     _lib = lib
     return lib
 
@@ -125,7 +136,8 @@ def exported_symbols() -> list[str]:
             "lp_graph_export", "lp_decompress", "lp_cluster", "lp_cluster_ex", "lp_contract",
             "lp_edge_cut", "lp_graph_free", "lp_batch_create", "lp_batch_info", "lp_batch_cluster_ex",
             "lp_batch_cluster", "lp_trim_memory", "lp_initial_partition", "lp_project", "lp_refine",
-            "lp_refine_ex"]
+            "lp_refine_ex", "lp_gain_table_create", "lp_gain_table_affinity", "lp_gain_table_move",
+            "lp_gain_table_info", "lp_gain_table_free"]
 
 
 def _check(st: int, where: str) -> None:
@@ -452,18 +464,20 @@ def lp_refine(g: Graph, blocks, k: int, max_block_weight: int, rounds: int = 5, 
 
 
 def partition(g: Graph, k: int, seed: int = 1, rounds: int = 5, eps_permille: int = 30, subrounds: int = 1,
-              refine_subrounds: int = 1, stream=None, trace: bool = False):
+              refine_subrounds: int = 1, gain_table: bool = False, stream=None, trace: bool = False):
     """Multilevel k-way partition (Section II-A), all steps on the device:
     coarsen with LP clustering under partition_cap, partition the coarsest
     graph (lp_initial_partition, then lp_refine there), then project to each
     finer level and refine it; level l (0 = the input) refines with seed + l.
     Returns the blocks of g (int32 device tensor); with trace=True also the
-    list of (n, cut after refinement) from the coarsest level to g."""
+    list of (n, cut after refinement) from the coarsest level to g. With
+    gain_table=True every refinement rates from a sparse gain table (same
+    result)."""
     cap = partition_cap(g.n, g.total_vwgt, k, eps_permille)
     lmax = max_block_weight(g.total_vwgt, k, eps_permille)
     n_target, _ = coarsen_params(g.n, g.total_vwgt)
     cfg = dict(subrounds=subrounds) if subrounds > 1 else None
-    rcfg = dict(subrounds=refine_subrounds) if refine_subrounds > 1 else None
+    rcfg = dict(subrounds=refine_subrounds, gain_table=int(bool(gain_table)))
     levels = []
     cur = g
     while len(levels) < 32 and cur.n > n_target:
@@ -486,3 +500,54 @@ def partition(g: Graph, k: int, seed: int = 1, rounds: int = 5, eps_permille: in
         if trace:
             steps.append((fine.n, lp_edge_cut(fine, blocks, stream=stream)))
     return (blocks, steps) if trace else blocks
+
+
+class GainTable:
+    """Owns an ``lp_gain_table``: the affinity of every vertex to every block
+    adjacent to it (Section V), for a partition of `g` into k blocks."""
+
+    def __init__(self, g: Graph, blocks, k: int, stream=None):
+        torch = _torch()
+        b = _dev(blocks, torch.int32)
+        h = _P()
+        _check(_load().lp_gain_table_create(g.handle, _ptr(b), int(k), _stream(stream), ctypes.byref(h)),
+               "lp_gain_table_create")
+        self._h = h
+        self.g = g
+        self.k = int(k)
+
+    def affinity(self, vertices, blocks, stream=None):
+        """int64 device tensor of the affinities of the (vertex, block) pairs."""
+        torch = _torch()
+        v = _dev(vertices, torch.int32)
+        b = _dev(blocks, torch.int32)
+        out = torch.empty(max(int(v.numel()), 1), dtype=torch.int64, device="cuda")
+        _check(_load().lp_gain_table_affinity(self._h, int(v.numel()), _ptr(v), _ptr(b), _ptr(out),
+                                              _stream(stream)), "lp_gain_table_affinity")
+        return out[: v.numel()]
+
+    def move(self, vertices, to, stream=None) -> None:
+        """Moves distinct vertices to new blocks at once."""
+        torch = _torch()
+        v = _dev(vertices, torch.int32)
+        t = _dev(to, torch.int32)
+        _check(_load().lp_gain_table_move(self._h, int(v.numel()), _ptr(v), _ptr(t), _stream(stream)),
+               "lp_gain_table_move")
+
+    def info(self):
+        """(slots, device bytes, missing entries met by updates, slices rebuilt)."""
+        e, b, m, r = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(_load().lp_gain_table_info(self._h, ctypes.byref(e), ctypes.byref(b), ctypes.byref(m),
+                                          ctypes.byref(r)), "lp_gain_table_info")
+        return e.value, b.value, m.value, r.value
+
+    def free(self) -> None:
+        if self._h is not None and _lib is not None:
+            _lib.lp_gain_table_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

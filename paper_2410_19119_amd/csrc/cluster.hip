@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "decode.h"
+#include "gain.h"
 #include "graph.h"
 
 namespace lp {
@@ -1544,16 +1545,20 @@ __global__ void k_admit(const uint32_t* seg, const int64_t* prefix, const uint32
 // the prefix at the last admitted one: one atomic per target, not per move.
 __global__ __launch_bounds__(256) void k_apply(const uint32_t* seg, const uint32_t* vals, const uint8_t* flag,
                                                const int64_t* wv, const int64_t* prefix, const uint32_t* count,
-                                               int32_t* C, int64_t* W, int64_t* stats, int round) {
+                                               int32_t* C, int64_t* W, int64_t* stats, int round, int4* mv) {
   __shared__ int64_t sm[4];
   const int64_t n = *count;
   int64_t moves = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    if (!flag[i]) continue;
+    if (!flag[i]) {
+      if (mv) mv[i] = make_int4(-1, 0, 0, 0);
+      continue;
+    }
     const int32_t u = (int32_t)vals[i];
     const int32_t t = (int32_t)seg[i];
     const int32_t old = C[u];
     C[u] = t;
+    if (mv) mv[i] = make_int4(u, old, t, 0);
     if (i + 1 == n || seg[i + 1] != (uint32_t)t || !flag[i + 1])
       atomicAdd((unsigned long long*)&W[t], (unsigned long long)prefix[i]);
     atomicAdd((unsigned long long*)&W[old], (unsigned long long)(-wv[i]));
@@ -2127,6 +2132,8 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
   const bool wide = g->max_wdeg > 0x7FFFFFFFll;
   int32_t t_lane = 16, t_tile = kTileMaxDeg, t_block = TileLarge::kEdges, hub_part = kDefaultHubPart;
   int32_t S = 1;  // sub-rounds per round (this one changes the result)
+  const bool use_gt = cfg_in && cfg_in->gain_table;  // refinement only: rate from a gain table
+  if (use_gt && init_k == 0) return LP_EINVAL;
   if (cfg_in) {
     if (cfg_in->t_lane) t_lane = cfg_in->t_lane;
     if (cfg_in->t_tile) t_tile = cfg_in->t_tile;
@@ -2158,6 +2165,7 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
   int64_t* wv = sc.alloc<int64_t>(n);
   int64_t* pref = sc.alloc<int64_t>(n);
   uint8_t* flag = sc.alloc<uint8_t>(n);
+  int4* mv = use_gt ? sc.alloc<int4>(n) : nullptr;
   const unsigned ncp = grid_for(n, kCpTile, 0x7FFFFFFF);
   uint32_t* pcnt = sc.alloc<uint32_t>(ncp);
   // per sub-round: hand-out counters of the small tiles, large tiles and pieces
@@ -2250,6 +2258,13 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
     if (sc.failed) return LP_ENOMEM;
   }
 
+  struct GtGuard {
+    GainTable t;
+    hipStream_t s;
+    ~GtGuard() {
+      if (t.off) gt_release(&t, s);
+    }
+  } gt{GainTable{}, s};
   if (init_k > 0) {
     LP_CHECK_HIP(hipMemsetAsync(W, 0, (size_t)n * sizeof(int64_t), s));
     hipLaunchKernelGGL(k_init_blocks, dim3(grid_for(n, 256, 512)), dim3(256), 0, s, n, g->vwgt, labels, init_k, W,
@@ -2259,6 +2274,7 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
     LP_CHECK_HIP(hipMemcpyAsync(&bad, &ctl->bad, sizeof(bad), hipMemcpyDeviceToHost, s));
     LP_CHECK_HIP(hipStreamSynchronize(s));
     if (bad) return LP_EINVAL;
+    if (use_gt) LP_CHECK(gt_create(g, labels, init_k, s, &gt.t));
   } else {
     hipLaunchKernelGGL(k_init, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, g->vwgt, labels, W, ptgt);
     LP_CHECK_LAUNCH();
@@ -2309,54 +2325,64 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
       // rating (all buckets) -> ptgt / pgain. The hub pieces run first, alone:
       // they are the head of the longest chain (pieces, then their reduction),
       // which then overlaps with the tiles and lanes on the side streams.
-      if (H > 0) {
+      // With a gain table the ratings are the table's affinities instead.
+      if (use_gt) {
+        const GtRound gr{labels, W, g->vwgt, cap, seed, (uint32_t)r, ptgt, pgain, &ctl->done};
+        LP_CHECK(begin(LP_PHASE_TILE));
+        LP_CHECK(gt_select(gt.t, gr, plan->order + plan->bstart[0], bn[0], plan->order + plan->bstart[1],
+                           bn[1] + bn[2] + bn[3], s));
+        LP_CHECK(end());
+      }
+      if (!use_gt && H > 0) {
         LP_CHECK(begin(LP_PHASE_HUB));
         LP_CHECK(launch_piece(g->compressed, wide, x, hm, npieces, hand_r + 16, piece_layout, piece_lds, s));
       }
-      LP_CHECK_HIP(hipEventRecord(ev.e[3], s));
-      for (int i = 0; i < 3; ++i) LP_CHECK_HIP(hipStreamWaitEvent(side[i], ev.e[3], 0));
-      if (H > 0) {
-        hipStream_t hs = side[0];
-        if (wide)
-          hipLaunchKernelGGL(k_hub_reduce<int64_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads),
-                             (size_t)kHubTable * 12 + sizeof(HubReduceSmem), hs, x, hm, ntasks);
-        else
-          hipLaunchKernelGGL(k_hub_reduce<int32_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads),
-                             (size_t)kHubTable * 8 + sizeof(HubReduceSmem), hs, x, hm, ntasks);
-        LP_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_hub_combine, dim3(grid_for(H, 4)), dim3(256), 0, hs, x, hm, H);
-        LP_CHECK_LAUNCH();
-        LP_CHECK(end(hs));
-      }
-      if (bn[2] > 0) {
-        LP_CHECK(begin(LP_PHASE_BLOCK, side[1]));
-        LP_CHECK(launch_tile_any<TileLarge>(g->compressed, rate_width(g), x, vd_of(2), tpl.tiles, tpl.ntiles,
-                                            hand_r + 8, tpl.grid,
-                                            g->weighted, side[1]));
-        LP_CHECK(end(side[1]));
-      }
-      if (bn[0] > 0) {
-        LP_CHECK(begin(LP_PHASE_LANE, side[2]));
-        if (g->compressed)
-          hipLaunchKernelGGL(k_rate_lane<true>, dim3(grid_for(bn[0], 256)), dim3(256), 0, side[2], x, vd_of(0),
-                             bn[0]);
-        else
-          hipLaunchKernelGGL(k_rate_lane<false>, dim3(grid_for(bn[0], 256)), dim3(256), 0, side[2], x, vd_of(0),
-                             bn[0]);
-        LP_CHECK_LAUNCH();
-        LP_CHECK(end(side[2]));
-      }
-      if (bn[1] > 0) {
-        LP_CHECK(begin(LP_PHASE_TILE));
-        LP_CHECK(launch_tile_any<TileSmall>(g->compressed, rate_width(g), x, vd_of(1), tps.tiles, tps.ntiles,
-                                            hand_r, tps.grid,
-                                            g->weighted, s));
-        LP_CHECK(end());
-      }
-      // join
-      for (int i = 0; i < 3; ++i) {
-        LP_CHECK_HIP(hipEventRecord(ev.e[i], side[i]));
-        LP_CHECK_HIP(hipStreamWaitEvent(s, ev.e[i], 0));
+      if (!use_gt) {
+        LP_CHECK_HIP(hipEventRecord(ev.e[3], s));
+        for (int i = 0; i < 3; ++i) LP_CHECK_HIP(hipStreamWaitEvent(side[i], ev.e[3], 0));
+        if (H > 0) {
+          hipStream_t hs = side[0];
+          if (wide)
+            hipLaunchKernelGGL(k_hub_reduce<int64_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads),
+                               (size_t)kHubTable * 12 + sizeof(HubReduceSmem), hs, x, hm, ntasks);
+          else
+            hipLaunchKernelGGL(k_hub_reduce<int32_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads),
+                               (size_t)kHubTable * 8 + sizeof(HubReduceSmem), hs, x, hm, ntasks);
+          LP_CHECK_LAUNCH();
+          hipLaunchKernelGGL(k_hub_combine, dim3(grid_for(H, 4)), dim3(256), 0, hs, x, hm, H);
+          LP_CHECK_LAUNCH();
+          LP_CHECK(end(hs));
+        }
+        if (bn[2] > 0) {
+          LP_CHECK(begin(LP_PHASE_BLOCK, side[1]));
+          LP_CHECK(launch_tile_any<TileLarge>(g->compressed, rate_width(g), x, vd_of(2), tpl.tiles, tpl.ntiles,
+                                              hand_r + 8, tpl.grid,
+                                              g->weighted, side[1]));
+          LP_CHECK(end(side[1]));
+        }
+        if (bn[0] > 0) {
+          LP_CHECK(begin(LP_PHASE_LANE, side[2]));
+          if (g->compressed)
+            hipLaunchKernelGGL(k_rate_lane<true>, dim3(grid_for(bn[0], 256)), dim3(256), 0, side[2], x, vd_of(0),
+                               bn[0]);
+          else
+            hipLaunchKernelGGL(k_rate_lane<false>, dim3(grid_for(bn[0], 256)), dim3(256), 0, side[2], x, vd_of(0),
+                               bn[0]);
+          LP_CHECK_LAUNCH();
+          LP_CHECK(end(side[2]));
+        }
+        if (bn[1] > 0) {
+          LP_CHECK(begin(LP_PHASE_TILE));
+          LP_CHECK(launch_tile_any<TileSmall>(g->compressed, rate_width(g), x, vd_of(1), tps.tiles, tps.ntiles,
+                                              hand_r, tps.grid,
+                                              g->weighted, s));
+          LP_CHECK(end());
+        }
+        // join
+        for (int i = 0; i < 3; ++i) {
+          LP_CHECK_HIP(hipEventRecord(ev.e[i], side[i]));
+          LP_CHECK_HIP(hipStreamWaitEvent(s, ev.e[i], 0));
+        }
       }
       // acceptance: compact in vertex order, sort by (target, gain desc)
       LP_CHECK(begin(LP_PHASE_ACCEPT));
@@ -2375,8 +2401,9 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
       hipLaunchKernelGGL(k_admit, dim3(ga), dim3(256), 0, s, seg, pref, &ctl->count, W, cap, x.gid, gcap, flag);
       LP_CHECK_LAUNCH();
       hipLaunchKernelGGL(k_apply, dim3(ga), dim3(256), 0, s, seg, vs, flag, wv, pref, &ctl->count, labels, W,
-                         ctl->stats, r);
+                         ctl->stats, r, mv);
       LP_CHECK_LAUNCH();
+      if (use_gt) LP_CHECK(gt_update(gt.t, mv, &ctl->count, n, labels, s));
       hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, s, &ctl->count, &ctl->done, ctl->stats, r, &ctl->rounds_run,
                          &ctl->round_props, sr == S - 1 ? 1 : 0);
       LP_CHECK_LAUNCH();

@@ -3,7 +3,7 @@ initial partition, projection through a contraction, size-constrained LP
 refinement (labels and per-round statistics, on graphs that reach every
 rating path, plain and compressed, with sub-rounds), the multilevel k-way
 partition driver, argument errors, and refinement at the benchmark's full
-size (R-MAT scale 24, k = 64)."""
+size (R-MAT scale 24, k = 64, rated from the graph and from a gain table)."""
 import dataclasses
 
 import numpy as np
@@ -158,4 +158,8 @@ def test_refine_full_size(lp, oracle_mod, rmat24):
     assert np.array_equal(_np(got), exp)
     assert st.proposals == ost.proposals and st.moves == ost.moves
     assert lp.lp_edge_cut(G, got) == oracle_mod.edge_cut(g, exp)
+    # rated from the sparse gain table instead
+    got, st = lp.lp_refine(G, start, k, lmax, 5, 1, config=dict(gain_table=1), stats=True)
+    assert np.array_equal(_np(got), exp)
+    assert st.proposals == ost.proposals and st.moves == ost.moves
     G.free()
