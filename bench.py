@@ -354,9 +354,15 @@ def bench_partition(args, G=None) -> dict:
             lp.lp_refine(G, ip, k, lmax, args.rounds, 1, config=cfg)
             torch.cuda.synchronize()
             _, st = lp.lp_refine(G, ip, k, lmax, args.rounds, 1, config=cfg, stats=True)
-            rms = st.phase_ms["round"] / max(1, st.phase_launches["round"])
-            ref[name] = {"round_ms": round(rms, 3), "setup_ms": round(st.phase_ms["setup"], 3),
-                         "moves": [int(x) for x in st.moves]}
+            nr = max(1, st.phase_launches["round"])
+            rms = st.phase_ms["round"] / nr
+            acc = st.phase_ms["accept"] / nr  # acceptance and moves (and the table update)
+            ref[name] = {"round_ms": round(rms, 3), "rate_ms": round(rms - acc, 3), "accept_ms": round(acc, 3),
+                         "setup_ms": round(st.phase_ms["setup"], 3), "moves": [int(x) for x in st.moves]}
+        T = lp.GainTable(G, ip, k)
+        slots, tbytes, _, _ = T.info()
+        T.free()
+        ref["gain_table"].update({"slots": int(slots), "bytes": int(tbytes), "graph_bytes": int(G.nbytes)})
         out[str(k)] = {"ms": round(1e3 * dt, 1), "ms_gain_table": round(1e3 * dt_gt, 1), "identical_blocks": same,
                        "levels": len(trace) - 1, "coarsest_n": trace[0][0],
                        "cut": int(cut), "cut_per_level": [int(c) for _, c in trace],
@@ -366,7 +372,10 @@ def bench_partition(args, G=None) -> dict:
         log(f"[partition] k={k}: {1e3 * dt:.0f} ms ({1e3 * dt_gt:.0f} ms with gain tables, identical {same}), "
             f"{len(trace) - 1} levels (coarsest n={trace[0][0]}), cut {cut} ({cut / (G.two_m // 2):.3f} of m), "
             f"max block {int(bw.max())} / bound {lmax}, refinement round {ref['graph']['round_ms']:.2f} ms "
-            f"(gain table {ref['gain_table']['round_ms']:.2f} ms after {ref['gain_table']['setup_ms']:.1f} ms setup)")
+            f"(rating {ref['graph']['rate_ms']:.2f}) | gain table {ref['gain_table']['round_ms']:.2f} ms "
+            f"(selection {ref['gain_table']['rate_ms']:.2f}, accept + update {ref['gain_table']['accept_ms']:.2f}) "
+            f"after {ref['gain_table']['setup_ms']:.1f} ms setup; "
+            f"{slots} slots, {tbytes / 1e9:.2f} GB vs {G.nbytes / 1e9:.2f} GB compressed graph)")
     return out
 
 

@@ -28,8 +28,9 @@ struct GainTable {
   void* val = nullptr;        // entries: affinities (int32 or int64)
   uint32_t* flag = nullptr;   // n: overflowed slice / duplicate check
   int32_t* list = nullptr;    // n: overflowed vertices
-  uint32_t* cnt = nullptr;    // [0] overflowed vertices, [1] missing entries, [2] slices rebuilt so far
-  int2* items = nullptr;      // fill work items (vertex, chunk)
+  uint32_t* cnt = nullptr;    // [0] overflowed vertices, [1] missing entries, [2] slices rebuilt so far,
+                              // [3] work items
+  int2* items = nullptr;      // work items of a fill (vertex, chunk) or an update (move, chunk)
   uint64_t nitems_cap = 0;
   uint64_t bytes = 0;
 };

@@ -289,22 +289,46 @@ __global__ __launch_bounds__(256) void k_gt_select_wave(GtView<V> t, GtRound r, 
   }
 }
 
-// Wavefront per move {u, from, to}: every neighbour v of u moves w(u, v)
-// from block `from` to block `to` in its slice. A slice without a free slot
-// for `to` is listed for a rebuild; a missing `from` entry is counted
-// (cnt[1]; never expected).
+// Work items of an update: one per move, one per chunk of a moved vertex
+// above the chunking threshold ({move index, chunk or -1}).
+__global__ __launch_bounds__(256) void k_gt_move_items(const int4* moves, const uint32_t* count, const int32_t* deg,
+                                                       int2* items, uint32_t* nitems) {
+  const int64_t m = *count;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x; b < m; b += stride) {
+    const int64_t i = b + threadIdx.x;
+    uint32_t ni = 0;
+    if (i < m) {
+      const int4 mv = moves[i];
+      if (mv.x >= 0 && mv.y != mv.z) {
+        const uint32_t d = (uint32_t)deg[mv.x];
+        ni = d > (uint32_t)LP_CHUNK_THRESHOLD ? (d + LP_CHUNK_LEN - 1) / LP_CHUNK_LEN : (d > 0 ? 1u : 0u);
+      }
+    }
+    const uint32_t incl = wave_incl_scan_add(ni);
+    uint32_t base = 0;
+    if (lane_id() == kWave - 1 && incl) base = atomicAdd(nitems, incl);
+    base = __shfl(base, kWave - 1, kWave);
+    for (uint32_t j = 0; j < ni; ++j) items[base + incl - ni + j] = make_int2((int)i, ni > 1 ? (int)j : -1);
+  }
+}
+
+// Wavefront per update item of a move {u, from, to}: every neighbour v of u
+// (in the item's chunk) moves w(u, v) from block `from` to block `to` in its
+// slice. A slice without a free slot for `to` is listed for a rebuild; a
+// missing `from` entry is counted (cnt[1]; never expected).
 template <typename V>
 __global__ __launch_bounds__(256) void k_gt_update(GraphView g, const int32_t* deg, const int4* moves,
-                                                   const uint32_t* count, GtView<V> t) {
+                                                   const int2* items, const uint32_t* nitems, GtView<V> t) {
   __shared__ DecodeSmem<kWave> dsm[kGtWaves];
   const int w = threadIdx.x / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  const uint32_t m = *count;
+  const uint32_t m = *nitems;
   for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; i < m; i += nw) {
-    const int4 mv = moves[i];
-    if (mv.x < 0 || mv.y == mv.z) continue;
+    const int2 it = items[i];
+    const int4 mv = moves[it.x];
     const int32_t u = mv.x, from = mv.y, to = mv.z;
-    wave_visit(g, u, (uint32_t)deg[u], -1, dsm[w], [&](int32_t v, int32_t wt) {
+    wave_visit(g, u, (uint32_t)deg[u], it.y, dsm[w], [&](int32_t v, int32_t wt) {
       const int64_t s = gt_slot(t, v, from, false);
       if (s >= 0) gt_atomic_add(&t.val[s], (V)-wt);
       else atomicAdd(&t.cnt[1], 1u);
@@ -355,16 +379,13 @@ lp_status gt_fill(const GainTable& t, const int32_t* blocks, Scratch& sc) {
   LP_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_gt_fill_lane<V>, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, g->view(), t.deg, blocks, v);
   LP_CHECK_LAUNCH();
-  const uint64_t cap = (uint64_t)n + g->two_m / LP_CHUNK_LEN + 1;
-  int2* items = sc.alloc<int2>(cap);
-  uint32_t* nitems = sc.alloc<uint32_t>(1);
-  if (sc.failed) return LP_ENOMEM;
+  uint32_t* nitems = t.cnt + 3;
   hipLaunchKernelGGL(k_gt_zero, dim3(1), dim3(64), 0, s, nitems, (int64_t)1);
   LP_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_gt_items, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, t.deg, n, items, nitems);
+  hipLaunchKernelGGL(k_gt_items, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, t.deg, n, t.items, nitems);
   LP_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_gt_fill_wave<V>, dim3(grid_for(n, 256 / kWave * 8, 16384)), dim3(256), 0, s, g->view(), t.deg,
-                     blocks, items, nitems, v);
+                     blocks, t.items, nitems, v);
   return last_error();
 }
 
@@ -389,8 +410,13 @@ lp_status gt_update_t(const GainTable& t, const int4* moves, const uint32_t* cou
                       const int32_t* blocks, hipStream_t s) {
   const GtView<V> v = view_of<V>(t);
   if (max_moves <= 0) return LP_OK;
+  hipLaunchKernelGGL(k_gt_zero, dim3(1), dim3(64), 0, s, t.cnt + 3, (int64_t)1);
+  LP_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_gt_move_items, dim3(grid_for(max_moves, 256, 16384)), dim3(256), 0, s, moves, count, t.deg,
+                     t.items, t.cnt + 3);
+  LP_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_gt_update<V>, dim3(grid_for(max_moves, kGtWaves, 8192)), dim3(256), 0, s, t.g->view(), t.deg,
-                     moves, count, v);
+                     moves, t.items, t.cnt + 3, v);
   LP_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_gt_rebuild<V>, dim3(256), dim3(256), 0, s, t.g->view(), t.deg, blocks, v);
   LP_CHECK_LAUNCH();
@@ -417,7 +443,9 @@ lp_status gt_create(const lp_graph* g, const int32_t* blocks, int32_t k, hipStre
   t->flag = (uint32_t*)grab((size_t)n * 4);
   t->list = (int32_t*)grab((size_t)n * 4);
   t->cnt = (uint32_t*)grab(4 * 4);
-  if (!t->off || !t->dense || !t->flag || !t->list || !t->cnt) {
+  t->nitems_cap = (uint64_t)n + g->two_m / LP_CHUNK_LEN + 1;
+  t->items = (int2*)grab(t->nitems_cap * sizeof(int2));
+  if (!t->off || !t->dense || !t->flag || !t->list || !t->cnt || !t->items) {
     gt_release(t, s);
     return LP_ENOMEM;
   }
@@ -443,7 +471,8 @@ lp_status gt_create(const lp_graph* g, const int32_t* blocks, int32_t k, hipStre
 }
 
 void gt_release(GainTable* t, hipStream_t s) {
-  for (void* p : {(void*)t->off, (void*)t->dense, (void*)t->flag, (void*)t->list, (void*)t->cnt, (void*)t->key, t->val})
+  for (void* p : {(void*)t->off, (void*)t->dense, (void*)t->flag, (void*)t->list, (void*)t->cnt, (void*)t->key, t->val,
+                  (void*)t->items})
     if (p) cache_free(p, s);
   *t = GainTable{};
 }
