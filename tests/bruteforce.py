@@ -3,8 +3,8 @@
 These are deliberately written differently from the oracle: ratings are a
 dense table over every cluster ID, computed from an edge list, and every
 property is checked by enumeration. They check the rules of the synchronous
-size-constrained label propagation (paper Section IV-A) and of contraction
-(Section IV-B) as stated in the design doc's reading of the paper.
+size-constrained label propagation (paper Section IV-A, read as rounds over a
+snapshot with prefix admission per target) and of contraction (Section IV-B).
 """
 from __future__ import annotations
 

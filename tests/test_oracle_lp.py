@@ -1,5 +1,5 @@
-"""Pins of the oracle's label propagation (paper Section IV-A, synchronous
-rounds; readings in the design doc): closed forms, brute-force enumeration of the
+"""Pins of the oracle's label propagation (paper Section IV-A, read as
+synchronous rounds over a snapshot): closed forms, brute-force enumeration of the
 per-round rule on tiny graphs, exhaustive small graphs, and thread-count
 invariance."""
 import itertools
