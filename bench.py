@@ -59,6 +59,7 @@ def workload(name: str):
 TRAFFIC_SOURCES = ("paper_2410_19119_amd/csrc/cluster.hip", "paper_2410_19119_amd/csrc/decode.h",
                    "paper_2410_19119_amd/csrc/lp_device.h", "paper_2410_19119_amd/csrc/lp_common.h")
 TRAFFIC_FILE = "profiles/rmat24_small_tile_hbm_traffic.md"
+ROUND_TRAFFIC_FILE = "profiles/rmat24_round_hbm_traffic.md"
 
 
 def kernel_source_hash() -> str:
@@ -70,11 +71,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed PMC
-    summary, or None when it is missing or the kernel sources changed since
-    the counters were taken."""
-    path = os.path.join(ROOT, TRAFFIC_FILE)
+def measured_traffic(path: str = TRAFFIC_FILE, key: str = "hbm_bytes_per_launch"):
+    """HBM bytes from a committed PMC summary (per launch of the dominant
+    kernel, or per LP round), or None when it is missing or the kernel
+    sources changed since the counters were taken."""
+    path = os.path.join(ROOT, path)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -86,7 +87,7 @@ def measured_traffic():
     if vals.get("source_hash") != kernel_source_hash():
         return None
     try:
-        return int(vals["hbm_bytes_per_launch"])
+        return int(vals[key])
     except (KeyError, ValueError):
         return None
 
@@ -688,6 +689,7 @@ def main() -> int:
         forms["subrounds"] = bench_subrounds(args, G)
         forms["partition"] = bench_partition(args, G)
 
+    round_traffic = measured_traffic(ROUND_TRAFFIC_FILE, "round_bytes") if args.workload == "rmat24" else None
     out = {
         "metric": "LP-round edges/s",
         "value": value,
@@ -707,7 +709,10 @@ def main() -> int:
         "lp_round_edges_per_s": lp_round_rate,
         "round_model": {"alg_bytes": int(round_bytes), "ms": round(round_ms, 4),
                         "frac_hbm": (round(round_bytes / (round_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
-                                     if round_ms else None)},
+                                     if round_ms else None),
+                        "traffic": round_traffic,
+                        "frac_hbm_traffic": (round(round_traffic / (round_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                                             if round_ms and round_traffic else None)},
         "phases": phases,
         "setup_ms": round(st.phase_ms["setup"], 3),
         "step_split_ms": {k: round(1e3 * v / args.steps, 2) for k, v in split.items()},
