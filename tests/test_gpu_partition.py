@@ -163,3 +163,32 @@ def test_refine_full_size(lp, oracle_mod, rmat24):
     assert np.array_equal(_np(got), exp)
     assert st.proposals == ost.proposals and st.moves == ost.moves
     G.free()
+
+
+def test_degenerate_inputs(lp, oracle_mod, synth_mod):
+    # no vertices; no edges; zero rounds; isolated vertices and a vertex heavier than the bound
+    import dataclasses
+    empty = synth_mod.from_edges(0, [])
+    E = lp.lp_compress(0, empty.xadj.view(np.int64), np.zeros(0, dtype=np.int32))
+    assert lp.lp_initial_partition(E, 3).numel() == 0
+    assert lp.lp_refine(E, np.zeros(0, dtype=np.int32), 1, 1, 5, 1).numel() == 0
+    assert lp.lp_project(np.zeros(0, dtype=np.int32), np.zeros(0, dtype=np.int32)).numel() == 0
+    g = synth_mod.from_edges(50, [])
+    G = lp.lp_compress(g.n, g.xadj.view(np.int64), g.adjncy)
+    start = oracle_mod.initial_partition(g, 4)
+    assert np.array_equal(_np(lp.lp_initial_partition(G, 4)), start)
+    assert np.array_equal(_np(lp.lp_refine(G, start, 4, 13, 5, 1)), start)
+    g = synth_mod.rmat_scale(11, 8, seed=9)
+    vw = synth_mod.vertex_weights(g.n, 1, 3, 9)
+    vw[7] = 10_000  # heavier than any bound below: never moves, never receives
+    g = dataclasses.replace(g, vwgt=vw)
+    G = lp.lp_compress(g.n, g.xadj.view(np.int64), g.adjncy, None, g.vwgt)
+    k = 6
+    lmax = oracle_mod.max_block_weight(int(vw.astype(np.int64).sum()), k)
+    start = oracle_mod.initial_partition(g, k)
+    for rounds in (0, 1, 5):
+        exp, _ = oracle_mod.lp_refine(g, start, k, lmax, rounds, 4)
+        assert np.array_equal(_np(lp.lp_refine(G, start, k, lmax, rounds, 4)), exp), rounds
+        got = _np(lp.lp_refine(G, start, k, lmax, rounds, 4, config=dict(gain_table=1)))
+        assert np.array_equal(got, exp), rounds
+    assert np.array_equal(_np(lp.lp_refine(G, start, k, lmax, 0, 4)), start)
