@@ -245,6 +245,105 @@ __device__ unsigned long long* lds_sort_u64(unsigned long long* a, unsigned long
   return src;
 }
 
+// Writes the k distinct (key << 32 | value) entries of a[] to `out` in key
+// order by bucket ranking: entries go to B buckets by a monotone map of their
+// key into [0, B) (so bucket order is key order), are scattered into b[] by
+// bucket, and each takes its bucket's start plus the number of smaller keys in
+// its bucket (ranked into a[], then copied out in order). Needs cnt[B] of LDS
+// besides a and b (k entries each). Returns false, having written nothing,
+// when the keys are so skewed that ranking inside the buckets would cost more
+// than kRankBudget comparisons per entry, so that the caller merge-sorts.
+constexpr uint32_t kRankBudget = 32;
+constexpr uint32_t kBucketBins = 1024;  // LDS bucket counters of a heavy reduction workgroup
+
+template <int NT>
+__device__ bool bucket_rank_write(unsigned long long* a, unsigned long long* b, uint32_t k, uint32_t* cnt,
+                                  uint32_t B, Rec* out, int32_t* scan_sm, uint32_t* red) {
+  const int tid = group_tid<NT>();
+  // key range
+  uint32_t mn = 0xFFFFFFFFu, mx = 0;
+  for (uint32_t i = tid; i < k; i += NT) {
+    const uint32_t key = (uint32_t)(a[i] >> 32);
+    mn = min(mn, key);
+    mx = max(mx, key);
+  }
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    mn = min(mn, (uint32_t)__shfl_xor((int)mn, d, kWave));
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, kWave));
+  }
+  constexpr int NW = NT / kWave;
+  if (lane_id() == 0) {
+    red[2 * (tid / kWave)] = mn;
+    red[2 * (tid / kWave) + 1] = mx;
+  }
+  for (uint32_t q = tid; q < B; q += NT) cnt[q] = 0;
+  group_sync<NT>();
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    mn = min(mn, red[2 * w]);
+    mx = max(mx, red[2 * w + 1]);
+  }
+  const float scale = (float)B / ((float)(mx - mn) + 1.0f);
+  auto bucket = [&](unsigned long long x) {
+    const uint32_t q = (uint32_t)((float)((uint32_t)(x >> 32) - mn) * scale);
+    return q < B ? q : B - 1;
+  };
+  for (uint32_t i = tid; i < k; i += NT) atomicAdd(&cnt[bucket(a[i])], 1u);
+  group_sync<NT>();
+  // ranking costs the sum of the squared bucket sizes; exclusive scan of the
+  // counts (B / NT consecutive per thread)
+  const uint32_t per = (B + NT - 1) / NT;
+  const uint32_t q0 = min(B, (uint32_t)tid * per), q1 = min(B, q0 + per);
+  uint32_t sq = 0;
+  int32_t sum = 0;
+  for (uint32_t q = q0; q < q1; ++q) {
+    sq += cnt[q] * cnt[q];
+    sum += (int32_t)cnt[q];
+  }
+  sq = wave_reduce_add(sq);
+  group_sync<NT>();
+  if (lane_id() == 0) red[tid / kWave] = sq;
+  int32_t tot;
+  int32_t run = block_incl_scan_add<NT, int32_t>(sum, scan_sm, &tot) - sum;
+  sq = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) sq += red[w];
+  if (sq > kRankBudget * k) {
+    group_sync<NT>();
+    return false;
+  }
+  for (uint32_t q = q0; q < q1; ++q) {
+    const uint32_t c = cnt[q];
+    cnt[q] = (uint32_t)run;
+    run += (int32_t)c;
+  }
+  group_sync<NT>();
+  // scatter by bucket: afterwards cnt[q] is the end of bucket q
+  for (uint32_t i = tid; i < k; i += NT) {
+    const unsigned long long x = a[i];
+    b[atomicAdd(&cnt[bucket(x)], 1u)] = x;
+  }
+  group_sync<NT>();
+  // ranks into a[] (free once scattered), then one coalesced copy out
+  unsigned long long* sorted = a;
+  for (uint32_t j = tid; j < k; j += NT) {
+    const unsigned long long x = b[j];
+    const uint32_t q = bucket(x);
+    const uint32_t s0 = q ? cnt[q - 1] : 0u, e0 = cnt[q];
+    uint32_t r = s0;
+    for (uint32_t m = s0; m < e0; ++m) r += b[m] < x;
+    sorted[r] = x;
+  }
+  group_sync<NT>();
+  for (uint32_t i = tid; i < k; i += NT) {
+    const unsigned long long x = sorted[i];
+    out[i] = Rec{(int32_t)(x >> 32), (int32_t)(uint32_t)x};
+  }
+  group_sync<NT>();
+  return true;
+}
+
 // Writes the table's entries to `out` sorted by key: every thread takes its
 // (strided) slots into registers, a prefix count compacts the entries to pk
 // as (key << 32 | value) pairs, which lds_sort_u64 sorts. Returns the entry
@@ -253,7 +352,8 @@ __device__ unsigned long long* lds_sort_u64(unsigned long long* a, unsigned long
 // keys and values), so both sort buffers fit in it once the slots are read.
 template <int NT, int SLOTS, typename V>
 __device__ uint32_t compact_sort_write(int32_t* keys, V* vals, uint32_t cap, Rec* out, uint32_t* err,
-                                       int32_t* scan_sm, unsigned long long* pk) {
+                                       int32_t* scan_sm, unsigned long long* pk, uint32_t* bcnt = nullptr,
+                                       uint32_t* red = nullptr) {
   const int tid = group_tid<NT>();
   int32_t kk[SLOTS];
   int64_t vv[SLOTS];
@@ -280,6 +380,11 @@ __device__ uint32_t compact_sort_write(int32_t* keys, V* vals, uint32_t cap, Rec
     }
   const uint32_t cnt = (uint32_t)tot;
   group_sync<NT>();
+  if (bcnt && cnt > kWave) {
+    uint32_t B = 64;
+    while (B < cnt && B < kBucketBins) B <<= 1;
+    if (bucket_rank_write<NT>(pk, pk + cnt, cnt, bcnt, B, out, scan_sm, red)) return cnt;
+  }
   const unsigned long long* sorted = lds_sort_u64<NT>(pk, pk + cnt, cnt);
   for (uint32_t i = tid; i < cnt; i += NT) {
     const unsigned long long x = sorted[i];
@@ -567,8 +672,10 @@ __global__ __launch_bounds__(256) void k_heavy_scatter(AggArgs A, Heavy hv, int3
 
 struct ReduceSmem {
   int32_t scan[kReduceThreads / kWave];
+  uint32_t red[2 * (kReduceThreads / kWave)];
   uint32_t distinct;
   uint32_t overflow;
+  uint32_t bcnt[kBucketBins];
 };
 
 // One workgroup per (cluster, partition): aggregate the partition's records
@@ -636,7 +743,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_heavy_reduce(AggArgs A, Heav
       Rec* dst = hv.out + obase + written;
       const uint32_t k = dense ? dense_write<NT, V>(vals, (uint32_t)(hi - lo), lo, dst, A.err, sm.scan)
                                : compact_sort_write<NT, kHeavyTable / NT, V>(keys, vals, tcap, dst, A.err, sm.scan,
-                                                                             (unsigned long long*)smem_raw);
+                                                                             (unsigned long long*)smem_raw, sm.bcnt,
+                                                                             sm.red);
       written += k;
       lo = hi;
       width = hi_p - lo;  // try the rest of the partition in one window again
