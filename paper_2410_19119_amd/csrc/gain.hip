@@ -162,20 +162,33 @@ __global__ __launch_bounds__(256) void k_gt_fill_lane(GraphView g, const int32_t
 }
 
 // Work items of the wavefront fill: one per vertex above kGtLaneMax, one per
-// chunk above the chunking threshold. One counter atomic per wavefront.
+// chunk above the chunking threshold. Every thread takes kGtItemRun
+// consecutive vertices, so that one counter atomic serves a whole workgroup.
+constexpr int kGtItemRun = 16;
+
+__device__ __forceinline__ uint32_t gt_items_of(uint32_t d) {
+  return d <= (uint32_t)kGtLaneMax ? 0u : d > (uint32_t)LP_CHUNK_THRESHOLD ? (d + LP_CHUNK_LEN - 1) / LP_CHUNK_LEN : 1u;
+}
+
 __global__ __launch_bounds__(256) void k_gt_items(const int32_t* deg, int32_t n, int2* items, uint32_t* nitems) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t b = (int64_t)blockIdx.x * blockDim.x; b < n; b += stride) {
-    const int64_t u = b + threadIdx.x;
-    const uint32_t d = u < n ? (uint32_t)deg[u] : 0u;
-    const uint32_t ni = d <= (uint32_t)kGtLaneMax ? 0u
-                        : d > (uint32_t)LP_CHUNK_THRESHOLD ? (d + LP_CHUNK_LEN - 1) / LP_CHUNK_LEN : 1u;
-    const uint32_t incl = wave_incl_scan_add(ni);
-    uint32_t base = 0;
-    if (lane_id() == kWave - 1 && incl) base = atomicAdd(nitems, incl);
-    base = __shfl(base, kWave - 1, kWave);
-    for (uint32_t j = 0; j < ni; ++j)
-      items[base + incl - ni + j] = make_int2((int)u, ni > 1 ? (int)j : -1);
+  __shared__ int32_t scan[256 / kWave + 1];
+  __shared__ uint32_t base_sm;
+  constexpr int64_t kSpan = 256 * kGtItemRun;
+  for (int64_t b = (int64_t)blockIdx.x * kSpan; b < n; b += (int64_t)gridDim.x * kSpan) {
+    const int64_t u0 = b + (int64_t)threadIdx.x * kGtItemRun;
+    const int64_t u1 = min((int64_t)n, u0 + kGtItemRun);
+    uint32_t cnt = 0;
+    for (int64_t u = u0; u < u1; ++u) cnt += gt_items_of((uint32_t)deg[u]);
+    int32_t tot;
+    const uint32_t incl = (uint32_t)block_incl_scan_add<256, int32_t>((int32_t)cnt, scan, &tot);
+    if (threadIdx.x == 255) base_sm = tot ? atomicAdd(nitems, (uint32_t)tot) : 0u;
+    __syncthreads();
+    uint32_t o = base_sm + incl - cnt;
+    for (int64_t u = u0; u < u1; ++u) {
+      const uint32_t ni = gt_items_of((uint32_t)deg[u]);
+      for (uint32_t j = 0; j < ni; ++j) items[o++] = make_int2((int)u, ni > 1 ? (int)j : -1);
+    }
+    __syncthreads();
   }
 }
 
@@ -382,7 +395,8 @@ lp_status gt_fill(const GainTable& t, const int32_t* blocks, Scratch& sc) {
   uint32_t* nitems = t.cnt + 3;
   hipLaunchKernelGGL(k_gt_zero, dim3(1), dim3(64), 0, s, nitems, (int64_t)1);
   LP_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_gt_items, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, t.deg, n, t.items, nitems);
+  hipLaunchKernelGGL(k_gt_items, dim3(grid_for(n, 256 * kGtItemRun, 65536)), dim3(256), 0, s, t.deg, n, t.items,
+                     nitems);
   LP_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_gt_fill_wave<V>, dim3(grid_for(n, 256 / kWave * 8, 16384)), dim3(256), 0, s, g->view(), t.deg,
                      blocks, t.items, nitems, v);
