@@ -302,8 +302,18 @@ __global__ __launch_bounds__(256) void k_gt_select_wave(GtView<V> t, GtRound r, 
   }
 }
 
-// Work items of an update: one per move, one per chunk of a moved vertex
-// above the chunking threshold ({move index, chunk or -1}).
+// The update of one neighbour v of a moved vertex: w(u, v) leaves block
+// `from` and joins block `to` in v's slice.
+template <typename V>
+__device__ __forceinline__ void gt_move_edge(const GtView<V>& t, int32_t v, int32_t from, int32_t to, int32_t wt) {
+  const int64_t s = gt_slot(t, v, from, false);
+  if (s >= 0) gt_atomic_add(&t.val[s], (V)-wt);
+  else atomicAdd(&t.cnt[1], 1u);
+  if (!gt_add(t, v, to, (V)wt) && atomicExch(&t.flag[v], 1u) == 0u) t.list[atomicAdd(&t.cnt[0], 1u)] = v;
+}
+
+// Work items of an update: one per move of a vertex above kGtLaneMax, one per
+// chunk above the chunking threshold ({move index, chunk or -1}).
 __global__ __launch_bounds__(256) void k_gt_move_items(const int4* moves, const uint32_t* count, const int32_t* deg,
                                                        int2* items, uint32_t* nitems) {
   const int64_t m = *count;
@@ -313,10 +323,7 @@ __global__ __launch_bounds__(256) void k_gt_move_items(const int4* moves, const 
     uint32_t ni = 0;
     if (i < m) {
       const int4 mv = moves[i];
-      if (mv.x >= 0 && mv.y != mv.z) {
-        const uint32_t d = (uint32_t)deg[mv.x];
-        ni = d > (uint32_t)LP_CHUNK_THRESHOLD ? (d + LP_CHUNK_LEN - 1) / LP_CHUNK_LEN : (d > 0 ? 1u : 0u);
-      }
+      if (mv.x >= 0 && mv.y != mv.z) ni = gt_items_of((uint32_t)deg[mv.x]);  // short ones: k_gt_update_lane
     }
     const uint32_t incl = wave_incl_scan_add(ni);
     uint32_t base = 0;
@@ -341,12 +348,22 @@ __global__ __launch_bounds__(256) void k_gt_update(GraphView g, const int32_t* d
     const int2 it = items[i];
     const int4 mv = moves[it.x];
     const int32_t u = mv.x, from = mv.y, to = mv.z;
-    wave_visit(g, u, (uint32_t)deg[u], it.y, dsm[w], [&](int32_t v, int32_t wt) {
-      const int64_t s = gt_slot(t, v, from, false);
-      if (s >= 0) gt_atomic_add(&t.val[s], (V)-wt);
-      else atomicAdd(&t.cnt[1], 1u);
-      if (!gt_add(t, v, to, (V)wt) && atomicExch(&t.flag[v], 1u) == 0u) t.list[atomicAdd(&t.cnt[0], 1u)] = v;
-    });
+    wave_visit(g, u, (uint32_t)deg[u], it.y, dsm[w],
+               [&](int32_t v, int32_t wt) { gt_move_edge(t, v, from, to, wt); });
+  }
+}
+
+// One lane per move of a vertex of degree <= kGtLaneMax.
+template <typename V>
+__global__ __launch_bounds__(256) void k_gt_update_lane(GraphView g, const int32_t* deg, const int4* moves,
+                                                        const uint32_t* count, GtView<V> t) {
+  const int64_t m = *count;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const int4 mv = moves[i];
+    if (mv.x < 0 || mv.y == mv.z) continue;
+    const uint32_t d = (uint32_t)deg[mv.x];
+    if (d == 0 || d > (uint32_t)kGtLaneMax) continue;
+    lane_visit(g, mv.x, d, [&](int32_t v, int32_t wt) { gt_move_edge(t, v, mv.y, mv.z, wt); });
   }
 }
 
@@ -425,6 +442,9 @@ lp_status gt_update_t(const GainTable& t, const int4* moves, const uint32_t* cou
   const GtView<V> v = view_of<V>(t);
   if (max_moves <= 0) return LP_OK;
   hipLaunchKernelGGL(k_gt_zero, dim3(1), dim3(64), 0, s, t.cnt + 3, (int64_t)1);
+  LP_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_gt_update_lane<V>, dim3(grid_for(max_moves, 256, 16384)), dim3(256), 0, s, t.g->view(), t.deg,
+                     moves, count, v);
   LP_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_gt_move_items, dim3(grid_for(max_moves, 256, 16384)), dim3(256), 0, s, moves, count, t.deg,
                      t.items, t.cnt + 3);
