@@ -37,7 +37,8 @@ def _check_all(lp, oracle_mod, T, g, blocks, k, rows=None):
 
 @pytest.mark.parametrize("compressed", [True, False])
 @pytest.mark.parametrize("name,k", [("rgg2d-16k", 8), ("rmat-s13-ef16", 64), ("rmat-s12-weighted", 300),
-                                    ("star-25000", 5), ("star-10001-w", 64), ("bip-3x9000-w", 2)])
+                                    ("star-25000", 5), ("star-10001-w", 64), ("bip-3x9000-w", 2),
+                                    ("bip-5x2048-heavy", 3)])  # weighted degrees above 2^31: int64 slots
 def test_table_matches_definition_through_moves(lp, oracle_mod, graphs, name, k, compressed):
     g = graphs[name]
     G = _gpu_graph(lp, g, compressed)
@@ -95,7 +96,7 @@ def test_table_errors(lp, graphs):
 
 
 CASES = [("rgg2d-16k", 8), ("rmat-s13-ef16", 64), ("rmat-s12-weighted", 5), ("star-25000", 2),
-         ("star-10001-w", 3), ("bip-5x2048", 4), ("bip-3x9000-w", 16)]
+         ("star-10001-w", 3), ("bip-5x2048", 4), ("bip-3x9000-w", 16), ("bip-5x2048-heavy", 4)]
 
 
 @pytest.mark.parametrize("compressed", [True, False])
