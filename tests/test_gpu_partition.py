@@ -59,7 +59,7 @@ def test_projection_matches_oracle(lp, oracle_mod, graphs):
 
 
 CASES = [("rgg2d-16k", 8), ("rmat-s13-ef16", 64), ("rmat-s12-weighted", 5), ("star-25000", 2),
-         ("star-10001-w", 3), ("bip-5x2048", 4), ("bip-3x9000-w", 16)]
+         ("star-10001-w", 3), ("bip-5x2048", 4), ("bip-3x9000-w", 16), ("bip-5x2048-heavy", 4)]
 
 
 @pytest.mark.parametrize("compressed", [True, False])
