@@ -6,8 +6,10 @@
  * size-constrained label-propagation (LP) clustering run directly on a
  * gap + VarInt compressed adjacency (Section III-A), with the two-phase split
  * of low- and high-degree vertices (Section IV-A2), followed by cluster
- * contraction (Section IV-B). Every step runs in hand-written HIP kernels for
- * gfx950.
+ * contraction (Section IV-B); on top of the coarsening hierarchy, the
+ * uncoarsening steps of a k-way partition (initial partition, projection,
+ * size-constrained LP refinement; Section II) and the sparse gain table of
+ * Section V. Every step runs in hand-written HIP kernels for gfx950.
  *
  * Conventions shared by every entry point:
  *  - Pointers named *_dev are device pointers on the current HIP device; all
@@ -17,7 +19,9 @@
  *    their work on it; results written to device buffers are valid once the
  *    stream has reached that point. Calls that return host values
  *    (lp_graph_info, lp_edge_cut, lp_cluster_ex with stats, lp_compress,
- *    lp_contract) synchronise the stream before returning.
+ *    lp_contract) synchronise the stream before returning; so do the calls
+ *    that check their arguments on the device (lp_refine, lp_gain_table_create,
+ *    lp_gain_table_move).
  *  - Scratch memory comes from the library's per-device memory cache in
  *    the order of `stream` and goes back to it before the call returns;
  *    memory released by one call is handed to the next (at once on the same
