@@ -1288,21 +1288,34 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta 
           over = true;
           break;
         }
-        // this thread's best slot ignoring the cap; one cluster-weight read;
-        // only if that cluster is full are the slots rescanned with the cap
-        Cand lb = cand_none();
+        // the largest rating other than the own cluster's, then the smallest
+        // tie-break key among the slots that have it (keys only for those);
+        // one cluster-weight read; only if that cluster is full are the slots
+        // rescanned with the cap
+        int64_t rmax = -1;
         for (uint32_t q = tid; q < tcap; q += NT) {
           const int32_t c = keys[q];
           if (c == kEmpty) continue;
           const int64_t r = (int64_t)vals[q];
-          if (c == own_c) {
-            own = r;
-            continue;
-          }
-          if (r < lb.r) continue;
+          if (c == own_c) own = r;
+          else rmax = r > rmax ? r : rmax;
+        }
+        rmax = wave_reduce_max(rmax);
+        __syncthreads();
+        if (lane_id() == 0) sm.red[tid / kWave] = rmax;
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < NT / kWave; ++w) rmax = sm.red[w] > rmax ? sm.red[w] : rmax;
+        Cand lb = cand_none();
+        for (uint32_t q = tid; q < tcap; q += NT) {
+          const int32_t c = keys[q];
+          if (c == kEmpty || c == own_c) continue;
+          const int64_t r = (int64_t)vals[q];
+          if (r != rmax) continue;
           const Cand cd{r, cluster_key(x, vp, c), c};
           if (cand_better(cd, lb)) lb = cd;
         }
+        lb = block_best<NT>(lb, sm.best);
         if (lb.c >= 0 && cand_better(lb, best)) {
           if (x.W[lb.c] + wu <= vp.cap) {
             best = lb;
