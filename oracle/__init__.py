@@ -7,7 +7,9 @@ baseline leg of ``bench.py`` may import this package. The GPU library never
 loads it and shares no code with it.
 
 The C part is built into ``liboracle.so`` by :func:`build` (gcc, OpenMP).
-The coarsening loop is plain Python on top of the C cluster / contract calls.
+The coarsening loop and the multilevel partition driver are plain Python on
+top of the C cluster / refine / contract calls; projection, block weights and
+the affinities of Section V are numpy written out from their definitions.
 """
 from __future__ import annotations
 
