@@ -513,8 +513,8 @@ def main() -> int:
     ap.add_argument("--no-checks", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is a design "
-              f"note, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path exists as a "
+              f"design only", file=sys.stderr)
         return 2
 
     import torch
