@@ -331,19 +331,20 @@ def bench_partition(args, G=None) -> dict:
     out = {}
     for k in [int(x) for x in args.partition_k.split(",")]:
         lmax = lp.max_block_weight(G.total_vwgt, k)
-        _, trace = lp.partition(G, k, seed=1, rounds=args.rounds, trace=True)
+        S = args.partition_subrounds
+        _, trace = lp.partition(G, k, seed=1, rounds=args.rounds, subrounds=S, refine_subrounds=S, trace=True)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        blocks = lp.partition(G, k, seed=1, rounds=args.rounds)
+        blocks = lp.partition(G, k, seed=1, rounds=args.rounds, subrounds=S, refine_subrounds=S)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         cut = lp.lp_edge_cut(G, blocks)
         bw = torch.bincount(blocks.to(torch.int64), minlength=k)
         # the same partition with every refinement rated from a sparse gain table
-        blocks_gt = lp.partition(G, k, seed=1, rounds=args.rounds, gain_table=True)
+        blocks_gt = lp.partition(G, k, seed=1, rounds=args.rounds, subrounds=S, refine_subrounds=S, gain_table=True)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        blocks_gt = lp.partition(G, k, seed=1, rounds=args.rounds, gain_table=True)
+        blocks_gt = lp.partition(G, k, seed=1, rounds=args.rounds, subrounds=S, refine_subrounds=S, gain_table=True)
         torch.cuda.synchronize()
         dt_gt = time.perf_counter() - t
         same = bool(torch.equal(blocks_gt, blocks))
@@ -364,7 +365,8 @@ def bench_partition(args, G=None) -> dict:
         slots, tbytes, _, _ = T.info()
         T.free()
         ref["gain_table"].update({"slots": int(slots), "bytes": int(tbytes), "graph_bytes": int(G.nbytes)})
-        out[str(k)] = {"ms": round(1e3 * dt, 1), "ms_gain_table": round(1e3 * dt_gt, 1), "identical_blocks": same,
+        out[str(k)] = {"subrounds": S, "ms": round(1e3 * dt, 1), "ms_gain_table": round(1e3 * dt_gt, 1),
+                       "identical_blocks": same,
                        "levels": len(trace) - 1, "coarsest_n": trace[0][0],
                        "cut": int(cut), "cut_per_level": [int(c) for _, c in trace],
                        "max_block_weight": int(bw.max()), "bound": lmax,
@@ -507,6 +509,8 @@ def main() -> int:
                     help="directed edges from which a job runs in the big-job lane (0: one lane)")
     ap.add_argument("--partition-k", default="64", help="block counts of the partition form")
     ap.add_argument("--partition-graph", default="rmat", choices=["rmat", "rgg2d"])
+    ap.add_argument("--partition-subrounds", type=int, default=1,
+                    help="sub-rounds per LP round in the partition's coarsening and refinement")
     ap.add_argument("--coarsen-graph", default="rmat", choices=["rmat", "rgg3d"])
     ap.add_argument("--coarsen-subrounds", type=int, default=1, help="sub-rounds per LP round in the coarsening")
     ap.add_argument("--coarsen-scale", type=int, default=26)
