@@ -671,6 +671,9 @@ def main() -> int:
                     "alg_bytes_per_launch": phases[dom]["alg_bytes"], "avg_launch_ms": phases[dom]["avg_ms"]}
     round_bytes = sum(phases[p]["alg_bytes"] for p in phases)
     round_ms = lp_ms / max(1, st.phase_launches["round"])
+    # the same mean round time of every timed step, and their median
+    step_round_ms = [s_.phase_ms["round"] / max(1, s_.phase_launches["round"]) for s_ in stats]
+    round_ms_median = float(np.median(step_round_ms)) if step_round_ms else None
 
     cpu = None
     if not args.no_cpu:
@@ -716,6 +719,8 @@ def main() -> int:
                    "step": "lp_cluster + lp_contract + lp_edge_cut"},
         "lp_round_edges_per_s": lp_round_rate,
         "round_model": {"alg_bytes": int(round_bytes), "ms": round(round_ms, 4),
+                        "ms_median_over_steps": round(round_ms_median, 4) if round_ms_median else None,
+                        "ms_each_step": [round(v, 4) for v in step_round_ms],
                         "frac_hbm": (round(round_bytes / (round_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
                                      if round_ms else None),
                         "traffic": round_traffic,
