@@ -57,49 +57,156 @@ static int cmp_i32(const void *a, const void *b) {
   return (x > y) - (x < y);
 }
 
+/* Ascending sort of non-negative int32 values: insertion sort for short runs,
+ * quicksort (median of three, loop on the larger side) up to 2^14 values, LSD
+ * radix sort with 11-bit digits beyond (scratch from malloc; qsort if that
+ * fails). */
+static void isort_i32(int32_t *a, int64_t d) {
+  for (int64_t i = 1; i < d; ++i) {
+    int32_t x = a[i];
+    int64_t j = i;
+    while (j > 0 && a[j - 1] > x) { a[j] = a[j - 1]; --j; }
+    a[j] = x;
+  }
+}
+
+static void qsort_i32(int32_t *a, int64_t d) {
+  while (d > 24) {
+    int32_t x = a[0], y = a[d / 2], z = a[d - 1];
+    int32_t piv = x < y ? (y < z ? y : (x < z ? z : x)) : (x < z ? x : (y < z ? z : y));
+    int64_t i = 0, j = d - 1;
+    for (;;) {
+      while (a[i] < piv) ++i;
+      while (a[j] > piv) --j;
+      if (i >= j) break;
+      int32_t t = a[i]; a[i] = a[j]; a[j] = t;
+      ++i; --j;
+    }
+    /* [0, j] <= piv <= [j + 1, d) */
+    int64_t left = j + 1, right = d - left;
+    if (left < right) { qsort_i32(a, left); a += left; d = right; }
+    else { qsort_i32(a + left, right); d = left; }
+  }
+  isort_i32(a, d);
+}
+
+static void sort_i32(int32_t *a, int64_t d) {
+  if (d <= (1 << 14)) { qsort_i32(a, d); return; }
+  uint32_t *tmp = (uint32_t *)malloc((size_t)d * sizeof(uint32_t));
+  if (!tmp) { qsort(a, (size_t)d, sizeof(int32_t), cmp_i32); return; }
+  uint32_t *src = (uint32_t *)a, *dst = tmp;
+  int64_t cnt[2048];
+  for (int pass = 0; pass < 3; ++pass) {
+    int sh = 11 * pass;
+    memset(cnt, 0, sizeof(cnt));
+    for (int64_t i = 0; i < d; ++i) cnt[(src[i] >> sh) & 2047]++;
+    int64_t run = 0;
+    for (int k = 0; k < 2048; ++k) { int64_t c = cnt[k]; cnt[k] = run; run += c; }
+    for (int64_t i = 0; i < d; ++i) dst[cnt[(src[i] >> sh) & 2047]++] = src[i];
+    uint32_t *t = src; src = dst; dst = t;
+  }
+  /* three passes: the result is in tmp */
+  memcpy(a, src, (size_t)d * sizeof(uint32_t));
+  free(tmp);
+}
+
 /* Build a symmetric, deduplicated, self-loop free CSR from a directed pair
- * source. `emit(ctx, pass, i, &u, &v)` yields edge i (returns 0 to skip it).
- * Each accepted pair is inserted in both directions. Two passes over the
- * source: the first counts degrees, the second scatters. */
+ * source. `emit(ctx, i, &u, &v)` yields pair i (returns 0 to skip it); each
+ * accepted pair is inserted in both directions. The pairs are cut into
+ * fixed chunks; pass 1 counts, per chunk, the entries of every bucket of
+ * 2^shift consecutive IDs (private counters, no atomics); pass 2 draws the
+ * pairs again and scatters (ID within bucket, neighbour) entries to their
+ * bucket; pass 3 places every bucket's entries by vertex, and every
+ * neighbourhood is sorted and deduplicated. The result depends only on the
+ * set of pairs, not on the thread count. */
 typedef int (*pair_fn)(const void *ctx, int64_t i, int32_t *u, int32_t *v);
 
 static int build_csr(int64_t n, int64_t npairs, pair_fn emit, const void *ctx,
                      synth_csr *out) {
-  uint64_t *cnt = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));
-  if (!cnt) return -1;
-#pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < npairs; ++i) {
-    int32_t u, v;
-    if (!emit(ctx, i, &u, &v) || u == v) continue;
-#pragma omp atomic
-    cnt[u + 1]++;
-#pragma omp atomic
-    cnt[v + 1]++;
+  int shift = 0;
+  while (n > 0 && ((n - 1) >> shift) >= (1 << 12)) ++shift;
+  int64_t nb = n > 0 ? ((n - 1) >> shift) + 1 : 1;
+  int64_t nc = 4 * (int64_t)omp_get_max_threads();
+  if (nc < 1) nc = 1;
+  uint64_t *hist = (uint64_t *)calloc((size_t)(nc * nb), sizeof(uint64_t));
+  uint64_t *bstart = (uint64_t *)malloc((size_t)(nb + 1) * sizeof(uint64_t));
+  uint64_t *vstart = (uint64_t *)malloc(((size_t)n + 1) * sizeof(uint64_t));
+  if (!hist || !bstart || !vstart) { free(hist); free(bstart); free(vstart); return -1; }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t c = 0; c < nc; ++c) {
+    uint64_t *h = hist + c * nb;
+    int64_t lo = npairs / nc * c + (c < npairs % nc ? c : npairs % nc);
+    int64_t hi = lo + npairs / nc + (c < npairs % nc ? 1 : 0);
+    for (int64_t i = lo; i < hi; ++i) {
+      int32_t u, v;
+      if (!emit(ctx, i, &u, &v) || u == v) continue;
+      h[u >> shift]++;
+      h[v >> shift]++;
+    }
   }
-  for (int64_t u = 0; u < n; ++u) cnt[u + 1] += cnt[u];
-  uint64_t total = cnt[n];
+  /* bucket-major positions: bucket b, then chunk c */
+  uint64_t total = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    bstart[b] = total;
+    for (int64_t c = 0; c < nc; ++c) {
+      uint64_t k = hist[c * nb + b];
+      hist[c * nb + b] = total;
+      total += k;
+    }
+  }
+  bstart[nb] = total;
   progress("degrees counted: vertices, directed pairs", n, (int64_t)total);
-  int32_t *tmp = (int32_t *)malloc((total ? total : 1) * sizeof(int32_t));
-  uint64_t *pos = (uint64_t *)malloc(((size_t)n + 1) * sizeof(uint64_t));
-  if (!tmp || !pos) { free(cnt); free(tmp); free(pos); return -1; }
-  memcpy(pos, cnt, ((size_t)n + 1) * sizeof(uint64_t));
-#pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < npairs; ++i) {
-    int32_t u, v;
-    if (!emit(ctx, i, &u, &v) || u == v) continue;
-    uint64_t pu = __atomic_fetch_add(&pos[u], 1, __ATOMIC_RELAXED);
-    uint64_t pv = __atomic_fetch_add(&pos[v], 1, __ATOMIC_RELAXED);
-    tmp[pu] = v;
-    tmp[pv] = u;
+  uint64_t *ent = (uint64_t *)malloc((total ? total : 1) * sizeof(uint64_t));
+  if (!ent) { free(hist); free(bstart); free(vstart); return -1; }
+  uint64_t mask = ((uint64_t)1 << shift) - 1;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t c = 0; c < nc; ++c) {
+    uint64_t *h = hist + c * nb;
+    int64_t lo = npairs / nc * c + (c < npairs % nc ? c : npairs % nc);
+    int64_t hi = lo + npairs / nc + (c < npairs % nc ? 1 : 0);
+    for (int64_t i = lo; i < hi; ++i) {
+      int32_t u, v;
+      if (!emit(ctx, i, &u, &v) || u == v) continue;
+      ent[h[u >> shift]++] = (((uint64_t)u & mask) << 32) | (uint32_t)v;
+      ent[h[v >> shift]++] = (((uint64_t)v & mask) << 32) | (uint32_t)u;
+    }
   }
+  free(hist);
   progress("pairs scattered", n, (int64_t)total);
+  int32_t *tmp = (int32_t *)malloc((total ? total : 1) * sizeof(int32_t));
+  if (!tmp) { free(bstart); free(vstart); free(ent); return -1; }
+  int64_t bw = (int64_t)1 << shift;
+#pragma omp parallel
+  {
+    uint64_t *lc = (uint64_t *)malloc((size_t)(bw + 1) * sizeof(uint64_t));
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t b = 0; b < nb; ++b) {
+      int64_t v0 = b << shift;
+      int64_t vn = n - v0 < bw ? n - v0 : bw;
+      memset(lc, 0, (size_t)(bw + 1) * sizeof(uint64_t));
+      for (uint64_t e = bstart[b]; e < bstart[b + 1]; ++e) lc[(ent[e] >> 32) + 1]++;
+      uint64_t run = bstart[b];
+      for (int64_t k = 0; k < vn; ++k) {
+        vstart[v0 + k] = run;
+        run += lc[k + 1];
+        lc[k + 1] = vstart[v0 + k];
+      }
+      for (uint64_t e = bstart[b]; e < bstart[b + 1]; ++e)
+        tmp[lc[(ent[e] >> 32) + 1]++] = (int32_t)(uint32_t)ent[e];
+    }
+    free(lc);
+  }
+  vstart[n] = total;
+  free(ent);
+  free(bstart);
   /* sort + dedupe each neighbourhood in place; record new degrees */
-  uint64_t *deg = pos; /* reuse */
+  uint64_t *deg = (uint64_t *)malloc(((size_t)n + 1) * sizeof(uint64_t));
+  if (!deg) { free(vstart); free(tmp); return -1; }
 #pragma omp parallel for schedule(dynamic, 1024)
   for (int64_t u = 0; u < n; ++u) {
-    uint64_t b = cnt[u], e = cnt[u + 1];
+    uint64_t b = vstart[u], e = vstart[u + 1];
     uint64_t d = e - b;
-    if (d > 1) qsort(tmp + b, d, sizeof(int32_t), cmp_i32);
+    if (d > 1) sort_i32(tmp + b, (int64_t)d);
     uint64_t k = 0;
     for (uint64_t j = 0; j < d; ++j)
       if (k == 0 || tmp[b + j] != tmp[b + k - 1]) tmp[b + k++] = tmp[b + j];
@@ -107,18 +214,18 @@ static int build_csr(int64_t n, int64_t npairs, pair_fn emit, const void *ctx,
   }
   progress("neighbourhoods sorted", n, 0);
   uint64_t *xadj = (uint64_t *)malloc(((size_t)n + 1) * sizeof(uint64_t));
-  if (!xadj) { free(cnt); free(tmp); free(pos); return -1; }
+  if (!xadj) { free(vstart); free(tmp); free(deg); return -1; }
   xadj[0] = 0;
   for (int64_t u = 0; u < n; ++u) xadj[u + 1] = xadj[u] + deg[u];
   uint64_t two_m = xadj[n];
   int32_t *adj = (int32_t *)malloc((two_m ? two_m : 1) * sizeof(int32_t));
-  if (!adj) { free(cnt); free(tmp); free(pos); free(xadj); return -1; }
+  if (!adj) { free(vstart); free(tmp); free(deg); free(xadj); return -1; }
 #pragma omp parallel for schedule(dynamic, 1024)
   for (int64_t u = 0; u < n; ++u)
-    memcpy(adj + xadj[u], tmp + cnt[u], (xadj[u + 1] - xadj[u]) * sizeof(int32_t));
-  free(cnt);
+    memcpy(adj + xadj[u], tmp + vstart[u], (xadj[u + 1] - xadj[u]) * sizeof(int32_t));
+  free(vstart);
   free(tmp);
-  free(pos);
+  free(deg);
   out->n = n;
   out->two_m = two_m;
   out->xadj = xadj;
@@ -145,15 +252,12 @@ static int rmat_pair(const void *c, int64_t i, int32_t *pu, int32_t *pv) {
       if (level >= x->scale) break;
       uint64_t q = h ? (r >> 32) : (r & 0xffffffffULL);
       int bit = x->scale - 1 - level;
-      if (q < x->ta) {
-      } else if (q < x->tab) {
-        v |= 1ULL << bit;
-      } else if (q < x->tabc) {
-        u |= 1ULL << bit;
-      } else {
-        u |= 1ULL << bit;
-        v |= 1ULL << bit;
-      }
+      /* quadrant a: neither bit; b: v's bit; c: u's bit; d: both
+       * (branch-free: the quadrant is a coin the predictor cannot learn) */
+      uint64_t bu = q >= x->tab;
+      uint64_t bv = (uint64_t)((q >= x->ta) & (q < x->tab)) | (uint64_t)(q >= x->tabc);
+      u |= bu << bit;
+      v |= bv << bit;
     }
   }
   if ((int64_t)u >= x->n_limit || (int64_t)v >= x->n_limit) return 0;
@@ -284,7 +388,7 @@ int synth_rgg(int dim, int64_t n, double r, uint64_t seed, synth_csr *out) {
         }
       }
       if (pass == 0) xadj[i + 1] = k;
-      else if (k > 1) qsort(adj + xadj[i], k, sizeof(int32_t), cmp_i32);
+      else if (k > 1) sort_i32(adj + xadj[i], (int64_t)k);
     }
     progress(pass == 0 ? "neighbours counted" : "neighbours written", n, pass);
   }
