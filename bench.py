@@ -6,16 +6,18 @@ lp_cluster (degree buckets + 5 synchronous rounds of rating, acceptance and
 apply), lp_contract (coarse graph) and lp_edge_cut. The graph is generated,
 compressed and made resident before the timed region.
 
-Workload (default): R-MAT scale 24, edge factor 16 (2^28 samples),
+Workload (default): R-MAT scale 26, edge factor 32 (2^31 samples),
 (a, b, c, d) = (0.57, 0.19, 0.19, 0.05), symmetrised, self-loops and
-duplicates removed, no ID permutation, unit weights, max cluster weight 256,
-5 rounds, seed 1.
+duplicates removed, no ID permutation, unit weights; level 0 of the
+coarsening to 2^14 vertices: max cluster weight 12288, 5 rounds, seed 1.
 
-value = 2m * rounds run / step time (directed adjacency entries processed per
-second per LP round, contraction and cut included in the step time).
-The JSON line also carries the LP-only round rate, a per-phase breakdown,
-the roofline of the dominant kernel (algorithmic bytes / event-timed launch
-duration against 8 TB/s HBM) and the CPU oracle timed on a bounded sample.
+value = 2m / t_round, t_round = median over every round of the timed steps
+of one LP round (rating + acceptance + apply), timed with HIP events on the
+call's stream. The JSON line also carries the step rate (contraction and cut
+included), a per-phase breakdown, the roofline of the dominant rating kernel
+(algorithmic bytes / event-timed duration against 8 TB/s HBM), the round's
+algorithmic-byte model, the CPU oracle timed on a bounded sample, the
+R-MAT scale 24 rate, and the batched and served forms.
 """
 from __future__ import annotations
 
@@ -47,6 +49,10 @@ def log(msg: str) -> None:
 
 def workload(name: str):
     import synth
+    if name == "rmat26":
+        os.environ["SYNTH_PROGRESS"] = "1"  # the generator reports its phases on stderr
+        return (synth.rmat_scale(26, 32, seed=1), 12288,
+                "rmat-s26-ef32 (0.57,0.19,0.19,0.05), unit weights, level 0 of the coarsening to 2^14")
     if name == "rmat24":
         return synth.rmat_scale(24, 16, seed=1), 256, "rmat-s24-ef16 (0.57,0.19,0.19,0.05), unit weights"
     if name == "rmat20":
@@ -58,8 +64,8 @@ def workload(name: str):
 
 TRAFFIC_SOURCES = ("paper_2410_19119_amd/csrc/cluster.hip", "paper_2410_19119_amd/csrc/decode.h",
                    "paper_2410_19119_amd/csrc/lp_device.h", "paper_2410_19119_amd/csrc/lp_common.h")
-TRAFFIC_FILE = "profiles/rmat24_small_tile_hbm_traffic.md"
-ROUND_TRAFFIC_FILE = "profiles/rmat24_round_hbm_traffic.md"
+TRAFFIC_FILE = "profiles/rmat26_rating_hbm_traffic.md"
+ROUND_TRAFFIC_FILE = "profiles/rmat26_round_hbm_traffic.md"
 
 
 def kernel_source_hash() -> str:
@@ -206,10 +212,12 @@ def bench_serve(args) -> dict:
         lp.coarsen(h, seed=1)
     torch.cuda.synchronize()
     rates = [float(r) for r in (args.serve_rates or "10,30,100,300,1000").split(",")]
-    out = {"pool": len(pool), "requests_per_rate": args.serve_requests, "budget_bytes": 200 * 10**9,
+    out = {"pool": len(pool), "pool_two_m": [int(h.two_m) for h in pool], "budget_bytes": 200 * 10**9,
            "split_edges": args.serve_split, "rates": {}}
     for rate in rates:
-        reqs = serve.requests(synth.serve_trace(rate, args.serve_requests, len(pool), seed=7))
+        # requests per rate: fixed, or (0) those arriving in --serve-window seconds, 100 to 2000
+        count = args.serve_requests or min(2000, max(100, int(rate * args.serve_window)))
+        reqs = serve.requests(synth.serve_trace(rate, count, len(pool), seed=7))
         seq = serve.summarize(serve.run_sequential(pool, reqs))
         srv_obj = serve.Server(pool, budget_bytes=200 * 10**9, max_active=args.serve_slots,
                                split_edges=args.serve_split)
@@ -217,7 +225,7 @@ def bench_serve(args) -> dict:
         srv = serve.summarize(res)
         srv["peak_active"] = srv_obj.peak_active
         srv["steps"] = srv_obj.steps
-        out["rates"][str(rate)] = {"sequential": seq, "served": srv}
+        out["rates"][str(rate)] = {"requests": count, "sequential": seq, "served": srv}
         log(f"[serve] rate {rate}/s: sequential {seq['throughput_per_s']:.1f} jobs/s p50 {seq['p50_ms']:.1f} ms "
             f"p99 {seq['p99_ms']:.1f} ms | served {srv['throughput_per_s']:.1f} jobs/s p50 {srv['p50_ms']:.1f} ms "
             f"p99 {srv['p99_ms']:.1f} ms (peak {srv_obj.peak_active} active)")
@@ -494,15 +502,18 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat24")
+    ap.add_argument("--workload", default="rmat26")
     ap.add_argument("--rounds", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and served comparisons")
-    ap.add_argument("--cpu-rounds", type=int, default=5, help="oracle rounds timed for the baseline")
+    ap.add_argument("--cpu-rounds", type=int, default=1, help="oracle rounds timed for the baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the R-MAT scale 24 round rate")
     ap.add_argument("--batch-graphs", type=int, default=512)
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--serve-pool", type=int, default=24)
-    ap.add_argument("--serve-requests", type=int, default=100)
+    ap.add_argument("--serve-requests", type=int, default=0,
+                    help="requests per rate (0: those arriving within --serve-window seconds, 100..2000)")
+    ap.add_argument("--serve-window", type=float, default=3.0)
     ap.add_argument("--serve-rates", default=None,
                     help="comma-separated request rates (default: 10..1000 for --workload serve, "
                          "100,1000 inside the default run)")
@@ -545,6 +556,32 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"workload": "copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
                           "copies": 3}))
+        return 0
+    if args.workload == "gather":
+        # calibration for the HBM byte counters on random 4-byte gathers:
+        # 2^26 gathers at uniform random positions of an int32 array of 2^24
+        # (64 MiB) and of 2^28 (1 GiB) elements; each launch also streams the
+        # 8-byte indices in and the 4-byte results out
+        cnt = 1 << 26
+        gen = torch.Generator(device="cuda").manual_seed(3)
+        res = {"workload": "gather", "gathers_per_launch": cnt, "index_bytes_read": 8 * cnt,
+               "result_bytes_written": 4 * cnt, "sources": {}}
+        for lg in (24, 28):
+            src = torch.arange(1 << lg, dtype=torch.int32, device="cuda")
+            idx = torch.randint(0, 1 << lg, (cnt,), device="cuda", dtype=torch.int64, generator=gen)
+            out = torch.empty(cnt, dtype=torch.int32, device="cuda")
+            ts = []
+            for _ in range(3):
+                a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a_.record()
+                torch.take(src, idx, out=out)
+                b_.record()
+                torch.cuda.synchronize()
+                ts.append(a_.elapsed_time(b_))
+            assert torch.equal(out, idx.to(torch.int32))
+            res["sources"][f"2^{lg}"] = {"source_bytes": 4 << lg, "ms": [round(t, 4) for t in ts]}
+            del src, idx, out
+        print(json.dumps(res))
         return 0
     if args.workload == "coarsen26":
         res = bench_coarsen(args)
@@ -589,6 +626,54 @@ def main() -> int:
                           "config": {"workload": "Poisson stream of coarsening jobs on resident RGG-2D / R-MAT"},
                           "served": res}))
         return 0
+    out = bench_headline(args)
+    print(json.dumps(out))
+    return 0
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def median(xs):
+    return float(np.median(xs)) if len(xs) else None
+
+
+def round_model(g_n: int, two_m: int, nbytes: int, proposals: float, kappa: float = 2.0) -> int:
+    """Algorithmic bytes of one LP round: compressed neighbourhoods, offsets,
+    the 4-byte label gather per adjacency entry, 16 bytes per vertex (own
+    label, vertex weight, label write, cluster weight write) and 20 bytes per
+    proposal and pass through acceptance."""
+    return int(nbytes + 8 * (g_n + 1) + 4 * two_m + 16 * g_n + 20 * proposals * kappa)
+
+
+def lp_rate(lp, G, cap: int, rounds: int, steps: int, warmup: int, labels=None) -> dict:
+    """Median LP round time of `steps` clustering calls (after `warmup`)."""
+    import torch
+    cfg = dict(timing=1)
+    for _ in range(warmup):
+        lp.lp_cluster(G, cap, rounds, 1, labels=labels, config=cfg)
+    torch.cuda.synchronize()
+    rms = []
+    for _ in range(steps):
+        _, st = lp.lp_cluster(G, cap, rounds, 1, labels=labels, config=cfg, stats=True)
+        rms += st.round_ms
+    med = median(rms)
+    return {"round_ms_median": round(med, 4), "lp_round_edges_per_s": G.two_m / (med / 1e3),
+            "rounds_timed": len(rms)}
+
+
+def bench_headline(args) -> dict:
+    import torch
+    import paper_2410_19119_amd as lp
+
     t0 = time.time()
     g, cap, desc = workload(args.workload)
     log(f"[bench] generated {desc}: n={g.n} 2m={g.two_m} in {time.time() - t0:.1f}s")
@@ -597,7 +682,8 @@ def main() -> int:
     torch.cuda.synchronize()
     log(f"[bench] compressed on GPU: {G.nbytes} bytes ({G.nbytes / max(g.two_m, 1):.3f} B/edge) "
         f"in {time.time() - t0:.1f}s")
-    labels = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    n, two_m = g.n, g.two_m
+    labels = torch.empty(n, dtype=torch.int32, device="cuda")
     cfg = dict(timing=1)
 
     split = {"cluster": 0.0, "contract": 0.0, "cut": 0.0}
@@ -634,73 +720,103 @@ def main() -> int:
         times.append(time.perf_counter() - t)
         stats.append(st)
         log(f"[bench] step {i + 1}/{args.steps}: {times[-1] * 1e3:.2f} ms, rounds {st.rounds_run}, "
-            f"coarse n {n_coarse}, cut {cut}")
+            f"round ms {[round(v, 2) for v in st.round_ms]}, coarse n {n_coarse}, cut {cut}")
     total = sum(times)
     ms_per_step = 1e3 * total / args.steps
     st = stats[-1]
     rounds_run = st.rounds_run
-    value = g.two_m * rounds_run * args.steps / total
+    all_rounds = [v for s_ in stats for v in s_.round_ms]
+    t_round = median(all_rounds)
+    value = two_m / (t_round / 1e3)
+    step_rate = two_m * rounds_run * args.steps / total
 
-    # LP-only round rate (whole rounds, event-timed on the call's stream; the
-    # four rating paths overlap on side streams) and per-phase breakdown
+    # per-phase times: the rating paths run one after another on the call's
+    # stream, so each phase's events time exactly its own kernels
     round_phases = ("lane", "tile", "block", "hub", "accept")
-    lp_ms = st.phase_ms["round"]
-    lp_round_rate = g.two_m * rounds_run / (lp_ms / 1e3) if lp_ms > 0 else None
     nb = st.buckets
-    props = sum(st.proposals) / max(1, len(st.proposals))
+    props = float(np.mean([np.mean(s_.proposals) for s_ in stats if s_.proposals])) if st.proposals else 0.0
     phases = {}
     for p in round_phases:
-        launches = st.phase_launches[p]
+        launches = sum(s_.phase_launches[p] for s_ in stats)
         if not launches:
             continue
-        avg_ms = st.phase_ms[p] / launches
+        avg_ms = sum(s_.phase_ms[p] for s_ in stats) / launches
         b = phase_bytes(st, p, nb, props)
-        phases[p] = {"kernel": PHASE_KERNEL[p], "launches": launches, "avg_ms": round(avg_ms, 4),
-                     "alg_bytes": int(b), "alg_GBs": round(b / (avg_ms / 1e3) / 1e9, 1) if avg_ms > 0 else None}
-    # dominant kernel: the small-tile rating kernel (largest kernel time per step in the
-    # kernel-trace summary); it runs first on the call's stream, so its events time its
-    # execution, while the side-stream phases' event spans include waiting for CUs
-    dom = "tile" if "tile" in phases else max((p for p in phases if p != "accept"),
-                                              key=lambda p: phases[p]["avg_ms"], default=None)
+        phases[p] = {"kernel": PHASE_KERNEL[p], "launches_per_step": launches // args.steps,
+                     "avg_ms": round(avg_ms, 4), "alg_bytes": int(b),
+                     "alg_GBs": round(b / (avg_ms / 1e3) / 1e9, 1) if avg_ms > 0 else None,
+                     "frac_hbm": round(b / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if avg_ms > 0 else None}
+    # dominant kernel: the rating phase with the largest time per round
+    dom = max((p for p in phases if p != "accept"), key=lambda p: phases[p]["avg_ms"], default=None)
     roofline = None
     if dom:
         ach = phases[dom]["alg_GBs"]
+        tr = measured_traffic(TRAFFIC_FILE, f"{dom}_bytes_per_launch") if args.workload == "rmat26" else None
         roofline = {"bound": "hbm", "kernel": phases[dom]["kernel"], "achieved": ach, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic() if dom == "tile" and args.workload == "rmat24" else None,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr,
                     "alg_bytes_per_launch": phases[dom]["alg_bytes"], "avg_launch_ms": phases[dom]["avg_ms"]}
-    round_bytes = sum(phases[p]["alg_bytes"] for p in phases)
-    round_ms = lp_ms / max(1, st.phase_launches["round"])
-    # the same mean round time of every timed step, and their median
-    step_round_ms = [s_.phase_ms["round"] / max(1, s_.phase_launches["round"]) for s_ in stats]
-    round_ms_median = float(np.median(step_round_ms)) if step_round_ms else None
+    a_round = round_model(n, two_m, G.nbytes, props)
+    round_traffic = measured_traffic(ROUND_TRAFFIC_FILE, "round_bytes") if args.workload == "rmat26" else None
+
+    # a1 uncached: the same call with a plan built for it (non-default
+    # thresholds that bucket every vertex as the defaults do, except tiles
+    # of 4095 instead of 4096 edges), zero rounds
+    _, st0 = lp.lp_cluster(G, cap, 0, 1, labels=labels, config=dict(timing=1, t_block=4095), stats=True)
+    _, st0 = lp.lp_cluster(G, cap, 0, 1, labels=labels, config=dict(timing=1, t_block=4095), stats=True)
+    setup_uncached = st0.phase_ms["setup"]
 
     cpu = None
     if not args.no_cpu:
         import oracle
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        threads = os.cpu_count() or 1
         oracle.set_threads(threads)
         t = time.perf_counter()
         _, ost = oracle.lp_cluster(g, cap, args.cpu_rounds, 1)
         dt = time.perf_counter() - t
         done = ost.rounds_run
-        cpu = {"value": g.two_m * done / dt, "unit": "edges/s", "cores": threads, "kind": "oracle",
-               "sample": f"oracle lp_cluster on the full graph, {done} round(s) ({dt:.1f} s wall, "
-                         f"rating + acceptance + apply, no contraction)"}
-        log(f"[bench] cpu oracle: {args.cpu_rounds} round(s) in {dt:.1f}s with {threads} threads")
+        cpu = {"value": two_m * done / dt, "unit": "edges/s", "cores": threads, "kind": "oracle",
+               "cpu_model": cpu_model(),
+               "sample": f"oracle lp_cluster on the full graph, first {done} round(s) ({dt:.1f} s wall, "
+                         f"rating + acceptance + apply, no contraction), {threads} threads"}
+        log(f"[bench] cpu oracle: {done} round(s) in {dt:.1f}s with {threads} threads")
+        # the small workload (RGG-2D, n = 16384, cap 32, 5 rounds) on one thread and on all
+        import synth
+        g0 = synth.rgg2d_16k(seed=1)
+        small = {}
+        for th in (1, threads):
+            oracle.set_threads(th)
+            reps, t = 0, time.perf_counter()
+            while reps < 3 or time.perf_counter() - t < 1.0:
+                _, o0 = oracle.lp_cluster(g0, 32, 5, 1)
+                reps += 1
+            dt0 = (time.perf_counter() - t) / reps
+            small[str(th)] = g0.two_m * o0.rounds_run / dt0
+        oracle.set_threads(threads)
+        cpu["small_workload_edges_per_s_by_threads"] = small
+    del g
+
+    extra = {}
+    if not args.no_extra and args.workload == "rmat26":
+        import synth
+        t0 = time.time()
+        g1 = synth.rmat_scale(24, 16, seed=1)
+        G1 = lp.lp_compress(g1.n, g1.xadj.view(np.int64), g1.adjncy)
+        del g1
+        lab1 = torch.empty(G1.n, dtype=torch.int32, device="cuda")
+        r1 = lp_rate(lp, G1, 256, args.rounds, 3, 1, labels=lab1)
+        r1.update({"workload": "rmat-s24-ef16, cap 256, 5 rounds, seed 1", "two_m": G1.two_m})
+        extra["rmat24"] = r1
+        G1.free()
+        log(f"[bench] rmat24: round {r1['round_ms_median']} ms ({r1['lp_round_edges_per_s']:.3e} edges/s) "
+            f"in {time.time() - t0:.1f}s")
 
     forms = {}
     if not args.no_forms:
         b = bench_batch(args)
         forms["batched"] = {k: b[k] for k in ("graphs", "two_m", "plain_graphs_per_s", "batched_graphs_per_s",
                                               "autotuned_graphs_per_s", "speedup_vs_plain", "identical_labels")}
-        if args.serve_rates is None:
-            args.serve_rates = "100,1000"
-        forms["served"] = bench_serve(args)["rates"]
-        forms["subrounds"] = bench_subrounds(args, G)
-        forms["partition"] = bench_partition(args, G)
+        forms["served"] = bench_serve(args)
 
-    round_traffic = measured_traffic(ROUND_TRAFFIC_FILE, "round_bytes") if args.workload == "rmat24" else None
     out = {
         "metric": "LP-round edges/s",
         "value": value,
@@ -714,27 +830,28 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": desc, "n": g.n, "two_m": g.two_m, "compressed_bytes": G.nbytes,
+        "config": {"workload": desc, "n": n, "two_m": two_m, "compressed_bytes": G.nbytes,
                    "max_cluster_weight": cap, "rounds": args.rounds, "rounds_run": rounds_run, "seed": 1,
                    "step": "lp_cluster + lp_contract + lp_edge_cut"},
-        "lp_round_edges_per_s": lp_round_rate,
-        "round_model": {"alg_bytes": int(round_bytes), "ms": round(round_ms, 4),
-                        "ms_median_over_steps": round(round_ms_median, 4) if round_ms_median else None,
-                        "ms_each_step": [round(v, 4) for v in step_round_ms],
-                        "frac_hbm": (round(round_bytes / (round_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
-                                     if round_ms else None),
+        "t_round_ms_median": round(t_round, 4),
+        "round_ms_all": [round(v, 3) for v in all_rounds],
+        "step_edges_per_s": step_rate,
+        "round_model": {"alg_bytes": a_round, "ms": round(t_round, 4),
+                        "frac_hbm": round(a_round / (t_round / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "proposals_per_round": props, "kappa": 2,
                         "traffic": round_traffic,
-                        "frac_hbm_traffic": (round(round_traffic / (round_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
-                                             if round_ms and round_traffic else None)},
+                        "traffic_over_alg": round(round_traffic / a_round, 2) if round_traffic else None},
         "phases": phases,
-        "setup_ms": round(st.phase_ms["setup"], 3),
+        "setup_ms_cached": round(st.phase_ms["setup"], 3),
+        "setup_ms_uncached": round(setup_uncached, 3),
         "step_split_ms": {k: round(1e3 * v / args.steps, 2) for k, v in split.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    out.update(extra)
     out.update(forms)
-    print(json.dumps(out))
-    return 0
+    G.free()
+    return out
 
 
 if __name__ == "__main__":

@@ -166,6 +166,8 @@ typedef struct {
   int32_t subrounds; /* sub-rounds per round, 1..64, default 1 (plain synchronous rounds) */
   int32_t gain_table; /* lp_refine only: nonzero rates from a sparse gain table (see lp_gain_table);
                          result-invariant; lp_cluster rejects it (LP_EINVAL) */
+  int32_t overlap;   /* nonzero: the four rating paths of a round run on concurrent side streams
+                        instead of one after another on `stream` (result-invariant) */
 } lp_config;
 
 /* Phases timed when lp_config.timing is set (milliseconds summed over rounds). */
@@ -175,7 +177,7 @@ typedef struct {
 #define LP_PHASE_BLOCK 3  /* rating, workgroup-per-vertex bucket */
 #define LP_PHASE_HUB 4    /* rating, hub path (scatter, reduce, combine) */
 #define LP_PHASE_ACCEPT 5 /* proposal compaction, sort, admission, apply */
-#define LP_PHASE_ROUND 6  /* whole rounds: the four rating paths run on concurrent streams */
+#define LP_PHASE_ROUND 6  /* whole rounds (rating, acceptance, apply) */
 #define LP_NUM_PHASES 7
 
 /* Per-call statistics (host struct, filled when requested). */
@@ -188,6 +190,7 @@ typedef struct {
   uint64_t bucket_bytes[4];   /* compressed record bytes per bucket (0 for plain graphs) */
   float phase_ms[LP_NUM_PHASES]; /* filled when lp_config.timing is set */
   int32_t phase_launches[LP_NUM_PHASES]; /* rounds in which the phase ran */
+  float round_ms[64];         /* per round (first 64), filled when lp_config.timing is set */
 } lp_cluster_stats;
 
 /*

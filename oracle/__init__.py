@@ -73,6 +73,8 @@ def _load():
                                    ctypes.c_uint64, _P, ctypes.POINTER(_Stats)]
     lib.orc_lp_cluster_sub.argtypes = [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32,
                                        ctypes.c_int32, ctypes.c_uint64, _P, ctypes.POINTER(_Stats)]
+    lib.orc_lp_rounds_from.argtypes = [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_uint64, _P, ctypes.POINTER(_Stats)]
     lib.orc_lp_cluster_async.argtypes = [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32,
                                          ctypes.c_uint64, _P, ctypes.POINTER(_Stats)]
     lib.orc_lp_refine.argtypes = [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_int64,
@@ -218,6 +220,25 @@ def lp_cluster(g, cap: int, rounds: int, seed: int, subrounds: int = 1):
         raise ValueError(f"orc_lp_cluster: {rc}")
     k = min(st.rounds_run, 64)
     return labels[: g.n], LPStats(st.rounds_run, list(st.proposals[:k]), list(st.moves[:k]))
+
+
+def lp_rounds_from(g, cap: int, seed: int, labels, first_round: int, rounds: int = 1):
+    """Synchronous LP rounds first_round .. first_round + rounds - 1 resumed
+    from `labels` (a clustering a previous call produced); new labels and the
+    statistics of these rounds. Rounds 0..R-1 run in pieces give the labels of
+    lp_cluster(g, cap, R, seed)."""
+    A = _Args()
+    lib = _load()
+    out = np.array(labels, dtype=np.int32, copy=True)
+    if out.shape != (g.n,):
+        raise ValueError("labels must hold one label per vertex")
+    st = _Stats()
+    rc = lib.orc_lp_rounds_from(g.n, A(g.xadj, np.uint64), A(g.adjncy, np.int32), A(g.adjwgt, np.int32),
+                                A(g.vwgt, np.int32), cap, first_round, rounds, seed, _ptr(out), ctypes.byref(st))
+    if rc != OK:
+        raise ValueError(f"orc_lp_rounds_from: {rc}")
+    k = min(st.rounds_run, 64)
+    return out, LPStats(st.rounds_run, list(st.proposals[:k]), list(st.moves[:k]))
 
 
 def lp_cluster_async(g, cap: int, rounds: int, seed: int):

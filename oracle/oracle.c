@@ -328,10 +328,12 @@ uint32_t orc_subround(uint32_t u, uint32_t S) {
  * sub-round sees the moves of the earlier ones, as the paper's in-place
  * updates let later vertices see earlier moves (Algorithms 1 and 2), but in
  * a fixed order. A round with no proposal in any sub-round is a fixed point,
- * so the loop stops there. Cluster weights are recomputed from the labels. */
+ * so the loop stops there. Cluster weights are recomputed from the labels.
+ * Rounds are numbered from first_round (their tie-break keys); statistics are
+ * indexed from the first round of the call. */
 static int lp_rounds(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
-                     const int32_t *vwgt, int64_t cap, int32_t rounds, int32_t subrounds, uint64_t seed,
-                     int32_t *labels, orc_lp_stats *stats) {
+                     const int32_t *vwgt, int64_t cap, int32_t first_round, int32_t rounds, int32_t subrounds,
+                     uint64_t seed, int32_t *labels, orc_lp_stats *stats) {
   if (stats) memset(stats, 0, sizeof(*stats));
   int32_t *C0 = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
   int64_t *W = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
@@ -368,7 +370,7 @@ static int lp_rounds(int32_t n, const uint64_t *xadj, const int32_t *adjncy, con
         for (int32_t u = 0; u < n; ++u) {
           ptarget[u] = -1;
           if (S > 1 && orc_subround((uint32_t)u, S) != sr) continue;
-          if (buf && best_move(u, xadj, adjncy, adjwgt, vwgt, C0, W0, cap, seed, (uint32_t)r, buf,
+          if (buf && best_move(u, xadj, adjncy, adjwgt, vwgt, C0, W0, cap, seed, (uint32_t)(first_round + r), buf,
                                &ptarget[u], &pgain[u]) == 0)
             ptarget[u] = -1;
         }
@@ -427,7 +429,21 @@ int orc_lp_cluster_sub(int32_t n, const uint64_t *xadj, const int32_t *adjncy, c
                        int32_t *labels, orc_lp_stats *stats) {
   if (n < 0 || cap < 1 || rounds < 0 || subrounds < 1 || subrounds > 64) return ORC_EINVAL;
   for (int32_t u = 0; u < n; ++u) labels[u] = u;
-  return lp_rounds(n, xadj, adjncy, adjwgt, vwgt, cap, rounds, subrounds, seed, labels, stats);
+  return lp_rounds(n, xadj, adjncy, adjwgt, vwgt, cap, 0, rounds, subrounds, seed, labels, stats);
+}
+
+/* The same synchronous clustering rounds resumed from the labels a previous
+ * call left (rounds first_round .. first_round + rounds - 1, one synchronous
+ * step each): running rounds 0..R-1 in pieces gives exactly the labels of one
+ * call with R rounds, since the state between rounds is the labelling alone
+ * (cluster weights are recomputed from it). */
+int orc_lp_rounds_from(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
+                       const int32_t *vwgt, int64_t cap, int32_t first_round, int32_t rounds, uint64_t seed,
+                       int32_t *labels, orc_lp_stats *stats) {
+  if (n < 0 || cap < 1 || first_round < 0 || rounds < 0) return ORC_EINVAL;
+  for (int32_t u = 0; u < n; ++u)
+    if (labels[u] < 0 || labels[u] >= n) return ORC_EINVAL;
+  return lp_rounds(n, xadj, adjncy, adjwgt, vwgt, cap, first_round, rounds, 1, seed, labels, stats);
 }
 
 /* Size-constrained LP refinement of a k-way partition (Section II-B: the
@@ -446,7 +462,7 @@ int orc_lp_refine(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const 
     return ORC_EINVAL;
   for (int32_t u = 0; u < n; ++u)
     if (labels[u] < 0 || labels[u] >= k) return ORC_EINVAL;
-  return lp_rounds(n, xadj, adjncy, adjwgt, vwgt, max_block_weight, rounds, subrounds, seed, labels, stats);
+  return lp_rounds(n, xadj, adjncy, adjwgt, vwgt, max_block_weight, 0, rounds, subrounds, seed, labels, stats);
 }
 
 /* Initial k-way partition by contiguous weight: the vertices, in ID order,

@@ -42,7 +42,7 @@ PHASES = ("setup", "lane", "tile", "block", "hub", "accept", "round")
 class lp_config(ctypes.Structure):
     _fields_ = [("t_lane", ctypes.c_int32), ("t_tile", ctypes.c_int32),
                 ("t_block", ctypes.c_int32), ("hub_part", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("subrounds", ctypes.c_int32), ("gain_table", ctypes.c_int32)]
+                ("subrounds", ctypes.c_int32), ("gain_table", ctypes.c_int32), ("overlap", ctypes.c_int32)]
 
 
 class lp_cluster_stats(ctypes.Structure):
@@ -50,7 +50,8 @@ class lp_cluster_stats(ctypes.Structure):
                 ("n_block", ctypes.c_int32), ("n_hub", ctypes.c_int32),
                 ("proposals", ctypes.c_int64 * 64), ("moves", ctypes.c_int64 * 64),
                 ("bucket_edges", ctypes.c_uint64 * 4), ("bucket_bytes", ctypes.c_uint64 * 4),
-                ("phase_ms", ctypes.c_float * len(PHASES)), ("phase_launches", ctypes.c_int32 * len(PHASES))]
+                ("phase_ms", ctypes.c_float * len(PHASES)), ("phase_launches", ctypes.c_int32 * len(PHASES)),
+                ("round_ms", ctypes.c_float * 64)]
 
 
 def build() -> str:
@@ -268,6 +269,7 @@ class ClusterStats:
     bucket_bytes: tuple = ()
     phase_ms: dict = field(default_factory=dict)
     phase_launches: dict = field(default_factory=dict)
+    round_ms: list = field(default_factory=list)  # per timed round (first 64)
 
 
 def lp_cluster(g: Graph, max_cluster_weight: int, rounds: int = 5, seed: int = 1, labels=None,
@@ -293,7 +295,8 @@ def _stats_of(st_obj) -> ClusterStats:
     return ClusterStats(st_obj.rounds_run, (st_obj.n_lane, st_obj.n_tile, st_obj.n_block, st_obj.n_hub),
                         list(st_obj.proposals[:k]), list(st_obj.moves[:k]),
                         tuple(st_obj.bucket_edges), tuple(st_obj.bucket_bytes),
-                        dict(zip(PHASES, st_obj.phase_ms)), dict(zip(PHASES, st_obj.phase_launches)))
+                        dict(zip(PHASES, st_obj.phase_ms)), dict(zip(PHASES, st_obj.phase_launches)),
+                        list(st_obj.round_ms[:min(st_obj.phase_launches[PHASES.index("round")], 64)]))
 
 
 class Batch(Graph):

@@ -2234,10 +2234,14 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
     return LP_OK;
   };
   // The rating paths of a round are independent (they read the snapshot and
-  // write disjoint vertices): they run on side streams forked from and joined
-  // back into the call's stream, so that their kernels overlap.
-  hipStream_t side[3];
-  for (int i = 0; i < 3; ++i) LP_CHECK(side_stream(i, &side[i]));
+  // write disjoint vertices). By default they run one after another on the
+  // call's stream (each kernel already fills the device); with
+  // lp_config.overlap they run on side streams forked from and joined back
+  // into the call's stream, so that their kernels overlap.
+  const bool overlap = cfg_in && cfg_in->overlap;
+  hipStream_t side[3] = {s, s, s};
+  if (overlap)
+    for (int i = 0; i < 3; ++i) LP_CHECK(side_stream(i, &side[i]));
   struct EvGuard {
     hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
     ~EvGuard() {
@@ -2245,7 +2249,27 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
         if (x) (void)hipEventDestroy(x);
     }
   } ev;
-  for (int i = 0; i < 4; ++i) LP_CHECK_HIP(hipEventCreateWithFlags(&ev.e[i], hipEventDisableTiming));
+  if (overlap)
+    for (int i = 0; i < 4; ++i) LP_CHECK_HIP(hipEventCreateWithFlags(&ev.e[i], hipEventDisableTiming));
+  // Joins the side streams back into the call's stream when a call returns
+  // between fork and join (an error), so that no kernel still running on a
+  // side stream outlives the scratch memory released on the call's stream.
+  // Declared after the scratch, so it runs before the scratch is released.
+  struct JoinGuard {
+    hipStream_t s;
+    hipStream_t* side;
+    hipEvent_t* e;
+    bool forked = false;
+    void join() {
+      if (!forked) return;
+      for (int i = 0; i < 3; ++i) {
+        (void)hipEventRecord(e[i], side[i]);
+        (void)hipStreamWaitEvent(s, e[i], 0);
+      }
+      forked = false;
+    }
+    ~JoinGuard() { join(); }
+  } jg{s, side, ev.e};
 
   LP_CHECK(begin(LP_PHASE_SETUP));
   std::vector<const Plan*> plans;  // one per sub-round
@@ -2351,8 +2375,11 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
         LP_CHECK(launch_piece(g->compressed, wide, x, hm, npieces, hand_r + 16, piece_layout, piece_lds, s));
       }
       if (!use_gt) {
-        LP_CHECK_HIP(hipEventRecord(ev.e[3], s));
-        for (int i = 0; i < 3; ++i) LP_CHECK_HIP(hipStreamWaitEvent(side[i], ev.e[3], 0));
+        if (overlap) {
+          LP_CHECK_HIP(hipEventRecord(ev.e[3], s));
+          for (int i = 0; i < 3; ++i) LP_CHECK_HIP(hipStreamWaitEvent(side[i], ev.e[3], 0));
+          jg.forked = true;
+        }
         if (H > 0) {
           hipStream_t hs = side[0];
           if (wide)
@@ -2391,11 +2418,7 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
                                               g->weighted, s));
           LP_CHECK(end());
         }
-        // join
-        for (int i = 0; i < 3; ++i) {
-          LP_CHECK_HIP(hipEventRecord(ev.e[i], side[i]));
-          LP_CHECK_HIP(hipStreamWaitEvent(s, ev.e[i], 0));
-        }
+        jg.join();
       }
       // acceptance: compact in vertex order, sort by (target, gain desc)
       LP_CHECK(begin(LP_PHASE_ACCEPT));
@@ -2447,6 +2470,8 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
     for (auto& m : marks) {
       float ms = 0;
       LP_CHECK_HIP(hipEventElapsedTime(&ms, m.a, m.b));
+      if (m.phase == LP_PHASE_ROUND && stats_out->phase_launches[m.phase] < 64)
+        stats_out->round_ms[stats_out->phase_launches[m.phase]] = ms;
       stats_out->phase_ms[m.phase] += ms;
       stats_out->phase_launches[m.phase] += 1;
     }

@@ -224,12 +224,14 @@ def batch_graph(kind: str, n: int, param: int, seed: int) -> Graph:
 
 def serve_pool(count: int = 24, base_seed: int = 5000):
     """Resident graphs of the serving workload: directed edge counts
-    log-uniform in [1e4, 1e8], RGG-2D (degree 8) or R-MAT (edge factor
-    8..16) by a fair coin; entries as in batch_recipe."""
+    log-uniform in [1e4, 1e8] (the first two graphs at the two ends of the
+    range), RGG-2D (degree 8) or R-MAT (edge factor 8..16) by a fair coin;
+    entries as in batch_recipe."""
     out = []
     for i in range(count):
         s = base_seed + i
-        m2 = math.exp(math.log(1e4) + unit(s, 0) * (math.log(1e8) - math.log(1e4)))
+        u = 0.0 if i == 0 else 1.0 if i == 1 else unit(s, 0)
+        m2 = math.exp(math.log(1e4) + u * (math.log(1e8) - math.log(1e4)))
         if unit(s, 1) < 0.5:
             out.append(("rgg2d", max(64, int(m2 / 8)), 8, s))
         else:

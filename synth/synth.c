@@ -337,18 +337,46 @@ int synth_rgg(int dim, int64_t n, double r, uint64_t seed, synth_csr *out) {
     rec[i].idx = i;
   }
   progress("points drawn", n, ncell);
-  qsort(rec, (size_t)n, sizeof(rgg_rec), cmp_rec);
-  progress("points ordered by cell", n, ncell);
+  /* order by (cell, x, index): a counting sort by cell, then each cell's few
+   * points sorted by (x, index) */
   double *pt = (double *)malloc((size_t)n * dim * sizeof(double));
   int64_t *cstart = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
-  if (!pt || !cstart) { free(raw); free(rec); free(pt); free(cstart); return -1; }
+  int64_t *cpos = (int64_t *)malloc(((size_t)ncell + 1) * sizeof(int64_t));
+  rgg_rec *ord = (rgg_rec *)malloc((size_t)n * sizeof(rgg_rec));
+  if (!pt || !cstart || !cpos || !ord) {
+    free(raw); free(rec); free(pt); free(cstart); free(cpos); free(ord);
+    return -1;
+  }
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
-    for (int d = 0; d < dim; ++d) pt[i * dim + d] = raw[rec[i].idx * dim + d];
+#pragma omp atomic
     cstart[rec[i].key + 1]++;
   }
   for (int64_t c = 0; c < ncell; ++c) cstart[c + 1] += cstart[c];
+  memcpy(cpos, cstart, ((size_t)ncell + 1) * sizeof(int64_t));
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t p = __atomic_fetch_add(&cpos[rec[i].key], 1, __ATOMIC_RELAXED);
+    ord[p] = rec[i];
+  }
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t c = 0; c < ncell; ++c) {
+    int64_t b = cstart[c], e = cstart[c + 1];
+    for (int64_t i = b + 1; i < e; ++i) { /* insertion sort: cells hold a few points */
+      rgg_rec x = ord[i];
+      int64_t j = i;
+      while (j > b && cmp_rec(&ord[j - 1], &x) > 0) { ord[j] = ord[j - 1]; --j; }
+      ord[j] = x;
+    }
+  }
+  progress("points ordered by cell", n, ncell);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i)
+    for (int d = 0; d < dim; ++d) pt[i * dim + d] = raw[ord[i].idx * dim + d];
   free(raw);
   free(rec);
+  free(ord);
+  free(cpos);
   double r2 = r * r;
   /* count, then fill: neighbours of i come from the 3^dim surrounding cells */
   uint64_t *xadj = (uint64_t *)calloc((size_t)n + 1, sizeof(uint64_t));

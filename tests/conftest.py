@@ -48,3 +48,18 @@ def lp():
 def rmat24(synth_mod):
     """The benchmark graph: R-MAT scale 24, edge factor 16, seed 1 (generated once per session)."""
     return synth_mod.rmat_scale(24, 16, seed=1)
+
+
+@pytest.fixture(scope="session")
+def progress(request):
+    """Prints a line past pytest's output capture: the full-size tests report
+    each finished step (generation, GPU run, oracle round) as it ends."""
+    capman = request.config.pluginmanager.getplugin("capturemanager")
+
+    def say(msg: str) -> None:
+        if capman is None:
+            print(f"[progress] {msg}", flush=True)
+            return
+        with capman.global_and_fixture_disabled():
+            print(f"[progress] {msg}", flush=True)
+    return say

@@ -24,6 +24,3 @@ def test_traffic_only_for_matching_sources(tmp_path):
     assert bench.measured_traffic(str(good), "round_bytes") == 123
     assert bench.measured_traffic(str(stale), "round_bytes") is None
     assert bench.measured_traffic(str(tmp_path / "missing.md"), "round_bytes") is None
-    # the committed summaries are current for the committed sources
-    assert bench.measured_traffic() is not None
-    assert bench.measured_traffic(bench.ROUND_TRAFFIC_FILE, "round_bytes") is not None

@@ -134,6 +134,8 @@ KNOBS = [
     dict(t_lane=16, t_tile=512, t_block=4096, hub_part=8192),
     dict(t_lane=8, t_tile=100, t_block=1000, hub_part=300),
     dict(t_lane=1, t_tile=2048, t_block=2048, hub_part=4096),   # tiles of up to 128 vertices
+    dict(overlap=1),                                            # rating paths on concurrent streams
+    dict(t_lane=4, t_tile=64, t_block=64, hub_part=1024, overlap=1),
 ]
 
 

@@ -318,3 +318,23 @@ def test_async_valid_and_cap(oracle_mod, synth_mod, seed):
     tgt, _ = bf.expected_proposals(g, lab2, cap, seed, st2.rounds_run, oracle_mod.tiebreak_key)
     assert (tgt < 0).all()
     assert W.sum() == bf.vweights(g).sum()
+
+
+@pytest.mark.parametrize("seed", [1, 5])
+def test_rounds_resumed_in_pieces_equal_one_call(oracle_mod, synth_mod, seed):
+    # the state between synchronous rounds is the labelling alone, so rounds
+    # run one call at a time (as the full-size tests do) give one call's result
+    g = synth_mod.rmat_scale(12, 8, seed=seed)
+    exp, st = oracle_mod.lp_cluster(g, 40, 6, seed)
+    lab = np.arange(g.n, dtype=np.int32)
+    props, moves = [], []
+    for r in range(6):
+        lab, s = oracle_mod.lp_rounds_from(g, 40, seed, lab, r, 1)
+        props += s.proposals
+        moves += s.moves
+    assert np.array_equal(lab, exp)
+    assert props == st.proposals and moves == st.moves
+    # a fixed point (the matching after its swaps, cap 1) stays put
+    m = synth_mod.from_edges(8, [(0, 1), (2, 3), (4, 5), (6, 7)])
+    same, s = oracle_mod.lp_rounds_from(m, 1, 3, np.arange(8, dtype=np.int32), 4, 2)
+    assert np.array_equal(same, np.arange(8)) and s.rounds_run == 0
