@@ -22,12 +22,13 @@
  *    lp_contract) synchronise the stream before returning; so do the calls
  *    that check their arguments on the device (lp_refine, lp_gain_table_create,
  *    lp_gain_table_move).
- *  - Scratch memory comes from the library's per-device memory cache in
- *    the order of `stream` and goes back to it before the call returns;
- *    memory released by one call is handed to the next (at once on the same
- *    stream, on another stream once the release has completed) instead of
- *    being returned to HIP, up to a quarter of the device's memory
- *    (lp_trim_memory returns it).
+ *  - Scratch memory comes from the caller's allocator when one is set
+ *    (lp_set_allocator), else from the library's per-device memory cache,
+ *    in the order of `stream`, and goes back to it before the call returns.
+ *    The cache hands memory released by one call to the next (at once on
+ *    the same stream, on another stream once the release has completed)
+ *    instead of returning it to HIP, keeping up to a quarter of the device's
+ *    memory (lp_trim_memory returns it; lp_memory_info reports it).
  *  - Errors are returned as lp_status codes; no exception crosses the ABI.
  *    Argument errors are detected before any work is enqueued. A device
  *    fault surfaces as LP_EDEVICE from the next synchronising call.
@@ -388,6 +389,40 @@ void lp_gain_table_free(lp_gain_table *t);
  * fill the cache again. For callers that share the device with other
  * allocators, e.g. between phases of a job. */
 void lp_trim_memory(void);
+
+/*
+ * The caller's device allocator (the boundary's allocator of scratch memory;
+ * e.g. a framework's caching allocator). alloc returns `bytes` of device
+ * memory on the current device usable in the order of `stream` (NULL when
+ * out of memory: the call then fails with LP_ENOMEM); free releases a block
+ * in the order of `stream` (the stream of the library's last use of it).
+ * Both are called from the thread of the library call, with no lock of the
+ * library held, and must be thread-safe if several threads call the library.
+ */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *stream, void *ctx);
+  void (*free)(void *ptr, void *stream, void *ctx);
+  void *ctx;
+} lp_allocator;
+
+/*
+ * lp_set_allocator — every later scratch allocation, and every buffer of a
+ * handle made inside a call (lp_contract's coarse graph, batch handles),
+ * comes from *a (copied; NULL restores the library's memory cache). Blocks
+ * are always released to the allocator that made them. Handles made by
+ * lp_compress and lp_graph_from_csr keep plain device allocations. Call it
+ * while no other library call is running. LP_EINVAL if a function is NULL.
+ */
+lp_status lp_set_allocator(const lp_allocator *a);
+
+/*
+ * lp_memory_info — device memory the library holds: bytes of the current
+ * device's memory cache handed out to calls and handles (*live_bytes) and
+ * kept for reuse (*cached_bytes), and bytes obtained from the caller's
+ * allocator and not yet released (*external_bytes, all devices). Any output
+ * may be NULL.
+ */
+lp_status lp_memory_info(uint64_t *live_bytes, uint64_t *cached_bytes, uint64_t *external_bytes);
 
 /* Frees a handle (NULL is ignored). A handle with plain allocations waits
  * for the device to be idle first; a handle made on a stream returns its

@@ -45,6 +45,14 @@ class lp_config(ctypes.Structure):
                 ("subrounds", ctypes.c_int32), ("gain_table", ctypes.c_int32), ("overlap", ctypes.c_int32)]
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class lp_allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
 class lp_cluster_stats(ctypes.Structure):
     _fields_ = [("rounds_run", ctypes.c_int32), ("n_lane", ctypes.c_int32), ("n_tile", ctypes.c_int32),
                 ("n_block", ctypes.c_int32), ("n_hub", ctypes.c_int32),
@@ -99,6 +107,10 @@ def _load():
     lib.lp_graph_free.restype = None
     lib.lp_trim_memory.argtypes = []
     lib.lp_trim_memory.restype = None
+    lib.lp_set_allocator.argtypes = [ctypes.POINTER(lp_allocator)]
+    lib.lp_set_allocator.restype = S
+    lib.lp_memory_info.argtypes = [ctypes.POINTER(ctypes.c_uint64)] * 3
+    lib.lp_memory_info.restype = S
     lib.lp_batch_create.argtypes = [ctypes.c_int32, _P, _P, ctypes.POINTER(_P)]
     lib.lp_batch_create.restype = S
     lib.lp_batch_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int32), _P]
@@ -132,11 +144,48 @@ def _load():
     return lib
 
 
+def _torch_alloc(nbytes, stream, ctx):
+    try:
+        return _torch()._C._cuda_cudaCachingAllocator_raw_alloc(int(nbytes), int(stream or 0))
+    except RuntimeError:  # out of memory: the library call fails with LP_ENOMEM
+        return None
+
+
+def _torch_free(ptr, stream, ctx):
+    _torch()._C._cuda_cudaCachingAllocator_raw_delete(int(ptr))
+
+
+_TORCH_ALLOCATOR = None  # keeps the callbacks alive while installed
+
+
+def use_torch_allocator(on: bool = True) -> None:
+    """Route the library's scratch memory through torch's caching allocator
+    (lp_set_allocator), or back to the library's own memory cache. Every
+    allocation then costs a Python callback (a few microseconds)."""
+    global _TORCH_ALLOCATOR
+    lib = _load()
+    if on:
+        a = lp_allocator(_ALLOC_FN(_torch_alloc), _FREE_FN(_torch_free), None)
+        _check(lib.lp_set_allocator(ctypes.byref(a)), "lp_set_allocator")
+        _TORCH_ALLOCATOR = a
+    else:
+        _check(lib.lp_set_allocator(None), "lp_set_allocator")
+        _TORCH_ALLOCATOR = None
+
+
+def memory_info() -> dict:
+    """Device memory the library holds (lp_memory_info): cache blocks in use,
+    cache blocks kept for reuse, and blocks from the caller's allocator."""
+    live, cached, ext = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(_load().lp_memory_info(ctypes.byref(live), ctypes.byref(cached), ctypes.byref(ext)), "lp_memory_info")
+    return {"live": live.value, "cached": cached.value, "external": ext.value}
+
+
 def exported_symbols() -> list[str]:
     return ["lp_strerror", "lp_version", "lp_compress", "lp_graph_from_csr", "lp_graph_info",
             "lp_graph_export", "lp_decompress", "lp_cluster", "lp_cluster_ex", "lp_contract",
             "lp_edge_cut", "lp_graph_free", "lp_batch_create", "lp_batch_info", "lp_batch_cluster_ex",
-            "lp_batch_cluster", "lp_trim_memory", "lp_initial_partition", "lp_project", "lp_refine",
+            "lp_batch_cluster", "lp_trim_memory", "lp_set_allocator", "lp_memory_info", "lp_initial_partition", "lp_project", "lp_refine",
             "lp_refine_ex", "lp_gain_table_create", "lp_gain_table_affinity", "lp_gain_table_move",
             "lp_gain_table_info", "lp_gain_table_free"]
 

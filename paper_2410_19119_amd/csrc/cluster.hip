@@ -821,8 +821,14 @@ struct HubMeta {
   const int2* pieces;        // (hub, piece within the hub)
   const int2* tasks;         // (hub, partition)
   HubStream* streams;        // kHubStreams per piece
-  int32_t* rec_c;            // records: cluster
-  void* rec_r;               // records: partial rating (int32 or int64)
+  int32_t* rec_c;            // records: cluster (packed: cluster << rbits | partial rating)
+  void* rec_r;               // records: partial rating (int32 or int64); unused when packed
+  // unit edge weights: one 32-bit word per record, the cluster in the high
+  // 32 - rbits bits and a partial rating of at most 2^rbits - 1 in the low
+  // ones (a larger rating takes several records, so a piece still needs at
+  // most one record per neighbour)
+  int32_t packed;
+  uint32_t rbits;
   uint32_t* poff;
   int64_t* res_r;            // per task
   uint64_t* res_key;
@@ -1110,9 +1116,12 @@ __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta
       if (vi[k] >= 0) tile_insert<V>(keys, vals, 0, S, nb[k], (V)wt[k]);
     __syncthreads();
     // distinct clusters grouped by partition
+    const uint32_t rmax = hm.packed ? (1u << hm.rbits) - 1u : 0u;
     for (uint32_t q = tid; q < S; q += NT) {
       const int32_t c = keys[q];
-      if (c != kEmpty) atomicAdd(&sh.hist[part_hash((uint32_t)c) % P], 1u);
+      if (c == kEmpty) continue;
+      const uint32_t nr = hm.packed ? ((uint32_t)vals[q] + rmax - 1u) / rmax : 1u;
+      atomicAdd(&sh.hist[part_hash((uint32_t)c) % P], nr);
     }
     __syncthreads();
     {
@@ -1134,9 +1143,20 @@ __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta
     for (uint32_t q = tid; q < S; q += NT) {
       const int32_t c = keys[q];
       if (c == kEmpty) continue;
-      const uint32_t slot = atomicAdd(&sh.hist[part_hash((uint32_t)c) % P], 1u);
-      hm.rec_c[rbase + slot] = c;
-      rec_r[rbase + slot] = vals[q];
+      if (hm.packed) {
+        uint32_t r = (uint32_t)vals[q];
+        const uint32_t nr = (r + rmax - 1u) / rmax;
+        uint32_t slot = atomicAdd(&sh.hist[part_hash((uint32_t)c) % P], nr);
+        for (; r > 0; ++slot) {
+          const uint32_t part = r < rmax ? r : rmax;
+          hm.rec_c[rbase + slot] = (int32_t)(((uint32_t)c << hm.rbits) | part);
+          r -= part;
+        }
+      } else {
+        const uint32_t slot = atomicAdd(&sh.hist[part_hash((uint32_t)c) % P], 1u);
+        hm.rec_c[rbase + slot] = c;
+        rec_r[rbase + slot] = vals[q];
+      }
     }
     __syncthreads();
   }
@@ -1243,8 +1263,14 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta 
                   else hi = mid;
                 }
                 const uint64_t r = rb0 + (uint64_t)(kb + lo) * kHubPiece + sm.ra[lo] + (uint32_t)(j - sm.pre[lo]);
-                cc[q] = hm.rec_c[r];
-                ww[q] = rec_r[r];
+                if (hm.packed) {
+                  const uint32_t pw = (uint32_t)hm.rec_c[r];
+                  cc[q] = (int32_t)(pw >> hm.rbits);
+                  ww[q] = (V)(pw & ((1u << hm.rbits) - 1u));
+                } else {
+                  cc[q] = hm.rec_c[r];
+                  ww[q] = rec_r[r];
+                }
               }
             }
 #pragma unroll
@@ -2285,8 +2311,12 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
   }
   HubMeta hbuf{};  // per-call hub buffers, shared by the sub-rounds
   if (hmax > 0) {
+    // packed records for unit edge weights: a cluster ID below n needs
+    // bitlen(n - 1) bits, the rest of the word holds the partial rating
+    hbuf.packed = (!g->weighted && !wide) ? 1 : 0;
+    hbuf.rbits = (uint32_t)(32 - std::max(1, bitlen((uint64_t)(n - 1))));
     hbuf.rec_c = sc.alloc<int32_t>(rsum);
-    hbuf.rec_r = wide ? (void*)sc.alloc<int64_t>(rsum) : (void*)sc.alloc<int32_t>(rsum);
+    hbuf.rec_r = hbuf.packed ? nullptr : wide ? (void*)sc.alloc<int64_t>(rsum) : (void*)sc.alloc<int32_t>(rsum);
     hbuf.poff = sc.alloc<uint32_t>(psum);
     hbuf.res_r = sc.alloc<int64_t>(tmax);
     hbuf.res_key = sc.alloc<uint64_t>(tmax);
@@ -2353,6 +2383,8 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
       HubMeta hm = plan->hm;
       hm.rec_c = hbuf.rec_c;
       hm.rec_r = hbuf.rec_r;
+      hm.packed = hbuf.packed;
+      hm.rbits = hbuf.rbits;
       hm.poff = hbuf.poff;
       hm.res_r = hbuf.res_r;
       hm.res_key = hbuf.res_key;

@@ -516,6 +516,13 @@ extern "C" void lp_graph_free(lp_graph* g) {
 
 extern "C" void lp_trim_memory(void) { cache_trim_all(); }
 
+extern "C" lp_status lp_set_allocator(const lp_allocator* a) { return set_allocator(a); }
+
+extern "C" lp_status lp_memory_info(uint64_t* live_bytes, uint64_t* cached_bytes, uint64_t* external_bytes) {
+  memory_info(live_bytes, cached_bytes, external_bytes);
+  return LP_OK;
+}
+
 extern "C" const char* lp_strerror(lp_status s) {
   switch (s) {
     case LP_OK: return "ok";

@@ -29,6 +29,11 @@ void* cache_alloc(size_t bytes, hipStream_t s);
 void cache_free(void* p, hipStream_t s);
 // Frees every cached block of every device (waits for each device first).
 void cache_trim_all();
+// The caller's allocator for all later cache_alloc calls (nullptr: the cache).
+lp_status set_allocator(const lp_allocator* a);
+// Bytes of the current device handed out and kept by the cache, and bytes
+// handed out by the caller's allocator (all devices).
+void memory_info(uint64_t* live, uint64_t* cached, uint64_t* external);
 
 // Stream-ordered scratch allocations from the cache, released (on the same
 // stream) when the object goes out of scope. A failed allocation sets

@@ -36,7 +36,7 @@ struct DevCache {
   std::multimap<size_t, CBlock> free_;    // by size
   std::unordered_map<void*, size_t> live;  // handed-out blocks
   std::vector<hipEvent_t> spare;           // events of reused blocks
-  size_t cached = 0, limit = 0;
+  size_t cached = 0, limit = 0, live_bytes = 0;
 };
 
 constexpr int kCacheDevices = 64;
@@ -50,6 +50,13 @@ DevCache* cache_of(int* dev_out) {
   }
   if (dev_out) *dev_out = dev;
   return &caches[dev];
+}
+
+// LPGPU_CACHE_LOG set: every HIP allocation and release of the cache is
+// reported on stderr.
+bool cache_log() {
+  static const bool on = getenv("LPGPU_CACHE_LOG") != nullptr;
+  return on;
 }
 
 // Sizes are rounded up to eight classes per power of two (at least 512
@@ -67,6 +74,7 @@ void trim_locked(DevCache& c, size_t keep) {
   for (auto it = c.free_.end(); c.cached > keep && it != c.free_.begin();) {
     --it;
     if (hipEventQuery(it->second.ev) != hipSuccess) continue;
+    if (cache_log()) fprintf(stderr, "[lpgpu-cache] hipFree %zu (cached %zu)\n", it->first, c.cached);
     (void)hipFree(it->second.p);
     (void)hipEventDestroy(it->second.ev);
     c.cached -= it->first;
@@ -75,9 +83,38 @@ void trim_locked(DevCache& c, size_t keep) {
   clear_error();
 }
 
+// The caller's allocator (lp_set_allocator): when set, every scratch block
+// and every buffer of a handle made inside a call comes from it. Blocks keep
+// the allocator that made them, so switching allocators never mixes them up.
+// The caller's functions are called without any lock of the library held.
+struct ExtBlock {
+  size_t bytes;
+  lp_allocator a;
+};
+std::mutex g_ext_mu;
+lp_allocator g_ext{};
+bool g_ext_on = false;
+std::unordered_map<void*, ExtBlock> g_ext_live;
+uint64_t g_ext_bytes = 0;
+
 }  // namespace
 
 void* cache_alloc(size_t bytes, hipStream_t s) {
+  lp_allocator a{};
+  bool ext = false;
+  {
+    std::lock_guard<std::mutex> lock(g_ext_mu);
+    ext = g_ext_on;
+    a = g_ext;
+  }
+  if (ext) {
+    void* p = a.alloc(bytes ? bytes : 1, (void*)s, a.ctx);
+    if (!p) return nullptr;
+    std::lock_guard<std::mutex> lock(g_ext_mu);
+    g_ext_live[p] = ExtBlock{bytes, a};
+    g_ext_bytes += bytes;
+    return p;
+  }
   DevCache* c = cache_of(nullptr);
   if (!c) return nullptr;
   const size_t need = size_class(bytes);
@@ -103,6 +140,7 @@ void* cache_alloc(size_t bytes, hipStream_t s) {
     c->spare.push_back(b.ev);
     c->cached -= it->first;
     c->live[p] = it->first;
+    c->live_bytes += it->first;
     c->free_.erase(it);
     return p;
   }
@@ -110,6 +148,7 @@ void* cache_alloc(size_t bytes, hipStream_t s) {
   if (hipMalloc(&p, need) != hipSuccess) {
     clear_error();
     // out of memory: wait for the device, empty the cache, try once more
+    if (cache_log()) fprintf(stderr, "[lpgpu-cache] out of memory for %zu bytes: emptying %zu cached\n", need, c->cached);
     (void)hipDeviceSynchronize();
     trim_locked(*c, 0);
     if (hipMalloc(&p, need) != hipSuccess) {
@@ -117,12 +156,32 @@ void* cache_alloc(size_t bytes, hipStream_t s) {
       return nullptr;
     }
   }
+  if (cache_log()) fprintf(stderr, "[lpgpu-cache] hipMalloc %zu (cached %zu)\n", need, c->cached);
   c->live[p] = need;
+  c->live_bytes += need;
   return p;
 }
 
 void cache_free(void* p, hipStream_t s) {
   if (!p) return;
+  {
+    ExtBlock b{};
+    bool ext = false;
+    {
+      std::lock_guard<std::mutex> lock(g_ext_mu);
+      auto it = g_ext_live.find(p);
+      if (it != g_ext_live.end()) {
+        b = it->second;
+        ext = true;
+        g_ext_bytes -= b.bytes;
+        g_ext_live.erase(it);
+      }
+    }
+    if (ext) {
+      b.a.free(p, (void*)s, b.a.ctx);
+      return;
+    }
+  }
   DevCache* c = cache_of(nullptr);
   if (!c) return;
   std::lock_guard<std::mutex> lock(c->mu);
@@ -130,6 +189,7 @@ void cache_free(void* p, hipStream_t s) {
   if (lv == c->live.end()) return;  // not a cache block
   const size_t size = lv->second;
   c->live.erase(lv);
+  c->live_bytes -= size;
   hipEvent_t ev = nullptr;
   if (!c->spare.empty()) {
     ev = c->spare.back();
@@ -152,6 +212,31 @@ void cache_free(void* p, hipStream_t s) {
   c->free_.insert({size, CBlock{p, s, ev}});
   c->cached += size;
   if (c->cached > c->limit) trim_locked(*c, c->limit);
+}
+
+lp_status set_allocator(const lp_allocator* a) {
+  if (a && (!a->alloc || !a->free)) return LP_EINVAL;
+  std::lock_guard<std::mutex> lock(g_ext_mu);
+  g_ext_on = a != nullptr;
+  g_ext = a ? *a : lp_allocator{};
+  return LP_OK;
+}
+
+void memory_info(uint64_t* live, uint64_t* cached, uint64_t* external) {
+  DevCache* c = cache_of(nullptr);
+  uint64_t l = 0, k = 0, e = 0;
+  if (c) {
+    std::lock_guard<std::mutex> lock(c->mu);
+    l = c->live_bytes;
+    k = c->cached;
+  }
+  {
+    std::lock_guard<std::mutex> lock(g_ext_mu);
+    e = g_ext_bytes;
+  }
+  if (live) *live = l;
+  if (cached) *cached = k;
+  if (external) *external = e;
 }
 
 void cache_trim_all() {

@@ -31,7 +31,7 @@ import time
 from collections import deque
 from dataclasses import dataclass, field
 
-from . import (Graph, coarsen, coarsen_params, lp_batch_cluster, lp_contract)
+from . import (Graph, coarsen, coarsen_params, lp_batch_cluster, lp_contract, memory_info)
 
 
 def job_bytes(g: Graph) -> int:
@@ -120,7 +120,14 @@ class Server:
     stream, so a step of small jobs never waits for the level of a big one,
     and the two lanes' kernels share the device; this lowers the median
     latency but costs throughput, so the default is one lane. The slot limit
-    holds per lane; the memory budget is shared."""
+    holds per lane; the memory budget is shared by the lanes.
+
+    Admission charges every job its estimate (job_bytes) against the budget
+    left after the resident graphs, and compares with the larger of the
+    admitted jobs' estimates and the device memory the library actually holds
+    (blocks in use, blocks its cache keeps for reuse, and blocks from a
+    caller's allocator). Only a job that arrives while no job is active in
+    any lane may exceed the budget on its own."""
 
     def __init__(self, pool: list[Graph], budget_bytes: int = 200 * 10**9, max_active: int = 64,
                  rounds: int = 5, max_levels: int = 32, keep_labels: bool = False, split_edges: int = 0):
@@ -136,6 +143,7 @@ class Server:
         self._mu = threading.Lock()
         self._used = 0
         self._active = 0
+        self.peak_used = 0  # largest sum of admitted estimates
 
     def run(self, reqs: list[Request]) -> list[Result]:
         if self.split_edges > 0:
@@ -165,13 +173,17 @@ class Server:
             raise errors[0]
         return sorted(results, key=lambda r: r.rid)
 
-    def _admit(self, est: int, lane_active: int) -> bool:
+    def _admit(self, est: int) -> bool:
         with self._mu:
-            if self._used + est > self.budget and lane_active:
-                return False
+            if self._active > 0:
+                m = memory_info()
+                held = max(self._used, m["live"] + m["cached"] + m["external"])
+                if held + est > self.budget:
+                    return False
             self._used += est
             self._active += 1
             self.peak_active = max(self.peak_active, self._active)
+            self.peak_used = max(self.peak_used, self._used)
             return True
 
     def _release(self, est: int) -> None:
@@ -193,7 +205,7 @@ class Server:
                     r = pending[0]
                     g = self.pool[r.graph]
                     est = job_bytes(g)
-                    if not self._admit(est, len(active)):
+                    if not self._admit(est):
                         break
                     pending.popleft()
                     n_target, cap = coarsen_params(g.n, g.total_vwgt)

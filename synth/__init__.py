@@ -181,22 +181,19 @@ def random_small(n: int, p_edge: float, seed: int) -> Graph:
 
 
 def from_edges(n: int, edges, weights=None) -> Graph:
-    """Symmetric CSR from an undirected edge list (u != v, no duplicates)."""
-    adj = [[] for _ in range(n)]
-    for i, (u, v) in enumerate(edges):
-        w = 1 if weights is None else int(weights[i])
-        adj[u].append((v, w))
-        adj[v].append((u, w))
+    """Symmetric CSR from an undirected edge list (u != v, no duplicates);
+    every neighbourhood sorted by (neighbour, weight)."""
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+    w = np.ones(len(e), dtype=np.int64) if weights is None else np.asarray(weights, dtype=np.int64)
+    src = np.concatenate([e[:, 0], e[:, 1]])
+    dst = np.concatenate([e[:, 1], e[:, 0]])
+    ww = np.concatenate([w, w])
+    order = np.lexsort((ww, dst, src))
     xadj = np.zeros(n + 1, dtype=np.uint64)
-    ids, wts = [], []
-    for u in range(n):
-        nb = sorted(adj[u])
-        xadj[u + 1] = xadj[u] + len(nb)
-        ids.extend(v for v, _ in nb)
-        wts.extend(w for _, w in nb)
-    g = Graph(n, xadj, np.array(ids, dtype=np.int32))
+    xadj[1:] = np.cumsum(np.bincount(src, minlength=n)[:n], dtype=np.uint64)
+    g = Graph(n, xadj, dst[order].astype(np.int32))
     if weights is not None:
-        g.adjwgt = np.array(wts, dtype=np.int32)
+        g.adjwgt = ww[order].astype(np.int32)
     return g
 
 

@@ -301,3 +301,21 @@ def test_contract_light_to_heavy_handover(lp, oracle_mod, synth_mod, labels_kind
         assert np.array_equal(_np(x).view(np.uint64), cg.xadj)
         assert np.array_equal(_np(a), cg.adjncy) and np.array_equal(_np(w), cg.adjwgt)
         assert np.array_equal(_np(v), cg.vwgt) and np.array_equal(_np(M), mp)
+
+
+@pytest.mark.parametrize("knobs,compressed", [(None, True), (dict(t_lane=1, t_tile=1, t_block=1, hub_part=256), True),
+                                              (None, False)])
+def test_packed_hub_records_split_large_ratings(lp, oracle_mod, synth_mod, knobs, compressed):
+    # 2^27 vertex IDs leave 5 bits of a packed 32-bit hub record for the
+    # partial rating (at most 31): once the leaves of a star gather in one
+    # cluster, each 4000-neighbour piece of the centre rates it up to 4000,
+    # which takes many records per cluster
+    n = 1 << 27
+    c = n - 25001
+    g = synth_mod.from_edges(n, [(c, v) for v in range(c + 1, n)])
+    G = _gpu_graph(lp, g, compressed)
+    exp, ost = oracle_mod.lp_cluster(g, 30000, 4, 3)
+    lab, st = lp.lp_cluster(G, 30000, 4, 3, config=knobs, stats=True)
+    assert np.array_equal(_np(lab), exp)
+    assert st.proposals == ost.proposals and st.moves == ost.moves
+    G.free()

@@ -28,6 +28,10 @@ def test_served_results_equal_alone(lp, synth_mod, slots, budget, split):
     assert [r.rid for r in res] == list(range(len(reqs)))
     if slots > 3 and budget > 1:
         assert srv.peak_active > 1  # jobs really shared steps
+    if budget == 1:
+        assert srv.peak_active == 1  # the budget holds across lanes: one job at a time
+    # admitted estimates stay within the budget, except a job admitted alone
+    assert srv.peak_used <= max(srv.budget, max(serve.job_bytes(g) for g in pool))
     for r, q in zip(res, reqs):
         levels, final, _, _ = lp.coarsen(pool[q.graph], seed=q.seed)
         assert len(r.labels) == len(levels) and r.final_n == final.n, q.rid
