@@ -67,6 +67,9 @@ def _load():
     lib.orc_compress_bound.restype = ctypes.c_uint64
     lib.orc_compress.argtypes = [ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_uint64)]
     lib.orc_decompress.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_int, _P, _P, _P, _P, _P]
+    lib.orc_compress_ex.argtypes = [ctypes.c_int32, _P, _P, _P, ctypes.c_int, _P, _P, ctypes.POINTER(ctypes.c_uint64)]
+    lib.orc_decompress_ex.argtypes = [ctypes.c_int32, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P,
+                                      _P]
     lib.orc_tiebreak_key.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
     lib.orc_tiebreak_key.restype = ctypes.c_uint64
     lib.orc_lp_cluster.argtypes = [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int64, ctypes.c_int32,
@@ -152,8 +155,9 @@ def unzigzag(z: int) -> int:
     return int(_load().orc_unzigzag(z))
 
 
-def compress(n: int, xadj, adjncy, adjwgt=None) -> tuple[np.ndarray, np.ndarray]:
-    """(offs uint64[n+1], bytes uint8[...]) of the compressed neighbourhoods."""
+def compress(n: int, xadj, adjncy, adjwgt=None, intervals: bool = False) -> tuple[np.ndarray, np.ndarray]:
+    """(offs uint64[n+1], bytes uint8[...]) of the compressed neighbourhoods
+    (gap encoding, plus interval encoding if `intervals`)."""
     lib = _load()
     xadj = _arr(xadj, np.uint64)
     adjncy = _arr(adjncy, np.int32)
@@ -163,14 +167,14 @@ def compress(n: int, xadj, adjncy, adjwgt=None) -> tuple[np.ndarray, np.ndarray]
     offs = np.empty(n + 1, dtype=np.uint64)
     out = np.empty(bound, dtype=np.uint8)
     nb = ctypes.c_uint64(0)
-    rc = lib.orc_compress(n, _ptr(xadj), _ptr(adjncy), _ptr(adjwgt), _ptr(offs), _ptr(out),
-                          ctypes.byref(nb))
+    rc = lib.orc_compress_ex(n, _ptr(xadj), _ptr(adjncy), _ptr(adjwgt), int(bool(intervals)), _ptr(offs), _ptr(out),
+                             ctypes.byref(nb))
     if rc != OK:
         raise RuntimeError(f"orc_compress: {rc}")
     return offs, out[: nb.value].copy()
 
 
-def decompress(n: int, two_m: int, weighted: bool, offs, data):
+def decompress(n: int, two_m: int, weighted: bool, offs, data, intervals: bool = False):
     """(xadj, adjncy, adjwgt or None); raises ValueError on a malformed stream."""
     lib = _load()
     offs = _arr(offs, np.uint64)
@@ -178,8 +182,8 @@ def decompress(n: int, two_m: int, weighted: bool, offs, data):
     xadj = np.empty(n + 1, dtype=np.uint64)
     adjncy = np.empty(max(two_m, 1), dtype=np.int32)
     adjwgt = np.empty(max(two_m, 1), dtype=np.int32) if weighted else None
-    rc = lib.orc_decompress(n, two_m, int(weighted), _ptr(offs), _ptr(data), _ptr(xadj), _ptr(adjncy),
-                            _ptr(adjwgt))
+    rc = lib.orc_decompress_ex(n, two_m, int(weighted), int(bool(intervals)), _ptr(offs), _ptr(data), _ptr(xadj),
+                               _ptr(adjncy), _ptr(adjwgt))
     if rc == EFORMAT:
         raise ValueError("malformed compressed graph")
     if rc != OK:

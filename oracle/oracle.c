@@ -7,8 +7,8 @@
  *
  * Contents, each following the paper (arxiv 2410.19119, "Tera-Scale
  * Multilevel Graph Partitioning") and the synchronous reading of it:
- *   - VarInt / zigzag codec and the gap-encoded neighbourhood format
- *     (Section III-A, "Compression Scheme");
+ *   - VarInt / zigzag codec and the gap-encoded neighbourhood format, with
+ *     or without interval encoding (Section III-A, "Compression Scheme");
  *   - size-constrained label-propagation clustering in synchronous rounds
  *     (Section IV-A, Algorithm 1 for what one vertex computes; the
  *     batch-synchronous form follows Section II-B on the distributed LP);
@@ -100,13 +100,98 @@ uint64_t orc_compress_bound(int32_t n, uint64_t two_m, int weighted) {
  *   VarInt(first edge ID of u)     -- gives degrees and edge IDs (Section III-A)
  *   if deg > 10 000: (ceil(deg/1000) - 1) little-endian uint32 byte offsets,
  *                    relative to the start of this record, of chunks 2, 3, ...
- *   per chunk of up to 1 000 neighbours:
+ *   per chunk of up to 1 000 neighbours (the whole neighbourhood if it is not
+ *   split), without intervals:
  *     VarInt(zigzag(v_0 - u)), then VarInt(v_i - v_{i-1}) for the rest (gap
  *     encoding); if weighted, each neighbour code is followed by
  *     VarInt(zigzag(w_i - w_{i-1})) with w_{-1} = 0 at the chunk start.
+ *   with intervals (Section III-A: a run x, x+1, ..., x+l-1 of l >= 3
+ *   consecutive IDs is kept as the pair (x, l)), per chunk:
+ *     the chunk's neighbours are split, left to right, into maximal runs of
+ *     IDs each one above the previous neighbour's; runs of length >= 3 are
+ *     intervals, every other neighbour a residual;
+ *     VarInt(k) = number of intervals;
+ *     per interval j: VarInt(zigzag(x_j - u)), VarInt(l_j - 3);
+ *     if weighted: the weights of the interval neighbours, interval by
+ *       interval, each as VarInt(zigzag(w - w_prev)), w_prev = 0 at the
+ *       chunk start;
+ *     the residuals r_0 < r_1 ... (in neighbour order) gap encoded as above:
+ *       VarInt(zigzag(r_0 - u)), then VarInt(r_i - r_{i-1}); if weighted each
+ *       followed by VarInt(zigzag(w - w_prev)), the weight chain continuing
+ *       from the interval weights.
  * Returns the number of bytes written. */
+static uint64_t encode_chunk_gaps(int32_t u, const orc_nb *nb, uint64_t b, uint64_t e, int weighted,
+                                  uint8_t *out) {
+  uint64_t k = 0;
+  int32_t wprev = 0;
+  for (uint64_t i = b; i < e; ++i) {
+    uint64_t code = (i == b) ? orc_zigzag((int64_t)nb[i].v - (int64_t)u)
+                             : (uint64_t)((int64_t)nb[i].v - (int64_t)nb[i - 1].v);
+    k += orc_varint_put(out + k, code);
+    if (weighted) {
+      k += orc_varint_put(out + k, orc_zigzag((int64_t)nb[i].w - (int64_t)wprev));
+      wprev = nb[i].w;
+    }
+  }
+  return k;
+}
+
+/* Marks the neighbours of nb[b..e) that belong to intervals (runs of >= 3
+ * IDs, each exactly one above the previous neighbour, found left to right)
+ * in in_run[i - b]; returns the number of intervals. */
+static uint64_t find_intervals(const orc_nb *nb, uint64_t b, uint64_t e, uint8_t *in_run) {
+  uint64_t count = 0;
+  for (uint64_t i = b; i < e;) {
+    uint64_t j = i + 1;
+    while (j < e && (int64_t)nb[j].v == (int64_t)nb[j - 1].v + 1) ++j;
+    const int is_interval = j - i >= 3;
+    for (uint64_t t = i; t < (is_interval ? j : i + 1); ++t) in_run[t - b] = (uint8_t)is_interval;
+    if (is_interval) {
+      ++count;
+      i = j;
+    } else {
+      ++i;
+    }
+  }
+  return count;
+}
+
+static uint64_t encode_chunk_intervals(int32_t u, const orc_nb *nb, uint64_t b, uint64_t e, int weighted,
+                                       uint8_t *in_run, uint8_t *out) {
+  uint64_t k = orc_varint_put(out, find_intervals(nb, b, e, in_run));
+  for (uint64_t i = b; i < e;) { /* the (start, length - 3) pairs */
+    if (!in_run[i - b]) { ++i; continue; }
+    uint64_t j = i + 1;
+    while (j < e && in_run[j - b] && (int64_t)nb[j].v == (int64_t)nb[j - 1].v + 1) ++j;
+    k += orc_varint_put(out + k, orc_zigzag((int64_t)nb[i].v - (int64_t)u));
+    k += orc_varint_put(out + k, j - i - 3);
+    i = j;
+  }
+  int32_t wprev = 0;
+  if (weighted)
+    for (uint64_t i = b; i < e; ++i)
+      if (in_run[i - b]) {
+        k += orc_varint_put(out + k, orc_zigzag((int64_t)nb[i].w - (int64_t)wprev));
+        wprev = nb[i].w;
+      }
+  int first = 1;
+  int32_t rprev = 0;
+  for (uint64_t i = b; i < e; ++i) {
+    if (in_run[i - b]) continue;
+    uint64_t code = first ? orc_zigzag((int64_t)nb[i].v - (int64_t)u) : (uint64_t)((int64_t)nb[i].v - rprev);
+    k += orc_varint_put(out + k, code);
+    if (weighted) {
+      k += orc_varint_put(out + k, orc_zigzag((int64_t)nb[i].w - (int64_t)wprev));
+      wprev = nb[i].w;
+    }
+    rprev = nb[i].v;
+    first = 0;
+  }
+  return k;
+}
+
 static uint64_t encode_nbh(int32_t u, uint64_t first_edge, const orc_nb *nb, uint64_t deg,
-                           int weighted, uint8_t *out) {
+                           int weighted, int intervals, uint8_t *in_run, uint8_t *out) {
   uint64_t k = orc_varint_put(out, first_edge);
   uint64_t nchunks = deg > ORC_CHUNK_THRESHOLD ? (deg + ORC_CHUNK_LEN - 1) / ORC_CHUNK_LEN : 1;
   uint64_t table = k;
@@ -119,29 +204,22 @@ static uint64_t encode_nbh(int32_t u, uint64_t first_edge, const orc_nb *nb, uin
       uint32_t rel = (uint32_t)k;
       memcpy(out + table + 4 * (ch - 1), &rel, 4);
     }
-    int32_t wprev = 0;
-    for (uint64_t i = b; i < e; ++i) {
-      uint64_t code = (i == b) ? orc_zigzag((int64_t)nb[i].v - (int64_t)u)
-                               : (uint64_t)((int64_t)nb[i].v - (int64_t)nb[i - 1].v);
-      k += orc_varint_put(out + k, code);
-      if (weighted) {
-        k += orc_varint_put(out + k, orc_zigzag((int64_t)nb[i].w - (int64_t)wprev));
-        wprev = nb[i].w;
-      }
-    }
+    k += intervals ? encode_chunk_intervals(u, nb, b, e, weighted, in_run, out + k)
+                   : encode_chunk_gaps(u, nb, b, e, weighted, out + k);
   }
   return k;
 }
 
 /* Compresses a CSR (neighbourhoods in any order; they are sorted here).
  * offs gets n+1 byte offsets; bytes must hold orc_compress_bound() bytes. */
-int orc_compress(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
-                 uint64_t *offs, uint8_t *bytes, uint64_t *nbytes) {
+int orc_compress_ex(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
+                    int intervals, uint64_t *offs, uint8_t *bytes, uint64_t *nbytes) {
   uint64_t maxdeg = 0;
   for (int32_t u = 0; u < n; ++u)
     if (xadj[u + 1] - xadj[u] > maxdeg) maxdeg = xadj[u + 1] - xadj[u];
   orc_nb *nb = (orc_nb *)malloc((maxdeg ? maxdeg : 1) * sizeof(orc_nb));
-  if (!nb) return ORC_ENOMEM;
+  uint8_t *in_run = (uint8_t *)malloc(maxdeg ? maxdeg : 1);
+  if (!nb || !in_run) { free(nb); free(in_run); return ORC_ENOMEM; }
   uint64_t pos = 0;
   for (int32_t u = 0; u < n; ++u) {
     uint64_t d = xadj[u + 1] - xadj[u];
@@ -151,19 +229,72 @@ int orc_compress(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const i
     }
     qsort(nb, d, sizeof(orc_nb), cmp_nb);
     offs[u] = pos;
-    pos += encode_nbh(u, xadj[u], nb, d, adjwgt != NULL, bytes + pos);
+    pos += encode_nbh(u, xadj[u], nb, d, adjwgt != NULL, intervals, in_run, bytes + pos);
   }
   offs[n] = pos;
   *nbytes = pos;
   free(nb);
+  free(in_run);
   return ORC_OK;
+}
+
+int orc_compress(int32_t n, const uint64_t *xadj, const int32_t *adjncy, const int32_t *adjwgt,
+                 uint64_t *offs, uint8_t *bytes, uint64_t *nbytes) {
+  return orc_compress_ex(n, xadj, adjncy, adjwgt, 0, offs, bytes, nbytes);
+}
+
+/* Decodes one chunk of `cnt` neighbours starting at byte *p (advancing it)
+ * into ids / wts; returns 0 on a malformed stream. Interval chunks give the
+ * interval neighbours first, then the residuals. */
+static int decode_chunk(const uint8_t *bytes, uint64_t end, uint64_t *p, int32_t u, int32_t n, uint64_t cnt,
+                        int weighted, int intervals, int32_t *ids, int32_t *wts) {
+  uint64_t i = 0, code;
+  int64_t wprev = 0;
+  if (intervals) {
+    uint64_t k;
+    if (!orc_varint_get(bytes, end, p, &k) || k > cnt) return 0;
+    for (uint64_t j = 0; j < k; ++j) {
+      uint64_t zs, lm3;
+      if (!orc_varint_get(bytes, end, p, &zs) || !orc_varint_get(bytes, end, p, &lm3)) return 0;
+      int64_t x = (int64_t)u + orc_unzigzag(zs);
+      uint64_t len = lm3 + 3;
+      if (len > cnt - i || x < 0 || x + (int64_t)len > n) return 0;
+      for (uint64_t t = 0; t < len; ++t) ids[i++] = (int32_t)(x + (int64_t)t);
+    }
+    for (uint64_t t = 0; t < i; ++t) {
+      if (weighted) {
+        if (!orc_varint_get(bytes, end, p, &code)) return 0;
+        wprev += orc_unzigzag(code);
+      } else {
+        wprev = 1;
+      }
+      wts[t] = (int32_t)wprev;
+    }
+  }
+  int64_t prev = 0;
+  for (uint64_t r = 0; i < cnt; ++i, ++r) {
+    if (!orc_varint_get(bytes, end, p, &code)) return 0;
+    int64_t v = r == 0 ? (int64_t)u + orc_unzigzag(code) : prev + (int64_t)code;
+    if (v < 0 || v >= n) return 0;
+    ids[i] = (int32_t)v;
+    prev = v;
+    if (weighted) {
+      if (!orc_varint_get(bytes, end, p, &code)) return 0;
+      wprev += orc_unzigzag(code);
+    } else {
+      wprev = 1;
+    }
+    wts[i] = (int32_t)wprev;
+  }
+  return 1;
 }
 
 /* Decodes the compressed graph back to CSR. Degrees come from the first-edge
  * headers (deg(u) = fe(u+1) - fe(u), fe(n) = 2m). The chunk table of every
- * split neighbourhood is checked against where the chunks actually start. */
-int orc_decompress(int32_t n, uint64_t two_m, int weighted, const uint64_t *offs,
-                   const uint8_t *bytes, uint64_t *xadj, int32_t *adjncy, int32_t *adjwgt) {
+ * split neighbourhood is checked against where the chunks actually start.
+ * Neighbourhoods come out sorted by (ID, weight), as they went in. */
+int orc_decompress_ex(int32_t n, uint64_t two_m, int weighted, int intervals, const uint64_t *offs,
+                      const uint8_t *bytes, uint64_t *xadj, int32_t *adjncy, int32_t *adjwgt) {
   uint64_t end = offs[n];
   uint64_t *fe = (uint64_t *)malloc(((size_t)n + 1) * sizeof(uint64_t));
   if (!fe) return ORC_ENOMEM;
@@ -173,46 +304,60 @@ int orc_decompress(int32_t n, uint64_t two_m, int weighted, const uint64_t *offs
   }
   fe[n] = two_m;
   if (n > 0 && fe[0] != 0) { free(fe); return ORC_EFORMAT; }
+  uint64_t maxdeg = 0;
   for (int32_t u = 0; u <= n; ++u) {
     if (u > 0 && fe[u] < fe[u - 1]) { free(fe); return ORC_EFORMAT; }
+    if (u > 0 && fe[u] - fe[u - 1] > maxdeg) maxdeg = fe[u] - fe[u - 1];
     xadj[u] = fe[u];
   }
-  for (int32_t u = 0; u < n; ++u) {
+  orc_nb *nb = (orc_nb *)malloc((maxdeg ? maxdeg : 1) * sizeof(orc_nb));
+  int32_t *ids = (int32_t *)malloc((maxdeg ? maxdeg : 1) * sizeof(int32_t));
+  int32_t *wts = (int32_t *)malloc((maxdeg ? maxdeg : 1) * sizeof(int32_t));
+  if (!nb || !ids || !wts) { free(fe); free(nb); free(ids); free(wts); return ORC_ENOMEM; }
+  int status = ORC_OK;
+  for (int32_t u = 0; u < n && status == ORC_OK; ++u) {
     uint64_t deg = fe[u + 1] - fe[u];
     uint64_t p = offs[u], hdr;
     orc_varint_get(bytes, end, &p, &hdr);
     uint64_t nchunks = deg > ORC_CHUNK_THRESHOLD ? (deg + ORC_CHUNK_LEN - 1) / ORC_CHUNK_LEN : 1;
     uint64_t table = p;
     if (nchunks > 1) p += 4 * (nchunks - 1);
-    int64_t prev = 0, wprev = 0;
-    for (uint64_t i = 0; i < deg; ++i) {
-      int chunk_start = (i == 0) || (nchunks > 1 && i % ORC_CHUNK_LEN == 0);
-      if (chunk_start && i > 0) {
+    for (uint64_t ch = 0; ch < nchunks; ++ch) {
+      uint64_t b = nchunks > 1 ? ch * ORC_CHUNK_LEN : 0;
+      uint64_t e = nchunks > 1 ? b + ORC_CHUNK_LEN : deg;
+      if (e > deg) e = deg;
+      if (ch > 0) {
         uint32_t rel;
-        memcpy(&rel, bytes + table + 4 * (i / ORC_CHUNK_LEN - 1), 4);
-        if (offs[u] + rel != p) { free(fe); return ORC_EFORMAT; }
+        memcpy(&rel, bytes + table + 4 * (ch - 1), 4);
+        if (offs[u] + rel != p) { status = ORC_EFORMAT; break; }
       }
-      uint64_t code;
-      if (!orc_varint_get(bytes, offs[u + 1], &p, &code)) { free(fe); return ORC_EFORMAT; }
-      int64_t v = chunk_start ? (int64_t)u + orc_unzigzag(code) : prev + (int64_t)code;
-      if (v < 0 || v >= n) { free(fe); return ORC_EFORMAT; }
-      adjncy[fe[u] + i] = (int32_t)v;
-      prev = v;
-      if (chunk_start) wprev = 0;
-      if (weighted) {
-        uint64_t wc;
-        if (!orc_varint_get(bytes, offs[u + 1], &p, &wc)) { free(fe); return ORC_EFORMAT; }
-        int64_t w = wprev + orc_unzigzag(wc);
-        if (adjwgt) adjwgt[fe[u] + i] = (int32_t)w;
-        wprev = w;
-      } else if (adjwgt) {
-        adjwgt[fe[u] + i] = 1;
+      if (!decode_chunk(bytes, offs[u + 1], &p, u, n, e - b, weighted, intervals, ids + b, wts + b)) {
+        status = ORC_EFORMAT;
+        break;
       }
     }
-    if (p != offs[u + 1]) { free(fe); return ORC_EFORMAT; }
+    if (status != ORC_OK) break;
+    if (p != offs[u + 1]) { status = ORC_EFORMAT; break; }
+    for (uint64_t i = 0; i < deg; ++i) {
+      nb[i].v = ids[i];
+      nb[i].w = wts[i];
+    }
+    if (intervals) qsort(nb, deg, sizeof(orc_nb), cmp_nb);
+    for (uint64_t i = 0; i < deg; ++i) {
+      adjncy[fe[u] + i] = nb[i].v;
+      if (adjwgt) adjwgt[fe[u] + i] = nb[i].w;
+    }
   }
   free(fe);
-  return ORC_OK;
+  free(nb);
+  free(ids);
+  free(wts);
+  return status;
+}
+
+int orc_decompress(int32_t n, uint64_t two_m, int weighted, const uint64_t *offs, const uint8_t *bytes,
+                   uint64_t *xadj, int32_t *adjncy, int32_t *adjwgt) {
+  return orc_decompress_ex(n, two_m, weighted, 0, offs, bytes, xadj, adjncy, adjwgt);
 }
 
 /* ---------------------------------------------- label propagation ---- */
