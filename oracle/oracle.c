@@ -40,9 +40,13 @@
 #define ORC_EFORMAT -4
 
 /* Format constants: neighbourhoods with more than 10 000 neighbours are split
- * into independently coded chunks of 1 000 (Section III-A). */
+ * into independently coded chunks of 1 000 (Section III-A). Interval-coded
+ * graphs split above 4 000 neighbours: the most neighbours one piece of the
+ * GPU's high-degree path rates, so that pieces start at chunks. */
 #define ORC_CHUNK_THRESHOLD 10000
+#define ORC_ITV_CHUNK_THRESHOLD 4000
 #define ORC_CHUNK_LEN 1000
+#define CHUNK_THRESHOLD(itv) ((itv) ? ORC_ITV_CHUNK_THRESHOLD : ORC_CHUNK_THRESHOLD)
 
 /* ------------------------------------------------------------ VarInt ---- */
 /* VarInt (Section III-A): 7 payload bits per byte, least significant group
@@ -98,8 +102,9 @@ uint64_t orc_compress_bound(int32_t n, uint64_t two_m, int weighted) {
 /* Encodes one neighbourhood, already sorted by (id, weight), at `out`.
  * Layout, in this order:
  *   VarInt(first edge ID of u)     -- gives degrees and edge IDs (Section III-A)
- *   if deg > 10 000: (ceil(deg/1000) - 1) little-endian uint32 byte offsets,
- *                    relative to the start of this record, of chunks 2, 3, ...
+ *   if deg > 10 000 (4 000 with intervals): (ceil(deg/1000) - 1) little-endian
+ *                    uint32 byte offsets, relative to the start of this
+ *                    record, of chunks 2, 3, ...
  *   per chunk of up to 1 000 neighbours (the whole neighbourhood if it is not
  *   split), without intervals:
  *     VarInt(zigzag(v_0 - u)), then VarInt(v_i - v_{i-1}) for the rest (gap
@@ -193,7 +198,7 @@ static uint64_t encode_chunk_intervals(int32_t u, const orc_nb *nb, uint64_t b, 
 static uint64_t encode_nbh(int32_t u, uint64_t first_edge, const orc_nb *nb, uint64_t deg,
                            int weighted, int intervals, uint8_t *in_run, uint8_t *out) {
   uint64_t k = orc_varint_put(out, first_edge);
-  uint64_t nchunks = deg > ORC_CHUNK_THRESHOLD ? (deg + ORC_CHUNK_LEN - 1) / ORC_CHUNK_LEN : 1;
+  uint64_t nchunks = deg > CHUNK_THRESHOLD(intervals) ? (deg + ORC_CHUNK_LEN - 1) / ORC_CHUNK_LEN : 1;
   uint64_t table = k;
   if (nchunks > 1) k += 4 * (nchunks - 1);
   for (uint64_t ch = 0; ch < nchunks; ++ch) {
@@ -319,7 +324,7 @@ int orc_decompress_ex(int32_t n, uint64_t two_m, int weighted, int intervals, co
     uint64_t deg = fe[u + 1] - fe[u];
     uint64_t p = offs[u], hdr;
     orc_varint_get(bytes, end, &p, &hdr);
-    uint64_t nchunks = deg > ORC_CHUNK_THRESHOLD ? (deg + ORC_CHUNK_LEN - 1) / ORC_CHUNK_LEN : 1;
+    uint64_t nchunks = deg > CHUNK_THRESHOLD(intervals) ? (deg + ORC_CHUNK_LEN - 1) / ORC_CHUNK_LEN : 1;
     uint64_t table = p;
     if (nchunks > 1) p += 4 * (nchunks - 1);
     for (uint64_t ch = 0; ch < nchunks; ++ch) {

@@ -3,7 +3,9 @@ x, x+1, ..., x+l-1 of at least three consecutive neighbour IDs is stored as
 the pair (x, l); weights stay gap + VarInt coded). Reading of the layout per
 chunk: VarInt(k intervals); per interval VarInt(zigzag(x - u)),
 VarInt(l - 3); the interval neighbours' weights; then the other neighbours
-gap encoded as in the plain format, weights continuing the same chain."""
+gap encoded as in the plain format, weights continuing the same chain.
+Interval-coded neighbourhoods are split into chunks of 1000 above 4000
+neighbours (10 000 without intervals)."""
 import numpy as np
 import pytest
 
@@ -87,7 +89,20 @@ def test_chunks_restart_intervals(oracle_mod, synth_mod):
     assert len(rec) < 200  # 10001 neighbours in a few bytes per chunk
 
 
-@pytest.mark.parametrize("d", [0, 1, 9999, 10000, 10001, 25000])
+def test_chunk_threshold_4000(oracle_mod, synth_mod):
+    # 4000 neighbours: one chunk; 4001: five chunks, so a table of four offsets
+    for d, table in ((4000, 0), (4001, 4)):
+        g = _graph(synth_mod, d + 1, [(0, v) for v in range(1, d + 1)])
+        offs, data = oracle_mod.compress(g.n, g.xadj, g.adjncy, intervals=True)
+        rec = data[offs[0]:offs[1]].tobytes()
+        k, _ = oracle_mod.varint_decode(rec[1 + 4 * table:])
+        assert k == 1  # the first chunk holds one interval
+        if table:
+            rels = [int.from_bytes(rec[1 + 4 * i: 5 + 4 * i], "little") for i in range(table)]
+            assert rels == sorted(rels) and rels[0] > 1 + 4 * table
+
+
+@pytest.mark.parametrize("d", [0, 1, 3999, 4000, 4001, 9999, 10000, 10001, 25000])
 @pytest.mark.parametrize("weighted", [False, True])
 def test_roundtrip_stars(oracle_mod, synth_mod, d, weighted):
     # stars with the centre inside the leaf range: long consecutive runs
