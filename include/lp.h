@@ -292,6 +292,27 @@ lp_status lp_contract(const lp_graph *g, const int32_t *labels_dev, int32_t *map
 lp_status lp_edge_cut(const lp_graph *g, const int32_t *labels_dev, int64_t *cut_out, void *stream);
 
 /*
+ * lp_edge_cut_noalloc — lp_edge_cut for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops): the same edge
+ * visit, but no allocation of any kind and no synchronisation.
+ * Arguments: g, labels_dev int32[n] as for lp_edge_cut; cut_dev receives the
+ * cut as a device int64 once `stream` reaches the end of the call.
+ * Scratch: a fixed 256-byte array of device memory per device, kept by the
+ * library until the process ends (the cut accumulator and the edge visit's
+ * counters); there is no size limit, since its size does not depend on the
+ * graph. Every call on one device shares that array and the last call's
+ * contents stay in it (each call clears it first): calls that overlap on one
+ * device (on different streams, or from different threads) race and must be
+ * ordered by the caller.
+ * The handle's degree-bucket plan (memory of the handle, built once on the
+ * first lp_cluster with default thresholds, lp_edge_cut or lp_contract on it)
+ * must exist, since building it allocates.
+ * Errors: LP_EINVAL (null arguments, or a handle without its plan),
+ * LP_EUNSUPPORTED (device index above 63), LP_EDEVICE.
+ */
+lp_status lp_edge_cut_noalloc(const lp_graph *g, const int32_t *labels_dev, int64_t *cut_dev, void *stream);
+
+/*
  * Uncoarsening slice of the multilevel scheme (Section II-A): an initial
  * partition of the coarsest graph, projected to each finer level and refined
  * there by size-constrained label propagation (Section II-B). Blocks are

@@ -103,6 +103,8 @@ def _load():
     lib.lp_contract.restype = S
     lib.lp_edge_cut.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_int64), _P]
     lib.lp_edge_cut.restype = S
+    lib.lp_edge_cut_noalloc.argtypes = [_P, _P, _P, _P]
+    lib.lp_edge_cut_noalloc.restype = S
     lib.lp_graph_free.argtypes = [_P]
     lib.lp_graph_free.restype = None
     lib.lp_trim_memory.argtypes = []
@@ -184,7 +186,7 @@ def memory_info() -> dict:
 def exported_symbols() -> list[str]:
     return ["lp_strerror", "lp_version", "lp_compress", "lp_graph_from_csr", "lp_graph_info",
             "lp_graph_export", "lp_decompress", "lp_cluster", "lp_cluster_ex", "lp_contract",
-            "lp_edge_cut", "lp_graph_free", "lp_batch_create", "lp_batch_info", "lp_batch_cluster_ex",
+            "lp_edge_cut", "lp_edge_cut_noalloc", "lp_graph_free", "lp_batch_create", "lp_batch_info", "lp_batch_cluster_ex",
             "lp_batch_cluster", "lp_trim_memory", "lp_set_allocator", "lp_memory_info", "lp_initial_partition", "lp_project", "lp_refine",
             "lp_refine_ex", "lp_gain_table_create", "lp_gain_table_affinity", "lp_gain_table_move",
             "lp_gain_table_info", "lp_gain_table_free"]
@@ -426,6 +428,16 @@ def lp_edge_cut(g: Graph, labels, stream=None) -> int:
     out = ctypes.c_int64()
     _check(_load().lp_edge_cut(g.handle, _ptr(lab), ctypes.byref(out), _stream(stream)), "lp_edge_cut")
     return out.value
+
+
+def lp_edge_cut_noalloc(g: Graph, labels, cut_out, stream=None) -> None:
+    """The cut written into cut_out (int64 device tensor of one element) with
+    no allocation and no synchronisation; the handle's plan must exist."""
+    torch = _torch()
+    lab = _dev(labels, torch.int32)
+    if cut_out.dtype != torch.int64 or not cut_out.is_cuda or cut_out.numel() < 1:
+        raise ValueError("cut_out must be an int64 device tensor")
+    _check(_load().lp_edge_cut_noalloc(g.handle, _ptr(lab), _ptr(cut_out), _stream(stream)), "lp_edge_cut_noalloc")
 
 
 def coarsen_params(n0: int, total_weight: int):

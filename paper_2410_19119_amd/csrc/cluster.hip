@@ -2012,16 +2012,25 @@ __global__ void k_zero_u32(uint32_t* a, int32_t n) {
 // One visit of every edge with the default plan: the cut (MODE == kModeCut)
 // or the contraction records (kModeRec). The lane, tile and piece kernels
 // decode exactly as for rating and stop after the label (or map) gather.
+// With `counters` given (32 words of the caller's memory), the visit
+// allocates nothing: it uses the plan the handle already holds (LP_EINVAL if
+// no earlier call built it) and those counters instead of scratch.
 template <int MODE>
 lp_status visit_edges_mode(const lp_graph* g, const int32_t* C, const uint64_t* rbase, const uint64_t* voff, Rec* rec,
-                           unsigned long long* cut, hipStream_t s) {
+                           unsigned long long* cut, hipStream_t s, uint32_t* counters = nullptr) {
   const Plan* plan = nullptr;
   std::unique_ptr<Plan> tmp;
-  LP_CHECK(get_plan(g, 16, kTileMaxDeg, TileLarge::kEdges, kDefaultHubPart, s, &plan, tmp));
+  if (counters) {
+    std::lock_guard<std::mutex> lock(g->plan_mu);
+    plan = (const Plan*)g->plan;
+    if (!plan) return LP_EINVAL;
+  } else {
+    LP_CHECK(get_plan(g, 16, kTileMaxDeg, TileLarge::kEdges, kDefaultHubPart, s, &plan, tmp));
+  }
   Scratch sc(s);
   // zero[0]: the round's "done" flag (never set here); zero[8..32): hand-out
   // counters of the small tiles, the large tiles and the pieces
-  uint32_t* zero = sc.alloc<uint32_t>(32);
+  uint32_t* zero = counters ? counters : sc.alloc<uint32_t>(32);
   if (!zero) return LP_ENOMEM;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, zero, 32);
   LP_CHECK_LAUNCH();
@@ -2135,6 +2144,12 @@ lp_status plan_degrees(const lp_graph* g, const int32_t** deg, hipStream_t s) {
 lp_status visit_edges_cut(const lp_graph* g, const int32_t* labels, unsigned long long* cut, hipStream_t s) {
   if (g->n == 0) return LP_OK;
   return visit_edges_mode<kModeCut>(g, labels, nullptr, nullptr, nullptr, cut, s);
+}
+
+lp_status visit_edges_cut_noalloc(const lp_graph* g, const int32_t* labels, unsigned long long* cut,
+                                  uint32_t* counters, hipStream_t s) {
+  if (g->n == 0) return LP_OK;
+  return visit_edges_mode<kModeCut>(g, labels, nullptr, nullptr, nullptr, cut, s, counters);
 }
 
 lp_status visit_edges_records(const lp_graph* g, const int32_t* map, const uint64_t* rbase, const uint64_t* voff,
