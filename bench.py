@@ -557,6 +557,11 @@ def main() -> int:
         print(json.dumps({"workload": "copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
                           "copies": 3}))
         return 0
+    if args.workload == "intervals":
+        print(json.dumps({"metric": "LP-round time and bytes per edge with interval encoding", "unit": "ms",
+                          "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "int32",
+                          "intervals": bench_intervals(args, args.coarsen_scale)}))
+        return 0
     if args.workload == "gather":
         # calibration for the HBM byte counters on random 4-byte gathers:
         # 2^26 gathers at uniform random positions of an int32 array of 2^24
@@ -668,6 +673,36 @@ def lp_rate(lp, G, cap: int, rounds: int, steps: int, warmup: int, labels=None) 
     med = median(rms)
     return {"round_ms_median": round(med, 4), "lp_round_edges_per_s": G.two_m / (med / 1e3),
             "rounds_timed": len(rms)}
+
+
+def bench_intervals(args, scale: int = 26) -> dict:
+    """Interval encoding on the geometric graph of the large coarsening
+    workload (RGG-3D, 2^26 vertices, average degree 27, cell-ordered IDs):
+    compressed bytes per edge with gap encoding alone and with intervals, and
+    the median LP round time of level 0 (cap 12288, 5 rounds, seed 1) on
+    each; the two must give the same labels."""
+    import torch
+
+    import paper_2410_19119_amd as lp
+    import synth
+
+    t0 = time.time()
+    g = synth.rgg3d(1 << scale, 27.0, seed=1)
+    log(f"[intervals] generated rgg3d n=2^{scale}: 2m={g.two_m} in {time.time() - t0:.1f}s")
+    out = {"workload": f"rgg3d n=2^{scale} avg-deg~27, cell-ordered, cap 12288, 5 rounds, seed 1", "two_m": g.two_m}
+    labs = {}
+    for name, itv in (("gap", False), ("intervals", True)):
+        G = lp.lp_compress(g.n, g.xadj.view(np.int64), g.adjncy, intervals=itv)
+        lab = torch.empty(G.n, dtype=torch.int32, device="cuda")
+        r = lp_rate(lp, G, 12288, args.rounds, 3, 1, labels=lab)
+        labs[name] = lab
+        r.update({"bytes": G.nbytes, "bytes_per_edge": round(G.nbytes / g.two_m, 4)})
+        out[name] = r
+        log(f"[intervals] {name}: {G.nbytes} bytes ({G.nbytes / g.two_m:.3f} B/edge), round {r['round_ms_median']} ms")
+        G.free()
+    out["identical_labels"] = bool(torch.equal(labs["gap"], labs["intervals"]))
+    out["bytes_ratio"] = round(out["intervals"]["bytes"] / out["gap"]["bytes"], 4)
+    return out
 
 
 def bench_headline(args) -> dict:
@@ -809,6 +844,9 @@ def bench_headline(args) -> dict:
         G1.free()
         log(f"[bench] rmat24: round {r1['round_ms_median']} ms ({r1['lp_round_edges_per_s']:.3e} edges/s) "
             f"in {time.time() - t0:.1f}s")
+
+    if not args.no_extra and args.workload == "rmat26":
+        extra["rgg3d26_intervals"] = bench_intervals(args)
 
     forms = {}
     if not args.no_forms:

@@ -27,7 +27,7 @@
  *    in the order of `stream`, and goes back to it before the call returns.
  *    The cache hands memory released by one call to the next (at once on
  *    the same stream, on another stream once the release has completed)
- *    instead of returning it to HIP, keeping up to a quarter of the device's
+ *    instead of returning it to HIP, keeping up to half of the device's
  *    memory (lp_trim_memory returns it; lp_memory_info reports it).
  *  - Errors are returned as lp_status codes; no exception crosses the ABI.
  *    Argument errors are detected before any work is enqueued. A device
@@ -69,6 +69,10 @@ typedef int32_t lp_status;
  * chunks of LP_CHUNK_LEN neighbours (Section III-A). Fixed by the format. */
 #define LP_CHUNK_THRESHOLD 10000
 #define LP_CHUNK_LEN 1000
+/* Interval-coded graphs (lp_compress_ex with LP_COMPRESS_INTERVALS) split
+ * neighbourhoods longer than this instead: the most neighbours the GPU's
+ * hub path rates in one piece, so that a piece always starts at a chunk. */
+#define LP_ITV_CHUNK_THRESHOLD 4000
 
 /* Human-readable name of a status code (static string). */
 const char *lp_strerror(lp_status s);
@@ -99,7 +103,7 @@ const char *lp_version(void);
  *     adjwgt is given, every neighbour code is followed by
  *     VarInt(zigzag(w_i - w_{i-1})), w_{-1} = 0 at each chunk start.
  * VarInt = LEB128: 7 data bits per byte, low group first, bit 7 set when
- * another byte follows (Section III-A). Interval encoding is not used.
+ * another byte follows (Section III-A). Interval encoding: lp_compress_ex.
  *
  * Output: *out receives a new handle owning device copies of the compressed
  * bytes, offsets and vertex weights. Synchronises `stream`.
@@ -109,6 +113,32 @@ const char *lp_version(void);
 lp_status lp_compress(int32_t n, const uint64_t *xadj_dev, const int32_t *adjncy_dev,
                       const int32_t *adjwgt_dev, const int32_t *vwgt_dev, void *stream,
                       lp_graph **out);
+
+/*
+ * lp_compress_ex — lp_compress with format flags. LP_COMPRESS_INTERVALS adds
+ * the interval encoding of Section III-A: a run x, x+1, ..., x+l-1 of l >= 3
+ * consecutive neighbour IDs is stored as the pair (x, l). Per chunk (records
+ * of more than LP_ITV_CHUNK_THRESHOLD neighbours are split into chunks of
+ * LP_CHUNK_LEN, each coded on its own) the chunk's sorted neighbours are cut,
+ * left to right, into maximal runs of IDs each one above the previous
+ * neighbour's; runs of at least three are intervals, every other neighbour a
+ * residual. Chunk layout:
+ *   VarInt(k), the number of intervals;
+ *   per interval: VarInt(zigzag(x - u)), VarInt(l - 3);
+ *   if adjwgt is given: the weights of the interval neighbours, interval by
+ *     interval, each VarInt(zigzag(w - w_prev)), w_prev = 0 at the chunk start;
+ *   the residuals r_0 < r_1 < ...: VarInt(zigzag(r_0 - u)), then
+ *     VarInt(r_i - r_{i-1}); with weights, each followed by
+ *     VarInt(zigzag(w - w_prev)), the chain continuing from the interval
+ *     weights.
+ * Decoding yields a chunk's interval neighbours first, then its residuals;
+ * lp_decompress merges them back into sorted order. Other flags: LP_EINVAL.
+ * Everything else as lp_compress; every entry point accepts both formats.
+ */
+#define LP_COMPRESS_INTERVALS 1
+lp_status lp_compress_ex(int32_t n, const uint64_t *xadj_dev, const int32_t *adjncy_dev,
+                         const int32_t *adjwgt_dev, const int32_t *vwgt_dev, int32_t flags, void *stream,
+                         lp_graph **out);
 
 /*
  * lp_graph_from_csr — plain (uncompressed) CSR handle, same input contract
@@ -121,7 +151,9 @@ lp_status lp_graph_from_csr(int32_t n, const uint64_t *xadj_dev, const int32_t *
                             lp_graph **out);
 
 /* Sizes of a handle (host outputs; any may be NULL). nbytes = compressed
- * adjacency bytes (0 for plain handles); total_vwgt = sum of vertex weights. */
+ * adjacency bytes (0 for plain handles); is_compressed = 0 (plain CSR),
+ * 1 (gap + VarInt) or 2 (gap + VarInt with intervals); total_vwgt = sum of
+ * vertex weights. */
 lp_status lp_graph_info(const lp_graph *g, int32_t *n, uint64_t *two_m, uint64_t *nbytes,
                         int32_t *is_compressed, int32_t *has_edge_weights, int64_t *total_vwgt);
 
@@ -131,10 +163,14 @@ lp_status lp_graph_info(const lp_graph *g, int32_t *n, uint64_t *two_m, uint64_t
 lp_status lp_graph_export(const lp_graph *g, uint64_t *offs_dev, uint8_t *bytes_dev, void *stream);
 
 /*
- * lp_decompress — decode a handle back to CSR (device outputs, caller
- * sized): xadj_dev uint64[n+1], adjncy_dev int32[2m], adjwgt_dev int32[2m]
- * (may be NULL; unit weights are written as 1), vwgt_dev int32[n] (may be
- * NULL). Neighbourhoods come out sorted by (ID, weight).
+ * lp_decompress — decode a handle back to CSR (the inverse of the gap +
+ * VarInt coding, and of the interval coding, of Section III-A; plain handles
+ * are copied). Device outputs, caller sized: xadj_dev uint64[n+1],
+ * adjncy_dev int32[2m], adjwgt_dev int32[2m] (may be NULL; unit weights are
+ * written as 1), vwgt_dev int32[n] (may be NULL). Neighbourhoods come out
+ * sorted by (ID, weight). Synchronises `stream`. Errors: LP_EINVAL for a
+ * null argument or a malformed compressed stream (the outputs are then
+ * unspecified), LP_EUNSUPPORTED for a batch handle, LP_ENOMEM, LP_EDEVICE.
  */
 lp_status lp_decompress(const lp_graph *g, uint64_t *xadj_dev, int32_t *adjncy_dev,
                         int32_t *adjwgt_dev, int32_t *vwgt_dev, void *stream);
@@ -230,7 +266,7 @@ lp_status lp_cluster_ex(const lp_graph *g, int64_t max_cluster_weight, int32_t r
  * Batches of graphs (many uneven graphs in one launch sequence).
  *
  * lp_batch_create — the disjoint union of G >= 1 graph handles as one batch
- * handle (all compressed or all plain, all with or all without edge
+ * handle (all plain or all compressed in one format, all with or all without edge
  * weights, else LP_EUNSUPPORTED; total vertices < 2^31). Graph i's vertices
  * occupy [vbase[i], vbase[i+1]) of the union. The inputs are copied (they
  * stay owned by the caller and may be freed afterwards); the batch handle is

@@ -84,6 +84,8 @@ def _load():
     lib.lp_version.restype = ctypes.c_char_p
     lib.lp_compress.argtypes = [ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]
     lib.lp_compress.restype = S
+    lib.lp_compress_ex.argtypes = [ctypes.c_int32, _P, _P, _P, _P, ctypes.c_int32, _P, ctypes.POINTER(_P)]
+    lib.lp_compress_ex.restype = S
     lib.lp_graph_from_csr.argtypes = [ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]
     lib.lp_graph_from_csr.restype = S
     lib.lp_graph_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint64),
@@ -184,7 +186,7 @@ def memory_info() -> dict:
 
 
 def exported_symbols() -> list[str]:
-    return ["lp_strerror", "lp_version", "lp_compress", "lp_graph_from_csr", "lp_graph_info",
+    return ["lp_strerror", "lp_version", "lp_compress", "lp_compress_ex", "lp_graph_from_csr", "lp_graph_info",
             "lp_graph_export", "lp_decompress", "lp_cluster", "lp_cluster_ex", "lp_contract",
             "lp_edge_cut", "lp_edge_cut_noalloc", "lp_graph_free", "lp_batch_create", "lp_batch_info", "lp_batch_cluster_ex",
             "lp_batch_cluster", "lp_trim_memory", "lp_set_allocator", "lp_memory_info", "lp_initial_partition", "lp_project", "lp_refine",
@@ -241,6 +243,7 @@ class Graph:
         self.two_m = two_m.value
         self.nbytes = nb.value
         self.compressed = bool(comp.value)
+        self.intervals = comp.value == 2
         self.weighted = bool(wt.value)
         self.total_vwgt = tot.value
 
@@ -264,7 +267,7 @@ class Graph:
         return f"Graph(n={self.n}, 2m={self.two_m}, {kind}, bytes={self.nbytes})"
 
 
-def _make(fn_name: str, n, xadj, adjncy, adjwgt=None, vwgt=None, stream=None) -> Graph:
+def _make(fn_name: str, n, xadj, adjncy, adjwgt=None, vwgt=None, stream=None, flags=None) -> Graph:
     torch = _torch()
     lib = _load()
     x = _dev(xadj, torch.int64)  # uint64 bit pattern
@@ -274,13 +277,23 @@ def _make(fn_name: str, n, xadj, adjncy, adjwgt=None, vwgt=None, stream=None) ->
     w = _dev(adjwgt, torch.int32)
     v = _dev(vwgt, torch.int32)
     h = _P()
-    st = getattr(lib, fn_name)(int(n), _ptr(x), _ptr(a), _ptr(w), _ptr(v), _stream(stream), ctypes.byref(h))
+    if flags is None:
+        st = getattr(lib, fn_name)(int(n), _ptr(x), _ptr(a), _ptr(w), _ptr(v), _stream(stream), ctypes.byref(h))
+    else:
+        st = getattr(lib, fn_name)(int(n), _ptr(x), _ptr(a), _ptr(w), _ptr(v), int(flags), _stream(stream),
+                                   ctypes.byref(h))
     _check(st, fn_name)
     return Graph(h)
 
 
-def lp_compress(n, xadj, adjncy, adjwgt=None, vwgt=None, stream=None) -> Graph:
-    """Compressed handle from a CSR (numpy or tensors; copied to the device)."""
+LP_COMPRESS_INTERVALS = 1
+
+
+def lp_compress(n, xadj, adjncy, adjwgt=None, vwgt=None, stream=None, intervals: bool = False) -> Graph:
+    """Compressed handle from a CSR (numpy or tensors; copied to the device);
+    with intervals=True runs of consecutive IDs are interval encoded."""
+    if intervals:
+        return _make("lp_compress_ex", n, xadj, adjncy, adjwgt, vwgt, stream, flags=LP_COMPRESS_INTERVALS)
     return _make("lp_compress", n, xadj, adjncy, adjwgt, vwgt, stream)
 
 

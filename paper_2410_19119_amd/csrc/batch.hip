@@ -121,9 +121,10 @@ extern "C" lp_status lp_batch_create(int32_t G, const lp_graph* const* gs, void*
   *out = nullptr;
   for (int32_t i = 0; i < G; ++i)
     if (!gs[i] || gs[i]->nbatch) return LP_EINVAL;
-  const bool comp = gs[0]->compressed, weighted = gs[0]->weighted;
+  const bool comp = gs[0]->compressed, weighted = gs[0]->weighted, itv = gs[0]->intervals;
   for (int32_t i = 0; i < G; ++i)
-    if ((bool)gs[i]->compressed != comp || (bool)gs[i]->weighted != weighted) return LP_EUNSUPPORTED;
+    if ((bool)gs[i]->compressed != comp || (bool)gs[i]->weighted != weighted || (bool)gs[i]->intervals != itv)
+      return LP_EUNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   std::vector<int32_t> vbase(G + 1);
   std::vector<uint64_t> bbase(G + 1), two_m(G);
@@ -154,6 +155,7 @@ extern "C" lp_status lp_batch_create(int32_t G, const lp_graph* const* gs, void*
   b->two_m = m;
   b->compressed = comp;
   b->weighted = weighted;
+  b->intervals = itv;
   b->total_vwgt = total;
   b->max_wdeg = max_wdeg;
   b->max_deg = max_deg;

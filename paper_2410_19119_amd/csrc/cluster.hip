@@ -81,6 +81,7 @@ __device__ __forceinline__ uint64_t cluster_key(const RoundCtx& x, const VParams
 struct VDesc {
   const int4* d;      // {u, deg, pos_lo, pos_hi}
   const uint32_t* len;
+  const uint32_t* num;  // interval-coded graphs: VarInts in the vertex's code bytes
 };
 
 __device__ __forceinline__ uint64_t vd_pos(const int4 v) {
@@ -106,7 +107,7 @@ __device__ __forceinline__ void consider(const RoundCtx& x, const VParams& p, in
 }
 
 // ------------------------------------------------------- lane per vertex --
-template <bool COMP, int MODE = kModeRate>
+template <bool COMP, int MODE = kModeRate, bool ITV = false>
 __global__ __launch_bounds__(256) void k_rate_lane(RoundCtx x, VDesc vd, int32_t cnt) {
   if (*x.done) return;
   const int32_t i = blockIdx.x * 256 + threadIdx.x;
@@ -119,8 +120,12 @@ __global__ __launch_bounds__(256) void k_rate_lane(RoundCtx x, VDesc vd, int32_t
       const int32_t own_c = x.C[u];
       uint64_t pos = vd_pos(v4);
       int32_t v = 0, w = 0;
+      LaneDec dec;
+      if constexpr (ITV) dec.init(x.g, u, pos);
       for (int k = 0; k < d; ++k) {
-        if constexpr (COMP) {
+        if constexpr (ITV) {
+          dec.next(v, w);
+        } else if constexpr (COMP) {
           const uint64_t code = varint_read(x.g.bytes, pos);
           v = (k == 0) ? u + (int32_t)unzigzag(code) : v + (int32_t)code;
           if (x.g.weighted) w = (k == 0 ? 0 : w) + (int32_t)unzigzag(varint_read(x.g.bytes, pos));
@@ -142,7 +147,21 @@ __global__ __launch_bounds__(256) void k_rate_lane(RoundCtx x, VDesc vd, int32_t
   const int32_t d = v4.y;
   int32_t lab[kMaxLane];
   int32_t wt[kMaxLane];
-  if constexpr (COMP) {
+  if constexpr (ITV) {
+    LaneDec dec;
+    dec.init(x.g, u, vd_pos(v4));
+#pragma unroll
+    for (int k = 0; k < kMaxLane; ++k) {
+      lab[k] = -1;
+      wt[k] = 0;
+      if (k < d) {
+        int32_t v, w;
+        dec.next(v, w);
+        lab[k] = x.C[v];
+        wt[k] = w;
+      }
+    }
+  } else if constexpr (COMP) {
     uint64_t pos = vd_pos(v4);
     int32_t v = 0, w = 0;
 #pragma unroll
@@ -291,11 +310,17 @@ __host__ __device__ inline TileLayout tile_layout(bool comp, bool weighted) {
   TileLayout L;
   const uint32_t per = weighted ? 2u : 1u;
   L.table_bytes = (uint32_t)T::kSlots * (4u + (uint32_t)sizeof(V));
-  const uint32_t nums = comp ? (per * T::kEdges + 6u * T::kVerts) * 4u : 0u;
-  // any single vertex of the bucket must fit: <= 5 bytes per number
-  const uint32_t worst = comp ? 5u * per * T::kEdges + 8u : 0u;
+  // numbers: at most per * E VarInts of the neighbours, one interval count per
+  // vertex of an interval-coded graph, and up to six zero bytes around each
+  // vertex's codes
+  const uint32_t nums = comp ? (per * T::kEdges + 7u * T::kVerts) * 4u : 0u;
+  // any single vertex of the bucket must fit: <= 5 bytes per number; the
+  // staging area later holds the interval table of an interval-coded tile
+  const uint32_t worst = comp ? 5u * per * T::kEdges + 16u : 0u;
+  const uint32_t itv = comp ? (2u * T::kVerts + 2u + 2u * ((uint32_t)T::kEdges / 3u + 1u)) * 4u : 0u;
   uint32_t sb = L.table_bytes > nums ? L.table_bytes - nums : 0u;
   if (sb < worst) sb = worst;
+  if (sb < itv) sb = itv;
   sb = (sb + 15u) & ~15u;
   L.stage_bytes = comp ? sb : 0u;
   L.nums_off = L.stage_bytes;
@@ -383,6 +408,105 @@ __device__ __forceinline__ void tile_seg_scan(bool head, int32_t s, int32_t s2, 
   }
   ex = ef ? es : cs + es;
   ex2 = ef ? es2 : cs2 + es2;
+}
+
+// Interval-coded segments (vertices of a tile, code streams of a hub piece):
+// the per-workgroup table of intervals, built from the numbers of step 2 in
+// the staging area that step 2 has finished with. Segment i's numbers start
+// at rstart[i] with its interval count k_i, then its (zigzag(x - u), l - 3)
+// pairs. The table gives every interval its start ID and the number of the
+// segment's neighbours in its earlier intervals; L[i] = all of segment i's
+// interval neighbours, which come first in its decoding order.
+struct ItvTable {
+  uint32_t* base;   // nseg + 1: first interval of each segment
+  uint32_t* L;      // nseg: interval neighbours of each segment
+  int32_t* start;   // per interval: first neighbour ID
+  uint32_t* cum;    // per interval: neighbours of the segment's earlier intervals
+};
+
+template <int NT, int MAXSEG, int MAXITV>
+__device__ __forceinline__ ItvTable itv_table(uint32_t* area, const uint32_t* nums, const uint32_t* rstart,
+                                              const uint32_t* ebase, const int32_t* seg_u, int32_t nseg,
+                                              int32_t* scan_sm, int32_t* scan_sm2, uint32_t* seg_flags) {
+  ItvTable t;
+  t.base = area;
+  t.L = area + (MAXSEG + 1);
+  t.start = (int32_t*)(area + 2 * MAXSEG + 2);
+  t.cum = area + 2 * MAXSEG + 2 + MAXITV;
+  const int tid = threadIdx.x;
+  uint32_t kk = 0;
+  if (tid < nseg && ebase[tid + 1] > ebase[tid]) kk = nums[rstart[tid]];  // empty segments have no count
+  int32_t tot;
+  const int32_t inc = block_incl_scan_add<NT, int32_t>((int32_t)kk, scan_sm, &tot);
+  if (tid < nseg) t.base[tid] = (uint32_t)(inc - (int32_t)kk);
+  if (tid == 0) {
+    t.base[nseg] = (uint32_t)tot;
+    *seg_flags = 0;
+  }
+  __syncthreads();
+  const uint32_t K = (uint32_t)tot;
+  const uint32_t Q = (K + NT - 1) / NT;
+  const uint32_t q0 = min(K, (uint32_t)tid * Q), q1 = min(K, q0 + Q);
+  int32_t run = 0;
+  bool anyh = false;
+  uint32_t first_head = q1;
+  int32_t i = q0 < K ? tile_find(t.base, nseg, q0) : 0;
+  for (uint32_t q = q0; q < q1; ++q) {
+    while (q >= t.base[i + 1]) ++i;
+    const uint32_t j = q - t.base[i];
+    const uint32_t b = rstart[i] + 1u + 2u * j;
+    t.start[q] = seg_u[i] + unzigzag32(nums[b]);
+    if (j == 0) {
+      if (!anyh) first_head = q;
+      anyh = true;
+      run = 0;
+    }
+    t.cum[q] = (uint32_t)run;
+    run += (int32_t)nums[b + 1] + 3;
+  }
+  int32_t ex, ex2;
+  tile_seg_scan<NT>(anyh, run, 0, scan_sm, scan_sm2, seg_flags, ex, ex2);
+  for (uint32_t q = q0; q < first_head; ++q) t.cum[q] += (uint32_t)ex;
+  __syncthreads();
+  if (tid < nseg) {
+    const uint32_t b0 = t.base[tid], b1 = t.base[tid + 1];
+    uint32_t L = 0;
+    if (b1 > b0) L = t.cum[b1 - 1] + nums[rstart[tid] + 2u * (b1 - b0)] + 3u;
+    t.L[tid] = L;
+  }
+  if (tid == 0) *seg_flags = 0;
+  __syncthreads();
+  return t;
+}
+
+// Neighbour `loc` of segment i of an interval-coded tile or piece, as one
+// item of the segmented prefix sums: the ID (absolute inside intervals, a
+// head; else the first residual restarts from base_v, later ones are gaps)
+// and the weight difference (the chain restarts at the segment's first
+// neighbour).
+__device__ __forceinline__ void itv_item(const ItvTable& t, const uint32_t* nums, uint32_t rs, int32_t i, uint32_t loc,
+                                         int32_t base_v, bool weighted, int32_t& dv, int32_t& dw, bool& hid) {
+  const uint32_t b0 = t.base[i], b1 = t.base[i + 1];
+  const uint32_t L = t.L[i];
+  const uint32_t wb = rs + 1u + 2u * (b1 - b0);  // first interval weight (or residual code)
+  if (loc < L) {
+    uint32_t lo = b0, hi = b1;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (t.cum[mid] <= loc) lo = mid;
+      else hi = mid;
+    }
+    dv = t.start[lo] + (int32_t)(loc - t.cum[lo]);
+    hid = true;
+    dw = weighted ? unzigzag32(nums[wb + loc]) : 0;
+  } else {
+    const uint32_t r = loc - L;
+    const uint32_t ci = wb + (weighted ? L + 2u * r : r);
+    const uint32_t code = nums[ci];
+    hid = r == 0;
+    dv = hid ? base_v + unzigzag32(code) : (int32_t)code;
+    dw = weighted ? unzigzag32(nums[ci + 1]) : 0;
+  }
 }
 
 // Value of the VarInt whose last byte is byte b (4..7) of the 8-byte window
@@ -477,7 +601,7 @@ __device__ __forceinline__ void tile_select(const RoundCtx& x, const int32_t* ke
   }
 }
 
-template <class T, typename V, bool COMP, int MODE = kModeRate>
+template <class T, typename V, bool COMP, int MODE = kModeRate, bool ITV = false>
 __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd, const int32_t* tiles,
                                                            const uint32_t* ntiles_p, uint32_t* ctr, TileLayout L) {
   constexpr int NT = T::kThreads, VT = T::kVerts, ITEMS = T::kItems, SG = T::kSelGroup;
@@ -529,7 +653,8 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
           const uint32_t len = vd.len[t0 + tid];
           const uint32_t pre = (uint32_t)(pos & 3u);
           ndw = (pre + len + 3u) >> 2;
-          nnum = per * d + 4u * ndw - len;
+          // numbers from the vertex's dwords: its VarInts plus one per zero byte
+          nnum = (ITV ? vd.num[t0 + tid] : per * d) + 4u * ndw - len;
           sh.len[tid] = len;
         }
         nsl = tile_slots(d);
@@ -621,7 +746,60 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
       const uint32_t Dd = (Et + NT - 1) / NT;
       const uint32_t e0 = tid * Dd;
       int32_t vi[ITEMS], nb[ITEMS], wt[ITEMS];
-      {
+      if constexpr (COMP && ITV) {
+        // interval-coded: the interval table (in the staging area), then every
+        // item's ID and weight difference; IDs restart at every interval
+        // neighbour and at the first residual, weights at the vertex's start
+        const ItvTable itv = itv_table<NT, VT, T::kEdges / 3 + 1>(A32, nums, sh.rstart, sh.ebase, sh.u, nv, sh.scan,
+                                                                    sh.scan2, &sh.seg_flags);
+        int32_t i = e0 < Et ? tile_find(sh.ebase, nv, e0) : 0;
+        uint32_t hidm = 0, hwm = 0;
+        int32_t a = 0, a2 = 0;
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+          const uint32_t e = e0 + k;
+          vi[k] = -1;
+          nb[k] = 0;
+          wt[k] = 1;
+          if ((uint32_t)k < Dd && e < Et) {
+            while (e >= sh.ebase[i + 1]) ++i;
+            vi[k] = i;
+            const uint32_t loc = e - sh.ebase[i];
+            int32_t dv, dw;
+            bool hid;
+            itv_item(itv, nums, sh.rstart[i], i, loc, sh.u[i], weighted, dv, dw, hid);
+            const bool hw = loc == 0;
+            a = hid ? dv : a + dv;
+            a2 = hw ? dw : a2 + dw;
+            hidm |= (uint32_t)hid << k;
+            hwm |= (uint32_t)hw << k;
+            nb[k] = a;
+            wt[k] = a2;
+          }
+        }
+        int32_t ex, ex2, unused;
+        tile_seg_scan<NT>(hidm != 0, a, 0, sh.scan, sh.scan2, &sh.seg_flags, ex, unused);
+        __syncthreads();
+        if (tid == 0) sh.seg_flags = 0;
+        __syncthreads();
+        if (weighted) {
+          tile_seg_scan<NT>(hwm != 0, a2, 0, sh.scan, sh.scan2, &sh.seg_flags, ex2, unused);
+          __syncthreads();
+          if (tid == 0) sh.seg_flags = 0;
+        }
+        const uint32_t fid = hidm ? (uint32_t)__ffs(hidm) - 1u : 32u;
+        const uint32_t fw = hwm ? (uint32_t)__ffs(hwm) - 1u : 32u;
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+          if (vi[k] < 0) continue;
+          if ((uint32_t)k < fid) nb[k] += ex;
+          if (weighted) {
+            if ((uint32_t)k < fw) wt[k] += ex2;
+          } else {
+            wt[k] = 1;
+          }
+        }
+      } else {
         int32_t i = e0 < Et ? tile_find(sh.ebase, nv, e0) : 0;
         bool any_head = false;
         int32_t s = 0, s2 = 0;
@@ -807,7 +985,16 @@ struct HubStream {
   uint32_t cnt;    // neighbours | kStreamZig
   int32_t base_v;  // the first neighbour is base_v + (zigzag or gap) code
   int32_t base_w;  // the first weight is base_w + unzigzag(code)
+  uint32_t nnum;   // interval-coded: VarInts in the stream's bytes
+  uint32_t pad;
 };
+
+// VarInts (bytes with the continuation bit clear) in bytes [p0, p1).
+__device__ __forceinline__ uint32_t count_varints(const uint8_t* b, uint64_t p0, uint64_t p1) {
+  uint32_t c = 0;
+  for (uint64_t p = p0; p < p1; ++p) c += (b[p] & 0x80u) ? 0u : 1u;
+  return c;
+}
 
 struct HubMeta {
   const int32_t* u;          // hub vertex
@@ -850,7 +1037,7 @@ __global__ __launch_bounds__(256) void k_hub_streams(GraphView g, HubMeta hm, in
     const uint32_t d = (uint32_t)hm.deg[h];
     const uint32_t npc = (uint32_t)hm.npieces[h];
     HubStream* st = hm.streams + (uint64_t)hm.piece_base[h] * kHubStreams;
-    const HubStream none{0, 0, 0, 0, 0};
+    const HubStream none{0, 0, 0, 0, 0, 0, 0};
     if (g.offs) {
       const Nbh hb = nbh_locate(g, u, d);
       if (hb.nchunks > 1) {
@@ -860,11 +1047,19 @@ __global__ __launch_bounds__(256) void k_hub_streams(GraphView g, HubMeta hm, in
             const uint64_t p0 = nbh_chunk_pos(g, hb, k);
             const uint64_t p1 = k + 1 < hb.nchunks ? nbh_chunk_pos(g, hb, k + 1) : g.offs[u + 1];
             const uint32_t cnt = min((uint32_t)LP_CHUNK_LEN, d - k * LP_CHUNK_LEN);
-            st[k] = HubStream{p0, (uint32_t)(p1 - p0), cnt | kStreamZig, u, 0};
+            const uint32_t nn = g.intervals ? count_varints(g.bytes, p0, p1) : 0u;
+            st[k] = HubStream{p0, (uint32_t)(p1 - p0), cnt | kStreamZig, u, 0, nn, 0};
           } else {
             st[k] = none;
           }
         }
+      } else if (g.intervals) {
+        // an unsplit interval-coded record has at most kHubPiece neighbours:
+        // one piece, one stream over the whole record
+        const uint64_t p0 = hb.codes, p1 = g.offs[u + 1];
+        const uint32_t nn = count_varints(g.bytes, p0, p1);  // every lane counts; lane 0 writes
+        for (uint32_t k = lane; k < npc * kHubStreams; k += kWave)
+          st[k] = k == 0 ? HubStream{p0, (uint32_t)(p1 - p0), d | kStreamZig, u, 0, nn, 0} : none;
       } else {
         uint64_t pos = hb.codes;
         int32_t pv = 0, pw = 0;
@@ -876,7 +1071,8 @@ __global__ __launch_bounds__(256) void k_hub_streams(GraphView g, HubMeta hm, in
                                     [](uint32_t, int32_t, int32_t) {});
           if (lane < kHubStreams)
             st[(uint64_t)j * kHubStreams + lane] =
-                lane == 0 ? HubStream{p0, (uint32_t)(pos - p0), cnt | (j == 0 ? kStreamZig : 0u), bv, bw} : none;
+                lane == 0 ? HubStream{p0, (uint32_t)(pos - p0), cnt | (j == 0 ? kStreamZig : 0u), bv, bw, 0, 0}
+                          : none;
         }
       }
     } else {
@@ -884,7 +1080,7 @@ __global__ __launch_bounds__(256) void k_hub_streams(GraphView g, HubMeta hm, in
       for (uint32_t k = lane; k < npc * kHubStreams; k += kWave) {
         const uint32_t j = k / kHubStreams;
         const uint32_t cnt = min((uint32_t)kHubPiece, d - j * kHubPiece);
-        st[k] = (k % kHubStreams == 0) ? HubStream{e0 + (uint64_t)j * kHubPiece, 0, cnt, 0, 0} : none;
+        st[k] = (k % kHubStreams == 0) ? HubStream{e0 + (uint64_t)j * kHubPiece, 0, cnt, 0, 0, 0, 0} : none;
       }
     }
   }
@@ -908,7 +1104,7 @@ struct PieceShared {
 };
 
 // H1: one workgroup per hub piece.
-template <typename V, bool COMP, int MODE = kModeRate>
+template <typename V, bool COMP, int MODE = kModeRate, bool ITV = false>
 __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta hm, int32_t npieces,
                                                             uint32_t* ctr, TileLayout L) {
   constexpr int NT = kPieceThreads, ITEMS = kPieceItems, NS = kHubStreams;
@@ -955,7 +1151,7 @@ __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta
         if (COMP && cnt > 0) {
           const uint32_t ndw = (pre + hs.len + 3u) >> 2;
           dw += ndw;
-          nn += per * cnt + 4u * ndw - hs.len;
+          nn += (ITV ? hs.nnum : per * cnt) + 4u * ndw - hs.len;
         }
       }
       sh.ebase[NS] = e;
@@ -1025,7 +1221,60 @@ __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta
     const uint32_t Dd = (Et + NT - 1) / NT;
     const uint32_t e0 = tid * Dd;
     int32_t vi[ITEMS], nb[ITEMS], wt[ITEMS];
-    {
+    if constexpr (COMP && ITV) {
+      // interval-coded: every stream is a chunk start (see k_hub_streams)
+      const ItvTable itv = itv_table<NT, NS, kHubPiece / 3 + 1>(A32, nums, sh.rstart, sh.ebase, sh.base_v, NS,
+                                                                 sh.scan, sh.scan2, &sh.seg_flags);
+      int32_t s = 0;
+      if (e0 < Et)
+        while (e0 >= sh.ebase[s + 1]) ++s;
+      uint32_t hidm = 0, hwm = 0;
+      int32_t a = 0, a2 = 0;
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t e = e0 + k;
+        vi[k] = -1;
+        nb[k] = 0;
+        wt[k] = 1;
+        if ((uint32_t)k < Dd && e < Et) {
+          while (e >= sh.ebase[s + 1]) ++s;
+          vi[k] = s;
+          const uint32_t loc = e - sh.ebase[s];
+          int32_t dv, dw;
+          bool hid;
+          itv_item(itv, nums, sh.rstart[s], s, loc, sh.base_v[s], weighted, dv, dw, hid);
+          const bool hw = loc == 0;
+          a = hid ? dv : a + dv;
+          a2 = hw ? dw : a2 + dw;
+          hidm |= (uint32_t)hid << k;
+          hwm |= (uint32_t)hw << k;
+          nb[k] = a;
+          wt[k] = a2;
+        }
+      }
+      int32_t ex, ex2, unused;
+      tile_seg_scan<NT>(hidm != 0, a, 0, sh.scan, sh.scan2, &sh.seg_flags, ex, unused);
+      __syncthreads();
+      if (tid == 0) sh.seg_flags = 0;
+      __syncthreads();
+      if (weighted) {
+        tile_seg_scan<NT>(hwm != 0, a2, 0, sh.scan, sh.scan2, &sh.seg_flags, ex2, unused);
+        __syncthreads();
+        if (tid == 0) sh.seg_flags = 0;
+      }
+      const uint32_t fid = hidm ? (uint32_t)__ffs(hidm) - 1u : 32u;
+      const uint32_t fw = hwm ? (uint32_t)__ffs(hwm) - 1u : 32u;
+#pragma unroll
+      for (int k = 0; k < ITEMS; ++k) {
+        if (vi[k] < 0) continue;
+        if ((uint32_t)k < fid) nb[k] += ex;
+        if (weighted) {
+          if ((uint32_t)k < fw) wt[k] += ex2;
+        } else {
+          wt[k] = 1;
+        }
+      }
+    } else {
       int32_t s = 0;
       if (e0 < Et)
         while (e0 >= sh.ebase[s + 1]) ++s;
@@ -1427,7 +1676,7 @@ __global__ void k_subround_deg(const int32_t* deg, int32_t n, uint32_t S, uint32
 // first code (compressed: after the first-edge header; these degrees are
 // never chunked) or first edge (plain).
 __global__ void k_build_desc(GraphView g, const int32_t* order, const int32_t* deg, int32_t cnt, int4* vdesc,
-                             uint32_t* vlen) {
+                             uint32_t* vlen, uint32_t* vnum) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t u = order[i];
     uint64_t pos;
@@ -1440,6 +1689,7 @@ __global__ void k_build_desc(GraphView g, const int32_t* order, const int32_t* d
     }
     vdesc[i] = make_int4(u, deg[u], (int)(uint32_t)pos, (int)(uint32_t)(pos >> 32));
     vlen[i] = len;
+    if (vnum) vnum[i] = count_varints(g.bytes, pos, pos + len);
   }
 }
 
@@ -1530,10 +1780,12 @@ __global__ __launch_bounds__(kCpThreads) void k_prop_count(const int32_t* ptgt, 
 }
 
 // Writes the proposals in increasing vertex order: key = target << G |
-// (2^G - 1 - gain), value = vertex; clears the proposal slots it took.
+// (2^G - 1 - gain), value = vertex. With sub-rounds it clears the proposal
+// slots it took (a later sub-round rates other vertices only); with one
+// sub-round every rated vertex writes its slot again in the next round.
 __global__ __launch_bounds__(kCpThreads) void k_prop_write(int32_t* ptgt, const int64_t* pgain, int32_t n,
                                                            const uint32_t* boff, int G, uint64_t* keys,
-                                                           uint32_t* vals, const uint32_t* done) {
+                                                           uint32_t* vals, const uint32_t* done, int reset) {
   __shared__ uint32_t sm[kCpThreads / kWave];
   if (*done) return;
   const int64_t base = (int64_t)blockIdx.x * kCpTile + (int64_t)threadIdx.x * kCpItems;
@@ -1554,7 +1806,7 @@ __global__ __launch_bounds__(kCpThreads) void k_prop_write(int32_t* ptgt, const 
         keys[o] = ((uint64_t)(uint32_t)t << G) | (dmax - (uint64_t)pgain[u]);
         vals[o] = (uint32_t)u;
         ++o;
-        ptgt[u] = -1;  // taken: a later sub-round rates other vertices only
+        if (reset) ptgt[u] = -1;
       }
     }
   }
@@ -1705,12 +1957,12 @@ inline RateWidth rate_width(const lp_graph* g) {
   return g->weighted ? RateWidth::k32 : RateWidth::k16;
 }
 
-template <class T, typename V, bool COMP, int MODE = kModeRate>
+template <class T, typename V, bool COMP, int MODE = kModeRate, bool ITV = false>
 lp_status launch_tile(const RoundCtx& x, VDesc vd, const int32_t* tiles, const uint32_t* ntiles, uint32_t* ctr,
                       unsigned grid, bool weighted, hipStream_t s) {
   const TileLayout L = tile_layout<T, V>(COMP, weighted);
   const size_t bytes = (size_t)L.abytes + sizeof(TileShared<T::kThreads, T::kVerts>);
-  auto kern = k_rate_tile<T, V, COMP, MODE>;
+  auto kern = k_rate_tile<T, V, COMP, MODE, ITV>;
   LP_CHECK(set_lds(kern, bytes));
   hipLaunchKernelGGL(kern, dim3(grid), dim3(T::kThreads), bytes, s, x, vd, tiles, ntiles, ctr, L);
   return last_error();
@@ -1719,6 +1971,13 @@ lp_status launch_tile(const RoundCtx& x, VDesc vd, const int32_t* tiles, const u
 template <class T>
 lp_status launch_tile_any(bool comp, RateWidth rw, const RoundCtx& x, VDesc vd, const int32_t* tiles,
                           const uint32_t* ntiles, uint32_t* ctr, unsigned grid, bool weighted, hipStream_t s) {
+  if (comp && x.g.intervals) {
+    if (rw == RateWidth::k16)
+      return launch_tile<T, uint16_t, true, kModeRate, true>(x, vd, tiles, ntiles, ctr, grid, weighted, s);
+    if (rw == RateWidth::k64)
+      return launch_tile<T, int64_t, true, kModeRate, true>(x, vd, tiles, ntiles, ctr, grid, weighted, s);
+    return launch_tile<T, int32_t, true, kModeRate, true>(x, vd, tiles, ntiles, ctr, grid, weighted, s);
+  }
   if (comp) {
     if (rw == RateWidth::k16) return launch_tile<T, uint16_t, true>(x, vd, tiles, ntiles, ctr, grid, weighted, s);
     if (rw == RateWidth::k64) return launch_tile<T, int64_t, true>(x, vd, tiles, ntiles, ctr, grid, weighted, s);
@@ -1734,19 +1993,35 @@ TileLayout piece_layout_of(bool comp, bool weighted) {
   TileLayout L;
   const uint32_t per = weighted ? 2u : 1u;
   L.table_bytes = (uint32_t)kPieceSlots * (4u + (uint32_t)sizeof(V));
-  const uint32_t nums = comp ? (per * kHubPiece + 6u * kHubStreams) * 4u : 0u;
-  const uint32_t worst = comp ? 5u * per * kHubPiece + 8u * kHubStreams : 0u;
-  L.stage_bytes = comp ? ((worst + 15u) & ~15u) : 0u;
+  const uint32_t nums = comp ? (per * kHubPiece + 7u * kHubStreams) * 4u : 0u;
+  const uint32_t worst = comp ? 5u * per * kHubPiece + 16u * kHubStreams : 0u;
+  const uint32_t itv = comp ? (2u * kHubStreams + 2u + 2u * ((uint32_t)kHubPiece / 3u + 1u)) * 4u : 0u;
+  L.stage_bytes = comp ? ((std::max(worst, itv) + 15u) & ~15u) : 0u;
   L.nums_off = L.stage_bytes;
   L.abytes = std::max(L.table_bytes, L.stage_bytes + nums);
   L.abytes = (L.abytes + 15u) & ~15u;
   return L;
 }
 
+// The lane kernel for the graph's format.
+template <int MODE = kModeRate>
+lp_status launch_lane(const RoundCtx& x, VDesc vd, int32_t cnt, hipStream_t s) {
+  const bool comp = x.g.offs != nullptr;
+  if (comp && x.g.intervals)
+    hipLaunchKernelGGL((k_rate_lane<true, MODE, true>), dim3(grid_for(cnt, 256)), dim3(256), 0, s, x, vd, cnt);
+  else if (comp)
+    hipLaunchKernelGGL((k_rate_lane<true, MODE>), dim3(grid_for(cnt, 256)), dim3(256), 0, s, x, vd, cnt);
+  else
+    hipLaunchKernelGGL((k_rate_lane<false, MODE>), dim3(grid_for(cnt, 256)), dim3(256), 0, s, x, vd, cnt);
+  return last_error();
+}
+
 template <int MODE = kModeRate>
 lp_status launch_piece(bool comp, bool wide, const RoundCtx& x, const HubMeta& hm, int32_t npieces, uint32_t* ctr,
                        const TileLayout& L, size_t lds, hipStream_t s) {
-  auto kern = comp ? (wide ? k_hub_piece<int64_t, true, MODE> : k_hub_piece<int32_t, true, MODE>)
+  auto kern = comp ? (x.g.intervals ? (wide ? k_hub_piece<int64_t, true, MODE, true>
+                                            : k_hub_piece<int32_t, true, MODE, true>)
+                                    : (wide ? k_hub_piece<int64_t, true, MODE> : k_hub_piece<int32_t, true, MODE>))
                    : (wide ? k_hub_piece<int64_t, false, MODE> : k_hub_piece<int32_t, false, MODE>);
   LP_CHECK(set_lds(kern, lds));
   const unsigned grid = grid_for(npieces, 1, 2048);
@@ -1854,12 +2129,17 @@ struct Plan {
   uint64_t rsum = 0, psum = 0;
   unsigned long long bsums[2 * kNumBuckets] = {};
   PlanMem mem;
-  VDesc vd(int b) const { return VDesc{vdesc + bstart[b], vlen + bstart[b]}; }
+  uint32_t* vnum = nullptr;  // interval-coded graphs: VarInts of every listed vertex
+  VDesc vd(int b) const { return VDesc{vdesc + bstart[b], vlen + bstart[b], vnum ? vnum + bstart[b] : nullptr}; }
 };
 
 lp_status build_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t t_block, int32_t hub_part,
                      hipStream_t s, Plan& P, int32_t sub_S = 1, int32_t sub_r = 0) {
   const int32_t n = g->n;
+  // interval-coded records above LP_ITV_CHUNK_THRESHOLD are chunked: the hub
+  // path rates them, whatever the tile bucket's bound
+  if (g->intervals && t_block > LP_ITV_CHUNK_THRESHOLD) t_block = LP_ITV_CHUNK_THRESHOLD;
+  if (t_tile > t_block) t_tile = t_block;
   P.sub_S = sub_S;
   P.sub_r = sub_r;
   P.t_lane = t_lane;
@@ -1910,10 +2190,11 @@ lp_status build_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t 
   const int32_t nlisted = (int32_t)P.bstart[3];
   P.vdesc = P.mem.alloc<int4>(nlisted);
   P.vlen = P.mem.alloc<uint32_t>(nlisted);
+  if (g->intervals) P.vnum = P.mem.alloc<uint32_t>(nlisted);
   if (P.mem.failed) return LP_ENOMEM;
   if (nlisted > 0) {
     hipLaunchKernelGGL(k_build_desc, dim3(grid_for(nlisted, 256, 65536)), dim3(256), 0, s, g->view(), P.order, deg,
-                       nlisted, P.vdesc, P.vlen);
+                       nlisted, P.vdesc, P.vlen, P.vnum);
     LP_CHECK_LAUNCH();
   }
   // tiles of the two tile buckets
@@ -2046,12 +2327,13 @@ lp_status visit_edges_mode(const lp_graph* g, const int32_t* C, const uint64_t* 
   if (plan->bn[0] > 0) {
     const VDesc vd = plan->vd(0);
     const int32_t c = plan->bn[0];
-    if (comp) hipLaunchKernelGGL((k_rate_lane<true, MODE>), dim3(grid_for(c, 256)), dim3(256), 0, s, x, vd, c);
-    else hipLaunchKernelGGL((k_rate_lane<false, MODE>), dim3(grid_for(c, 256)), dim3(256), 0, s, x, vd, c);
-    LP_CHECK_LAUNCH();
+    LP_CHECK(launch_lane<MODE>(x, vd, c, s));
   }
   if (plan->bn[1] > 0) {
-    if (comp)
+    if (comp && g->intervals)
+      LP_CHECK((launch_tile<TileSmall, int32_t, true, MODE, true>(x, plan->vd(1), plan->tps.tiles, plan->tps.ntiles,
+                                                                  zero + 8, plan->tps.grid, g->weighted, s)));
+    else if (comp)
       LP_CHECK((launch_tile<TileSmall, int32_t, true, MODE>(x, plan->vd(1), plan->tps.tiles, plan->tps.ntiles,
                                                             zero + 8, plan->tps.grid, g->weighted, s)));
     else
@@ -2059,7 +2341,10 @@ lp_status visit_edges_mode(const lp_graph* g, const int32_t* C, const uint64_t* 
                                                              zero + 8, plan->tps.grid, g->weighted, s)));
   }
   if (plan->bn[2] > 0) {
-    if (comp)
+    if (comp && g->intervals)
+      LP_CHECK((launch_tile<TileLarge, int32_t, true, MODE, true>(x, plan->vd(2), plan->tpl.tiles, plan->tpl.ntiles,
+                                                                  zero + 16, plan->tpl.grid, g->weighted, s)));
+    else if (comp)
       LP_CHECK((launch_tile<TileLarge, int32_t, true, MODE>(x, plan->vd(2), plan->tpl.tiles, plan->tpl.ntiles,
                                                             zero + 16, plan->tpl.grid, g->weighted, s)));
     else
@@ -2449,13 +2734,7 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
         }
         if (bn[0] > 0) {
           LP_CHECK(begin(LP_PHASE_LANE, side[2]));
-          if (g->compressed)
-            hipLaunchKernelGGL(k_rate_lane<true>, dim3(grid_for(bn[0], 256)), dim3(256), 0, side[2], x, vd_of(0),
-                               bn[0]);
-          else
-            hipLaunchKernelGGL(k_rate_lane<false>, dim3(grid_for(bn[0], 256)), dim3(256), 0, side[2], x, vd_of(0),
-                               bn[0]);
-          LP_CHECK_LAUNCH();
+          LP_CHECK(launch_lane(x, vd_of(0), bn[0], side[2]));
           LP_CHECK(end(side[2]));
         }
         if (bn[1] > 0) {
@@ -2472,7 +2751,8 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
       hipLaunchKernelGGL(k_prop_count, dim3(ncp), dim3(kCpThreads), 0, s, ptgt, n, pcnt, &ctl->done);
       LP_CHECK_LAUNCH();
       LP_CHECK(scan_exclusive_u32(pcnt, pcnt, ncp, &ctl->count, sc));
-      hipLaunchKernelGGL(k_prop_write, dim3(ncp), dim3(kCpThreads), 0, s, ptgt, pgain, n, pcnt, G, ka, va, &ctl->done);
+      hipLaunchKernelGGL(k_prop_write, dim3(ncp), dim3(kCpThreads), 0, s, ptgt, pgain, n, pcnt, G, ka, va, &ctl->done,
+                         S > 1 ? 1 : 0);
       LP_CHECK_LAUNCH();
       uint64_t* ks;
       uint32_t* vs;

@@ -202,6 +202,235 @@ __global__ __launch_bounds__(256) void k_encode(CsrIn g, const uint64_t* offs, u
   }
 }
 
+// ------------------------------------------------- interval encoding ----
+// Interval-coded records (Section III-A; layout in lp.h): one lane writes a
+// whole record, chunk by chunk, in four passes over each chunk's sorted
+// neighbours: the interval count, the (start, length - 3) pairs, the weights
+// of the interval neighbours, and the remaining neighbours gap encoded.
+// A run is a maximal stretch of IDs each one above the previous neighbour's,
+// found left to right; runs of three or more are intervals.
+__device__ __forceinline__ uint32_t put_or_len(uint8_t* out, uint64_t pos, uint64_t x) {
+  return out ? varint_put(out + pos, x) : varint_len(x);
+}
+
+__device__ __forceinline__ uint64_t run_end(const int32_t* a, uint64_t i, uint64_t e) {
+  uint64_t j = i + 1;
+  while (j < e && (int64_t)a[j] == (int64_t)a[j - 1] + 1) ++j;
+  return j;
+}
+
+// Size of u's record (out == nullptr) or the record written at out.
+__device__ uint64_t itv_record(const CsrIn& g, int64_t u, uint8_t* out) {
+  const uint64_t b = g.xadj[u], e = g.xadj[u + 1], d = e - b;
+  const int32_t* a = g.adjncy;
+  const uint64_t nch = d > LP_ITV_CHUNK_THRESHOLD ? (d + LP_CHUNK_LEN - 1) / LP_CHUNK_LEN : 1;
+  uint64_t k = put_or_len(out, 0, b);
+  const uint64_t table = k;
+  if (nch > 1) k += 4 * (nch - 1);
+  for (uint64_t ch = 0; ch < nch; ++ch) {
+    const uint64_t cb = nch > 1 ? b + ch * LP_CHUNK_LEN : b;
+    const uint64_t ce = nch > 1 ? min(e, cb + LP_CHUNK_LEN) : e;
+    if (ch > 0 && out) {
+      const uint32_t rel = (uint32_t)k;
+      uint8_t* t = out + table + 4 * (ch - 1);
+      t[0] = (uint8_t)rel;
+      t[1] = (uint8_t)(rel >> 8);
+      t[2] = (uint8_t)(rel >> 16);
+      t[3] = (uint8_t)(rel >> 24);
+    }
+    uint64_t cnt = 0;
+    for (uint64_t i = cb; i < ce;) {
+      const uint64_t j = run_end(a, i, ce);
+      if (j - i >= 3) {
+        ++cnt;
+        i = j;
+      } else {
+        ++i;
+      }
+    }
+    k += put_or_len(out, k, cnt);
+    for (uint64_t i = cb; i < ce;) {
+      const uint64_t j = run_end(a, i, ce);
+      if (j - i >= 3) {
+        k += put_or_len(out, k, zigzag((int64_t)a[i] - u));
+        k += put_or_len(out, k, j - i - 3);
+        i = j;
+      } else {
+        ++i;
+      }
+    }
+    int64_t wprev = 0;
+    if (g.adjwgt)
+      for (uint64_t i = cb; i < ce;) {
+        const uint64_t j = run_end(a, i, ce);
+        if (j - i >= 3) {
+          for (uint64_t t = i; t < j; ++t) {
+            k += put_or_len(out, k, zigzag((int64_t)g.adjwgt[t] - wprev));
+            wprev = g.adjwgt[t];
+          }
+          i = j;
+        } else {
+          ++i;
+        }
+      }
+    bool first = true;
+    int64_t rprev = 0;
+    for (uint64_t i = cb; i < ce;) {
+      const uint64_t j = run_end(a, i, ce);
+      if (j - i >= 3) {
+        i = j;
+        continue;
+      }
+      k += put_or_len(out, k, first ? zigzag((int64_t)a[i] - u) : (uint64_t)((int64_t)a[i] - rprev));
+      if (g.adjwgt) {
+        k += put_or_len(out, k, zigzag((int64_t)g.adjwgt[i] - wprev));
+        wprev = g.adjwgt[i];
+      }
+      rprev = a[i];
+      first = false;
+      ++i;
+    }
+  }
+  return k;
+}
+
+__global__ void k_record_size_itv(CsrIn g, uint64_t* size) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < g.n; u += (int64_t)gridDim.x * blockDim.x)
+    size[u] = itv_record(g, u, nullptr);
+}
+
+__global__ void k_encode_itv(CsrIn g, const uint64_t* offs, uint8_t* out) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < g.n; u += (int64_t)gridDim.x * blockDim.x)
+    (void)itv_record(g, u, out + offs[u]);
+}
+
+// Bounded VarInt read for decompression: false past `end` or beyond 64 bits.
+__device__ __forceinline__ bool varint_read_to(const uint8_t* b, uint64_t end, uint64_t& pos, uint64_t& x) {
+  x = 0;
+  for (int shift = 0; shift < 64; shift += 7) {
+    if (pos >= end) return false;
+    const uint32_t c = b[pos++];
+    x |= (uint64_t)(c & 0x7F) << shift;
+    if (!(c & 0x80)) return true;
+  }
+  return false;
+}
+
+// One chunk of an interval-coded record written in (ID, weight) order: the
+// interval neighbours and the other neighbours are each increasing in that
+// order, so one lane merges the two on the fly. False on a malformed chunk.
+__device__ bool itv_chunk_sorted(const GraphView& g, int32_t u, uint64_t pos, uint64_t end, uint32_t cnt,
+                                 int32_t* ids, int32_t* wts) {
+  const uint8_t* B = g.bytes;
+  uint64_t kk, x;
+  if (!varint_read_to(B, end, pos, kk) || kk > cnt) return false;
+  const uint64_t pairs = pos;
+  uint64_t L = 0;
+  for (uint64_t j = 0; j < kk; ++j) {
+    uint64_t len;
+    if (!varint_read_to(B, end, pos, x) || !varint_read_to(B, end, pos, len)) return false;
+    L += len + 3;
+  }
+  if (L > cnt) return false;
+  // interval weights start at pos; the residuals after them
+  const uint64_t wstart = pos;
+  int64_t wlast = 0;
+  if (g.weighted)
+    for (uint64_t t = 0; t < L; ++t) {
+      if (!varint_read_to(B, end, pos, x)) return false;
+      wlast += unzigzag(x);
+    }
+  uint64_t pa = pairs, pw = wstart, pr = pos;
+  // cursor A: interval neighbours; cursor B: the other neighbours
+  uint64_t ja = 0, rema = 0, nb_left = cnt - L;
+  int64_t va = 0, wa = 0, vb = 0, wb = wlast;
+  bool has_a = false, has_b = false, first_b = true;
+  auto next_a = [&]() -> bool {
+    if (rema == 0) {
+      if (ja == kk) {
+        has_a = false;
+        return true;
+      }
+      uint64_t zs, len;
+      if (!varint_read_to(B, end, pa, zs) || !varint_read_to(B, end, pa, len)) return false;
+      va = (int64_t)u + unzigzag(zs);
+      rema = len + 3;
+      ++ja;
+    } else {
+      ++va;
+    }
+    --rema;
+    if (g.weighted) {
+      uint64_t c;
+      if (!varint_read_to(B, end, pw, c)) return false;
+      wa += unzigzag(c);
+    } else {
+      wa = 1;
+    }
+    has_a = true;
+    return va >= 0 && va < g.n;
+  };
+  auto next_b = [&]() -> bool {
+    if (nb_left == 0) {
+      has_b = false;
+      return true;
+    }
+    uint64_t c;
+    if (!varint_read_to(B, end, pr, c)) return false;
+    vb = first_b ? (int64_t)u + unzigzag(c) : vb + (int64_t)c;
+    first_b = false;
+    if (g.weighted) {
+      if (!varint_read_to(B, end, pr, c)) return false;
+      wb += unzigzag(c);
+    } else {
+      wb = 1;
+    }
+    --nb_left;
+    has_b = true;
+    return vb >= 0 && vb < g.n;
+  };
+  if (!next_a() || !next_b()) return false;
+  for (uint32_t i = 0; i < cnt; ++i) {
+    const bool take_a = has_a && (!has_b || va < vb || (va == vb && wa <= wb));
+    if (take_a) {
+      ids[i] = (int32_t)va;
+      if (wts) wts[i] = (int32_t)wa;
+      if (!next_a()) return false;
+    } else {
+      if (!has_b) return false;
+      ids[i] = (int32_t)vb;
+      if (wts) wts[i] = (int32_t)wb;
+      if (!next_b()) return false;
+    }
+  }
+  return pr == end;
+}
+
+// Decompression of an interval-coded graph: one lane per vertex, chunk by
+// chunk; the whole record must be consumed.
+__global__ void k_decode_all_itv(GraphView g, const uint64_t* xadj, int32_t* adjncy, int32_t* adjwgt,
+                                 uint32_t* err) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < g.n; u += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t fe = xadj[u];
+    const uint32_t deg = (uint32_t)(xadj[u + 1] - fe);
+    if (deg == 0) continue;
+    const Nbh h = nbh_locate(g, (int32_t)u, deg);
+    for (uint32_t ch = 0; ch < h.nchunks; ++ch) {
+      const uint64_t p0 = nbh_chunk_pos(g, h, ch);
+      const uint64_t p1 = ch + 1 < h.nchunks ? nbh_chunk_pos(g, h, ch + 1) : g.offs[u + 1];
+      const uint32_t first = ch * LP_CHUNK_LEN;
+      const uint32_t cnt = (h.nchunks > 1) ? min((uint32_t)LP_CHUNK_LEN, deg - first) : deg;
+      if (p1 < p0 || p1 > g.offs[u + 1] ||
+          !itv_chunk_sorted(g, (int32_t)u, p0, p1, cnt, adjncy + fe + first, adjwgt ? adjwgt + fe + first : nullptr)) {
+        atomicOr(err, 1u);
+        break;
+      }
+      if (adjwgt && !g.weighted)
+        for (uint32_t i = 0; i < cnt; ++i) adjwgt[fe + first + i] = 1;
+    }
+  }
+}
+
 __global__ void k_degrees_comp(GraphView g, int32_t* deg) {
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < g.n; u += (int64_t)gridDim.x * blockDim.x) {
     uint64_t p;
@@ -323,7 +552,8 @@ lp_status compute_degrees(const lp_graph* g, int32_t* deg, hipStream_t s) {
 using namespace lp;
 
 static lp_status make_handle(int32_t n, const uint64_t* xadj, const int32_t* adjncy, const int32_t* adjwgt,
-                             const int32_t* vwgt, void* stream, bool compress, lp_graph** out) {
+                             const int32_t* vwgt, void* stream, bool compress, lp_graph** out,
+                             bool intervals = false) {
   if (!out || n < 0 || (n > 0 && (!xadj || !adjncy)) || (n == 0 && !xadj)) return LP_EINVAL;
   *out = nullptr;
   hipStream_t s = (hipStream_t)stream;
@@ -359,6 +589,7 @@ static lp_status make_handle(int32_t n, const uint64_t* xadj, const int32_t* adj
       break;
     }
     g->compressed = 1;
+    g->intervals = intervals ? 1 : 0;
     uint64_t* size = sc.alloc<uint64_t>((size_t)n + 1);
     uint64_t* total_dev = sc.alloc<uint64_t>(1);
     if (!size || !total_dev) {
@@ -370,7 +601,10 @@ static lp_status make_handle(int32_t n, const uint64_t* xadj, const int32_t* adj
       break;
     }
     if (n > 0) {
-      hipLaunchKernelGGL(k_record_size, dim3(grid_for((int64_t)n * kWave, 256, 65536)), dim3(256), 0, s, in, size);
+      if (intervals)
+        hipLaunchKernelGGL(k_record_size_itv, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, in, size);
+      else
+        hipLaunchKernelGGL(k_record_size, dim3(grid_for((int64_t)n * kWave, 256, 65536)), dim3(256), 0, s, in, size);
       st = last_error();
       if (st) break;
     }
@@ -396,8 +630,11 @@ static lp_status make_handle(int32_t n, const uint64_t* xadj, const int32_t* adj
       break;
     }
     if (n > 0) {
-      hipLaunchKernelGGL(k_encode, dim3(grid_for((int64_t)n * kWave, 256, 65536)), dim3(256), 0, s, in, g->offs,
-                         g->bytes);
+      if (intervals)
+        hipLaunchKernelGGL(k_encode_itv, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, in, g->offs, g->bytes);
+      else
+        hipLaunchKernelGGL(k_encode, dim3(grid_for((int64_t)n * kWave, 256, 65536)), dim3(256), 0, s, in, g->offs,
+                           g->bytes);
       st = last_error();
     }
   } while (0);
@@ -414,6 +651,13 @@ extern "C" lp_status lp_compress(int32_t n, const uint64_t* xadj, const int32_t*
                                  const int32_t* vwgt, void* stream, lp_graph** out) {
   clear_error();
   return make_handle(n, xadj, adjncy, adjwgt, vwgt, stream, true, out);
+}
+
+extern "C" lp_status lp_compress_ex(int32_t n, const uint64_t* xadj, const int32_t* adjncy, const int32_t* adjwgt,
+                                    const int32_t* vwgt, int32_t flags, void* stream, lp_graph** out) {
+  clear_error();
+  if (flags & ~LP_COMPRESS_INTERVALS) return LP_EINVAL;
+  return make_handle(n, xadj, adjncy, adjwgt, vwgt, stream, true, out, (flags & LP_COMPRESS_INTERVALS) != 0);
 }
 
 extern "C" lp_status lp_graph_from_csr(int32_t n, const uint64_t* xadj, const int32_t* adjncy,
@@ -470,8 +714,12 @@ extern "C" lp_status lp_decompress(const lp_graph* g, uint64_t* xadj, int32_t* a
   hipLaunchKernelGGL(k_xadj_from_headers, dim3(grid_for((int64_t)g->n + 1, 256, 65536)), dim3(256), 0, s, v, xadj);
   LP_CHECK_LAUNCH();
   if (g->n) {
-    hipLaunchKernelGGL(k_decode_all, dim3(grid_for((int64_t)g->n * kWave, 256, 65536)), dim3(256), 0, s, v, xadj,
-                       adjncy, adjwgt, err);
+    if (g->intervals)
+      hipLaunchKernelGGL(k_decode_all_itv, dim3(grid_for(g->n, 256, 65536)), dim3(256), 0, s, v, xadj, adjncy, adjwgt,
+                         err);
+    else
+      hipLaunchKernelGGL(k_decode_all, dim3(grid_for((int64_t)g->n * kWave, 256, 65536)), dim3(256), 0, s, v, xadj,
+                         adjncy, adjwgt, err);
     LP_CHECK_LAUNCH();
   }
   uint32_t h = 0;
@@ -487,7 +735,7 @@ extern "C" lp_status lp_graph_info(const lp_graph* g, int32_t* n, uint64_t* two_
   if (n) *n = g->n;
   if (two_m) *two_m = g->two_m;
   if (nbytes) *nbytes = g->nbytes;
-  if (is_compressed) *is_compressed = g->compressed;
+  if (is_compressed) *is_compressed = g->compressed ? (g->intervals ? 2 : 1) : 0;
   if (has_edge_weights) *has_edge_weights = g->weighted;
   if (total_vwgt) *total_vwgt = g->total_vwgt;
   return LP_OK;

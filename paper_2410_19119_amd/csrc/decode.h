@@ -7,7 +7,9 @@
 //    (bit 7 clear), assembles each number from the at most five bytes that
 //    precede its terminator, compacts the numbers into LDS in stream order by
 //    a prefix count of terminators, and turns gaps into neighbour IDs with a
-//    group-wide prefix sum.
+//    group-wide prefix sum (gap-only format);
+//  - LaneDec / lane_decode_chunk: one lane walks one chunk of either format,
+//    the interval neighbours of an interval-coded chunk first.
 #pragma once
 
 #include "lp_device.h"
@@ -18,7 +20,7 @@ namespace lp {
 struct Nbh {
   uint64_t rec;     // offs[u]
   uint64_t codes;   // first code of chunk 0
-  uint32_t nchunks; // 1 unless deg > LP_CHUNK_THRESHOLD
+  uint32_t nchunks; // 1 unless deg > chunk_threshold(intervals)
 };
 
 __device__ __forceinline__ Nbh nbh_locate(const GraphView& g, int32_t u, uint32_t deg) {
@@ -26,7 +28,7 @@ __device__ __forceinline__ Nbh nbh_locate(const GraphView& g, int32_t u, uint32_
   uint64_t pos;
   (void)read_header(g, u, pos);
   h.rec = g.offs[u];
-  h.nchunks = deg > LP_CHUNK_THRESHOLD ? (deg + LP_CHUNK_LEN - 1) / LP_CHUNK_LEN : 1;
+  h.nchunks = deg > chunk_threshold(g.intervals) ? (deg + LP_CHUNK_LEN - 1) / LP_CHUNK_LEN : 1;
   h.codes = pos + (h.nchunks > 1 ? 4ull * (h.nchunks - 1) : 0ull);
   return h;
 }
@@ -156,23 +158,81 @@ __device__ bool group_decode(const uint8_t* __restrict__ bytes, uint64_t& pos, i
   return true;
 }
 
+// One lane's decoder of one chunk (a whole unsplit neighbourhood, or one
+// chunk of a split one) whose codes start at byte pos: next() yields the
+// chunk's neighbours one by one with their weights (1 for unit weights). In
+// an interval-coded chunk it first walks the (start, length) pairs and the
+// interval weights (a second cursor), then the gap-coded residuals, whose
+// codes follow the interval weights.
+struct LaneDec {
+  const uint8_t* b;
+  uint64_t pos;   // next pair, then next residual code
+  uint64_t wpos;  // next interval weight
+  int32_t u, x, v, w;
+  uint32_t kleft, rem;
+  bool weighted, itv, first_res;
+
+  __device__ __forceinline__ void init(const GraphView& g, int32_t u_, uint64_t p) {
+    b = g.bytes;
+    u = u_;
+    pos = p;
+    weighted = g.weighted != 0;
+    itv = g.intervals != 0;
+    x = v = w = 0;
+    rem = 0;
+    kleft = 0;
+    first_res = true;
+    if (itv) {
+      kleft = (uint32_t)varint_read(b, pos);
+      wpos = pos;
+      for (uint32_t j = 0; j < 2 * kleft; ++j) (void)varint_read(b, wpos);
+      if (kleft == 0) pos = wpos;
+    }
+  }
+
+  __device__ __forceinline__ void next(int32_t& ov, int32_t& ow) {
+    if (rem > 0 || kleft > 0) {
+      if (rem == 0) {
+        x = u + (int32_t)unzigzag(varint_read(b, pos));
+        rem = 3 + (uint32_t)varint_read(b, pos);
+        --kleft;
+      }
+      ov = x++;
+      --rem;
+      if (weighted) w += (int32_t)unzigzag(varint_read(b, wpos));
+      if (rem == 0 && kleft == 0) pos = wpos;  // residuals follow the interval weights
+    } else {
+      const uint64_t code = varint_read(b, pos);
+      v = first_res ? u + (int32_t)unzigzag(code) : v + (int32_t)code;
+      first_res = false;
+      ov = v;
+      if (weighted) w += (int32_t)unzigzag(varint_read(b, pos));
+    }
+    ow = weighted ? w : 1;
+  }
+};
+
+// Serial decode of one chunk of cnt neighbours by one lane: f(i, v, w) for
+// i = 0..cnt-1 in decoding order.
+template <typename F>
+__device__ __forceinline__ void lane_decode_chunk(const GraphView& g, int32_t u, uint64_t pos, uint32_t cnt, F&& f) {
+  LaneDec d;
+  d.init(g, u, pos);
+  for (uint32_t i = 0; i < cnt; ++i) {
+    int32_t v, w;
+    d.next(v, w);
+    f(i, v, w);
+  }
+}
+
 // Serial decode of a short (unchunked) neighbourhood by one lane; calls
-// f(i, v, w) for i = 0..deg-1 in order.
+// f(i, v, w) for i = 0..deg-1 (the interval neighbours of an interval-coded
+// record first).
 template <typename F>
 __device__ __forceinline__ void lane_decode(const GraphView& g, int32_t u, uint32_t deg, F&& f) {
   uint64_t pos;
   (void)read_header(g, u, pos);
-  int32_t v = 0, w = 0;
-  for (uint32_t i = 0; i < deg; ++i) {
-    uint64_t code = varint_read(g.bytes, pos);
-    v = (i == 0) ? u + (int32_t)unzigzag(code) : v + (int32_t)code;
-    if (g.weighted) {
-      w = (i == 0 ? 0 : w) + (int32_t)unzigzag(varint_read(g.bytes, pos));
-    } else {
-      w = 1;
-    }
-    f(i, v, w);
-  }
+  lane_decode_chunk(g, u, pos, deg, f);
 }
 
 }  // namespace lp

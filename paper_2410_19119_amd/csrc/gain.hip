@@ -83,7 +83,16 @@ __device__ __forceinline__ V gt_get(const GtView<V>& t, int32_t u, int32_t b) {
 // 1000-edge pieces above the chunking threshold.
 template <typename F>
 __device__ void wave_visit(const GraphView& g, int32_t u, uint32_t deg, int32_t c, DecodeSmem<kWave>& dsm, F&& f) {
-  if (g.offs) {
+  if (g.offs && g.intervals) {
+    // interval-coded: every lane decodes whole chunks on its own
+    const Nbh h = nbh_locate(g, u, deg);
+    const uint32_t c0 = c < 0 ? 0u : (uint32_t)c, c1 = c < 0 ? h.nchunks : (uint32_t)c + 1;
+    for (uint32_t ch = c0 + (uint32_t)lane_id(); ch < c1; ch += kWave) {
+      const uint32_t first = ch * LP_CHUNK_LEN;
+      const uint32_t cnt = h.nchunks > 1 ? min((uint32_t)LP_CHUNK_LEN, deg - first) : deg;
+      lane_decode_chunk(g, u, nbh_chunk_pos(g, h, ch), cnt, [&](uint32_t, int32_t v, int32_t w) { f(v, w); });
+    }
+  } else if (g.offs) {
     const Nbh h = nbh_locate(g, u, deg);
     const uint32_t c0 = c < 0 ? 0u : (uint32_t)c, c1 = c < 0 ? h.nchunks : (uint32_t)c + 1;
     for (uint32_t ch = c0; ch < c1; ++ch) {
@@ -166,11 +175,12 @@ __global__ __launch_bounds__(256) void k_gt_fill_lane(GraphView g, const int32_t
 // consecutive vertices, so that one counter atomic serves a whole workgroup.
 constexpr int kGtItemRun = 16;
 
-__device__ __forceinline__ uint32_t gt_items_of(uint32_t d) {
-  return d <= (uint32_t)kGtLaneMax ? 0u : d > (uint32_t)LP_CHUNK_THRESHOLD ? (d + LP_CHUNK_LEN - 1) / LP_CHUNK_LEN : 1u;
+__device__ __forceinline__ uint32_t gt_items_of(uint32_t d, uint32_t thr) {
+  return d <= (uint32_t)kGtLaneMax ? 0u : d > thr ? (d + LP_CHUNK_LEN - 1) / LP_CHUNK_LEN : 1u;
 }
 
-__global__ __launch_bounds__(256) void k_gt_items(const int32_t* deg, int32_t n, int2* items, uint32_t* nitems) {
+__global__ __launch_bounds__(256) void k_gt_items(const int32_t* deg, int32_t n, uint32_t thr, int2* items,
+                                                  uint32_t* nitems) {
   __shared__ int32_t scan[256 / kWave + 1];
   __shared__ uint32_t base_sm;
   constexpr int64_t kSpan = 256 * kGtItemRun;
@@ -178,14 +188,14 @@ __global__ __launch_bounds__(256) void k_gt_items(const int32_t* deg, int32_t n,
     const int64_t u0 = b + (int64_t)threadIdx.x * kGtItemRun;
     const int64_t u1 = min((int64_t)n, u0 + kGtItemRun);
     uint32_t cnt = 0;
-    for (int64_t u = u0; u < u1; ++u) cnt += gt_items_of((uint32_t)deg[u]);
+    for (int64_t u = u0; u < u1; ++u) cnt += gt_items_of((uint32_t)deg[u], thr);
     int32_t tot;
     const uint32_t incl = (uint32_t)block_incl_scan_add<256, int32_t>((int32_t)cnt, scan, &tot);
     if (threadIdx.x == 255) base_sm = tot ? atomicAdd(nitems, (uint32_t)tot) : 0u;
     __syncthreads();
     uint32_t o = base_sm + incl - cnt;
     for (int64_t u = u0; u < u1; ++u) {
-      const uint32_t ni = gt_items_of((uint32_t)deg[u]);
+      const uint32_t ni = gt_items_of((uint32_t)deg[u], thr);
       for (uint32_t j = 0; j < ni; ++j) items[o++] = make_int2((int)u, ni > 1 ? (int)j : -1);
     }
     __syncthreads();
@@ -315,7 +325,7 @@ __device__ __forceinline__ void gt_move_edge(const GtView<V>& t, int32_t v, int3
 // Work items of an update: one per move of a vertex above kGtLaneMax, one per
 // chunk above the chunking threshold ({move index, chunk or -1}).
 __global__ __launch_bounds__(256) void k_gt_move_items(const int4* moves, const uint32_t* count, const int32_t* deg,
-                                                       int2* items, uint32_t* nitems) {
+                                                       uint32_t thr, int2* items, uint32_t* nitems) {
   const int64_t m = *count;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t b = (int64_t)blockIdx.x * blockDim.x; b < m; b += stride) {
@@ -323,7 +333,7 @@ __global__ __launch_bounds__(256) void k_gt_move_items(const int4* moves, const 
     uint32_t ni = 0;
     if (i < m) {
       const int4 mv = moves[i];
-      if (mv.x >= 0 && mv.y != mv.z) ni = gt_items_of((uint32_t)deg[mv.x]);  // short ones: k_gt_update_lane
+      if (mv.x >= 0 && mv.y != mv.z) ni = gt_items_of((uint32_t)deg[mv.x], thr);  // short ones: k_gt_update_lane
     }
     const uint32_t incl = wave_incl_scan_add(ni);
     uint32_t base = 0;
@@ -412,8 +422,8 @@ lp_status gt_fill(const GainTable& t, const int32_t* blocks, Scratch& sc) {
   uint32_t* nitems = t.cnt + 3;
   hipLaunchKernelGGL(k_gt_zero, dim3(1), dim3(64), 0, s, nitems, (int64_t)1);
   LP_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_gt_items, dim3(grid_for(n, 256 * kGtItemRun, 65536)), dim3(256), 0, s, t.deg, n, t.items,
-                     nitems);
+  hipLaunchKernelGGL(k_gt_items, dim3(grid_for(n, 256 * kGtItemRun, 65536)), dim3(256), 0, s, t.deg, n,
+                     chunk_threshold(g->intervals), t.items, nitems);
   LP_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_gt_fill_wave<V>, dim3(grid_for(n, 256 / kWave * 8, 16384)), dim3(256), 0, s, g->view(), t.deg,
                      blocks, t.items, nitems, v);
@@ -447,7 +457,7 @@ lp_status gt_update_t(const GainTable& t, const int4* moves, const uint32_t* cou
                      moves, count, v);
   LP_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_gt_move_items, dim3(grid_for(max_moves, 256, 16384)), dim3(256), 0, s, moves, count, t.deg,
-                     t.items, t.cnt + 3);
+                     chunk_threshold(t.g->intervals), t.items, t.cnt + 3);
   LP_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_gt_update<V>, dim3(grid_for(max_moves, kGtWaves, 8192)), dim3(256), 0, s, t.g->view(), t.deg,
                      moves, t.items, t.cnt + 3, v);

@@ -16,6 +16,7 @@ struct lp_graph {
   uint64_t two_m = 0;
   int32_t compressed = 0;
   int32_t weighted = 0;     // edge weights stored
+  int32_t intervals = 0;    // compressed with interval encoding
   int64_t total_vwgt = 0;   // sum of vertex weights
   int64_t max_wdeg = 0;     // max over u of the summed weight of u's edges
   int64_t max_deg = 0;
@@ -49,6 +50,7 @@ struct lp_graph {
     lp::GraphView v;
     v.n = n;
     v.weighted = weighted;
+    v.intervals = intervals;
     v.two_m = two_m;
     v.offs = offs;
     v.bytes = bytes;

@@ -20,6 +20,7 @@ constexpr int kWave = 64;
 struct GraphView {
   int32_t n;
   int32_t weighted;  // edge weights present
+  int32_t intervals; // compressed with interval encoding
   uint64_t two_m;
   const uint64_t* offs;
   const uint8_t* bytes;
@@ -28,6 +29,12 @@ struct GraphView {
   const int32_t* adjwgt;
   const int32_t* vwgt;
 };
+
+// Degree above which a compressed neighbourhood is split into chunks of
+// LP_CHUNK_LEN (Section III-A); interval-coded graphs split earlier.
+__host__ __device__ __forceinline__ uint32_t chunk_threshold(bool intervals) {
+  return intervals ? LP_ITV_CHUNK_THRESHOLD : LP_CHUNK_THRESHOLD;
+}
 
 __device__ __forceinline__ int64_t vweight(const GraphView& g, int32_t u) {
   return g.vwgt ? (int64_t)g.vwgt[u] : 1;

@@ -123,7 +123,10 @@ void* cache_alloc(size_t bytes, hipStream_t s) {
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) tot = 0;
     clear_error();
-    c->limit = std::max<size_t>(tot / 4, (size_t)2 << 30);
+    // keep up to half of the device: the working set of one call (a
+    // contraction of 4e9 edges takes two record buffers of 33 GB) must stay
+    // cached between calls, or every call pays for mapping it again
+    c->limit = std::max<size_t>(tot / 2, (size_t)2 << 30);
   }
   for (auto it = c->free_.lower_bound(need); it != c->free_.end() && it->first <= need + need / 4; ++it) {
     CBlock& b = it->second;
