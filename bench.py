@@ -529,6 +529,8 @@ def main() -> int:
     ap.add_argument("--coarsen-subrounds", type=int, default=1, help="sub-rounds per LP round in the coarsening")
     ap.add_argument("--coarsen-scale", type=int, default=26)
     ap.add_argument("--no-checks", action="store_true")
+    ap.add_argument("--knobs", default=";hub_part=1024;hub_part=512;hub_part=4096;overlap=1",
+                    help="semicolon-separated knob settings of the knobs form (k=v,k=v)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path exists as a "
@@ -556,6 +558,34 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"workload": "copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
                           "copies": 3}))
+        return 0
+    if args.workload == "knobs":
+        # result-invariant knobs on the headline workload: phase times per setting
+        import torch
+        g, cap, desc = workload("rmat26")
+        G = lp.lp_compress(g.n, g.xadj.view(np.int64), g.adjncy)
+        del g
+        lab0 = None
+        res = {}
+        for spec in args.knobs.split(";"):
+            cfg = dict(timing=1)
+            for kv in filter(None, spec.split(",")):
+                k, v = kv.split("=")
+                cfg[k] = int(v)
+            lab, _ = lp.lp_cluster(G, cap, args.rounds, 1, config=cfg, stats=True)
+            rms, ph = [], {}
+            for _ in range(2):
+                lab, st = lp.lp_cluster(G, cap, args.rounds, 1, config=cfg, stats=True)
+                rms += st.round_ms
+                for p_ in ("lane", "tile", "block", "hub", "accept"):
+                    ph[p_] = ph.get(p_, 0.0) + st.phase_ms[p_] / max(1, st.phase_launches[p_]) / 2
+            same = True if lab0 is None else bool(torch.equal(lab, lab0))
+            if lab0 is None:
+                lab0 = lab.clone()
+            res[spec or "default"] = {"round_ms_median": round(float(np.median(rms)), 3),
+                                      "phases_ms": {k: round(v, 3) for k, v in ph.items()}, "identical_labels": same}
+            log(f"[knobs] {spec or 'default'}: {res[spec or 'default']}")
+        print(json.dumps({"workload": desc, "knobs": res}))
         return 0
     if args.workload == "intervals":
         print(json.dumps({"metric": "LP-round time and bytes per edge with interval encoding", "unit": "ms",

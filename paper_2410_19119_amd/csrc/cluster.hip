@@ -267,6 +267,7 @@ struct TileCfg {
 using TileSmall = TileCfg<256, 2048, 80>;
 using TileLarge = TileCfg<512, 4096, 4>;
 constexpr int kTileSeg = 128;  // vertices walked by one thread of the tiling pass
+constexpr int kTileGrab = 8;   // tiles taken per atomic of a hand-out counter
 constexpr int kTileMaxDeg = 2048;  // largest degree of the small-tile bucket (default and bound of t_tile)
 
 template <int NT, int VT>
@@ -343,21 +344,49 @@ __device__ __forceinline__ int32_t tile_find(const uint32_t* base, int32_t cnt, 
 
 __device__ __forceinline__ uint32_t tile_slots(uint32_t d) { return d + (d >> 1) + 1; }
 
+// Adds w to slot q of the rating table.
 template <typename V>
-__device__ __forceinline__ void tile_insert(int32_t* keys, V* vals, uint32_t base, uint32_t size, int32_t c, V w) {
-  uint32_t h = __umulhi(slot_hash((uint32_t)c), size);
-  while (true) {
-    const int32_t old = atomicCAS(&keys[base + h], kEmpty, c);
-    if (old == kEmpty || old == c) break;
-    if (++h == size) h = 0;
-  }
+__device__ __forceinline__ void tile_add(V* vals, uint32_t q, V w) {
   if constexpr (sizeof(V) == 2) {
-    // 16-bit ratings (unit edge weights: a rating is at most the vertex's
-    // degree, below 2^16) share 32-bit words; no carry crosses a half
-    const uint32_t q = base + h;
     atomicAdd(reinterpret_cast<unsigned*>(vals) + (q >> 1), (unsigned)(uint16_t)w << ((q & 1u) * 16u));
   } else {
-    lds_add(&vals[base + h], w);
+    lds_add(&vals[q], w);
+  }
+}
+
+// A thread's ITEMS records (cluster nb[k], weight wt[k] of vertex vi[k]; vi[k]
+// < 0 skips) into the LDS table, the vertex's slots [base, base + size) given
+// by span(vi): every record's first slot is computed, then the first probes
+// of all records are issued together (independent LDS atomics), then the few
+// that collided walk on.
+template <int ITEMS, typename V, class Span>
+__device__ __forceinline__ void tile_insert_all(int32_t* keys, V* vals, const int32_t* vi, const int32_t* nb,
+                                                const int32_t* wt, Span span) {
+  uint32_t q[ITEMS], b[ITEMS], sz[ITEMS];
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    span(vi[k] < 0 ? 0 : vi[k], b[k], sz[k]);
+    q[k] = b[k] + __umulhi(slot_hash((uint32_t)nb[k]), sz[k]);
+  }
+  int32_t old[ITEMS];
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    old[k] = kEmpty;
+    if (vi[k] >= 0) old[k] = atomicCAS(&keys[q[k]], kEmpty, nb[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    if (vi[k] < 0) continue;
+    if (old[k] != kEmpty && old[k] != nb[k]) {
+      uint32_t h = q[k] - b[k];
+      while (true) {
+        if (++h == sz[k]) h = 0;
+        const int32_t o = atomicCAS(&keys[b[k] + h], kEmpty, nb[k]);
+        if (o == kEmpty || o == nb[k]) break;
+      }
+      q[k] = b[k] + h;
+    }
+    tile_add<V>(vals, q[k], (V)wt[k]);
   }
 }
 
@@ -515,12 +544,64 @@ __device__ __forceinline__ void itv_item(const ItvTable& t, const uint32_t* nums
 __device__ __forceinline__ uint32_t window_value(uint64_t w, uint64_t term, uint32_t b) {
   const uint64_t below = term & ((1ull << (8 * b)) - 1ull);
   const uint32_t s = below ? (uint32_t)((63 - __clzll(below)) >> 3) + 1u : (b >= 4 ? b - 4 : 0u);
-  uint32_t v = 0;
+  const uint32_t len = min(b - s + 1u, 5u);  // a longer run (a malformed stream) reads five bytes
+  uint32_t y = (uint32_t)(w >> (8 * s));
+  if (len < 4) y &= (1u << (8 * len)) - 1u;
+  // the 7-bit groups of the first four bytes, then the fifth's low bits
+  uint32_t v = (y & 0x7Fu) | ((y >> 1) & 0x3F80u) | ((y >> 2) & 0x1FC000u) | ((y >> 3) & 0xFE00000u);
+  if (len == 5) v |= (uint32_t)((w >> (8 * (s + 4))) & 0x7Full) << 28;
+  return v;
+}
+
+// Step 2 of a staged code stream (Dt dwords in A32): the numbers in stream
+// order, one thread per run of consecutive dwords. With POS (gap-only
+// format) only the byte at which every number ends is stored, and
+// number_at reads a number's value when it is needed; otherwise the values
+// themselves (interval-coded streams, whose pairs the interval table reads).
+template <int NT, bool POS>
+__device__ __forceinline__ void stage_numbers(const uint32_t* A32, uint32_t Dt, uint32_t* nums, int32_t* scan_sm) {
+  const uint32_t Q = (Dt + NT - 1) / NT;
+  const uint32_t j0 = min(Dt, threadIdx.x * Q), j1 = min(Dt, j0 + Q);
+  int32_t cnt = 0;
+  for (uint32_t j = j0; j < j1; ++j) cnt += __popc(~A32[j] & 0x80808080u);
+  int32_t tot;
+  uint32_t idx = (uint32_t)(block_incl_scan_add<NT, int32_t>(cnt, scan_sm, &tot) - cnt);
+  uint32_t prev = j0 > 0 ? A32[j0 - 1] : 0u;
+  for (uint32_t j = j0; j < j1; ++j) {
+    const uint32_t cur = A32[j];
+    if constexpr (POS) {
+      const uint32_t t = ~cur & 0x80808080u;
 #pragma unroll
-  for (uint32_t k = 0; k < 5; ++k) {
-    const uint32_t p = s + k;
-    if (p <= b) v |= (uint32_t)((w >> (8 * p)) & 0x7Full) << (7 * k);
+      for (uint32_t b = 0; b < 4; ++b)
+        if ((t >> (8 * b + 7)) & 1u) nums[idx++] = 4u * j + b;
+    } else {
+      const uint64_t w = ((uint64_t)cur << 32) | prev;
+      const uint64_t term = ~w & 0x8080808080808080ull;
+      uint32_t tc = (uint32_t)(term >> 32);
+      while (tc) {
+        const uint32_t b = 4u + (((uint32_t)__ffs(tc) - 1u) >> 3);
+        tc &= tc - 1u;
+        nums[idx++] = window_value(w, term, b);
+      }
+    }
+    prev = cur;
   }
+  __syncthreads();
+}
+
+// Value of number k of a staged stream whose end bytes stage_numbers<POS>
+// stored in ends[]: it starts after number k - 1 ends and runs to the first
+// byte with the top bit clear (at most five bytes: if none of the first four
+// ends it, the fifth does).
+__device__ __forceinline__ uint32_t number_at(const uint32_t* A32, const uint32_t* ends, uint32_t k) {
+  const uint32_t s = k ? ends[k - 1] + 1u : 0u;
+  const uint32_t lo = A32[s >> 2], hi = A32[(s >> 2) + 1];
+  uint32_t y = __builtin_amdgcn_alignbyte(hi, lo, s & 3u);  // bytes s .. s + 3
+  const uint32_t t = ~y & 0x80808080u;
+  y &= t ^ (t - 1u);  // up to the first byte that ends the number
+  uint32_t v = (y & 0x7Fu) | (__builtin_amdgcn_ubfe(y, 8, 7) << 7) | (__builtin_amdgcn_ubfe(y, 16, 7) << 14) |
+               (__builtin_amdgcn_ubfe(y, 24, 7) << 21);
+  if (t == 0u) v |= ((hi >> (8u * (s & 3u))) & 0x7Fu) << 28;
   return v;
 }
 
@@ -620,23 +701,30 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
   const int sgi = tid / SG;           // selection group of this thread
   const int sl = tid % SG;            // lane within the selection group
 
-  // Tiles are handed out at run time: the workgroups of one XCD first take
-  // tiles of their own eighth of the list (one counter per eighth), then help
-  // with the other eighths, so that workgroups that become resident late (the
-  // kernel shares the device with the other rating paths) take fewer tiles.
+  // Tiles are handed out at run time, kTileGrab at a time (a device-wide
+  // atomic costs about as much as the setup of a tile, and all workgroups
+  // contend for few counters): the workgroups of one XCD first take tiles of
+  // their own eighth of the list (one counter per eighth), then help with the
+  // other eighths, so that workgroups that become resident late (the kernel
+  // may share the device with the other rating paths) take fewer tiles.
   const uint32_t T_ = *ntiles_p;
   const uint32_t xcd = blockIdx.x & 7u;
   for (uint32_t k8 = 0; k8 < 8; ++k8) {
     const uint32_t xr = (xcd + k8) & 7u;
     const uint32_t lo = (uint32_t)(((uint64_t)T_ * xr) >> 3), hi = (uint32_t)(((uint64_t)T_ * (xr + 1)) >> 3);
+    uint32_t t = hi, tend = hi;
     while (true) {
-      if (tid == 0) sh.next = lo + atomicAdd(&ctr[xr], 1u);
-      __syncthreads();
-      const uint32_t t = sh.next;
-      __syncthreads();
-      if (t >= hi) break;
-      const int32_t t0 = tiles[t];
-      const int32_t nv = tiles[t + 1] - t0;
+      if (t >= tend) {
+        if (tid == 0) sh.next = lo + atomicAdd(&ctr[xr], (uint32_t)kTileGrab);
+        __syncthreads();
+        t = sh.next;
+        __syncthreads();
+        if (t >= hi) break;
+        tend = min(hi, t + (uint32_t)kTileGrab);
+      }
+      const uint32_t tcur = t++;
+      const int32_t t0 = tiles[tcur];
+      const int32_t nv = tiles[tcur + 1] - t0;
       // 0. vertex descriptors and bases
       uint32_t d = 0, ndw = 0, nnum = 0, nsl = 0;
       if (tid < nv) {
@@ -687,59 +775,49 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
       const uint32_t Et = sh.ebase[nv];
       const uint32_t St = sh.tbase[nv];
       if constexpr (COMP) {
-        // 1. stage the code bytes (four independent loads in flight per thread)
+        // 1. stage the code bytes: four consecutive dwords per thread (one
+        // search for their vertex, four independent loads in flight)
         const uint32_t Dt = sh.dwbase[nv];
-        for (uint32_t j0 = tid; j0 < Dt; j0 += 4 * NT) {
+        for (uint32_t jb = 4 * tid; jb < Dt; jb += 4 * NT) {
           uint32_t w[4], off[4];
           int32_t vi4[4];
+          int32_t i = tile_find(sh.dwbase, nv, jb);
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
-            const uint32_t j = j0 + (uint32_t)k * NT;
+            const uint32_t j = jb + (uint32_t)k;
             vi4[k] = -1;
             w[k] = 0;
             off[k] = 0;
             if (j < Dt) {
-              const int32_t i = tile_find(sh.dwbase, nv, j);
+              while (j >= sh.dwbase[i + 1]) ++i;
               vi4[k] = i;
               off[k] = 4u * (j - sh.dwbase[i]);
               w[k] = *(const uint32_t*)(x.g.bytes + (sh.pos[i] & ~3ull) + off[k]);
             }
           }
+          uint4 o;
+          uint32_t* ov = (uint32_t*)&o;
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
+            ov[k] = 0;
             if (vi4[k] < 0) continue;
-            const int32_t i = vi4[k];
-            const uint32_t b0 = (uint32_t)(sh.pos[i] & 3u), b1 = b0 + sh.len[i];
-            uint32_t v = w[k];
+            const int32_t i2 = vi4[k];
+            // bytes [b0, b1) of the vertex's dwords are its codes
+            const int32_t b0 = (int32_t)(sh.pos[i2] & 3u), b1 = b0 + (int32_t)sh.len[i2];
+            const int32_t lo = min(max(b0 - (int32_t)off[k], 0), 4), hi = min(max(b1 - (int32_t)off[k], 0), 4);
+            ov[k] = w[k] & (uint32_t)(((1ull << (8 * hi)) - 1ull) ^ ((1ull << (8 * lo)) - 1ull));
+          }
+          if (jb + 4 <= Dt) {
+            *(uint4*)&A32[jb] = o;
+          } else {
 #pragma unroll
-            for (uint32_t b = 0; b < 4; ++b)
-              if (off[k] + b < b0 || off[k] + b >= b1) v &= ~(0xFFu << (8 * b));
-            A32[j0 + (uint32_t)k * NT] = v;
+            for (int k = 0; k < 4; ++k)
+              if (jb + k < Dt) A32[jb + k] = ov[k];
           }
         }
         __syncthreads();
-        // 2. numbers in stream order
-        {
-          const uint32_t Q = (Dt + NT - 1) / NT;
-          const uint32_t j0 = min(Dt, tid * Q), j1 = min(Dt, j0 + Q);
-          int32_t cnt = 0;
-          for (uint32_t j = j0; j < j1; ++j) cnt += __popc(~A32[j] & 0x80808080u);
-          int32_t tot;
-          uint32_t idx = (uint32_t)(block_incl_scan_add<NT, int32_t>(cnt, sh.scan, &tot) - cnt);
-          uint32_t prev = j0 > 0 ? A32[j0 - 1] : 0u;
-          for (uint32_t j = j0; j < j1; ++j) {
-            const uint32_t cur = A32[j];
-            const uint64_t w = ((uint64_t)cur << 32) | prev;
-            const uint64_t term = ~w & 0x8080808080808080ull;
-            uint32_t tc = (uint32_t)(term >> 32);
-            while (tc) {
-              const uint32_t b = 4u + (((uint32_t)__ffs(tc) - 1u) >> 3);
-              tc &= tc - 1u;
-              nums[idx++] = window_value(w, term, b);
-            }
-            prev = cur;
-          }
-        }
+        // 2. numbers in stream order (gap-only: where each one ends)
+        stage_numbers<NT, !ITV>(A32, Dt, nums, sh.scan);
         __syncthreads();
       }
       // 3. neighbour IDs, weights and labels of this thread's slice
@@ -815,10 +893,10 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
             const uint32_t loc = e - sh.ebase[i];
             if constexpr (COMP) {
               const uint32_t ci = sh.rstart[i] + per * loc;
-              const uint32_t code = nums[ci];
+              const uint32_t code = number_at(A32, nums, ci);
               const bool head = loc == 0;
               const int32_t dv = head ? sh.u[i] + unzigzag32(code) : (int32_t)code;
-              const int32_t dw = weighted ? unzigzag32(nums[ci + 1]) : 0;
+              const int32_t dw = weighted ? unzigzag32(number_at(A32, nums, ci + 1)) : 0;
               if (head) {
                 any_head = true;
                 s = dv;
@@ -885,12 +963,10 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
       for (uint32_t q = tid; q < St; q += NT) vals[q] = 0;
       __syncthreads();
       // 4. ratings
-#pragma unroll
-      for (int k = 0; k < ITEMS; ++k) {
-        if (vi[k] < 0) continue;
-        const int32_t i = vi[k];
-        tile_insert<V>(keys, vals, sh.tbase[i], sh.tbase[i + 1] - sh.tbase[i], nb[k], (V)wt[k]);
-      }
+      tile_insert_all<ITEMS, V>(keys, vals, vi, nb, wt, [&](int32_t i, uint32_t& b, uint32_t& sz) {
+        b = sh.tbase[i];
+        sz = sh.tbase[i + 1] - b;
+      });
       __syncthreads();
       // 5. selection: one walk over the slots of each vertex; tiles of small
       // vertices use 16-lane groups (four vertices per wavefront at a time)
@@ -973,6 +1049,7 @@ constexpr int kPieceThreads = 512;
 constexpr int kPieceItems = (kHubPiece + kPieceThreads - 1) / kPieceThreads;
 constexpr int kPieceSlots = kHubPiece + kHubPiece / 2 + 16;
 constexpr int kMaxParts = 1024;
+constexpr int kPieceGrab = 4;  // pieces taken per atomic of the hand-out counter
 constexpr int kDefaultHubPart = 2048;
 constexpr int kMaxSubrounds = 64;  // target partial records per (hub, partition) task
 constexpr uint32_t kStreamZig = 0x80000000u;  // first code is zigzag(v - base_v)
@@ -996,6 +1073,17 @@ __device__ __forceinline__ uint32_t count_varints(const uint8_t* b, uint64_t p0,
   return c;
 }
 
+// A (hub, partition) reduction task, everything H2 needs in one load.
+struct HubTask {
+  int32_t u;        // hub vertex
+  int32_t nparts;   // P_h
+  int32_t nseg;     // pieces of the hub
+  int32_t part;     // the partition
+  uint64_t rec0;    // first record of the hub (piece j at + j * kHubPiece)
+  uint64_t poff0;   // piece j's P_h + 1 partition offsets at + j * (P_h + 1)
+};
+static_assert(sizeof(HubTask) == 32, "HubTask is eight words");
+
 struct HubMeta {
   const int32_t* u;          // hub vertex
   const int32_t* deg;
@@ -1006,7 +1094,7 @@ struct HubMeta {
   const uint64_t* poff_base; // piece j's P_h + 1 partition offsets at + j * (P_h + 1)
   const int32_t* task_base;  // first (hub, partition) task
   const int2* pieces;        // (hub, piece within the hub)
-  const int2* tasks;         // (hub, partition)
+  const HubTask* tdesc;      // (hub, partition) tasks
   HubStream* streams;        // kHubStreams per piece
   int32_t* rec_c;            // records: cluster (packed: cluster << rbits | partial rating)
   void* rec_r;               // records: partial rating (int32 or int64); unused when packed
@@ -1016,6 +1104,7 @@ struct HubMeta {
   // most one record per neighbour)
   int32_t packed;
   uint32_t rbits;
+  uint32_t tmax;  // LDS table entries of a reduction task (power of two)
   uint32_t* poff;
   int64_t* res_r;            // per task
   uint64_t* res_key;
@@ -1120,13 +1209,18 @@ __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta
   uint32_t* nums = (uint32_t*)(A + L.nums_off);
   PieceShared& sh = *(PieceShared*)(A + L.abytes);
   V* rec_r = (V*)hm.rec_r;
-  // pieces are handed out at run time (one counter)
+  // pieces are handed out at run time, kPieceGrab at a time (one counter)
+  uint32_t pnext = 0, pend = 0;
   while (true) {
-    if (tid == 0) sh.next = atomicAdd(ctr, 1u);
-    __syncthreads();
-    const int64_t pc = sh.next;
-    __syncthreads();
-    if (pc >= npieces) break;
+    if (pnext >= pend) {
+      if (tid == 0) sh.next = atomicAdd(ctr, (uint32_t)kPieceGrab);
+      __syncthreads();
+      pnext = sh.next;
+      __syncthreads();
+      if (pnext >= (uint32_t)npieces) break;
+      pend = min((uint32_t)npieces, pnext + (uint32_t)kPieceGrab);
+    }
+    const int64_t pc = pnext++;
     const int2 pj = hm.pieces[pc];
     const int h = pj.x;
     const uint32_t P = (uint32_t)hm.nparts[h];
@@ -1164,57 +1258,47 @@ __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta
     const uint32_t Et = sh.ebase[NS];
     if constexpr (COMP) {
       const uint32_t Dt = sh.dwbase[NS];
-      for (uint32_t j0 = tid; j0 < Dt; j0 += 4 * NT) {
+      // four consecutive dwords per thread, four independent loads in flight
+      for (uint32_t jb = 4 * tid; jb < Dt; jb += 4 * NT) {
         uint32_t w[4], off[4];
         int32_t si[4];
+        int32_t s = 0;
+        while (jb >= sh.dwbase[s + 1]) ++s;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          const uint32_t j = j0 + (uint32_t)k * NT;
+          const uint32_t j = jb + (uint32_t)k;
           si[k] = -1;
           w[k] = 0;
           off[k] = 0;
           if (j < Dt) {
-            int32_t s = 0;
             while (j >= sh.dwbase[s + 1]) ++s;
             si[k] = s;
             off[k] = 4u * (j - sh.dwbase[s]);
             w[k] = *(const uint32_t*)(x.g.bytes + (sh.pos[s] & ~3ull) + off[k]);
           }
         }
+        uint4 o;
+        uint32_t* ov = (uint32_t*)&o;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
+          ov[k] = 0;
           if (si[k] < 0) continue;
-          const int32_t s = si[k];
-          const uint32_t b0 = (uint32_t)(sh.pos[s] & 3u), b1 = b0 + sh.len[s];
-          uint32_t v = w[k];
+          const int32_t s2 = si[k];
+          // bytes [b0, b1) of the stream's dwords are its codes
+          const int32_t b0 = (int32_t)(sh.pos[s2] & 3u), b1 = b0 + (int32_t)sh.len[s2];
+          const int32_t lo = min(max(b0 - (int32_t)off[k], 0), 4), hi = min(max(b1 - (int32_t)off[k], 0), 4);
+          ov[k] = w[k] & (uint32_t)(((1ull << (8 * hi)) - 1ull) ^ ((1ull << (8 * lo)) - 1ull));
+        }
+        if (jb + 4 <= Dt) {
+          *(uint4*)&A32[jb] = o;
+        } else {
 #pragma unroll
-          for (uint32_t b = 0; b < 4; ++b)
-            if (off[k] + b < b0 || off[k] + b >= b1) v &= ~(0xFFu << (8 * b));
-          A32[j0 + (uint32_t)k * NT] = v;
+          for (int k = 0; k < 4; ++k)
+            if (jb + k < Dt) A32[jb + k] = ov[k];
         }
       }
       __syncthreads();
-      {
-        const uint32_t Q = (Dt + NT - 1) / NT;
-        const uint32_t j0 = min(Dt, tid * Q), j1 = min(Dt, j0 + Q);
-        int32_t cnt = 0;
-        for (uint32_t j = j0; j < j1; ++j) cnt += __popc(~A32[j] & 0x80808080u);
-        int32_t tot;
-        uint32_t idx = (uint32_t)(block_incl_scan_add<NT, int32_t>(cnt, sh.scan, &tot) - cnt);
-        uint32_t prev = j0 > 0 ? A32[j0 - 1] : 0u;
-        for (uint32_t j = j0; j < j1; ++j) {
-          const uint32_t cur = A32[j];
-          const uint64_t w = ((uint64_t)cur << 32) | prev;
-          const uint64_t term = ~w & 0x8080808080808080ull;
-          uint32_t tc = (uint32_t)(term >> 32);
-          while (tc) {
-            const uint32_t b = 4u + (((uint32_t)__ffs(tc) - 1u) >> 3);
-            tc &= tc - 1u;
-            nums[idx++] = window_value(w, term, b);
-          }
-          prev = cur;
-        }
-      }
+      stage_numbers<NT, !ITV>(A32, Dt, nums, sh.scan);
       __syncthreads();
     }
     // neighbour IDs, weights and labels of this thread's slice
@@ -1292,11 +1376,11 @@ __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta
           const uint32_t loc = e - sh.ebase[s];
           if constexpr (COMP) {
             const uint32_t ci = sh.rstart[s] + per * loc;
-            const uint32_t code = nums[ci];
+            const uint32_t code = number_at(A32, nums, ci);
             const bool head = loc == 0;
             const int32_t dv =
                 head ? sh.base_v[s] + (sh.zig[s] ? unzigzag32(code) : (int32_t)code) : (int32_t)code;
-            const int32_t dw = weighted ? (head ? sh.base_w[s] : 0) + unzigzag32(nums[ci + 1]) : 0;
+            const int32_t dw = weighted ? (head ? sh.base_w[s] : 0) + unzigzag32(number_at(A32, nums, ci + 1)) : 0;
             if (head) {
               any_head = true;
               a = dv;
@@ -1360,9 +1444,10 @@ __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta
     for (uint32_t q = tid; q < S; q += NT) keys[q] = kEmpty;
     for (uint32_t q = tid; q < S; q += NT) vals[q] = 0;
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < ITEMS; ++k)
-      if (vi[k] >= 0) tile_insert<V>(keys, vals, 0, S, nb[k], (V)wt[k]);
+    tile_insert_all<ITEMS, V>(keys, vals, vi, nb, wt, [&](int32_t, uint32_t& b, uint32_t& sz) {
+      b = 0;
+      sz = S;
+    });
     __syncthreads();
     // distinct clusters grouped by partition
     const uint32_t rmax = hm.packed ? (1u << hm.rbits) - 1u : 0u;
@@ -1411,8 +1496,19 @@ __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta
   }
 }
 
-constexpr uint32_t kHubTable = 4096;  // max LDS entries of a (hub, partition) task
-constexpr int kRedItems = 8;          // records loaded per thread before inserting
+constexpr uint32_t kHubTableMin = 1024, kHubTableMax = 16384;
+
+// LDS entries of a (hub, partition) task's table: a power of two that holds
+// hub_part records at a load of at most 5/8 (a partition with more records
+// is summed in label-range sub-passes).
+inline uint32_t hub_table(int32_t hub_part, bool wide) {
+  const uint32_t cap = wide ? kHubTableMax / 2 : kHubTableMax;  // 64-bit ratings: 12 bytes per entry
+  uint32_t t = kHubTableMin;
+  while ((uint64_t)t * 5u < (uint64_t)hub_part * 8u && t < cap) t <<= 1;
+  return t;
+}
+constexpr int kRedItems = 8;                          // records per thread and window
+constexpr int kRedWindow = kHubThreads * kRedItems;  // records placed by one owner map
 
 struct HubReduceSmem {
   Cand best[kHubThreads / kWave];
@@ -1420,52 +1516,91 @@ struct HubReduceSmem {
   int32_t scan[kHubThreads / kWave];
   uint32_t distinct;
   uint32_t overflow;
-  uint32_t ra[kHubThreads];
-  int32_t pre[kHubThreads + 1];
+  alignas(16) uint64_t base[kHubThreads];  // per piece of a batch: its first record's address minus its first position
+  alignas(16) uint16_t own[kRedWindow];    // owner map of a window: 1 + the batch's piece that holds each position
 };
 
-// H2: one workgroup per (hub, partition). The table is sized to the
-// partition's record count (a power of two >= 2 * count, at most kHubTable);
-// the partition's records of all the hub's pieces are walked as one flat
-// range per batch of kHubThreads pieces and summed in LDS. A partition with
-// more records than half the table is split into label-range sub-passes
-// (doubled again if a sub-pass still sees too many distinct clusters).
+// Block-wide inclusive max-scan of one non-negative int per thread, seeded
+// with `carry`; *total = the maximum over the block and the carry.
+template <int NT>
+__device__ __forceinline__ int32_t block_incl_scan_max(int32_t x, int32_t carry, int32_t* sm, int32_t* total) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int32_t y = __shfl_up(x, d, kWave);
+    if (lane_id() >= d) x = y > x ? y : x;
+  }
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane_id() == kWave - 1) sm[w] = x;
+  __syncthreads();
+  int32_t off = carry, tot = carry;
+#pragma unroll
+  for (int i = 0; i < NT / kWave; ++i) {
+    const int32_t v = sm[i];
+    if (i < w) off = v > off ? v : off;
+    tot = v > tot ? v : tot;
+  }
+  *total = tot;
+  return x > off ? x : off;
+}
+
+// H2: (hub, partition) tasks, a fixed stride of them per workgroup; the
+// next task's descriptor is loaded while the current one runs. The table
+// holds the partition's record count at a load of at most 5/8 (at most
+// hm.tmax entries; more records are summed in label-range sub-passes,
+// doubled again if a sub-pass still sees too many distinct clusters). The
+// partition's records lie in one run per piece; a batch of kHubThreads
+// pieces is walked as one flat range, window by window, each record finding
+// its piece through an owner map (piece starts scattered into LDS, then a
+// block-wide max-scan).
 template <typename V>
 __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta hm, int32_t ntasks) {
   extern __shared__ __align__(16) uint8_t smem_raw[];
   constexpr int NT = kHubThreads;
   int32_t* keys = (int32_t*)smem_raw;
-  V* vals = (V*)(smem_raw + (size_t)kHubTable * 4);
-  HubReduceSmem& sm = *(HubReduceSmem*)(smem_raw + (size_t)kHubTable * (4 + sizeof(V)));
+  const uint32_t tmax = hm.tmax;
+  V* vals = (V*)(smem_raw + (size_t)tmax * 4);
+  HubReduceSmem& sm = *(HubReduceSmem*)(smem_raw + (size_t)tmax * (4 + sizeof(V)));
   const V* rec_r = (const V*)hm.rec_r;
   if (*x.done) return;
-  const int tid = threadIdx.x;
-  for (int64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
-    const int2 task = hm.tasks[t];
-    const int h = task.x;
-    const uint32_t p = (uint32_t)task.y;
-    const int32_t u = hm.u[h];
-    const uint32_t P = (uint32_t)hm.nparts[h];
-    const uint32_t nseg = (uint32_t)hm.npieces[h];
-    const uint64_t rb0 = hm.rec_base[h];
-    const uint32_t* po = hm.poff + hm.poff_base[h];
+  const int tid = threadIdx.x, lane = lane_id();
+  constexpr int kDescWords = (int)(sizeof(HubTask) / 4);
+  // lanes 0..7 of every wave hold the current task's descriptor words
+  const int64_t t0 = blockIdx.x;
+  uint32_t dw = (t0 < ntasks && lane < kDescWords) ? ((const uint32_t*)(hm.tdesc + t0))[lane] : 0u;
+  for (int64_t t = t0; t < ntasks; t += gridDim.x) {
+    const int32_t u = __builtin_amdgcn_readlane((int)dw, 0);
+    const uint32_t P = (uint32_t)__builtin_amdgcn_readlane((int)dw, 1);
+    const uint32_t nseg = (uint32_t)__builtin_amdgcn_readlane((int)dw, 2);
+    const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)dw, 3);
+    const uint64_t rb0 = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)dw, 4) |
+                         ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)dw, 5) << 32);
+    const uint64_t pb0 = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)dw, 6) |
+                         ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)dw, 7) << 32);
+    const int64_t tn = t + gridDim.x;
+    dw = (tn < ntasks && lane < kDescWords) ? ((const uint32_t*)(hm.tdesc + tn))[lane] : 0u;
+    const uint32_t* po = hm.poff + pb0;
     const int32_t own_c = x.C[u];
     const int64_t wu = vweight(x.g, u);
     const VParams vp = vparams(x, u);
-    // records of this partition
+    // records of this partition; the first batch's runs stay in registers
+    uint32_t ra0 = 0, c0 = 0;
     int64_t cnt = 0;
-    for (uint32_t k = tid; k < nseg; k += NT)
-      cnt += po[(uint64_t)k * (P + 1) + p + 1] - po[(uint64_t)k * (P + 1) + p];
-    cnt = block_reduce_add<NT, int64_t>(cnt, sm.red);
-    uint32_t logc = 6;
-    while ((1ull << logc) < 2ull * (uint64_t)cnt && logc < 40) ++logc;
-    uint32_t S = 1;  // label-range sub-passes
-    if ((1ull << logc) > kHubTable) {
-      S = (uint32_t)((1ull << logc) / kHubTable);
-      logc = ceil_log2(kHubTable);
+    for (uint32_t k = tid; k < nseg; k += NT) {
+      const uint32_t a = po[(uint64_t)k * (P + 1) + p], e = po[(uint64_t)k * (P + 1) + p + 1];
+      cnt += e - a;
+      if (k < (uint32_t)NT) {
+        ra0 = a;
+        c0 = e - a;
+      }
     }
-    const uint32_t tcap = 1u << logc, mask = tcap - 1, shift = 32 - logc;
-    const uint32_t limit = tcap / 2;
+    cnt = block_reduce_add<NT, int64_t>(cnt, sm.red);
+    uint32_t tcap = 64;
+    while (tcap < tmax && (uint64_t)tcap * 5u < (uint64_t)cnt * 8u) tcap <<= 1;
+    uint32_t S = 1;  // label-range sub-passes
+    while ((uint64_t)tcap * 5u * S < (uint64_t)cnt * 8u) S <<= 1;
+    const uint32_t logc = ceil_log2(tcap), mask = tcap - 1, shift = 32 - logc;
+    const uint32_t limit = tcap - tcap / 4;  // distinct clusters a sub-pass may hold
     Cand best;
     int64_t own;
     while (true) {
@@ -1473,9 +1608,14 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta 
       own = 0;
       bool over = false;
       for (uint32_t sp = 0; sp < S; ++sp) {
-        for (uint32_t q = tid; q < tcap; q += NT) {
-          keys[q] = kEmpty;
-          vals[q] = 0;
+        for (uint32_t q = 4 * tid; q < tcap; q += 4 * NT) *(int4*)&keys[q] = make_int4(kEmpty, kEmpty, kEmpty, kEmpty);
+        for (uint32_t q = 4 * tid; q < tcap; q += 4 * NT) {
+          if constexpr (sizeof(V) == 8) {
+            *(int4*)&vals[q] = make_int4(0, 0, 0, 0);
+            *(int4*)&vals[q + 2] = make_int4(0, 0, 0, 0);
+          } else {
+            *(int4*)&vals[q] = make_int4(0, 0, 0, 0);
+          }
         }
         if (tid == 0) {
           sm.distinct = 0;
@@ -1484,19 +1624,53 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta 
         __syncthreads();
         for (uint32_t kb = 0; kb < nseg; kb += NT) {
           const uint32_t k = kb + tid;
-          uint32_t ra = 0, c = 0;
-          if (k < nseg) {
-            ra = po[(uint64_t)k * (P + 1) + p];
-            c = po[(uint64_t)k * (P + 1) + p + 1] - ra;
+          uint32_t ra = ra0, c = c0;
+          if (kb > 0) {
+            ra = 0;
+            c = 0;
+            if (k < nseg) {
+              ra = po[(uint64_t)k * (P + 1) + p];
+              c = po[(uint64_t)k * (P + 1) + p + 1] - ra;
+            }
+          } else if (k >= nseg) {
+            c = 0;
           }
           int32_t total;
-          const int32_t incl = block_incl_scan_add<NT, int32_t>((int32_t)c, sm.scan, &total);
-          sm.ra[tid] = ra;
-          sm.pre[tid] = incl - (int32_t)c;
-          __syncthreads();
-          // the batch's records in rounds of kRedItems per thread: all loads of
-          // a round are issued before any insertion
-          for (int32_t j0 = 0; j0 < total; j0 += NT * kRedItems) {
+          const int32_t pre = block_incl_scan_add<NT, int32_t>((int32_t)c, sm.scan, &total) - (int32_t)c;
+          sm.base[tid] = rb0 + (uint64_t)k * kHubPiece + ra - (uint64_t)pre;
+          int32_t carry = 0;
+          for (int32_t j0 = 0; j0 < total; j0 += kRedWindow) {
+            // owner map of positions [j0, j0 + kRedWindow)
+            *(int4*)&sm.own[8 * tid] = make_int4(0, 0, 0, 0);
+            __syncthreads();
+            if (c > 0 && pre >= j0 && pre < j0 + kRedWindow) sm.own[pre - j0] = (uint16_t)(tid + 1);
+            __syncthreads();
+            int4 o4 = *(const int4*)&sm.own[8 * tid];
+            uint16_t ov[8];
+            __builtin_memcpy(ov, &o4, 16);
+            int32_t run = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) run = (int32_t)ov[q] > run ? (int32_t)ov[q] : run;
+            int32_t blockmax;
+            int32_t m = block_incl_scan_max<NT>(run, carry, sm.scan, &blockmax);
+            // exclusive prefix of this thread's eight positions
+            const int32_t prev = __shfl_up(m, 1, kWave);
+            int32_t ex = lane > 0 ? prev : 0;
+            if (lane == 0) {
+              const int w = tid / kWave;
+              ex = carry;
+              for (int i = 0; i < w; ++i) ex = sm.scan[i] > ex ? sm.scan[i] : ex;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              ex = (int32_t)ov[q] > ex ? (int32_t)ov[q] : ex;
+              ov[q] = (uint16_t)ex;
+            }
+            __builtin_memcpy(&o4, ov, 16);
+            __syncthreads();  // every wave has read the cross-wave maxima
+            *(int4*)&sm.own[8 * tid] = o4;
+            carry = blockmax;
+            __syncthreads();
             int32_t cc[kRedItems];
             V ww[kRedItems];
 #pragma unroll
@@ -1505,13 +1679,7 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta 
               cc[q] = kEmpty;
               ww[q] = 0;
               if (j < total) {
-                int32_t lo = 0, hi = NT;
-                while (hi - lo > 1) {
-                  const int32_t mid = (lo + hi) >> 1;
-                  if (sm.pre[mid] <= j) lo = mid;
-                  else hi = mid;
-                }
-                const uint64_t r = rb0 + (uint64_t)(kb + lo) * kHubPiece + sm.ra[lo] + (uint32_t)(j - sm.pre[lo]);
+                const uint64_t r = sm.base[sm.own[q * NT + tid] - 1] + (uint64_t)j;
                 if (hm.packed) {
                   const uint32_t pw = (uint32_t)hm.rec_c[r];
                   cc[q] = (int32_t)(pw >> hm.rbits);
@@ -1528,18 +1696,24 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta 
               if (c2 == kEmpty) continue;
               if (S > 1 && (uint32_t)(((uint64_t)(uint32_t)c2 * S) / (uint64_t)x.g.n) != sp) continue;
               const V w = ww[q];
-              uint32_t hs = slot_hash((uint32_t)c2) >> shift;
-              // one sub-pass: the table has at least twice as many slots as
-              // the partition has records, so it cannot fill and the distinct
-              // count (one contended LDS atomic per new cluster) is not needed
+              // buckets of four slots, read at once: a record finds its
+              // cluster or the bucket's first free slot in one LDS read
+              uint32_t b = (slot_hash((uint32_t)c2) >> shift) & ~3u;
+              // one sub-pass: the table has room for every record, so it
+              // cannot fill and the distinct count (one contended LDS atomic
+              // per new cluster) is not needed
               bool reserved = S == 1;
               while (true) {
-                const int32_t kk = keys[hs];
-                if (kk == c2) {
-                  lds_add(&vals[hs], w);
+                const int4 k4 = *(const int4*)&keys[b];
+                const uint32_t hit = (uint32_t)(k4.x == c2) | ((uint32_t)(k4.y == c2) << 1) |
+                                     ((uint32_t)(k4.z == c2) << 2) | ((uint32_t)(k4.w == c2) << 3);
+                if (hit) {
+                  lds_add(&vals[b + (uint32_t)__ffs(hit) - 1u], w);
                   break;
                 }
-                if (kk == kEmpty) {
+                const uint32_t fr = (uint32_t)(k4.x == kEmpty) | ((uint32_t)(k4.y == kEmpty) << 1) |
+                                    ((uint32_t)(k4.z == kEmpty) << 2) | ((uint32_t)(k4.w == kEmpty) << 3);
+                if (fr) {
                   if (!reserved) {
                     if (atomicAdd(&sm.distinct, 1u) >= limit) {
                       sm.overflow = 1;
@@ -1547,59 +1721,89 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta 
                     }
                     reserved = true;
                   }
-                  const int32_t old = atomicCAS(&keys[hs], kEmpty, c2);
+                  // slots fill in order, so the first free slot ends the
+                  // bucket's occupied prefix; if another record takes it
+                  // first, the bucket is read again
+                  const uint32_t sl = b + (uint32_t)__ffs(fr) - 1u;
+                  const int32_t old = atomicCAS(&keys[sl], kEmpty, c2);
                   if (old == kEmpty || old == c2) {
-                    lds_add(&vals[hs], w);
+                    lds_add(&vals[sl], w);
                     break;
                   }
+                  continue;
                 }
-                hs = (hs + 1) & mask;
+                b = (b + 4u) & mask;
               }
             }
+            __syncthreads();  // the owner map is rebuilt by the next window
           }
-          __syncthreads();
+          __syncthreads();  // sm.base is rewritten by the next batch
         }
         if (sm.overflow) {
           over = true;
           break;
         }
-        // the largest rating other than the own cluster's, then the smallest
-        // tie-break key among the slots that have it (keys only for those);
-        // one cluster-weight read; only if that cluster is full are the slots
-        // rescanned with the cap
-        int64_t rmax = -1;
-        for (uint32_t q = tid; q < tcap; q += NT) {
-          const int32_t c = keys[q];
-          if (c == kEmpty) continue;
-          const int64_t r = (int64_t)vals[q];
-          if (c == own_c) own = r;
-          else rmax = r > rmax ? r : rmax;
-        }
-        rmax = wave_reduce_max(rmax);
-        __syncthreads();
-        if (lane_id() == 0) sm.red[tid / kWave] = rmax;
-        __syncthreads();
-#pragma unroll
-        for (int w = 0; w < NT / kWave; ++w) rmax = sm.red[w] > rmax ? sm.red[w] : rmax;
+        // one pass over the table: the own cluster's rating and the best
+        // other cluster by (rating, smallest tie-break key), keys computed
+        // only for slots that reach the thread's best rating
         Cand lb = cand_none();
-        for (uint32_t q = tid; q < tcap; q += NT) {
-          const int32_t c = keys[q];
-          if (c == kEmpty || c == own_c) continue;
-          const int64_t r = (int64_t)vals[q];
-          if (r != rmax) continue;
-          const Cand cd{r, cluster_key(x, vp, c), c};
-          if (cand_better(cd, lb)) lb = cd;
+        for (uint32_t q = 4 * tid; q < tcap; q += 4 * NT) {
+          const int4 k4 = *(const int4*)&keys[q];
+          int64_t r4[4];
+          if constexpr (sizeof(V) == 8) {
+            const int4 a = *(const int4*)&vals[q], b = *(const int4*)&vals[q + 2];
+            r4[0] = ((int64_t)(uint32_t)a.y << 32) | (uint32_t)a.x;
+            r4[1] = ((int64_t)(uint32_t)a.w << 32) | (uint32_t)a.z;
+            r4[2] = ((int64_t)(uint32_t)b.y << 32) | (uint32_t)b.x;
+            r4[3] = ((int64_t)(uint32_t)b.w << 32) | (uint32_t)b.z;
+          } else {
+            const int4 a = *(const int4*)&vals[q];
+            r4[0] = a.x;
+            r4[1] = a.y;
+            r4[2] = a.z;
+            r4[3] = a.w;
+          }
+          const int32_t kc[4] = {k4.x, k4.y, k4.z, k4.w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int32_t c = kc[i];
+            if (c == kEmpty) continue;
+            if (c == own_c) {
+              own = r4[i];
+              continue;
+            }
+            if (r4[i] < lb.r) continue;
+            const Cand cd{r4[i], cluster_key(x, vp, c), c};
+            if (cand_better(cd, lb)) lb = cd;
+          }
         }
         lb = block_best<NT>(lb, sm.best);
         if (lb.c >= 0 && cand_better(lb, best)) {
           if (x.W[lb.c] + wu <= vp.cap) {
             best = lb;
           } else {
-            for (uint32_t q = tid; q < tcap; q += NT) {
-              const int32_t c = keys[q];
-              if (c == kEmpty || c == own_c) continue;
-              consider(x, vp, c, (int64_t)vals[q], wu, best);
+            // the best cluster is full: rescan with the cap, the cluster
+            // weights of four slots loaded at once
+            Cand fb = best;
+            for (uint32_t q = 4 * tid; q < tcap; q += 4 * NT) {
+              const int4 k4 = *(const int4*)&keys[q];
+              const int32_t kc[4] = {k4.x, k4.y, k4.z, k4.w};
+              int64_t r4[4], wc[4];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) r4[i] = (int64_t)vals[q + i];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const bool cand = kc[i] != kEmpty && kc[i] != own_c && r4[i] >= fb.r;
+                wc[i] = cand ? x.W[kc[i]] : INT64_MAX;
+              }
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                if (wc[i] == INT64_MAX || r4[i] < fb.r || wc[i] + wu > vp.cap) continue;
+                const Cand cd{r4[i], cluster_key(x, vp, kc[i]), kc[i]};
+                if (cand_better(cd, fb)) fb = cd;
+              }
             }
+            best = block_best<NT>(fb, sm.best);
           }
         }
         __syncthreads();
@@ -1608,7 +1812,6 @@ __global__ __launch_bounds__(kHubThreads) void k_hub_reduce(RoundCtx x, HubMeta 
       __syncthreads();
       S *= 2;
     }
-    best = block_best<NT>(best, sm.best);
     own = block_reduce_add<NT, int64_t>(own, sm.red);
     if (tid == 0) {
       hm.res_r[t] = best.r;
@@ -2215,17 +2418,16 @@ lp_status build_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t 
     LP_CHECK_HIP(hipMemcpyAsync(hu.data(), P.order + P.bstart[3], H * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     LP_CHECK_HIP(hipMemcpyAsync(hd.data(), hdeg_dev, H * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     LP_CHECK_HIP(hipStreamSynchronize(s));
-    int64_t maxd = 0;
-    for (int h = 0; h < H; ++h) maxd = std::max<int64_t>(maxd, hd[h]);
-    const int64_t part = std::max<int64_t>(hub_part, (maxd + kMaxParts - 1) / kMaxParts);
+    // partitions of about hub_part records (at most kMaxParts)
     std::vector<int32_t> np(H), npc(H), pcb(H), tb(H);
     std::vector<uint64_t> rbase(H), pbase(H);
-    std::vector<int2> pieces, tasks;
+    std::vector<int2> pieces;
+    std::vector<HubTask> tasks;
     uint64_t rsum = 0, psum = 0;
     int32_t ntasks = 0;
     for (int h = 0; h < H; ++h) {
       const int64_t d = hd[h];
-      np[h] = (int32_t)std::max<int64_t>(1, (d + part - 1) / part);
+      np[h] = (int32_t)std::min<int64_t>(kMaxParts, std::max<int64_t>(1, (d + hub_part - 1) / hub_part));
       npc[h] = (int32_t)((d + kHubPiece - 1) / kHubPiece);
       pcb[h] = (int32_t)pieces.size();
       rbase[h] = rsum;
@@ -2235,7 +2437,7 @@ lp_status build_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t 
       psum += (uint64_t)npc[h] * (np[h] + 1);
       ntasks += np[h];
       for (int k = 0; k < npc[h]; ++k) pieces.push_back(make_int2(h, k));
-      for (int p = 0; p < np[h]; ++p) tasks.push_back(make_int2(h, p));
+      for (int p = 0; p < np[h]; ++p) tasks.push_back(HubTask{hu[h], np[h], npc[h], p, rbase[h], pbase[h]});
     }
     P.npieces = (int32_t)pieces.size();
     P.ntasks = ntasks;
@@ -2251,7 +2453,7 @@ lp_status build_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t 
     uint64_t* d_rb = P.mem.alloc<uint64_t>(H);
     uint64_t* d_pb = P.mem.alloc<uint64_t>(H);
     int2* d_pieces = P.mem.alloc<int2>(P.npieces);
-    int2* d_tasks = P.mem.alloc<int2>(ntasks);
+    HubTask* d_tasks = P.mem.alloc<HubTask>(ntasks);
     hm.streams = P.mem.alloc<HubStream>((size_t)P.npieces * kHubStreams);
     if (P.mem.failed) return LP_ENOMEM;
     LP_CHECK_HIP(hipMemcpyAsync(d_u, hu.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
@@ -2263,7 +2465,7 @@ lp_status build_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t 
     LP_CHECK_HIP(hipMemcpyAsync(d_rb, rbase.data(), H * sizeof(uint64_t), hipMemcpyHostToDevice, s));
     LP_CHECK_HIP(hipMemcpyAsync(d_pb, pbase.data(), H * sizeof(uint64_t), hipMemcpyHostToDevice, s));
     LP_CHECK_HIP(hipMemcpyAsync(d_pieces, pieces.data(), P.npieces * sizeof(int2), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_tasks, tasks.data(), ntasks * sizeof(int2), hipMemcpyHostToDevice, s));
+    LP_CHECK_HIP(hipMemcpyAsync(d_tasks, tasks.data(), ntasks * sizeof(HubTask), hipMemcpyHostToDevice, s));
     hm.u = d_u;
     hm.deg = d_deg;
     hm.nparts = d_np;
@@ -2273,7 +2475,7 @@ lp_status build_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t 
     hm.poff_base = d_pb;
     hm.task_base = d_tb;
     hm.pieces = d_pieces;
-    hm.tasks = d_tasks;
+    hm.tdesc = d_tasks;
     hipLaunchKernelGGL(k_hub_streams, dim3(grid_for(H, 4, 4096)), dim3(256), 0, s, g->view(), hm, H);
     LP_CHECK_LAUNCH();
   }
@@ -2665,8 +2867,8 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
                                       : piece_layout_of<int32_t>(g->compressed, g->weighted);
   const size_t piece_lds = (size_t)piece_layout.abytes + sizeof(PieceShared);
   if (hmax > 0) {
-    if (wide) LP_CHECK(set_lds(k_hub_reduce<int64_t>, (size_t)kHubTable * 12 + sizeof(HubReduceSmem)));
-    else LP_CHECK(set_lds(k_hub_reduce<int32_t>, (size_t)kHubTable * 8 + sizeof(HubReduceSmem)));
+    if (wide) LP_CHECK(set_lds(k_hub_reduce<int64_t>, (size_t)hub_table(hub_part, true) * 12 + sizeof(HubReduceSmem)));
+    else LP_CHECK(set_lds(k_hub_reduce<int32_t>, (size_t)hub_table(hub_part, false) * 8 + sizeof(HubReduceSmem)));
   }
 
   for (int32_t r = 0; r < rounds; ++r) {
@@ -2685,6 +2887,7 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
       hm.rec_r = hbuf.rec_r;
       hm.packed = hbuf.packed;
       hm.rbits = hbuf.rbits;
+      hm.tmax = hub_table(hub_part, wide);
       hm.poff = hbuf.poff;
       hm.res_r = hbuf.res_r;
       hm.res_key = hbuf.res_key;
@@ -2714,12 +2917,13 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
         }
         if (H > 0) {
           hipStream_t hs = side[0];
+          // as many workgroups as the LDS lets every CU hold, each taking a fixed stride of tasks
+          const size_t red_lds = (size_t)hm.tmax * (wide ? 12 : 8) + sizeof(HubReduceSmem);
+          const unsigned red_grid = grid_for(ntasks, 1, 256u * (unsigned)std::max<size_t>(1, (160u << 10) / red_lds));
           if (wide)
-            hipLaunchKernelGGL(k_hub_reduce<int64_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads),
-                               (size_t)kHubTable * 12 + sizeof(HubReduceSmem), hs, x, hm, ntasks);
+            hipLaunchKernelGGL(k_hub_reduce<int64_t>, dim3(red_grid), dim3(kHubThreads), red_lds, hs, x, hm, ntasks);
           else
-            hipLaunchKernelGGL(k_hub_reduce<int32_t>, dim3(grid_for(ntasks, 1)), dim3(kHubThreads),
-                               (size_t)kHubTable * 8 + sizeof(HubReduceSmem), hs, x, hm, ntasks);
+            hipLaunchKernelGGL(k_hub_reduce<int32_t>, dim3(red_grid), dim3(kHubThreads), red_lds, hs, x, hm, ntasks);
           LP_CHECK_LAUNCH();
           hipLaunchKernelGGL(k_hub_combine, dim3(grid_for(H, 4)), dim3(256), 0, hs, x, hm, H);
           LP_CHECK_LAUNCH();

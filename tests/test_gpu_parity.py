@@ -319,3 +319,34 @@ def test_packed_hub_records_split_large_ratings(lp, oracle_mod, synth_mod, knobs
     assert np.array_equal(_np(lab), exp)
     assert st.proposals == ost.proposals and st.moves == ost.moves
     G.free()
+
+
+def _giant_hubs(synth_mod):
+    # hub 0 joined to every leaf (1.1M neighbours: more than 256 pieces, so
+    # its partitions are summed over several piece batches), hub 1 to every
+    # other leaf, and a ring over the leaves so that later rounds see mixed
+    # labels around the hubs
+    leaves = 1_100_000
+    n = leaves + 2
+    lv = np.arange(2, n, dtype=np.int64)
+    e = [np.stack([np.zeros(leaves, np.int64), lv], 1),
+         np.stack([np.ones(leaves // 2, np.int64), lv[::2]], 1),
+         np.stack([lv[:-1], lv[1:]], 1)]
+    return synth_mod.from_edges(n, np.concatenate(e))
+
+
+@pytest.fixture(scope="module")
+def giant_hubs(synth_mod):
+    return _giant_hubs(synth_mod)
+
+
+@pytest.mark.parametrize("knobs", [None,
+                                   dict(hub_part=256),    # 1024 partitions of ~1100 records: two label sub-passes
+                                   dict(hub_part=8192)])  # ~8200 records per partition: four owner-map windows
+@pytest.mark.parametrize("compressed", [True, False])
+def test_giant_hub_partitions(lp, oracle_mod, giant_hubs, knobs, compressed):
+    g = giant_hubs
+    G = _gpu_graph(lp, g, compressed)
+    exp, _ = oracle_mod.lp_cluster(g, 3000, 4, 21)
+    lab = lp.lp_cluster(G, 3000, 4, 21, config=knobs)
+    assert np.array_equal(_np(lab), exp)
