@@ -1045,9 +1045,26 @@ __global__ void k_tile_plan(VDesc vd, int32_t cnt, uint32_t emax, uint32_t vmax,
 // partitions of a hub.
 constexpr int kHubPiece = 4 * LP_CHUNK_LEN;
 constexpr int kHubStreams = 4;  // code streams per piece
-constexpr int kPieceThreads = 512;
-constexpr int kPieceItems = (kHubPiece + kPieceThreads - 1) / kPieceThreads;
-constexpr int kPieceSlots = kHubPiece + kHubPiece / 2 + 16;
+
+// Workgroup shape of a piece: threads, neighbours, code streams. Whole hubs
+// (kWhole) are rated by one workgroup alone, their table in LDS, without
+// partial records: up to sixteen of the format's chunks with 16-bit ratings,
+// twelve with 32-bit ones.
+template <int NT_, int E_, int NS_, bool WHOLE_>
+struct PieceCfg {
+  static constexpr int kThreads = NT_;
+  static constexpr int kEdges = E_;
+  static constexpr int kStreams = NS_;
+  static constexpr bool kWhole = WHOLE_;
+  static constexpr int kItems = (E_ + NT_ - 1) / NT_;
+  static constexpr int kSlots = E_ + E_ / 2 + 16;
+};
+using PieceHub = PieceCfg<512, kHubPiece, kHubStreams, false>;
+using PieceWhole16 = PieceCfg<1024, 16 * LP_CHUNK_LEN, 16, true>;
+using PieceWhole32 = PieceCfg<1024, 12 * LP_CHUNK_LEN, 12, true>;
+static_assert(PieceHub::kEdges == PieceHub::kStreams * LP_CHUNK_LEN && PieceWhole16::kEdges == PieceWhole16::kStreams * LP_CHUNK_LEN &&
+                  PieceWhole32::kEdges == PieceWhole32::kStreams * LP_CHUNK_LEN,
+              "a piece holds whole chunks, one stream each");
 constexpr int kMaxParts = 1024;
 constexpr int kPieceGrab = 4;  // pieces taken per atomic of the hand-out counter
 constexpr int kDefaultHubPart = 2048;
@@ -1115,7 +1132,9 @@ struct HubMeta {
 // Stream descriptors of every hub piece, once per call: one wavefront per
 // hub. Split records take their chunk table; unsplit records are decoded
 // once to record the decoder state at every piece boundary.
+template <class Cfg>
 __global__ __launch_bounds__(256) void k_hub_streams(GraphView g, HubMeta hm, int32_t nhubs) {
+  constexpr uint32_t NS = (uint32_t)Cfg::kStreams, PIECE = (uint32_t)Cfg::kEdges;
   __shared__ DecodeSmem<kWave> dsm[4];
   const int lane = lane_id();
   const int w = threadIdx.x / kWave;
@@ -1125,13 +1144,13 @@ __global__ __launch_bounds__(256) void k_hub_streams(GraphView g, HubMeta hm, in
     const int32_t u = hm.u[h];
     const uint32_t d = (uint32_t)hm.deg[h];
     const uint32_t npc = (uint32_t)hm.npieces[h];
-    HubStream* st = hm.streams + (uint64_t)hm.piece_base[h] * kHubStreams;
+    HubStream* st = hm.streams + (uint64_t)hm.piece_base[h] * NS;
     const HubStream none{0, 0, 0, 0, 0, 0, 0};
     if (g.offs) {
       const Nbh hb = nbh_locate(g, u, d);
       if (hb.nchunks > 1) {
-        // chunk k is stream k % 4 of piece k / 4; unused slots of the last piece are empty
-        for (uint32_t k = lane; k < npc * kHubStreams; k += kWave) {
+        // chunk k is stream k % NS of piece k / NS; unused slots of the last piece are empty
+        for (uint32_t k = lane; k < npc * NS; k += kWave) {
           if (k < hb.nchunks) {
             const uint64_t p0 = nbh_chunk_pos(g, hb, k);
             const uint64_t p1 = k + 1 < hb.nchunks ? nbh_chunk_pos(g, hb, k + 1) : g.offs[u + 1];
@@ -1143,60 +1162,65 @@ __global__ __launch_bounds__(256) void k_hub_streams(GraphView g, HubMeta hm, in
           }
         }
       } else if (g.intervals) {
-        // an unsplit interval-coded record has at most kHubPiece neighbours:
+        // an unsplit interval-coded record has at most PIECE neighbours:
         // one piece, one stream over the whole record
         const uint64_t p0 = hb.codes, p1 = g.offs[u + 1];
         const uint32_t nn = count_varints(g.bytes, p0, p1);  // every lane counts; lane 0 writes
-        for (uint32_t k = lane; k < npc * kHubStreams; k += kWave)
+        for (uint32_t k = lane; k < npc * NS; k += kWave)
           st[k] = k == 0 ? HubStream{p0, (uint32_t)(p1 - p0), d | kStreamZig, u, 0, nn, 0} : none;
       } else {
         uint64_t pos = hb.codes;
         int32_t pv = 0, pw = 0;
         for (uint32_t j = 0; j < npc; ++j) {
-          const uint32_t cnt = min((uint32_t)kHubPiece, d - j * kHubPiece);
+          const uint32_t cnt = min(PIECE, d - j * PIECE);
           const uint64_t p0 = pos;
           const int32_t bv = j == 0 ? u : pv, bw = j == 0 ? 0 : pw;
           (void)group_decode<kWave>(g.bytes, pos, u, cnt, g.weighted, j == 0, pv, pw, dsm[w],
                                     [](uint32_t, int32_t, int32_t) {});
-          if (lane < kHubStreams)
-            st[(uint64_t)j * kHubStreams + lane] =
+          if (lane < NS)
+            st[(uint64_t)j * NS + lane] =
                 lane == 0 ? HubStream{p0, (uint32_t)(pos - p0), cnt | (j == 0 ? kStreamZig : 0u), bv, bw, 0, 0}
                           : none;
         }
       }
     } else {
       const uint64_t e0 = g.xadj[u];
-      for (uint32_t k = lane; k < npc * kHubStreams; k += kWave) {
-        const uint32_t j = k / kHubStreams;
-        const uint32_t cnt = min((uint32_t)kHubPiece, d - j * kHubPiece);
-        st[k] = (k % kHubStreams == 0) ? HubStream{e0 + (uint64_t)j * kHubPiece, 0, cnt, 0, 0, 0, 0} : none;
+      for (uint32_t k = lane; k < npc * NS; k += kWave) {
+        const uint32_t j = k / NS;
+        const uint32_t cnt = min(PIECE, d - j * PIECE);
+        st[k] = (k % NS == 0) ? HubStream{e0 + (uint64_t)j * PIECE, 0, cnt, 0, 0, 0, 0} : none;
       }
     }
   }
 }
 
+template <class Cfg>
 struct PieceShared {
-  uint64_t pos[kHubStreams];
-  uint32_t len[kHubStreams];
-  int32_t base_v[kHubStreams];
-  int32_t base_w[kHubStreams];
-  uint32_t zig[kHubStreams];
-  uint32_t ebase[kHubStreams + 1];
-  uint32_t dwbase[kHubStreams + 1];
-  uint32_t rstart[kHubStreams + 1];
-  uint32_t hist[kMaxParts];
-  unsigned long long red_u[kPieceThreads / kWave];
-  int32_t scan[kPieceThreads / kWave];
-  int32_t scan2[kPieceThreads / kWave];
+  static constexpr int NS = Cfg::kStreams, NW = Cfg::kThreads / kWave;
+  uint64_t pos[NS];
+  uint32_t len[NS];
+  int32_t base_v[NS];
+  int32_t base_w[NS];
+  uint32_t zig[NS];
+  uint32_t ebase[NS + 1];
+  uint32_t dwbase[NS + 1];
+  uint32_t rstart[NS + 1];
+  uint32_t hist[Cfg::kWhole ? 1 : kMaxParts];
+  unsigned long long red_u[NW];
+  int32_t scan[NW];
+  int32_t scan2[NW];
+  Cand best[NW];
+  int64_t red[NW];
   uint32_t seg_flags;
   uint32_t next;  // piece handed to the workgroup
 };
 
-// H1: one workgroup per hub piece.
-template <typename V, bool COMP, int MODE = kModeRate, bool ITV = false>
-__global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta hm, int32_t npieces,
+// H1: one workgroup per hub piece (of a whole hub: H1 to H3 at once).
+template <class Cfg, typename V, bool COMP, int MODE = kModeRate, bool ITV = false>
+__global__ __launch_bounds__(Cfg::kThreads) void k_hub_piece(RoundCtx x, HubMeta hm, int32_t npieces,
                                                             uint32_t* ctr, TileLayout L) {
-  constexpr int NT = kPieceThreads, ITEMS = kPieceItems, NS = kHubStreams;
+  constexpr int NT = Cfg::kThreads, ITEMS = Cfg::kItems, NS = Cfg::kStreams;
+  constexpr bool WHOLE = Cfg::kWhole;
   extern __shared__ __align__(16) uint8_t smem_raw[];
   if (*x.done) return;
   const int tid = threadIdx.x;
@@ -1205,9 +1229,9 @@ __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta
   uint8_t* A = smem_raw;
   uint32_t* A32 = (uint32_t*)A;
   int32_t* keys = (int32_t*)A;
-  V* vals = (V*)(A + (size_t)kPieceSlots * 4);
+  V* vals = (V*)(A + (size_t)Cfg::kSlots * 4);
   uint32_t* nums = (uint32_t*)(A + L.nums_off);
-  PieceShared& sh = *(PieceShared*)(A + L.abytes);
+  PieceShared<Cfg>& sh = *(PieceShared<Cfg>*)(A + L.abytes);
   V* rec_r = (V*)hm.rec_r;
   // pieces are handed out at run time, kPieceGrab at a time (one counter)
   uint32_t pnext = 0, pend = 0;
@@ -1223,9 +1247,9 @@ __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta
     const int64_t pc = pnext++;
     const int2 pj = hm.pieces[pc];
     const int h = pj.x;
-    const uint32_t P = (uint32_t)hm.nparts[h];
-    const uint64_t rbase = hm.rec_base[h] + (uint64_t)pj.y * kHubPiece;
-    uint32_t* po = hm.poff + hm.poff_base[h] + (uint64_t)pj.y * (P + 1);
+    const uint32_t P = WHOLE ? 1u : (uint32_t)hm.nparts[h];
+    const uint64_t rbase = WHOLE ? 0ull : hm.rec_base[h] + (uint64_t)pj.y * kHubPiece;
+    uint32_t* po = WHOLE ? nullptr : hm.poff + hm.poff_base[h] + (uint64_t)pj.y * (P + 1);
     // 0. streams
     if (tid == 0) {
       uint32_t e = 0, dw = 0, nn = 0;
@@ -1253,7 +1277,8 @@ __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta
       sh.rstart[NS] = nn;
       sh.seg_flags = 0;
     }
-    for (uint32_t p = tid; p < P; p += NT) sh.hist[p] = 0;
+    if constexpr (!WHOLE)
+      for (uint32_t p = tid; p < P; p += NT) sh.hist[p] = 0;
     __syncthreads();
     const uint32_t Et = sh.ebase[NS];
     if constexpr (COMP) {
@@ -1307,7 +1332,7 @@ __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta
     int32_t vi[ITEMS], nb[ITEMS], wt[ITEMS];
     if constexpr (COMP && ITV) {
       // interval-coded: every stream is a chunk start (see k_hub_streams)
-      const ItvTable itv = itv_table<NT, NS, kHubPiece / 3 + 1>(A32, nums, sh.rstart, sh.ebase, sh.base_v, NS,
+      const ItvTable itv = itv_table<NT, NS, Cfg::kEdges / 3 + 1>(A32, nums, sh.rstart, sh.ebase, sh.base_v, NS,
                                                                  sh.scan, sh.scan2, &sh.seg_flags);
       int32_t s = 0;
       if (e0 < Et)
@@ -1431,7 +1456,7 @@ __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta
         c = block_reduce_add<NT, unsigned long long>(c, sh.red_u);
         if (tid == 0 && c) atomicAdd(x.cut, c);
       } else {
-        Rec* r = x.rec + x.rbase[own] + x.voff[u] + (uint64_t)pj.y * kHubPiece;
+        Rec* r = x.rec + x.rbase[own] + x.voff[u] + (uint64_t)pj.y * Cfg::kEdges;
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k)
           if (vi[k] >= 0) r[e0 + k] = Rec{nb[k] == own ? -1 : nb[k], wt[k]};
@@ -1449,6 +1474,51 @@ __global__ __launch_bounds__(kPieceThreads) void k_hub_piece(RoundCtx x, HubMeta
       sz = S;
     });
     __syncthreads();
+    if constexpr (WHOLE) {
+      // the hub's own rating and best cluster by (rating, smallest key),
+      // keys computed only for slots that reach the thread's best rating;
+      // if that cluster is full, the best one with room
+      const int32_t u = hm.u[h];
+      const int32_t own_c = x.C[u];
+      const int64_t wu = vweight(x.g, u);
+      const VParams vp = vparams(x, u);
+      Cand lb = cand_none();
+      int64_t own = 0;
+      for (uint32_t q = tid; q < S; q += NT) {
+        const int32_t c = keys[q];
+        if (c == kEmpty) continue;
+        const int64_t r = (int64_t)vals[q];
+        if (c == own_c) {
+          own = r;
+          continue;
+        }
+        if (r < lb.r) continue;
+        const Cand cd{r, cluster_key(x, vp, c), c};
+        if (cand_better(cd, lb)) lb = cd;
+      }
+      lb = block_best<NT>(lb, sh.best);
+      own = block_reduce_add<NT, int64_t>(own, sh.red);
+      Cand best = cand_none();
+      if (lb.c >= 0 && lb.r > own) {
+        if (x.W[lb.c] + wu <= vp.cap) {
+          best = lb;
+        } else {
+          Cand fb = cand_none();
+          for (uint32_t q = tid; q < S; q += NT) {
+            const int32_t c = keys[q];
+            if (c == kEmpty || c == own_c) continue;
+            const int64_t r = (int64_t)vals[q];
+            if (r <= own || r < fb.r) continue;
+            const Cand cd{r, cluster_key(x, vp, c), c};
+            if (cand_better(cd, fb) && x.W[c] + wu <= vp.cap) fb = cd;
+          }
+          best = block_best<NT>(fb, sh.best);
+        }
+      }
+      if (tid == 0) emit(x, u, best, own);
+      __syncthreads();
+      continue;
+    }
     // distinct clusters grouped by partition
     const uint32_t rmax = hm.packed ? (1u << hm.rbits) - 1u : 0u;
     for (uint32_t q = tid; q < S; q += NT) {
@@ -2077,6 +2147,12 @@ __global__ void k_round_end(const uint32_t* count, uint32_t* done, int64_t* stat
   *round_props = 0;
 }
 
+// Bytes of the compressed records of the listed vertices.
+__global__ void k_rec_bytes(const uint64_t* offs, const int32_t* idx, int32_t cnt, uint64_t* out) {
+  for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x)
+    out[i] = offs[idx[i] + 1] - offs[idx[i]];
+}
+
 __global__ void k_gather_i32(const int32_t* src, const int32_t* idx, int32_t cnt, int32_t* out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
     out[i] = src[idx[i]];
@@ -2191,19 +2267,32 @@ lp_status launch_tile_any(bool comp, RateWidth rw, const RoundCtx& x, VDesc vd, 
   return launch_tile<T, int32_t, false>(x, vd, tiles, ntiles, ctr, grid, weighted, s);
 }
 
-template <typename V>
+template <class Cfg, typename V>
 TileLayout piece_layout_of(bool comp, bool weighted) {
   TileLayout L;
   const uint32_t per = weighted ? 2u : 1u;
-  L.table_bytes = (uint32_t)kPieceSlots * (4u + (uint32_t)sizeof(V));
-  const uint32_t nums = comp ? (per * kHubPiece + 7u * kHubStreams) * 4u : 0u;
-  const uint32_t worst = comp ? 5u * per * kHubPiece + 16u * kHubStreams : 0u;
-  const uint32_t itv = comp ? (2u * kHubStreams + 2u + 2u * ((uint32_t)kHubPiece / 3u + 1u)) * 4u : 0u;
-  L.stage_bytes = comp ? ((std::max(worst, itv) + 15u) & ~15u) : 0u;
+  L.table_bytes = (uint32_t)Cfg::kSlots * (4u + (uint32_t)sizeof(V));
+  const uint32_t nums = comp ? (per * Cfg::kEdges + 7u * Cfg::kStreams) * 4u : 0u;
+  const uint32_t worst = comp ? 5u * per * Cfg::kEdges + 16u * Cfg::kStreams : 0u;
+  const uint32_t itv = comp ? (2u * Cfg::kStreams + 2u + 2u * ((uint32_t)Cfg::kEdges / 3u + 1u)) * 4u : 0u;
+  uint32_t sb = worst;
+  // a whole hub's staged bytes share the table's room: a hub whose record
+  // does not fit is cut into pieces instead (whole_fits)
+  if (Cfg::kWhole) sb = std::min(worst, L.table_bytes > nums ? L.table_bytes - nums : 0u);
+  sb = std::max(sb, itv);
+  L.stage_bytes = comp ? ((sb + 15u) & ~15u) : 0u;
   L.nums_off = L.stage_bytes;
   L.abytes = std::max(L.table_bytes, L.stage_bytes + nums);
   L.abytes = (L.abytes + 15u) & ~15u;
   return L;
+}
+
+// Whether a hub of degree d whose record takes `bytes` can be rated whole
+// with the layout L of shape Cfg (dwords of up to kStreams streams staged).
+template <class Cfg>
+bool whole_fits(const TileLayout& L, bool comp, int64_t d, uint64_t bytes) {
+  if (d > Cfg::kEdges) return false;
+  return !comp || bytes + 8u * (uint64_t)Cfg::kStreams + 16u <= (uint64_t)L.stage_bytes;
 }
 
 // The lane kernel for the graph's format.
@@ -2219,17 +2308,34 @@ lp_status launch_lane(const RoundCtx& x, VDesc vd, int32_t cnt, hipStream_t s) {
   return last_error();
 }
 
-template <int MODE = kModeRate>
-lp_status launch_piece(bool comp, bool wide, const RoundCtx& x, const HubMeta& hm, int32_t npieces, uint32_t* ctr,
-                       const TileLayout& L, size_t lds, hipStream_t s) {
-  auto kern = comp ? (x.g.intervals ? (wide ? k_hub_piece<int64_t, true, MODE, true>
-                                            : k_hub_piece<int32_t, true, MODE, true>)
-                                    : (wide ? k_hub_piece<int64_t, true, MODE> : k_hub_piece<int32_t, true, MODE>))
-                   : (wide ? k_hub_piece<int64_t, false, MODE> : k_hub_piece<int32_t, false, MODE>);
+template <class Cfg, typename V, int MODE = kModeRate>
+lp_status launch_piece_t(const RoundCtx& x, const HubMeta& hm, int32_t npieces, uint32_t* ctr, hipStream_t s) {
+  const bool comp = x.g.offs != nullptr;
+  const TileLayout L = piece_layout_of<Cfg, V>(comp, x.g.weighted != 0);
+  const size_t lds = (size_t)L.abytes + sizeof(PieceShared<Cfg>);
+  auto kern = comp ? (x.g.intervals ? k_hub_piece<Cfg, V, true, MODE, true> : k_hub_piece<Cfg, V, true, MODE>)
+                   : k_hub_piece<Cfg, V, false, MODE>;
   LP_CHECK(set_lds(kern, lds));
-  const unsigned grid = grid_for(npieces, 1, 2048);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kPieceThreads), lds, s, x, hm, npieces, ctr, L);
+  const unsigned grid = grid_for(npieces, 1, Cfg::kWhole ? 1024 : 2048);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(Cfg::kThreads), lds, s, x, hm, npieces, ctr, L);
   return last_error();
+}
+
+// The pieces of the hubs that are cut (ratings of the graph's width).
+template <int MODE = kModeRate>
+lp_status launch_piece(bool wide, const RoundCtx& x, const HubMeta& hm, int32_t npieces, uint32_t* ctr,
+                       hipStream_t s) {
+  if (wide) return launch_piece_t<PieceHub, int64_t, MODE>(x, hm, npieces, ctr, s);
+  return launch_piece_t<PieceHub, int32_t, MODE>(x, hm, npieces, ctr, s);
+}
+
+// The whole hubs: 16-bit ratings for unit edge weights, else 32-bit (graphs
+// with 64-bit ratings have none).
+template <int MODE = kModeRate>
+lp_status launch_whole(bool weighted, const RoundCtx& x, const HubMeta& hw, int32_t nwhole, uint32_t* ctr,
+                       hipStream_t s) {
+  if (!weighted) return launch_piece_t<PieceWhole16, uint16_t, MODE>(x, hw, nwhole, ctr, s);
+  return launch_piece_t<PieceWhole32, int32_t, MODE>(x, hw, nwhole, ctr, s);
 }
 
 // Tiles of one tile bucket, planned on the device (the count stays there).
@@ -2328,7 +2434,9 @@ struct Plan {
   uint32_t* vlen = nullptr;
   TilePlan tps, tpl;
   HubMeta hm{};  // static parts only; per-call buffers are set by the caller
-  int32_t H = 0, npieces = 0, ntasks = 0;
+  HubMeta hw{};  // the hubs rated whole (u, deg, pieces, streams)
+  int32_t H = 0, npieces = 0, ntasks = 0;  // hubs cut into pieces
+  int32_t nwhole = 0;
   uint64_t rsum = 0, psum = 0;
   unsigned long long bsums[2 * kNumBuckets] = {};
   PlanMem mem;
@@ -2405,79 +2513,140 @@ lp_status build_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t 
   LP_CHECK(plan_tiles<TileSmall>(P.vd(1), P.bn[1], g->compressed, rate_width(g), g->weighted, gid, sc, P.mem, P.tps));
   LP_CHECK(plan_tiles<TileLarge>(P.vd(2), P.bn[2], g->compressed, rate_width(g), g->weighted, gid, sc, P.mem, P.tpl));
 
-  // hubs: metadata (host-built, small) and the code streams of their pieces
-  const int32_t H = P.bn[3];
-  P.H = H;
-  if (H > 0) {
-    std::vector<int32_t> hu(H), hd(H);
-    int32_t* hdeg_dev = sc.alloc<int32_t>(H);
-    if (!hdeg_dev) return LP_ENOMEM;
-    hipLaunchKernelGGL(k_gather_i32, dim3(grid_for(H, 256, 4096)), dim3(256), 0, s, deg, P.order + P.bstart[3], H,
-                       hdeg_dev);
+  // hubs: metadata (host-built, small) and the code streams of their pieces.
+  // A hub whose record fits one workgroup's LDS is rated whole; the others
+  // are cut into pieces.
+  const int32_t Hall = P.bn[3];
+  P.H = 0;
+  P.nwhole = 0;
+  if (Hall > 0) {
+    std::vector<int32_t> au(Hall), ad(Hall);
+    std::vector<uint64_t> ab(Hall, 0);
+    int32_t* hdeg_dev = sc.alloc<int32_t>(Hall);
+    uint64_t* hbytes_dev = sc.alloc<uint64_t>(Hall);
+    if (!hdeg_dev || !hbytes_dev) return LP_ENOMEM;
+    hipLaunchKernelGGL(k_gather_i32, dim3(grid_for(Hall, 256, 4096)), dim3(256), 0, s, deg, P.order + P.bstart[3],
+                       Hall, hdeg_dev);
     LP_CHECK_LAUNCH();
-    LP_CHECK_HIP(hipMemcpyAsync(hu.data(), P.order + P.bstart[3], H * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    LP_CHECK_HIP(hipMemcpyAsync(hd.data(), hdeg_dev, H * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    LP_CHECK_HIP(hipStreamSynchronize(s));
-    // partitions of about hub_part records (at most kMaxParts)
-    std::vector<int32_t> np(H), npc(H), pcb(H), tb(H);
-    std::vector<uint64_t> rbase(H), pbase(H);
-    std::vector<int2> pieces;
-    std::vector<HubTask> tasks;
-    uint64_t rsum = 0, psum = 0;
-    int32_t ntasks = 0;
-    for (int h = 0; h < H; ++h) {
-      const int64_t d = hd[h];
-      np[h] = (int32_t)std::min<int64_t>(kMaxParts, std::max<int64_t>(1, (d + hub_part - 1) / hub_part));
-      npc[h] = (int32_t)((d + kHubPiece - 1) / kHubPiece);
-      pcb[h] = (int32_t)pieces.size();
-      rbase[h] = rsum;
-      pbase[h] = psum;
-      tb[h] = ntasks;
-      rsum += (uint64_t)d;
-      psum += (uint64_t)npc[h] * (np[h] + 1);
-      ntasks += np[h];
-      for (int k = 0; k < npc[h]; ++k) pieces.push_back(make_int2(h, k));
-      for (int p = 0; p < np[h]; ++p) tasks.push_back(HubTask{hu[h], np[h], npc[h], p, rbase[h], pbase[h]});
+    if (g->compressed) {
+      hipLaunchKernelGGL(k_rec_bytes, dim3(grid_for(Hall, 256, 4096)), dim3(256), 0, s, g->offs,
+                         P.order + P.bstart[3], Hall, hbytes_dev);
+      LP_CHECK_LAUNCH();
+      LP_CHECK_HIP(hipMemcpyAsync(ab.data(), hbytes_dev, Hall * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     }
-    P.npieces = (int32_t)pieces.size();
-    P.ntasks = ntasks;
-    P.rsum = rsum;
-    P.psum = psum;
-    HubMeta& hm = P.hm;
-    int32_t* d_u = P.mem.alloc<int32_t>(H);
-    int32_t* d_deg = P.mem.alloc<int32_t>(H);
-    int32_t* d_np = P.mem.alloc<int32_t>(H);
-    int32_t* d_npc = P.mem.alloc<int32_t>(H);
-    int32_t* d_pcb = P.mem.alloc<int32_t>(H);
-    int32_t* d_tb = P.mem.alloc<int32_t>(H);
-    uint64_t* d_rb = P.mem.alloc<uint64_t>(H);
-    uint64_t* d_pb = P.mem.alloc<uint64_t>(H);
-    int2* d_pieces = P.mem.alloc<int2>(P.npieces);
-    HubTask* d_tasks = P.mem.alloc<HubTask>(ntasks);
-    hm.streams = P.mem.alloc<HubStream>((size_t)P.npieces * kHubStreams);
-    if (P.mem.failed) return LP_ENOMEM;
-    LP_CHECK_HIP(hipMemcpyAsync(d_u, hu.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_deg, hd.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_np, np.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_npc, npc.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_pcb, pcb.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_tb, tb.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_rb, rbase.data(), H * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_pb, pbase.data(), H * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_pieces, pieces.data(), P.npieces * sizeof(int2), hipMemcpyHostToDevice, s));
-    LP_CHECK_HIP(hipMemcpyAsync(d_tasks, tasks.data(), ntasks * sizeof(HubTask), hipMemcpyHostToDevice, s));
-    hm.u = d_u;
-    hm.deg = d_deg;
-    hm.nparts = d_np;
-    hm.npieces = d_npc;
-    hm.piece_base = d_pcb;
-    hm.rec_base = d_rb;
-    hm.poff_base = d_pb;
-    hm.task_base = d_tb;
-    hm.pieces = d_pieces;
-    hm.tdesc = d_tasks;
-    hipLaunchKernelGGL(k_hub_streams, dim3(grid_for(H, 4, 4096)), dim3(256), 0, s, g->view(), hm, H);
-    LP_CHECK_LAUNCH();
+    LP_CHECK_HIP(hipMemcpyAsync(au.data(), P.order + P.bstart[3], Hall * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LP_CHECK_HIP(hipMemcpyAsync(ad.data(), hdeg_dev, Hall * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    LP_CHECK_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> hu, hd, wu, wd;
+    const bool comp = g->compressed != 0;
+    const TileLayout WL = g->weighted ? piece_layout_of<PieceWhole32, int32_t>(comp, true)
+                                      : piece_layout_of<PieceWhole16, uint16_t>(comp, false);
+    for (int32_t i = 0; i < Hall; ++i) {
+      const bool whole = !P.wide && (g->weighted ? whole_fits<PieceWhole32>(WL, comp, ad[i], ab[i])
+                                                 : whole_fits<PieceWhole16>(WL, comp, ad[i], ab[i]));
+      (whole ? wu : hu).push_back(au[i]);
+      (whole ? wd : hd).push_back(ad[i]);
+    }
+    const int32_t H = (int32_t)hu.size();
+    const int32_t HW = (int32_t)wu.size();
+    P.H = H;
+    P.nwhole = HW;
+    if (HW > 0) {
+      HubMeta& hw = P.hw;
+      const int NSW = g->weighted ? PieceWhole32::kStreams : PieceWhole16::kStreams;
+      std::vector<int32_t> ones(HW, 1), idx(HW);
+      std::vector<int2> wp(HW);
+      for (int32_t i = 0; i < HW; ++i) {
+        idx[i] = i;
+        wp[i] = make_int2(i, 0);
+      }
+      int32_t* d_u = P.mem.alloc<int32_t>(HW);
+      int32_t* d_deg = P.mem.alloc<int32_t>(HW);
+      int32_t* d_one = P.mem.alloc<int32_t>(HW);
+      int32_t* d_idx = P.mem.alloc<int32_t>(HW);
+      int2* d_wp = P.mem.alloc<int2>(HW);
+      hw.streams = P.mem.alloc<HubStream>((size_t)HW * NSW);
+      if (P.mem.failed) return LP_ENOMEM;
+      LP_CHECK_HIP(hipMemcpyAsync(d_u, wu.data(), HW * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      LP_CHECK_HIP(hipMemcpyAsync(d_deg, wd.data(), HW * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      LP_CHECK_HIP(hipMemcpyAsync(d_one, ones.data(), HW * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      LP_CHECK_HIP(hipMemcpyAsync(d_idx, idx.data(), HW * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      LP_CHECK_HIP(hipMemcpyAsync(d_wp, wp.data(), HW * sizeof(int2), hipMemcpyHostToDevice, s));
+      hw.u = d_u;
+      hw.deg = d_deg;
+      hw.npieces = d_one;
+      hw.piece_base = d_idx;
+      hw.pieces = d_wp;
+      if (g->weighted)
+        hipLaunchKernelGGL(k_hub_streams<PieceWhole32>, dim3(grid_for(HW, 4, 4096)), dim3(256), 0, s, g->view(), hw,
+                           HW);
+      else
+        hipLaunchKernelGGL(k_hub_streams<PieceWhole16>, dim3(grid_for(HW, 4, 4096)), dim3(256), 0, s, g->view(), hw,
+                           HW);
+      LP_CHECK_LAUNCH();
+    }
+    if (H > 0) {
+      // partitions of about hub_part records (at most kMaxParts)
+      std::vector<int32_t> np(H), npc(H), pcb(H), tb(H);
+      std::vector<uint64_t> rbase(H), pbase(H);
+      std::vector<int2> pieces;
+      std::vector<HubTask> tasks;
+      uint64_t rsum = 0, psum = 0;
+      int32_t ntasks = 0;
+      for (int h = 0; h < H; ++h) {
+        const int64_t d = hd[h];
+        np[h] = (int32_t)std::min<int64_t>(kMaxParts, std::max<int64_t>(1, (d + hub_part - 1) / hub_part));
+        npc[h] = (int32_t)((d + kHubPiece - 1) / kHubPiece);
+        pcb[h] = (int32_t)pieces.size();
+        rbase[h] = rsum;
+        pbase[h] = psum;
+        tb[h] = ntasks;
+        rsum += (uint64_t)d;
+        psum += (uint64_t)npc[h] * (np[h] + 1);
+        ntasks += np[h];
+        for (int k = 0; k < npc[h]; ++k) pieces.push_back(make_int2(h, k));
+        for (int p = 0; p < np[h]; ++p) tasks.push_back(HubTask{hu[h], np[h], npc[h], p, rbase[h], pbase[h]});
+      }
+      P.npieces = (int32_t)pieces.size();
+      P.ntasks = ntasks;
+      P.rsum = rsum;
+      P.psum = psum;
+      HubMeta& hm = P.hm;
+      int32_t* d_u = P.mem.alloc<int32_t>(H);
+      int32_t* d_deg = P.mem.alloc<int32_t>(H);
+      int32_t* d_np = P.mem.alloc<int32_t>(H);
+      int32_t* d_npc = P.mem.alloc<int32_t>(H);
+      int32_t* d_pcb = P.mem.alloc<int32_t>(H);
+      int32_t* d_tb = P.mem.alloc<int32_t>(H);
+      uint64_t* d_rb = P.mem.alloc<uint64_t>(H);
+      uint64_t* d_pb = P.mem.alloc<uint64_t>(H);
+      int2* d_pieces = P.mem.alloc<int2>(P.npieces);
+      HubTask* d_tasks = P.mem.alloc<HubTask>(ntasks);
+      hm.streams = P.mem.alloc<HubStream>((size_t)P.npieces * kHubStreams);
+      if (P.mem.failed) return LP_ENOMEM;
+      LP_CHECK_HIP(hipMemcpyAsync(d_u, hu.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      LP_CHECK_HIP(hipMemcpyAsync(d_deg, hd.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      LP_CHECK_HIP(hipMemcpyAsync(d_np, np.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      LP_CHECK_HIP(hipMemcpyAsync(d_npc, npc.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      LP_CHECK_HIP(hipMemcpyAsync(d_pcb, pcb.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      LP_CHECK_HIP(hipMemcpyAsync(d_tb, tb.data(), H * sizeof(int32_t), hipMemcpyHostToDevice, s));
+      LP_CHECK_HIP(hipMemcpyAsync(d_rb, rbase.data(), H * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+      LP_CHECK_HIP(hipMemcpyAsync(d_pb, pbase.data(), H * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+      LP_CHECK_HIP(hipMemcpyAsync(d_pieces, pieces.data(), P.npieces * sizeof(int2), hipMemcpyHostToDevice, s));
+      LP_CHECK_HIP(hipMemcpyAsync(d_tasks, tasks.data(), ntasks * sizeof(HubTask), hipMemcpyHostToDevice, s));
+      hm.u = d_u;
+      hm.deg = d_deg;
+      hm.nparts = d_np;
+      hm.npieces = d_npc;
+      hm.piece_base = d_pcb;
+      hm.rec_base = d_rb;
+      hm.poff_base = d_pb;
+      hm.task_base = d_tb;
+      hm.pieces = d_pieces;
+      hm.tdesc = d_tasks;
+      hipLaunchKernelGGL(k_hub_streams<PieceHub>, dim3(grid_for(H, 4, 4096)), dim3(256), 0, s, g->view(), hm, H);
+      LP_CHECK_LAUNCH();
+    }
   }
   LP_CHECK_HIP(hipStreamSynchronize(s));  // host vectors go out of scope; the plan is complete
   return LP_OK;
@@ -2553,11 +2722,8 @@ lp_status visit_edges_mode(const lp_graph* g, const int32_t* C, const uint64_t* 
       LP_CHECK((launch_tile<TileLarge, int32_t, false, MODE>(x, plan->vd(2), plan->tpl.tiles, plan->tpl.ntiles,
                                                              zero + 16, plan->tpl.grid, g->weighted, s)));
   }
-  if (plan->H > 0) {
-    const TileLayout L = piece_layout_of<int32_t>(comp, g->weighted);
-    LP_CHECK(launch_piece<MODE>(comp, false, x, plan->hm, plan->npieces, zero + 24, L,
-                                (size_t)L.abytes + sizeof(PieceShared), s));
-  }
+  if (plan->nwhole > 0) LP_CHECK(launch_whole<MODE>(g->weighted, x, plan->hw, plan->nwhole, zero + 28, s));
+  if (plan->H > 0) LP_CHECK(launch_piece<MODE>(false, x, plan->hm, plan->npieces, zero + 24, s));
   return LP_OK;
 }
 
@@ -2863,9 +3029,6 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
   x.gbase = batch ? g->gbase : nullptr;
   x.gcap = gcap;
   x.gseed = gseed;
-  const TileLayout piece_layout = wide ? piece_layout_of<int64_t>(g->compressed, g->weighted)
-                                      : piece_layout_of<int32_t>(g->compressed, g->weighted);
-  const size_t piece_lds = (size_t)piece_layout.abytes + sizeof(PieceShared);
   if (hmax > 0) {
     if (wide) LP_CHECK(set_lds(k_hub_reduce<int64_t>, (size_t)hub_table(hub_part, true) * 12 + sizeof(HubReduceSmem)));
     else LP_CHECK(set_lds(k_hub_reduce<int32_t>, (size_t)hub_table(hub_part, false) * 8 + sizeof(HubReduceSmem)));
@@ -2905,9 +3068,11 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
                            bn[1] + bn[2] + bn[3], s));
         LP_CHECK(end());
       }
-      if (!use_gt && H > 0) {
+      if (!use_gt && (H > 0 || plan->nwhole > 0)) {
         LP_CHECK(begin(LP_PHASE_HUB));
-        LP_CHECK(launch_piece(g->compressed, wide, x, hm, npieces, hand_r + 16, piece_layout, piece_lds, s));
+        if (plan->nwhole > 0) LP_CHECK(launch_whole(g->weighted, x, plan->hw, plan->nwhole, hand_r + 20, s));
+        if (H > 0) LP_CHECK(launch_piece(wide, x, hm, npieces, hand_r + 16, s));
+        else LP_CHECK(end());
       }
       if (!use_gt) {
         if (overlap) {

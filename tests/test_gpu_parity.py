@@ -350,3 +350,32 @@ def test_giant_hub_partitions(lp, oracle_mod, giant_hubs, knobs, compressed):
     exp, _ = oracle_mod.lp_cluster(g, 3000, 4, 21)
     lab = lp.lp_cluster(G, 3000, 4, 21, config=knobs)
     assert np.array_equal(_np(lab), exp)
+
+
+def _kab_ring(synth_mod, a, b):
+    # K_{a,b} plus a ring over the b side: the a side has degree b exactly
+    # (b = 16000: the largest hub rated whole with 16-bit ratings, sixteen
+    # chunks; b = 16001: cut into pieces)
+    edges = [(i, a + j) for i in range(a) for j in range(b)]
+    edges += [(a + j, a + (j + 1) % b) for j in range(b)]
+    return synth_mod.from_edges(a + b, edges)
+
+
+@pytest.mark.parametrize("a,b", [(3, 16000), (2, 16001), (4, 12000)])
+@pytest.mark.parametrize("fmt", ["gap", "intervals", "plain"])
+def test_whole_hub_bounds(lp, oracle_mod, synth_mod, a, b, fmt):
+    g = _kab_ring(synth_mod, a, b)
+    if fmt == "plain":
+        G = lp.lp_graph_from_csr(g.n, g.xadj.view(np.int64), g.adjncy, g.adjwgt, g.vwgt)
+    else:
+        G = lp.lp_compress(g.n, g.xadj.view(np.int64), g.adjncy, g.adjwgt, g.vwgt, intervals=fmt == "intervals")
+    for cap, rounds, seed in ((50, 4, 3), (20000, 3, 5)):
+        exp, _ = oracle_mod.lp_cluster(g, cap, rounds, seed)
+        assert np.array_equal(_np(lp.lp_cluster(G, cap, rounds, seed)), exp)
+    # the edge visits (cut, contraction records) take the same whole / cut split
+    lab = (np.arange(g.n, dtype=np.int64) * 7919 % 101).astype(np.int32)
+    assert lp.lp_edge_cut(G, lab) == oracle_mod.edge_cut(g, lab)
+    cg, mp = oracle_mod.contract(g, lab)
+    C, M = lp.lp_contract(G, lab)
+    x, adj, w, v = lp.lp_decompress(C)
+    assert np.array_equal(_np(M), mp) and np.array_equal(_np(adj), cg.adjncy) and np.array_equal(_np(w), cg.adjwgt)
