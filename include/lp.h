@@ -205,6 +205,15 @@ typedef struct {
                          result-invariant; lp_cluster rejects it (LP_EINVAL) */
   int32_t overlap;   /* nonzero: the four rating paths of a round run on concurrent side streams
                         instead of one after another on `stream` (result-invariant) */
+  int32_t reorder;   /* result-invariant: rate on a degree-ordered copy of the graph, built on the
+                        first call and kept with the handle until lp_graph_free (about the size of
+                        the graph again; the build synchronises the stream and takes one-time
+                        scratch of about 28 bytes per directed edge). Random label gathers then
+                        find the labels of the vertices most edges point to in fewer cache lines.
+                        0: automatic (single graphs of at least 2^20 vertices, lp_cluster_ex from
+                        singletons with one sub-round); 1: always where it applies; 2: never.
+                        lp_refine(_ex), sub-rounds, batches and the gain table always rate on the
+                        graph as given. */
 } lp_config;
 
 /* Phases timed when lp_config.timing is set (milliseconds summed over rounds). */

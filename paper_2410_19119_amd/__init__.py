@@ -42,7 +42,8 @@ PHASES = ("setup", "lane", "tile", "block", "hub", "accept", "round")
 class lp_config(ctypes.Structure):
     _fields_ = [("t_lane", ctypes.c_int32), ("t_tile", ctypes.c_int32),
                 ("t_block", ctypes.c_int32), ("hub_part", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("subrounds", ctypes.c_int32), ("gain_table", ctypes.c_int32), ("overlap", ctypes.c_int32)]
+                ("subrounds", ctypes.c_int32), ("gain_table", ctypes.c_int32), ("overlap", ctypes.c_int32),
+                ("reorder", ctypes.c_int32)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblpgpu.so")
-SOURCES = ["prims.hip", "codec.hip", "cluster.hip", "contract.hip", "cut.hip", "batch.hip", "partition.hip", "gain.hip"]
+SOURCES = ["prims.hip", "codec.hip", "cluster.hip", "contract.hip", "cut.hip", "batch.hip", "partition.hip", "gain.hip", "reorder.hip"]
 ARCH = os.environ.get("LPGPU_ARCH", "gfx950")
 
 FLAGS = [

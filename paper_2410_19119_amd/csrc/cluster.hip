@@ -23,6 +23,7 @@
 #include "decode.h"
 #include "gain.h"
 #include "graph.h"
+#include "reorder.h"
 
 namespace lp {
 
@@ -37,6 +38,10 @@ struct RoundCtx {
   uint32_t round;
   int32_t* ptgt;     // proposal target per vertex, -1 = none
   int64_t* pgain;    // proposal gain per vertex
+  // rating on a degree-ordered copy (reorder.h): original vertex of every
+  // vertex of the copy, where its proposal is written (labels hold original
+  // cluster IDs); nullptr = not reordered
+  const int32_t* pmap;
   const uint32_t* done;
   // batches of graphs (disjoint union): graph of each vertex, first vertex,
   // cap and seed of each graph; gid == nullptr for a single graph
@@ -88,12 +93,19 @@ __device__ __forceinline__ uint64_t vd_pos(const int4 v) {
   return (uint64_t)(uint32_t)v.z | ((uint64_t)(uint32_t)v.w << 32);
 }
 
+// Slot of vertex u's proposal: its original ID when rating a reordered copy.
+__device__ __forceinline__ int32_t prop_slot(const RoundCtx& x, int32_t u) { return x.pmap ? x.pmap[u] : u; }
+
+// Writes vertex u's proposal. On a reordered copy the slots were reset to
+// "none" before the round and only proposals are written (scattered writes
+// to the original vertices cost more than the coalesced ones of the copy).
 __device__ __forceinline__ void emit(const RoundCtx& x, int32_t u, const Cand& best, int64_t own) {
+  const int32_t pu = prop_slot(x, u);
   if (best.c >= 0 && best.r > own) {
-    x.ptgt[u] = best.c;
-    x.pgain[u] = best.r - own;
-  } else {
-    x.ptgt[u] = -1;
+    x.ptgt[pu] = best.c;
+    x.pgain[pu] = best.r - own;
+  } else if (!x.pmap) {
+    x.ptgt[pu] = -1;
   }
 }
 
@@ -670,12 +682,12 @@ __device__ __forceinline__ void tile_select(const RoundCtx& x, const int32_t* ke
         sh.best_c[i] = best.r > own ? best.c : -1;
         sh.gain[i] = best.r - own;
       } else {
-        const int32_t u = sh.u[i];
+        const int32_t pu = prop_slot(x, sh.u[i]);
         if (best.c >= 0) {
-          x.ptgt[u] = best.c;
-          x.pgain[u] = best.r - own0;
-        } else {
-          x.ptgt[u] = -1;
+          x.ptgt[pu] = best.c;
+          x.pgain[pu] = best.r - own0;
+        } else if (!x.pmap) {
+          x.ptgt[pu] = -1;
         }
       }
     }
@@ -975,10 +987,10 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
       else tile_select<SG, NT, V>(x, keys, vals, sh, nv, tid, false);
       __syncthreads();
       if (tid < nv) {
-        const int32_t u = sh.u[tid];
+        const int32_t u = prop_slot(x, sh.u[tid]);
         const int32_t c = sh.best_c[tid];
         if (c < 0) {
-          x.ptgt[u] = -1;
+          if (!x.pmap) x.ptgt[u] = -1;
         } else if (x.W[c] + sh.wu[tid] <= sh.vp.cap) {
           x.ptgt[u] = c;
           x.pgain[u] = sh.gain[tid];
@@ -2053,9 +2065,10 @@ __global__ __launch_bounds__(kCpThreads) void k_prop_count(const int32_t* ptgt, 
 }
 
 // Writes the proposals in increasing vertex order: key = target << G |
-// (2^G - 1 - gain), value = vertex. With sub-rounds it clears the proposal
-// slots it took (a later sub-round rates other vertices only); with one
-// sub-round every rated vertex writes its slot again in the next round.
+// (2^G - 1 - gain), value = vertex. With sub-rounds, or when rating a
+// reordered copy (which writes proposals only), it clears the proposal slots
+// it took; otherwise every rated vertex writes its slot again in the next
+// round.
 __global__ __launch_bounds__(kCpThreads) void k_prop_write(int32_t* ptgt, const int64_t* pgain, int32_t n,
                                                            const uint32_t* boff, int G, uint64_t* keys,
                                                            uint32_t* vals, const uint32_t* done, int reset) {
@@ -2109,7 +2122,8 @@ __global__ void k_admit(const uint32_t* seg, const int64_t* prefix, const uint32
 // the prefix at the last admitted one: one atomic per target, not per move.
 __global__ __launch_bounds__(256) void k_apply(const uint32_t* seg, const uint32_t* vals, const uint8_t* flag,
                                                const int64_t* wv, const int64_t* prefix, const uint32_t* count,
-                                               int32_t* C, int64_t* W, int64_t* stats, int round, int4* mv) {
+                                               int32_t* C, int64_t* W, int64_t* stats, int round, int4* mv,
+                                               int32_t* Cc, const int32_t* pos) {
   __shared__ int64_t sm[4];
   const int64_t n = *count;
   int64_t moves = 0;
@@ -2122,6 +2136,7 @@ __global__ __launch_bounds__(256) void k_apply(const uint32_t* seg, const uint32
     const int32_t t = (int32_t)seg[i];
     const int32_t old = C[u];
     C[u] = t;
+    if (Cc) Cc[pos[u]] = t;  // the reordered copy's labels (indexed by its vertices)
     if (mv) mv[i] = make_int4(u, old, t, 0);
     if (i + 1 == n || seg[i + 1] != (uint32_t)t || !flag[i + 1])
       atomicAdd((unsigned long long*)&W[t], (unsigned long long)prefix[i]);
@@ -2966,9 +2981,30 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
   } jg{s, side, ev.e};
 
   LP_CHECK(begin(LP_PHASE_SETUP));
+  // Rating on a degree-ordered copy of the graph (result-invariant, reorder.h):
+  // the copy's labels hold the original cluster IDs (tie-break keys and
+  // cluster weights need no translation), proposals land at the original
+  // vertices, so acceptance orders them exactly as on the graph as given;
+  // apply keeps both label arrays. The handle's own default plan is built as
+  // well, for the edge visits (cut, contraction) on the original graph.
+  const int32_t ro_mode = cfg_in ? cfg_in->reorder : 0;
+  if (ro_mode < 0 || ro_mode > 2) return LP_EINVAL;
+  const bool use_ro = ro_mode != 2 && init_k == 0 && !batch && !use_gt && S == 1 && reorder_applies(g) &&
+                      (ro_mode == 1 || n >= (1 << 20));
+  const Reorder* ro = nullptr;
+  int32_t* Cc = nullptr;
+  if (use_ro) {
+    LP_CHECK(get_reorder(g, s, &ro));
+    const Plan* p0;
+    std::unique_ptr<Plan> t0;
+    LP_CHECK(get_plan(g, 16, kTileMaxDeg, TileLarge::kEdges, kDefaultHubPart, s, &p0, t0));
+    Cc = sc.alloc<int32_t>(n);
+    if (!Cc) return LP_ENOMEM;
+  }
+  const lp_graph* gr = use_ro ? ro->g : g;  // the graph the rating kernels read
   std::vector<const Plan*> plans;  // one per sub-round
   std::unique_ptr<Plan> plan_tmp;
-  LP_CHECK(get_plans(g, t_lane, t_tile, t_block, hub_part, S, s, plans, plan_tmp));
+  LP_CHECK(get_plans(gr, t_lane, t_tile, t_block, hub_part, S, s, plans, plan_tmp));
   uint64_t rsum = 0, psum = 0;
   int32_t tmax = 0, hmax = 0;
   for (const Plan* p : plans) {
@@ -3013,12 +3049,15 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
   } else {
     hipLaunchKernelGGL(k_init, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, g->vwgt, labels, W, ptgt);
     LP_CHECK_LAUNCH();
+    // the copy's labels: vertex i starts in the cluster of its original ID
+    if (use_ro) LP_CHECK_HIP(hipMemcpyAsync(Cc, ro->orig, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   }
   LP_CHECK(end());
 
   RoundCtx x;
-  x.g = g->view();
-  x.C = labels;
+  x.g = gr->view();
+  x.C = use_ro ? Cc : labels;
+  x.pmap = use_ro ? ro->orig : nullptr;
   x.W = W;
   x.cap = cap;
   x.seed = seed;
@@ -3121,7 +3160,7 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
       LP_CHECK_LAUNCH();
       LP_CHECK(scan_exclusive_u32(pcnt, pcnt, ncp, &ctl->count, sc));
       hipLaunchKernelGGL(k_prop_write, dim3(ncp), dim3(kCpThreads), 0, s, ptgt, pgain, n, pcnt, G, ka, va, &ctl->done,
-                         S > 1 ? 1 : 0);
+                         (S > 1 || use_ro) ? 1 : 0);
       LP_CHECK_LAUNCH();
       uint64_t* ks;
       uint32_t* vs;
@@ -3133,7 +3172,7 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
       hipLaunchKernelGGL(k_admit, dim3(ga), dim3(256), 0, s, seg, pref, &ctl->count, W, cap, x.gid, gcap, flag);
       LP_CHECK_LAUNCH();
       hipLaunchKernelGGL(k_apply, dim3(ga), dim3(256), 0, s, seg, vs, flag, wv, pref, &ctl->count, labels, W,
-                         ctl->stats, r, mv);
+                         ctl->stats, r, mv, Cc, use_ro ? ro->pos : nullptr);
       LP_CHECK_LAUNCH();
       if (use_gt) LP_CHECK(gt_update(gt.t, mv, &ctl->count, n, labels, s));
       hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, s, &ctl->count, &ctl->done, ctl->stats, r, &ctl->rounds_run,
@@ -3144,6 +3183,7 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
     if (timing) LP_CHECK_HIP(hipEventRecord(marks[round_mark].b, s));
   }
   if (batch) LP_CHECK(batch_localize(g, labels, out_labels, labels_each, s));
+
   if (stats_out) {
     Ctl h;
     LP_CHECK_HIP(hipMemcpyAsync(&h, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));

@@ -751,12 +751,14 @@ extern "C" void lp_graph_free(lp_graph* g) {
     (void)hipGetDevice(&cur);
     if (cur != g->device) (void)hipSetDevice(g->device);
     if (g->plan && g->plan_free) g->plan_free(g->plan);
+    if (g->reord && g->reord_free) g->reord_free(g->reord);
     for (void* p : bufs) cache_free(p, g->mem_stream);
     if (cur != g->device) (void)hipSetDevice(cur);
     clear_error();
   } else {
     (void)hipDeviceSynchronize();
     if (g->plan && g->plan_free) g->plan_free(g->plan);
+    if (g->reord && g->reord_free) g->reord_free(g->reord);
     for (void* p : bufs) (void)hipFree(p);
   }
   delete g;

@@ -45,6 +45,10 @@ struct lp_graph {
   mutable void* plan = nullptr;
   void (*plan_free)(void*) = nullptr;
   mutable std::mutex plan_mu;
+  // degree-ordered copy for the rating kernels (reorder.h), built on first use
+  mutable void* reord = nullptr;
+  mutable void (*reord_free)(void*) = nullptr;
+  mutable std::mutex reord_mu;
 
   lp::GraphView view() const {
     lp::GraphView v;

@@ -379,3 +379,45 @@ def test_whole_hub_bounds(lp, oracle_mod, synth_mod, a, b, fmt):
     C, M = lp.lp_contract(G, lab)
     x, adj, w, v = lp.lp_decompress(C)
     assert np.array_equal(_np(M), mp) and np.array_equal(_np(adj), cg.adjncy) and np.array_equal(_np(w), cg.adjwgt)
+
+
+REORDER_KNOBS = [dict(reorder=1), dict(reorder=1, t_lane=1, t_tile=1, t_block=1, hub_part=256),
+                 dict(reorder=1, t_lane=4, t_tile=64, t_block=64, hub_part=1024, overlap=1)]
+
+
+@pytest.mark.parametrize("name", ["rgg2d-16k", "rmat-s13-ef16", "rmat-s12-weighted", "star-25000", "star-10001-w",
+                                  "bip-5x2048-heavy", "bip-3x9000-w"])
+@pytest.mark.parametrize("fmt", ["gap", "intervals", "plain"])
+def test_degree_ordered_copy_gives_identical_results(lp, oracle_mod, graphs, name, fmt):
+    # rating on the degree-ordered copy: labels valued by the original IDs,
+    # proposals at the original vertices, so labels and per-round counts equal
+    # the oracle's on the graph as given
+    g = graphs[name]
+    if fmt == "plain":
+        G = lp.lp_graph_from_csr(g.n, g.xadj.view(np.int64), g.adjncy, g.adjwgt, g.vwgt)
+    else:
+        G = lp.lp_compress(g.n, g.xadj.view(np.int64), g.adjncy, g.adjwgt, g.vwgt, intervals=fmt == "intervals")
+    exp, ost = oracle_mod.lp_cluster(g, 64, 4, 11)
+    for knobs in REORDER_KNOBS:
+        lab, st = lp.lp_cluster(G, 64, 4, 11, config=knobs, stats=True)
+        assert np.array_equal(_np(lab), exp), knobs
+        assert st.rounds_run == ost.rounds_run and st.proposals == ost.proposals and st.moves == ost.moves
+    # the cut and contraction after a reordered clustering run on the graph as given
+    lab = lp.lp_cluster(G, 64, 4, 11, config=dict(reorder=1))
+    assert lp.lp_edge_cut(G, lab) == oracle_mod.edge_cut(g, exp)
+
+
+def test_degree_ordered_copy_giant_hubs(lp, oracle_mod, giant_hubs):
+    g = giant_hubs
+    G = lp.lp_compress(g.n, g.xadj.view(np.int64), g.adjncy)
+    exp, ost = oracle_mod.lp_cluster(g, 3000, 4, 21)
+    for knobs in (dict(reorder=0), dict(reorder=2), dict(reorder=1, hub_part=256)):
+        lab, st = lp.lp_cluster(G, 3000, 4, 21, config=knobs, stats=True)
+        assert np.array_equal(_np(lab), exp), knobs
+        assert st.proposals == ost.proposals and st.moves == ost.moves
+
+
+def test_reorder_option_errors(lp, graphs):
+    G = _gpu_graph(lp, graphs["rgg2d-16k"])
+    with pytest.raises(lp.LPError):
+        lp.lp_cluster(G, 5, 1, 1, config=dict(reorder=3))
