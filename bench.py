@@ -770,14 +770,19 @@ def bench_headline(args) -> dict:
         C.free()
         return st, cut, n_coarse
 
-    # first call on the handle, zero rounds: plans and, for a graph of at
-    # least 2^20 vertices, the degree-ordered copy the rating kernels read
+    # the first call on the handle builds the plans; a call with the copy
+    # forced (zero rounds) builds the degree-ordered copy, which later calls
+    # use automatically on a skewed graph of at least 2^20 vertices
     torch.cuda.synchronize()
     t = time.perf_counter()
     lp.lp_cluster(G, cap, 0, 1, labels=labels)
     torch.cuda.synchronize()
     first_call_ms = 1e3 * (time.perf_counter() - t)
-    log(f"[bench] first call (plans, degree-ordered copy): {first_call_ms:.1f} ms")
+    t = time.perf_counter()
+    lp.lp_cluster(G, cap, 0, 1, labels=labels, config=dict(reorder=1))
+    torch.cuda.synchronize()
+    copy_build_ms = 1e3 * (time.perf_counter() - t)
+    log(f"[bench] first call (plans) {first_call_ms:.1f} ms, degree-ordered copy {copy_build_ms:.1f} ms")
     for i in range(args.warmup):
         step()
         log(f"[bench] warmup {i + 1}/{args.warmup} done")
@@ -929,6 +934,7 @@ def bench_headline(args) -> dict:
         "setup_ms_cached": round(st.phase_ms["setup"], 3),
         "setup_ms_uncached": round(setup_uncached, 3),
         "first_call_ms": round(first_call_ms, 1),
+        "copy_build_ms": round(copy_build_ms, 1),
         "t_round_ms_median_graph_as_given": round(t_round_asis, 4),
         "step_split_ms": {k: round(1e3 * v / args.steps, 2) for k, v in split.items()},
         "roofline": roofline,

@@ -210,8 +210,12 @@ typedef struct {
                         the graph again; the build synchronises the stream and takes one-time
                         scratch of about 28 bytes per directed edge). Random label gathers then
                         find the labels of the vertices most edges point to in fewer cache lines.
-                        0: automatic (single graphs of at least 2^20 vertices, lp_cluster_ex from
-                        singletons with one sub-round); 1: always where it applies; 2: never.
+                        0: automatic: from the second lp_cluster(_ex) call on a handle made by
+                        lp_compress(_ex) or lp_graph_from_csr (not on coarse graphs) with at least
+                        2^20 vertices and a largest degree of at least 32 times the average, for
+                        calls that start from singletons with one sub-round (a graph clustered
+                        once would not repay the build); 1: always where it applies, from the
+                        first call; 2: never.
                         lp_refine(_ex), sub-rounds, batches and the gain table always rate on the
                         graph as given. */
 } lp_config;

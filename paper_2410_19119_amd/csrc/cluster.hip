@@ -2989,8 +2989,15 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
   // well, for the edge visits (cut, contraction) on the original graph.
   const int32_t ro_mode = cfg_in ? cfg_in->reorder : 0;
   if (ro_mode < 0 || ro_mode > 2) return LP_EINVAL;
+  // automatic: large graphs with a skewed degree distribution (a graph whose
+  // IDs already follow its geometry, like the cell-ordered RGGs, loses that
+  // locality when renumbered by degree), from the second clustering of a
+  // handle the caller made (the build costs about as much as 15 rounds: a
+  // graph clustered once, like a coarse level, would not repay it)
+  const int32_t calls = init_k == 0 && !batch ? g->cluster_calls.fetch_add(1) + 1 : 0;
+  const bool skewed = g->max_deg >= 32 * (int64_t)((g->two_m + n - 1) / n);
   const bool use_ro = ro_mode != 2 && init_k == 0 && !batch && !use_gt && S == 1 && reorder_applies(g) &&
-                      (ro_mode == 1 || n >= (1 << 20));
+                      (ro_mode == 1 || (n >= (1 << 20) && skewed && !g->stream_mem && (calls >= 2 || g->reord)));
   const Reorder* ro = nullptr;
   int32_t* Cc = nullptr;
   if (use_ro) {

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -46,6 +47,7 @@ struct lp_graph {
   void (*plan_free)(void*) = nullptr;
   mutable std::mutex plan_mu;
   // degree-ordered copy for the rating kernels (reorder.h), built on first use
+  mutable std::atomic<int32_t> cluster_calls{0};  // lp_cluster(_ex) calls on this handle
   mutable void* reord = nullptr;
   mutable void (*reord_free)(void*) = nullptr;
   mutable std::mutex reord_mu;

@@ -4,7 +4,7 @@ seed 1), in the launch configuration bench.py times. The graph has
 4,157,283,128 adjacency entries (past any signed 32-bit edge index) and
 9.2 GB of code bytes (past any 32-bit byte offset), so the 64-bit edge and
 byte offset paths of compression, rating, contraction and the cut run. Every label and the per-round proposal / move counts against the
-oracle; the cut against the oracle; the coarse graph: the fine-to-coarse map
+oracle, rated on the graph as given and on its degree-ordered copy; the cut against the oracle; the coarse graph: the fine-to-coarse map
 and every coarse vertex weight, the total coarse edge weight (twice the
 cut), and sampled coarse rows plus the 20 heaviest clusters recomputed from
 the definition of the quotient graph."""
@@ -34,10 +34,14 @@ def gpu_run(lp, rmat26, progress):
     t = time.time()
     G = lp.lp_compress(g.n, g.xadj.view(np.int64), g.adjncy)
     lab, st = lp.lp_cluster(G, CAP, ROUNDS, SEED, config=dict(timing=1), stats=True)
+    # rated again on the degree-ordered copy, as bench.py's timed steps are
+    lab_ro, st_ro = lp.lp_cluster(G, CAP, ROUNDS, SEED, config=dict(timing=1, reorder=1), stats=True)
+    same_ro = bool((lab_ro == lab).all().item()) and st_ro.proposals == st.proposals and st_ro.moves == st.moves
+    del lab_ro
     cut = lp.lp_edge_cut(G, lab)
     C, mp = lp.lp_contract(G, lab)
     out = dict(nbytes=G.nbytes, two_m=G.two_m, labels=lab.cpu().numpy(), stats=st, map=mp.cpu().numpy(), cut=cut,
-               cn=C.n)
+               cn=C.n, same_ro=same_ro)
     G.free()
     x, a, w, v = lp.lp_decompress(C)
     out.update(cx=x.cpu().numpy().view(np.uint64), ca=a.cpu().numpy(), cw=w.cpu().numpy(), cv=v.cpu().numpy())
@@ -58,6 +62,7 @@ def test_labels_and_counts_match_oracle(oracle_mod, rmat26, gpu_run, progress):
     st = gpu_run["stats"]
     assert st.rounds_run == len(props)
     assert st.proposals == props and st.moves == moves
+    assert gpu_run["same_ro"]  # the degree-ordered copy gives the same labels and counts
 
 
 def test_cut_matches_oracle(oracle_mod, rmat26, gpu_run):
