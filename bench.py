@@ -508,6 +508,8 @@ def main() -> int:
     ap.add_argument("--no-forms", action="store_true", help="skip the batched and served comparisons")
     ap.add_argument("--cpu-rounds", type=int, default=1, help="oracle rounds timed for the baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the R-MAT scale 24 round rate")
+    ap.add_argument("--no-as-given", action="store_true",
+                    help="skip the rounds rated on the graph as given (profiled runs keep one configuration)")
     ap.add_argument("--batch-graphs", type=int, default=512)
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--serve-pool", type=int, default=24)
@@ -837,12 +839,15 @@ def bench_headline(args) -> dict:
     round_traffic = measured_traffic(ROUND_TRAFFIC_FILE, "round_bytes") if args.workload == "rmat26" else None
 
     # the same rounds rated on the graph as given (no degree-ordered copy)
-    asis = []
-    for _ in range(2):
-        _, st_a = lp.lp_cluster(G, cap, args.rounds, 1, labels=labels, config=dict(timing=1, reorder=2), stats=True)
-        asis += st_a.round_ms
-    t_round_asis = median(asis)
-    log(f"[bench] rounds on the graph as given: median {t_round_asis:.2f} ms")
+    t_round_asis = None
+    if not args.no_as_given:
+        asis = []
+        for _ in range(2):
+            _, st_a = lp.lp_cluster(G, cap, args.rounds, 1, labels=labels, config=dict(timing=1, reorder=2),
+                                    stats=True)
+            asis += st_a.round_ms
+        t_round_asis = median(asis)
+        log(f"[bench] rounds on the graph as given: median {t_round_asis:.2f} ms")
 
     # a1 uncached: the same call with a plan built for it (non-default
     # thresholds that bucket every vertex as the defaults do, except tiles
@@ -935,7 +940,7 @@ def bench_headline(args) -> dict:
         "setup_ms_uncached": round(setup_uncached, 3),
         "first_call_ms": round(first_call_ms, 1),
         "copy_build_ms": round(copy_build_ms, 1),
-        "t_round_ms_median_graph_as_given": round(t_round_asis, 4),
+        "t_round_ms_median_graph_as_given": round(t_round_asis, 4) if t_round_asis else None,
         "step_split_ms": {k: round(1e3 * v / args.steps, 2) for k, v in split.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -2073,28 +2073,43 @@ __global__ __launch_bounds__(kCpThreads) void k_prop_write(int32_t* ptgt, const 
                                                            const uint32_t* boff, int G, uint64_t* keys,
                                                            uint32_t* vals, const uint32_t* done, int reset) {
   __shared__ uint32_t sm[kCpThreads / kWave];
+  __shared__ uint64_t skey[kCpTile];
+  __shared__ uint32_t sval[kCpTile];
   if (*done) return;
   const int64_t base = (int64_t)blockIdx.x * kCpTile + (int64_t)threadIdx.x * kCpItems;
+  int32_t t8[kCpItems];
+  static_assert(kCpItems == 8, "two 16-byte loads per thread");
+  if (base + kCpItems <= n && ((uintptr_t)ptgt & 15u) == 0) {
+    const int4 a = *(const int4*)(ptgt + base), b = *(const int4*)(ptgt + base + 4);
+    t8[0] = a.x, t8[1] = a.y, t8[2] = a.z, t8[3] = a.w, t8[4] = b.x, t8[5] = b.y, t8[6] = b.z, t8[7] = b.w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < kCpItems; ++i) t8[i] = base + i < n ? ptgt[base + i] : -1;
+  }
   uint32_t c = 0;
 #pragma unroll
-  for (int i = 0; i < kCpItems; ++i)
-    if (base + i < n && ptgt[base + i] >= 0) ++c;
+  for (int i = 0; i < kCpItems; ++i) c += t8[i] >= 0 ? 1u : 0u;
   uint32_t tot;
   uint32_t incl = block_incl_scan_add<kCpThreads, uint32_t>(c, sm, &tot);
-  uint32_t o = boff[blockIdx.x] + incl - c;
+  // the block's proposals in vertex order, staged in LDS and written out by
+  // consecutive threads
+  uint32_t o = incl - c;
   const uint64_t dmax = (G >= 64) ? ~0ull : ((1ull << G) - 1);
 #pragma unroll
   for (int i = 0; i < kCpItems; ++i) {
     const int64_t u = base + i;
-    if (u < n) {
-      const int32_t t = ptgt[u];
-      if (t >= 0) {
-        keys[o] = ((uint64_t)(uint32_t)t << G) | (dmax - (uint64_t)pgain[u]);
-        vals[o] = (uint32_t)u;
-        ++o;
-        if (reset) ptgt[u] = -1;
-      }
+    if (t8[i] >= 0) {
+      skey[o] = ((uint64_t)(uint32_t)t8[i] << G) | (dmax - (uint64_t)pgain[u]);
+      sval[o] = (uint32_t)u;
+      ++o;
+      if (reset) ptgt[u] = -1;
     }
+  }
+  __syncthreads();
+  const uint32_t ob = boff[blockIdx.x];
+  for (uint32_t j = threadIdx.x; j < tot; j += kCpThreads) {
+    keys[ob + j] = skey[j];
+    vals[ob + j] = sval[j];
   }
 }
 
