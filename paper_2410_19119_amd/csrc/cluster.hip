@@ -55,6 +55,10 @@ struct RoundCtx {
   const uint64_t* voff;     // records: slice of every fine vertex in its coarse vertex's region
   Rec* rec;                 // records: output, {coarse neighbour or -1, weight} per fine edge
   unsigned long long* cut;  // cut: accumulator of the weights of edges between clusters
+  // records: each vertex's edges to one coarse neighbour as one record with
+  // their summed weight (one of them; the others -1), set where every summed
+  // weighted degree fits 32 bits
+  int32_t rec_sum;
 };
 
 // What an edge visit computes: ratings and proposals, the cut, or the
@@ -204,9 +208,26 @@ __global__ __launch_bounds__(256) void k_rate_lane(RoundCtx x, VDesc vd, int32_t
   const int32_t own_c = x.C[u];
   if constexpr (MODE == kModeRec) {
     Rec* r = x.rec + x.rbase[own_c] + x.voff[u];
+    if (x.rec_sum) {
+      // the first edge to each coarse neighbour carries the sum of the
+      // vertex's edges to it, the others become empty records
 #pragma unroll
-    for (int k = 0; k < kMaxLane; ++k)
-      if (k < d) r[k] = Rec{lab[k] == own_c ? -1 : lab[k], wt[k]};
+      for (int k = 0; k < kMaxLane; ++k) {
+        if (k >= d) continue;
+        const int32_t c = lab[k];
+        bool first = c != own_c;
+#pragma unroll
+        for (int j = 0; j < k; ++j) first &= lab[j] != c;
+        int32_t sum = 0;
+#pragma unroll
+        for (int j = k; j < kMaxLane; ++j) sum += lab[j] == c ? wt[j] : 0;
+        r[k] = first ? Rec{c, sum} : Rec{-1, 0};
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kMaxLane; ++k)
+        if (k < d) r[k] = Rec{lab[k] == own_c ? -1 : lab[k], wt[k]};
+    }
     return;
   }
   const int64_t wu = vweight(x.g, u);
@@ -370,10 +391,13 @@ __device__ __forceinline__ void tile_add(V* vals, uint32_t q, V w) {
 // < 0 skips) into the LDS table, the vertex's slots [base, base + size) given
 // by span(vi): every record's first slot is computed, then the first probes
 // of all records are issued together (independent LDS atomics), then the few
-// that collided walk on.
-template <int ITEMS, typename V, class Span>
+// that collided walk on. With CLAIM, qo[k] receives record k's slot and bit k
+// of *claim is set if record k put its cluster into the table (exactly one
+// record per distinct cluster of a vertex does).
+template <int ITEMS, typename V, class Span, bool CLAIM = false>
 __device__ __forceinline__ void tile_insert_all(int32_t* keys, V* vals, const int32_t* vi, const int32_t* nb,
-                                                const int32_t* wt, Span span) {
+                                                const int32_t* wt, Span span, uint32_t* qo = nullptr,
+                                                uint32_t* claim = nullptr) {
   uint32_t q[ITEMS], b[ITEMS], sz[ITEMS];
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
@@ -386,20 +410,30 @@ __device__ __forceinline__ void tile_insert_all(int32_t* keys, V* vals, const in
     old[k] = kEmpty;
     if (vi[k] >= 0) old[k] = atomicCAS(&keys[q[k]], kEmpty, nb[k]);
   }
+  uint32_t cl = 0;
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     if (vi[k] < 0) continue;
+    bool mine = old[k] == kEmpty;
     if (old[k] != kEmpty && old[k] != nb[k]) {
       uint32_t h = q[k] - b[k];
       while (true) {
         if (++h == sz[k]) h = 0;
         const int32_t o = atomicCAS(&keys[b[k] + h], kEmpty, nb[k]);
-        if (o == kEmpty || o == nb[k]) break;
+        if (o == kEmpty || o == nb[k]) {
+          mine = o == kEmpty;
+          break;
+        }
       }
       q[k] = b[k] + h;
     }
     tile_add<V>(vals, q[k], (V)wt[k]);
+    if constexpr (CLAIM) {
+      qo[k] = q[k];
+      cl |= (mine ? 1u : 0u) << k;
+    }
   }
+  if constexpr (CLAIM) *claim = cl;
 }
 
 // Segmented scan over the workgroup of (head, s, s2): a head restarts the
@@ -786,6 +820,10 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
       __syncthreads();
       const uint32_t Et = sh.ebase[nv];
       const uint32_t St = sh.tbase[nv];
+      auto tspan = [&](int32_t i, uint32_t& b, uint32_t& sz) {
+        b = sh.tbase[i];
+        sz = sh.tbase[i + 1] - b;
+      };
       if constexpr (COMP) {
         // 1. stage the code bytes: four consecutive dwords per thread (one
         // search for their vertex, four independent loads in flight)
@@ -959,12 +997,37 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
         continue;
       }
       if constexpr (MODE == kModeRec) {
+        if (x.rec_sum) {
+          // each vertex's edges summed per coarse neighbour in the vertex's
+          // table: the edge that put a neighbour into the table carries the
+          // sum, the vertex's other edges to it (and to its own coarse
+          // vertex) become empty records
+          __syncthreads();  // numbers consumed: region A becomes the table
+          for (uint32_t q = tid; q < St; q += NT) keys[q] = kEmpty;
+          for (uint32_t q = tid; q < St; q += NT) vals[q] = 0;
+          __syncthreads();
+          int32_t vj[ITEMS];
 #pragma unroll
-        for (int k = 0; k < ITEMS; ++k) {
-          if (vi[k] < 0) continue;
-          const int32_t i = vi[k];
-          const uint32_t loc = e0 + k - sh.ebase[i];
-          x.rec[sh.rb[i] + loc] = Rec{nb[k] == sh.own_c[i] ? -1 : nb[k], wt[k]};
+          for (int k = 0; k < ITEMS; ++k) vj[k] = vi[k] >= 0 && nb[k] != sh.own_c[vi[k]] ? vi[k] : -1;
+          uint32_t qs[ITEMS], claim = 0;
+          tile_insert_all<ITEMS, V, decltype(tspan), true>(keys, vals, vj, nb, wt, tspan, qs, &claim);
+          __syncthreads();
+#pragma unroll
+          for (int k = 0; k < ITEMS; ++k) {
+            if (vi[k] < 0) continue;
+            const int32_t i = vi[k];
+            const uint32_t loc = e0 + k - sh.ebase[i];
+            const bool lead = vj[k] >= 0 && ((claim >> k) & 1u);
+            x.rec[sh.rb[i] + loc] = lead ? Rec{nb[k], (int32_t)vals[qs[k]]} : Rec{-1, 0};
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < ITEMS; ++k) {
+            if (vi[k] < 0) continue;
+            const int32_t i = vi[k];
+            const uint32_t loc = e0 + k - sh.ebase[i];
+            x.rec[sh.rb[i] + loc] = Rec{nb[k] == sh.own_c[i] ? -1 : nb[k], wt[k]};
+          }
         }
         __syncthreads();
         continue;
@@ -975,10 +1038,7 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
       for (uint32_t q = tid; q < St; q += NT) vals[q] = 0;
       __syncthreads();
       // 4. ratings
-      tile_insert_all<ITEMS, V>(keys, vals, vi, nb, wt, [&](int32_t i, uint32_t& b, uint32_t& sz) {
-        b = sh.tbase[i];
-        sz = sh.tbase[i + 1] - b;
-      });
+      tile_insert_all<ITEMS, V>(keys, vals, vi, nb, wt, tspan);
       __syncthreads();
       // 5. selection: one walk over the slots of each vertex; tiles of small
       // vertices use 16-lane groups (four vertices per wavefront at a time)
@@ -1467,6 +1527,32 @@ __global__ __launch_bounds__(Cfg::kThreads) void k_hub_piece(RoundCtx x, HubMeta
           if (vi[k] >= 0 && nb[k] != own) c += (unsigned long long)wt[k];
         c = block_reduce_add<NT, unsigned long long>(c, sh.red_u);
         if (tid == 0 && c) atomicAdd(x.cut, c);
+      } else if (x.rec_sum) {
+        // the piece's edges summed per coarse neighbour in the table (as in
+        // the tiles): the edge that put a neighbour into the table carries
+        // the sum, the others become empty records
+        __syncthreads();  // numbers consumed: region A becomes the table
+        const uint32_t S = tile_slots(Et);
+        for (uint32_t q = tid; q < S; q += NT) keys[q] = kEmpty;
+        for (uint32_t q = tid; q < S; q += NT) vals[q] = 0;
+        __syncthreads();
+        int32_t vj[ITEMS];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) vj[k] = vi[k] >= 0 && nb[k] != own ? vi[k] : -1;
+        uint32_t qs[ITEMS], claim = 0;
+        auto pspan = [&](int32_t, uint32_t& b, uint32_t& sz) {
+          b = 0;
+          sz = S;
+        };
+        tile_insert_all<ITEMS, V, decltype(pspan), true>(keys, vals, vj, nb, wt, pspan, qs, &claim);
+        __syncthreads();
+        Rec* r = x.rec + x.rbase[own] + x.voff[u] + (uint64_t)pj.y * Cfg::kEdges;
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+          if (vi[k] < 0) continue;
+          const bool lead = vj[k] >= 0 && ((claim >> k) & 1u);
+          r[e0 + k] = lead ? Rec{nb[k], (int32_t)vals[qs[k]]} : Rec{-1, 0};
+        }
       } else {
         Rec* r = x.rec + x.rbase[own] + x.voff[u] + (uint64_t)pj.y * Cfg::kEdges;
 #pragma unroll
@@ -2724,6 +2810,7 @@ lp_status visit_edges_mode(const lp_graph* g, const int32_t* C, const uint64_t* 
   x.voff = voff;
   x.rec = rec;
   x.cut = cut;
+  x.rec_sum = MODE == kModeRec && g->max_wdeg <= 0x7FFFFFFFll ? 1 : 0;
   const bool comp = g->compressed;
   if (plan->bn[0] > 0) {
     const VDesc vd = plan->vd(0);

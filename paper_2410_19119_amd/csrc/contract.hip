@@ -22,6 +22,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "decode.h"
 #include "graph.h"
@@ -46,6 +47,9 @@ constexpr uint32_t kMaxHeavyParts = 4096;
 constexpr uint32_t kHeavySample = 2048;  // records sampled per heavy cluster for the partition splitters
 constexpr int kLightThreads = 256;
 constexpr int kReduceThreads = 256;
+constexpr uint64_t kBigTask = 16384;  // records of a task reduced by the wide configuration
+constexpr int kBigThreads = 1024;
+constexpr uint32_t kBigTable = 8192;
 
 
 // ------------------------------------------------------------- setup -----
@@ -670,37 +674,42 @@ __global__ __launch_bounds__(256) void k_heavy_scatter(AggArgs A, Heavy hv, int3
   }
 }
 
+template <int NT>
 struct ReduceSmem {
-  int32_t scan[kReduceThreads / kWave];
-  uint32_t red[2 * (kReduceThreads / kWave)];
+  int32_t scan[NT / kWave];
+  uint32_t red[2 * (NT / kWave)];
   uint32_t distinct;
   uint32_t overflow;
   uint32_t bcnt[kBucketBins];
 };
 
-// One workgroup per (cluster, partition): aggregate the partition's records
-// in LDS over coarse-ID windows (a window whose distinct count exceeds half
-// the table is halved and retried), emitting each window sorted. The table
-// is sized by the task's record count.
-template <typename V>
-__global__ __launch_bounds__(kReduceThreads) void k_heavy_reduce(AggArgs A, Heavy hv, int32_t ntasks) {
+// One workgroup of NT threads per (cluster, partition): aggregate the
+// partition's records in an LDS table of TABLE entries over coarse-ID windows
+// (a window whose distinct count exceeds half the table is halved and
+// retried), emitting each window sorted. The table is sized by the task's
+// record count. With `list`, the workgroups take the listed tasks; without,
+// every task of at most max_rec records (larger ones are listed for the wide
+// configuration).
+template <int NT, uint32_t TABLE, typename V>
+__global__ __launch_bounds__(NT) void k_heavy_reduce(AggArgs A, Heavy hv, const int32_t* list, int32_t ntasks,
+                                                     uint64_t max_rec) {
   extern __shared__ __align__(16) uint8_t smem_raw[];
-  constexpr int NT = kReduceThreads;
   V* vals = (V*)smem_raw;
-  int32_t* keys = (int32_t*)(smem_raw + (size_t)kHeavyTable * sizeof(V));
-  ReduceSmem& sm = *(ReduceSmem*)(smem_raw + (size_t)kHeavyTable * (4 + sizeof(V)));
+  int32_t* keys = (int32_t*)(smem_raw + (size_t)TABLE * sizeof(V));
+  ReduceSmem<NT>& sm = *(ReduceSmem<NT>*)(smem_raw + (size_t)TABLE * (4 + sizeof(V)));
   const int tid = threadIdx.x;
-  const uint64_t nc = (uint64_t)A.nc;
-  for (int64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
+  for (int64_t i = blockIdx.x; i < ntasks; i += gridDim.x) {
+    const int64_t t = list ? (int64_t)list[i] : i;
+    const uint64_t obase = hv.tcnt[t];
+    const uint64_t nrec = hv.tcnt[t + 1] - obase;
+    if (!list && nrec > max_rec) continue;
     const int2 task = hv.tasks[t];
     const int32_t h = task.x;
     const uint32_t p = (uint32_t)task.y;
     const int32_t* bnd = hv.bnd + hv.tbase[h] + h;
     const uint64_t lo_p = (uint64_t)bnd[p], hi_p = (uint64_t)bnd[p + 1];
-    const uint64_t obase = hv.tcnt[t];
-    const uint64_t nrec = hv.tcnt[t + 1] - obase;
     const uint32_t logc =
-        min(ceil_log2(kHeavyTable), max(6u, ceil_log2((uint32_t)std::min<uint64_t>(2 * nrec + 2, kHeavyTable))));
+        min(ceil_log2(TABLE), max(6u, ceil_log2((uint32_t)std::min<uint64_t>(2 * nrec + 2, TABLE))));
     const uint32_t tcap = 1u << logc, mask = tcap - 1, shift = 32 - logc;
     const uint32_t limit = tcap / 2;
     const Rec* src = hv.rec2 + obase;
@@ -708,9 +717,9 @@ __global__ __launch_bounds__(kReduceThreads) void k_heavy_reduce(AggArgs A, Heav
     uint64_t lo = lo_p, width = hi_p - lo_p;
     while (lo < hi_p) {
       const uint64_t hi = std::min<uint64_t>(hi_p, lo + width);
-      // a window at most kHeavyTable IDs wide is summed in a direct array
+      // a window at most TABLE IDs wide is summed in a direct array
       // indexed by b - lo: no hashing, no overflow, no sort
-      const bool dense = hi - lo <= kHeavyTable;
+      const bool dense = hi - lo <= TABLE;
       if (dense) {
         for (uint32_t q = tid; q < (uint32_t)(hi - lo); q += NT) vals[q] = 0;
       } else {
@@ -724,35 +733,69 @@ __global__ __launch_bounds__(kReduceThreads) void k_heavy_reduce(AggArgs A, Heav
         sm.overflow = 0;
       }
       __syncthreads();
-      for (uint64_t j = tid; j < nrec; j += NT) {
-        const Rec x = src[j];
-        if ((uint64_t)x.b >= lo && (uint64_t)x.b < hi) {
-          if (dense)
-            tbl_val_add(&vals[(uint64_t)x.b - lo], (int64_t)x.w);
-          else
-            tbl_add_guarded(keys, vals, mask, shift, x.b, (int64_t)x.w, limit, &sm.distinct, &sm.overflow,
-                            2 * nrec + 2 > tcap);
+      // kHeavyUnroll records in flight per thread; each thread sums a run of
+      // equal coarse IDs in registers and adds it to the table when the ID
+      // changes, so records of one hot neighbour cost few LDS atomics
+      const bool guard = 2 * nrec + 2 > tcap;
+      int32_t rk = -1;
+      int64_t rs = 0;
+      auto flush = [&]() {
+        if (rk < 0) return;
+        if (dense)
+          tbl_val_add(&vals[(uint64_t)rk - lo], rs);
+        else
+          tbl_add_guarded(keys, vals, mask, shift, rk, rs, limit, &sm.distinct, &sm.overflow, guard);
+      };
+      for (uint64_t j0 = 0; j0 < nrec; j0 += (uint64_t)NT * kHeavyUnroll) {
+        Rec x[kHeavyUnroll];
+#pragma unroll
+        for (int u = 0; u < kHeavyUnroll; ++u) {
+          const uint64_t j = j0 + (uint64_t)u * NT + tid;
+          x[u] = j < nrec ? src[j] : Rec{-1, 0};
         }
+#pragma unroll
+        for (int u = 0; u < kHeavyUnroll; ++u) {
+          if ((uint64_t)x[u].b >= lo && (uint64_t)x[u].b < hi) {
+            if (x[u].b == rk) {
+              rs += x[u].w;
+            } else {
+              flush();
+              rk = x[u].b;
+              rs = x[u].w;
+            }
+          }
+        }
+        if (!dense && *(volatile uint32_t*)&sm.overflow) break;
       }
+      flush();
       __syncthreads();
       if (!dense && sm.overflow) {
-        width = std::max<uint64_t>(kHeavyTable, (hi - lo) / 2);
+        width = std::max<uint64_t>(TABLE, (hi - lo) / 2);
         __syncthreads();
         continue;
       }
       Rec* dst = hv.out + obase + written;
       const uint32_t k = dense ? dense_write<NT, V>(vals, (uint32_t)(hi - lo), lo, dst, A.err, sm.scan)
-                               : compact_sort_write<NT, kHeavyTable / NT, V>(keys, vals, tcap, dst, A.err, sm.scan,
+                               : compact_sort_write<NT, TABLE / NT, V>(keys, vals, tcap, dst, A.err, sm.scan,
                                                                              (unsigned long long*)smem_raw, sm.bcnt,
                                                                              sm.red);
       written += k;
+      // the next window keeps the width that fitted, twice as wide when it
+      // used under a quarter of the table
+      width = (hi - lo) * (k < limit / 4 ? 2 : 1);
       lo = hi;
-      width = hi_p - lo;  // try the rest of the partition in one window again
       __syncthreads();
     }
     if (tid == 0) hv.tdeg[t] = written;
     __syncthreads();
   }
+}
+
+// Tasks of more than thr records, in any order (they go to the wide
+// reduction configuration).
+__global__ void k_heavy_big(const uint64_t* tcnt, int32_t T, uint64_t thr, int32_t* list, uint32_t* cnt) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < T; t += (int64_t)gridDim.x * blockDim.x)
+    if (tcnt[t + 1] - tcnt[t] > thr) list[atomicAdd(cnt, 1u)] = (int32_t)t;
 }
 
 __global__ void k_heavy_cdeg(Heavy hv, int32_t H, uint64_t* cdeg) {
@@ -902,6 +945,71 @@ lp_status launch_light(const AggArgs& A, const int32_t* list, uint32_t cnt, uint
   return last_error();
 }
 
+template <int NT, uint32_t TABLE, typename V>
+lp_status launch_reduce(const AggArgs& A, const Heavy& hv, const int32_t* list, int32_t ntasks, uint64_t max_rec,
+                        hipStream_t s) {
+  const size_t bytes = (size_t)TABLE * (4 + sizeof(V)) + sizeof(ReduceSmem<NT>);
+  auto k = k_heavy_reduce<NT, TABLE, V>;
+  LP_CHECK(set_lds(k, bytes));
+  // the listed tasks are few and long: at most as many workgroups as fit
+  const uint32_t grid = list ? (uint32_t)std::min<int64_t>(ntasks, 2048) : grid_for(ntasks, 1, 1u << 20);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(NT), bytes, s, A, hv, list, ntasks, max_rec);
+  return last_error();
+}
+
+// Diagnostics of the heavy path (LPGPU_DEBUG): reduction time, the spread of
+// records over tasks, the largest tasks with their ID width and distinct
+// count. Synchronises the stream.
+void heavy_debug(const Heavy& hv, int32_t H, int32_t T, uint32_t nbig, hipEvent_t* ev, hipStream_t s) {
+  (void)hipEventRecord(ev[2], s);
+  std::vector<uint64_t> tc((size_t)T + 1), td((size_t)T);
+  std::vector<int2> tk((size_t)T);
+  std::vector<int32_t> bnd((size_t)T + H), parts((size_t)H);
+  std::vector<uint32_t> tb((size_t)H + 1);
+  (void)hipMemcpyAsync(tc.data(), hv.tcnt, tc.size() * 8, hipMemcpyDeviceToHost, s);
+  (void)hipMemcpyAsync(td.data(), hv.tdeg, td.size() * 8, hipMemcpyDeviceToHost, s);
+  (void)hipMemcpyAsync(tk.data(), hv.tasks, tk.size() * sizeof(int2), hipMemcpyDeviceToHost, s);
+  (void)hipMemcpyAsync(bnd.data(), hv.bnd, bnd.size() * 4, hipMemcpyDeviceToHost, s);
+  (void)hipMemcpyAsync(parts.data(), hv.parts, parts.size() * 4, hipMemcpyDeviceToHost, s);
+  (void)hipMemcpyAsync(tb.data(), hv.tbase, tb.size() * 4, hipMemcpyDeviceToHost, s);
+  (void)hipStreamSynchronize(s);
+  float ms = 0.f, ms_big = 0.f;
+  (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+  (void)hipEventElapsedTime(&ms_big, ev[1], ev[2]);
+  for (int i = 0; i < 3; ++i) (void)hipEventDestroy(ev[i]);
+  std::vector<uint64_t> nr((size_t)T);
+  uint64_t tot = 0, big = 0, bigrec = 0, huge = 0, hugerec = 0, single = 0, singlerec = 0, dist = 0;
+  for (int32_t t = 0; t < T; ++t) {
+    nr[t] = tc[t + 1] - tc[t];
+    tot += nr[t];
+    dist += td[t];
+    if (nr[t] > 2048) big++, bigrec += nr[t];
+    if (nr[t] > 65536) huge++, hugerec += nr[t];
+    const int32_t h = tk[t].x, p = tk[t].y;
+    const int32_t* b = bnd.data() + tb[h] + h;
+    if (b[p + 1] - b[p] == 1) single++, singlerec += nr[t];
+  }
+  int32_t capped = 0;
+  for (int32_t h = 0; h < H; ++h) capped += parts[h] == (int32_t)kMaxHeavyParts;
+  std::vector<int32_t> ord((size_t)T);
+  for (int32_t t = 0; t < T; ++t) ord[t] = t;
+  const int32_t top = std::min<int32_t>(T, 8);
+  std::partial_sort(ord.begin(), ord.begin() + top, ord.end(), [&](int32_t a, int32_t b) { return nr[a] > nr[b]; });
+  fprintf(stderr,
+          "[lpgpu] heavy reduce %.3f ms, %u large tasks %.3f ms: tasks %d records %llu distinct %llu; >2048: %llu "
+          "tasks %llu records; >65536: %llu tasks %llu records; single-ID tasks %llu with %llu records; clusters at "
+          "the part cap %d\n",
+          ms, nbig, ms_big, T, (unsigned long long)tot, (unsigned long long)dist, (unsigned long long)big,
+          (unsigned long long)bigrec, (unsigned long long)huge, (unsigned long long)hugerec,
+          (unsigned long long)single, (unsigned long long)singlerec, capped);
+  for (int32_t i = 0; i < top; ++i) {
+    const int32_t t = ord[i], h = tk[t].x, p = tk[t].y;
+    const int32_t* b = bnd.data() + tb[h] + h;
+    fprintf(stderr, "[lpgpu]   task %d: cluster %d part %d/%d records %llu distinct %llu ids [%d, %d)\n", t, h, p,
+            parts[h], (unsigned long long)nr[t], (unsigned long long)td[t], b[p], b[p + 1]);
+  }
+}
+
 // Heavy clusters: metadata, partitioning, counts, reduction. Fills the coarse
 // degrees of heavy clusters and leaves what placement needs in *hv_out.
 // rec2 has the layout of the record buffer.
@@ -961,30 +1069,41 @@ lp_status contract_heavy(const AggArgs& A, const int32_t* hl, int32_t H, Rec* re
   hipLaunchKernelGGL(k_heavy_count, dim3(grid_for((int64_t)T, 4, 65536)), dim3(256), 0, s, hv, T);
   LP_CHECK_LAUNCH();
   LP_CHECK(scan_exclusive_u64(tcnt, tcnt, (int64_t)T + 1, &tot[2], sc));
+  int32_t* big = sc.alloc<int32_t>((size_t)T + 1);
+  if (!big) return LP_ENOMEM;
+  LP_CHECK_HIP(hipMemsetAsync(tot32 + 2, 0, 4, s));
+  hipLaunchKernelGGL(k_heavy_big, dim3(grid_for(T, 256, 4096)), dim3(256), 0, s, tcnt, T, (uint64_t)kBigTask, big,
+                     tot32 + 2);
+  LP_CHECK_LAUNCH();
   if (NCH > 0) {
     hipLaunchKernelGGL(k_heavy_scatter, dim3(grid_for(NCH, 1, 1u << 20)), dim3(256), 0, s, A, hv, NCH);
     LP_CHECK_LAUNCH();
   }
   uint64_t nout = 0;
+  uint32_t nbig = 0;
   LP_CHECK_HIP(hipMemcpyAsync(&nout, tot + 2, 8, hipMemcpyDeviceToHost, s));
+  LP_CHECK_HIP(hipMemcpyAsync(&nbig, tot32 + 2, 4, hipMemcpyDeviceToHost, s));
   LP_CHECK_HIP(hipStreamSynchronize(s));
-  if (getenv("LPGPU_DEBUG"))
+  const bool debug = getenv("LPGPU_DEBUG") != nullptr;
+  if (debug)
     fprintf(stderr, "[lpgpu] contract heavy: clusters %d chunks %d tasks %d records %llu\n", H, NCH, T,
             (unsigned long long)nout);
   hv.out = sc.alloc<Rec>(nout);
   if (sc.failed) return LP_ENOMEM;
-  if (narrow) {
-    const size_t rbytes = (size_t)kHeavyTable * 8 + sizeof(ReduceSmem);
-    LP_CHECK(set_lds(k_heavy_reduce<uint32_t>, rbytes));
-    hipLaunchKernelGGL(k_heavy_reduce<uint32_t>, dim3(grid_for(T, 1, 1u << 20)), dim3(kReduceThreads), rbytes, s, A,
-                       hv, T);
-  } else {
-    const size_t rbytes = (size_t)kHeavyTable * 12 + sizeof(ReduceSmem);
-    LP_CHECK(set_lds(k_heavy_reduce<int64_t>, rbytes));
-    hipLaunchKernelGGL(k_heavy_reduce<int64_t>, dim3(grid_for(T, 1, 1u << 20)), dim3(kReduceThreads), rbytes, s, A,
-                       hv, T);
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  if (debug) {
+    for (int i = 0; i < 3; ++i) (void)hipEventCreate(&ev[i]);
+    (void)hipEventRecord(ev[0], s);
   }
-  LP_CHECK_LAUNCH();
+  // tasks of up to kBigTask records by 256-thread workgroups; the larger
+  // ones (partitions of the largest clusters, or many records of few coarse
+  // neighbours) by 1024-thread workgroups with four times the table
+  if (narrow) LP_CHECK((launch_reduce<kReduceThreads, kHeavyTable, uint32_t>(A, hv, nullptr, T, kBigTask, s)));
+  else LP_CHECK((launch_reduce<kReduceThreads, kHeavyTable, int64_t>(A, hv, nullptr, T, kBigTask, s)));
+  if (debug) (void)hipEventRecord(ev[1], s);
+  if (nbig && narrow) LP_CHECK((launch_reduce<kBigThreads, kBigTable, uint32_t>(A, hv, big, (int32_t)nbig, 0, s)));
+  else if (nbig) LP_CHECK((launch_reduce<kBigThreads, kBigTable, int64_t>(A, hv, big, (int32_t)nbig, 0, s)));
+  if (debug) heavy_debug(hv, H, T, nbig, ev, s);
   hipLaunchKernelGGL(k_heavy_cdeg, dim3(grid_for(H, 256, 4096)), dim3(256), 0, s, hv, H, A.cdeg);
   LP_CHECK_LAUNCH();
   uint64_t* tscan = sc.alloc<uint64_t>((size_t)T + 1);

@@ -255,6 +255,54 @@ def test_contract_errors(lp, synth_mod):
     assert e.value.status == lp.LP_EINVAL
 
 
+@pytest.mark.parametrize("compressed", [True, False])
+def test_contract_wide_weighted_degrees(lp, oracle_mod, synth_mod, compressed):
+    # a centre whose summed weight exceeds 2^31 (records keep one per edge,
+    # no per-vertex sums) next to low-degree vertices, leaves grouped in
+    # threes so every coarse edge weight still fits 32 bits; also a hub
+    # wider than the whole-hub limit
+    k = 40000
+    edges = [(0, 1 + j) for j in range(k)] + [(1 + j, 2 + j) for j in range(k - 1)]
+    w = [2**29 + (j * 7919) % 1000 for j in range(k)] + [1 + j % 5 for j in range(k - 1)]
+    g = synth_mod.from_edges(k + 1, edges, w)
+    lab = np.concatenate([[0], 1 + 3 * (np.arange(k) // 3)]).astype(np.int32)
+    cg, mp = oracle_mod.contract(g, lab)
+    C, M = lp.lp_contract(_gpu_graph(lp, g, compressed), lab)
+    x, a, w_, v = lp.lp_decompress(C)
+    assert np.array_equal(_np(M), mp)
+    assert np.array_equal(_np(x).view(np.uint64), cg.xadj)
+    assert np.array_equal(_np(a), cg.adjncy) and np.array_equal(_np(w_), cg.adjwgt)
+
+
+def _hot_cluster(synth_mod):
+    # cluster A (10^6 vertices, label 0) joined to both vertices of cluster B
+    # and to 8 of 200000 singleton clusters C each: 10^7 records in A, so its
+    # partitions are as many as the splitter sample allows (about 4900
+    # records, over 1024 distinct: several windows), and the partition of B's
+    # coarse vertex holds its 10^6 summed records plus the spread ones that
+    # follow in ID order (over 16384 records and 4096 distinct: the wide
+    # reduction with its own window retries)
+    na, nb, nc = 1_000_000, 2, 200_000
+    a = np.arange(na, dtype=np.int64)
+    e = [np.stack([a, np.full(na, na + j, np.int64)], 1) for j in range(nb)]
+    e += [np.stack([a, na + nb + (7 * a + 25_000 * k) % nc], 1) for k in range(8)]
+    g = synth_mod.from_edges(na + nb + nc, np.concatenate(e))
+    lab = np.concatenate([np.zeros(na), np.full(nb, na), na + nb + np.arange(nc)]).astype(np.int32)
+    return g, lab
+
+
+@pytest.mark.parametrize("compressed", [True, False])
+def test_contract_hot_neighbour_and_wide_reduction(lp, oracle_mod, synth_mod, compressed):
+    g, lab = _hot_cluster(synth_mod)
+    cg, mp = oracle_mod.contract(g, lab)
+    C, M = lp.lp_contract(_gpu_graph(lp, g, compressed), lab)
+    x, a, w, v = lp.lp_decompress(C)
+    assert np.array_equal(_np(M), mp)
+    assert np.array_equal(_np(x).view(np.uint64), cg.xadj)
+    assert np.array_equal(_np(a), cg.adjncy) and np.array_equal(_np(w), cg.adjwgt)
+    assert np.array_equal(_np(v), cg.vwgt)
+
+
 def test_cut_matches_oracle(lp, oracle_mod, graphs):
     for name in ("rgg2d-16k", "rmat-s12-weighted", "star-10001-w"):
         g = graphs[name]
