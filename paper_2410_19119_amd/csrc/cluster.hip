@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void k_rate_lane(RoundCtx x, VDesc vd, int32_t
   }
   const int32_t own_c = x.C[u];
   if constexpr (MODE == kModeRec) {
-    Rec* r = x.rec + x.rbase[own_c] + x.voff[u];
+    Rec* r = x.rec + x.rbase[own_c] + x.voff[prop_slot(x, u)];
     if (x.rec_sum) {
       // the first edge to each coarse neighbour carries the sum of the
       // vertex's edges to it, the others become empty records
@@ -782,7 +782,7 @@ __global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd,
         sh.own_c[tid] = x.C[u];
         sh.wu[tid] = x.g.vwgt ? x.g.vwgt[u] : 1;
         sh.pos[tid] = pos;
-        if constexpr (MODE == kModeRec) sh.rb[tid] = x.rbase[sh.own_c[tid]] + x.voff[u];
+        if constexpr (MODE == kModeRec) sh.rb[tid] = x.rbase[sh.own_c[tid]] + x.voff[prop_slot(x, u)];
         if constexpr (COMP) {
           const uint32_t len = vd.len[t0 + tid];
           const uint32_t pre = (uint32_t)(pos & 3u);
@@ -1546,7 +1546,7 @@ __global__ __launch_bounds__(Cfg::kThreads) void k_hub_piece(RoundCtx x, HubMeta
         };
         tile_insert_all<ITEMS, V, decltype(pspan), true>(keys, vals, vj, nb, wt, pspan, qs, &claim);
         __syncthreads();
-        Rec* r = x.rec + x.rbase[own] + x.voff[u] + (uint64_t)pj.y * Cfg::kEdges;
+        Rec* r = x.rec + x.rbase[own] + x.voff[prop_slot(x, u)] + (uint64_t)pj.y * Cfg::kEdges;
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
           if (vi[k] < 0) continue;
@@ -1554,7 +1554,7 @@ __global__ __launch_bounds__(Cfg::kThreads) void k_hub_piece(RoundCtx x, HubMeta
           r[e0 + k] = lead ? Rec{nb[k], (int32_t)vals[qs[k]]} : Rec{-1, 0};
         }
       } else {
-        Rec* r = x.rec + x.rbase[own] + x.voff[u] + (uint64_t)pj.y * Cfg::kEdges;
+        Rec* r = x.rec + x.rbase[own] + x.voff[prop_slot(x, u)] + (uint64_t)pj.y * Cfg::kEdges;
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k)
           if (vi[k] >= 0) r[e0 + k] = Rec{nb[k] == own ? -1 : nb[k], wt[k]};
@@ -2773,6 +2773,12 @@ void plan_delete(void* p) { delete (Plan*)p; }
 lp_status get_plan(const lp_graph* g, int32_t t_lane, int32_t t_tile, int32_t t_block, int32_t hub_part,
                    hipStream_t s, const Plan** out, std::unique_ptr<Plan>& tmp);
 
+// Labels of the degree-ordered copy: vertex i of the copy is vertex orig[i].
+__global__ void k_permute_labels(int32_t n, const int32_t* orig, const int32_t* C, int32_t* Cp) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    Cp[i] = C[orig[i]];
+}
+
 __global__ void k_zero_u32(uint32_t* a, int32_t n) {
   for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = 0;
 }
@@ -2783,9 +2789,25 @@ __global__ void k_zero_u32(uint32_t* a, int32_t n) {
 // With `counters` given (32 words of the caller's memory), the visit
 // allocates nothing: it uses the plan the handle already holds (LP_EINVAL if
 // no earlier call built it) and those counters instead of scratch.
+//
+// A handle whose degree-ordered copy exists (built by an earlier clustering
+// call) is visited on the copy, whose gathers touch fewer lines: the labels
+// (map) are permuted to the copy's numbering, and records still go to the
+// slices of the original vertices. The allocation-free visit keeps to the
+// graph as given.
 template <int MODE>
 lp_status visit_edges_mode(const lp_graph* g, const int32_t* C, const uint64_t* rbase, const uint64_t* voff, Rec* rec,
                            unsigned long long* cut, hipStream_t s, uint32_t* counters = nullptr) {
+  Scratch sc(s);
+  const Reorder* ro = counters ? nullptr : existing_reorder(g);
+  if (ro) {
+    int32_t* Cp = sc.alloc<int32_t>(g->n);
+    if (!Cp) return LP_ENOMEM;
+    hipLaunchKernelGGL(k_permute_labels, dim3(grid_for(g->n, 256, 65536)), dim3(256), 0, s, g->n, ro->orig, C, Cp);
+    LP_CHECK_LAUNCH();
+    C = Cp;
+    g = ro->g;
+  }
   const Plan* plan = nullptr;
   std::unique_ptr<Plan> tmp;
   if (counters) {
@@ -2795,7 +2817,6 @@ lp_status visit_edges_mode(const lp_graph* g, const int32_t* C, const uint64_t* 
   } else {
     LP_CHECK(get_plan(g, 16, kTileMaxDeg, TileLarge::kEdges, kDefaultHubPart, s, &plan, tmp));
   }
-  Scratch sc(s);
   // zero[0]: the round's "done" flag (never set here); zero[8..32): hand-out
   // counters of the small tiles, the large tiles and the pieces
   uint32_t* zero = counters ? counters : sc.alloc<uint32_t>(32);
@@ -2810,6 +2831,7 @@ lp_status visit_edges_mode(const lp_graph* g, const int32_t* C, const uint64_t* 
   x.voff = voff;
   x.rec = rec;
   x.cut = cut;
+  x.pmap = ro ? ro->orig : nullptr;
   x.rec_sum = MODE == kModeRec && g->max_wdeg <= 0x7FFFFFFFll ? 1 : 0;
   const bool comp = g->compressed;
   if (plan->bn[0] > 0) {

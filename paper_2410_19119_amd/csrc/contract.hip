@@ -39,7 +39,8 @@ constexpr uint32_t kErrLabel = 1, kErrOverflow = 2, kErrFormat = 4;
 constexpr uint32_t kClassWave = 256;     // records per wavefront-cluster
 constexpr uint32_t kClassBlockS = 1024;  // records per workgroup-cluster, small table
 constexpr uint32_t kClassBlockL = 2048;  // records per workgroup-cluster, large table
-constexpr uint32_t kHeavyChunk = 16384;  // records per partitioning chunk
+constexpr uint32_t kHeavyChunk = 16384;  // records per partitioning chunk (at least)
+constexpr uint32_t kMaxChunks = 4096;    // chunks per heavy cluster (at most: larger chunks beyond)
 constexpr int kHeavyUnroll = 8;          // records in flight per thread while partitioning
 constexpr uint32_t kHeavyTable = 2048;   // LDS entries of a heavy (cluster, partition) task
 constexpr uint32_t kHeavyPart = 896;     // records per heavy partition (target; below kHeavyTable / 2)
@@ -508,13 +509,21 @@ struct Heavy {
   int32_t* bnd;             // P + 1 coarse-ID boundaries per heavy cluster (at tbase[h] + h)
 };
 
+// Records per partitioning chunk of a heavy cluster of d records: at least
+// kHeavyChunk, and few enough chunks that the (chunk, partition) count table
+// of a cluster stays within kMaxChunks rows.
+__host__ __device__ inline uint64_t chunk_size(uint64_t d) {
+  return std::max<uint64_t>(kHeavyChunk, (d + kMaxChunks - 1) / kMaxChunks);
+}
+
 __global__ void k_heavy_meta(const int32_t* hl, int32_t H, const unsigned long long* dsum, int32_t nc, int32_t* parts,
                              uint32_t* ccount, uint32_t* pcount, uint64_t* tabcount) {
   for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < H; h += (int64_t)gridDim.x * blockDim.x) {
     const int32_t a = hl[h];
     const uint64_t d = dsum[a];
     const uint32_t P = (uint32_t)std::min<uint64_t>(kMaxHeavyParts, std::max<uint64_t>(1, (d + kHeavyPart - 1) / kHeavyPart));
-    const uint32_t nch = (uint32_t)((d + kHeavyChunk - 1) / kHeavyChunk);
+    const uint64_t csz = chunk_size(d);
+    const uint32_t nch = (uint32_t)((d + csz - 1) / csz);
     parts[h] = (int32_t)P;
     pcount[h] = P;
     ccount[h] = nch;
@@ -531,9 +540,12 @@ __global__ void k_heavy_lists(int32_t H, const int32_t* parts, const uint32_t* c
 }
 
 // Partition splitters of every heavy cluster: a sample of up to kHeavySample
-// records, 256 per partition (evenly spaced over the cluster's records), is sorted and cut at P
-// quantiles, so the partitions hold about equal numbers of records however
-// skewed the coarse IDs are. Partition p holds IDs [bnd[p], bnd[p+1]).
+// records, 256 per partition (evenly spaced over the cluster's records), is
+// sorted and cut at quantiles, so the partitions hold about equal numbers of
+// records however skewed the coarse IDs are. Only records with a coarse
+// neighbour count: their number is estimated from the sample, and
+// partitions beyond about one per kHeavyPart of them stay empty. Partition p
+// holds IDs [bnd[p], bnd[p+1]).
 __global__ __launch_bounds__(256) void k_heavy_splitters(AggArgs A, Heavy hv, int32_t H) {
   __shared__ unsigned long long sa[kHeavySample], sb[kHeavySample];
   __shared__ int32_t scan[4];
@@ -555,11 +567,14 @@ __global__ __launch_bounds__(256) void k_heavy_splitters(AggArgs A, Heavy hv, in
     (void)block_incl_scan_add<256, int32_t>(valid, scan, &V);
     __syncthreads();
     const unsigned long long* srt = lds_sort_u64<256>(sa, sb, S);
+    // about kHeavyPart records with a coarse neighbour per partition
+    const uint64_t want = ((uint64_t)V * d + (uint64_t)S * kHeavyPart - 1) / ((uint64_t)S * kHeavyPart);
+    const uint32_t Pe = (uint32_t)std::min<uint64_t>(P, std::max<uint64_t>(1, want));
     for (uint32_t p = threadIdx.x; p <= P; p += 256) {
       int32_t v;
       if (p == 0) v = 0;
-      else if (p == P || V == 0) v = A.nc;
-      else v = (int32_t)(srt[(uint64_t)p * V / P] >> 32);
+      else if (p >= Pe || V == 0) v = A.nc;
+      else v = (int32_t)(srt[(uint64_t)p * V / Pe] >> 32);
       bnd[p] = v;
     }
     __syncthreads();
@@ -587,8 +602,9 @@ __global__ __launch_bounds__(256) void k_heavy_hist(AggArgs A, Heavy hv, int32_t
     const int32_t h = ch.x;
     const int32_t a = hv.clusters[h];
     const uint32_t P = (uint32_t)hv.parts[h];
-    const uint64_t off = (uint64_t)ch.y * kHeavyChunk;
-    const uint32_t len = (uint32_t)std::min<uint64_t>(kHeavyChunk, A.dsum[a] - off);
+    const uint64_t d = A.dsum[a], csz = chunk_size(d);
+    const uint64_t off = (uint64_t)ch.y * csz;
+    const uint32_t len = (uint32_t)std::min<uint64_t>(csz, d - off);
     const Rec* src = A.rec + A.rbase[a] + off;
     const int32_t* bnd = hv.bnd + hv.tbase[h] + h;
     for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) hist[j] = 0;
@@ -650,8 +666,9 @@ __global__ __launch_bounds__(256) void k_heavy_scatter(AggArgs A, Heavy hv, int3
     const int32_t h = ch.x;
     const int32_t a = hv.clusters[h];
     const uint32_t P = (uint32_t)hv.parts[h];
-    const uint64_t off = (uint64_t)ch.y * kHeavyChunk;
-    const uint32_t len = (uint32_t)std::min<uint64_t>(kHeavyChunk, A.dsum[a] - off);
+    const uint64_t d = A.dsum[a], csz = chunk_size(d);
+    const uint64_t off = (uint64_t)ch.y * csz;
+    const uint32_t len = (uint32_t)std::min<uint64_t>(csz, d - off);
     const Rec* src = A.rec + A.rbase[a] + off;
     const int32_t* bnd = hv.bnd + hv.tbase[h] + h;
     const uint32_t* tab = hv.ctab + hv.pbase[h] + (uint64_t)ch.y * P;
@@ -703,6 +720,10 @@ __global__ __launch_bounds__(NT) void k_heavy_reduce(AggArgs A, Heavy hv, const 
     const uint64_t obase = hv.tcnt[t];
     const uint64_t nrec = hv.tcnt[t + 1] - obase;
     if (!list && nrec > max_rec) continue;
+    if (nrec == 0) {
+      if (tid == 0) hv.tdeg[t] = 0;
+      continue;
+    }
     const int2 task = hv.tasks[t];
     const int32_t h = task.x;
     const uint32_t p = (uint32_t)task.y;
@@ -1223,8 +1244,10 @@ extern "C" lp_status lp_contract(const lp_graph* g, const int32_t* labels, int32
     const int64_t stride = nc;
     int32_t* hlist = lists + 3 * stride;
     uint32_t* nheavy = &ctl->ccount[4];
-    // 32-bit table sums where no coarse edge weight can reach 2^31
-    const bool narrow = !g->weighted && g->two_m < (1ull << 31);
+    // 32-bit table sums where no coarse edge weight can reach 2^31: unit
+    // weights and fewer than 2^32 adjacency entries (a coarse edge counts
+    // fine edges of one direction, at most half of them)
+    const bool narrow = !g->weighted && g->two_m < (1ull << 32);
     if (narrow) {
       st = launch_light<kWave, uint32_t>(A, lists, h.ccount[1], 2 * kClassWave, hlist, nheavy, s);
       if (!st)

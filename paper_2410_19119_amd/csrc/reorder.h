@@ -23,4 +23,7 @@ bool reorder_applies(const lp_graph* g);
 // The handle's copy, built on first use (synchronises s then).
 lp_status get_reorder(const lp_graph* g, hipStream_t s, const Reorder** out);
 
+// The handle's copy if an earlier call built it, else nullptr.
+const Reorder* existing_reorder(const lp_graph* g);
+
 }  // namespace lp

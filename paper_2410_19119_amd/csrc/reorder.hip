@@ -165,4 +165,9 @@ lp_status get_reorder(const lp_graph* g, hipStream_t s, const Reorder** out) {
   return LP_OK;
 }
 
+const Reorder* existing_reorder(const lp_graph* g) {
+  std::lock_guard<std::mutex> lock(g->reord_mu);
+  return (const Reorder*)g->reord;
+}
+
 }  // namespace lp

@@ -450,9 +450,24 @@ def test_degree_ordered_copy_gives_identical_results(lp, oracle_mod, graphs, nam
         lab, st = lp.lp_cluster(G, 64, 4, 11, config=knobs, stats=True)
         assert np.array_equal(_np(lab), exp), knobs
         assert st.rounds_run == ost.rounds_run and st.proposals == ost.proposals and st.moves == ost.moves
-    # the cut and contraction after a reordered clustering run on the graph as given
+    # once the copy exists, the cut and the contraction records visit the
+    # copy (labels permuted to it, records at the original vertices): the
+    # cut, the fine-to-coarse map and the coarse graph equal the oracle's
     lab = lp.lp_cluster(G, 64, 4, 11, config=dict(reorder=1))
     assert lp.lp_edge_cut(G, lab) == oracle_mod.edge_cut(g, exp)
+    try:
+        cg, mp = oracle_mod.contract(g, exp)
+    except OverflowError:  # a coarse edge weight beyond 32 bits: the library reports it too
+        with pytest.raises(lp.LPError) as e:
+            lp.lp_contract(G, lab)
+        assert e.value.status == lp.LP_EOVERFLOW
+        return
+    C, M = lp.lp_contract(G, lab)
+    x, a, w, v = lp.lp_decompress(C)
+    assert np.array_equal(_np(M), mp)
+    assert np.array_equal(_np(x).view(np.uint64), cg.xadj)
+    assert np.array_equal(_np(a), cg.adjncy) and np.array_equal(_np(w), cg.adjwgt)
+    assert np.array_equal(_np(v), cg.vwgt)
 
 
 def test_degree_ordered_copy_giant_hubs(lp, oracle_mod, giant_hubs):
@@ -463,6 +478,13 @@ def test_degree_ordered_copy_giant_hubs(lp, oracle_mod, giant_hubs):
         lab, st = lp.lp_cluster(G, 3000, 4, 21, config=knobs, stats=True)
         assert np.array_equal(_np(lab), exp), knobs
         assert st.proposals == ost.proposals and st.moves == ost.moves
+    # cut and contraction on the copy (hub pieces and whole hubs in record mode)
+    assert lp.lp_edge_cut(G, lab) == oracle_mod.edge_cut(g, exp)
+    cg, mp = oracle_mod.contract(g, exp)
+    C, M = lp.lp_contract(G, lab)
+    x, a, w, v = lp.lp_decompress(C)
+    assert np.array_equal(_np(M), mp) and np.array_equal(_np(x).view(np.uint64), cg.xadj)
+    assert np.array_equal(_np(a), cg.adjncy) and np.array_equal(_np(w), cg.adjwgt)
 
 
 def test_reorder_option_errors(lp, graphs):
