@@ -297,6 +297,15 @@ struct TileCfg {
   static constexpr int kSlots = E + E / 2 + VT;
   static constexpr int kSelGroup = VT > 8 ? kWave : NT;  // threads per selected vertex
 };
+
+// Waves per SIMD a tile kernel is compiled for: the small tiles' rating of a
+// compressed graph is capped at 80 registers, so six workgroups share a CU
+// (as many as their LDS allows) to hide the latency of their gathers and
+// barriers; other instances keep the compiler's choice.
+template <class T, int MODE, bool COMP>
+constexpr int tile_waves_per_eu() {
+  return T::kThreads == 256 && MODE == kModeRate && COMP ? 6 : 1;
+}
 using TileSmall = TileCfg<256, 2048, 80>;
 using TileLarge = TileCfg<512, 4096, 4>;
 constexpr int kTileSeg = 128;  // vertices walked by one thread of the tiling pass
@@ -729,7 +738,8 @@ __device__ __forceinline__ void tile_select(const RoundCtx& x, const int32_t* ke
 }
 
 template <class T, typename V, bool COMP, int MODE = kModeRate, bool ITV = false>
-__global__ __launch_bounds__(T::kThreads) void k_rate_tile(RoundCtx x, VDesc vd, const int32_t* tiles,
+__global__ __launch_bounds__(T::kThreads) __attribute__((amdgpu_waves_per_eu(tile_waves_per_eu<T, MODE, COMP>())))
+void k_rate_tile(RoundCtx x, VDesc vd, const int32_t* tiles,
                                                            const uint32_t* ntiles_p, uint32_t* ctr, TileLayout L) {
   constexpr int NT = T::kThreads, VT = T::kVerts, ITEMS = T::kItems, SG = T::kSelGroup;
   constexpr int NSG = NT / SG;  // selection groups per workgroup
