@@ -699,12 +699,17 @@ def lp_rate(lp, G, cap: int, rounds: int, steps: int, warmup: int, labels=None) 
         lp.lp_cluster(G, cap, rounds, 1, labels=labels, config=cfg)
     torch.cuda.synchronize()
     rms = []
+    ph, nl = {}, {}
     for _ in range(steps):
         _, st = lp.lp_cluster(G, cap, rounds, 1, labels=labels, config=cfg, stats=True)
         rms += st.round_ms
+        for p in ("lane", "tile", "block", "hub", "accept"):
+            ph[p] = ph.get(p, 0.0) + st.phase_ms[p]
+            nl[p] = nl.get(p, 0) + st.phase_launches[p]
     med = median(rms)
     return {"round_ms_median": round(med, 4), "lp_round_edges_per_s": G.two_m / (med / 1e3),
-            "rounds_timed": len(rms)}
+            "rounds_timed": len(rms),
+            "phase_ms_per_round": {p: round(ph[p] / nl[p], 4) for p in ph if nl[p]}}
 
 
 def bench_intervals(args, scale: int = 26) -> dict:

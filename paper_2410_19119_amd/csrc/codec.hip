@@ -71,16 +71,30 @@ __device__ __forceinline__ void block_max2(unsigned long long a, unsigned long l
   }
 }
 
+// The wave-per-vertex kernels below take vertices in order, kCodecVerts at a
+// time from a counter (one per launch): the resident waves then read xadj and
+// adjncy in a window of consecutive vertices that slides over the graph.
+// With a static stride, waves that met high-degree vertices fell behind and
+// the reads spread over the whole adjacency (on R-MAT scale 26, stored in
+// its given order, 20-30x slower than on the same graph numbered by degree).
+constexpr int64_t kCodecVerts = 128;
+constexpr unsigned kCodecGrid = 2048;  // workgroups of 256 threads
+
+__device__ __forceinline__ int64_t next_vertices(unsigned long long* ctr) {
+  uint32_t c = 0;
+  if (lane_id() == 0) c = (uint32_t)atomicAdd(ctr, 1ull);
+  return (int64_t)(uint32_t)__shfl((int)c, 0, kWave) * kCodecVerts;
+}
+
 // One wave per vertex: range / self-loop / weight / order checks, weighted
 // degree and degree maxima.
 __global__ __launch_bounds__(256) void k_validate(CsrIn g, uint32_t* err, unsigned long long* max_wdeg,
-                                                  unsigned long long* max_deg) {
+                                                  unsigned long long* max_deg, unsigned long long* ctr) {
   const int lane = lane_id();
-  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
   uint32_t bad = 0;
   unsigned long long mw = 0, md = 0;
-  for (int64_t u = wid; u < g.n; u += nw) {
+  for (int64_t u0 = next_vertices(ctr); u0 < g.n; u0 = next_vertices(ctr))
+  for (int64_t u = u0; u < min(g.n, u0 + kCodecVerts); ++u) {
     const uint64_t b = g.xadj[u], e = g.xadj[u + 1];
     if (e < b) {
       bad |= kErrXadj;
@@ -124,11 +138,10 @@ __global__ __launch_bounds__(256) void k_vwgt_check(const int32_t* vwgt, int32_t
 }
 
 // Record size of each vertex (wave per vertex).
-__global__ __launch_bounds__(256) void k_record_size(CsrIn g, uint64_t* size) {
+__global__ __launch_bounds__(256) void k_record_size(CsrIn g, uint64_t* size, unsigned long long* ctr) {
   const int lane = lane_id();
-  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  for (int64_t u = wid; u < g.n; u += nw) {
+  for (int64_t u0 = next_vertices(ctr); u0 < g.n; u0 = next_vertices(ctr))
+  for (int64_t u = u0; u < min(g.n, u0 + kCodecVerts); ++u) {
     const uint64_t b = g.xadj[u], e = g.xadj[u + 1];
     const uint64_t d = e - b;
     const uint64_t nch = d > LP_CHUNK_THRESHOLD ? (d + LP_CHUNK_LEN - 1) / LP_CHUNK_LEN : 1;
@@ -151,11 +164,10 @@ __global__ __launch_bounds__(256) void k_record_size(CsrIn g, uint64_t* size) {
 }
 
 // Writes every record at offs[u] (wave per vertex).
-__global__ __launch_bounds__(256) void k_encode(CsrIn g, const uint64_t* offs, uint8_t* out) {
+__global__ __launch_bounds__(256) void k_encode(CsrIn g, const uint64_t* offs, uint8_t* out, unsigned long long* ctr) {
   const int lane = lane_id();
-  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  for (int64_t u = wid; u < g.n; u += nw) {
+  for (int64_t u0 = next_vertices(ctr); u0 < g.n; u0 = next_vertices(ctr))
+  for (int64_t u = u0; u < min(g.n, u0 + kCodecVerts); ++u) {
     const uint64_t b = g.xadj[u], e = g.xadj[u + 1];
     const uint64_t d = e - b;
     const uint64_t nch = d > LP_CHUNK_THRESHOLD ? (d + LP_CHUNK_LEN - 1) / LP_CHUNK_LEN : 1;
@@ -455,12 +467,11 @@ __global__ void k_xadj_from_headers(GraphView g, uint64_t* xadj) {
 }
 
 __global__ __launch_bounds__(256) void k_decode_all(GraphView g, const uint64_t* xadj, int32_t* adjncy,
-                                                    int32_t* adjwgt, uint32_t* err) {
+                                                    int32_t* adjwgt, uint32_t* err, unsigned long long* ctr) {
   __shared__ DecodeSmem<kWave> smem[kWavesPerBlock];
   const int w = threadIdx.x / kWave;
-  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  for (int64_t u = wid; u < g.n; u += nw) {
+  for (int64_t u0 = next_vertices(ctr); u0 < g.n; u0 = next_vertices(ctr))
+  for (int64_t u = u0; u < min((int64_t)g.n, u0 + kCodecVerts); ++u) {
     const uint64_t fe = xadj[u];
     const uint32_t deg = (uint32_t)(xadj[u + 1] - fe);
     if (deg == 0) continue;
@@ -498,14 +509,14 @@ lp_status check_csr(const CsrIn& in, hipStream_t s, uint64_t* two_m, int64_t* ma
   struct Acc {
     uint32_t err;
     uint32_t pad;
-    unsigned long long wdeg, deg, tot;
+    unsigned long long wdeg, deg, tot, ctr;
   };
   Acc* acc = sc.alloc<Acc>(1);
   if (!acc) return LP_ENOMEM;
   LP_CHECK_HIP(hipMemsetAsync(acc, 0, sizeof(Acc), s));
   if (in.n > 0) {
-    hipLaunchKernelGGL(k_validate, dim3(grid_for((int64_t)in.n * kWave, 256, 4096)), dim3(256), 0, s, in,
-                       &acc->err, &acc->wdeg, &acc->deg);
+    hipLaunchKernelGGL(k_validate, dim3(grid_for((int64_t)in.n * kWave, 256, kCodecGrid)), dim3(256), 0, s, in,
+                       &acc->err, &acc->wdeg, &acc->deg, &acc->ctr);
     LP_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_vwgt_check, dim3(grid_for(in.n, 256, 4096)), dim3(256), 0, s, in.vwgt, in.n, &acc->err,
                        &acc->tot);
@@ -592,8 +603,13 @@ static lp_status make_handle(int32_t n, const uint64_t* xadj, const int32_t* adj
     g->intervals = intervals ? 1 : 0;
     uint64_t* size = sc.alloc<uint64_t>((size_t)n + 1);
     uint64_t* total_dev = sc.alloc<uint64_t>(1);
-    if (!size || !total_dev) {
+    unsigned long long* ctr = sc.alloc<unsigned long long>(2);  // hand-out counters of the two passes
+    if (!size || !total_dev || !ctr) {
       st = LP_ENOMEM;
+      break;
+    }
+    if (hipMemsetAsync(ctr, 0, 2 * sizeof(unsigned long long), s) != hipSuccess) {
+      st = LP_EDEVICE;
       break;
     }
     if (hipMalloc((void**)&g->offs, ((size_t)n + 1) * sizeof(uint64_t)) != hipSuccess) {
@@ -604,7 +620,8 @@ static lp_status make_handle(int32_t n, const uint64_t* xadj, const int32_t* adj
       if (intervals)
         hipLaunchKernelGGL(k_record_size_itv, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, in, size);
       else
-        hipLaunchKernelGGL(k_record_size, dim3(grid_for((int64_t)n * kWave, 256, 65536)), dim3(256), 0, s, in, size);
+        hipLaunchKernelGGL(k_record_size, dim3(grid_for((int64_t)n * kWave, 256, kCodecGrid)), dim3(256), 0, s, in,
+                           size, ctr);
       st = last_error();
       if (st) break;
     }
@@ -633,8 +650,8 @@ static lp_status make_handle(int32_t n, const uint64_t* xadj, const int32_t* adj
       if (intervals)
         hipLaunchKernelGGL(k_encode_itv, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, in, g->offs, g->bytes);
       else
-        hipLaunchKernelGGL(k_encode, dim3(grid_for((int64_t)n * kWave, 256, 65536)), dim3(256), 0, s, in, g->offs,
-                           g->bytes);
+        hipLaunchKernelGGL(k_encode, dim3(grid_for((int64_t)n * kWave, 256, kCodecGrid)), dim3(256), 0, s, in,
+                           g->offs, g->bytes, ctr + 1);
       st = last_error();
     }
   } while (0);
@@ -707,9 +724,11 @@ extern "C" lp_status lp_decompress(const lp_graph* g, uint64_t* xadj, int32_t* a
     }
     return LP_OK;
   }
-  uint32_t* err = sc.alloc<uint32_t>(1);
-  if (!err) return LP_ENOMEM;
-  LP_CHECK_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), s));
+  // err, then the hand-out counter of the decode
+  unsigned long long* errc = sc.alloc<unsigned long long>(2);
+  if (!errc) return LP_ENOMEM;
+  uint32_t* err = (uint32_t*)errc;
+  LP_CHECK_HIP(hipMemsetAsync(errc, 0, 2 * sizeof(unsigned long long), s));
   GraphView v = g->view();
   hipLaunchKernelGGL(k_xadj_from_headers, dim3(grid_for((int64_t)g->n + 1, 256, 65536)), dim3(256), 0, s, v, xadj);
   LP_CHECK_LAUNCH();
@@ -718,8 +737,8 @@ extern "C" lp_status lp_decompress(const lp_graph* g, uint64_t* xadj, int32_t* a
       hipLaunchKernelGGL(k_decode_all_itv, dim3(grid_for(g->n, 256, 65536)), dim3(256), 0, s, v, xadj, adjncy, adjwgt,
                          err);
     else
-      hipLaunchKernelGGL(k_decode_all, dim3(grid_for((int64_t)g->n * kWave, 256, 65536)), dim3(256), 0, s, v, xadj,
-                         adjncy, adjwgt, err);
+      hipLaunchKernelGGL(k_decode_all, dim3(grid_for((int64_t)g->n * kWave, 256, kCodecGrid)), dim3(256), 0, s, v,
+                         xadj, adjncy, adjwgt, err, errc + 1);
     LP_CHECK_LAUNCH();
   }
   uint32_t h = 0;
