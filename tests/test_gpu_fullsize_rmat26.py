@@ -7,7 +7,9 @@ byte offset paths of compression, rating, contraction and the cut run. Every lab
 oracle, rated on the graph as given and on its degree-ordered copy; the cut against the oracle; the coarse graph: the fine-to-coarse map
 and every coarse vertex weight, the total coarse edge weight (twice the
 cut), and sampled coarse rows plus the 20 heaviest clusters recomputed from
-the definition of the quotient graph."""
+the definition of the quotient graph; the coarsening loop: its stop rule and
+cap, and the second level's labels against the oracle on that level's
+graph."""
 import time
 
 import numpy as np
@@ -42,6 +44,21 @@ def gpu_run(lp, rmat26, progress):
     C, mp = lp.lp_contract(G, lab)
     out = dict(nbytes=G.nbytes, two_m=G.two_m, labels=lab.cpu().numpy(), stats=st, map=mp.cpu().numpy(), cut=cut,
                cn=C.n, same_ro=same_ro)
+    # the coarsening loop (R-20) as the library runs it: every level's labels,
+    # the coarse sizes, and the second level's graph for the oracle
+    levels, final, n_target, cap = lp.coarsen(G, SEED)
+    out.update(n_target=n_target, cap=cap, level_n=[L.n for L, _, _ in levels], final_n=final.n,
+               level0_labels_equal=bool((levels[0][1] == lab).all().item()))
+    if len(levels) > 1:
+        L1, lab1, _ = levels[1]
+        x1, a1, w1, v1 = lp.lp_decompress(L1)
+        out.update(g1=dict(xadj=x1.cpu().numpy().view(np.uint64), adjncy=a1.cpu().numpy(), adjwgt=w1.cpu().numpy(),
+                           vwgt=v1.cpu().numpy()), labels1=lab1.cpu().numpy())
+        del x1, a1, w1, v1
+    for L, _, _ in levels[1:]:
+        L.free()
+    final.free()
+    del levels
     G.free()
     x, a, w, v = lp.lp_decompress(C)
     out.update(cx=x.cpu().numpy().view(np.uint64), ca=a.cpu().numpy(), cw=w.cpu().numpy(), cv=v.cpu().numpy())
@@ -80,3 +97,27 @@ def test_coarse_graph(rmat26, gpu_run, progress):
     t = time.time()
     k = check_coarse_rows(g, cmap, cn, cx, r["ca"], r["cw"], sample=1500, seed=11)
     progress(f"rmat-s26: {k} coarse rows checked in {time.time() - t:.0f}s")
+
+
+def test_coarsening_loop(oracle_mod, synth_mod, gpu_run, progress):
+    # the stop rule and the level-constant cap of R-20 for n = 2^26 unit
+    # vertices: n_target = min(2^14, max(256, n / 64)) = 16384, cap = 3n / n_target
+    r = gpu_run
+    assert (r["n_target"], r["cap"]) == (16384, CAP)
+    assert r["level0_labels_equal"] and r["level_n"][0] == 1 << 26
+    assert len(r["level_n"]) >= 2 and r["level_n"][1] == r["cn"]
+    # the loop stops at the first level that shrinks by less than 5 % (or
+    # reaches n_target), and not before
+    sizes = r["level_n"] + [r["final_n"]]
+    for k in range(1, len(sizes) - 1):
+        assert 100 * sizes[k] <= 95 * sizes[k - 1] and sizes[k] > 16384
+    assert 100 * sizes[-1] > 95 * sizes[-2] or sizes[-1] <= 16384
+    # level 1 clusters the coarse graph with seed + 1: labels and counts equal
+    # the oracle's on that graph (which test_coarse_graph checks on samples)
+    g1 = synth_mod.Graph(r["level_n"][1], **r["g1"], name="rmat26-level1")
+    t = time.time()
+    exp1, props, moves = oracle_rounds(oracle_mod, g1, CAP, ROUNDS, SEED + 1, progress, "rmat-s26 level 1")
+    progress(f"rmat-s26 level 1: oracle in {time.time() - t:.0f}s")
+    assert np.array_equal(r["labels1"], exp1)
+    assert coarse_map(exp1)[1] == r["final_n"]
+
