@@ -40,7 +40,7 @@ constexpr uint32_t kClassWave = 256;     // records per wavefront-cluster
 constexpr uint32_t kClassBlockS = 1024;  // records per workgroup-cluster, small table
 constexpr uint32_t kClassBlockL = 2048;  // records per workgroup-cluster, large table
 constexpr uint32_t kHeavyChunk = 16384;  // records per partitioning chunk (at least)
-constexpr uint32_t kMaxChunks = 4096;    // chunks per heavy cluster (at most: larger chunks beyond)
+constexpr uint32_t kMaxChunks = 1024;    // chunks per heavy cluster (at most: larger chunks beyond)
 constexpr int kHeavyUnroll = 8;          // records in flight per thread while partitioning
 constexpr uint32_t kHeavyTable = 2048;   // LDS entries of a heavy (cluster, partition) task
 constexpr uint32_t kHeavyPart = 896;     // records per heavy partition (target; below kHeavyTable / 2)
