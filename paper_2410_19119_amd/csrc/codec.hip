@@ -71,30 +71,61 @@ __device__ __forceinline__ void block_max2(unsigned long long a, unsigned long l
   }
 }
 
-// The wave-per-vertex kernels below take vertices in order, kCodecVerts at a
-// time from a counter (one per launch): the resident waves then read xadj and
-// adjncy in a window of consecutive vertices that slides over the graph.
-// With a static stride, waves that met high-degree vertices fell behind and
-// the reads spread over the whole adjacency (on R-MAT scale 26, stored in
-// its given order, 20-30x slower than on the same graph numbered by degree).
-constexpr int64_t kCodecVerts = 128;
+// The wave-per-vertex kernels below take their vertices in blocks, in order,
+// from a counter (one per launch). A vertex u costs its degree plus one, so
+// it starts at key(u) = xadj[u] + u (increasing in u), and block c holds the
+// vertices whose key lies in [c * kCodecWork, (c + 1) * kCodecWork), i.e.
+// vertices blk[c] .. blk[c + 1] - 1: at most kCodecWork vertices, and the
+// adjacency of those plus the rest of the last one. The resident waves then
+// read a window of the adjacency that slides over it, a run of high-degree
+// vertices (a degree-ordered graph starts with one) spreads over as many
+// blocks as its entries fill, and a run of isolated vertices (such a graph
+// ends with one) over as many as its count fills. With a static stride,
+// waves that met high-degree vertices fell behind and the reads spread over
+// the whole adjacency (R-MAT scale 26 in its given order compressed 30x
+// slower than the same graph numbered by degree).
+constexpr uint64_t kCodecWork = 16384;
 constexpr unsigned kCodecGrid = 2048;  // workgroups of 256 threads
 
-__device__ __forceinline__ int64_t next_vertices(unsigned long long* ctr) {
+struct CodecBlocks {
+  const int64_t* blk;        // nb + 1 entries
+  int64_t nb;
+  unsigned long long* ctr;   // hand-out counter (zero before the launch)
+};
+
+// blk[c] = the smallest u with key(u) >= c * kCodecWork (c < nb), blk[nb] =
+// n. xadj must be non-decreasing from 0 (a decrease sets *err and leaves blk
+// incomplete).
+__global__ void k_codec_blocks(const uint64_t* xadj, int64_t n, int64_t nb, int64_t* blk, uint32_t* err) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u <= n; u += (int64_t)gridDim.x * blockDim.x) {
+    if (u > 0 && xadj[u] < xadj[u - 1]) {
+      atomicOr(err, 1u);
+      continue;
+    }
+    const uint64_t hi = xadj[u] + (uint64_t)u;
+    // blocks c with key(u - 1) < c * kCodecWork <= key(u) (u > 0), or c = 0
+    const int64_t c0 = u ? (int64_t)((xadj[u - 1] + (uint64_t)(u - 1)) / kCodecWork) + 1 : 0;
+    const int64_t c1 = min((int64_t)(hi / kCodecWork), nb - 1);
+    for (int64_t c = c0; c <= c1; ++c) blk[c] = u;
+    if (u == n) blk[nb] = n;
+  }
+}
+
+__device__ __forceinline__ int64_t next_block(const CodecBlocks& cb) {
   uint32_t c = 0;
-  if (lane_id() == 0) c = (uint32_t)atomicAdd(ctr, 1ull);
-  return (int64_t)(uint32_t)__shfl((int)c, 0, kWave) * kCodecVerts;
+  if (lane_id() == 0) c = (uint32_t)atomicAdd(cb.ctr, 1ull);
+  return (int64_t)(uint32_t)__shfl((int)c, 0, kWave);
 }
 
 // One wave per vertex: range / self-loop / weight / order checks, weighted
 // degree and degree maxima.
 __global__ __launch_bounds__(256) void k_validate(CsrIn g, uint32_t* err, unsigned long long* max_wdeg,
-                                                  unsigned long long* max_deg, unsigned long long* ctr) {
+                                                  unsigned long long* max_deg, CodecBlocks cb) {
   const int lane = lane_id();
   uint32_t bad = 0;
   unsigned long long mw = 0, md = 0;
-  for (int64_t u0 = next_vertices(ctr); u0 < g.n; u0 = next_vertices(ctr))
-  for (int64_t u = u0; u < min(g.n, u0 + kCodecVerts); ++u) {
+  for (int64_t c = next_block(cb); c < cb.nb; c = next_block(cb))
+  for (int64_t u = cb.blk[c]; u < cb.blk[c + 1]; ++u) {
     const uint64_t b = g.xadj[u], e = g.xadj[u + 1];
     if (e < b) {
       bad |= kErrXadj;
@@ -138,10 +169,10 @@ __global__ __launch_bounds__(256) void k_vwgt_check(const int32_t* vwgt, int32_t
 }
 
 // Record size of each vertex (wave per vertex).
-__global__ __launch_bounds__(256) void k_record_size(CsrIn g, uint64_t* size, unsigned long long* ctr) {
+__global__ __launch_bounds__(256) void k_record_size(CsrIn g, uint64_t* size, CodecBlocks cb) {
   const int lane = lane_id();
-  for (int64_t u0 = next_vertices(ctr); u0 < g.n; u0 = next_vertices(ctr))
-  for (int64_t u = u0; u < min(g.n, u0 + kCodecVerts); ++u) {
+  for (int64_t c = next_block(cb); c < cb.nb; c = next_block(cb))
+  for (int64_t u = cb.blk[c]; u < cb.blk[c + 1]; ++u) {
     const uint64_t b = g.xadj[u], e = g.xadj[u + 1];
     const uint64_t d = e - b;
     const uint64_t nch = d > LP_CHUNK_THRESHOLD ? (d + LP_CHUNK_LEN - 1) / LP_CHUNK_LEN : 1;
@@ -164,10 +195,10 @@ __global__ __launch_bounds__(256) void k_record_size(CsrIn g, uint64_t* size, un
 }
 
 // Writes every record at offs[u] (wave per vertex).
-__global__ __launch_bounds__(256) void k_encode(CsrIn g, const uint64_t* offs, uint8_t* out, unsigned long long* ctr) {
+__global__ __launch_bounds__(256) void k_encode(CsrIn g, const uint64_t* offs, uint8_t* out, CodecBlocks cb) {
   const int lane = lane_id();
-  for (int64_t u0 = next_vertices(ctr); u0 < g.n; u0 = next_vertices(ctr))
-  for (int64_t u = u0; u < min(g.n, u0 + kCodecVerts); ++u) {
+  for (int64_t c = next_block(cb); c < cb.nb; c = next_block(cb))
+  for (int64_t u = cb.blk[c]; u < cb.blk[c + 1]; ++u) {
     const uint64_t b = g.xadj[u], e = g.xadj[u + 1];
     const uint64_t d = e - b;
     const uint64_t nch = d > LP_CHUNK_THRESHOLD ? (d + LP_CHUNK_LEN - 1) / LP_CHUNK_LEN : 1;
@@ -467,11 +498,11 @@ __global__ void k_xadj_from_headers(GraphView g, uint64_t* xadj) {
 }
 
 __global__ __launch_bounds__(256) void k_decode_all(GraphView g, const uint64_t* xadj, int32_t* adjncy,
-                                                    int32_t* adjwgt, uint32_t* err, unsigned long long* ctr) {
+                                                    int32_t* adjwgt, uint32_t* err, CodecBlocks cb) {
   __shared__ DecodeSmem<kWave> smem[kWavesPerBlock];
   const int w = threadIdx.x / kWave;
-  for (int64_t u0 = next_vertices(ctr); u0 < g.n; u0 = next_vertices(ctr))
-  for (int64_t u = u0; u < min((int64_t)g.n, u0 + kCodecVerts); ++u) {
+  for (int64_t c = next_block(cb); c < cb.nb; c = next_block(cb))
+  for (int64_t u = cb.blk[c]; u < cb.blk[c + 1]; ++u) {
     const uint64_t fe = xadj[u];
     const uint32_t deg = (uint32_t)(xadj[u + 1] - fe);
     if (deg == 0) continue;
@@ -499,24 +530,49 @@ __global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) a[i] = v;
 }
 
+// The hand-out blocks of a CSR whose offsets xadj[0..n] (xadj[n] = two_m)
+// are on the device, with nctr zeroed counters (one per launch that uses
+// them: cb.ctr + i). LP_EINVAL if xadj decreases somewhere. Synchronises the
+// scratch stream.
+lp_status codec_blocks(const uint64_t* xadj, int64_t n, uint64_t two_m, int nctr, Scratch& sc, CodecBlocks* cb) {
+  hipStream_t s = sc.stream();
+  const int64_t nb = (int64_t)((two_m + (uint64_t)n) / kCodecWork) + 1;
+  int64_t* blk = sc.alloc<int64_t>((size_t)nb + 1);
+  unsigned long long* ctr = sc.alloc<unsigned long long>((size_t)nctr + 1);  // counters, then an error word
+  if (!blk || !ctr) return LP_ENOMEM;
+  LP_CHECK_HIP(hipMemsetAsync(ctr, 0, ((size_t)nctr + 1) * sizeof(unsigned long long), s));
+  uint32_t* err = (uint32_t*)(ctr + nctr);
+  hipLaunchKernelGGL(k_codec_blocks, dim3(grid_for(n + 1, 256, 65536)), dim3(256), 0, s, xadj, n, nb, blk, err);
+  LP_CHECK_LAUNCH();
+  uint32_t h = 0;
+  LP_CHECK_HIP(hipMemcpyAsync(&h, err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  LP_CHECK_HIP(hipStreamSynchronize(s));
+  if (h) return LP_EINVAL;
+  *cb = CodecBlocks{blk, nb, ctr};
+  return LP_OK;
+}
+
+// Input checks of a CSR; also the codec hand-out blocks (counters for
+// validation, record sizes and encoding).
 lp_status check_csr(const CsrIn& in, hipStream_t s, uint64_t* two_m, int64_t* max_wdeg, int64_t* max_deg,
-                    int64_t* total_vwgt, Scratch& sc) {
+                    int64_t* total_vwgt, Scratch& sc, CodecBlocks* cb) {
   uint64_t x0 = 0, xn = 0;
   LP_CHECK_HIP(hipMemcpyAsync(&x0, in.xadj, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   LP_CHECK_HIP(hipMemcpyAsync(&xn, in.xadj + in.n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   LP_CHECK_HIP(hipStreamSynchronize(s));
   if (x0 != 0) return LP_EINVAL;
+  LP_CHECK(codec_blocks(in.xadj, in.n, xn, 3, sc, cb));
   struct Acc {
     uint32_t err;
     uint32_t pad;
-    unsigned long long wdeg, deg, tot, ctr;
+    unsigned long long wdeg, deg, tot;
   };
   Acc* acc = sc.alloc<Acc>(1);
   if (!acc) return LP_ENOMEM;
   LP_CHECK_HIP(hipMemsetAsync(acc, 0, sizeof(Acc), s));
   if (in.n > 0) {
     hipLaunchKernelGGL(k_validate, dim3(grid_for((int64_t)in.n * kWave, 256, kCodecGrid)), dim3(256), 0, s, in,
-                       &acc->err, &acc->wdeg, &acc->deg, &acc->ctr);
+                       &acc->err, &acc->wdeg, &acc->deg, *cb);
     LP_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_vwgt_check, dim3(grid_for(in.n, 256, 4096)), dim3(256), 0, s, in.vwgt, in.n, &acc->err,
                        &acc->tot);
@@ -572,7 +628,8 @@ static lp_status make_handle(int32_t n, const uint64_t* xadj, const int32_t* adj
   CsrIn in{n, xadj, adjncy, adjwgt, vwgt};
   uint64_t two_m = 0;
   int64_t max_wdeg = 0, max_deg = 0, total = 0;
-  LP_CHECK(check_csr(in, s, &two_m, &max_wdeg, &max_deg, &total, sc));
+  CodecBlocks cb{};
+  LP_CHECK(check_csr(in, s, &two_m, &max_wdeg, &max_deg, &total, sc, &cb));
   if (max_deg > 0x7FFFFFFF) return LP_EUNSUPPORTED;
   lp_graph* g = new lp_graph();
   (void)hipGetDevice(&g->device);
@@ -603,13 +660,8 @@ static lp_status make_handle(int32_t n, const uint64_t* xadj, const int32_t* adj
     g->intervals = intervals ? 1 : 0;
     uint64_t* size = sc.alloc<uint64_t>((size_t)n + 1);
     uint64_t* total_dev = sc.alloc<uint64_t>(1);
-    unsigned long long* ctr = sc.alloc<unsigned long long>(2);  // hand-out counters of the two passes
-    if (!size || !total_dev || !ctr) {
+    if (!size || !total_dev) {
       st = LP_ENOMEM;
-      break;
-    }
-    if (hipMemsetAsync(ctr, 0, 2 * sizeof(unsigned long long), s) != hipSuccess) {
-      st = LP_EDEVICE;
       break;
     }
     if (hipMalloc((void**)&g->offs, ((size_t)n + 1) * sizeof(uint64_t)) != hipSuccess) {
@@ -621,7 +673,7 @@ static lp_status make_handle(int32_t n, const uint64_t* xadj, const int32_t* adj
         hipLaunchKernelGGL(k_record_size_itv, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, in, size);
       else
         hipLaunchKernelGGL(k_record_size, dim3(grid_for((int64_t)n * kWave, 256, kCodecGrid)), dim3(256), 0, s, in,
-                           size, ctr);
+                           size, CodecBlocks{cb.blk, cb.nb, cb.ctr + 1});
       st = last_error();
       if (st) break;
     }
@@ -651,7 +703,7 @@ static lp_status make_handle(int32_t n, const uint64_t* xadj, const int32_t* adj
         hipLaunchKernelGGL(k_encode_itv, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, in, g->offs, g->bytes);
       else
         hipLaunchKernelGGL(k_encode, dim3(grid_for((int64_t)n * kWave, 256, kCodecGrid)), dim3(256), 0, s, in,
-                           g->offs, g->bytes, ctr + 1);
+                           g->offs, g->bytes, CodecBlocks{cb.blk, cb.nb, cb.ctr + 2});
       st = last_error();
     }
   } while (0);
@@ -724,21 +776,21 @@ extern "C" lp_status lp_decompress(const lp_graph* g, uint64_t* xadj, int32_t* a
     }
     return LP_OK;
   }
-  // err, then the hand-out counter of the decode
-  unsigned long long* errc = sc.alloc<unsigned long long>(2);
-  if (!errc) return LP_ENOMEM;
-  uint32_t* err = (uint32_t*)errc;
-  LP_CHECK_HIP(hipMemsetAsync(errc, 0, 2 * sizeof(unsigned long long), s));
+  uint32_t* err = sc.alloc<uint32_t>(1);
+  if (!err) return LP_ENOMEM;
+  LP_CHECK_HIP(hipMemsetAsync(err, 0, sizeof(uint32_t), s));
   GraphView v = g->view();
   hipLaunchKernelGGL(k_xadj_from_headers, dim3(grid_for((int64_t)g->n + 1, 256, 65536)), dim3(256), 0, s, v, xadj);
   LP_CHECK_LAUNCH();
+  CodecBlocks cb{};
+  if (g->n && !g->intervals) LP_CHECK(codec_blocks(xadj, g->n, g->two_m, 1, sc, &cb));
   if (g->n) {
     if (g->intervals)
       hipLaunchKernelGGL(k_decode_all_itv, dim3(grid_for(g->n, 256, 65536)), dim3(256), 0, s, v, xadj, adjncy, adjwgt,
                          err);
     else
       hipLaunchKernelGGL(k_decode_all, dim3(grid_for((int64_t)g->n * kWave, 256, kCodecGrid)), dim3(256), 0, s, v,
-                         xadj, adjncy, adjwgt, err, errc + 1);
+                         xadj, adjncy, adjwgt, err, cb);
     LP_CHECK_LAUNCH();
   }
   uint32_t h = 0;
