@@ -831,8 +831,22 @@ def bench_headline(args) -> dict:
                      "avg_ms": round(avg_ms, 4), "alg_bytes": int(b),
                      "alg_GBs": round(b / (avg_ms / 1e3) / 1e9, 1) if avg_ms > 0 else None,
                      "frac_hbm": round(b / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if avg_ms > 0 else None}
-    # dominant kernel: the rating phase with the largest time per round
-    dom = max((p for p in phases if p != "accept"), key=lambda p: phases[p]["avg_ms"], default=None)
+    # dominant kernel: the single kernel with the largest time per round. The
+    # hub path is several kernels (whole hubs, pieces, reduction and combine),
+    # timed one by one; its algorithmic bytes are counted for the path as a
+    # whole, so if one of them dominated, the line would report the path.
+    kernel_ms = {p: phases[p]["avg_ms"] for p in ("lane", "tile", "block") if p in phases}
+    hub_kernels = {}
+    for p in ("hub_whole", "hub_pieces", "hub_reduce"):
+        launches = sum(s_.phase_launches[p] for s_ in stats)
+        if launches:
+            hub_kernels[p] = round(sum(s_.phase_ms[p] for s_ in stats) / launches, 4)
+    if "hub" in phases:
+        phases["hub"]["kernels_avg_ms"] = hub_kernels
+    kernel_ms.update(hub_kernels)
+    dom = max(kernel_ms, key=kernel_ms.get) if kernel_ms else None
+    if dom in hub_kernels:
+        dom = "hub"
     roofline = None
     if dom:
         ach = phases[dom]["alg_GBs"]

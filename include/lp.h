@@ -225,10 +225,14 @@ typedef struct {
 #define LP_PHASE_LANE 1   /* rating, lane-per-vertex bucket */
 #define LP_PHASE_TILE 2   /* rating, edge-balanced tile bucket */
 #define LP_PHASE_BLOCK 3  /* rating, workgroup-per-vertex bucket */
-#define LP_PHASE_HUB 4    /* rating, hub path (scatter, reduce, combine) */
+#define LP_PHASE_HUB 4    /* rating, hub path (whole hubs, pieces, reduction, combine) */
 #define LP_PHASE_ACCEPT 5 /* proposal compaction, sort, admission, apply */
 #define LP_PHASE_ROUND 6  /* whole rounds (rating, acceptance, apply) */
-#define LP_NUM_PHASES 7
+/* the kernels of the hub path, each timed alone (within LP_PHASE_HUB) */
+#define LP_PHASE_HUB_WHOLE 7   /* hubs rated whole, one workgroup each */
+#define LP_PHASE_HUB_PIECES 8  /* pieces of the larger hubs */
+#define LP_PHASE_HUB_REDUCE 9  /* reduction of the pieces' partial ratings, and combine */
+#define LP_NUM_PHASES 10
 
 /* Per-call statistics (host struct, filled when requested). */
 typedef struct {

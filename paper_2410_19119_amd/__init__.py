@@ -36,7 +36,7 @@ class LPError(RuntimeError):
         super().__init__(f"{where}: {msg} ({status})")
 
 
-PHASES = ("setup", "lane", "tile", "block", "hub", "accept", "round")
+PHASES = ("setup", "lane", "tile", "block", "hub", "accept", "round", "hub_whole", "hub_pieces", "hub_reduce")
 
 
 class lp_config(ctypes.Structure):

@@ -3076,6 +3076,12 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
     LP_CHECK_HIP(hipEventRecord(marks.back().b, on ? on : s));
     return LP_OK;
   };
+  // a phase that encloses others: closed by the index begin() gave it
+  auto end_at = [&](size_t idx, hipStream_t on = nullptr) -> lp_status {
+    if (!timing) return LP_OK;
+    LP_CHECK_HIP(hipEventRecord(marks[idx].b, on ? on : s));
+    return LP_OK;
+  };
   // The rating paths of a round are independent (they read the snapshot and
   // write disjoint vertices). By default they run one after another on the
   // call's stream (each kernel already fills the device); with
@@ -3248,11 +3254,22 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
                            bn[1] + bn[2] + bn[3], s));
         LP_CHECK(end());
       }
+      size_t hub_mark = 0;
       if (!use_gt && (H > 0 || plan->nwhole > 0)) {
+        hub_mark = marks.size();
         LP_CHECK(begin(LP_PHASE_HUB));
-        if (plan->nwhole > 0) LP_CHECK(launch_whole(g->weighted, x, plan->hw, plan->nwhole, hand_r + 20, s));
-        if (H > 0) LP_CHECK(launch_piece(wide, x, hm, npieces, hand_r + 16, s));
-        else LP_CHECK(end());
+        if (plan->nwhole > 0) {
+          LP_CHECK(begin(LP_PHASE_HUB_WHOLE));
+          LP_CHECK(launch_whole(g->weighted, x, plan->hw, plan->nwhole, hand_r + 20, s));
+          LP_CHECK(end());
+        }
+        if (H > 0) {
+          LP_CHECK(begin(LP_PHASE_HUB_PIECES));
+          LP_CHECK(launch_piece(wide, x, hm, npieces, hand_r + 16, s));
+          LP_CHECK(end());
+        } else {
+          LP_CHECK(end_at(hub_mark));
+        }
       }
       if (!use_gt) {
         if (overlap) {
@@ -3262,6 +3279,7 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
         }
         if (H > 0) {
           hipStream_t hs = side[0];
+          LP_CHECK(begin(LP_PHASE_HUB_REDUCE, hs));
           // as many workgroups as the LDS lets every CU hold, each taking a fixed stride of tasks
           const size_t red_lds = (size_t)hm.tmax * (wide ? 12 : 8) + sizeof(HubReduceSmem);
           const unsigned red_grid = grid_for(ntasks, 1, 256u * (unsigned)std::max<size_t>(1, (160u << 10) / red_lds));
@@ -3273,6 +3291,7 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
           hipLaunchKernelGGL(k_hub_combine, dim3(grid_for(H, 4)), dim3(256), 0, hs, x, hm, H);
           LP_CHECK_LAUNCH();
           LP_CHECK(end(hs));
+          LP_CHECK(end_at(hub_mark, hs));
         }
         if (bn[2] > 0) {
           LP_CHECK(begin(LP_PHASE_BLOCK, side[1]));
