@@ -81,6 +81,30 @@ def test_decompress_roundtrip(lp, graphs, name):
     assert np.array_equal(_np(v), g.vwgt if g.vwgt is not None else np.ones(g.n, np.int32))
 
 
+@pytest.mark.parametrize("case", ["hub-then-isolated", "isolated-only", "weighted-hubs-first"])
+def test_codec_work_blocks(lp, oracle_mod, synth_mod, case):
+    # the codec kernels take vertices in blocks of 16384 units of work (degree
+    # plus one per vertex): hubs spanning many blocks, long runs of isolated
+    # vertices, and a work total that is an exact multiple of the block
+    if case == "hub-then-isolated":
+        edges = [(0, v) for v in range(1, 40001)] + [(90001 + i, 90002 + i) for i in range(999)]
+        g = synth_mod.from_edges(91001, edges)
+    elif case == "isolated-only":
+        g = synth_mod.from_edges(16384, [])
+    else:
+        hubs = [(h, v) for h in range(3) for v in range(3, 30003) if (v * 7 + h) % 3]
+        g = synth_mod.from_edges(30003 + 70000, hubs, [1 + (i * 7919) % 50 for i in range(len(hubs))])
+    G = _gpu_graph(lp, g)
+    offs, data = lp.lp_graph_export(G)
+    o_offs, o_data = oracle_mod.compress(g.n, g.xadj, g.adjncy, g.adjwgt)
+    assert np.array_equal(_np(offs).view(np.uint64), o_offs)
+    assert np.array_equal(_np(data), o_data)
+    x, a, w, v = lp.lp_decompress(G)
+    assert np.array_equal(_np(x).view(np.uint64), g.xadj) and np.array_equal(_np(a), g.adjncy)
+    if g.adjwgt is not None:
+        assert np.array_equal(_np(w), g.adjwgt)
+
+
 def test_compress_rejects_bad_input(lp, synth_mod):
     g = synth_mod.from_edges(3, [(0, 1), (1, 2)])
     adj = g.adjncy.copy()
@@ -98,6 +122,12 @@ def test_compress_rejects_bad_input(lp, synth_mod):
     adj[0], adj[1] = adj[1], adj[0]  # unsorted neighbourhood
     with pytest.raises(lp.LPError):
         lp.lp_compress(h.n, h.xadj.view(np.int64), adj)
+    x = g.xadj.copy()
+    x[1], x[2] = x[2], x[1]  # offsets that decrease
+    for make in (lp.lp_compress, lp.lp_graph_from_csr):
+        with pytest.raises(lp.LPError) as e:
+            make(g.n, x.view(np.int64), g.adjncy)
+        assert e.value.status == lp.LP_EINVAL
 
 
 # ----------------------------------------------------------------- cluster --
