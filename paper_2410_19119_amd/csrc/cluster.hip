@@ -2245,9 +2245,18 @@ __global__ __launch_bounds__(256) void k_apply(const uint32_t* seg, const uint32
     }
     const int32_t u = (int32_t)vals[i];
     const int32_t t = (int32_t)seg[i];
-    const int32_t old = C[u];
-    C[u] = t;
-    if (Cc) Cc[pos[u]] = t;  // the reordered copy's labels (indexed by its vertices)
+    int32_t old;
+    if (Cc) {
+      // rating on the degree-ordered copy: only the copy's labels (indexed by
+      // its vertices) change during the rounds; the caller's follow after
+      // the last round (k_ro_labels)
+      const int32_t pu = pos[u];
+      old = Cc[pu];
+      Cc[pu] = t;
+    } else {
+      old = C[u];
+      C[u] = t;
+    }
     if (mv) mv[i] = make_int4(u, old, t, 0);
     if (i + 1 == n || seg[i + 1] != (uint32_t)t || !flag[i + 1])
       atomicAdd((unsigned long long*)&W[t], (unsigned long long)prefix[i]);
@@ -2257,6 +2266,13 @@ __global__ __launch_bounds__(256) void k_apply(const uint32_t* seg, const uint32
   moves = block_reduce_add<256, int64_t>(moves, sm);
   if (threadIdx.x == 0 && moves && round < 64)
     atomicAdd((unsigned long long*)&stats[64 + round], (unsigned long long)moves);
+}
+
+// The caller's labels after rounds on the degree-ordered copy: vertex i of
+// the copy is original vertex orig[i].
+__global__ void k_ro_labels(int32_t n, const int32_t* orig, const int32_t* Cc, int32_t* C) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    C[orig[i]] = Cc[i];
 }
 
 // End of a sub-round: its proposals count towards the round; after the
@@ -3341,6 +3357,10 @@ static lp_status cluster_impl(const lp_graph* g, int64_t cap, const int64_t* cap
       LP_CHECK(end());
     }
     if (timing) LP_CHECK_HIP(hipEventRecord(marks[round_mark].b, s));
+  }
+  if (use_ro) {
+    hipLaunchKernelGGL(k_ro_labels, dim3(grid_for(n, 256, 65536)), dim3(256), 0, s, n, ro->orig, Cc, labels);
+    LP_CHECK_LAUNCH();
   }
   if (batch) LP_CHECK(batch_localize(g, labels, out_labels, labels_each, s));
 
