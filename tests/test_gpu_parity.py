@@ -304,7 +304,7 @@ def test_contract_wide_weighted_degrees(lp, oracle_mod, synth_mod, compressed):
     assert np.array_equal(_np(a), cg.adjncy) and np.array_equal(_np(w_), cg.adjwgt)
 
 
-def _hot_cluster(synth_mod):
+def _hot_cluster(synth_mod, weighted=False):
     # cluster A (10^6 vertices, label 0) joined to both vertices of cluster B
     # and to 8 of 200000 singleton clusters C each: 10^7 records in A, so its
     # partitions are as many as the splitter sample allows (about 4900
@@ -316,14 +316,17 @@ def _hot_cluster(synth_mod):
     a = np.arange(na, dtype=np.int64)
     e = [np.stack([a, np.full(na, na + j, np.int64)], 1) for j in range(nb)]
     e += [np.stack([a, na + nb + (7 * a + 25_000 * k) % nc], 1) for k in range(8)]
-    g = synth_mod.from_edges(na + nb + nc, np.concatenate(e))
+    e = np.concatenate(e)
+    w = (1 + (e[:, 0] * 7 + e[:, 1]) % 5).astype(np.int64) if weighted else None
+    g = synth_mod.from_edges(na + nb + nc, e, w)
     lab = np.concatenate([np.zeros(na), np.full(nb, na), na + nb + np.arange(nc)]).astype(np.int32)
     return g, lab
 
 
-@pytest.mark.parametrize("compressed", [True, False])
-def test_contract_hot_neighbour_and_wide_reduction(lp, oracle_mod, synth_mod, compressed):
-    g, lab = _hot_cluster(synth_mod)
+@pytest.mark.parametrize("compressed,weighted", [(True, False), (False, False), (True, True)])
+def test_contract_hot_neighbour_and_wide_reduction(lp, oracle_mod, synth_mod, compressed, weighted):
+    # weighted: 64-bit table sums in every reduction configuration
+    g, lab = _hot_cluster(synth_mod, weighted)
     cg, mp = oracle_mod.contract(g, lab)
     C, M = lp.lp_contract(_gpu_graph(lp, g, compressed), lab)
     x, a, w, v = lp.lp_decompress(C)
