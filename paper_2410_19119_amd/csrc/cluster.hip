@@ -452,25 +452,24 @@ __device__ __forceinline__ void tile_seg_scan(bool head, int32_t s, int32_t s2, 
                                              uint32_t* smf, int32_t& ex, int32_t& ex2) {
   const int lane = lane_id();
   int32_t f = head ? 1 : 0;
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int32_t fu = __shfl_up(f, d, kWave);
-    const int32_t su = __shfl_up(s, d, kWave);
-    const int32_t su2 = __shfl_up(s2, d, kWave);
-    if (lane >= d) {
-      if (!f) {
-        s += su;
-        s2 += su2;
-      }
-      f |= fu;
+  // inclusive segmented scan of the wave with DPP moves (as in
+  // wave_incl_scan_add_i32): a lane adds what reaches it only while it has
+  // not seen a head, and takes over the head flag
+  auto step = [&](int32_t fu, int32_t su, int32_t su2) {
+    if (!f) {
+      s += su;
+      s2 += su2;
     }
-  }
-  int32_t ef = __shfl_up(f, 1, kWave), es = __shfl_up(s, 1, kWave), es2 = __shfl_up(s2, 1, kWave);
-  if (lane == 0) {
-    ef = 0;
-    es = 0;
-    es2 = 0;
-  }
+    f |= fu;
+  };
+  step(dpp_i32<0x111>(f), dpp_i32<0x111>(s), dpp_i32<0x111>(s2));
+  step(dpp_i32<0x112>(f), dpp_i32<0x112>(s), dpp_i32<0x112>(s2));
+  step(dpp_i32<0x114>(f), dpp_i32<0x114>(s), dpp_i32<0x114>(s2));
+  step(dpp_i32<0x118>(f), dpp_i32<0x118>(s), dpp_i32<0x118>(s2));
+  step(dpp_i32<0x142, 0xa>(f), dpp_i32<0x142, 0xa>(s), dpp_i32<0x142, 0xa>(s2));
+  step(dpp_i32<0x143, 0xc>(f), dpp_i32<0x143, 0xc>(s), dpp_i32<0x143, 0xc>(s2));
+  // exclusive values: one lane up (lane 0 gets zeros)
+  const int32_t ef = dpp_i32<0x138>(f), es = dpp_i32<0x138>(s), es2 = dpp_i32<0x138>(s2);
   const int w = threadIdx.x / kWave;
   __syncthreads();
   if (lane == kWave - 1) {
@@ -660,24 +659,66 @@ __device__ __forceinline__ uint32_t number_at(const uint32_t* A32, const uint32_
   return v;
 }
 
-// Best candidate and sum over groups of G lanes of a wavefront (G <= 64).
+// DPP move of a 64-bit value (row_shl:n = 0x100 + n: lane i of a row of 16
+// gets lane i + n); lanes that receive nothing keep `fill`.
+template <int CTRL>
+__device__ __forceinline__ int64_t dpp_i64(int64_t v, int64_t fill) {
+  const int32_t lo = __builtin_amdgcn_update_dpp((int32_t)fill, (int32_t)v, CTRL, 0xf, 0xf, false);
+  const int32_t hi = __builtin_amdgcn_update_dpp((int32_t)(fill >> 32), (int32_t)(v >> 32), CTRL, 0xf, 0xf, false);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ Cand dpp_cand(const Cand& x) {
+  return Cand{dpp_i64<CTRL>(x.r, -1), (uint64_t)dpp_i64<CTRL>((int64_t)x.key, -1),
+              __builtin_amdgcn_update_dpp(-1, x.c, CTRL, 0xf, 0xf, false)};
+}
+
+__device__ __forceinline__ Cand readlane_cand(const Cand& x, int l) {
+  const int32_t rl = __builtin_amdgcn_readlane((int32_t)x.r, l), rh = __builtin_amdgcn_readlane((int32_t)(x.r >> 32), l);
+  const int32_t kl = __builtin_amdgcn_readlane((int32_t)x.key, l);
+  const int32_t kh = __builtin_amdgcn_readlane((int32_t)(x.key >> 32), l);
+  return Cand{(int64_t)(((uint64_t)(uint32_t)rh << 32) | (uint32_t)rl), ((uint64_t)(uint32_t)kh << 32) | (uint32_t)kl,
+              __builtin_amdgcn_readlane(x.c, l)};
+}
+
+// Best candidate and sum over groups of G lanes of a wavefront (G = 16 or
+// 64), delivered to the group's first lane (the others hold partial
+// results): DPP shifts inside rows of 16 lanes (lanes that receive nothing
+// see "no candidate" / 0), then for G = 64 the rows' first lanes read out.
 template <int G>
 __device__ __forceinline__ Cand group_best_lanes(Cand x) {
-#pragma unroll
-  for (int d = G / 2; d > 0; d >>= 1) {
-    Cand y;
-    y.r = __shfl_xor(x.r, d, G);
-    y.key = __shfl_xor(x.key, d, G);
-    y.c = __shfl_xor(x.c, d, G);
+  static_assert(G == 16 || G == kWave, "groups of 16 lanes or the wavefront");
+  auto take = [&](const Cand& y) {
     if (cand_better(y, x)) x = y;
+  };
+  take(dpp_cand<0x101>(x));
+  take(dpp_cand<0x102>(x));
+  take(dpp_cand<0x104>(x));
+  take(dpp_cand<0x108>(x));
+  if constexpr (G == kWave) {
+    take(readlane_cand(x, 16));
+    take(readlane_cand(x, 32));
+    take(readlane_cand(x, 48));
   }
   return x;
 }
 
 template <int G>
 __device__ __forceinline__ int64_t group_sum_lanes(int64_t v) {
+  static_assert(G == 16 || G == kWave, "groups of 16 lanes or the wavefront");
+  v += dpp_i64<0x101>(v, 0);
+  v += dpp_i64<0x102>(v, 0);
+  v += dpp_i64<0x104>(v, 0);
+  v += dpp_i64<0x108>(v, 0);
+  if constexpr (G == kWave) {
+    int64_t t = 0;
 #pragma unroll
-  for (int d = G / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, G);
+    for (int l = 16; l < kWave; l += 16)
+      t += (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int32_t)(v >> 32), l) << 32) |
+                     (uint32_t)__builtin_amdgcn_readlane((int32_t)v, l));
+    v += t;
+  }
   return v;
 }
 

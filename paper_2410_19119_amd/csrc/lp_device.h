@@ -102,21 +102,51 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// DPP moves of a 32-bit value between lanes (VALU, no LDS round trip); lanes
+// that receive nothing (outside the row, or a row not in ROW_MASK) get 0.
+// CTRL: row_shr:n = 0x110 + n within rows of 16 lanes; row_bcast:15 = 0x142
+// (lane 15 of each row to the next row); row_bcast:31 = 0x143 (lane 31 to
+// rows 2 and 3); wave_shr:1 = 0x138 (one lane up across the wave).
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int32_t dpp_i32(int32_t v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, false);
+}
+
+// Inclusive wave64 sum of a 32-bit value: shifts by 1, 2, 4, 8 inside rows of
+// 16 lanes, then each row's total passed on by the two row broadcasts.
+__device__ __forceinline__ int32_t wave_incl_scan_add_i32(int32_t v) {
+  v += dpp_i32<0x111>(v);
+  v += dpp_i32<0x112>(v);
+  v += dpp_i32<0x114>(v);
+  v += dpp_i32<0x118>(v);
+  v += dpp_i32<0x142, 0xa>(v);
+  v += dpp_i32<0x143, 0xc>(v);
+  return v;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan_add(T x) {
+  if constexpr (sizeof(T) == 4) {
+    return (T)wave_incl_scan_add_i32((int32_t)x);
+  } else {
 #pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    T y = __shfl_up(x, d, kWave);
-    if (lane_id() >= d) x += y;
+    for (int d = 1; d < kWave; d <<= 1) {
+      T y = __shfl_up(x, d, kWave);
+      if (lane_id() >= d) x += y;
+    }
+    return x;
   }
-  return x;
 }
 
 template <typename T>
 __device__ __forceinline__ T wave_reduce_add(T x) {
+  if constexpr (sizeof(T) == 4) {
+    return (T)__builtin_amdgcn_readlane(wave_incl_scan_add_i32((int32_t)x), kWave - 1);
+  } else {
 #pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
-  return x;
+    for (int d = kWave / 2; d > 0; d >>= 1) x += __shfl_xor(x, d, kWave);
+    return x;
+  }
 }
 
 template <typename T>
