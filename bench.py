@@ -691,6 +691,22 @@ def round_model(g_n: int, two_m: int, nbytes: int, proposals: float, kappa: floa
     return int(nbytes + 8 * (g_n + 1) + 4 * two_m + 16 * g_n + 20 * proposals * kappa)
 
 
+def dominant_phase(phase_ms: dict, hub_kernels: dict):
+    """The rating phase whose single kernel takes the most time per round:
+    lanes, small tiles or large tiles by their kernel's time, the hub path by
+    the longest of its kernels (whole hubs, pieces, reduction), timed one by
+    one. The hub path's algorithmic bytes are counted for the path as a whole,
+    so when one of its kernels dominates, the phase reported is "hub".
+    Acceptance is several small kernels and never the dominant one."""
+    kernel_ms = {p: phase_ms[p] for p in ("lane", "tile", "block") if p in phase_ms}
+    if "hub" in phase_ms:
+        kernel_ms.update(hub_kernels)
+    if not kernel_ms:
+        return None
+    dom = max(kernel_ms, key=kernel_ms.get)
+    return "hub" if dom in hub_kernels else dom
+
+
 def lp_rate(lp, G, cap: int, rounds: int, steps: int, warmup: int, labels=None) -> dict:
     """Median LP round time of `steps` clustering calls (after `warmup`)."""
     import torch
@@ -831,11 +847,6 @@ def bench_headline(args) -> dict:
                      "avg_ms": round(avg_ms, 4), "alg_bytes": int(b),
                      "alg_GBs": round(b / (avg_ms / 1e3) / 1e9, 1) if avg_ms > 0 else None,
                      "frac_hbm": round(b / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if avg_ms > 0 else None}
-    # dominant kernel: the single kernel with the largest time per round. The
-    # hub path is several kernels (whole hubs, pieces, reduction and combine),
-    # timed one by one; its algorithmic bytes are counted for the path as a
-    # whole, so if one of them dominated, the line would report the path.
-    kernel_ms = {p: phases[p]["avg_ms"] for p in ("lane", "tile", "block") if p in phases}
     hub_kernels = {}
     for p in ("hub_whole", "hub_pieces", "hub_reduce"):
         launches = sum(s_.phase_launches[p] for s_ in stats)
@@ -843,10 +854,7 @@ def bench_headline(args) -> dict:
             hub_kernels[p] = round(sum(s_.phase_ms[p] for s_ in stats) / launches, 4)
     if "hub" in phases:
         phases["hub"]["kernels_avg_ms"] = hub_kernels
-    kernel_ms.update(hub_kernels)
-    dom = max(kernel_ms, key=kernel_ms.get) if kernel_ms else None
-    if dom in hub_kernels:
-        dom = "hub"
+    dom = dominant_phase({p: phases[p]["avg_ms"] for p in phases}, hub_kernels)
     roofline = None
     if dom:
         ach = phases[dom]["alg_GBs"]
